@@ -1,0 +1,257 @@
+"""Seeded synthetic Parquet files: the shared INPUT GENERATOR.
+
+Both the CPU oracle and the GPU reader consume the bytes produced here; this
+module holds no decoding arithmetic.  The C core (``pqgen.c``) encodes; the
+recipes below fix the workloads (column mixes, null rates, distributions,
+row-group and page sizes, codec) used by tests and by the benchmark.
+
+The file knobs are the four the paper studies (Sec. 1, Sec. 3: page count /
+page size, row-group size, encoding, compression).  The column mix of the wide
+table stands in for the paper's TPC-H ``lineitem`` workload (Sec. 3 setup),
+which is not reproduced: every value here is synthetic.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libpqgen.so")
+
+INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
+PLAIN, PLAIN_DICTIONARY, RLE, DELTA_BINARY_PACKED, RLE_DICTIONARY = 0, 2, 3, 5, 8
+UNIFORM, ZIPF, SORTED, DICTVALS, STRINGS, CONST, RUNS = 0, 1, 2, 3, 4, 5, 6
+UNCOMPRESSED, SNAPPY = 0, 1
+
+KiB = 1024
+MiB = 1024 * 1024
+
+
+class _Col(ctypes.Structure):
+    _fields_ = [
+        ("ptype", ctypes.c_int32), ("encoding", ctypes.c_int32), ("optional", ctypes.c_int32),
+        ("dist", ctypes.c_int32), ("null_prob", ctypes.c_double),
+        ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
+        ("dlo", ctypes.c_double), ("dhi", ctypes.c_double), ("zipf_s", ctypes.c_double),
+        ("str_min", ctypes.c_int32), ("str_max", ctypes.c_int32),
+        ("gap_max", ctypes.c_int32), ("run_len", ctypes.c_int32),
+    ]
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64), ("num_rows", ctypes.c_int64), ("rg_rows", ctypes.c_int64),
+        ("page_bytes", ctypes.c_int64), ("dict_cap", ctypes.c_int64),
+        ("codec", ctypes.c_int32), ("page_version", ctypes.c_int32),
+        ("delta_block", ctypes.c_int32), ("delta_mini", ctypes.c_int32),
+        ("max_bp_groups", ctypes.c_int32), ("rle_min", ctypes.c_int32),
+        ("ncols", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+        ("snappy_skip", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    ]
+
+
+@dataclasses.dataclass
+class Col:
+    ptype: int
+    encoding: int = PLAIN
+    optional: bool = False
+    dist: int = UNIFORM
+    null_prob: float = 0.0
+    lo: int = 0
+    hi: int = 1 << 20
+    dlo: float = 0.0
+    dhi: float = 1e6
+    zipf_s: float = 1.1
+    str_min: int = 8
+    str_max: int = 44
+    gap_max: int = 8
+    run_len: int = 16
+
+
+@dataclasses.dataclass
+class FileSpec:
+    cols: List[Col]
+    num_rows: int
+    rg_rows: int
+    page_bytes: int = 1 * MiB
+    dict_cap: int = 0
+    codec: int = UNCOMPRESSED
+    page_version: int = 1
+    delta_block: int = 128
+    delta_mini: int = 4
+    max_bp_groups: int = 63
+    rle_min: int = 8
+    seed: int = 0x5EED0000
+    snappy_literal_only: bool = False
+    name: str = "custom"
+
+    def _c(self, nthreads: int):
+        sp = _Spec()
+        sp.seed = self.seed & 0xFFFFFFFFFFFFFFFF
+        sp.num_rows = self.num_rows
+        sp.rg_rows = max(1, self.rg_rows)
+        sp.page_bytes = self.page_bytes
+        sp.dict_cap = self.dict_cap
+        sp.codec = self.codec
+        sp.page_version = self.page_version
+        sp.delta_block = self.delta_block
+        sp.delta_mini = self.delta_mini
+        sp.max_bp_groups = self.max_bp_groups
+        sp.rle_min = self.rle_min
+        sp.ncols = len(self.cols)
+        sp.nthreads = nthreads
+        sp.snappy_skip = 1 if self.snappy_literal_only else 0
+        arr = (_Col * len(self.cols))()
+        for i, c in enumerate(self.cols):
+            for f in dataclasses.fields(Col):
+                v = getattr(c, f.name)
+                setattr(arr[i], f.name, int(v) if isinstance(v, bool) else v)
+        return sp, arr
+
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C writer into datagen/libpqgen.so."""
+    src = os.path.join(_HERE, "pqgen.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-pthread", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.pqg_write.restype = ctypes.c_void_p
+        L.pqg_write.argtypes = [ctypes.POINTER(_Spec), ctypes.POINTER(_Col), ctypes.POINTER(ctypes.c_size_t)]
+        L.pqg_free.argtypes = [ctypes.c_void_p]
+        L.pqg_snappy.restype = ctypes.c_void_p
+        L.pqg_snappy.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.pqg_expected_fixed.argtypes = [ctypes.POINTER(_Spec), ctypes.POINTER(_Col), ctypes.c_int,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        L.pqg_expected_strings.restype = ctypes.c_int64
+        L.pqg_expected_strings.argtypes = [ctypes.POINTER(_Spec), ctypes.POINTER(_Col), ctypes.c_int,
+                                           ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def write(spec: FileSpec, nthreads: Optional[int] = None) -> np.ndarray:
+    """Encode `spec` into a Parquet file; returns its bytes as a uint8 array."""
+    L = lib()
+    nt = nthreads or min(16, os.cpu_count() or 1)
+    sp, arr = spec._c(nt)
+    n = ctypes.c_size_t(0)
+    p = L.pqg_write(ctypes.byref(sp), arr, ctypes.byref(n))
+    try:
+        out = np.empty(n.value, dtype=np.uint8)
+        ctypes.memmove(out.ctypes.data, p, n.value)
+    finally:
+        L.pqg_free(p)
+    return out
+
+
+def snappy_compress(data: bytes, literal_only: bool = False) -> bytes:
+    L = lib()
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    n = ctypes.c_size_t(0)
+    p = L.pqg_snappy(buf, len(data), 1 if literal_only else 0, ctypes.byref(n))
+    try:
+        return ctypes.string_at(p, n.value)
+    finally:
+        L.pqg_free(p)
+
+
+_NP = {INT32: np.int32, INT64: np.int64, DOUBLE: np.float64}
+
+
+def expected(spec: FileSpec, col: int, row0: int = 0, nrows: Optional[int] = None) -> dict:
+    """Decoded rows [row0, row0+nrows) of column `col`, straight from the seeds.
+
+    Returns {"values"| "offsets"+"chars", "validity"} in the reader's output
+    layout: null slots zero, LSB-first validity, int64 offsets from 0.
+    """
+    L = lib()
+    sp, arr = spec._c(1)
+    n = spec.num_rows - row0 if nrows is None else nrows
+    c = spec.cols[col]
+    validity = np.zeros((n + 7) // 8, dtype=np.uint8)
+    if c.ptype == BYTE_ARRAY:
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        total = L.pqg_expected_strings(ctypes.byref(sp), arr, col, row0, n, offsets.ctypes.data, None, None)
+        chars = np.zeros(max(total, 1), dtype=np.uint8)
+        L.pqg_expected_strings(ctypes.byref(sp), arr, col, row0, n, offsets.ctypes.data, chars.ctypes.data,
+                               validity.ctypes.data)
+        return {"offsets": offsets, "chars": chars[:total], "validity": validity}
+    vals = np.zeros(n, dtype=_NP[c.ptype])
+    L.pqg_expected_fixed(ctypes.byref(sp), arr, col, row0, n, vals.ctypes.data, validity.ctypes.data)
+    return {"values": vals, "validity": validity}
+
+
+# --------------------------------------------------------------------------
+# Workload recipes
+# --------------------------------------------------------------------------
+
+def small_table(rows: int = 1_000_000, page_bytes: int = 1 * MiB, seed: int = 0x5EED0000) -> FileSpec:
+    """One uncompressed row group, all REQUIRED: an INT32 PLAIN column uniform
+    in [0, 2^20) and an INT64 RLE_DICTIONARY column with 1024 distinct
+    uniformly random values (index bit width 10)."""
+    return FileSpec(
+        cols=[
+            Col(INT32, PLAIN, False, UNIFORM, lo=0, hi=1 << 20),
+            Col(INT64, RLE_DICTIONARY, False, DICTVALS, hi=1024),
+        ],
+        num_rows=rows, rg_rows=rows, page_bytes=page_bytes, seed=seed, name="small_2col")
+
+
+def wide_cols(null_prob: float = 0.10, plain_hicard_strings: bool = False) -> List[Col]:
+    """The 16-column fact table: 6 INT32, 4 INT64, 3 DOUBLE, 3 BYTE_ARRAY,
+    every column OPTIONAL with Bernoulli(null_prob) nulls."""
+    p = null_prob
+    return [
+        Col(INT32, PLAIN, True, UNIFORM, p, lo=-(1 << 31), hi=1 << 31),        # c0
+        Col(INT32, PLAIN, True, UNIFORM, p, lo=0, hi=1 << 20),                 # c1
+        Col(INT32, PLAIN, True, UNIFORM, p, lo=0, hi=1 << 31),                 # c2
+        Col(INT32, RLE_DICTIONARY, True, ZIPF, p, hi=1 << 10, zipf_s=1.1),     # c3
+        Col(INT32, RLE_DICTIONARY, True, ZIPF, p, hi=1 << 16, zipf_s=1.1),     # c4
+        Col(INT32, RLE_DICTIONARY, True, ZIPF, p, hi=1 << 20, zipf_s=1.1),     # c5
+        Col(INT64, DELTA_BINARY_PACKED, True, SORTED, p, lo=0, hi=1 << 40, gap_max=8),  # c6
+        Col(INT64, RLE_DICTIONARY, True, DICTVALS, p, hi=100),                 # c7
+        Col(INT64, RLE_DICTIONARY, True, DICTVALS, p, hi=10_000),              # c8
+        Col(INT64, RLE_DICTIONARY, True, DICTVALS, p, hi=1_000_000),           # c9
+        Col(DOUBLE, PLAIN, True, UNIFORM, p, dlo=0.0, dhi=1e6),                # c10
+        Col(DOUBLE, PLAIN, True, UNIFORM, p, dlo=0.0, dhi=1e6),                # c11
+        Col(DOUBLE, PLAIN, True, UNIFORM, p, dlo=0.0, dhi=1e6),                # c12
+        Col(BYTE_ARRAY, RLE_DICTIONARY, True, STRINGS, p, hi=100, str_min=8, str_max=44),        # c13
+        Col(BYTE_ARRAY, RLE_DICTIONARY, True, STRINGS, p, hi=10_000, str_min=8, str_max=44),     # c14
+        Col(BYTE_ARRAY, RLE_DICTIONARY, True, STRINGS, p, hi=1_000_000, str_min=8, str_max=44),  # c15
+    ]
+
+
+def wide_table(rows: int = 64_000_000, rg_rows: int = 64_000_000, page_bytes: int = 1 * MiB,
+               seed: int = 0x5EED0001, codec: int = UNCOMPRESSED, dict_cap: int = 0,
+               page_version: int = 1) -> FileSpec:
+    """The wide fact table (16 columns, 10% nulls).  Uncompressed with no
+    dictionary cap by default; with codec=SNAPPY and dict_cap=1 MiB it is the
+    compressed variant whose high-cardinality dictionary columns fall back to
+    PLAIN."""
+    return FileSpec(cols=wide_cols(), num_rows=rows, rg_rows=rg_rows, page_bytes=page_bytes,
+                    seed=seed, codec=codec, dict_cap=dict_cap, page_version=page_version,
+                    name="wide16")
+
+
+def snappy_wide_table(rows: int = 64_000_000, rg_rows: int = 64_000_000, page_bytes: int = 1 * MiB,
+                      seed: int = 0x5EED0002) -> FileSpec:
+    return wide_table(rows, rg_rows, page_bytes, seed, codec=SNAPPY, dict_cap=1 * MiB)
