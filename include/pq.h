@@ -1,0 +1,168 @@
+/*
+ * pq.h -- C ABI of the MI355X Parquet column-chunk scanner.
+ *
+ * Scope.  A Parquet file that is already resident in GPU memory is scanned
+ * into device-resident columnar buffers: page headers are parsed, Snappy
+ * page bodies decompressed, definition levels and dictionary indices decoded
+ * from the RLE/bit-packed hybrid, dictionaries gathered, and PLAIN,
+ * DELTA_BINARY_PACKED and BYTE_ARRAY values decoded.  This is the GPU scan the
+ * paper studies (Sec. 2: row groups -> column chunks -> pages, V1/V2
+ * encodings, chunk-level compression, decompression and decoding as GPU
+ * kernels; Sec. 3: the page count, row-group size, encoding and compression
+ * knobs), applied to files already in HBM.  Supported: flat schemas (no
+ * nesting, no REPEATED), physical types INT32, INT64, DOUBLE, BYTE_ARRAY;
+ * REQUIRED and OPTIONAL columns; V1 and V2 data pages; PLAIN,
+ * PLAIN_DICTIONARY, RLE_DICTIONARY and DELTA_BINARY_PACKED (INT32/INT64);
+ * codecs UNCOMPRESSED and SNAPPY.
+ *
+ * Output layout (per selected column, rows of the selected row groups
+ * concatenated in row-group order):
+ *   values    fixed-width little-endian values, `rows` entries; null rows 0.
+ *             DOUBLE is copied as its 64-bit pattern (no floating point).
+ *   validity  LSB-first bitmap, bit i of byte i/8, 1 = valid; (rows+7)/8
+ *             bytes; bits past `rows` in the last byte are 0.  May be NULL for
+ *             REQUIRED columns (if given, it is set to all ones).
+ *   offsets   BYTE_ARRAY only: rows+1 int64 values, offsets[0] = 0,
+ *             offsets[i+1] - offsets[i] = length of row i (0 for nulls).
+ *   chars     BYTE_ARRAY only: the concatenated bytes of all valid rows.
+ *
+ * Pointers.  Every buffer passed to this library is a device pointer unless
+ * stated otherwise.  The library never frees caller memory.
+ *
+ * Errors.  Functions return PQ_OK (0) or a negative pq_status.  Errors the
+ * host can detect return before anything is enqueued.  Corruption found by a
+ * kernel sets a sticky per-handle error word (first error wins); kernels
+ * never write outside the caller's buffers, and outputs are undefined after
+ * such an error.  pq_scan_check() synchronises the stream and reports it.
+ * pq_last_error() gives a thread-local message for the last failure.
+ *
+ * Concurrency.  One handle may be scanned concurrently on several streams
+ * with separate workspaces; those scans share the handle's error word.
+ */
+#ifndef PQ_H
+#define PQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pq_file_s* pq_file;
+typedef void* pq_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  PQ_OK = 0,
+  PQ_EINVAL = -1,       /* bad argument (NULL pointer, range, mask) */
+  PQ_ECORRUPT = -2,     /* the file violates the format */
+  PQ_EUNSUPPORTED = -3, /* valid Parquet outside the supported subset */
+  PQ_ENOMEM = -4,       /* device or host allocation failed */
+  PQ_EHIP = -5,         /* a HIP runtime call failed */
+  PQ_ECAPACITY = -7     /* an output or workspace buffer is smaller than planned */
+} pq_status;
+
+typedef enum { PQ_INT32 = 1, PQ_INT64 = 2, PQ_DOUBLE = 5, PQ_BYTE_ARRAY = 6 } pq_type;
+
+typedef struct {
+  int32_t type;     /* pq_type */
+  int32_t nullable; /* 1 = OPTIONAL, 0 = REQUIRED */
+  char name[64];    /* leaf name, truncated to 63 bytes */
+} pq_column_info;
+
+/* Sizes of one scan, filled by pq_plan(). */
+typedef struct {
+  int64_t rows;               /* output rows: sum of the selected row groups */
+  uint64_t workspace_bytes;   /* device workspace pq_plan/pq_scan need */
+  int64_t chars_bytes[64];    /* per selected column (in mask order); -1 until known */
+} pq_scan_sizes;
+
+/* Output buffers of one selected column. */
+typedef struct {
+  void* values;          /* fixed-width columns: rows * width bytes */
+  uint8_t* validity;     /* (rows+7)/8 bytes; may be NULL for REQUIRED */
+  int64_t* offsets;      /* BYTE_ARRAY: rows+1 */
+  uint8_t* chars;        /* BYTE_ARRAY */
+  uint64_t chars_capacity;
+} pq_column_out;
+
+/* Statistics of an opened file (page table and tile index built at open). */
+typedef struct {
+  int64_t pages;          /* data pages */
+  int64_t dict_pages;
+  int64_t tiles;          /* decode tiles (row ranges of one page) */
+  int64_t compressed_pages;
+  uint64_t encoded_bytes; /* sum of compressed page payload sizes */
+  uint64_t uncompressed_bytes;
+  double open_ms_device;  /* device time of the open-time kernels */
+} pq_file_stats;
+
+/*
+ * Opens a Parquet file that lies in device memory (a2 and a1 of the scan).
+ *   dev_buf  device pointer to the whole file (borrowed: it must stay valid
+ *            and unmodified until pq_close; it is never written).  It must be
+ *            readable up to `len` rounded up to a multiple of 16 bytes, which
+ *            every HIP and PyTorch allocation is.
+ *   len      file length in bytes.
+ *   stream   stream used for the open-time kernels; the call synchronises it.
+ *   out      receives the handle.
+ * The footer is copied to the host and decoded there (file layout and
+ * Thrift-compact metadata, Sec. 2's row-group/chunk/page hierarchy); a kernel
+ * then walks every column chunk's page headers into a device page table, and
+ * a second kernel builds the tile index (entry positions of every fixed-size
+ * row tile in the level and value streams of each page) that lets a scan
+ * start decoding at any tile.  Returns PQ_ECORRUPT for a malformed file,
+ * PQ_EUNSUPPORTED for valid files outside the supported subset.
+ */
+pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out);
+
+pq_status pq_num_row_groups(pq_file f, int32_t* n);
+pq_status pq_num_columns(pq_file f, int32_t* n);
+pq_status pq_column_info_get(pq_file f, int32_t col, pq_column_info* out);
+pq_status pq_row_group_rows(pq_file f, int32_t rg, int64_t* rows);
+pq_status pq_file_stats_get(pq_file f, pq_file_stats* out);
+
+/*
+ * Sizes a scan of columns `col_mask` (bit i = leaf column i, at most 64
+ * columns) over row groups [rg_begin, rg_end).
+ *   workspace == NULL: fills rows and workspace_bytes only (host-only, no
+ *     GPU work); chars_bytes of BYTE_ARRAY columns are -1.
+ *   workspace != NULL (>= workspace_bytes): additionally runs the string
+ *     length pass on `stream`, synchronises it, and fills chars_bytes.
+ * chars_bytes of non-string columns are 0.
+ */
+pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
+                  uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream);
+
+/*
+ * Enqueues the scan (a3..a12) on `stream` and returns without synchronising.
+ *   outs       host array of n_outs descriptors; outs[k] belongs to the k-th
+ *              set bit of col_mask in ascending order.
+ *   workspace  device buffer of at least the planned workspace_bytes, owned
+ *              by the caller, not used by anything else until the scan ends.
+ * Steps enqueued: clear error word / validity edge words; Snappy
+ * decompression of compressed pages into the workspace; dictionary pages ->
+ * device dictionaries; DELTA tile sums and string sizes, with their prefix
+ * scans; then the decode kernels (definition levels -> validity and ranks,
+ * dictionary indices -> gather, PLAIN, DELTA_BINARY_PACKED, BYTE_ARRAY ->
+ * offsets and chars).  Returns PQ_ECAPACITY if a chars buffer is smaller
+ * than needed (this check synchronises `stream` when string columns are
+ * selected and chars_capacity is not at least the planned size).
+ */
+pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
+                  int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream);
+
+/* Synchronises `stream` and returns (then clears) the handle's error word:
+   PQ_OK, or PQ_ECORRUPT/PQ_EUNSUPPORTED found by a kernel. */
+pq_status pq_scan_check(pq_file f, pq_stream stream);
+
+/* Frees the handle's host and device memory (not dev_buf). */
+void pq_close(pq_file f);
+
+/* Thread-local description of the last error. */
+const char* pq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PQ_H */

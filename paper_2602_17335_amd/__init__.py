@@ -1,0 +1,231 @@
+"""MI355X Parquet column-chunk scanner: Python binding of libpqscan.so.
+
+Argument marshalling only.  Every step of the scan runs in the HIP kernels
+behind the C ABI in include/pq.h; PyTorch supplies device memory and the
+stream.  There is no CPU fallback: importing fails loudly when the library is
+missing, and the scan needs a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpqscan.so")
+
+PQ_OK, PQ_EINVAL, PQ_ECORRUPT, PQ_EUNSUPPORTED, PQ_ENOMEM, PQ_EHIP, PQ_ECAPACITY = 0, -1, -2, -3, -4, -5, -7
+INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
+_WIDTH = {INT32: 4, INT64: 8, DOUBLE: 8}
+
+EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get", "pq_row_group_rows",
+           "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check", "pq_close", "pq_last_error")
+
+
+class PqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pq error {code}: {msg}")
+        self.code = code
+
+
+class ColumnInfo(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("nullable", ctypes.c_int32), ("name", ctypes.c_char * 64)]
+
+
+class ScanSizes(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("workspace_bytes", ctypes.c_uint64), ("chars_bytes", ctypes.c_int64 * 64)]
+
+
+class ColumnOut(ctypes.Structure):
+    _fields_ = [("values", ctypes.c_void_p), ("validity", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("chars", ctypes.c_void_p), ("chars_capacity", ctypes.c_uint64)]
+
+
+class FileStats(ctypes.Structure):
+    _fields_ = [("pages", ctypes.c_int64), ("dict_pages", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("compressed_pages", ctypes.c_int64), ("encoded_bytes", ctypes.c_uint64),
+                ("uncompressed_bytes", ctypes.c_uint64), ("open_ms_device", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libpqscan.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2602_17335_amd.build` "
+                              "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+        L.pq_open_device.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.pq_num_row_groups.argtypes = [vp, ctypes.POINTER(i32)]
+        L.pq_num_columns.argtypes = [vp, ctypes.POINTER(i32)]
+        L.pq_column_info_get.argtypes = [vp, i32, ctypes.POINTER(ColumnInfo)]
+        L.pq_row_group_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
+        L.pq_file_stats_get.argtypes = [vp, ctypes.POINTER(FileStats)]
+        L.pq_plan.argtypes = [vp, u64, i32, i32, vp, u64, ctypes.POINTER(ScanSizes), vp]
+        L.pq_scan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp]
+        L.pq_scan_check.argtypes = [vp, vp]
+        L.pq_close.argtypes = [vp]
+        L.pq_close.restype = None
+        L.pq_last_error.restype = ctypes.c_char_p
+        for name in ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get",
+                     "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PQ_OK:
+        raise PqError(rc, lib().pq_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def validity_bytes(rows: int) -> int:
+    """Bytes the library writes for a validity bitmap of `rows` rows."""
+    return (rows + 31) // 32 * 4
+
+
+def to_device(data, device="cuda"):
+    """Copies file bytes (numpy uint8 / bytes) into a fresh device buffer that
+    is 16-byte aligned and padded to a multiple of 16 bytes."""
+    import numpy as np
+    import torch
+    a = np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else np.asarray(data, dtype=np.uint8)
+    n = a.size
+    buf = torch.empty((n + 15) // 16 * 16 + 16, dtype=torch.uint8, device=device)
+    buf[:n].copy_(torch.from_numpy(a), non_blocking=False)
+    return buf, n
+
+
+class DeviceFile:
+    """A Parquet file resident in device memory, opened for scanning."""
+
+    def __init__(self, dev_buf, nbytes: Optional[int] = None, stream=None):
+        self._buf = dev_buf  # keep the borrowed buffer alive
+        n = dev_buf.numel() if nbytes is None else nbytes
+        h = ctypes.c_void_p()
+        _check(lib().pq_open_device(ctypes.c_void_p(dev_buf.data_ptr()), n, ctypes.c_void_p(_stream_ptr(stream)),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.nbytes = n
+
+    def close(self):
+        if self._h:
+            lib().pq_close(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_columns(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().pq_num_columns(self._h, ctypes.byref(n)))
+        return n.value
+
+    @property
+    def num_row_groups(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().pq_num_row_groups(self._h, ctypes.byref(n)))
+        return n.value
+
+    def row_group_rows(self, rg: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().pq_row_group_rows(self._h, rg, ctypes.byref(n)))
+        return n.value
+
+    def column_info(self, col: int) -> ColumnInfo:
+        ci = ColumnInfo()
+        _check(lib().pq_column_info_get(self._h, col, ctypes.byref(ci)))
+        return ci
+
+    def stats(self) -> FileStats:
+        s = FileStats()
+        _check(lib().pq_file_stats_get(self._h, ctypes.byref(s)))
+        return s
+
+    def plan(self, mask: int, rg_begin: int, rg_end: int, workspace=None, stream=None) -> ScanSizes:
+        sz = ScanSizes()
+        wp = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
+        wb = workspace.numel() if workspace is not None else 0
+        _check(lib().pq_plan(self._h, mask, rg_begin, rg_end, wp, wb, ctypes.byref(sz),
+                             ctypes.c_void_p(_stream_ptr(stream))))
+        return sz
+
+    def scan_into(self, mask: int, rg_begin: int, rg_end: int, outs: Sequence[ColumnOut], workspace, stream=None):
+        """Enqueues pq_scan with caller-provided buffers (no synchronisation)."""
+        arr = (ColumnOut * max(len(outs), 1))(*outs)
+        _check(lib().pq_scan(self._h, mask, rg_begin, rg_end, arr, len(outs), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+
+    def check(self, stream=None):
+        _check(lib().pq_scan_check(self._h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def allocate(self, columns: Sequence[int], rg_begin: int = 0, rg_end: Optional[int] = None, stream=None):
+        """Plans a scan and allocates its workspace and output tensors.
+        Returns (mask, rg_end, workspace, outs, tensors)."""
+        import torch
+        if rg_end is None:
+            rg_end = self.num_row_groups
+        mask = 0
+        for c in columns:
+            mask |= 1 << c
+        sz = self.plan(mask, rg_begin, rg_end, stream=stream)
+        ws = torch.empty(max(int(sz.workspace_bytes), 256), dtype=torch.uint8, device="cuda")
+        cols = sorted(columns)
+        if any(self.column_info(c).type == BYTE_ARRAY for c in cols):
+            sz = self.plan(mask, rg_begin, rg_end, workspace=ws, stream=stream)
+        rows = int(sz.rows)
+        outs, tensors = [], {}
+        for k, c in enumerate(cols):
+            ci = self.column_info(c)
+            vb = torch.zeros(max(validity_bytes(rows), 4), dtype=torch.uint8, device="cuda")
+            o = ColumnOut()
+            o.validity = vb.data_ptr()
+            t = {"validity_buf": vb, "rows": rows}
+            if ci.type == BYTE_ARRAY:
+                offs = torch.empty(rows + 1, dtype=torch.int64, device="cuda")
+                nch = int(sz.chars_bytes[k])
+                chars = torch.empty(max(nch, 1), dtype=torch.uint8, device="cuda")
+                o.offsets, o.chars, o.chars_capacity = offs.data_ptr(), chars.data_ptr(), nch
+                t.update(offsets=offs, chars_buf=chars, chars_bytes=nch)
+            else:
+                dt = {INT32: torch.int32, INT64: torch.int64, DOUBLE: torch.float64}[ci.type]
+                vals = torch.empty(max(rows, 1), dtype=dt, device="cuda")
+                o.values = vals.data_ptr()
+                t["values_buf"] = vals
+            outs.append(o)
+            tensors[c] = t
+        return mask, rg_end, ws, outs, tensors
+
+    def scan(self, columns: Sequence[int], rg_begin: int = 0, rg_end: Optional[int] = None, stream=None,
+             check: bool = True) -> Dict[int, dict]:
+        """Scans `columns` over row groups [rg_begin, rg_end) into new device
+        tensors: {col: {"values"| "offsets","chars", "validity"}}."""
+        mask, rg_end, ws, outs, tensors = self.allocate(columns, rg_begin, rg_end, stream)
+        self.scan_into(mask, rg_begin, rg_end, outs, ws, stream)
+        if check:
+            self.check(stream)
+        res = {}
+        for c, t in tensors.items():
+            rows = t["rows"]
+            d = {"validity": t["validity_buf"][: (rows + 7) // 8], "rows": rows}
+            if "offsets" in t:
+                d["offsets"] = t["offsets"]
+                d["chars"] = t["chars_buf"][: t["chars_bytes"]]
+            else:
+                d["values"] = t["values_buf"][:rows]
+            res[c] = d
+        return res

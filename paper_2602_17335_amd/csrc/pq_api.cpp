@@ -1,0 +1,790 @@
+// pq_api.cpp -- host side of the GPU Parquet scan: the C ABI declared in
+// include/pq.h.  Footer decode (Thrift compact), page-table and tile-index
+// construction at open, workspace planning and kernel orchestration per scan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pq.h"
+#include "pq_internal.h"
+
+namespace pqk {
+__global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
+                       const uint32_t* page_base, PageDev* pages, uint32_t* err);
+__global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* err);
+__global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
+                         uint32_t* err);
+__global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
+__global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
+                       DictSlot* slots, const uint32_t* strck, uint32_t* err);
+__global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
+                          const TileDev* tiles, const DictSlot* slots, SegTable seg, uint32_t* err);
+__global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
+__global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
+                               const TileDev* tiles, const DictSlot* slots, SegTable seg, uint32_t* err);
+__global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
+                             const TileDev* tiles, const DictSlot* slots, const uint32_t* strck, SegTable seg,
+                             uint32_t* err);
+}  // namespace pqk
+
+using namespace pqk;
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local char g_msg[512];
+
+static pq_status fail(pq_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static pq_status fail(pq_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_OR(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(PQ_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+extern "C" const char* pq_last_error(void) { return g_msg; }
+
+// ---------------------------------------------------------------------------
+// Thrift compact decoder for the footer (host)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TReader {
+  const uint8_t* p;
+  size_t n, pos = 0;
+  bool bad = false;
+  uint8_t u8() {
+    if (pos >= n) { bad = true; return 0; }
+    return p[pos++];
+  }
+  uint64_t uleb() {
+    uint64_t v = 0;
+    for (int s = 0; s < 70; s += 7) {
+      uint8_t b = u8();
+      if (bad) return 0;
+      if (s == 63 && (b & 0x7e)) { bad = true; return 0; }
+      v |= (uint64_t)(b & 0x7f) << s;
+      if (!(b & 0x80)) return v;
+    }
+    bad = true;
+    return 0;
+  }
+  int64_t zz() { uint64_t v = uleb(); return (int64_t)(v >> 1) ^ -(int64_t)(v & 1); }
+  // next field of a struct; false at STOP
+  bool field(int& last, int& id, int& type) {
+    uint8_t b = u8();
+    if (bad || b == 0) return false;
+    type = b & 15;
+    id = (b >> 4) ? last + (b >> 4) : (int)zz();
+    last = id;
+    return !bad;
+  }
+  void list_header(uint64_t& size, int& etype) {
+    uint8_t b = u8();
+    etype = b & 15;
+    size = b >> 4;
+    if (size == 15) size = uleb();
+  }
+  void skip(int type, int depth = 0) {
+    if (depth > 32) { bad = true; return; }
+    switch (type) {
+      case 1: case 2: return;
+      case 3: u8(); return;
+      case 4: case 5: case 6: uleb(); return;
+      case 7: if (n - pos < 8) bad = true; else pos += 8; return;
+      case 8: { uint64_t l = uleb(); if (bad || l > n - pos) bad = true; else pos += l; return; }
+      case 9: case 10: {
+        uint64_t sz; int et;
+        list_header(sz, et);
+        for (uint64_t i = 0; i < sz && !bad; ++i) {
+          if (et == 1 || et == 2) u8(); else skip(et, depth + 1);
+        }
+        return;
+      }
+      case 11: {
+        uint64_t sz = uleb();
+        if (!sz) return;
+        uint8_t kv = u8();
+        for (uint64_t i = 0; i < sz && !bad; ++i) { skip(kv >> 4, depth + 1); skip(kv & 15, depth + 1); }
+        return;
+      }
+      case 12: {
+        int last = 0, id, t;
+        while (!bad && field(last, id, t)) skip(t, depth + 1);
+        return;
+      }
+      default: bad = true;
+    }
+  }
+};
+
+struct ColMeta {
+  int type = 0, optional = 0;
+  std::string name;
+};
+struct ChunkMeta {
+  int type = -1, codec = 0;
+  int64_t num_values = -1, total_compressed = -1, data_off = -1, dict_off = -1;
+  bool has_dict = false, external = false;
+};
+
+pq_status parse_footer(const uint8_t* p, size_t n, std::vector<ColMeta>& cols, std::vector<int64_t>& rg_rows,
+                       std::vector<ChunkMeta>& chunks /* [rg][col] */) {
+  TReader r{p, n};
+  int last = 0, id, t;
+  bool have_schema = false, have_rgs = false;
+  while (r.field(last, id, t)) {
+    if (id == 2 && t == 9) {
+      uint64_t sz; int et;
+      r.list_header(sz, et);
+      if (r.bad || et != 12 || sz < 1) return fail(PQ_ECORRUPT, "bad schema list");
+      for (uint64_t e = 0; e < sz; ++e) {
+        int l2 = 0, i2, t2, type = -1, rep = 0, nch = 0;
+        std::string name;
+        while (r.field(l2, i2, t2)) {
+          if (i2 == 1 && t2 == 5) type = (int)r.zz();
+          else if (i2 == 3 && t2 == 5) rep = (int)r.zz();
+          else if (i2 == 5 && t2 == 5) nch = (int)r.zz();
+          else if (i2 == 4 && t2 == 8) {
+            uint64_t l = r.uleb();
+            if (r.bad || l > r.n - r.pos) return fail(PQ_ECORRUPT, "bad schema name");
+            name.assign((const char*)r.p + r.pos, l);
+            r.pos += l;
+          } else r.skip(t2);
+        }
+        if (r.bad) return fail(PQ_ECORRUPT, "bad schema element");
+        if (e == 0) {
+          if ((uint64_t)nch != sz - 1) return fail(PQ_EUNSUPPORTED, "nested schemas are not supported");
+          continue;
+        }
+        if (nch != 0 || type < 0) return fail(PQ_EUNSUPPORTED, "nested schemas are not supported");
+        if (rep == 2) return fail(PQ_EUNSUPPORTED, "REPEATED columns are not supported");
+        if (type != T_INT32 && type != T_INT64 && type != T_DOUBLE && type != T_BYTE_ARRAY)
+          return fail(PQ_EUNSUPPORTED, "column %s: physical type %d is not supported", name.c_str(), type);
+        ColMeta c;
+        c.type = type;
+        c.optional = rep == 1;
+        c.name = name;
+        cols.push_back(c);
+      }
+      have_schema = true;
+    } else if (id == 4 && t == 9) {
+      uint64_t nrg; int et;
+      r.list_header(nrg, et);
+      if (r.bad || et != 12 || !have_schema) return fail(PQ_ECORRUPT, "bad row-group list");
+      for (uint64_t g = 0; g < nrg; ++g) {
+        int l2 = 0, i2, t2;
+        int64_t rows = -1;
+        bool have_cols = false;
+        while (r.field(l2, i2, t2)) {
+          if (i2 == 1 && t2 == 9) {
+            uint64_t nc; int e2;
+            r.list_header(nc, e2);
+            if (r.bad || e2 != 12 || nc != cols.size()) return fail(PQ_ECORRUPT, "row group column count mismatch");
+            for (uint64_t c = 0; c < nc; ++c) {
+              ChunkMeta cm;
+              int l3 = 0, i3, t3;
+              while (r.field(l3, i3, t3)) {
+                if (i3 == 1 && t3 == 8) { cm.external = true; r.skip(t3); }
+                else if (i3 == 3 && t3 == 12) {
+                  int l4 = 0, i4, t4;
+                  while (r.field(l4, i4, t4)) {
+                    if (i4 == 1 && t4 == 5) cm.type = (int)r.zz();
+                    else if (i4 == 4 && t4 == 5) cm.codec = (int)r.zz();
+                    else if (i4 == 5 && t4 == 6) cm.num_values = r.zz();
+                    else if (i4 == 7 && t4 == 6) cm.total_compressed = r.zz();
+                    else if (i4 == 9 && t4 == 6) cm.data_off = r.zz();
+                    else if (i4 == 11 && t4 == 6) { cm.dict_off = r.zz(); cm.has_dict = true; }
+                    else r.skip(t4);
+                  }
+                } else r.skip(t3);
+              }
+              chunks.push_back(cm);
+            }
+            have_cols = true;
+          } else if (i2 == 3 && t2 == 6) rows = r.zz();
+          else r.skip(t2);
+        }
+        if (r.bad || !have_cols || rows < 0) return fail(PQ_ECORRUPT, "bad row group");
+        rg_rows.push_back(rows);
+      }
+      have_rgs = true;
+    } else {
+      r.skip(t);
+    }
+    if (r.bad) break;
+  }
+  if (r.bad || !have_schema || !have_rgs) return fail(PQ_ECORRUPT, "malformed file metadata");
+  return PQ_OK;
+}
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct pq_file_s {
+  const uint8_t* file = nullptr;
+  uint64_t len = 0;
+  int ncols = 0, nrg = 0;
+  std::vector<ColMeta> cols;
+  std::vector<int64_t> rg_rows, rg_row0;
+  std::vector<ChunkDev> chunks;          // col-major
+  std::vector<uint32_t> chunk_page0;     // first page of each chunk (+ sentinel)
+  std::vector<uint32_t> chunk_tile0;     // first tile of each chunk (+ sentinel)
+  std::vector<PageDev> pages;            // host copy (after the index pass)
+  std::vector<uint64_t> scratch_prefix;  // per page (+ sentinel): file-wide scratch offset
+  uint64_t total_tiles = 0, total_strck = 0;
+  PageDev* d_pages = nullptr;
+  TileDev* d_tiles = nullptr;
+  uint32_t* d_strck = nullptr;
+  ChunkDev* d_chunks = nullptr;
+  uint32_t* d_err = nullptr;
+  pq_file_stats stats{};
+};
+
+static void free_handle(pq_file f) {
+  if (!f) return;
+  if (f->d_pages) (void)hipFree(f->d_pages);
+  if (f->d_tiles) (void)hipFree(f->d_tiles);
+  if (f->d_strck) (void)hipFree(f->d_strck);
+  if (f->d_chunks) (void)hipFree(f->d_chunks);
+  if (f->d_err) (void)hipFree(f->d_err);
+  delete f;
+}
+
+static pq_status device_error(uint32_t code) {
+  const uint32_t c = code & 0xff, where = code >> 8;
+  static const char* names[] = {"none", "page header", "page leaves its column chunk", "page order",
+                                "page value counts", "definition levels", "value stream", "dictionary index",
+                                "DELTA_BINARY_PACKED data", "Snappy stream", "unsupported feature",
+                                "dictionary missing", "V2 page header", "BYTE_ARRAY lengths", "chars capacity"};
+  const char* nm = c < sizeof(names) / sizeof(names[0]) ? names[c] : "?";
+  if (c == ERR_UNSUPPORTED) return fail(PQ_EUNSUPPORTED, "device: unsupported feature (at %u)", where);
+  if (c == ERR_CAPACITY) return fail(PQ_ECAPACITY, "device: chars buffer too small (column %u)", where);
+  return fail(PQ_ECORRUPT, "device: corrupt %s (at %u)", nm, where);
+}
+
+static pq_status read_err(pq_file f, hipStream_t s) {
+  uint32_t e = 0;
+  HIP_OR(hipMemcpyAsync(&e, f->d_err, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR(hipStreamSynchronize(s));
+  if (e) {
+    HIP_OR(hipMemsetAsync(f->d_err, 0, 4, s));
+    HIP_OR(hipStreamSynchronize(s));
+    return device_error(e);
+  }
+  return PQ_OK;
+}
+
+static SegTable make_segs(const std::vector<Segment>& v) {
+  SegTable t;
+  memset(&t, 0, sizeof(t));
+  t.n = (int32_t)v.size();
+  for (size_t i = 0; i < v.size(); ++i) t.s[i] = v[i];
+  return t;
+}
+
+extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out) {
+  if (!out) return fail(PQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!dev_buf) return fail(PQ_EINVAL, "dev_buf is NULL");
+  if (((uintptr_t)dev_buf & 15) != 0) return fail(PQ_EINVAL, "dev_buf must be 16-byte aligned");
+  if (len < 12) return fail(PQ_ECORRUPT, "file shorter than 12 bytes");
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  const uint8_t* file = (const uint8_t*)dev_buf;
+  uint8_t tail[8], head[4];
+  HIP_OR(hipMemcpyAsync(tail, file + len - 8, 8, hipMemcpyDeviceToHost, s));
+  HIP_OR(hipMemcpyAsync(head, file, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR(hipStreamSynchronize(s));
+  if (memcmp(tail + 4, "PAR1", 4) || memcmp(head, "PAR1", 4)) return fail(PQ_ECORRUPT, "bad magic");
+  uint64_t flen = (uint64_t)tail[0] | ((uint64_t)tail[1] << 8) | ((uint64_t)tail[2] << 16) | ((uint64_t)tail[3] << 24);
+  if (flen + 12 > len) return fail(PQ_ECORRUPT, "footer length exceeds file");
+  std::vector<uint8_t> foot(flen);
+  if (flen) {
+    HIP_OR(hipMemcpyAsync(foot.data(), file + len - 8 - flen, flen, hipMemcpyDeviceToHost, s));
+    HIP_OR(hipStreamSynchronize(s));
+  }
+  pq_file f = new pq_file_s();
+  f->file = file;
+  f->len = len;
+  std::vector<ChunkMeta> cms;
+  pq_status st = parse_footer(foot.data(), foot.size(), f->cols, f->rg_rows, cms);
+  if (st != PQ_OK) { free_handle(f); return st; }
+  f->ncols = (int)f->cols.size();
+  f->nrg = (int)f->rg_rows.size();
+  if (f->ncols > 64) { free_handle(f); return fail(PQ_EUNSUPPORTED, "more than 64 columns"); }
+  f->rg_row0.resize(f->nrg + 1, 0);
+  for (int g = 0; g < f->nrg; ++g) f->rg_row0[g + 1] = f->rg_row0[g] + f->rg_rows[g];
+  const uint64_t data_end = len - 8 - flen;
+  const int nchunks = f->ncols * f->nrg;
+  f->chunks.resize(nchunks);
+  for (int c = 0; c < f->ncols; ++c)
+    for (int g = 0; g < f->nrg; ++g) {
+      const ChunkMeta& m = cms[(size_t)g * f->ncols + c];
+      if (m.external) { free_handle(f); return fail(PQ_EUNSUPPORTED, "column chunk in another file"); }
+      if (m.type != f->cols[c].type) { free_handle(f); return fail(PQ_ECORRUPT, "chunk type differs from schema"); }
+      if (m.codec != 0 && m.codec != 1) { free_handle(f); return fail(PQ_EUNSUPPORTED, "codec %d is not supported", m.codec); }
+      if (m.num_values != f->rg_rows[g]) { free_handle(f); return fail(PQ_ECORRUPT, "chunk value count differs from row-group rows"); }
+      int64_t start = m.data_off;
+      if (m.has_dict && m.dict_off > 0 && m.dict_off < m.data_off) start = m.dict_off;
+      if (start < 4 || m.total_compressed < 0 || (uint64_t)start + (uint64_t)m.total_compressed > data_end) {
+        free_handle(f);
+        return fail(PQ_ECORRUPT, "column chunk outside the file");
+      }
+      ChunkDev& cd = f->chunks[(size_t)c * f->nrg + g];
+      cd.start = (uint64_t)start;
+      cd.end = (uint64_t)start + (uint64_t)m.total_compressed;
+      cd.rows = f->rg_rows[g];
+      cd.type = m.type;
+      cd.codec = m.codec;
+      cd.optional = f->cols[c].optional;
+      cd.col = c;
+    }
+
+  // ---- a2: device page-header walk ----
+  hipEvent_t e0, e1;
+  HIP_OR(hipEventCreate(&e0));
+  HIP_OR(hipEventCreate(&e1));
+  HIP_OR(hipEventRecord(e0, s));
+  uint32_t *d_counts = nullptr, *d_base = nullptr;
+  auto cleanup_tmp = [&]() {
+    if (d_counts) (void)hipFree(d_counts);
+    if (d_base) (void)hipFree(d_base);
+    d_counts = d_base = nullptr;
+  };
+#define OPEN_HIP(expr)                                                          \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      cleanup_tmp();                                                            \
+      free_handle(f);                                                           \
+      return fail(PQ_EHIP, "%s: %s", #expr, hipGetErrorString(e_));            \
+    }                                                                           \
+  } while (0)
+#define OPEN_ERR()                                                              \
+  do {                                                                          \
+    pq_status st_ = read_err(f, s);                                             \
+    if (st_ != PQ_OK) { cleanup_tmp(); free_handle(f); return st_; }            \
+  } while (0)
+
+  OPEN_HIP(hipMalloc(&f->d_err, 4));
+  OPEN_HIP(hipMemsetAsync(f->d_err, 0, 4, s));
+  if (nchunks > 0) {
+    OPEN_HIP(hipMalloc(&f->d_chunks, sizeof(ChunkDev) * nchunks));
+    OPEN_HIP(hipMalloc(&d_counts, sizeof(uint32_t) * nchunks));
+    OPEN_HIP(hipMalloc(&d_base, sizeof(uint32_t) * nchunks));
+    OPEN_HIP(hipMemcpyAsync(f->d_chunks, f->chunks.data(), sizeof(ChunkDev) * nchunks, hipMemcpyHostToDevice, s));
+    const int blocks = (nchunks + 63) / 64;
+    hipLaunchKernelGGL(k_walk, dim3(blocks), dim3(64), 0, s, file, f->d_chunks, nchunks, d_counts, nullptr, nullptr, f->d_err);
+    OPEN_HIP(hipGetLastError());
+    OPEN_ERR();
+  }
+  std::vector<uint32_t> counts(nchunks);
+  if (nchunks) OPEN_HIP(hipMemcpy(counts.data(), d_counts, sizeof(uint32_t) * nchunks, hipMemcpyDeviceToHost));
+  f->chunk_page0.assign(nchunks + 1, 0);
+  for (int q = 0; q < nchunks; ++q) f->chunk_page0[q + 1] = f->chunk_page0[q] + counts[q];
+  const uint32_t npages = f->chunk_page0[nchunks];
+  if (npages > 0) {
+    OPEN_HIP(hipMalloc(&f->d_pages, sizeof(PageDev) * npages));
+    OPEN_HIP(hipMemcpyAsync(d_base, f->chunk_page0.data(), sizeof(uint32_t) * nchunks, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_walk, dim3((nchunks + 63) / 64), dim3(64), 0, s, file, f->d_chunks, nchunks, nullptr, d_base,
+                       f->d_pages, f->d_err);
+    OPEN_HIP(hipGetLastError());
+    OPEN_ERR();
+    f->pages.resize(npages);
+    OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
+  }
+  cleanup_tmp();
+
+  // ---- host layout: rows, dictionary links, tiles, scratch, checkpoints ----
+  f->chunk_tile0.assign(nchunks + 1, 0);
+  f->scratch_prefix.assign(npages + 1, 0);
+  uint64_t tiles = 0, strck = 0, scratch = 0;
+  for (int q = 0; q < nchunks; ++q) {
+    const ChunkDev& cd = f->chunks[q];
+    const int g = q % f->nrg;
+    int64_t row = f->rg_row0[g];
+    uint32_t dict = ~0u;
+    f->chunk_tile0[q] = (uint32_t)tiles;
+    for (uint32_t p = f->chunk_page0[q]; p < f->chunk_page0[q + 1]; ++p) {
+      PageDev& pg = f->pages[p];
+      pg.scratch_off = scratch;
+      f->scratch_prefix[p] = scratch;
+      uint64_t slen = 0;
+      if (cd.codec == 1) {
+        if (pg.kind == PAGE_DATA_V2) slen = pg.v2_compressed ? pg.uncomp_size - pg.rep_len - pg.def_len : 0;
+        else slen = pg.uncomp_size;
+        // V1/dictionary pages are always compressed with the chunk codec; an
+        // empty page still decompresses to 0 bytes
+        if (slen == 0 && pg.kind != PAGE_DATA_V2) slen = 0;
+      }
+      pg.scratch_len = (uint32_t)slen;
+      if (cd.codec == 1 && (pg.kind != PAGE_DATA_V2 || pg.v2_compressed)) scratch += align_up(slen + SCRATCH_PAD, 16);
+      if (pg.kind == PAGE_DICT) {
+        dict = p;
+        pg.row0 = row;
+        if (cd.type == T_BYTE_ARRAY) {
+          pg.strck_begin = (uint32_t)strck;
+          strck += (uint64_t)pg.num_values / STR_CK + 1;
+        }
+        continue;
+      }
+      pg.dict_page = dict;
+      pg.row0 = row;
+      row += pg.num_values;
+      pg.tile_begin = (uint32_t)tiles;
+      tiles += ((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS;
+      if (cd.type == T_BYTE_ARRAY && pg.encoding == E_PLAIN) {
+        pg.strck_begin = (uint32_t)strck;
+        strck += (uint64_t)pg.num_values / STR_CK + 1;
+      }
+    }
+  }
+  f->chunk_tile0[nchunks] = (uint32_t)tiles;
+  f->scratch_prefix[npages] = scratch;
+  if (tiles > 0xffffffffull) { free_handle(f); return fail(PQ_EUNSUPPORTED, "too many tiles"); }
+  f->total_tiles = tiles;
+  f->total_strck = strck;
+
+  // ---- compressed pages decompressed once for the index pass ----
+  uint8_t* d_scratch = nullptr;
+  ColScan* d_cs = nullptr;
+  auto cleanup_open = [&]() {
+    if (d_scratch) (void)hipFree(d_scratch);
+    if (d_cs) (void)hipFree(d_cs);
+    d_scratch = nullptr;
+    d_cs = nullptr;
+  };
+  if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
+  if (scratch > 0) {
+    if (hipMalloc(&d_scratch, scratch) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for decompression"); }
+    if (hipMalloc(&d_cs, sizeof(ColScan)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
+    ColScan cs;
+    memset(&cs, 0, sizeof(cs));
+    (void)hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s);
+    std::vector<Segment> segs{Segment{0, 0, npages, 0}};
+    SegTable st2 = make_segs(segs);
+    const uint32_t waves = npages;
+    hipLaunchKernelGGL(k_snappy, dim3((waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cs, st2, d_scratch, f->d_err);
+    if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
+  }
+  if (tiles) {
+    if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: tile index allocation"); }
+  }
+  if (strck) {
+    if (hipMalloc(&f->d_strck, sizeof(uint32_t) * strck) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: checkpoint allocation"); }
+  }
+  if (npages) {
+    hipLaunchKernelGGL(k_index, dim3((npages + 63) / 64), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
+                       f->d_chunks, f->d_tiles, f->d_strck, f->d_err);
+    if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
+  }
+  HIP_OR(hipEventRecord(e1, s));
+  {
+    pq_status st3 = read_err(f, s);
+    if (st3 != PQ_OK) { cleanup_open(); free_handle(f); return st3; }
+  }
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (npages) OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
+  cleanup_open();
+#undef OPEN_HIP
+#undef OPEN_ERR
+
+  // ---- statistics ----
+  pq_file_stats& S = f->stats;
+  for (const PageDev& pg : f->pages) {
+    if (pg.kind == PAGE_DICT) S.dict_pages++;
+    else S.pages++;
+    if (pg.scratch_len) S.compressed_pages++;
+    S.encoded_bytes += pg.comp_size;
+    S.uncompressed_bytes += pg.uncomp_size;
+  }
+  S.tiles = (int64_t)tiles;
+  S.open_ms_device = ms;
+  (void)t0;
+  *out = f;
+  return PQ_OK;
+}
+
+extern "C" void pq_close(pq_file f) { free_handle(f); }
+
+extern "C" pq_status pq_num_row_groups(pq_file f, int32_t* n) {
+  if (!f || !n) return fail(PQ_EINVAL, "NULL argument");
+  *n = f->nrg;
+  return PQ_OK;
+}
+extern "C" pq_status pq_num_columns(pq_file f, int32_t* n) {
+  if (!f || !n) return fail(PQ_EINVAL, "NULL argument");
+  *n = f->ncols;
+  return PQ_OK;
+}
+extern "C" pq_status pq_column_info_get(pq_file f, int32_t col, pq_column_info* out) {
+  if (!f || !out || col < 0 || col >= f->ncols) return fail(PQ_EINVAL, "bad column");
+  out->type = f->cols[col].type;
+  out->nullable = f->cols[col].optional;
+  memset(out->name, 0, sizeof(out->name));
+  strncpy(out->name, f->cols[col].name.c_str(), sizeof(out->name) - 1);
+  return PQ_OK;
+}
+extern "C" pq_status pq_row_group_rows(pq_file f, int32_t rg, int64_t* rows) {
+  if (!f || !rows || rg < 0 || rg >= f->nrg) return fail(PQ_EINVAL, "bad row group");
+  *rows = f->rg_rows[rg];
+  return PQ_OK;
+}
+extern "C" pq_status pq_file_stats_get(pq_file f, pq_file_stats* out) {
+  if (!f || !out) return fail(PQ_EINVAL, "NULL argument");
+  *out = f->stats;
+  return PQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scan planning
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+  std::vector<ColScan> cols;
+  std::vector<DictSlot> slots;
+  int64_t rows = 0;
+  uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
+  // launch lists
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, str_segs;
+  std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
+  std::vector<int32_t> str_cols;    // string ColScan indices
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_wgs = 0, fixed_wgs = 0, str_wgs = 0;
+  uint32_t dict_grid_x = 0;
+  uint64_t ws_which = 0;
+};
+
+pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P) {
+  if (rg_b < 0 || rg_e > f->nrg || rg_b > rg_e) return fail(PQ_EINVAL, "bad row-group range [%d, %d)", rg_b, rg_e);
+  if (f->ncols < 64 && (mask >> f->ncols)) return fail(PQ_EINVAL, "column mask selects missing columns");
+  P.rows = f->rg_row0[rg_e] - f->rg_row0[rg_b];
+  uint64_t off = 0;
+  int ncs = __builtin_popcountll(mask);
+  P.ws_cols = off;
+  off = align_up(off + sizeof(ColScan) * (ncs ? ncs : 1), 256);
+  P.ws_which = off;
+  off = align_up(off + sizeof(int32_t) * 64, 256);
+  // dictionary slots: one per scanned chunk
+  const int nch = rg_e - rg_b;
+  P.ws_slots = off;
+  off = align_up(off + sizeof(DictSlot) * (size_t)(ncs * nch ? ncs * nch : 1), 256);
+  for (int c = 0; c < f->ncols; ++c) {
+    if (!((mask >> c) & 1)) continue;
+    ColScan cs;
+    memset(&cs, 0, sizeof(cs));
+    cs.type = f->cols[c].type;
+    cs.optional = f->cols[c].optional;
+    cs.width = cs.type == T_INT32 ? 4 : (cs.type == T_BYTE_ARRAY ? 0 : 8);
+    cs.col = c;
+    const uint32_t q0 = (uint32_t)(c * f->nrg + rg_b), q1 = (uint32_t)(c * f->nrg + rg_e);
+    cs.tile_begin = f->chunk_tile0[q0];
+    cs.tile_end = f->chunk_tile0[q1];
+    cs.page_begin = f->chunk_page0[q0];
+    cs.page_end = f->chunk_page0[q1];
+    cs.row_base = f->rg_row0[rg_b];
+    cs.rows = P.rows;
+    cs.scratch_base = f->scratch_prefix[cs.page_begin];
+    const uint64_t sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
+    cs.ws_scratch = off;
+    off = align_up(off + sbytes, 256);
+    cs.dict_slot0 = (uint32_t)P.slots.size();
+    cs.rg_begin = rg_b;
+    cs.nrg = f->nrg;
+    for (int g = rg_b; g < rg_e; ++g) {
+      const uint32_t q = (uint32_t)(c * f->nrg + g);
+      DictSlot sl;
+      memset(&sl, 0, sizeof(sl));
+      sl.page = ~0u;
+      if (f->chunk_page0[q] < f->chunk_page0[q + 1] && f->pages[f->chunk_page0[q]].kind == PAGE_DICT) {
+        const PageDev& dp = f->pages[f->chunk_page0[q]];
+        sl.page = f->chunk_page0[q];
+        sl.n = (uint32_t)dp.num_values;
+        sl.ws_entries = off;
+        const uint64_t bytes = cs.type == T_BYTE_ARRAY ? 8ull * sl.n : (uint64_t)cs.width * sl.n;
+        off = align_up(off + bytes + 16, 256);
+        const uint32_t gx = cs.type == T_BYTE_ARRAY ? (sl.n / STR_CK + 1 + 255) / 256 : (sl.n + 8191) / 8192;
+        P.dict_grid_x = std::max(P.dict_grid_x, std::max(gx, 1u));
+      }
+      P.slots.push_back(sl);
+    }
+    bool has_delta = false;
+    if (cs.type != T_BYTE_ARRAY)
+      for (uint32_t p = cs.page_begin; p < cs.page_end; ++p)
+        if (f->pages[p].kind != PAGE_DICT && f->pages[p].encoding == E_DELTA) { has_delta = true; break; }
+    const uint32_t nt = cs.tile_end - cs.tile_begin;
+    if (cs.type == T_BYTE_ARRAY || has_delta) {
+      cs.ws_tile_aux = off;
+      off = align_up(off + 8ull * (nt + 1), 256);
+    }
+    const uint32_t idx = (uint32_t)P.cols.size();
+    if (nt) {
+      if (cs.type == T_BYTE_ARRAY) {
+        P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_wgs});
+        P.pre_wgs += nt;
+        P.str_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_wgs});
+        P.str_wgs += nt;
+      } else {
+        if (has_delta) {
+          P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_wgs});
+          P.pre_wgs += nt;
+        }
+        P.fixed_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_wgs});
+        P.fixed_wgs += nt;
+      }
+      P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
+      P.prep_threads += nt;
+    }
+    if (cs.type == T_BYTE_ARRAY || has_delta) P.scan_cols.push_back((int32_t)idx);
+    if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
+    if (sbytes) {
+      P.snappy_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.snappy_waves});
+      P.snappy_waves += cs.page_end - cs.page_begin;
+    }
+    P.cols.push_back(cs);
+  }
+  P.ws_total = std::max<uint64_t>(off, 256);
+  return PQ_OK;
+}
+
+}  // namespace
+
+static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool plan_only) {
+  ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
+  DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
+  int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
+  if (!P.cols.empty()) HIP_OR(hipMemcpyAsync(d_cols, P.cols.data(), sizeof(ColScan) * P.cols.size(), hipMemcpyHostToDevice, s));
+  if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
+  if (!P.scan_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.scan_cols.data(), sizeof(int32_t) * P.scan_cols.size(), hipMemcpyHostToDevice, s));
+  const uint8_t* file = f->file;
+  if (P.snappy_waves) {
+    if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
+    hipLaunchKernelGGL(k_snappy, dim3((P.snappy_waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cols,
+                       make_segs(P.snappy_segs), ws, f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (!P.slots.empty() && P.dict_grid_x) {
+    hipLaunchKernelGGL(k_dict, dim3((uint32_t)P.slots.size(), P.dict_grid_x), dim3(256), 0, s, file, ws, d_cols,
+                       (int)P.cols.size(), f->d_pages, d_slots, f->d_strck, f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.pre_wgs) {
+    hipLaunchKernelGGL(k_prepass, dim3(P.pre_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles, d_slots,
+                       make_segs(P.pre_segs), f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (!P.scan_cols.empty()) {
+    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, s, ws, d_cols, d_which, f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (plan_only) return PQ_OK;
+  if (P.prep_threads) {
+    hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
+                       make_segs(P.prep_segs));
+    HIP_OR(hipGetLastError());
+  }
+  if (P.fixed_wgs) {
+    hipLaunchKernelGGL(k_decode_fixed, dim3(P.fixed_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
+                       d_slots, make_segs(P.fixed_segs), f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.str_wgs) {
+    hipLaunchKernelGGL(k_decode_str, dim3(P.str_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
+                       d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
+                             uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream) {
+  if (!f || !out) return fail(PQ_EINVAL, "NULL argument");
+  Plan P;
+  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
+  if (st != PQ_OK) return st;
+  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+  out->rows = P.rows;
+  out->workspace_bytes = P.ws_total;
+  for (int k = 0; k < 64; ++k) out->chars_bytes[k] = 0;
+  for (size_t k = 0; k < P.cols.size(); ++k)
+    if (P.cols[k].type == T_BYTE_ARRAY) out->chars_bytes[k] = -1;
+  if (!workspace || P.str_cols.empty()) return PQ_OK;
+  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned");
+  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  // the plan pass must not trip the capacity check
+  for (ColScan& cs : P.cols) { cs.chars_capacity = ~0ull; cs.offsets = nullptr; }
+  st = enqueue(f, P, (uint8_t*)workspace, s, true);
+  if (st != PQ_OK) return st;
+  std::vector<uint64_t> tot(P.str_cols.size());
+  for (size_t k = 0; k < P.str_cols.size(); ++k) {
+    const ColScan& cs = P.cols[P.str_cols[k]];
+    HIP_OR(hipMemcpyAsync(&tot[k], (uint8_t*)workspace + cs.ws_tile_aux + 8ull * (cs.tile_end - cs.tile_begin), 8,
+                          hipMemcpyDeviceToHost, s));
+  }
+  st = read_err(f, s);
+  if (st != PQ_OK) return st;
+  for (size_t k = 0; k < P.str_cols.size(); ++k) out->chars_bytes[P.str_cols[k]] = (int64_t)tot[k];
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
+                             int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  Plan P;
+  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
+  if (st != PQ_OK) return st;
+  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+  if ((int32_t)P.cols.size() != n_outs) return fail(PQ_EINVAL, "n_outs (%d) differs from the mask's columns (%d)", n_outs, (int)P.cols.size());
+  if (n_outs && !outs) return fail(PQ_EINVAL, "outs is NULL");
+  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned (%llu < %llu)",
+                                                (unsigned long long)workspace_bytes, (unsigned long long)P.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
+  for (size_t k = 0; k < P.cols.size(); ++k) {
+    ColScan& cs = P.cols[k];
+    const pq_column_out& o = outs[k];
+    if (o.validity && ((uintptr_t)o.validity & 3)) return fail(PQ_EINVAL, "column %d: validity must be 4-byte aligned", cs.col);
+    if (cs.type == T_BYTE_ARRAY) {
+      if (P.rows > 0 && !o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);
+      if (!o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);
+      if (o.chars_capacity && !o.chars) return fail(PQ_EINVAL, "column %d: chars is NULL", cs.col);
+      cs.offsets = o.offsets;
+      cs.chars = o.chars;
+      cs.chars_capacity = o.chars ? o.chars_capacity : 0;
+    } else {
+      if (P.rows > 0 && !o.values) return fail(PQ_EINVAL, "column %d: values is NULL", cs.col);
+      if ((uintptr_t)o.values % (uint64_t)cs.width) return fail(PQ_EINVAL, "column %d: values misaligned", cs.col);
+      cs.values = o.values;
+    }
+    cs.validity = o.validity;
+  }
+  return enqueue(f, P, (uint8_t*)workspace, (hipStream_t)stream, false);
+}
+
+extern "C" pq_status pq_scan_check(pq_file f, pq_stream stream) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  return read_err(f, (hipStream_t)stream);
+}

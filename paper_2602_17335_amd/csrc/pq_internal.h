@@ -1,0 +1,141 @@
+// pq_internal.h -- data structures shared by the host library and the
+// kernels of the GPU scan (chunk table, page table, tile index, per-scan
+// column table).
+#pragma once
+#include <stdint.h>
+
+namespace pqk {
+
+// ---------------------------------------------------------------------------
+// format constants (Apache Parquet format description)
+// ---------------------------------------------------------------------------
+enum : int32_t { T_INT32 = 1, T_INT64 = 2, T_DOUBLE = 5, T_BYTE_ARRAY = 6 };
+enum : int32_t { E_PLAIN = 0, E_PLAIN_DICT = 2, E_RLE = 3, E_DELTA = 5, E_RLE_DICT = 8 };
+enum : int32_t { PAGE_DATA = 0, PAGE_INDEX = 1, PAGE_DICT = 2, PAGE_DATA_V2 = 3 };
+
+// device error codes (first error wins; stored as code | (where << 8))
+enum : uint32_t {
+  ERR_NONE = 0,
+  ERR_HEADER = 1,        // page header malformed
+  ERR_CHUNK_BOUNDS = 2,  // a page leaves its column chunk
+  ERR_PAGE_ORDER = 3,    // dictionary page not first / twice
+  ERR_ROWS = 4,          // page value counts do not add up to the row group
+  ERR_LEVELS = 5,        // definition-level stream truncated or level > 1
+  ERR_VALUES = 6,        // value stream truncated
+  ERR_DICT_INDEX = 7,    // dictionary index >= dictionary size
+  ERR_DELTA = 8,         // DELTA_BINARY_PACKED header/body invalid
+  ERR_SNAPPY = 9,        // Snappy stream invalid
+  ERR_UNSUPPORTED = 10,  // encoding / feature outside the supported subset
+  ERR_DICT_MISSING = 11, // dictionary-encoded page without a dictionary
+  ERR_V2 = 12,           // V2 header inconsistent
+  ERR_STRING = 13,       // BYTE_ARRAY length chain invalid
+  ERR_CAPACITY = 14      // chars buffer smaller than the decoded strings
+};
+
+// Tile = fixed number of rows of one data page.
+constexpr int TILE_ROWS = 4096;
+// BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
+// string dictionary pages.
+constexpr int STR_CK = 32;
+// Bytes of slack after every decompressed region (reads run up to 12 bytes
+// past a stream end).
+constexpr int SCRATCH_PAD = 16;
+
+struct ChunkDev {
+  uint64_t start, end;   // byte range of the column chunk in the file
+  int64_t rows;          // row-group rows
+  int32_t type;          // physical type
+  int32_t codec;         // 0 none, 1 snappy
+  int32_t optional;
+  int32_t col;
+};
+
+// Page table entry (one per page, dictionary pages included), in
+// column-major chunk order: column 0 rg 0.., column 1 rg 0.., ...
+struct PageDev {
+  uint64_t payload;      // file offset of the page payload
+  uint32_t comp_size;    // compressed_page_size
+  uint32_t uncomp_size;  // uncompressed_page_size
+  int32_t num_values;    // rows of the page (flat schema); entries for dictionary pages
+  int32_t num_nulls;     // V2 header value; -1 for V1
+  uint32_t chunk;        // chunk index (col * nrg + rg)
+  uint8_t kind;          // PAGE_DATA, PAGE_DICT, PAGE_DATA_V2 (index pages are dropped)
+  uint8_t encoding;
+  uint8_t v2_compressed; // V2 is_compressed flag (default 1)
+  uint8_t flags;         // bit0: level stream in scratch; bit1: value stream in scratch
+  int32_t def_len;       // level bytes (V2 header; V1 from the body)
+  int32_t rep_len;       // V2 header
+  uint64_t def_off;      // file offset, or offset inside the page's scratch region
+  uint64_t val_off;      // same for the value stream
+  uint32_t val_len;
+  uint32_t scratch_len;  // decompressed bytes written to scratch (0: not compressed)
+  uint64_t scratch_off;  // offset of this page's region in the file-wide scratch layout
+  int64_t row0;          // file row of the page's first row
+  uint32_t tile_begin;   // first tile of this page
+  uint32_t nonnull;      // non-null values (filled by the index pass)
+  uint32_t strck_begin;  // first string checkpoint (PLAIN strings / string dictionaries)
+  uint32_t dict_page;    // data pages: page index of the chunk's dictionary page (~0u: none)
+};
+
+// One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.
+struct TileDev {
+  uint32_t page;
+  uint32_t row0;      // page-relative
+  uint32_t k0;        // non-null values before row0 in the page
+  uint32_t nn;        // non-null values inside the tile
+  uint32_t def_pos;   // level stream: byte offset of the run header holding row0
+  uint32_t def_skip;  // values of that run before row0
+  uint32_t val_pos;   // value stream entry: run header (dictionary), block header
+                      // (DELTA), byte offset of value k0 (PLAIN strings)
+  uint32_t val_skip;  // dictionary/DELTA: values of that run/block before k0;
+                      // PLAIN strings: byte offset just past the tile's last value
+};
+
+// Decoded dictionary of one column chunk inside the workspace.
+struct DictSlot {
+  const uint8_t* body;   // dictionary page body (file or scratch), set on the device
+  uint64_t ws_entries;   // workspace offset: fixed-width entries, or (pos,len) u32 pairs
+  uint32_t n;            // entries (0: chunk has no dictionary)
+  uint32_t page;         // dictionary page index (~0u: none)
+};
+
+// Per-scan, per-selected-column table (built on the host, copied into the
+// caller's workspace before the kernels run).
+struct ColScan {
+  int32_t type;
+  int32_t optional;
+  int32_t width;          // 4 or 8 (fixed width); 0 for BYTE_ARRAY
+  int32_t col;
+  uint32_t tile_begin;    // tiles of this column inside the scan: [tile_begin, tile_end)
+  uint32_t tile_end;
+  uint32_t page_begin;    // pages (incl. dictionary pages) of the scanned chunks
+  uint32_t page_end;
+  int64_t row_base;       // file row of the scan's first output row
+  int64_t rows;           // output rows
+  uint64_t scratch_base;  // file-wide scratch offset of this column's first scanned page
+  uint64_t ws_scratch;    // workspace offset where this column's decompressed pages start
+  uint32_t dict_slot0;    // first DictSlot of this column (one per scanned chunk)
+  int32_t rg_begin;       // first scanned row group
+  uint64_t ws_tile_aux;   // workspace offset of per-tile int64 auxiliaries
+  uint64_t chars_capacity;
+  void* values;
+  uint8_t* validity;
+  int64_t* offsets;
+  uint8_t* chars;
+  int32_t nrg;            // row groups in the file (chunk = col * nrg + rg)
+  int32_t pad_;
+};
+
+// A run of tiles handled by one launch: ColScan `cs`, tiles [t0, t1),
+// workgroups [wg0, wg0 + t1 - t0).
+struct Segment {
+  uint32_t cs, t0, t1, wg0;
+};
+constexpr int MAX_SEGS = 64;
+struct SegTable {
+  Segment s[MAX_SEGS];
+  int32_t n;
+  int32_t pad_;
+};
+
+}  // namespace pqk

@@ -1,0 +1,373 @@
+// pq_open_kernels.hip -- kernels that run once when a file is opened:
+//   k_walk   page-header walk of every column chunk -> device page table
+//   k_index  tile index: entry positions of every TILE_ROWS-row tile in the
+//            level and value streams of each data page, string checkpoints.
+#include <hip/hip_runtime.h>
+
+#include "pq_device.hpp"
+#include "pq_internal.h"
+
+namespace pqk {
+
+// One lane per column chunk.  Walks PageHeader, payload, PageHeader, ...
+// from the chunk start until the chunk's byte range is consumed.  With
+// `pages == nullptr` it only counts pages (first pass); otherwise it writes
+// the page table entries at page_base[chunk].
+__global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
+                       const uint32_t* page_base, PageDev* pages, uint32_t* err) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nchunks) return;
+  ChunkDev c = chunks[q];
+  BR r;
+  r.init(file);
+  uint64_t pos = c.start;
+  uint32_t n = 0;
+  int64_t rows = 0;
+  bool seen_data = false, seen_dict = false;
+  while (pos < c.end) {
+    PageHdr h;
+    if (!parse_page_header(r, pos, c.end, h) || h.type < 0 || h.unc < 0 || h.comp < 0) { set_err(err, ERR_HEADER, q); return; }
+    uint64_t payload = pos;
+    if ((uint64_t)h.comp > c.end - payload) { set_err(err, ERR_CHUNK_BOUNDS, q); return; }
+    pos = payload + (uint64_t)h.comp;
+    if (h.type == PAGE_DICT) {
+      if (seen_data || seen_dict) { set_err(err, ERR_PAGE_ORDER, q); return; }
+      if (!h.has_sub || h.nv < 0) { set_err(err, ERR_HEADER, q); return; }
+      if (h.enc != E_PLAIN && h.enc != E_PLAIN_DICT) { set_err(err, ERR_UNSUPPORTED, q); return; }
+      if (c.codec == 0 && h.comp != h.unc) { set_err(err, ERR_HEADER, q); return; }
+      seen_dict = true;
+    } else if (h.type == PAGE_DATA || h.type == PAGE_DATA_V2) {
+      if (!h.has_sub || h.nv < 0) { set_err(err, ERR_HEADER, q); return; }
+      bool enc_ok = h.enc == E_PLAIN || h.enc == E_PLAIN_DICT || h.enc == E_RLE_DICT ||
+                    (h.enc == E_DELTA && (c.type == T_INT32 || c.type == T_INT64));
+      if (!enc_ok) { set_err(err, ERR_UNSUPPORTED, q); return; }
+      if (h.type == PAGE_DATA_V2) {
+        if (h.rep_len != 0) { set_err(err, ERR_UNSUPPORTED, q); return; }
+        if (h.def_len < 0 || h.nrows != h.nv || h.def_len > h.comp || h.def_len > h.unc || h.nnulls < 0 ||
+            (!c.optional && (h.def_len != 0 || h.nnulls != 0))) { set_err(err, ERR_V2, q); return; }
+        bool compressed = c.codec == 1 && h.is_comp;
+        if (!compressed && h.comp != h.unc) { set_err(err, ERR_V2, q); return; }
+      } else if (c.codec == 0 && h.comp != h.unc) { set_err(err, ERR_HEADER, q); return; }
+      rows += h.nv;
+      if (rows > c.rows) { set_err(err, ERR_ROWS, q); return; }
+      seen_data = true;
+    } else {
+      continue;  // index pages and unknown page types are skipped
+    }
+    if (pages) {
+      PageDev p;
+      p.payload = payload;
+      p.comp_size = (uint32_t)h.comp;
+      p.uncomp_size = (uint32_t)h.unc;
+      p.num_values = h.nv;
+      p.num_nulls = h.type == PAGE_DATA_V2 ? h.nnulls : -1;
+      p.chunk = (uint32_t)q;
+      p.kind = (uint8_t)h.type;
+      p.encoding = (uint8_t)h.enc;
+      p.v2_compressed = (uint8_t)(h.type == PAGE_DATA_V2 ? h.is_comp : 1);
+      p.flags = 0;
+      p.def_len = h.type == PAGE_DATA_V2 ? h.def_len : 0;
+      p.rep_len = h.type == PAGE_DATA_V2 ? h.rep_len : 0;
+      p.def_off = 0; p.val_off = 0; p.val_len = 0;
+      p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
+      p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u;
+      pages[page_base[q] + n] = p;
+    }
+    ++n;
+  }
+  if (pos != c.end || rows != c.rows) { set_err(err, ERR_ROWS, q); return; }
+  if (counts) counts[q] = n;
+}
+
+// Hybrid-run cursor used by the index pass (one lane).
+struct RunCur {
+  uint64_t hp;     // header position of the current run
+  uint64_t next;   // position after the current run
+  int64_t start;   // first value index of the current run
+  uint64_t n;      // values in the run
+  int bp;          // bit-packed?
+  uint64_t pay;    // payload byte position (bit-packed)
+  uint32_t val;    // RLE value
+};
+
+// Reads the run header at cur.next; returns false when the stream ends or a
+// run leaves it.
+__device__ inline bool run_next(BR& r, uint64_t end, uint32_t w, RunCur& c) {
+  uint64_t pos = c.next;
+  c.start += (int64_t)c.n;
+  c.hp = pos;
+  bool bad = false;
+  uint64_t h = br_uleb(r, pos, end, bad);
+  if (bad) return false;
+  if (h & 1) {
+    uint64_t g = h >> 1;
+    if (g > (1ull << 28)) return false;
+    c.bp = 1;
+    c.n = g * 8;
+    c.pay = pos;
+    uint64_t nb = g * w;
+    if (nb > end - pos) return false;
+    c.next = pos + nb;
+    c.val = 0;
+  } else {
+    c.bp = 0;
+    c.n = h >> 1;
+    uint32_t vb = (w + 7) / 8;
+    if (vb > end - pos) return false;
+    uint32_t v = 0;
+    for (uint32_t j = 0; j < vb; ++j) v |= r.byte(pos + j) << (8 * j);
+    c.val = v;
+    c.pay = pos;
+    c.next = pos + vb;
+  }
+  return true;
+}
+
+// number of set bits among the first `k` values of a bit-packed w=1 run
+__device__ inline uint32_t bp_popcount(BR& r, uint64_t pay, uint64_t k) {
+  uint32_t s = 0;
+  uint64_t full = k >> 3;
+  for (uint64_t i = 0; i < full; ++i) s += __popc(r.byte(pay + i));
+  uint32_t rem = (uint32_t)(k & 7);
+  if (rem) s += __popc(r.byte(pay + full) & ((1u << rem) - 1));
+  return s;
+}
+
+// One lane per page.  `scratch` holds every compressed page decompressed at
+// its file-wide scratch offset.
+__global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* err) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npages) return;
+  PageDev pg = pages[p];
+  ChunkDev ch = chunks[pg.chunk];
+  const bool in_scratch = pg.scratch_len > 0;
+  BR r;
+
+  if (pg.kind == PAGE_DICT) {
+    const uint8_t* base = in_scratch ? scratch : file;
+    uint64_t off = in_scratch ? pg.scratch_off : pg.payload;
+    uint64_t blen = pg.uncomp_size;
+    pg.val_off = off;
+    pg.val_len = (uint32_t)blen;
+    pg.flags = in_scratch ? 2 : 0;
+    if (ch.type == T_BYTE_ARRAY) {
+      r.init(base);
+      uint64_t q = 0;
+      for (int64_t k = 0; k < pg.num_values; ++k) {
+        if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = (uint32_t)q;
+        if (blen - q < 4) { set_err(err, ERR_STRING, p); return; }
+        uint32_t l = r.u32(off + q);
+        q += 4;
+        if (l > blen - q) { set_err(err, ERR_STRING, p); return; }
+        q += l;
+      }
+    } else {
+      uint64_t w = ch.type == T_INT32 ? 4 : 8;
+      if ((uint64_t)pg.num_values * w > blen) { set_err(err, ERR_VALUES, p); return; }
+    }
+    pages[p] = pg;
+    return;
+  }
+
+  // ---- stream layout of a data page ----
+  const uint8_t* dbase;
+  const uint8_t* vbase;
+  uint64_t def_off = 0, def_len = 0, val_off = 0, val_len = 0;
+  if (pg.kind == PAGE_DATA) {
+    const uint8_t* base = in_scratch ? scratch : file;
+    uint64_t off = in_scratch ? pg.scratch_off : pg.payload;
+    uint64_t blen = pg.uncomp_size;
+    dbase = vbase = base;
+    r.init(base);
+    if (ch.optional) {
+      if (blen < 4) { set_err(err, ERR_LEVELS, p); return; }
+      uint64_t L = r.u32(off);
+      if (L > blen - 4) { set_err(err, ERR_LEVELS, p); return; }
+      def_off = off + 4; def_len = L;
+      val_off = off + 4 + L; val_len = blen - 4 - L;
+    } else {
+      val_off = off; val_len = blen;
+    }
+    pg.flags = in_scratch ? 3 : 0;
+  } else {
+    dbase = file;
+    def_off = pg.payload + (uint64_t)pg.rep_len;
+    def_len = (uint64_t)pg.def_len;
+    if (in_scratch) {
+      vbase = scratch;
+      val_off = pg.scratch_off;
+      val_len = pg.scratch_len;
+      pg.flags = 2;
+    } else {
+      vbase = file;
+      val_off = def_off + def_len;
+      val_len = pg.comp_size - (uint64_t)pg.rep_len - def_len;
+      pg.flags = 0;
+    }
+  }
+  pg.def_off = def_off;
+  pg.def_len = (int32_t)def_len;
+  pg.val_off = val_off;
+  pg.val_len = (uint32_t)val_len;
+
+  const int64_t nv = pg.num_values;
+  const uint32_t ntiles = (uint32_t)((nv + TILE_ROWS - 1) / TILE_ROWS);
+
+  // ---- definition levels: tile entry points and non-null counts ----
+  uint32_t nonnull = 0;
+  if (ch.optional) {
+    r.init(dbase);
+    const uint64_t end = def_off + def_len;
+    RunCur c;
+    c.next = def_off; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = def_off;
+    uint64_t before = 0;  // valid rows in runs before the current one
+    bool have = false;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+      const int64_t target = (int64_t)t * TILE_ROWS;
+      while (!have || c.start + (int64_t)c.n <= target) {
+        if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
+        if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
+        have = true;
+      }
+      const uint64_t skip = (uint64_t)(target - c.start);
+      TileDev td;
+      td.page = (uint32_t)p;
+      td.row0 = (uint32_t)target;
+      td.k0 = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, skip) : (uint64_t)c.val * skip));
+      td.nn = 0;
+      td.def_pos = (uint32_t)(c.hp - def_off);
+      td.def_skip = (uint32_t)skip;
+      td.val_pos = 0;
+      td.val_skip = 0;
+      tiles[pg.tile_begin + t] = td;
+    }
+    if (nv > 0) {
+      while (!have || c.start + (int64_t)c.n < nv) {
+        if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
+        if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
+        have = true;
+      }
+      const uint64_t part = (uint64_t)(nv - c.start);
+      nonnull = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, part) : (uint64_t)c.val * part));
+    }
+  } else {
+    nonnull = (uint32_t)nv;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+      TileDev td;
+      td.page = (uint32_t)p;
+      td.row0 = t * TILE_ROWS;
+      td.k0 = t * TILE_ROWS;
+      td.nn = 0;
+      td.def_pos = 0; td.def_skip = 0; td.val_pos = 0; td.val_skip = 0;
+      tiles[pg.tile_begin + t] = td;
+    }
+  }
+  if (pg.kind == PAGE_DATA_V2 && (int64_t)pg.num_nulls != nv - (int64_t)nonnull) { set_err(err, ERR_V2, p); return; }
+  pg.nonnull = nonnull;
+  for (uint32_t t = 0; t < ntiles; ++t) {
+    uint32_t k0 = tiles[pg.tile_begin + t].k0;
+    uint32_t k1 = t + 1 < ntiles ? tiles[pg.tile_begin + t + 1].k0 : nonnull;
+    tiles[pg.tile_begin + t].nn = k1 - k0;
+  }
+
+  // ---- value stream entry points ----
+  r.init(vbase);
+  const uint64_t vend = val_off + val_len;
+  const int enc = pg.encoding;
+  if (enc == E_PLAIN && ch.type != T_BYTE_ARRAY) {
+    uint64_t w = ch.type == T_INT32 ? 4 : 8;
+    if ((uint64_t)nonnull * w > val_len) { set_err(err, ERR_VALUES, p); return; }
+  } else if (enc == E_PLAIN) {
+    uint64_t q = val_off;
+    uint32_t t = 0;
+    for (uint32_t k = 0; k <= nonnull; ++k) {
+      while (t < ntiles && tiles[pg.tile_begin + t].k0 == k) {
+        tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
+        if (t > 0) tiles[pg.tile_begin + t - 1].val_skip = (uint32_t)(q - val_off);
+        ++t;
+      }
+      if (k == nonnull) break;
+      if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = (uint32_t)(q - val_off);
+      if (vend - q < 4) { set_err(err, ERR_STRING, p); return; }
+      uint32_t l = r.u32(q);
+      q += 4;
+      if (l > vend - q) { set_err(err, ERR_STRING, p); return; }
+      q += l;
+    }
+    if (ntiles > 0) tiles[pg.tile_begin + ntiles - 1].val_skip = (uint32_t)(q - val_off);
+  } else if (enc == E_PLAIN_DICT || enc == E_RLE_DICT) {
+    if (pg.dict_page == ~0u) { set_err(err, ERR_DICT_MISSING, p); return; }
+    if (nonnull > 0) {
+      if (val_len < 1) { set_err(err, ERR_VALUES, p); return; }
+      const uint32_t w = r.byte(val_off);
+      if (w > 32) { set_err(err, ERR_VALUES, p); return; }
+      RunCur c;
+      c.next = val_off + 1; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = val_off + 1;
+      bool have = false;
+      for (uint32_t t = 0; t < ntiles; ++t) {
+        const int64_t target = (int64_t)tiles[pg.tile_begin + t].k0;
+        if (target >= (int64_t)nonnull) continue;  // tile without values
+        while (!have || c.start + (int64_t)c.n <= target) {
+          if (!run_next(r, vend, w, c)) { set_err(err, ERR_VALUES, p); return; }
+          have = true;
+        }
+        tiles[pg.tile_begin + t].val_pos = (uint32_t)(c.hp - val_off);
+        tiles[pg.tile_begin + t].val_skip = (uint32_t)(target - c.start);
+      }
+      while (!have || c.start + (int64_t)c.n < (int64_t)nonnull) {
+        if (!run_next(r, vend, w, c)) { set_err(err, ERR_VALUES, p); return; }
+        have = true;
+      }
+    }
+  } else if (enc == E_DELTA) {
+    bool bad = false;
+    uint64_t q = val_off;
+    uint64_t B = br_uleb(r, q, vend, bad), M = br_uleb(r, q, vend, bad), total = br_uleb(r, q, vend, bad);
+    br_uleb(r, q, vend, bad);
+    if (bad || B == 0 || B % 128 != 0 || M == 0 || B % M != 0 || (B / M) % 32 != 0 || total != nonnull) {
+      set_err(err, ERR_DELTA, p);
+      return;
+    }
+    if (M > 16 || B > 65536) { set_err(err, ERR_UNSUPPORTED, p); return; }
+    const uint32_t maxw = ch.type == T_INT32 ? 32 : 64;
+    const uint64_t per = B / M;
+    // block b holds values [1 + b*B, 1 + (b+1)*B); value 0 is in the header
+    const uint64_t nblocks = total > 1 ? (total - 1 + B - 1) / B : 0;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+      tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
+      tiles[pg.tile_begin + t].val_skip = 0;
+    }
+    uint32_t t = 0;
+    for (uint64_t b = 0; b < nblocks; ++b) {
+      while (t < ntiles) {
+        const TileDev td = tiles[pg.tile_begin + t];
+        const uint64_t last = (uint64_t)td.k0 + td.nn;  // one past the tile's last value
+        if (td.nn == 0 || last <= 1) { ++t; continue; }  // needs no block
+        const uint64_t first = td.k0 == 0 ? 1 : td.k0;
+        const uint64_t nb = (first - 1) / B;
+        if (nb != b) break;
+        tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
+        tiles[pg.tile_begin + t].val_skip = (uint32_t)((first - 1) % B);
+        ++t;
+      }
+      br_uleb(r, q, vend, bad);  // min delta
+      if (bad || M > vend - q) { set_err(err, ERR_DELTA, p); return; }
+      const uint64_t left = total - 1 - b * B;  // values from this block on
+      const uint64_t used = left < B ? left : B;
+      const uint64_t used_mb = (used + per - 1) / per;
+      uint64_t body = 0;
+      for (uint64_t m = 0; m < used_mb; ++m) {
+        const uint32_t w = r.byte(q + m);
+        if (w > maxw) { set_err(err, ERR_DELTA, p); return; }
+        body += per * w / 8;
+      }
+      q += M;
+      if (body > vend - q) { set_err(err, ERR_DELTA, p); return; }
+      q += body;
+    }
+  }
+  pages[p] = pg;
+}
+
+}  // namespace pqk

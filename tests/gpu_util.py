@@ -1,0 +1,59 @@
+"""Helpers shared by the GPU tests: run the HIP scan through the C ABI and
+compare every output buffer with the CPU oracle, byte for byte."""
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def gpu_scan(data, columns=None, rg_begin=0, rg_end=None):
+    import paper_2602_17335_amd as pqs
+    buf, n = pqs.to_device(data)
+    f = pqs.DeviceFile(buf, n)
+    if columns is None:
+        columns = list(range(f.num_columns))
+    out = f.scan(columns, rg_begin, rg_end)
+    return f, out
+
+
+def compare_column(o, g, name=""):
+    """o: oracle dict, g: GPU dict of torch tensors."""
+    rows = o["rows"]
+    assert g["rows"] == rows, (name, g["rows"], rows)
+    gv = g["validity"].cpu().numpy()
+    assert gv.size == o["validity"].size
+    if not (gv == o["validity"]).all():
+        bad = np.nonzero(gv != o["validity"])[0]
+        raise AssertionError(f"{name}: validity differs at bytes {bad[:10]} (of {bad.size})")
+    if "offsets" in o:
+        goff = g["offsets"].cpu().numpy()
+        if not (goff == o["offsets"]).all():
+            bad = np.nonzero(goff != o["offsets"])[0]
+            raise AssertionError(f"{name}: offsets differ at rows {bad[:10]} (of {bad.size}): "
+                                 f"gpu {goff[bad[:5]]} oracle {o['offsets'][bad[:5]]}")
+        gch = g["chars"].cpu().numpy()
+        assert gch.size == o["chars"].size, (name, gch.size, o["chars"].size)
+        if not (gch == o["chars"]).all():
+            bad = np.nonzero(gch != o["chars"])[0]
+            raise AssertionError(f"{name}: chars differ at {bad[:10]} (of {bad.size})")
+    else:
+        gvals = g["values"].cpu().numpy().view(np.uint8)
+        ov = o["values"].view(np.uint8)
+        if not (gvals == ov).all():
+            w = o["values"].itemsize
+            bad = np.nonzero((gvals != ov).reshape(-1, w).any(axis=1))[0]
+            raise AssertionError(f"{name}: values differ at rows {bad[:10]} (of {bad.size}): "
+                                 f"gpu {g['values'].cpu().numpy()[bad[:5]]} oracle {o['values'][bad[:5]]}")
+
+
+def check_file(data, columns=None, rg_begin=0, rg_end=None, label=""):
+    print(f"[gpu] {label}: {len(data)} bytes cols={columns} rg=[{rg_begin},{rg_end})", flush=True)
+    sys.stdout.flush()
+    f, out = gpu_scan(data, columns, rg_begin, rg_end)
+    ofile = oracle.File(data)
+    if rg_end is None:
+        rg_end = ofile.num_row_groups
+    for c, g in out.items():
+        compare_column(ofile.read(c, rg_begin, rg_end), g, f"{label} col{c}")
+    return f
