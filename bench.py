@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU Parquet scan: decoded GB/s and % of HBM peak.
+
+One step = one pq_scan of every selected column of a device-resident file
+(Snappy decompression when the file is compressed, dictionary decode, DELTA
+and string prefix passes, and the decode kernels), with the file already in
+HBM when the timed region starts.  The default workload is the 16-column
+wide fact table: 64,000,000 rows, one 64M-row row group, 1 MiB pages,
+uncompressed, every column OPTIONAL with 10% nulls (synthetic, seeded; it
+stands in for the paper's TPC-H lineitem scans, Sec. 3 setup).
+
+Prints one JSON line.  Per-kernel device times come from HIP events that the
+library records around each kernel on the scan's stream; the dominant
+kernel's algorithmic bytes over its average duration give the roofline
+fraction against the MI355X's 8 TB/s HBM peak.  The CPU baseline is the
+plain single-threaded oracle on a bounded sample of the same recipe.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Parquet scan decoded GB/s & % HBM peak; batched vs plain form; p99 latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_2602_17335_amd/csrc/pq_scan_kernels.hip", "paper_2602_17335_amd/csrc/pq_device.hpp",
+                "paper_2602_17335_amd/csrc/pq_internal.h"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def decoded_bytes(out_tensors, types):
+    """Bytes of the decoded result: values (null slots included), the
+    validity bitmap, int64 offsets and chars."""
+    total = 0
+    for c, t in out_tensors.items():
+        rows = t["rows"]
+        total += (rows + 7) // 8
+        if "offsets" in t:
+            total += 8 * (rows + 1) + t["chars_bytes"]
+        else:
+            total += rows * (4 if types[c] == 1 else 8)
+    return total
+
+
+def algorithmic_bytes(kernel, f, cols, types, out_tensors, rows):
+    """Bytes one launch of `kernel` must move: encoded page bytes it reads
+    plus decoded bytes it writes (dictionary gathers served by the caches
+    are not counted)."""
+    b = 0
+    for c in cols:
+        data, dic = f.column_bytes(c)
+        t = out_tensors[c]
+        is_str = types[c] == 6
+        if kernel == "k_decode_fixed" and not is_str:
+            b += data + rows * (4 if types[c] == 1 else 8) + (rows + 7) // 8
+        elif kernel == "k_decode_str" and is_str:
+            b += data + 8 * (rows + 1) + t["chars_bytes"] + (rows + 7) // 8
+    return b
+
+
+def cpu_baseline(args, spec_fn):
+    import datagen as dg
+    import oracle
+    spec = spec_fn(args.cpu_rows, args.cpu_rows)
+    data = dg.write(spec, nthreads=min(16, os.cpu_count() or 1))
+    f = oracle.File(data)
+    t0 = time.perf_counter()
+    tot = 0
+    for c in range(f.num_columns):
+        o = f.read(c)
+        tot += o["validity"].nbytes
+        tot += o["values"].nbytes if "values" in o else o["offsets"].nbytes + o["chars"].nbytes
+    dt = time.perf_counter() - t0
+    return {"value": round(tot / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"same recipe at {args.cpu_rows:,} rows (one row group, {args.page_bytes} B pages, "
+                      f"{'snappy' if args.codec == 'snappy' else 'uncompressed'}), all 16 columns, "
+                      f"{tot / 1e9:.2f} GB decoded in {dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rows", type=int, default=64_000_000)
+    ap.add_argument("--rg-rows", type=int, default=64_000_000)
+    ap.add_argument("--page-bytes", type=int, default=1 << 20)
+    ap.add_argument("--codec", choices=["none", "snappy"], default="none")
+    ap.add_argument("--columns", default="all", help="comma-separated column indices, or 'all'")
+    ap.add_argument("--cpu-rows", type=int, default=16_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
+              "(shards would be scanned independently per GPU, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import datagen as dg
+    import paper_2602_17335_amd as pqs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.codec == "snappy":
+        def spec_fn(rows, rg):
+            return dg.snappy_wide_table(rows, rg, args.page_bytes)
+    else:
+        def spec_fn(rows, rg):
+            return dg.wide_table(rows, rg, args.page_bytes)
+    spec = spec_fn(args.rows, args.rg_rows)
+    t0 = time.perf_counter()
+    data = dg.write(spec, nthreads=min(16, os.cpu_count() or 1))
+    log(f"generated {len(data) / 1e9:.3f} GB file in {time.perf_counter() - t0:.1f} s")
+    buf, nbytes = pqs.to_device(data)
+    del data
+    torch.cuda.synchronize()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        bcopy = torch.empty_like(a)
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
+        log("copy probe: 1 GiB device-to-device copy done")
+
+    t0 = time.perf_counter()
+    f = pqs.DeviceFile(buf, nbytes)
+    torch.cuda.synchronize()
+    open_ms = (time.perf_counter() - t0) * 1e3
+    st = f.stats()
+    log(f"opened: {st.pages} data pages, {st.dict_pages} dictionary pages, {st.tiles} tiles, "
+        f"open {open_ms:.1f} ms wall ({st.open_ms_device:.1f} ms device)")
+    ncols = f.num_columns
+    cols = list(range(ncols)) if args.columns == "all" else [int(x) for x in args.columns.split(",")]
+    types = {c: f.column_info(c).type for c in range(ncols)}
+    mask, rg_end, ws, outs, tens = f.allocate(cols)
+    rows = next(iter(tens.values()))["rows"]
+    dec = decoded_bytes(tens, types)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        f.scan_into(mask, 0, rg_end, outs, ws)
+    f.check()
+    log(f"warmup done ({args.warmup} scans)")
+
+    f.profile(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        f.scan_into(mask, 0, rg_end, outs, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    f.check()
+    prof = f.profile_read()
+    f.profile(False)
+    ms = total_ms / args.steps
+    value = dec / (ms / 1e3) / 1e9
+    log(f"{args.steps} scans: {ms:.3f} ms/scan, {value:.1f} GB/s decoded")
+    kern = {k: {"launches": n, "avg_ms": round(t / n, 4), "share": round(t / total_ms, 3)} for k, (n, t) in prof.items()}
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"]):
+        log(f"  {k:16s} {v['avg_ms']:8.3f} ms/launch  {v['share'] * 100:5.1f}% of the timed region")
+
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    n_l, t_l = prof[dom]
+    alg = algorithmic_bytes(dom, f, cols, types, tens, rows)
+    achieved = alg / (t_l / n_l / 1e3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            with open(tfile) as fh:
+                tj = json.load(fh)
+            key = f"{dom}|rows={args.rows}|rg={args.rg_rows}|page={args.page_bytes}|codec={args.codec}|cols={args.columns}"
+            ent = tj.get(key)
+            if ent and ent.get("kernel_source_hash") == kernel_source_hash():
+                traffic = ent["bytes_per_launch"]
+        except (OSError, ValueError, KeyError):
+            traffic = None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "algorithmic_bytes_per_launch": alg}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU baseline: oracle on a bounded sample ...")
+        cpu = cpu_baseline(args, spec_fn)
+        log(f"CPU baseline: {cpu['value']} GB/s")
+
+    workload = (f"wide16: {args.rows:,} rows, row groups of {args.rg_rows:,}, {args.page_bytes // 1024} KiB pages, "
+                f"{'Snappy' if args.codec == 'snappy' else 'uncompressed'}, 16 OPTIONAL columns with 10% nulls "
+                f"(6 INT32, 4 INT64, 3 DOUBLE, 3 BYTE_ARRAY; PLAIN / dictionary / DELTA)")
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": workload, "rows": rows, "row_group_rows": args.rg_rows, "page_bytes": args.page_bytes,
+                   "codec": args.codec, "columns": len(cols), "file_bytes": nbytes, "decoded_bytes_per_step": dec,
+                   "pages": st.pages, "dict_pages": st.dict_pages, "tiles": st.tiles,
+                   "open_ms": round(open_ms, 2), "open_ms_device": round(st.open_ms_device, 2),
+                   "form": "plain (one launch per kernel kind per scan)", "kernels": kern},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -19,9 +19,11 @@
  * concatenated in row-group order):
  *   values    fixed-width little-endian values, `rows` entries; null rows 0.
  *             DOUBLE is copied as its 64-bit pattern (no floating point).
- *   validity  LSB-first bitmap, bit i of byte i/8, 1 = valid; (rows+7)/8
- *             bytes; bits past `rows` in the last byte are 0.  May be NULL for
- *             REQUIRED columns (if given, it is set to all ones).
+ *   validity  LSB-first bitmap, bit i of byte i/8, 1 = valid.  The library
+ *             writes whole 32-bit words: the buffer must be 4-byte aligned
+ *             and hold ((rows+31)/32)*4 bytes; bits past `rows` are 0.  May
+ *             be NULL (the levels are still decoded); for REQUIRED columns a
+ *             given buffer is set to all ones.
  *   offsets   BYTE_ARRAY only: rows+1 int64 values, offsets[0] = 0,
  *             offsets[i+1] - offsets[i] = length of row i (0 for nulls).
  *   chars     BYTE_ARRAY only: the concatenated bytes of all valid rows.
@@ -80,7 +82,7 @@ typedef struct {
 /* Output buffers of one selected column. */
 typedef struct {
   void* values;          /* fixed-width columns: rows * width bytes */
-  uint8_t* validity;     /* (rows+7)/8 bytes; may be NULL for REQUIRED */
+  uint8_t* validity;     /* ((rows+31)/32)*4 bytes, 4-byte aligned; may be NULL */
   int64_t* offsets;      /* BYTE_ARRAY: rows+1 */
   uint8_t* chars;        /* BYTE_ARRAY */
   uint64_t chars_capacity;
@@ -98,7 +100,7 @@ typedef struct {
 } pq_file_stats;
 
 /*
- * Opens a Parquet file that lies in device memory (a2 and a1 of the scan).
+ * Opens a Parquet file that lies in device memory.
  *   dev_buf  device pointer to the whole file (borrowed: it must stay valid
  *            and unmodified until pq_close; it is never written).  It must be
  *            readable up to `len` rounded up to a multiple of 16 bytes, which
@@ -135,7 +137,7 @@ pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
                   uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream);
 
 /*
- * Enqueues the scan (a3..a12) on `stream` and returns without synchronising.
+ * Enqueues the scan on `stream` and returns without synchronising.
  *   outs       host array of n_outs descriptors; outs[k] belongs to the k-th
  *              set bit of col_mask in ascending order.
  *   workspace  device buffer of at least the planned workspace_bytes, owned
@@ -145,16 +147,37 @@ pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
  * device dictionaries; DELTA tile sums and string sizes, with their prefix
  * scans; then the decode kernels (definition levels -> validity and ranks,
  * dictionary indices -> gather, PLAIN, DELTA_BINARY_PACKED, BYTE_ARRAY ->
- * offsets and chars).  Returns PQ_ECAPACITY if a chars buffer is smaller
- * than needed (this check synchronises `stream` when string columns are
- * selected and chars_capacity is not at least the planned size).
+ * offsets and chars).  A chars buffer smaller than the decoded strings
+ * is reported by pq_scan_check() as PQ_ECAPACITY (no chars
+ * are written for the tiles that would overflow; nothing is written past
+ * chars_capacity).
  */
 pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
                   int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream);
+/* The workspace must be 256-byte aligned.  values must be aligned to the
+   value width.  Returns PQ_EINVAL / PQ_ECAPACITY (workspace) before
+   enqueueing anything. */
 
 /* Synchronises `stream` and returns (then clears) the handle's error word:
    PQ_OK, or PQ_ECORRUPT/PQ_EUNSUPPORTED found by a kernel. */
 pq_status pq_scan_check(pq_file f, pq_stream stream);
+
+/* Encoded bytes of column `col` over all row groups: data-page payloads
+   (levels + values as stored) and dictionary-page payloads. */
+pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes);
+
+/* Measurement hook.  While enabled, every kernel pq_scan enqueues on a
+   handle is bracketed by a pair of HIP events on the scan's stream;
+   pq_profile_read() waits for the recorded events and returns, per kernel
+   name, the number of launches and the summed device time since the last
+   pq_profile(f, 1).  pq_profile(f, 0) stops recording. */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double total_ms;
+} pq_kernel_time;
+pq_status pq_profile(pq_file f, int32_t enable);
+pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n);
 
 /* Frees the handle's host and device memory (not dev_buf). */
 void pq_close(pq_file f);

@@ -19,7 +19,8 @@ INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
 _WIDTH = {INT32: 4, INT64: 8, DOUBLE: 8}
 
 EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get", "pq_row_group_rows",
-           "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check", "pq_close", "pq_last_error")
+           "pq_file_stats_get", "pq_column_bytes", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
+           "pq_profile_read", "pq_close", "pq_last_error")
 
 
 class PqError(RuntimeError):
@@ -39,6 +40,10 @@ class ScanSizes(ctypes.Structure):
 class ColumnOut(ctypes.Structure):
     _fields_ = [("values", ctypes.c_void_p), ("validity", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
                 ("chars", ctypes.c_void_p), ("chars_capacity", ctypes.c_uint64)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
 class FileStats(ctypes.Structure):
@@ -66,13 +71,17 @@ def lib() -> ctypes.CDLL:
         L.pq_row_group_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.pq_file_stats_get.argtypes = [vp, ctypes.POINTER(FileStats)]
         L.pq_plan.argtypes = [vp, u64, i32, i32, vp, u64, ctypes.POINTER(ScanSizes), vp]
+        L.pq_column_bytes.argtypes = [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.pq_profile.argtypes = [vp, i32]
+        L.pq_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
         L.pq_scan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp]
         L.pq_scan_check.argtypes = [vp, vp]
         L.pq_close.argtypes = [vp]
         L.pq_close.restype = None
         L.pq_last_error.restype = ctypes.c_char_p
         for name in ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get",
-                     "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check"):
+                     "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check",
+                     "pq_column_bytes", "pq_profile", "pq_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -155,6 +164,22 @@ class DeviceFile:
         s = FileStats()
         _check(lib().pq_file_stats_get(self._h, ctypes.byref(s)))
         return s
+
+    def column_bytes(self, col: int):
+        """(encoded data-page bytes, dictionary-page bytes) of a column."""
+        d, k = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pq_column_bytes(self._h, col, ctypes.byref(d), ctypes.byref(k)))
+        return d.value, k.value
+
+    def profile(self, enable: bool):
+        _check(lib().pq_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> Dict[str, tuple]:
+        """{kernel: (launches, total device ms)} since profile(True)."""
+        arr = (KernelTime * 16)()
+        n = ctypes.c_int32()
+        _check(lib().pq_profile_read(self._h, arr, 16, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}
 
     def plan(self, mask: int, rg_begin: int, rg_end: int, workspace=None, stream=None) -> ScanSizes:
         sz = ScanSizes()

@@ -257,10 +257,54 @@ struct pq_file_s {
   ChunkDev* d_chunks = nullptr;
   uint32_t* d_err = nullptr;
   pq_file_stats stats{};
+  // measurement hook: event pairs around each launched kernel
+  bool profiling = false;
+  struct Rec { int kernel; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms[8] = {0};
+  uint64_t prof_n[8] = {0};
+};
+
+static const char* kKernelNames[8] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
+                                      "k_decode_fixed", "k_decode_str", "other"};
+
+static hipEvent_t pool_get(pq_file f) {
+  if (!f->event_pool.empty()) {
+    hipEvent_t e = f->event_pool.back();
+    f->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  pq_file f;
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(pq_file f_, int k_, hipStream_t s_) : f(f_), k(k_), s(s_) {
+    if (f->profiling) {
+      a = pool_get(f);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = pool_get(f);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    f->recs.push_back(pq_file_s::Rec{k, a, b});
+  }
 };
 
 static void free_handle(pq_file f) {
   if (!f) return;
+  for (auto& r : f->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : f->event_pool) (void)hipEventDestroy(e);
   if (f->d_pages) (void)hipFree(f->d_pages);
   if (f->d_tiles) (void)hipFree(f->d_tiles);
   if (f->d_strck) (void)hipFree(f->d_strck);
@@ -681,36 +725,43 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   const uint8_t* file = f->file;
   if (P.snappy_waves) {
     if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
+    ProfScope ps_(f, 0, s);
     hipLaunchKernelGGL(k_snappy, dim3((P.snappy_waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cols,
                        make_segs(P.snappy_segs), ws, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.slots.empty() && P.dict_grid_x) {
+    ProfScope ps_(f, 1, s);
     hipLaunchKernelGGL(k_dict, dim3((uint32_t)P.slots.size(), P.dict_grid_x), dim3(256), 0, s, file, ws, d_cols,
                        (int)P.cols.size(), f->d_pages, d_slots, f->d_strck, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.pre_wgs) {
+    ProfScope ps_(f, 2, s);
     hipLaunchKernelGGL(k_prepass, dim3(P.pre_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles, d_slots,
                        make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.scan_cols.empty()) {
+    ProfScope ps_(f, 3, s);
     hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, s, ws, d_cols, d_which, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (plan_only) return PQ_OK;
   if (P.prep_threads) {
+    ProfScope ps_(f, 4, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
                        make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
   }
   if (P.fixed_wgs) {
+    ProfScope ps_(f, 5, s);
     hipLaunchKernelGGL(k_decode_fixed, dim3(P.fixed_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
                        d_slots, make_segs(P.fixed_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.str_wgs) {
+    ProfScope ps_(f, 6, s);
     hipLaunchKernelGGL(k_decode_str, dim3(P.str_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
                        d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
     HIP_OR(hipGetLastError());
@@ -787,4 +838,53 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
 extern "C" pq_status pq_scan_check(pq_file f, pq_stream stream) {
   if (!f) return fail(PQ_EINVAL, "NULL handle");
   return read_err(f, (hipStream_t)stream);
+}
+
+extern "C" pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes) {
+  if (!f || col < 0 || col >= f->ncols) return fail(PQ_EINVAL, "bad column");
+  uint64_t d = 0, k = 0;
+  const uint32_t q0 = (uint32_t)(col * f->nrg), q1 = (uint32_t)((col + 1) * f->nrg);
+  for (uint32_t p = f->chunk_page0[q0]; p < f->chunk_page0[q1]; ++p) {
+    if (f->pages[p].kind == PAGE_DICT) k += f->pages[p].comp_size;
+    else d += f->pages[p].comp_size;
+  }
+  if (data_bytes) *data_bytes = d;
+  if (dict_bytes) *dict_bytes = k;
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_profile(pq_file f, int32_t enable) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  for (auto& r : f->recs) { f->event_pool.push_back(r.a); f->event_pool.push_back(r.b); }
+  f->recs.clear();
+  for (int k = 0; k < 8; ++k) { f->prof_ms[k] = 0; f->prof_n[k] = 0; }
+  f->profiling = enable != 0;
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n) {
+  if (!f || !n) return fail(PQ_EINVAL, "NULL argument");
+  for (auto& r : f->recs) {
+    HIP_OR(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_OR(hipEventElapsedTime(&ms, r.a, r.b));
+    f->prof_ms[r.kernel] += ms;
+    f->prof_n[r.kernel] += 1;
+    f->event_pool.push_back(r.a);
+    f->event_pool.push_back(r.b);
+  }
+  f->recs.clear();
+  int32_t k = 0;
+  for (int j = 0; j < 8; ++j) {
+    if (!f->prof_n[j]) continue;
+    if (out && k < capacity) {
+      memset(out[k].name, 0, sizeof(out[k].name));
+      strncpy(out[k].name, kKernelNames[j], sizeof(out[k].name) - 1);
+      out[k].launches = f->prof_n[j];
+      out[k].total_ms = f->prof_ms[j];
+    }
+    ++k;
+  }
+  *n = k;
+  return PQ_OK;
 }
