@@ -33,7 +33,7 @@ enum : uint32_t {
 };
 
 // Tile = fixed number of rows of one data page.
-constexpr int TILE_ROWS = 4096;
+constexpr int TILE_ROWS = 2048;
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;
@@ -75,6 +75,15 @@ struct PageDev {
   uint32_t nonnull;      // non-null values (filled by the index pass)
   uint32_t strck_begin;  // first string checkpoint (PLAIN strings / string dictionaries)
   uint32_t dict_page;    // data pages: page index of the chunk's dictionary page (~0u: none)
+  // value-stream header facts, parsed once by the index pass:
+  //   dictionary pages' data: enc_w = index bit width
+  //   DELTA_BINARY_PACKED: enc_w = block size, enc_m = miniblocks,
+  //   delta_first = first value, blocks_at = offset of block 0 in the stream
+  uint32_t enc_w;
+  uint32_t enc_m;
+  int64_t delta_first;
+  uint32_t blocks_at;
+  uint32_t pad1;
 };
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.
@@ -93,7 +102,9 @@ struct TileDev {
 
 // Decoded dictionary of one column chunk inside the workspace.
 struct DictSlot {
-  const uint8_t* body;   // dictionary page body (file or scratch), set on the device
+  const uint8_t* body;   // 16-byte aligned base holding the dictionary page body (file or
+                         // scratch), set on the device
+  uint64_t body_off;     // offset of the body from `body`, set on the device
   uint64_t ws_entries;   // workspace offset: fixed-width entries, or (pos,len) u32 pairs
   uint32_t n;            // entries (0: chunk has no dictionary)
   uint32_t page;         // dictionary page index (~0u: none)

@@ -71,6 +71,7 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
       p.def_off = 0; p.val_off = 0; p.val_len = 0;
       p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
       p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u;
+      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.pad1 = 0;
       pages[page_base[q] + n] = p;
     }
     ++n;
@@ -302,6 +303,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       if (val_len < 1) { set_err(err, ERR_VALUES, p); return; }
       const uint32_t w = r.byte(val_off);
       if (w > 32) { set_err(err, ERR_VALUES, p); return; }
+      pg.enc_w = w;
       RunCur c;
       c.next = val_off + 1; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = val_off + 1;
       bool have = false;
@@ -324,7 +326,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     bool bad = false;
     uint64_t q = val_off;
     uint64_t B = br_uleb(r, q, vend, bad), M = br_uleb(r, q, vend, bad), total = br_uleb(r, q, vend, bad);
-    br_uleb(r, q, vend, bad);
+    const int64_t first = unzz(br_uleb(r, q, vend, bad));
     if (bad || B == 0 || B % 128 != 0 || M == 0 || B % M != 0 || (B / M) % 32 != 0 || total != nonnull) {
       set_err(err, ERR_DELTA, p);
       return;
@@ -332,6 +334,10 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     if (M > 16 || B > 65536) { set_err(err, ERR_UNSUPPORTED, p); return; }
     const uint32_t maxw = ch.type == T_INT32 ? 32 : 64;
     const uint64_t per = B / M;
+    pg.enc_w = (uint32_t)B;
+    pg.enc_m = (uint32_t)M;
+    pg.delta_first = first;
+    pg.blocks_at = (uint32_t)(q - val_off);
     // block b holds values [1 + b*B, 1 + (b+1)*B); value 0 is in the header
     const uint64_t nblocks = total > 1 ? (total - 1 + B - 1) / B : 0;
     for (uint32_t t = 0; t < ntiles; ++t) {
