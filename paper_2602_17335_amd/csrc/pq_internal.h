@@ -33,7 +33,7 @@ enum : uint32_t {
 };
 
 // Tile = fixed number of rows of one data page.
-constexpr int TILE_ROWS = 2048;
+constexpr int TILE_ROWS = 1024;
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;

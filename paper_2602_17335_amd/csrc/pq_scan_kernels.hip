@@ -9,12 +9,14 @@
 //   k_decode_str   definition levels, PLAIN / dictionary strings
 //
 // Work unit of the decode kernels: one TILE_ROWS-row tile of one page per
-// 256-thread workgroup, entered through the tile index built at open.  Each
-// tile first copies the byte ranges of its level and value streams into LDS
-// with one coalesced 16-byte-per-lane load; a single wave then walks the
-// run / block headers over the staged bytes, 64 candidate header positions
-// at a time (each lane parses the header that would start at its byte; the
-// real chain is followed with readlane), and all threads expand the runs.
+// 256-thread workgroup, entered through the tile index built at open.  A
+// tile issues every global load it needs up front: the byte ranges of its
+// level and value streams are copied into LDS with coalesced 16-byte loads.
+// One wave then walks the level stream's run headers while another walks the
+// value stream's (or a lane walks the DELTA block headers): each lane parses
+// the header that would start at its byte, and the real chain is followed
+// through those 64 candidates with readlane.  All threads then expand runs,
+// compute ranks, and write the outputs with coalesced stores.
 #include <hip/hip_runtime.h>
 
 #include "pq_device.hpp"
@@ -25,12 +27,15 @@ namespace pqk {
 constexpr int WG = 256;
 constexpr int NWAVES = WG / 64;
 constexpr int TR = TILE_ROWS;        // rows per tile
+constexpr int PER = TR / WG;         // rows (or values) per thread
 constexpr int NWORDS = TR / 32;      // validity words per tile
-constexpr int RUNCAP = 512;          // run-table entries per batch
-constexpr int STAGE_DEF = 2048;      // bytes of staged level stream
-constexpr int STAGE_VAL = 9216;      // bytes of staged value stream
-constexpr int DBLK_CAP = 24;         // DELTA blocks per tile (TR / 128 + 2)
+constexpr int DRUNCAP = 128;         // level runs per batch
+constexpr int VRUNCAP = 64;          // index runs per batch
+constexpr int DSTAGE = 1024;         // staged level-stream bytes
+constexpr int VSTAGE = TR * 8 + 256; // staged value-stream bytes
+constexpr int DBLK_CAP = TR / 128 + 2;
 constexpr int DMINI_MAX = 16;
+constexpr int GROUP_CHARS = 3072;    // per-wave LDS bytes for one 64-row group of strings
 
 struct Run {
   int32_t vstart;  // first value (tile-relative; negative for a run entered mid-way)
@@ -75,47 +80,62 @@ __device__ __forceinline__ void find_segment(const SegTable& seg, uint32_t wg, u
 }
 
 // ---------------------------------------------------------------------------
-// byte sources: staged LDS copy, or global memory (fallback)
+// byte source: a staged LDS copy of a stream range, or global memory when the
+// range does not fit the LDS buffer.  Positions are relative to `origin`.
 // ---------------------------------------------------------------------------
-struct LSrc {
-  const uint8_t* p;  // 16-byte aligned LDS buffer
-  uint32_t len;      // staged bytes (multiple of 16)
-  __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)p[i] : 0u; }
+struct Src {
+  const uint8_t* p;  // LDS buffer, or the 16-byte aligned global base
+  uint64_t origin;   // global: absolute offset of position 0
+  uint64_t len;      // readable positions [0, len)
+  bool lds;
+
+  __device__ __forceinline__ uint32_t byte(uint64_t i) const {
+    if (i >= len) return 0u;
+    return lds ? (uint32_t)p[i] : (uint32_t)p[origin + i];
+  }
+  __device__ __forceinline__ uint32_t dword_at(uint64_t dw) const {  // LDS aligned dword dw
+    return dw < (len >> 2) ? reinterpret_cast<const uint32_t*>(p)[dw] : 0u;
+  }
+  // w (<= 64) bits at bit position `bit`, least significant first
   __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const {
     if (w == 0) return 0;
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+    if (!lds) return get_bits(p, origin * 8 + bit, w);
     const uint64_t dw = bit >> 5;
     const uint32_t sh = (uint32_t)(bit & 31);
-    const uint64_t nd = len >> 2;
-    const uint64_t lo = dw < nd ? q[dw] : 0u;
-    const uint64_t mid = dw + 1 < nd ? q[dw + 1] : 0u;
-    uint64_t v = (lo | (mid << 32)) >> sh;
-    if (sh + w > 64) v |= (uint64_t)(dw + 2 < nd ? q[dw + 2] : 0u) << (64 - sh);
+    uint64_t v = ((uint64_t)dword_at(dw) | ((uint64_t)dword_at(dw + 1) << 32)) >> sh;
+    if (sh + w > 64) v |= (uint64_t)dword_at(dw + 2) << (64 - sh);
     return w == 64 ? v : (v & ((1ull << w) - 1));
   }
-};
-struct GSrc {
-  const uint8_t* base;  // 16-byte aligned
-  uint64_t origin;      // absolute offset of position 0
-  uint64_t len;
-  __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)base[origin + i] : 0u; }
-  __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const { return get_bits(base, origin * 8 + bit, w); }
+  __device__ __forceinline__ uint32_t u32(uint64_t pos) const { return (uint32_t)bits(pos * 8, 32); }
+  __device__ __forceinline__ uint64_t u64(uint64_t pos) const { return bits(pos * 8, 64); }
 };
 
-// Copies bytes [abs_begin, abs_end) of `base` into LDS, starting at the
-// 16-byte boundary at or below abs_begin.  Uniform result: false if they do
-// not fit `cap` (nothing copied).
-__device__ __forceinline__ bool stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t abs_begin,
-                                      uint64_t abs_end, uint64_t& origin, uint32_t& len) {
-  origin = abs_begin & ~15ull;
-  const uint64_t n16 = (abs_end - origin + 15) >> 4;
-  if (abs_end <= abs_begin) { len = 0; return true; }
-  if (n16 * 16 > cap) return false;
-  const uint4* src = reinterpret_cast<const uint4*>(base + origin);
-  uint4* dst = reinterpret_cast<uint4*>(lds);
-  for (uint32_t i = threadIdx.x; i < (uint32_t)n16; i += WG) dst[i] = src[i];
-  len = (uint32_t)(n16 * 16);
-  return true;
+// Copies bytes [a0, a1) of `base` (16-byte aligned) into LDS from the 16-byte
+// boundary at or below a0, when they fit `cap`; otherwise describes them in
+// global memory.  Loads only; the caller synchronises.
+__device__ __forceinline__ Src stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t a0, uint64_t a1,
+                                     uint64_t& pos0) {
+  Src s;
+  if (a1 < a0) a1 = a0;
+  const uint64_t org = a0 & ~15ull;
+  const uint64_t n16 = (a1 - org + 15) >> 4;
+  if (n16 * 16 <= cap) {
+    const uint4* src = reinterpret_cast<const uint4*>(base + org);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)n16; i += WG) dst[i] = src[i];
+    s.p = lds;
+    s.origin = 0;
+    s.len = n16 * 16;
+    s.lds = true;
+    pos0 = a0 - org;
+  } else {
+    s.p = base;
+    s.origin = a0;
+    s.len = a1 - a0;
+    s.lds = false;
+    pos0 = 0;
+  }
+  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -163,31 +183,44 @@ __device__ __forceinline__ uint64_t wg_excl_scan_u64(uint64_t v, uint64_t* s_tmp
 // ---------------------------------------------------------------------------
 // RLE / bit-packed hybrid: run-header walk by one wave
 // ---------------------------------------------------------------------------
-// Follows the chain of run headers from position `cur` (whose run starts at
-// value `v`, tile-relative) until value `count` is covered or `cap` runs are
-// recorded.  Each lane parses the header that would start at cur + lane; the
-// wave then follows the real chain through those 64 candidates with
-// readlane, and the header lanes write their runs (with prefix-summed value
-// starts) and the first-run marks of the 32-value words their runs cover.
-// Uniform in/out: cur, v.  Returns the runs recorded; *bad on a malformed
-// header (or levels > 1).
-template <class Src>
-__device__ uint32_t wave_walk(const Src& src, uint64_t& cur, int64_t& v, uint32_t count, uint32_t w, bool levels,
-                              Run* runs, uint32_t cap, uint32_t* s_first, bool& bad) {
+struct WalkState {
+  uint64_t cur;   // position of the next run header
+  int64_t v;      // tile-relative first value of the run at `cur`
+  uint32_t nr;    // runs recorded in the current batch
+  uint32_t lo;    // first value of the current batch
+  uint32_t hi;    // values covered by the current batch (clamped to count)
+  uint32_t bad;
+};
+
+// Follows the chain of run headers from st.cur until `count` values are
+// covered or `cap` runs are recorded.  Each lane parses the header that would
+// start at cur + lane; the wave follows the real chain through the 64
+// candidates with readlane; the header lanes then write their runs (value
+// starts prefix-summed) and the first-run marks of the 32-value words their
+// runs cover.  Executed by all lanes of one wave; lane 0 updates `st`.
+__device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32_t w, bool levels, Run* runs,
+                           uint32_t cap, uint32_t* s_first) {
   const int lane = threadIdx.x & 63;
+  uint64_t cur = st->cur;
+  int64_t v = st->v;
+  const uint32_t lo = (uint32_t)max((int64_t)0, v);
   uint32_t nr = 0;
+  bool bad = false;
   while (v < (int64_t)count && nr < cap) {
     const uint64_t p = cur + (uint64_t)lane;
-    // candidate header at p
+    uint32_t b[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) b[k] = src.byte(p + k);
     uint64_t h = 0;
     uint32_t hl = 0;
     bool ok = false;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const uint32_t b = src.byte(p + k);
-      h |= (uint64_t)(b & 0x7f) << (7 * k);
-      if (!(b & 0x80)) { hl = k + 1; ok = true; break; }
+    for (int k = 4; k >= 0; --k) {  // the shortest terminated prefix wins
+      if (!(b[k] & 0x80)) { hl = k + 1; ok = true; }
     }
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if ((uint32_t)k < hl) h |= (uint64_t)(b[k] & 0x7f) << (7 * k);
     const bool isbp = h & 1;
     const uint64_t g = h >> 1;
     uint64_t cnt, plen;
@@ -199,14 +232,19 @@ __device__ uint32_t wave_walk(const Src& src, uint64_t& cur, int64_t& v, uint32_
       cnt = g;
       plen = (w + 7) / 8;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if ((uint32_t)k < plen) val |= src.byte(p + hl + k) << (8 * k);
+      for (int k = 0; k < 4; ++k) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int j = 1; j < 9; ++j)
+          if ((uint32_t)j == hl + k) x = b[j];
+        if ((uint32_t)k < plen) val |= x << (8 * k);
+      }
       if (levels && val > 1) ok = false;
     }
     if (cnt > 0x7fffffffull || plen > 0x7fffffffull || p + hl > src.len) ok = false;
     const uint32_t adv = (uint32_t)(hl + plen);
     const uint32_t c32 = (uint32_t)cnt;
-    const uint32_t pay_end = (uint32_t)min(p + hl, (uint64_t)0xffffffffull);  // payload start
+    const uint32_t ps32 = (uint32_t)min(p + hl, (uint64_t)0xffffffffull);
     // follow the chain
     uint32_t l = 0;
     uint64_t mask = 0;
@@ -215,20 +253,17 @@ __device__ uint32_t wave_walk(const Src& src, uint64_t& cur, int64_t& v, uint32_
     while (l < 64 && v < (int64_t)count && nr + nwin < cap) {
       if (!__builtin_amdgcn_readlane((int)ok, (int)l)) { bad = true; break; }
       const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)c32, (int)l);
-      {
-        // the part of this run the tile needs must lie inside the source
-        const uint64_t need = min((uint64_t)c, (uint64_t)((int64_t)count - v));
-        const uint64_t ps = (uint32_t)__builtin_amdgcn_readlane((int)pay_end, (int)l);
-        const bool rbp = (uint32_t)__builtin_amdgcn_readlane((int)isbp, (int)l) != 0;
-        const uint64_t nb = rbp ? (need * w + 7) / 8 : (uint64_t)(w + 7) / 8;
-        if (ps + nb > src.len) { bad = true; break; }
-      }
+      // the part of this run the tile needs must lie inside the source
+      const uint64_t need = min((uint64_t)c, (uint64_t)((int64_t)count - v));
+      const uint64_t ps = (uint32_t)__builtin_amdgcn_readlane((int)ps32, (int)l);
+      const bool rbp = __builtin_amdgcn_readlane((int)isbp, (int)l) != 0;
+      const uint64_t nb = rbp ? (need * w + 7) / 8 : (uint64_t)(w + 7) / 8;
+      if (ps + nb > src.len) { bad = true; break; }
       if (c) { mask |= 1ull << l; ++nwin; }
       v += c;
       l += (uint32_t)__builtin_amdgcn_readlane((int)adv, (int)l);
     }
-    if (bad) return nr;
-    // record the runs of this window
+    if (bad) break;
     const bool me = (mask >> lane) & 1ull;
     const uint64_t cm = me ? (uint64_t)c32 : 0ull;
     const uint64_t incl = wave_incl_scan_u64(cm);
@@ -246,12 +281,18 @@ __device__ uint32_t wave_walk(const Src& src, uint64_t& cur, int64_t& v, uint32_
     nr += nwin;
     cur += l;
   }
-  return nr;
+  if (lane == 0) {
+    st->cur = cur;
+    st->v = v;
+    st->nr = nr;
+    st->lo = lo;
+    st->hi = (uint32_t)(v < (int64_t)count ? v : (int64_t)count);
+    st->bad = (bad || (nr == 0 && lo < count)) ? 1u : 0u;
+  }
 }
 
-// Expands the definition levels of one batch [lo, hi) of tile rows into the
-// LDS validity words (one thread per 32-row word).
-template <class Src>
+// Expands the definition levels of rows [lo, hi) into the LDS validity words
+// (one thread per 32-row word).
 __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s_first, uint32_t lo, uint32_t hi,
                               uint32_t* s_valid) {
   const uint32_t w0 = lo >> 5, w1 = (hi + 31) >> 5;
@@ -263,7 +304,7 @@ __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s
     while (r < re) {
       const Run R = runs[k];
       const uint32_t n = R.nbp & 0x7fffffffu;
-      const uint32_t e = min(re, (uint32_t)((int64_t)R.vstart + n));
+      const uint32_t e = (uint32_t)min((int64_t)re, (int64_t)R.vstart + n);
       const uint32_t c = e - r;
       uint32_t b;
       if (R.nbp >> 31) b = (uint32_t)src.bits(R.pay + (uint64_t)((int64_t)r - R.vstart), c);
@@ -276,9 +317,8 @@ __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s
   }
 }
 
-// Decodes values [lo, hi) of a batch of an index stream (bit width w) into
-// idx[]; flags indices >= dn.
-template <class Src>
+// Decodes values [lo, hi) of an index stream (bit width w) into idx[];
+// flags indices >= dn.
 __device__ void expand_indices(const Src& src, const Run* runs, uint32_t nr, const uint32_t* s_first, uint32_t lo,
                                uint32_t hi, uint32_t w, uint32_t dn, uint32_t* idx, uint32_t* s_flag) {
   for (uint32_t i = lo + threadIdx.x; i < hi; i += WG) {
@@ -292,40 +332,81 @@ __device__ void expand_indices(const Src& src, const Run* runs, uint32_t nr, con
   }
 }
 
-// Walks + expands a whole hybrid stream segment of `count` values (batches
-// of RUNCAP runs).  MODE 0: definition levels into s_valid; MODE 1:
-// dictionary indices into idx.  Returns false on a malformed stream.
-template <int MODE, class Src>
-__device__ bool decode_hybrid(const Src& src, uint64_t pos, uint32_t skip, uint32_t count, uint32_t w, Run* runs,
-                              uint32_t* s_first, uint32_t* s_valid, uint32_t* idx, uint32_t dn, uint32_t* s_meta,
-                              uint32_t* s_flag) {
-  uint64_t cur = pos;
-  int64_t v = -(int64_t)skip;
-  uint32_t lo = 0;
-  while (lo < count) {
-    if (threadIdx.x < 64) {
-      bool bad = false;
-      const uint32_t nr = wave_walk(src, cur, v, count, w, MODE == 0, runs, RUNCAP, s_first, bad);
-      if (threadIdx.x == 0) {
-        s_meta[0] = nr;
-        s_meta[1] = (bad || nr == 0) ? 1u : 0u;
-        s_meta[2] = (uint32_t)(v < (int64_t)count ? v : (int64_t)count);
+// ---------------------------------------------------------------------------
+// DELTA_BINARY_PACKED: one lane walks the tile's blocks into LDS
+// ---------------------------------------------------------------------------
+__device__ void delta_blocks(const Src& src, uint64_t pos, const PageDev& pg, const TileDev& td, bool is32, DBlock* blk,
+                             uint32_t* s_dmeta) {
+  bool bad = false;
+  uint32_t nb = 0;
+  const uint64_t B = pg.enc_w, M = pg.enc_m;
+  if (td.nn > 0 && (uint64_t)td.k0 + td.nn > 1) {
+    const uint64_t per = B / M;
+    const uint64_t first = td.k0 == 0 ? 1 : td.k0;
+    const uint64_t dlo = first - 1;
+    const uint64_t dhi = (uint64_t)td.k0 + td.nn - 1;
+    const uint64_t total = pg.nonnull;
+    uint64_t bidx = dlo / B;
+    int64_t rel = -(int64_t)td.val_skip;
+    uint64_t q = pos;
+    const uint32_t maxw = is32 ? 32 : 64;
+    while ((uint64_t)((int64_t)dlo + rel) < dhi) {
+      if (nb == DBLK_CAP || q >= src.len) { bad = true; break; }
+      DBlock& D = blk[nb];
+      D.dfirst = (int32_t)rel;
+      uint64_t u = 0;
+      int s = 0;
+      for (;;) {
+        const uint32_t b = src.byte(q++);
+        if (s < 64) u |= (uint64_t)(b & 0x7f) << s;
+        s += 7;
+        if (!(b & 0x80) || s > 70) break;
       }
+      D.min_delta = unzz(u);
+      const uint64_t left = total - 1 - bidx * B;
+      const uint64_t used = left < B ? left : B;
+      const uint64_t used_mb = (used + per - 1) / per;
+      uint64_t bits = 0;
+      for (uint64_t m = 0; m < M; ++m) {
+        uint32_t w = m < used_mb ? src.byte(q + m) : 0;
+        if (w > maxw) { bad = true; w = 0; }
+        D.w[m] = (uint8_t)w;
+        D.woff[m] = (uint32_t)bits;
+        bits += per * w;
+      }
+      D.nmb = (uint32_t)M;
+      q += M;
+      D.bit0 = q * 8;
+      q += bits / 8;
+      rel += (int64_t)B;
+      ++bidx;
+      ++nb;
     }
-    __syncthreads();
-    if (s_meta[1]) return false;
-    const uint32_t nr = s_meta[0], hi = s_meta[2];
-    if (MODE == 0) expand_levels(src, runs, s_first, lo, hi, s_valid);
-    else expand_indices(src, runs, nr, s_first, lo, hi, w, dn, idx, s_flag);
-    // wave 0 keeps cur / v in registers for the next batch
-    lo = hi;
-    __syncthreads();
   }
-  return true;
+  s_dmeta[1] = bad ? 1u : 0u;
+  s_dmeta[0] = nb;
+}
+
+// D_j of tile value j: the stream's first value for global value 0, else
+// min_delta + packed bits of its miniblock.
+__device__ __forceinline__ uint64_t delta_term(const Src& src, const DBlock* blk, const PageDev& pg, const TileDev& td,
+                                               uint32_t j) {
+  const uint64_t k = (uint64_t)td.k0 + j;
+  if (k == 0) return (uint64_t)pg.delta_first;
+  const uint64_t B = pg.enc_w, M = pg.enc_m;
+  const uint64_t first = td.k0 == 0 ? 1 : td.k0;
+  const uint64_t drel = (k - 1) - (first - 1) + td.val_skip;
+  const uint64_t bi = drel / B;
+  const uint64_t o = drel - bi * B;
+  const uint64_t per = B / M;
+  const DBlock& D = blk[bi];
+  const uint32_t m = (uint32_t)(o / per), i = (uint32_t)(o - (uint64_t)m * per);
+  const uint32_t w = D.w[m];
+  return (uint64_t)D.min_delta + src.bits(D.bit0 + D.woff[m] + (uint64_t)i * w, w);
 }
 
 // ---------------------------------------------------------------------------
-// per-tile phases
+// per-tile context and stream ranges
 // ---------------------------------------------------------------------------
 struct TileCtx {
   ColScan cs;
@@ -343,68 +424,76 @@ __device__ __forceinline__ void load_tile(TileCtx& c, const ColScan* cols, const
                                           const SegTable& seg, const uint8_t* file, uint8_t* ws) {
   uint32_t csi, t;
   find_segment(seg, blockIdx.x, csi, t);
-  c.cs = cols[csi];
   c.t = t;
   c.td = tiles[t];
+  c.next = tiles[t + 1 < seg.s[seg.n - 1].t1 ? t + 1 : t];
+  c.cs = cols[csi];
   c.pg = pages[c.td.page];
   c.nrows = (uint32_t)min((int64_t)TR, (int64_t)c.pg.num_values - c.td.row0);
   c.out0 = c.pg.row0 + c.td.row0 - c.cs.row_base;
   c.st = page_streams(c.pg, c.cs, file, ws);
-  const uint32_t ntiles = (uint32_t)(((int64_t)c.pg.num_values + TR - 1) / TR);
-  c.has_next = t + 1 < c.pg.tile_begin + ntiles;
-  if (c.has_next) c.next = tiles[t + 1];
+  c.has_next = c.next.page == c.td.page && c.next.row0 > c.td.row0;
 }
 
-// Decodes the tile's definition levels into s_valid and writes the output
-// validity words; returns false on error (recorded).
-__device__ bool tile_levels(const TileCtx& c, uint8_t* s_stage, Run* runs, uint32_t* s_first, uint32_t* s_valid,
-                            uint32_t* s_meta, uint32_t* s_flag, uint32_t* err) {
-  const Streams& st = c.st;
-  const uint64_t a0 = st.doff + c.td.def_pos;
-  uint64_t a1 = st.dend;
-  if (c.has_next) a1 = min(a1, st.doff + (uint64_t)c.next.def_pos + 16 + ((uint64_t)c.next.def_skip + 7) / 8);
-  uint64_t origin;
-  uint32_t len;
-  const bool staged = stage(s_stage, STAGE_DEF, st.dbase, a0, a1, origin, len);
-  __syncthreads();
-  bool ok;
-  if (staged) {
-    LSrc src{s_stage, len};
-    ok = decode_hybrid<0>(src, a0 - origin, c.td.def_skip, c.nrows, 1, runs, s_first, s_valid, nullptr, 0, s_meta, s_flag);
-  } else {
-    GSrc src{st.dbase, a0, st.dend - a0};
-    ok = decode_hybrid<0>(src, 0, c.td.def_skip, c.nrows, 1, runs, s_first, s_valid, nullptr, 0, s_meta, s_flag);
+// level-stream byte range a tile needs
+__device__ __forceinline__ void level_range(const TileCtx& c, uint64_t& a0, uint64_t& a1) {
+  a0 = c.st.doff + c.td.def_pos;
+  a1 = c.st.dend;
+  if (c.has_next) a1 = min(a1, c.st.doff + (uint64_t)c.next.def_pos + 16 + ((uint64_t)c.next.def_skip + 7) / 8);
+}
+
+// value-stream byte range a tile needs
+__device__ __forceinline__ void value_range(const TileCtx& c, uint64_t& a0, uint64_t& a1) {
+  const int enc = c.pg.encoding;
+  const bool nextvals = c.has_next && c.next.k0 < c.pg.nonnull;
+  if (enc == E_PLAIN && c.cs.type == T_BYTE_ARRAY) {  // strings: located through checkpoints
+    a0 = a1 = c.st.voff;
+    return;
   }
-  if (!ok) {
-    if (threadIdx.x == 0) set_err(err, ERR_LEVELS, c.td.page);
-    return false;
-  }
-  // output bits [out0, out0 + nrows) <- tile bits [0, nrows)
-  if (c.cs.validity) {
-    const int64_t out0 = c.out0;
-    const int64_t w_first = out0 >> 5;
-    const int64_t w_last = (out0 + c.nrows - 1) >> 5;
-    uint32_t* vout = reinterpret_cast<uint32_t*>(c.cs.validity);
-    for (int64_t W = w_first + threadIdx.x; W <= w_last; W += WG) {
-      const int64_t b0 = W * 32 - out0;
-      uint32_t word;
-      if (b0 >= 0) {
-        const uint32_t tw = (uint32_t)(b0 >> 5), sh = (uint32_t)(b0 & 31);
-        const uint32_t lo = s_valid[tw];
-        const uint32_t hi2 = (tw + 1 < NWORDS) ? s_valid[tw + 1] : 0u;
-        word = sh ? ((lo >> sh) | (hi2 << (32 - sh))) : lo;
-      } else {
-        word = s_valid[0] << (uint32_t)(-b0);
-      }
-      const int64_t lo_b = b0 < 0 ? -b0 : 0;
-      const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
-      const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
-      word &= mask;
-      if (mask == 0xffffffffu) vout[W] = word;
-      else if (word) atomicOr(&vout[W], word);
+  if (enc == E_PLAIN) {
+    const uint64_t w = c.cs.width;
+    a0 = c.st.voff + (uint64_t)c.td.k0 * w;
+    a1 = a0 + (uint64_t)c.td.nn * w;
+  } else if (enc == E_DELTA) {
+    a0 = c.st.voff + c.td.val_pos;
+    a1 = c.st.vend;
+    if (nextvals) {
+      const uint64_t more = c.next.val_skip ? 16 + c.pg.enc_m + (uint64_t)c.pg.enc_w * (c.cs.type == T_INT32 ? 4 : 8) : 16;
+      a1 = min(a1, c.st.voff + (uint64_t)c.next.val_pos + more);
     }
+  } else {  // dictionary indices
+    a0 = c.st.voff + c.td.val_pos;
+    a1 = c.st.vend;
+    if (nextvals) a1 = min(a1, c.st.voff + (uint64_t)c.next.val_pos + 16 + ((uint64_t)c.next.val_skip * c.pg.enc_w + 7) / 8);
   }
-  return true;
+  if (c.td.nn == 0) a1 = a0;
+}
+
+// Writes the tile's validity words into the output bitmap.
+__device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t* s_valid) {
+  if (!c.cs.validity) return;
+  const int64_t out0 = c.out0;
+  const int64_t w_first = out0 >> 5;
+  const int64_t w_last = (out0 + c.nrows - 1) >> 5;
+  uint32_t* vout = reinterpret_cast<uint32_t*>(c.cs.validity);
+  for (int64_t W = w_first + threadIdx.x; W <= w_last; W += WG) {
+    const int64_t b0 = W * 32 - out0;
+    uint32_t word;
+    if (b0 >= 0) {
+      const uint32_t tw = (uint32_t)(b0 >> 5), sh = (uint32_t)(b0 & 31);
+      const uint32_t lo = s_valid[tw];
+      const uint32_t hi2 = (tw + 1 < NWORDS) ? s_valid[tw + 1] : 0u;
+      word = sh ? ((lo >> sh) | (hi2 << (32 - sh))) : lo;
+    } else {
+      word = s_valid[0] << (uint32_t)(-b0);
+    }
+    const int64_t lo_b = b0 < 0 ? -b0 : 0;
+    const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
+    const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
+    word &= mask;
+    if (mask == 0xffffffffu) vout[W] = word;
+    else if (word) atomicOr(&vout[W], word);
+  }
 }
 
 // exclusive popcount prefix over the tile's validity words (wave 0)
@@ -412,11 +501,10 @@ __device__ __forceinline__ void tile_rank_prefix(const uint32_t* s_valid, uint32
   if (threadIdx.x < 64) {
     const uint32_t nw = (nrows + 31) / 32;
     const uint32_t j = threadIdx.x;
-    const uint32_t c = j < nw ? __popc(s_valid[j]) : 0;
-    const uint32_t inc = wave_incl_scan_u32(c);
-    if (j < nw) s_pre[j] = inc - c;
+    const uint32_t cnt = j < nw ? __popc(s_valid[j]) : 0;
+    const uint32_t inc = wave_incl_scan_u32(cnt);
+    if (j < nw) s_pre[j] = inc - cnt;
   }
-  __syncthreads();
 }
 
 __device__ __forceinline__ bool row_valid(const uint32_t* s_valid, uint32_t r) { return (s_valid[r >> 5] >> (r & 31)) & 1u; }
@@ -424,175 +512,83 @@ __device__ __forceinline__ uint32_t row_rank(const uint32_t* s_valid, const uint
   return s_pre[r >> 5] + __popc(s_valid[r >> 5] & ((1u << (r & 31)) - 1u));
 }
 
-// Decodes the tile's dictionary indices (values [0, nn)) into idx; false on
-// error (recorded).
-__device__ bool tile_indices(const TileCtx& c, uint32_t dn, uint8_t* s_stage, Run* runs, uint32_t* s_first, uint32_t* idx,
-                             uint32_t* s_meta, uint32_t* s_flag, uint32_t* err) {
-  const Streams& st = c.st;
-  const uint32_t w = c.pg.enc_w;
-  const uint64_t a0 = st.voff + c.td.val_pos;
-  uint64_t a1 = st.vend;
-  if (c.has_next && c.next.k0 < c.pg.nonnull)
-    a1 = min(a1, st.voff + (uint64_t)c.next.val_pos + 16 + ((uint64_t)c.next.val_skip * w + 7) / 8);
-  uint64_t origin;
-  uint32_t len;
-  if (threadIdx.x == 0) *s_flag = 0;
-  const bool staged = stage(s_stage, STAGE_VAL, st.vbase, a0, a1, origin, len);
-  __syncthreads();
-  bool ok;
-  if (staged) {
-    LSrc src{s_stage, len};
-    ok = decode_hybrid<1>(src, a0 - origin, c.td.val_skip, c.td.nn, w, runs, s_first, nullptr, idx, dn, s_meta, s_flag);
-  } else {
-    GSrc src{st.vbase, a0, st.vend - a0};
-    ok = decode_hybrid<1>(src, 0, c.td.val_skip, c.td.nn, w, runs, s_first, nullptr, idx, dn, s_meta, s_flag);
-  }
-  if (!ok) {
-    if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page);
-    return false;
-  }
-  if (*s_flag) {
-    if (threadIdx.x == 0) set_err(err, ERR_DICT_INDEX, c.td.page);
-    return false;
-  }
-  return true;
-}
+// Shared state of the front half of a decode tile (levels, values).
+struct TileShared {
+  uint32_t valid[NWORDS];
+  uint32_t pre[NWORDS];
+  uint32_t dfirst[NWORDS];
+  uint32_t vfirst[NWORDS];
+  WalkState dst, vst;
+  uint32_t dmeta[2];
+  uint32_t flag;
+  uint64_t tmp[NWAVES];
+  Run druns[DRUNCAP];
+  Run vruns[VRUNCAP];
+  __attribute__((aligned(16))) uint8_t dstage[DSTAGE];
+  __attribute__((aligned(16))) uint8_t vstage[VSTAGE];
+};
 
-// DELTA_BINARY_PACKED: thread 0 walks the tile's blocks (headers and
-// miniblock widths) over the source into LDS.
-template <class Src>
-__device__ bool delta_blocks(const Src& src, uint64_t pos, const TileCtx& c, bool is32, DBlock* blk, uint32_t* s_meta) {
+// Front half of a decode tile: stages both streams, walks them (levels on
+// wave 0, dictionary indices on wave 1, DELTA blocks on wave 2), expands the
+// levels into sh.valid (+ output validity, ranks) and the indices into idx.
+// Returns false on error (recorded).  On return the value source `vs` and
+// its start position `vpos` describe the staged value stream.
+__device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, uint32_t* idx, DBlock* blk, Src& vs,
+                           uint64_t& vpos, uint32_t* err) {
+  const bool opt = c.cs.optional;
+  const int enc = c.pg.encoding;
+  const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
+  const bool is_delta = enc == E_DELTA;
+  uint64_t d0 = 0, d1 = 0, v0, v1;
+  if (opt) level_range(c, d0, d1);
+  value_range(c, v0, v1);
+  uint64_t dpos = 0;
+  Src ds;
+  if (opt) ds = stage(sh.dstage, DSTAGE, c.st.dbase, d0, d1, dpos);
+  vs = stage(sh.vstage, VSTAGE, c.st.vbase, v0, v1, vpos);
+  for (uint32_t j = threadIdx.x; j < NWORDS; j += WG) sh.valid[j] = 0;
   if (threadIdx.x == 0) {
-    bool bad = false;
-    uint32_t nb = 0;
-    const uint64_t B = c.pg.enc_w, M = c.pg.enc_m;
-    const TileDev& td = c.td;
-    if (td.nn > 0 && (uint64_t)td.k0 + td.nn > 1) {
-      const uint64_t per = B / M;
-      const uint64_t first = td.k0 == 0 ? 1 : td.k0;
-      const uint64_t dlo = first - 1;
-      const uint64_t dhi = (uint64_t)td.k0 + td.nn - 1;
-      const uint64_t total = c.pg.nonnull;
-      uint64_t bidx = dlo / B;
-      int64_t rel = -(int64_t)td.val_skip;
-      uint64_t q = pos;
-      const uint32_t maxw = is32 ? 32 : 64;
-      while ((uint64_t)((int64_t)dlo + rel) < dhi) {
-        if (nb == DBLK_CAP) { bad = true; break; }
-        DBlock& D = blk[nb];
-        D.dfirst = (int32_t)rel;
-        // zigzag ULEB128 min delta
-        uint64_t u = 0;
-        int s = 0;
-        for (;;) {
-          const uint32_t b = src.byte(q++);
-          if (s < 64) u |= (uint64_t)(b & 0x7f) << s;
-          s += 7;
-          if (!(b & 0x80) || s > 70) break;
-        }
-        D.min_delta = unzz(u);
-        const uint64_t left = total - 1 - bidx * B;
-        const uint64_t used = left < B ? left : B;
-        const uint64_t used_mb = (used + per - 1) / per;
-        uint64_t bits = 0;
-        for (uint64_t m = 0; m < M; ++m) {
-          uint32_t w = m < used_mb ? src.byte(q + m) : 0;
-          if (w > maxw) { bad = true; w = 0; }
-          D.w[m] = (uint8_t)w;
-          D.woff[m] = (uint32_t)bits;
-          bits += per * w;
-        }
-        D.nmb = (uint32_t)M;
-        q += M;
-        D.bit0 = q * 8;
-        q += bits / 8;
-        rel += (int64_t)B;
-        ++bidx;
-        ++nb;
-      }
-    }
-    s_meta[1] = bad ? 1u : 0u;
-    s_meta[0] = nb;
+    sh.flag = 0;
+    sh.dst.cur = dpos; sh.dst.v = -(int64_t)c.td.def_skip; sh.dst.bad = 0;
+    sh.vst.cur = vpos; sh.vst.v = -(int64_t)c.td.val_skip; sh.vst.bad = 0;
+    sh.dmeta[0] = 0; sh.dmeta[1] = 0;
   }
   __syncthreads();
-  return s_meta[1] == 0;
-}
-
-// D_k of tile value j: the stream's first value for global value 0, else
-// min_delta + packed bits of its miniblock.
-template <class Src>
-__device__ __forceinline__ uint64_t delta_term(const Src& src, const DBlock* blk, const TileCtx& c, uint32_t j) {
-  const uint64_t k = (uint64_t)c.td.k0 + j;
-  if (k == 0) return (uint64_t)c.pg.delta_first;
-  const uint64_t B = c.pg.enc_w, M = c.pg.enc_m;
-  const uint64_t first = c.td.k0 == 0 ? 1 : c.td.k0;
-  const uint64_t drel = (k - 1) - (first - 1) + c.td.val_skip;
-  const uint64_t bi = drel / B;
-  const uint64_t o = drel - bi * B;
-  const uint64_t per = B / M;
-  const DBlock& D = blk[bi];
-  const uint32_t m = (uint32_t)(o / per), i = (uint32_t)(o - (uint64_t)m * per);
-  const uint32_t w = D.w[m];
-  return (uint64_t)D.min_delta + src.bits(D.bit0 + D.woff[m] + (uint64_t)i * w, w);
-}
-
-// Sum (wrapping) of the tile's DELTA terms, or the terms themselves with a
-// carry: out_vals[j] = carry + D_0 + ... + D_j.  Returns false on error.
-template <bool VALUES>
-__device__ bool tile_delta(const TileCtx& c, uint64_t carry, uint8_t* s_stage, DBlock* blk, uint64_t* out_vals,
-                           uint64_t* s_tmp, uint32_t* s_meta, uint64_t* sum_out, uint32_t* err) {
-  const Streams& st = c.st;
-  const bool is32 = c.cs.type == T_INT32;
-  const uint64_t a0 = st.voff + c.td.val_pos;
-  uint64_t a1 = st.vend;
-  if (c.has_next && c.next.k0 < c.pg.nonnull && c.next.val_skip == 0) a1 = min(a1, st.voff + (uint64_t)c.next.val_pos + 16);
-  else if (c.has_next && c.next.k0 < c.pg.nonnull)
-    a1 = min(a1, st.voff + (uint64_t)c.next.val_pos + 16 + c.pg.enc_m + (uint64_t)c.pg.enc_w * (is32 ? 4 : 8));
-  uint64_t origin;
-  uint32_t len;
-  const bool staged = stage(s_stage, STAGE_VAL, st.vbase, a0, a1, origin, len);
+  const int wave = threadIdx.x >> 6;
+  const bool idx_walk = is_dict && c.td.nn > 0;
+  if (wave == 0 && opt) walk_batch(ds, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst);
+  if (wave == 1 && idx_walk) walk_batch(vs, &sh.vst, c.td.nn, c.pg.enc_w, false, sh.vruns, VRUNCAP, sh.vfirst);
+  if (threadIdx.x == 128 && is_delta) delta_blocks(vs, vpos, c.pg, c.td, c.cs.type == T_INT32, blk, sh.dmeta);
   __syncthreads();
-  constexpr int PER = TR / WG;
-  uint64_t loc[PER];
-  uint64_t acc = 0;
-  bool ok;
-  if (staged) {
-    LSrc src{s_stage, len};
-    ok = delta_blocks(src, a0 - origin, c, is32, blk, s_meta);
-    if (ok) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t j = threadIdx.x * PER + q;
-        acc += j < c.td.nn ? delta_term(src, blk, c, j) : 0;
-        loc[q] = acc;
-      }
-    }
-  } else {
-    GSrc src{st.vbase, a0, st.vend - a0};
-    ok = delta_blocks(src, 0, c, is32, blk, s_meta);
-    if (ok) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t j = threadIdx.x * PER + q;
-        acc += j < c.td.nn ? delta_term(src, blk, c, j) : 0;
-        loc[q] = acc;
-      }
+  // levels: expand this batch, walk further batches if any
+  if (opt) {
+    for (;;) {
+      if (sh.dst.bad) { if (threadIdx.x == 0) set_err(err, ERR_LEVELS, c.td.page); return false; }
+      expand_levels(ds, sh.druns, sh.dfirst, sh.dst.lo, sh.dst.hi, sh.valid);
+      if (sh.dst.hi >= c.nrows) break;
+      __syncthreads();
+      if (wave == 0) walk_batch(ds, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst);
+      __syncthreads();
     }
   }
-  if (!ok) {
-    if (threadIdx.x == 0) set_err(err, ERR_DELTA, c.td.page);
-    return false;
-  }
-  uint64_t tot;
-  const uint64_t ex = wg_excl_scan_u64(acc, s_tmp, &tot);
-  if (VALUES) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t j = threadIdx.x * PER + q;
-      if (j < c.td.nn) out_vals[j] = carry + ex + loc[q];
+  if (idx_walk) {
+    for (;;) {
+      if (sh.vst.bad) { if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page); return false; }
+      expand_indices(vs, sh.vruns, sh.vst.nr, sh.vfirst, sh.vst.lo, sh.vst.hi, c.pg.enc_w, dict_n, idx, &sh.flag);
+      if (sh.vst.hi >= c.td.nn) break;
+      __syncthreads();
+      if (wave == 0) walk_batch(vs, &sh.vst, c.td.nn, c.pg.enc_w, false, sh.vruns, VRUNCAP, sh.vfirst);
+      __syncthreads();
     }
   }
-  *sum_out = tot;
+  if (is_delta && sh.dmeta[1]) { if (threadIdx.x == 0) set_err(err, ERR_DELTA, c.td.page); return false; }
+  __syncthreads();
+  if (sh.flag) { if (threadIdx.x == 0) set_err(err, ERR_DICT_INDEX, c.td.page); return false; }
+  if (opt) {
+    write_validity(c, sh.valid);
+    tile_rank_prefix(sh.valid, sh.pre, c.nrows);
+    __syncthreads();
+  }
   return true;
 }
 
@@ -797,39 +793,67 @@ __global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* co
 // ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                                                const TileDev* tiles, const DictSlot* slots, SegTable seg, uint32_t* err) {
-  __shared__ __align__(16) uint8_t s_stage[STAGE_VAL];
-  __shared__ Run s_runs[RUNCAP];
+__global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
+                                                const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
+                                                const TileDev* __restrict__ tiles, const DictSlot* __restrict__ slots,
+                                                SegTable seg, uint32_t* __restrict__ err) {
+  __shared__ __align__(16) uint8_t s_stage[VSTAGE];
+  __shared__ Run s_runs[VRUNCAP];
   __shared__ uint32_t s_first[NWORDS];
-  __shared__ __align__(16) uint64_t s_pairs[TR];
+  __shared__ uint32_t s_idx[TR];
   __shared__ DBlock s_blk[DBLK_CAP];
   __shared__ uint64_t s_tmp[NWAVES];
-  __shared__ uint32_t s_meta[4];
+  __shared__ WalkState s_st;
+  __shared__ uint32_t s_dmeta[2];
   __shared__ uint32_t s_flag;
   TileCtx c;
   load_tile(c, cols, pages, tiles, seg, file, ws);
   uint64_t* aux = reinterpret_cast<uint64_t*>(ws + c.cs.ws_tile_aux) + (c.t - c.cs.tile_begin);
-  if (c.cs.type != T_BYTE_ARRAY) {  // DELTA tile sum
-    uint64_t sum;
-    if (!tile_delta<false>(c, 0, s_stage, s_blk, nullptr, s_tmp, s_meta, &sum, err)) return;
-    if (threadIdx.x == 0) *aux = sum;
-    return;
-  }
-  if (c.pg.encoding == E_PLAIN) {
+  const bool is_str = c.cs.type == T_BYTE_ARRAY;
+  if (is_str && c.pg.encoding == E_PLAIN) {
     if (threadIdx.x == 0) *aux = (uint64_t)c.td.val_skip - c.td.val_pos - 4ull * c.td.nn;
     return;
   }
-  const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-  const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
-  if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
   if (c.td.nn == 0) { if (threadIdx.x == 0) *aux = 0; return; }
-  const uint32_t* pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
-  uint32_t* idx = reinterpret_cast<uint32_t*>(s_pairs);
-  if (!tile_indices(c, sl.n, s_stage, s_runs, s_first, idx, s_meta, &s_flag, err)) return;
+  uint64_t a0, a1, vpos;
+  value_range(c, a0, a1);
+  const Src vs = stage(s_stage, VSTAGE, c.st.vbase, a0, a1, vpos);
+  if (threadIdx.x == 0) { s_flag = 0; s_st.cur = vpos; s_st.v = -(int64_t)c.td.val_skip; s_st.bad = 0; }
   __syncthreads();
   uint64_t acc = 0;
-  for (uint32_t i = threadIdx.x; i < c.td.nn; i += WG) acc += pairs[2 * idx[i] + 1];
+  if (!is_str) {  // DELTA tile sum
+    if (threadIdx.x == 0) delta_blocks(vs, vpos, c.pg, c.td, c.cs.type == T_INT32, s_blk, s_dmeta);
+    __syncthreads();
+    if (s_dmeta[1]) { if (threadIdx.x == 0) set_err(err, ERR_DELTA, c.td.page); return; }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t j = threadIdx.x * PER + q;
+      if (j < c.td.nn) acc += delta_term(vs, s_blk, c.pg, c.td, j);
+    }
+  } else {  // dictionary strings: sum of entry lengths over the tile's indices
+    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
+    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
+    for (;;) {
+      if (threadIdx.x < 64) walk_batch(vs, &s_st, c.td.nn, c.pg.enc_w, false, s_runs, VRUNCAP, s_first);
+      __syncthreads();
+      if (s_st.bad) { if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page); return; }
+      expand_indices(vs, s_runs, s_st.nr, s_first, s_st.lo, s_st.hi, c.pg.enc_w, sl.n, s_idx, &s_flag);
+      if (s_st.hi >= c.td.nn) break;
+      __syncthreads();
+    }
+    __syncthreads();
+    if (s_flag) { if (threadIdx.x == 0) set_err(err, ERR_DICT_INDEX, c.td.page); return; }
+    const uint32_t* __restrict__ pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
+    uint32_t l[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t i = threadIdx.x + q * WG;
+      l[q] = i < c.td.nn ? pairs[2 * s_idx[i] + 1] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc += l[q];
+  }
   uint64_t tot;
   wg_excl_scan_u64(acc, s_tmp, &tot);
   if (threadIdx.x == 0) *aux = tot;
@@ -838,68 +862,100 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* file, uint8_t* ws
 // ---------------------------------------------------------------------------
 // k_decode_fixed: INT32 / INT64 / DOUBLE tiles
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols,
-                                                     const PageDev* pages, const TileDev* tiles, const DictSlot* slots,
-                                                     SegTable seg, uint32_t* err) {
-  __shared__ __align__(16) uint8_t s_stage[STAGE_VAL];
-  __shared__ Run s_runs[RUNCAP];
-  __shared__ uint32_t s_valid[NWORDS];
-  __shared__ uint32_t s_pre[NWORDS];
-  __shared__ uint32_t s_first[NWORDS];
+__global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
+                                                     const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
+                                                     const TileDev* __restrict__ tiles,
+                                                     const DictSlot* __restrict__ slots, SegTable seg,
+                                                     uint32_t* __restrict__ err) {
+  __shared__ TileShared sh;
   __shared__ __align__(16) uint64_t s_vals[TR];
   __shared__ DBlock s_blk[DBLK_CAP];
-  __shared__ uint64_t s_tmp[NWAVES];
-  __shared__ uint32_t s_meta[4];
-  __shared__ uint32_t s_flag;
 
   TileCtx c;
   load_tile(c, cols, pages, tiles, seg, file, ws);
   const bool opt = c.cs.optional;
   const int width = c.cs.width;
-  const uint32_t nrows = c.nrows;
-  if (opt) {
-    for (uint32_t j = threadIdx.x; j < NWORDS; j += WG) s_valid[j] = 0;
-    if (!tile_levels(c, s_stage, s_runs, s_first, s_valid, s_meta, &s_flag, err)) return;
-    tile_rank_prefix(s_valid, s_pre, nrows);
-  }
   const int enc = c.pg.encoding;
+  const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
+  DictSlot sl;
+  sl.page = ~0u;
+  sl.n = 0;
+  sl.ws_entries = 0;
+  if (is_dict) {
+    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
+    sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
+  }
+  uint32_t* idx = reinterpret_cast<uint32_t*>(s_vals);
+  Src vs;
+  uint64_t vpos;
+  if (!tile_front(c, sh, sl.n, idx, s_blk, vs, vpos, err)) return;
+  const uint32_t nrows = c.nrows;
   const int64_t out0 = c.out0;
 
+  // rows r = threadIdx.x + q*WG: coalesced stores; every load is issued before the stores
   if (enc == E_PLAIN) {
-    const Streams& st = c.st;
-    for (uint32_t r = threadIdx.x; r < nrows; r += WG) {
-      const bool v = !opt || row_valid(s_valid, r);
-      const uint64_t k = (uint64_t)c.td.k0 + (opt ? row_rank(s_valid, s_pre, r) : r);
-      if (width == 4) {
-        const uint32_t x = v ? ld_u32(st.vbase, st.voff + k * 4) : 0u;
-        reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x;
-      } else {
-        const uint64_t x = v ? ld_u64(st.vbase, st.voff + k * 8) : 0ull;
-        reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x;
+    if (width == 4) {
+      uint32_t x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
+        const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
+        x[q] = v ? vs.u32(vpos + (uint64_t)k * 4) : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        if (r < nrows) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x[q];
+      }
+    } else {
+      uint64_t x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
+        const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
+        x[q] = v ? vs.u64(vpos + (uint64_t)k * 8) : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        if (r < nrows) reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x[q];
       }
     }
     return;
   }
 
-  if (enc == E_PLAIN_DICT || enc == E_RLE_DICT) {
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
-    if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
-    uint32_t* idx = reinterpret_cast<uint32_t*>(s_vals);
-    if (c.td.nn > 0) {
-      if (!tile_indices(c, sl.n, s_stage, s_runs, s_first, idx, s_meta, &s_flag, err)) return;
-      __syncthreads();
-    }
-    const uint8_t* ent = ws + sl.ws_entries;
-    for (uint32_t r = threadIdx.x; r < nrows; r += WG) {
-      const bool v = !opt || row_valid(s_valid, r);
-      const uint32_t k = opt ? row_rank(s_valid, s_pre, r) : r;
-      if (width == 4) {
-        const uint32_t x = v ? reinterpret_cast<const uint32_t*>(ent)[idx[k]] : 0u;
-        reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x;
-      } else {
-        const uint64_t x = v ? reinterpret_cast<const uint64_t*>(ent)[idx[k]] : 0ull;
-        reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x;
+  if (is_dict) {
+    const uint8_t* __restrict__ ent = ws + sl.ws_entries;
+    if (width == 4) {
+      uint32_t x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
+        const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
+        x[q] = v ? reinterpret_cast<const uint32_t*>(ent)[idx[k]] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        if (r < nrows) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x[q];
+      }
+    } else {
+      uint64_t x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
+        const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
+        x[q] = v ? reinterpret_cast<const uint64_t*>(ent)[idx[k]] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t r = threadIdx.x + q * WG;
+        if (r < nrows) reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x[q];
       }
     }
     return;
@@ -908,12 +964,29 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* file, uint8_
   if (enc == E_DELTA) {
     const uint64_t* aux = reinterpret_cast<const uint64_t*>(ws + c.cs.ws_tile_aux);
     const uint64_t carry = aux[c.t - c.cs.tile_begin] - aux[c.pg.tile_begin - c.cs.tile_begin];
-    uint64_t sum;
-    if (!tile_delta<true>(c, carry, s_stage, s_blk, s_vals, s_tmp, s_meta, &sum, err)) return;
+    // thread j owns values [PER*j, PER*j + PER)
+    uint64_t loc[PER];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t j = threadIdx.x * PER + q;
+      acc += j < c.td.nn ? delta_term(vs, s_blk, c.pg, c.td, j) : 0;
+      loc[q] = acc;
+    }
+    uint64_t tot;
+    const uint64_t ex = wg_excl_scan_u64(acc, sh.tmp, &tot);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t j = threadIdx.x * PER + q;
+      if (j < c.td.nn) s_vals[j] = carry + ex + loc[q];
+    }
     __syncthreads();
-    for (uint32_t r = threadIdx.x; r < nrows; r += WG) {
-      const bool v = !opt || row_valid(s_valid, r);
-      const uint32_t k = opt ? row_rank(s_valid, s_pre, r) : r;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t r = threadIdx.x + q * WG;
+      if (r >= nrows) break;
+      const bool v = !opt || row_valid(sh.valid, r);
+      const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
       const uint64_t x = v ? s_vals[k] : 0ull;
       if (width == 4) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = (uint32_t)x;
       else reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x;
@@ -924,38 +997,84 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* file, uint8_
 }
 
 // ---------------------------------------------------------------------------
+// string copy: one lane copies one string of L bytes from source offset S of a
+// 4-byte aligned base to chars offset D, 32 bytes per step: nine aligned
+// source dwords are loaded together, realigned with byte funnel shifts, and
+// written as aligned dwords (bytes at the string's two ends).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void copy_string(const uint8_t* __restrict__ sbase, uint64_t S, uint8_t* __restrict__ chars,
+                                            uint64_t D, uint32_t L) {
+  for (uint32_t j0 = 0; j0 < L; j0 += 32) {
+    const uint32_t n = min(32u, L - j0);
+    const uint64_t s = S + j0, d = D + j0;
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(sbase + (s & ~3ull));
+    const uint32_t ss = (uint32_t)(s & 3);
+    const uint32_t nsw = (ss + n + 3) >> 2;
+    uint32_t w[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) w[k] = (uint32_t)k < nsw ? q[k] : 0u;
+    uint32_t rr[9];  // string bytes [4k, 4k+4) of this step
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rr[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
+    const uint32_t dd = (uint32_t)(d & 3);
+    uint32_t* dw = reinterpret_cast<uint32_t*>(chars + (d & ~3ull));
+    const uint32_t ndw = (dd + n + 3) >> 2;
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+      if ((uint32_t)m >= ndw) break;
+      const uint32_t prev = m == 0 ? 0u : rr[m - 1 < 9 ? m - 1 : 8];
+      const uint32_t curw = m < 9 ? rr[m] : 0u;
+      const uint32_t word = dd ? __builtin_amdgcn_alignbyte(curw, prev, 4 - dd) : curw;
+      // bytes of destination word m that belong to this string: [lo, hi)
+      const int lo = m == 0 ? (int)dd : 0;
+      const int hi = (int)min(4u, dd + n - 4u * (uint32_t)m);
+      if (lo == 0 && hi == 4) {
+        dw[m] = word;
+      } else {
+        uint8_t* b = reinterpret_cast<uint8_t*>(dw + m);
+        for (int k = lo; k < hi; ++k) b[k] = (uint8_t)(word >> (8 * k));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_decode_str: BYTE_ARRAY tiles -> offsets and chars
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols,
-                                                   const PageDev* pages, const TileDev* tiles, const DictSlot* slots,
-                                                   const uint32_t* strck, SegTable seg, uint32_t* err) {
-  __shared__ __align__(16) uint8_t s_stage[STAGE_VAL];
-  __shared__ Run s_runs[RUNCAP];
-  __shared__ uint32_t s_valid[NWORDS];
-  __shared__ uint32_t s_pre[NWORDS];
-  __shared__ uint32_t s_first[NWORDS];
+__global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
+                                                   const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
+                                                   const TileDev* __restrict__ tiles,
+                                                   const DictSlot* __restrict__ slots,
+                                                   const uint32_t* __restrict__ strck, SegTable seg,
+                                                   uint32_t* __restrict__ err) {
+  __shared__ TileShared sh;
   __shared__ __align__(16) uint64_t s_vals[TR];  // per value: pos | len << 32
-  __shared__ uint32_t s_idx[TR];
-  __shared__ uint64_t s_tmp[NWAVES];
-  __shared__ uint32_t s_meta[4];
-  __shared__ uint32_t s_flag;
+  __shared__ uint32_t s_idx[TR + 1];
 
   TileCtx c;
   load_tile(c, cols, pages, tiles, seg, file, ws);
   const bool opt = c.cs.optional;
   const uint32_t nrows = c.nrows;
-  if (opt) {
-    for (uint32_t j = threadIdx.x; j < NWORDS; j += WG) s_valid[j] = 0;
-    if (!tile_levels(c, s_stage, s_runs, s_first, s_valid, s_meta, &s_flag, err)) return;
-    tile_rank_prefix(s_valid, s_pre, nrows);
+  const bool is_plain = c.pg.encoding == E_PLAIN;
+  DictSlot sl;
+  sl.page = ~0u;
+  sl.n = 0;
+  sl.ws_entries = 0;
+  sl.body = nullptr;
+  sl.body_off = 0;
+  if (!is_plain) {
+    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
+    sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
   }
-  if (threadIdx.x == 0) s_flag = 0;
-  __syncthreads();
+  Src vs;
+  uint64_t vpos;
+  if (!tile_front(c, sh, sl.n, s_idx, nullptr, vs, vpos, err)) return;
 
-  // ---- (pos, len) of the tile's values; sources are (aligned base, offset) ----
+  // ---- (pos, len) of the tile's values; source = (aligned base, offset) ----
   const uint8_t* sbase;
   uint64_t soff;
-  if (c.pg.encoding == E_PLAIN) {
+  if (is_plain) {
     sbase = c.st.vbase;
     soff = c.st.voff;
     const TileDev& td = c.td;
@@ -966,52 +1085,52 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* file, uint8_t*
       for (uint32_t j = 0; j < STR_CK; ++j) {
         const uint32_t k = ck * STR_CK + j;
         if (k >= td.k0 + td.nn) break;
-        if ((uint64_t)c.pg.val_len - q < 4) { s_flag = 1; break; }
+        if ((uint64_t)c.pg.val_len - q < 4) { sh.flag = 1; break; }
         const uint32_t l = ld_u32(c.st.vbase, c.st.voff + q);
         q += 4;
-        if (l > (uint64_t)c.pg.val_len - q) { s_flag = 1; break; }
+        if (l > (uint64_t)c.pg.val_len - q) { sh.flag = 1; break; }
         if (k >= td.k0) s_vals[k - td.k0] = q | ((uint64_t)l << 32);
         q += l;
       }
     }
     __syncthreads();
-    if (s_flag) { if (threadIdx.x == 0) set_err(err, ERR_STRING, c.td.page); return; }
+    if (sh.flag) { if (threadIdx.x == 0) set_err(err, ERR_STRING, c.td.page); return; }
   } else {
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
-    if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
     sbase = sl.body;
     soff = sl.body_off;
-    if (c.td.nn > 0) {
-      if (!tile_indices(c, sl.n, s_stage, s_runs, s_first, s_idx, s_meta, &s_flag, err)) return;
-      __syncthreads();
-      const uint32_t* pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
-      for (uint32_t i = threadIdx.x; i < c.td.nn; i += WG) {
-        const uint32_t x = s_idx[i];
-        s_vals[i] = (uint64_t)pairs[2 * x] | ((uint64_t)pairs[2 * x + 1] << 32);
-      }
-      __syncthreads();
+    const uint32_t* __restrict__ pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
+    uint64_t pv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t i = threadIdx.x + q * WG;
+      pv[q] = i < c.td.nn ? *reinterpret_cast<const uint64_t*>(pairs + 2 * s_idx[i]) : 0ull;
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t i = threadIdx.x + q * WG;
+      if (i < c.td.nn) s_vals[i] = pv[q];
+    }
+    __syncthreads();
   }
 
-  // ---- offsets: exclusive scan of row lengths; thread j owns rows [8j, 8j+8) ----
+  // ---- offsets: exclusive scan of row lengths; thread j owns rows [PER*j, PER*j+PER) ----
   const uint64_t* aux = reinterpret_cast<const uint64_t*>(ws + c.cs.ws_tile_aux);
   const uint64_t base = aux[c.t - c.cs.tile_begin];
-  constexpr int PER = TR / WG;
   uint32_t lens[PER];
   uint64_t acc = 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const uint32_t r = threadIdx.x * PER + q;
     uint32_t l = 0;
-    if (r < nrows && (!opt || row_valid(s_valid, r))) l = (uint32_t)(s_vals[opt ? row_rank(s_valid, s_pre, r) : r] >> 32);
+    if (r < nrows && (!opt || row_valid(sh.valid, r))) l = (uint32_t)(s_vals[opt ? row_rank(sh.valid, sh.pre, r) : r] >> 32);
     lens[q] = l;
     acc += l;
   }
   uint64_t tot;
-  uint64_t run = wg_excl_scan_u64(acc, s_tmp, &tot);
-  const bool fits = base + tot <= c.cs.chars_capacity && tot < 0xffffffffull;
-  uint32_t* s_off = reinterpret_cast<uint32_t*>(s_stage);  // rows+1 relative offsets (stage is free now)
+  uint64_t run = wg_excl_scan_u64(acc, sh.tmp, &tot);
+  if (tot >= 0xffffffffull) { if (threadIdx.x == 0) set_err(err, ERR_UNSUPPORTED, c.td.page); return; }
+  const bool fits = base + tot <= c.cs.chars_capacity;
+  uint32_t* s_off = s_idx;  // tile-relative row offsets (indices are no longer needed)
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const uint32_t r = threadIdx.x * PER + q;
@@ -1023,39 +1142,17 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* file, uint8_t*
   }
   if (threadIdx.x == 0) s_off[nrows] = (uint32_t)tot;
   __syncthreads();
-  if (!fits || !c.cs.chars || tot == 0) return;
-
-  // ---- chars: one wave per 64-row group writes its output range dword by dword ----
-  uint8_t* chars = c.cs.chars;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t ngroups = (nrows + 63) / 64;
-  for (uint32_t g = wave; g < ngroups; g += NWAVES) {
-    const uint32_t r0 = g * 64, r1 = min(r0 + 64, nrows);
-    const uint32_t A = s_off[r0], Bq = s_off[r1];
-    if (A == Bq) continue;
-    const uint64_t d0 = (base + A) >> 2, d1 = (base + Bq + 3) >> 2;
-    for (uint64_t d = d0 + lane; d < d1; d += 64) {
-      const uint64_t q0a = max(d * 4, base + A), q1a = min(d * 4 + 4, base + Bq);
-      const uint32_t q0 = (uint32_t)(q0a - base), q1 = (uint32_t)(q1a - base);
-      // last row of the group whose range starts at or before q0
-      uint32_t lo = r0, hi = r1 - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= q0) lo = mid; else hi = mid - 1;
-      }
-      uint32_t row = lo;
-      if (q1 - q0 == 4 && s_off[row + 1] >= q1) {
-        const uint32_t pos = (uint32_t)s_vals[opt ? row_rank(s_valid, s_pre, row) : row];
-        const uint32_t x = ld_u32(sbase, soff + pos + (q0 - s_off[row]));
-        *reinterpret_cast<uint32_t*>(chars + d * 4) = x;
-      } else {
-        for (uint32_t q = q0; q < q1; ++q) {
-          while (s_off[row + 1] <= q) ++row;
-          const uint32_t pos = (uint32_t)s_vals[opt ? row_rank(s_valid, s_pre, row) : row];
-          const uint32_t x = ld_u32(sbase, soff + pos + (q - s_off[row])) & 0xffu;
-          chars[base + q] = (uint8_t)x;
-        }
-      }
+  uint8_t* __restrict__ chars = c.cs.chars;
+  if (!fits || !chars) return;
+  // chars: neighbouring lanes copy neighbouring rows
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t r = threadIdx.x + q * WG;
+    if (r >= nrows) break;
+    const uint32_t len = s_off[r + 1] - s_off[r];
+    if (len) {
+      const uint32_t pos = (uint32_t)s_vals[opt ? row_rank(sh.valid, sh.pre, r) : r];
+      copy_string(sbase, soff + pos, chars, base + s_off[r], len);
     }
   }
 }
