@@ -80,60 +80,95 @@ __device__ __forceinline__ void find_segment(const SegTable& seg, uint32_t wg, u
 }
 
 // ---------------------------------------------------------------------------
-// byte source: a staged LDS copy of a stream range, or global memory when the
-// range does not fit the LDS buffer.  Positions are relative to `origin`.
+// byte sources: a staged copy of a stream range in LDS (LSrc), or the range
+// in global memory when it does not fit the LDS buffer (GSrc).  Positions are
+// relative to the start of the copy (LSrc) or to `origin` (GSrc).  They are
+// separate types so that LDS reads compile to ds_read and global reads to
+// global_load.
 // ---------------------------------------------------------------------------
-struct Src {
-  const uint8_t* p;  // LDS buffer, or the 16-byte aligned global base
-  uint64_t origin;   // global: absolute offset of position 0
-  uint64_t len;      // readable positions [0, len)
-  bool lds;
+typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+typedef __attribute__((address_space(1))) const uint8_t glb_u8;
+typedef __attribute__((address_space(1))) const uint32_t glb_u32;
 
-  __device__ __forceinline__ uint32_t byte(uint64_t i) const {
-    if (i >= len) return 0u;
-    return lds ? (uint32_t)p[i] : (uint32_t)p[origin + i];
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+struct LSrc {
+  lds_u8* p;     // 16-byte aligned LDS buffer
+  uint32_t len;  // staged bytes (multiple of 16)
+  __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)p[i] : 0u; }
+  __device__ __forceinline__ uint32_t dword_at(uint64_t dw) const {
+    return dw < (len >> 2) ? reinterpret_cast<lds_u32*>(p)[dw] : 0u;
   }
-  __device__ __forceinline__ uint32_t dword_at(uint64_t dw) const {  // LDS aligned dword dw
-    return dw < (len >> 2) ? reinterpret_cast<const uint32_t*>(p)[dw] : 0u;
-  }
-  // w (<= 64) bits at bit position `bit`, least significant first
   __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const {
     if (w == 0) return 0;
-    if (!lds) return get_bits(p, origin * 8 + bit, w);
     const uint64_t dw = bit >> 5;
     const uint32_t sh = (uint32_t)(bit & 31);
     uint64_t v = ((uint64_t)dword_at(dw) | ((uint64_t)dword_at(dw + 1) << 32)) >> sh;
     if (sh + w > 64) v |= (uint64_t)dword_at(dw + 2) << (64 - sh);
     return w == 64 ? v : (v & ((1ull << w) - 1));
   }
+  __device__ __forceinline__ uint64_t size() const { return len; }
   __device__ __forceinline__ uint32_t u32(uint64_t pos) const { return (uint32_t)bits(pos * 8, 32); }
   __device__ __forceinline__ uint64_t u64(uint64_t pos) const { return bits(pos * 8, 64); }
 };
 
-// Copies bytes [a0, a1) of `base` (16-byte aligned) into LDS from the 16-byte
-// boundary at or below a0, when they fit `cap`; otherwise describes them in
-// global memory.  Loads only; the caller synchronises.
-__device__ __forceinline__ Src stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t a0, uint64_t a1,
-                                     uint64_t& pos0) {
-  Src s;
+struct GSrc {
+  glb_u8* base;     // 16-byte aligned global base
+  uint64_t origin;  // absolute offset of position 0
+  uint64_t len;
+  __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)base[origin + i] : 0u; }
+  __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const {
+    if (w == 0) return 0;
+    const uint64_t b = origin * 8 + bit;
+    const uint64_t dw = b >> 5;
+    const uint32_t sh = (uint32_t)(b & 31);
+    glb_u32* q = reinterpret_cast<glb_u32*>(base) + dw;
+    uint64_t v = ((uint64_t)q[0] | ((uint64_t)q[1] << 32)) >> sh;
+    if (sh + w > 64) v |= (uint64_t)q[2] << (64 - sh);
+    return w == 64 ? v : (v & ((1ull << w) - 1));
+  }
+  __device__ __forceinline__ uint64_t size() const { return len; }
+  __device__ __forceinline__ uint32_t u32(uint64_t pos) const { return (uint32_t)bits(pos * 8, 32); }
+  __device__ __forceinline__ uint64_t u64(uint64_t pos) const { return bits(pos * 8, 64); }
+};
+
+// A staged stream: bytes [a0, a1) of `base` copied into LDS from the 16-byte
+// boundary at or below a0 when they fit `cap`, else left in global memory.
+struct Staged {
+  bool in_lds;
+  LSrc l;
+  GSrc g;
+  uint64_t pos0;  // position of a0 in the source
+};
+
+// Issues the loads of a stage (no barrier).
+__device__ __forceinline__ Staged stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t a0, uint64_t a1) {
+  Staged s;
   if (a1 < a0) a1 = a0;
   const uint64_t org = a0 & ~15ull;
   const uint64_t n16 = (a1 - org + 15) >> 4;
+  s.l.p = (lds_u8*)lds;
+  s.l.len = 0;
+  s.g.base = (glb_u8*)base;
+  s.g.origin = a0;
+  s.g.len = a1 - a0;
   if (n16 * 16 <= cap) {
-    const uint4* src = reinterpret_cast<const uint4*>(base + org);
-    uint4* dst = reinterpret_cast<uint4*>(lds);
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(1))) v4u* src = reinterpret_cast<const __attribute__((address_space(1))) v4u*>(
+        (glb_u8*)base + org);
+    __attribute__((address_space(3))) v4u* dst = reinterpret_cast<__attribute__((address_space(3))) v4u*>(
+        (__attribute__((address_space(3))) uint8_t*)lds);
     for (uint32_t i = threadIdx.x; i < (uint32_t)n16; i += WG) dst[i] = src[i];
-    s.p = lds;
-    s.origin = 0;
-    s.len = n16 * 16;
-    s.lds = true;
-    pos0 = a0 - org;
+    s.in_lds = true;
+    s.l.len = (uint32_t)(n16 * 16);
+    s.pos0 = a0 - org;
   } else {
-    s.p = base;
-    s.origin = a0;
-    s.len = a1 - a0;
-    s.lds = false;
-    pos0 = 0;
+    s.in_lds = false;
+    s.pos0 = 0;
   }
   return s;
 }
@@ -198,6 +233,7 @@ struct WalkState {
 // candidates with readlane; the header lanes then write their runs (value
 // starts prefix-summed) and the first-run marks of the 32-value words their
 // runs cover.  Executed by all lanes of one wave; lane 0 updates `st`.
+template <class Src>
 __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32_t w, bool levels, Run* runs,
                            uint32_t cap, uint32_t* s_first) {
   const int lane = threadIdx.x & 63;
@@ -241,7 +277,7 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
       }
       if (levels && val > 1) ok = false;
     }
-    if (cnt > 0x7fffffffull || plen > 0x7fffffffull || p + hl > src.len) ok = false;
+    if (cnt > 0x7fffffffull || plen > 0x7fffffffull || p + hl > src.size()) ok = false;
     const uint32_t adv = (uint32_t)(hl + plen);
     const uint32_t c32 = (uint32_t)cnt;
     const uint32_t ps32 = (uint32_t)min(p + hl, (uint64_t)0xffffffffull);
@@ -258,7 +294,7 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
       const uint64_t ps = (uint32_t)__builtin_amdgcn_readlane((int)ps32, (int)l);
       const bool rbp = __builtin_amdgcn_readlane((int)isbp, (int)l) != 0;
       const uint64_t nb = rbp ? (need * w + 7) / 8 : (uint64_t)(w + 7) / 8;
-      if (ps + nb > src.len) { bad = true; break; }
+      if (ps + nb > src.size()) { bad = true; break; }
       if (c) { mask |= 1ull << l; ++nwin; }
       v += c;
       l += (uint32_t)__builtin_amdgcn_readlane((int)adv, (int)l);
@@ -293,6 +329,7 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
 
 // Expands the definition levels of rows [lo, hi) into the LDS validity words
 // (one thread per 32-row word).
+template <class Src>
 __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s_first, uint32_t lo, uint32_t hi,
                               uint32_t* s_valid) {
   const uint32_t w0 = lo >> 5, w1 = (hi + 31) >> 5;
@@ -319,6 +356,7 @@ __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s
 
 // Decodes values [lo, hi) of an index stream (bit width w) into idx[];
 // flags indices >= dn.
+template <class Src>
 __device__ void expand_indices(const Src& src, const Run* runs, uint32_t nr, const uint32_t* s_first, uint32_t lo,
                                uint32_t hi, uint32_t w, uint32_t dn, uint32_t* idx, uint32_t* s_flag) {
   for (uint32_t i = lo + threadIdx.x; i < hi; i += WG) {
@@ -335,6 +373,7 @@ __device__ void expand_indices(const Src& src, const Run* runs, uint32_t nr, con
 // ---------------------------------------------------------------------------
 // DELTA_BINARY_PACKED: one lane walks the tile's blocks into LDS
 // ---------------------------------------------------------------------------
+template <class Src>
 __device__ void delta_blocks(const Src& src, uint64_t pos, const PageDev& pg, const TileDev& td, bool is32, DBlock* blk,
                              uint32_t* s_dmeta) {
   bool bad = false;
@@ -351,7 +390,7 @@ __device__ void delta_blocks(const Src& src, uint64_t pos, const PageDev& pg, co
     uint64_t q = pos;
     const uint32_t maxw = is32 ? 32 : 64;
     while ((uint64_t)((int64_t)dlo + rel) < dhi) {
-      if (nb == DBLK_CAP || q >= src.len) { bad = true; break; }
+      if (nb == DBLK_CAP || q >= src.size()) { bad = true; break; }
       DBlock& D = blk[nb];
       D.dfirst = (int32_t)rel;
       uint64_t u = 0;
@@ -389,6 +428,7 @@ __device__ void delta_blocks(const Src& src, uint64_t pos, const PageDev& pg, co
 
 // D_j of tile value j: the stream's first value for global value 0, else
 // min_delta + packed bits of its miniblock.
+template <class Src>
 __device__ __forceinline__ uint64_t delta_term(const Src& src, const DBlock* blk, const PageDev& pg, const TileDev& td,
                                                uint32_t j) {
   const uint64_t k = (uint64_t)td.k0 + j;
@@ -475,7 +515,7 @@ __device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t*
   const int64_t out0 = c.out0;
   const int64_t w_first = out0 >> 5;
   const int64_t w_last = (out0 + c.nrows - 1) >> 5;
-  uint32_t* vout = reinterpret_cast<uint32_t*>(c.cs.validity);
+  __attribute__((address_space(1))) uint32_t* vout = gptr(reinterpret_cast<uint32_t*>(c.cs.validity));
   for (int64_t W = w_first + threadIdx.x; W <= w_last; W += WG) {
     const int64_t b0 = W * 32 - out0;
     uint32_t word;
@@ -492,7 +532,7 @@ __device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t*
     const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
     word &= mask;
     if (mask == 0xffffffffu) vout[W] = word;
-    else if (word) atomicOr(&vout[W], word);
+    else if (word) atomicOr(reinterpret_cast<uint32_t*>(c.cs.validity) + W, word);
   }
 }
 
@@ -531,10 +571,20 @@ struct TileShared {
 // Front half of a decode tile: stages both streams, walks them (levels on
 // wave 0, dictionary indices on wave 1, DELTA blocks on wave 2), expands the
 // levels into sh.valid (+ output validity, ranks) and the indices into idx.
-// Returns false on error (recorded).  On return the value source `vs` and
-// its start position `vpos` describe the staged value stream.
-__device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, uint32_t* idx, DBlock* blk, Src& vs,
-                           uint64_t& vpos, uint32_t* err) {
+// Returns false on error (recorded).  `vs` describes the value stream.
+#define PQ_WITH_SRC(S, CALL) \
+  do {                       \
+    if ((S).in_lds) {        \
+      const LSrc& src_ = (S).l; \
+      CALL;                  \
+    } else {                 \
+      const GSrc& src_ = (S).g; \
+      CALL;                  \
+    }                        \
+  } while (0)
+
+__device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, uint32_t* idx, DBlock* blk, Staged& vs,
+                           uint32_t* err) {
   const bool opt = c.cs.optional;
   const int enc = c.pg.encoding;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
@@ -542,42 +592,43 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
   uint64_t d0 = 0, d1 = 0, v0, v1;
   if (opt) level_range(c, d0, d1);
   value_range(c, v0, v1);
-  uint64_t dpos = 0;
-  Src ds;
-  if (opt) ds = stage(sh.dstage, DSTAGE, c.st.dbase, d0, d1, dpos);
-  vs = stage(sh.vstage, VSTAGE, c.st.vbase, v0, v1, vpos);
+  Staged ds;
+  ds.in_lds = false;
+  if (opt) ds = stage(sh.dstage, DSTAGE, c.st.dbase, d0, d1);
+  vs = stage(sh.vstage, VSTAGE, c.st.vbase, v0, v1);
   for (uint32_t j = threadIdx.x; j < NWORDS; j += WG) sh.valid[j] = 0;
   if (threadIdx.x == 0) {
     sh.flag = 0;
-    sh.dst.cur = dpos; sh.dst.v = -(int64_t)c.td.def_skip; sh.dst.bad = 0;
-    sh.vst.cur = vpos; sh.vst.v = -(int64_t)c.td.val_skip; sh.vst.bad = 0;
+    sh.dst.cur = ds.pos0; sh.dst.v = -(int64_t)c.td.def_skip; sh.dst.bad = 0;
+    sh.vst.cur = vs.pos0; sh.vst.v = -(int64_t)c.td.val_skip; sh.vst.bad = 0;
     sh.dmeta[0] = 0; sh.dmeta[1] = 0;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const bool idx_walk = is_dict && c.td.nn > 0;
-  if (wave == 0 && opt) walk_batch(ds, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst);
-  if (wave == 1 && idx_walk) walk_batch(vs, &sh.vst, c.td.nn, c.pg.enc_w, false, sh.vruns, VRUNCAP, sh.vfirst);
-  if (threadIdx.x == 128 && is_delta) delta_blocks(vs, vpos, c.pg, c.td, c.cs.type == T_INT32, blk, sh.dmeta);
+  const uint32_t w = c.pg.enc_w;
+  if (wave == 0 && opt) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
+  if (wave == 1 && idx_walk) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
+  if (threadIdx.x == 128 && is_delta)
+    PQ_WITH_SRC(vs, delta_blocks(src_, vs.pos0, c.pg, c.td, c.cs.type == T_INT32, blk, sh.dmeta));
   __syncthreads();
-  // levels: expand this batch, walk further batches if any
   if (opt) {
     for (;;) {
       if (sh.dst.bad) { if (threadIdx.x == 0) set_err(err, ERR_LEVELS, c.td.page); return false; }
-      expand_levels(ds, sh.druns, sh.dfirst, sh.dst.lo, sh.dst.hi, sh.valid);
+      PQ_WITH_SRC(ds, expand_levels(src_, sh.druns, sh.dfirst, sh.dst.lo, sh.dst.hi, sh.valid));
       if (sh.dst.hi >= c.nrows) break;
       __syncthreads();
-      if (wave == 0) walk_batch(ds, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst);
+      if (wave == 0) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
       __syncthreads();
     }
   }
   if (idx_walk) {
     for (;;) {
       if (sh.vst.bad) { if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page); return false; }
-      expand_indices(vs, sh.vruns, sh.vst.nr, sh.vfirst, sh.vst.lo, sh.vst.hi, c.pg.enc_w, dict_n, idx, &sh.flag);
+      PQ_WITH_SRC(vs, expand_indices(src_, sh.vruns, sh.vst.nr, sh.vfirst, sh.vst.lo, sh.vst.hi, w, dict_n, idx, &sh.flag));
       if (sh.vst.hi >= c.td.nn) break;
       __syncthreads();
-      if (wave == 0) walk_batch(vs, &sh.vst, c.td.nn, c.pg.enc_w, false, sh.vruns, VRUNCAP, sh.vfirst);
+      if (wave == 0) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
       __syncthreads();
     }
   }
@@ -808,43 +859,45 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
   __shared__ uint32_t s_flag;
   TileCtx c;
   load_tile(c, cols, pages, tiles, seg, file, ws);
-  uint64_t* aux = reinterpret_cast<uint64_t*>(ws + c.cs.ws_tile_aux) + (c.t - c.cs.tile_begin);
+  __attribute__((address_space(1))) uint64_t* aux =
+      reinterpret_cast<__attribute__((address_space(1))) uint64_t*>(gptr(ws + c.cs.ws_tile_aux)) + (c.t - c.cs.tile_begin);
   const bool is_str = c.cs.type == T_BYTE_ARRAY;
   if (is_str && c.pg.encoding == E_PLAIN) {
     if (threadIdx.x == 0) *aux = (uint64_t)c.td.val_skip - c.td.val_pos - 4ull * c.td.nn;
     return;
   }
   if (c.td.nn == 0) { if (threadIdx.x == 0) *aux = 0; return; }
-  uint64_t a0, a1, vpos;
+  uint64_t a0, a1;
   value_range(c, a0, a1);
-  const Src vs = stage(s_stage, VSTAGE, c.st.vbase, a0, a1, vpos);
-  if (threadIdx.x == 0) { s_flag = 0; s_st.cur = vpos; s_st.v = -(int64_t)c.td.val_skip; s_st.bad = 0; }
+  const Staged vs = stage(s_stage, VSTAGE, c.st.vbase, a0, a1);
+  if (threadIdx.x == 0) { s_flag = 0; s_st.cur = vs.pos0; s_st.v = -(int64_t)c.td.val_skip; s_st.bad = 0; }
   __syncthreads();
   uint64_t acc = 0;
   if (!is_str) {  // DELTA tile sum
-    if (threadIdx.x == 0) delta_blocks(vs, vpos, c.pg, c.td, c.cs.type == T_INT32, s_blk, s_dmeta);
+    if (threadIdx.x == 0) PQ_WITH_SRC(vs, delta_blocks(src_, vs.pos0, c.pg, c.td, c.cs.type == T_INT32, s_blk, s_dmeta));
     __syncthreads();
     if (s_dmeta[1]) { if (threadIdx.x == 0) set_err(err, ERR_DELTA, c.td.page); return; }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t j = threadIdx.x * PER + q;
-      if (j < c.td.nn) acc += delta_term(vs, s_blk, c.pg, c.td, j);
-    }
+    PQ_WITH_SRC(vs, {
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t j = threadIdx.x * PER + q;
+        if (j < c.td.nn) acc += delta_term(src_, s_blk, c.pg, c.td, j);
+      }
+    });
   } else {  // dictionary strings: sum of entry lengths over the tile's indices
     const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
     const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
     if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
     for (;;) {
-      if (threadIdx.x < 64) walk_batch(vs, &s_st, c.td.nn, c.pg.enc_w, false, s_runs, VRUNCAP, s_first);
+      if (threadIdx.x < 64) PQ_WITH_SRC(vs, walk_batch(src_, &s_st, c.td.nn, c.pg.enc_w, false, s_runs, VRUNCAP, s_first));
       __syncthreads();
       if (s_st.bad) { if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page); return; }
-      expand_indices(vs, s_runs, s_st.nr, s_first, s_st.lo, s_st.hi, c.pg.enc_w, sl.n, s_idx, &s_flag);
+      PQ_WITH_SRC(vs, expand_indices(src_, s_runs, s_st.nr, s_first, s_st.lo, s_st.hi, c.pg.enc_w, sl.n, s_idx, &s_flag));
       if (s_st.hi >= c.td.nn) break;
       __syncthreads();
     }
     __syncthreads();
     if (s_flag) { if (threadIdx.x == 0) set_err(err, ERR_DICT_INDEX, c.td.page); return; }
-    const uint32_t* __restrict__ pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
+    glb_u32* pairs = reinterpret_cast<glb_u32*>(gptr(ws + sl.ws_entries));
     uint32_t l[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -887,11 +940,13 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
     if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
   }
   uint32_t* idx = reinterpret_cast<uint32_t*>(s_vals);
-  Src vs;
-  uint64_t vpos;
-  if (!tile_front(c, sh, sl.n, idx, s_blk, vs, vpos, err)) return;
+  Staged vs;
+  if (!tile_front(c, sh, sl.n, idx, s_blk, vs, err)) return;
+  const uint64_t vpos = vs.pos0;
   const uint32_t nrows = c.nrows;
   const int64_t out0 = c.out0;
+  __attribute__((address_space(1))) uint32_t* out32 = gptr(reinterpret_cast<uint32_t*>(c.cs.values));
+  __attribute__((address_space(1))) uint64_t* out64 = gptr(reinterpret_cast<uint64_t*>(c.cs.values));
 
   // rows r = threadIdx.x + q*WG: coalesced stores; every load is issued before the stores
   if (enc == E_PLAIN) {
@@ -902,12 +957,12 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
         const uint32_t r = threadIdx.x + q * WG;
         const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
         const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
-        x[q] = v ? vs.u32(vpos + (uint64_t)k * 4) : 0u;
+        PQ_WITH_SRC(vs, x[q] = v ? src_.u32(vpos + (uint64_t)k * 4) : 0u);
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x[q];
+        if (r < nrows) out32[out0 + r] = x[q];
       }
     } else {
       uint64_t x[PER];
@@ -916,19 +971,19 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
         const uint32_t r = threadIdx.x + q * WG;
         const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
         const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
-        x[q] = v ? vs.u64(vpos + (uint64_t)k * 8) : 0ull;
+        PQ_WITH_SRC(vs, x[q] = v ? src_.u64(vpos + (uint64_t)k * 8) : 0ull);
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x[q];
+        if (r < nrows) out64[out0 + r] = x[q];
       }
     }
     return;
   }
 
   if (is_dict) {
-    const uint8_t* __restrict__ ent = ws + sl.ws_entries;
+    glb_u8* ent = gptr(ws + sl.ws_entries);
     if (width == 4) {
       uint32_t x[PER];
 #pragma unroll
@@ -936,12 +991,12 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
         const uint32_t r = threadIdx.x + q * WG;
         const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
         const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
-        x[q] = v ? reinterpret_cast<const uint32_t*>(ent)[idx[k]] : 0u;
+        x[q] = v ? reinterpret_cast<glb_u32*>(ent)[idx[k]] : 0u;
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = x[q];
+        if (r < nrows) out32[out0 + r] = x[q];
       }
     } else {
       uint64_t x[PER];
@@ -950,12 +1005,12 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
         const uint32_t r = threadIdx.x + q * WG;
         const bool v = r < nrows && (!opt || row_valid(sh.valid, r));
         const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
-        x[q] = v ? reinterpret_cast<const uint64_t*>(ent)[idx[k]] : 0ull;
+        x[q] = v ? reinterpret_cast<const __attribute__((address_space(1))) uint64_t*>(ent)[idx[k]] : 0ull;
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x[q];
+        if (r < nrows) out64[out0 + r] = x[q];
       }
     }
     return;
@@ -968,11 +1023,13 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
     uint64_t loc[PER];
     uint64_t acc = 0;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const uint32_t j = threadIdx.x * PER + q;
-      acc += j < c.td.nn ? delta_term(vs, s_blk, c.pg, c.td, j) : 0;
-      loc[q] = acc;
-    }
+    PQ_WITH_SRC(vs, {
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t j = threadIdx.x * PER + q;
+        acc += j < c.td.nn ? delta_term(src_, s_blk, c.pg, c.td, j) : 0;
+        loc[q] = acc;
+      }
+    });
     uint64_t tot;
     const uint64_t ex = wg_excl_scan_u64(acc, sh.tmp, &tot);
 #pragma unroll
@@ -988,8 +1045,8 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
       const bool v = !opt || row_valid(sh.valid, r);
       const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
       const uint64_t x = v ? s_vals[k] : 0ull;
-      if (width == 4) reinterpret_cast<uint32_t*>(c.cs.values)[out0 + r] = (uint32_t)x;
-      else reinterpret_cast<uint64_t*>(c.cs.values)[out0 + r] = x;
+      if (width == 4) out32[out0 + r] = (uint32_t)x;
+      else out64[out0 + r] = x;
     }
     return;
   }
@@ -1002,12 +1059,12 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 // source dwords are loaded together, realigned with byte funnel shifts, and
 // written as aligned dwords (bytes at the string's two ends).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void copy_string(const uint8_t* __restrict__ sbase, uint64_t S, uint8_t* __restrict__ chars,
+__device__ __forceinline__ void copy_string(glb_u8* sbase, uint64_t S, __attribute__((address_space(1))) uint8_t* chars,
                                             uint64_t D, uint32_t L) {
   for (uint32_t j0 = 0; j0 < L; j0 += 32) {
     const uint32_t n = min(32u, L - j0);
     const uint64_t s = S + j0, d = D + j0;
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(sbase + (s & ~3ull));
+    glb_u32* q = reinterpret_cast<glb_u32*>(sbase + (s & ~3ull));
     const uint32_t ss = (uint32_t)(s & 3);
     const uint32_t nsw = (ss + n + 3) >> 2;
     uint32_t w[10];
@@ -1017,7 +1074,8 @@ __device__ __forceinline__ void copy_string(const uint8_t* __restrict__ sbase, u
 #pragma unroll
     for (int k = 0; k < 9; ++k) rr[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
     const uint32_t dd = (uint32_t)(d & 3);
-    uint32_t* dw = reinterpret_cast<uint32_t*>(chars + (d & ~3ull));
+    __attribute__((address_space(1))) uint32_t* dw =
+        reinterpret_cast<__attribute__((address_space(1))) uint32_t*>(chars + (d & ~3ull));
     const uint32_t ndw = (dd + n + 3) >> 2;
 #pragma unroll
     for (int m = 0; m < 10; ++m) {
@@ -1031,7 +1089,7 @@ __device__ __forceinline__ void copy_string(const uint8_t* __restrict__ sbase, u
       if (lo == 0 && hi == 4) {
         dw[m] = word;
       } else {
-        uint8_t* b = reinterpret_cast<uint8_t*>(dw + m);
+        __attribute__((address_space(1))) uint8_t* b = reinterpret_cast<__attribute__((address_space(1))) uint8_t*>(dw + m);
         for (int k = lo; k < hi; ++k) b[k] = (uint8_t)(word >> (8 * k));
       }
     }
@@ -1067,9 +1125,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
     if (sl.page == ~0u) { if (threadIdx.x == 0) set_err(err, ERR_DICT_MISSING, c.td.page); return; }
   }
-  Src vs;
-  uint64_t vpos;
-  if (!tile_front(c, sh, sl.n, s_idx, nullptr, vs, vpos, err)) return;
+  Staged vs;
+  if (!tile_front(c, sh, sl.n, s_idx, nullptr, vs, err)) return;
 
   // ---- (pos, len) of the tile's values; source = (aligned base, offset) ----
   const uint8_t* sbase;
@@ -1098,12 +1155,13 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   } else {
     sbase = sl.body;
     soff = sl.body_off;
-    const uint32_t* __restrict__ pairs = reinterpret_cast<const uint32_t*>(ws + sl.ws_entries);
+    const __attribute__((address_space(1))) uint64_t* pairs =
+        reinterpret_cast<const __attribute__((address_space(1))) uint64_t*>(gptr(ws + sl.ws_entries));
     uint64_t pv[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const uint32_t i = threadIdx.x + q * WG;
-      pv[q] = i < c.td.nn ? *reinterpret_cast<const uint64_t*>(pairs + 2 * s_idx[i]) : 0ull;
+      pv[q] = i < c.td.nn ? pairs[s_idx[i]] : 0ull;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -1114,7 +1172,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   }
 
   // ---- offsets: exclusive scan of row lengths; thread j owns rows [PER*j, PER*j+PER) ----
-  const uint64_t* aux = reinterpret_cast<const uint64_t*>(ws + c.cs.ws_tile_aux);
+  const __attribute__((address_space(1))) uint64_t* aux =
+      reinterpret_cast<const __attribute__((address_space(1))) uint64_t*>(gptr(ws + c.cs.ws_tile_aux));
   const uint64_t base = aux[c.t - c.cs.tile_begin];
   uint32_t lens[PER];
   uint64_t acc = 0;
@@ -1135,15 +1194,16 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   for (int q = 0; q < PER; ++q) {
     const uint32_t r = threadIdx.x * PER + q;
     if (r < nrows) {
-      if (c.cs.offsets) c.cs.offsets[c.out0 + r] = (int64_t)(base + run);
+      if (c.cs.offsets) gptr(c.cs.offsets)[c.out0 + r] = (int64_t)(base + run);
       s_off[r] = (uint32_t)run;
     }
     run += lens[q];
   }
   if (threadIdx.x == 0) s_off[nrows] = (uint32_t)tot;
   __syncthreads();
-  uint8_t* __restrict__ chars = c.cs.chars;
-  if (!fits || !chars) return;
+  if (!fits || !c.cs.chars) return;
+  __attribute__((address_space(1))) uint8_t* chars = gptr(c.cs.chars);
+  glb_u8* sb = (glb_u8*)sbase;
   // chars: neighbouring lanes copy neighbouring rows
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -1152,7 +1212,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     const uint32_t len = s_off[r + 1] - s_off[r];
     if (len) {
       const uint32_t pos = (uint32_t)s_vals[opt ? row_rank(sh.valid, sh.pre, r) : r];
-      copy_string(sbase, soff + pos, chars, base + s_off[r], len);
+      copy_string(sb, soff + pos, chars, base + s_off[r], len);
     }
   }
 }
