@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pq.h"
+#include "pq.h"
 #include "pq_internal.h"
 
 namespace pqk {

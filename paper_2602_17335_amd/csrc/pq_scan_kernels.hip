@@ -228,15 +228,21 @@ struct WalkState {
 };
 
 // Follows the chain of run headers from st.cur until `count` values are
-// covered or `cap` runs are recorded.  Each lane parses the header that would
-// start at cur + lane; the wave follows the real chain through the 64
-// candidates with readlane; the header lanes then write their runs (value
-// starts prefix-summed) and the first-run marks of the 32-value words their
-// runs cover.  Executed by all lanes of one wave; lane 0 updates `st`.
+// covered or `cap` runs are recorded.  Executed by all lanes of one wave.
+// Each lane parses the header that would start at cur + lane.  When the run
+// at cur spans the whole 64-byte window it is taken alone; otherwise the
+// chain through the 64 candidates is resolved in parallel: successor tables
+// J_k (2^k steps) are built by pointer doubling with ds_bpermute, and each
+// lane finds, by binary lifting from the chain start, the last chain element
+// at or before itself (it is on the chain iff that is itself).  Chain lanes
+// prefix-sum their value counts, and the runs the tile needs are written to
+// the run table together with the first-run marks of the 32-value words they
+// cover.  Lane 0 updates `st`.
 template <class Src>
 __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32_t w, bool levels, Run* runs,
                            uint32_t cap, uint32_t* s_first) {
   const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
   uint64_t cur = st->cur;
   int64_t v = st->v;
   const uint32_t lo = (uint32_t)max((int64_t)0, v);
@@ -247,13 +253,12 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
     uint32_t b[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) b[k] = src.byte(p + k);
-    uint64_t h = 0;
     uint32_t hl = 0;
     bool ok = false;
 #pragma unroll
-    for (int k = 4; k >= 0; --k) {  // the shortest terminated prefix wins
+    for (int k = 4; k >= 0; --k)
       if (!(b[k] & 0x80)) { hl = k + 1; ok = true; }
-    }
+    uint64_t h = 0;
 #pragma unroll
     for (int k = 0; k < 5; ++k)
       if ((uint32_t)k < hl) h |= (uint64_t)(b[k] & 0x7f) << (7 * k);
@@ -278,44 +283,80 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
       if (levels && val > 1) ok = false;
     }
     if (cnt > 0x7fffffffull || plen > 0x7fffffffull || p + hl > src.size()) ok = false;
-    const uint32_t adv = (uint32_t)(hl + plen);
-    const uint32_t c32 = (uint32_t)cnt;
-    const uint32_t ps32 = (uint32_t)min(p + hl, (uint64_t)0xffffffffull);
-    // follow the chain
-    uint32_t l = 0;
-    uint64_t mask = 0;
-    const int64_t v0 = v;
-    uint32_t nwin = 0;
-    while (l < 64 && v < (int64_t)count && nr + nwin < cap) {
-      if (!__builtin_amdgcn_readlane((int)ok, (int)l)) { bad = true; break; }
-      const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)c32, (int)l);
-      // the part of this run the tile needs must lie inside the source
-      const uint64_t need = min((uint64_t)c, (uint64_t)((int64_t)count - v));
-      const uint64_t ps = (uint32_t)__builtin_amdgcn_readlane((int)ps32, (int)l);
-      const bool rbp = __builtin_amdgcn_readlane((int)isbp, (int)l) != 0;
-      const uint64_t nb = rbp ? (need * w + 7) / 8 : (uint64_t)(w + 7) / 8;
-      if (ps + nb > src.size()) { bad = true; break; }
-      if (c) { mask |= 1ull << l; ++nwin; }
-      v += c;
-      l += (uint32_t)__builtin_amdgcn_readlane((int)adv, (int)l);
+    const uint32_t adv = max(1u, (uint32_t)min(hl + plen, (uint64_t)0x7fffffffull));
+    const uint64_t ps = p + hl;  // payload start
+
+    uint32_t adv0 = (uint32_t)__builtin_amdgcn_readlane((int)adv, 0);
+    uint64_t mask;    // chain lanes the tile needs (recorded)
+    uint64_t incl;    // inclusive prefix of counts over chain lanes
+    uint64_t cm;
+    bool onchain;
+    if (adv0 >= 64) {
+      onchain = lane == 0;
+    } else {
+      // successor tables and binary lifting (64 = outside the window)
+      const uint32_t nxt = min((uint32_t)lane + adv, 64u);
+      uint32_t J[6];
+      J[0] = nxt;
+#pragma unroll
+      for (int k = 1; k < 6; ++k) {
+        const uint32_t prev = J[k - 1];
+        const uint32_t nn2 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(min(prev, 63u) << 2), (int)prev);
+        J[k] = prev < 64 ? nn2 : 64u;
+      }
+      uint32_t pos = 0;
+#pragma unroll
+      for (int k = 5; k >= 0; --k) {
+        const uint32_t nx = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(pos << 2), (int)J[k]);
+        if (nx <= (uint32_t)lane) pos = nx;
+      }
+      onchain = pos == (uint32_t)lane;
     }
-    if (bad) break;
-    const bool me = (mask >> lane) & 1ull;
-    const uint64_t cm = me ? (uint64_t)c32 : 0ull;
-    const uint64_t incl = wave_incl_scan_u64(cm);
-    if (me) {
-      const uint32_t k = nr + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-      const int64_t vs = v0 + (int64_t)(incl - cm);
+    cm = onchain ? cnt : 0ull;
+    incl = wave_incl_scan_u64(cm);
+    const int64_t vs = v + (int64_t)(incl - cm);
+    const bool needed = onchain && vs < (int64_t)count && cnt > 0;
+    const uint64_t need_mask = __ballot(needed);
+    const uint32_t rk = (uint32_t)__popcll(need_mask & lt_mask);
+    const bool keep = needed && nr + rk < cap;
+    // the part of each kept run the tile needs must lie inside the source
+    const uint64_t need = keep ? min(cnt, (uint64_t)((int64_t)count - vs)) : 0ull;
+    const uint64_t nb = isbp ? (need * w + 7) / 8 : (uint64_t)(w + 7) / 8;
+    const bool badl = (onchain && !ok && vs < (int64_t)count) || (keep && ps + nb > src.size());
+    if (__ballot(badl)) { bad = true; break; }
+    mask = __ballot(keep);
+    if (keep) {
+      const uint32_t kk = nr + rk;
       Run R;
       R.vstart = (int32_t)vs;
-      R.nbp = c32 | (isbp ? 0x80000000u : 0u);
-      R.pay = isbp ? (p + hl) * 8 : (uint64_t)val;
-      runs[k] = R;
+      R.nbp = (uint32_t)cnt | (isbp ? 0x80000000u : 0u);
+      R.pay = isbp ? ps * 8 : (uint64_t)val;
+      runs[kk] = R;
       int64_t j = vs <= 0 ? 0 : (vs + 31) >> 5;
-      for (; j < NWORDS && j * 32 < vs + (int64_t)c32; ++j) s_first[j] = k;
+      for (; j < NWORDS && j * 32 < vs + (int64_t)cnt; ++j) s_first[j] = kk;
     }
-    nr += nwin;
-    cur += l;
+    const uint32_t nkept = (uint32_t)__popcll(mask);
+    if (nr + (uint32_t)__popcll(need_mask) > cap) {
+      // table full: continue at the first needed run that was not recorded
+      const uint64_t fm = __ballot(needed && nr + rk == cap);
+      const int f = __builtin_ctzll(fm);
+      const uint64_t inc_f = ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, f)) |
+                             ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(incl >> 32), f) << 32);
+      const uint64_t cm_f = ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)cm, f)) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(cm >> 32), f) << 32);
+      v = v + (int64_t)(inc_f - cm_f);
+      cur = cur + (uint64_t)f;
+      nr = cap;
+      break;
+    }
+    nr += nkept;
+    // advance past the window: the last chain lane's successor
+    const uint64_t em = __ballot(onchain && (adv0 >= 64 || (uint32_t)lane + adv >= 64));
+    const int e = em ? 63 - __builtin_clzll(em) : 0;
+    const uint64_t inc_e = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, e)) |
+                           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(incl >> 32), e) << 32);
+    v += (int64_t)inc_e;
+    cur += (uint64_t)e + (uint32_t)__builtin_amdgcn_readlane((int)adv, e);
   }
   if (lane == 0) {
     st->cur = cur;
@@ -605,11 +646,13 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
+  // the walking waves rotate with the workgroup so they spread over the SIMDs
+  const int wdef = blockIdx.x & 3, wval = (blockIdx.x + 1) & 3, wdelta = (blockIdx.x + 2) & 3;
   const bool idx_walk = is_dict && c.td.nn > 0;
   const uint32_t w = c.pg.enc_w;
-  if (wave == 0 && opt) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
-  if (wave == 1 && idx_walk) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
-  if (threadIdx.x == 128 && is_delta)
+  if (wave == wdef && opt) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
+  if (wave == wval && idx_walk) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
+  if ((int)threadIdx.x == wdelta * 64 && is_delta)
     PQ_WITH_SRC(vs, delta_blocks(src_, vs.pos0, c.pg, c.td, c.cs.type == T_INT32, blk, sh.dmeta));
   __syncthreads();
   if (opt) {
@@ -618,7 +661,7 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
       PQ_WITH_SRC(ds, expand_levels(src_, sh.druns, sh.dfirst, sh.dst.lo, sh.dst.hi, sh.valid));
       if (sh.dst.hi >= c.nrows) break;
       __syncthreads();
-      if (wave == 0) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
+      if (wave == wdef) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
       __syncthreads();
     }
   }
@@ -628,7 +671,7 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
       PQ_WITH_SRC(vs, expand_indices(src_, sh.vruns, sh.vst.nr, sh.vfirst, sh.vst.lo, sh.vst.hi, w, dict_n, idx, &sh.flag));
       if (sh.vst.hi >= c.td.nn) break;
       __syncthreads();
-      if (wave == 0) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
+      if (wave == wval) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
       __syncthreads();
     }
   }
