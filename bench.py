@@ -13,7 +13,7 @@ Prints one JSON line.  Per-kernel device times come from HIP events that the
 library records around each kernel on the scan's stream; the dominant
 kernel's algorithmic bytes over its average duration give the roofline
 fraction against the MI355X's 8 TB/s HBM peak.  The CPU baseline is the
-plain single-threaded oracle on a bounded sample of the same recipe.
+plain single-threaded oracle run over the same file on one host core.
 """
 import argparse
 import hashlib
@@ -73,11 +73,10 @@ def algorithmic_bytes(kernel, f, cols, types, out_tensors, rows):
     return b
 
 
-def cpu_baseline(args, spec_fn):
-    import datagen as dg
+def cpu_baseline(data, nbytes_label):
+    """The oracle (single-threaded) over every column of the benchmark file
+    itself, in host memory."""
     import oracle
-    spec = spec_fn(args.cpu_rows, args.cpu_rows)
-    data = dg.write(spec, nthreads=min(16, os.cpu_count() or 1))
     f = oracle.File(data)
     t0 = time.perf_counter()
     tot = 0
@@ -87,9 +86,24 @@ def cpu_baseline(args, spec_fn):
         tot += o["values"].nbytes if "values" in o else o["offsets"].nbytes + o["chars"].nbytes
     dt = time.perf_counter() - t0
     return {"value": round(tot / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"same recipe at {args.cpu_rows:,} rows (one row group, {args.page_bytes} B pages, "
-                      f"{'snappy' if args.codec == 'snappy' else 'uncompressed'}), all 16 columns, "
-                      f"{tot / 1e9:.2f} GB decoded in {dt:.1f} s on one host core"}
+            "sample": f"the benchmark file itself ({nbytes_label}), all columns, {tot / 1e9:.2f} GB decoded "
+                      f"in {dt:.1f} s on one host core"}
+
+
+def read_traffic(key):
+    """Measured HBM bytes per launch recorded by a rocprofv3 counter run
+    (profiles/traffic.txt: `key source_hash fetch_bytes write_bytes` per
+    line); None unless the kernel sources still hash the same."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 4 and parts[0] == key and parts[1] == h:
+                return int(parts[2]) + int(parts[3])
+    return None
 
 
 def main():
@@ -102,7 +116,6 @@ def main():
     ap.add_argument("--page-bytes", type=int, default=1 << 20)
     ap.add_argument("--codec", choices=["none", "snappy"], default="none")
     ap.add_argument("--columns", default="all", help="comma-separated column indices, or 'all'")
-    ap.add_argument("--cpu-rows", type=int, default=16_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -128,7 +141,8 @@ def main():
     data = dg.write(spec, nthreads=min(16, os.cpu_count() or 1))
     log(f"generated {len(data) / 1e9:.3f} GB file in {time.perf_counter() - t0:.1f} s")
     buf, nbytes = pqs.to_device(data)
-    del data
+    if args.no_cpu_baseline:
+        del data
     torch.cuda.synchronize()
 
     if args.copy_probe:
@@ -183,26 +197,16 @@ def main():
     n_l, t_l = prof[dom]
     alg = algorithmic_bytes(dom, f, cols, types, tens, rows)
     achieved = alg / (t_l / n_l / 1e3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        try:
-            with open(tfile) as fh:
-                tj = json.load(fh)
-            key = f"{dom}|rows={args.rows}|rg={args.rg_rows}|page={args.page_bytes}|codec={args.codec}|cols={args.columns}"
-            ent = tj.get(key)
-            if ent and ent.get("kernel_source_hash") == kernel_source_hash():
-                traffic = ent["bytes_per_launch"]
-        except (OSError, ValueError, KeyError):
-            traffic = None
+    traffic_key = f"{dom}:rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
+    traffic = read_traffic(traffic_key)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "algorithmic_bytes_per_launch": alg}
+            "algorithmic_bytes_per_launch": alg, "traffic_key": traffic_key}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle on a bounded sample ...")
-        cpu = cpu_baseline(args, spec_fn)
+        cpu = cpu_baseline(data, f"{nbytes / 1e9:.2f} GB, {args.rows:,} rows")
         log(f"CPU baseline: {cpu['value']} GB/s")
 
     workload = (f"wide16: {args.rows:,} rows, row groups of {args.rg_rows:,}, {args.page_bytes // 1024} KiB pages, "
