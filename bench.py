@@ -205,7 +205,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("CPU baseline: oracle on a bounded sample ...")
+        log("CPU baseline: oracle over the same file ...")
         cpu = cpu_baseline(data, f"{nbytes / 1e9:.2f} GB, {args.rows:,} rows")
         log(f"CPU baseline: {cpu['value']} GB/s")
 
