@@ -21,9 +21,9 @@
  *             DOUBLE is copied as its 64-bit pattern (no floating point).
  *   validity  LSB-first bitmap, bit i of byte i/8, 1 = valid.  The library
  *             writes whole 32-bit words: the buffer must be 4-byte aligned
- *             and hold ((rows+31)/32)*4 bytes; bits past `rows` are 0.  May
- *             be NULL (the levels are still decoded); for REQUIRED columns a
- *             given buffer is set to all ones.
+ *             and hold ((rows+31)/32)*4 bytes; bits past `rows` are 0.
+ *             Required for OPTIONAL columns; may be NULL for REQUIRED columns
+ *             (a given buffer is then set to all ones).
  *   offsets   BYTE_ARRAY only: rows+1 int64 values, offsets[0] = 0,
  *             offsets[i+1] - offsets[i] = length of row i (0 for nulls).
  *   chars     BYTE_ARRAY only: the concatenated bytes of all valid rows.
@@ -82,7 +82,7 @@ typedef struct {
 /* Output buffers of one selected column. */
 typedef struct {
   void* values;          /* fixed-width columns: rows * width bytes */
-  uint8_t* validity;     /* ((rows+31)/32)*4 bytes, 4-byte aligned; may be NULL */
+  uint8_t* validity;     /* ((rows+31)/32)*4 bytes, 4-byte aligned; NULL only for REQUIRED */
   int64_t* offsets;      /* BYTE_ARRAY: rows+1 */
   uint8_t* chars;        /* BYTE_ARRAY */
   uint64_t chars_capacity;

@@ -22,6 +22,8 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
+__global__ void k_levels(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
+                         const TileDev* tiles, SegTable seg, uint32_t* err);
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
                        DictSlot* slots, const uint32_t* strck, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
@@ -267,7 +269,7 @@ struct pq_file_s {
 };
 
 static const char* kKernelNames[8] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
-                                      "k_decode_fixed", "k_decode_str", "other"};
+                                      "k_decode_fixed", "k_decode_str", "k_levels"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -613,10 +615,10 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, str_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, str_segs, lev_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_wgs = 0, fixed_wgs = 0, str_wgs = 0;
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_wgs = 0, fixed_wgs = 0, str_wgs = 0, lev_units = 0;
   uint32_t dict_grid_x = 0;
   uint64_t ws_which = 0;
 };
@@ -700,6 +702,10 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
       P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
       P.prep_threads += nt;
+      if (cs.optional) {
+        P.lev_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.lev_units});
+        P.lev_units += nt;
+      }
     }
     if (cs.type == T_BYTE_ARRAY || has_delta) P.scan_cols.push_back((int32_t)idx);
     if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
@@ -752,6 +758,12 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     ProfScope ps_(f, 4, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
                        make_segs(P.prep_segs));
+    HIP_OR(hipGetLastError());
+  }
+  if (P.lev_units) {
+    ProfScope ps_(f, 7, s);
+    hipLaunchKernelGGL(k_levels, dim3((P.lev_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
+                       f->d_tiles, make_segs(P.lev_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.fixed_wgs) {
@@ -818,6 +830,7 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
     ColScan& cs = P.cols[k];
     const pq_column_out& o = outs[k];
     if (o.validity && ((uintptr_t)o.validity & 3)) return fail(PQ_EINVAL, "column %d: validity must be 4-byte aligned", cs.col);
+    if (cs.optional && !o.validity && P.rows > 0) return fail(PQ_EINVAL, "column %d: OPTIONAL column needs a validity buffer", cs.col);
     if (cs.type == T_BYTE_ARRAY) {
       if (P.rows > 0 && !o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);
       if (!o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);

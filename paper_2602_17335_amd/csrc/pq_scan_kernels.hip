@@ -145,8 +145,10 @@ struct Staged {
   uint64_t pos0;  // position of a0 in the source
 };
 
-// Issues the loads of a stage (no barrier).
-__device__ __forceinline__ Staged stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t a0, uint64_t a1) {
+// Issues the loads of a stage (no barrier); threads tid, tid+stride, ...
+// copy 16 bytes each.
+__device__ __forceinline__ Staged stage(uint8_t* lds, uint32_t cap, const uint8_t* base, uint64_t a0, uint64_t a1,
+                                        uint32_t tid = threadIdx.x, uint32_t stride = WG) {
   Staged s;
   if (a1 < a0) a1 = a0;
   const uint64_t org = a0 & ~15ull;
@@ -162,7 +164,7 @@ __device__ __forceinline__ Staged stage(uint8_t* lds, uint32_t cap, const uint8_
         (glb_u8*)base + org);
     __attribute__((address_space(3))) v4u* dst = reinterpret_cast<__attribute__((address_space(3))) v4u*>(
         (__attribute__((address_space(3))) uint8_t*)lds);
-    for (uint32_t i = threadIdx.x; i < (uint32_t)n16; i += WG) dst[i] = src[i];
+    for (uint32_t i = tid; i < (uint32_t)n16; i += stride) dst[i] = src[i];
     s.in_lds = true;
     s.l.len = (uint32_t)(n16 * 16);
     s.pos0 = a0 - org;
@@ -372,9 +374,9 @@ __device__ void walk_batch(const Src& src, WalkState* st, uint32_t count, uint32
 // (one thread per 32-row word).
 template <class Src>
 __device__ void expand_levels(const Src& src, const Run* runs, const uint32_t* s_first, uint32_t lo, uint32_t hi,
-                              uint32_t* s_valid) {
+                              uint32_t* s_valid, uint32_t tid, uint32_t stride) {
   const uint32_t w0 = lo >> 5, w1 = (hi + 31) >> 5;
-  for (uint32_t j = w0 + threadIdx.x; j < w1; j += WG) {
+  for (uint32_t j = w0 + tid; j < w1; j += stride) {
     uint32_t r = max(j * 32, lo);
     const uint32_t re = min(j * 32 + 32, hi);
     uint32_t k = (j * 32 < lo) ? 0u : s_first[j];
@@ -551,13 +553,14 @@ __device__ __forceinline__ void value_range(const TileCtx& c, uint64_t& a0, uint
 }
 
 // Writes the tile's validity words into the output bitmap.
-__device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t* s_valid) {
+__device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t* s_valid, uint32_t tid,
+                                               uint32_t stride) {
   if (!c.cs.validity) return;
   const int64_t out0 = c.out0;
   const int64_t w_first = out0 >> 5;
   const int64_t w_last = (out0 + c.nrows - 1) >> 5;
   __attribute__((address_space(1))) uint32_t* vout = gptr(reinterpret_cast<uint32_t*>(c.cs.validity));
-  for (int64_t W = w_first + threadIdx.x; W <= w_last; W += WG) {
+  for (int64_t W = w_first + tid; W <= w_last; W += stride) {
     const int64_t b0 = W * 32 - out0;
     uint32_t word;
     if (b0 >= 0) {
@@ -572,7 +575,7 @@ __device__ __forceinline__ void write_validity(const TileCtx& c, const uint32_t*
     const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
     const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
     word &= mask;
-    if (mask == 0xffffffffu) vout[W] = word;
+    if (mask == 0xffffffffu) __builtin_nontemporal_store(word, &vout[W]);
     else if (word) atomicOr(reinterpret_cast<uint32_t*>(c.cs.validity) + W, word);
   }
 }
@@ -597,22 +600,42 @@ __device__ __forceinline__ uint32_t row_rank(const uint32_t* s_valid, const uint
 struct TileShared {
   uint32_t valid[NWORDS];
   uint32_t pre[NWORDS];
-  uint32_t dfirst[NWORDS];
   uint32_t vfirst[NWORDS];
-  WalkState dst, vst;
+  WalkState vst;
   uint32_t dmeta[2];
   uint32_t flag;
   uint64_t tmp[NWAVES];
-  Run druns[DRUNCAP];
   Run vruns[VRUNCAP];
-  __attribute__((aligned(16))) uint8_t dstage[DSTAGE];
   __attribute__((aligned(16))) uint8_t vstage[VSTAGE];
 };
 
-// Front half of a decode tile: stages both streams, walks them (levels on
-// wave 0, dictionary indices on wave 1, DELTA blocks on wave 2), expands the
-// levels into sh.valid (+ output validity, ranks) and the indices into idx.
-// Returns false on error (recorded).  `vs` describes the value stream.
+// Loads the tile's validity words (written by k_levels) from the output
+// bitmap: tile bit i = output bit out0 + i.
+__device__ __forceinline__ void load_validity(const TileCtx& c, uint32_t* s_valid) {
+  if (threadIdx.x < NWORDS) {
+    const uint32_t j = threadIdx.x;
+    uint32_t word = 0;
+    if (j * 32 < c.nrows) {
+      const int64_t b = c.out0 + (int64_t)j * 32;
+      const __attribute__((address_space(1))) uint32_t* v = gptr(reinterpret_cast<const uint32_t*>(c.cs.validity));
+      const int64_t W = b >> 5;
+      const uint32_t sh = (uint32_t)(b & 31);
+      const int64_t nw = (c.cs.rows + 31) >> 5;
+      const uint32_t lo = v[W];
+      const uint32_t hi = (sh && W + 1 < nw) ? v[W + 1] : 0u;
+      word = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
+      const uint32_t rem = c.nrows - j * 32;
+      if (rem < 32) word &= (1u << rem) - 1;
+    }
+    s_valid[j] = word;
+  }
+}
+
+// Front half of a decode tile: loads the validity words (k_levels wrote
+// them) and stages the value stream; then one wave walks the dictionary
+// index runs (or one lane the DELTA blocks) while the ranks are computed,
+// and all threads expand the indices into idx.  Returns false on error
+// (recorded).  `vs` describes the staged value stream.
 #define PQ_WITH_SRC(S, CALL) \
   do {                       \
     if ((S).in_lds) {        \
@@ -630,41 +653,32 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
   const int enc = c.pg.encoding;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   const bool is_delta = enc == E_DELTA;
-  uint64_t d0 = 0, d1 = 0, v0, v1;
-  if (opt) level_range(c, d0, d1);
+  uint64_t v0, v1;
   value_range(c, v0, v1);
-  Staged ds;
-  ds.in_lds = false;
-  if (opt) ds = stage(sh.dstage, DSTAGE, c.st.dbase, d0, d1);
   vs = stage(sh.vstage, VSTAGE, c.st.vbase, v0, v1);
-  for (uint32_t j = threadIdx.x; j < NWORDS; j += WG) sh.valid[j] = 0;
+  if (opt) load_validity(c, sh.valid);
   if (threadIdx.x == 0) {
     sh.flag = 0;
-    sh.dst.cur = ds.pos0; sh.dst.v = -(int64_t)c.td.def_skip; sh.dst.bad = 0;
     sh.vst.cur = vs.pos0; sh.vst.v = -(int64_t)c.td.val_skip; sh.vst.bad = 0;
     sh.dmeta[0] = 0; sh.dmeta[1] = 0;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
-  // the walking waves rotate with the workgroup so they spread over the SIMDs
-  const int wdef = blockIdx.x & 3, wval = (blockIdx.x + 1) & 3, wdelta = (blockIdx.x + 2) & 3;
+  // the walking wave rotates with the workgroup so walkers spread over the SIMDs
+  const int wval = (blockIdx.x + 1) & 3, wdelta = (blockIdx.x + 2) & 3, wrank = blockIdx.x & 3;
   const bool idx_walk = is_dict && c.td.nn > 0;
   const uint32_t w = c.pg.enc_w;
-  if (wave == wdef && opt) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
   if (wave == wval && idx_walk) PQ_WITH_SRC(vs, walk_batch(src_, &sh.vst, c.td.nn, w, false, sh.vruns, VRUNCAP, sh.vfirst));
   if ((int)threadIdx.x == wdelta * 64 && is_delta)
     PQ_WITH_SRC(vs, delta_blocks(src_, vs.pos0, c.pg, c.td, c.cs.type == T_INT32, blk, sh.dmeta));
-  __syncthreads();
-  if (opt) {
-    for (;;) {
-      if (sh.dst.bad) { if (threadIdx.x == 0) set_err(err, ERR_LEVELS, c.td.page); return false; }
-      PQ_WITH_SRC(ds, expand_levels(src_, sh.druns, sh.dfirst, sh.dst.lo, sh.dst.hi, sh.valid));
-      if (sh.dst.hi >= c.nrows) break;
-      __syncthreads();
-      if (wave == wdef) PQ_WITH_SRC(ds, walk_batch(src_, &sh.dst, c.nrows, 1, true, sh.druns, DRUNCAP, sh.dfirst));
-      __syncthreads();
-    }
+  if (wave == wrank && opt) {
+    // exclusive popcount prefix over the validity words
+    const uint32_t j = threadIdx.x & 63;
+    const uint32_t cnt = j < NWORDS ? __popc(sh.valid[j]) : 0;
+    const uint32_t inc = wave_incl_scan_u32(cnt);
+    if (j < NWORDS) sh.pre[j] = inc - cnt;
   }
+  __syncthreads();
   if (idx_walk) {
     for (;;) {
       if (sh.vst.bad) { if (threadIdx.x == 0) set_err(err, ERR_VALUES, c.td.page); return false; }
@@ -678,11 +692,6 @@ __device__ bool tile_front(const TileCtx& c, TileShared& sh, uint32_t dict_n, ui
   if (is_delta && sh.dmeta[1]) { if (threadIdx.x == 0) set_err(err, ERR_DELTA, c.td.page); return false; }
   __syncthreads();
   if (sh.flag) { if (threadIdx.x == 0) set_err(err, ERR_DICT_INDEX, c.td.page); return false; }
-  if (opt) {
-    write_validity(c, sh.valid);
-    tile_rank_prefix(sh.valid, sh.pre, c.nrows);
-    __syncthreads();
-  }
   return true;
 }
 
@@ -885,6 +894,65 @@ __global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* co
 }
 
 // ---------------------------------------------------------------------------
+// k_levels: definition levels -> output validity, one wave per tile
+// ---------------------------------------------------------------------------
+struct LevelShared {
+  uint32_t valid[NWORDS];
+  uint32_t first[NWORDS];
+  WalkState st;
+  Run runs[DRUNCAP];
+  __attribute__((aligned(16))) uint8_t stage[DSTAGE];
+};
+
+// Orders this wave's LDS accesses (no other wave takes part).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(WG) void k_levels(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
+                                               const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
+                                               const TileDev* __restrict__ tiles, SegTable seg,
+                                               uint32_t* __restrict__ err) {
+  __shared__ LevelShared lsh[NWAVES];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  LevelShared& sh = lsh[wave];
+  const uint32_t unit = blockIdx.x * NWAVES + wave;
+  int k = 0;
+  for (int j = 1; j < seg.n; ++j)
+    if (seg.s[j].wg0 <= unit) k = j;
+  const uint32_t t = seg.s[k].t0 + (unit - seg.s[k].wg0);
+  if (t >= seg.s[k].t1) return;  // the whole wave leaves
+  TileCtx c;
+  c.t = t;
+  c.td = tiles[t];
+  c.next = tiles[t + 1 < seg.s[seg.n - 1].t1 ? t + 1 : t];
+  c.cs = cols[seg.s[k].cs];
+  c.pg = pages[c.td.page];
+  c.nrows = (uint32_t)min((int64_t)TR, (int64_t)c.pg.num_values - c.td.row0);
+  c.out0 = c.pg.row0 + c.td.row0 - c.cs.row_base;
+  c.st = page_streams(c.pg, c.cs, file, ws);
+  c.has_next = c.next.page == c.td.page && c.next.row0 > c.td.row0;
+  uint64_t d0, d1;
+  level_range(c, d0, d1);
+  const Staged ds = stage(sh.stage, DSTAGE, c.st.dbase, d0, d1, lane, 64);
+  for (uint32_t j = lane; j < NWORDS; j += 64) sh.valid[j] = 0;
+  if (lane == 0) { sh.st.cur = ds.pos0; sh.st.v = -(int64_t)c.td.def_skip; sh.st.bad = 0; }
+  wave_sync();
+  for (;;) {
+    PQ_WITH_SRC(ds, walk_batch(src_, &sh.st, c.nrows, 1, true, sh.runs, DRUNCAP, sh.first));
+    wave_sync();
+    if (sh.st.bad) { if (lane == 0) set_err(err, ERR_LEVELS, c.td.page); return; }
+    const uint32_t lo = sh.st.lo, hi = sh.st.hi;
+    PQ_WITH_SRC(ds, expand_levels(src_, sh.runs, sh.first, lo, hi, sh.valid, lane, 64));
+    wave_sync();
+    if (hi >= c.nrows) break;
+  }
+  write_validity(c, sh.valid, lane, 64);
+}
+
+// ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
@@ -1005,7 +1073,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) out32[out0 + r] = x[q];
+        if (r < nrows) __builtin_nontemporal_store(x[q], &out32[out0 + r]);
       }
     } else {
       uint64_t x[PER];
@@ -1019,7 +1087,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) out64[out0 + r] = x[q];
+        if (r < nrows) __builtin_nontemporal_store(x[q], &out64[out0 + r]);
       }
     }
     return;
@@ -1039,7 +1107,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) out32[out0 + r] = x[q];
+        if (r < nrows) __builtin_nontemporal_store(x[q], &out32[out0 + r]);
       }
     } else {
       uint64_t x[PER];
@@ -1053,7 +1121,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const uint32_t r = threadIdx.x + q * WG;
-        if (r < nrows) out64[out0 + r] = x[q];
+        if (r < nrows) __builtin_nontemporal_store(x[q], &out64[out0 + r]);
       }
     }
     return;
@@ -1088,8 +1156,8 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
       const bool v = !opt || row_valid(sh.valid, r);
       const uint32_t k = opt ? row_rank(sh.valid, sh.pre, r) : r;
       const uint64_t x = v ? s_vals[k] : 0ull;
-      if (width == 4) out32[out0 + r] = (uint32_t)x;
-      else out64[out0 + r] = x;
+      if (width == 4) __builtin_nontemporal_store((uint32_t)x, &out32[out0 + r]);
+      else __builtin_nontemporal_store(x, &out64[out0 + r]);
     }
     return;
   }
@@ -1130,7 +1198,7 @@ __device__ __forceinline__ void copy_string(glb_u8* sbase, uint64_t S, __attribu
       const int lo = m == 0 ? (int)dd : 0;
       const int hi = (int)min(4u, dd + n - 4u * (uint32_t)m);
       if (lo == 0 && hi == 4) {
-        dw[m] = word;
+        __builtin_nontemporal_store(word, &dw[m]);
       } else {
         __attribute__((address_space(1))) uint8_t* b = reinterpret_cast<__attribute__((address_space(1))) uint8_t*>(dw + m);
         for (int k = lo; k < hi; ++k) b[k] = (uint8_t)(word >> (8 * k));
@@ -1237,7 +1305,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   for (int q = 0; q < PER; ++q) {
     const uint32_t r = threadIdx.x * PER + q;
     if (r < nrows) {
-      if (c.cs.offsets) gptr(c.cs.offsets)[c.out0 + r] = (int64_t)(base + run);
+      if (c.cs.offsets) __builtin_nontemporal_store((int64_t)(base + run), &gptr(c.cs.offsets)[c.out0 + r]);
       s_off[r] = (uint32_t)run;
     }
     run += lens[q];
