@@ -18,22 +18,27 @@ namespace pqk {
 __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* err);
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckd, uint32_t* ckv,
+                        uint32_t* err);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
 __global__ void k_levels(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                         const TileDev* tiles, SegTable seg, uint32_t* err);
+                         const TileDev* tiles, const uint32_t* ckd, SegTable seg, uint32_t* err);
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
                        DictSlot* slots, const uint32_t* strck, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                          const TileDev* tiles, const DictSlot* slots, SegTable seg, uint32_t* err);
+                          const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, SegTable seg,
+                          uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const DictSlot* slots, SegTable seg, uint32_t* err);
+                               const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, SegTable seg,
+                               uint32_t* err);
+__global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
+                               const TileDev* tiles, const uint32_t* ckv, SegTable seg, uint32_t* err);
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                             const TileDev* tiles, const DictSlot* slots, const uint32_t* strck, SegTable seg,
-                             uint32_t* err);
+                             const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, const uint32_t* strck,
+                             SegTable seg, uint32_t* err);
 }  // namespace pqk
 
 using namespace pqk;
@@ -241,6 +246,8 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
+constexpr int NKERN = 9;  // kernels with a profiling slot
+
 struct pq_file_s {
   const uint8_t* file = nullptr;
   uint64_t len = 0;
@@ -256,6 +263,8 @@ struct pq_file_s {
   PageDev* d_pages = nullptr;
   TileDev* d_tiles = nullptr;
   uint32_t* d_strck = nullptr;
+  uint32_t* d_ckd = nullptr;  // level-stream checkpoints, NSUB per tile
+  uint32_t* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
   ChunkDev* d_chunks = nullptr;
   uint32_t* d_err = nullptr;
   pq_file_stats stats{};
@@ -264,12 +273,12 @@ struct pq_file_s {
   struct Rec { int kernel; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
-  double prof_ms[8] = {0};
-  uint64_t prof_n[8] = {0};
+  double prof_ms[NKERN] = {0};
+  uint64_t prof_n[NKERN] = {0};
 };
 
-static const char* kKernelNames[8] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
-                                      "k_decode_fixed", "k_decode_str", "k_levels"};
+static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
+                                          "k_decode_fixed", "k_decode_str", "k_levels", "k_decode_delta"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -310,6 +319,8 @@ static void free_handle(pq_file f) {
   if (f->d_pages) (void)hipFree(f->d_pages);
   if (f->d_tiles) (void)hipFree(f->d_tiles);
   if (f->d_strck) (void)hipFree(f->d_strck);
+  if (f->d_ckd) (void)hipFree(f->d_ckd);
+  if (f->d_ckv) (void)hipFree(f->d_ckv);
   if (f->d_chunks) (void)hipFree(f->d_chunks);
   if (f->d_err) (void)hipFree(f->d_err);
   delete f;
@@ -533,14 +544,18 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
   }
   if (tiles) {
-    if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: tile index allocation"); }
+    if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess ||
+        hipMalloc(&f->d_ckd, sizeof(uint32_t) * NSUB * tiles) != hipSuccess ||
+        hipMalloc(&f->d_ckv, sizeof(uint32_t) * NSUB * tiles) != hipSuccess) {
+      cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: tile index allocation");
+    }
   }
   if (strck) {
     if (hipMalloc(&f->d_strck, sizeof(uint32_t) * strck) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: checkpoint allocation"); }
   }
   if (npages) {
     hipLaunchKernelGGL(k_index, dim3((npages + 63) / 64), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
-                       f->d_chunks, f->d_tiles, f->d_strck, f->d_err);
+                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckd, f->d_ckv, f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
   }
   HIP_OR(hipEventRecord(e1, s));
@@ -615,10 +630,12 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, str_segs, lev_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs, lev_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_wgs = 0, fixed_wgs = 0, str_wgs = 0, lev_units = 0;
+  // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0,
+           lev_units = 0;
   uint32_t dict_grid_x = 0;
   uint64_t ws_which = 0;
 };
@@ -676,10 +693,13 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
       P.slots.push_back(sl);
     }
-    bool has_delta = false;
+    bool has_delta = false, has_other = false;
     if (cs.type != T_BYTE_ARRAY)
-      for (uint32_t p = cs.page_begin; p < cs.page_end; ++p)
-        if (f->pages[p].kind != PAGE_DICT && f->pages[p].encoding == E_DELTA) { has_delta = true; break; }
+      for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
+        if (f->pages[p].kind == PAGE_DICT) continue;
+        if (f->pages[p].encoding == E_DELTA) has_delta = true;
+        else has_other = true;
+      }
     const uint32_t nt = cs.tile_end - cs.tile_begin;
     if (cs.type == T_BYTE_ARRAY || has_delta) {
       cs.ws_tile_aux = off;
@@ -688,17 +708,21 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     const uint32_t idx = (uint32_t)P.cols.size();
     if (nt) {
       if (cs.type == T_BYTE_ARRAY) {
-        P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_wgs});
-        P.pre_wgs += nt;
-        P.str_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_wgs});
-        P.str_wgs += nt;
+        P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
+        P.pre_units += nt;
+        P.str_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units});
+        P.str_units += nt;
       } else {
         if (has_delta) {
-          P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_wgs});
-          P.pre_wgs += nt;
+          P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
+          P.pre_units += nt;
+          P.delta_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.delta_units});
+          P.delta_units += nt;
         }
-        P.fixed_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_wgs});
-        P.fixed_wgs += nt;
+        if (has_other) {
+          P.fixed_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_units});
+          P.fixed_units += nt;
+        }
       }
       P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
       P.prep_threads += nt;
@@ -742,10 +766,10 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        (int)P.cols.size(), f->d_pages, d_slots, f->d_strck, f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (P.pre_wgs) {
+  if (P.pre_units) {
     ProfScope ps_(f, 2, s);
-    hipLaunchKernelGGL(k_prepass, dim3(P.pre_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles, d_slots,
-                       make_segs(P.pre_segs), f->d_err);
+    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
+                       f->d_tiles, f->d_ckv, d_slots, make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.scan_cols.empty()) {
@@ -763,19 +787,25 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   if (P.lev_units) {
     ProfScope ps_(f, 7, s);
     hipLaunchKernelGGL(k_levels, dim3((P.lev_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, make_segs(P.lev_segs), f->d_err);
+                       f->d_tiles, f->d_ckd, make_segs(P.lev_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (P.fixed_wgs) {
+  if (P.fixed_units) {
     ProfScope ps_(f, 5, s);
-    hipLaunchKernelGGL(k_decode_fixed, dim3(P.fixed_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
-                       d_slots, make_segs(P.fixed_segs), f->d_err);
+    hipLaunchKernelGGL(k_decode_fixed, dim3((P.fixed_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
+                       f->d_pages, f->d_tiles, f->d_ckv, d_slots, make_segs(P.fixed_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (P.str_wgs) {
+  if (P.delta_units) {
+    ProfScope ps_(f, 8, s);
+    hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
+                       f->d_pages, f->d_tiles, f->d_ckv, make_segs(P.delta_segs), f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.str_units) {
     ProfScope ps_(f, 6, s);
-    hipLaunchKernelGGL(k_decode_str, dim3(P.str_wgs), dim3(256), 0, s, file, ws, d_cols, f->d_pages, f->d_tiles,
-                       d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
+    hipLaunchKernelGGL(k_decode_str, dim3((P.str_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
+                       f->d_tiles, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
@@ -870,7 +900,7 @@ extern "C" pq_status pq_profile(pq_file f, int32_t enable) {
   if (!f) return fail(PQ_EINVAL, "NULL handle");
   for (auto& r : f->recs) { f->event_pool.push_back(r.a); f->event_pool.push_back(r.b); }
   f->recs.clear();
-  for (int k = 0; k < 8; ++k) { f->prof_ms[k] = 0; f->prof_n[k] = 0; }
+  for (int k = 0; k < NKERN; ++k) { f->prof_ms[k] = 0; f->prof_n[k] = 0; }
   f->profiling = enable != 0;
   return PQ_OK;
 }
@@ -888,7 +918,7 @@ extern "C" pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t cap
   }
   f->recs.clear();
   int32_t k = 0;
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NKERN; ++j) {
     if (!f->prof_n[j]) continue;
     if (out && k < capacity) {
       memset(out[k].name, 0, sizeof(out[k].name));

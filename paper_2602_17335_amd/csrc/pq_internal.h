@@ -34,6 +34,15 @@ enum : uint32_t {
 
 // Tile = fixed number of rows of one data page.
 constexpr int TILE_ROWS = 1024;
+// Sub-tile checkpoints: every tile also records the entry points of its
+// level stream at every SUB_ROWS rows and of its value stream at every
+// SUB_ROWS values (dictionary indices) or at every block (DELTA), so that a
+// scan decodes the pieces of a tile independently.  Each checkpoint packs a
+// byte offset relative to the tile's entry and a skip count as two u16
+// (low: offset, high: skip); CK_NONE marks one that does not fit.
+constexpr int SUB_ROWS = 64;
+constexpr int NSUB = TILE_ROWS / SUB_ROWS;
+constexpr uint32_t CK_NONE = 0xffffffffu;
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;

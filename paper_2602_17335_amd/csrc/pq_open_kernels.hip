@@ -136,8 +136,13 @@ __device__ inline uint32_t bp_popcount(BR& r, uint64_t pay, uint64_t k) {
 
 // One lane per page.  `scratch` holds every compressed page decompressed at
 // its file-wide scratch offset.
+__device__ __forceinline__ uint32_t pack_ck(uint64_t delta, uint64_t skip) {
+  return (delta < 0xffffu && skip < 0xffffu) ? (uint32_t)(delta | (skip << 16)) : CK_NONE;
+}
+
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* err) {
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckd, uint32_t* ckv,
+                        uint32_t* err) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npages) return;
   PageDev pg = pages[p];
@@ -215,7 +220,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
   const int64_t nv = pg.num_values;
   const uint32_t ntiles = (uint32_t)((nv + TILE_ROWS - 1) / TILE_ROWS);
 
-  // ---- definition levels: tile entry points and non-null counts ----
+  // ---- definition levels: tile entry points, sub-tile checkpoints, non-null counts ----
   uint32_t nonnull = 0;
   if (ch.optional) {
     r.init(dbase);
@@ -224,24 +229,28 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     c.next = def_off; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = def_off;
     uint64_t before = 0;  // valid rows in runs before the current one
     bool have = false;
-    for (uint32_t t = 0; t < ntiles; ++t) {
-      const int64_t target = (int64_t)t * TILE_ROWS;
+    TileDev td;
+    for (int64_t target = 0; target < nv; target += SUB_ROWS) {
       while (!have || c.start + (int64_t)c.n <= target) {
         if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
         if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
         have = true;
       }
       const uint64_t skip = (uint64_t)(target - c.start);
-      TileDev td;
-      td.page = (uint32_t)p;
-      td.row0 = (uint32_t)target;
-      td.k0 = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, skip) : (uint64_t)c.val * skip));
-      td.nn = 0;
-      td.def_pos = (uint32_t)(c.hp - def_off);
-      td.def_skip = (uint32_t)skip;
-      td.val_pos = 0;
-      td.val_skip = 0;
-      tiles[pg.tile_begin + t] = td;
+      const uint32_t t = (uint32_t)(target / TILE_ROWS), sub = (uint32_t)((target % TILE_ROWS) / SUB_ROWS);
+      if (sub == 0) {
+        td.page = (uint32_t)p;
+        td.row0 = (uint32_t)target;
+        td.k0 = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, skip) : (uint64_t)c.val * skip));
+        td.nn = 0;
+        td.def_pos = (uint32_t)(c.hp - def_off);
+        td.def_skip = (uint32_t)skip;
+        td.val_pos = 0;
+        td.val_skip = 0;
+        tiles[pg.tile_begin + t] = td;
+        for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
+      }
+      ckd[(size_t)(pg.tile_begin + t) * NSUB + sub] = pack_ck(c.hp - def_off - td.def_pos, skip);
     }
     if (nv > 0) {
       while (!have || c.start + (int64_t)c.n < nv) {
@@ -262,8 +271,11 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       td.nn = 0;
       td.def_pos = 0; td.def_skip = 0; td.val_pos = 0; td.val_skip = 0;
       tiles[pg.tile_begin + t] = td;
+      for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
     }
   }
+  for (uint32_t t = 0; t < ntiles; ++t)
+    for (int k = 0; k < NSUB; ++k) ckv[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
   if (pg.kind == PAGE_DATA_V2 && (int64_t)pg.num_nulls != nv - (int64_t)nonnull) { set_err(err, ERR_V2, p); return; }
   pg.nonnull = nonnull;
   for (uint32_t t = 0; t < ntiles; ++t) {
@@ -308,14 +320,21 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       c.next = val_off + 1; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = val_off + 1;
       bool have = false;
       for (uint32_t t = 0; t < ntiles; ++t) {
-        const int64_t target = (int64_t)tiles[pg.tile_begin + t].k0;
-        if (target >= (int64_t)nonnull) continue;  // tile without values
-        while (!have || c.start + (int64_t)c.n <= target) {
-          if (!run_next(r, vend, w, c)) { set_err(err, ERR_VALUES, p); return; }
-          have = true;
+        TileDev& tdr = tiles[pg.tile_begin + t];
+        const uint32_t k0 = tdr.k0, nnt = tdr.nn;
+        for (uint32_t sub = 0; sub < NSUB && sub * SUB_ROWS < nnt; ++sub) {
+          const int64_t target = (int64_t)k0 + (int64_t)sub * SUB_ROWS;
+          while (!have || c.start + (int64_t)c.n <= target) {
+            if (!run_next(r, vend, w, c)) { set_err(err, ERR_VALUES, p); return; }
+            have = true;
+          }
+          if (sub == 0) {
+            tdr.val_pos = (uint32_t)(c.hp - val_off);
+            tdr.val_skip = (uint32_t)(target - c.start);
+          }
+          ckv[(size_t)(pg.tile_begin + t) * NSUB + sub] =
+              pack_ck(c.hp - val_off - tdr.val_pos, (uint64_t)(target - c.start));
         }
-        tiles[pg.tile_begin + t].val_pos = (uint32_t)(c.hp - val_off);
-        tiles[pg.tile_begin + t].val_skip = (uint32_t)(target - c.start);
       }
       while (!have || c.start + (int64_t)c.n < (int64_t)nonnull) {
         if (!run_next(r, vend, w, c)) { set_err(err, ERR_VALUES, p); return; }
@@ -344,7 +363,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
       tiles[pg.tile_begin + t].val_skip = 0;
     }
-    uint32_t t = 0;
+    uint32_t t = 0, ulo = 0;
     for (uint64_t b = 0; b < nblocks; ++b) {
       while (t < ntiles) {
         const TileDev td = tiles[pg.tile_begin + t];
@@ -356,6 +375,23 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
         tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
         tiles[pg.tile_begin + t].val_skip = (uint32_t)((first - 1) % B);
         ++t;
+      }
+      // this block's header, as checkpoint (b - entry block) of every tile
+      // entered so far whose deltas reach block b; tiles before `ulo` end
+      // before it
+      while (ulo < t) {
+        const TileDev tu = tiles[pg.tile_begin + ulo];
+        if (tu.nn != 0 && (uint64_t)tu.k0 + tu.nn > 1 && ((uint64_t)tu.k0 + tu.nn - 2) / B >= b) break;
+        ++ulo;
+      }
+      for (uint32_t u = ulo; u < t; ++u) {
+        const TileDev tu = tiles[pg.tile_begin + u];
+        if (tu.nn == 0 || (uint64_t)tu.k0 + tu.nn <= 1) continue;
+        const uint64_t fu = tu.k0 == 0 ? 1 : tu.k0;
+        const uint64_t bu = (fu - 1) / B;                    // entry block of tile u
+        const uint64_t lastb = ((uint64_t)tu.k0 + tu.nn - 2) / B;  // block of its last delta
+        if (b >= bu && b <= lastb && b - bu < NSUB)
+          ckv[(size_t)(pg.tile_begin + u) * NSUB + (b - bu)] = pack_ck(q - val_off - tu.val_pos, 0);
       }
       br_uleb(r, q, vend, bad);  // min delta
       if (bad || M > vend - q) { set_err(err, ERR_DELTA, p); return; }
