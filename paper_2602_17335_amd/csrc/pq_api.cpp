@@ -23,8 +23,6 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
-__global__ void k_levels(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                         const TileDev* tiles, const uint32_t* ckd, SegTable seg, uint32_t* err);
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
                        DictSlot* slots, const uint32_t* strck, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
@@ -32,13 +30,14 @@ __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols,
                           uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, SegTable seg,
-                               uint32_t* err);
+                               const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, const DictSlot* slots,
+                               SegTable seg, uint32_t* err);
 __global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckv, SegTable seg, uint32_t* err);
+                               const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, SegTable seg,
+                               uint32_t* err);
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                             const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, const uint32_t* strck,
-                             SegTable seg, uint32_t* err);
+                             const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, const DictSlot* slots,
+                             const uint32_t* strck, SegTable seg, uint32_t* err);
 }  // namespace pqk
 
 using namespace pqk;
@@ -246,7 +245,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 9;  // kernels with a profiling slot
+constexpr int NKERN = 8;  // kernels with a profiling slot
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -278,7 +277,7 @@ struct pq_file_s {
 };
 
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
-                                          "k_decode_fixed", "k_decode_str", "k_levels", "k_decode_delta"};
+                                          "k_decode_fixed", "k_decode_str", "k_decode_delta"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -630,12 +629,11 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs, lev_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0,
-           lev_units = 0;
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0;
   uint32_t dict_grid_x = 0;
   uint64_t ws_which = 0;
 };
@@ -726,10 +724,6 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
       P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
       P.prep_threads += nt;
-      if (cs.optional) {
-        P.lev_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.lev_units});
-        P.lev_units += nt;
-      }
     }
     if (cs.type == T_BYTE_ARRAY || has_delta) P.scan_cols.push_back((int32_t)idx);
     if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
@@ -784,28 +778,22 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
   }
-  if (P.lev_units) {
-    ProfScope ps_(f, 7, s);
-    hipLaunchKernelGGL(k_levels, dim3((P.lev_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckd, make_segs(P.lev_segs), f->d_err);
-    HIP_OR(hipGetLastError());
-  }
   if (P.fixed_units) {
     ProfScope ps_(f, 5, s);
     hipLaunchKernelGGL(k_decode_fixed, dim3((P.fixed_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckv, d_slots, make_segs(P.fixed_segs), f->d_err);
+                       f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, d_slots, make_segs(P.fixed_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {
-    ProfScope ps_(f, 8, s);
+    ProfScope ps_(f, 7, s);
     hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckv, make_segs(P.delta_segs), f->d_err);
+                       f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, make_segs(P.delta_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.str_units) {
     ProfScope ps_(f, 6, s);
     hipLaunchKernelGGL(k_decode_str, dim3((P.str_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
+                       f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;

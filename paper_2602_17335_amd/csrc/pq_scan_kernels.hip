@@ -5,12 +5,11 @@
 //   k_dict          dictionary pages -> device dictionaries
 //   k_prepass       per-tile DELTA sums and string byte counts
 //   k_tile_scan     exclusive prefix over tiles (DELTA carries, string bases)
-//   k_levels        definition levels -> validity bitmap
-//   k_decode_fixed  PLAIN / dictionary INT32, INT64, DOUBLE values
-//   k_decode_delta  DELTA_BINARY_PACKED INT32 / INT64 values
-//   k_decode_str    PLAIN / dictionary BYTE_ARRAY values -> offsets and chars
+//   k_decode_fixed  definition levels; PLAIN / dictionary INT32, INT64, DOUBLE values
+//   k_decode_delta  definition levels; DELTA_BINARY_PACKED INT32 / INT64 values
+//   k_decode_str    definition levels; PLAIN / dictionary BYTE_ARRAY values -> offsets and chars
 //
-// Work unit of the level, prepass and decode kernels: one TILE_ROWS-row tile
+// Work unit of the prepass and decode kernels: one TILE_ROWS-row tile
 // of one page per wave, four independent tiles per 256-thread workgroup, no
 // workgroup barriers.  A tile is entered through the index built at open:
 // besides the tile's own entry points, the run header holding every SUB_ROWS-th
@@ -211,55 +210,10 @@ __device__ __forceinline__ bool wave_tile(const SegTable& seg, const ColScan* co
   return true;
 }
 
-// Validity word j = lane (< 32) of the tile, read back from the output bitmap
-// (k_levels wrote it); all ones over the tile's rows for a REQUIRED column.
-__device__ __forceinline__ uint32_t tile_valid_word(const WaveTile& c, uint32_t lane) {
-  const uint32_t j = lane;
-  if (j >= NWORDS || j * 32 >= c.nrows) return 0u;
-  const uint32_t rem = c.nrows - j * 32;
-  const uint32_t tail = rem < 32 ? (1u << rem) - 1u : 0xffffffffu;
-  if (!c.cs.optional) return tail;
-  const int64_t b = c.out0 + (int64_t)j * 32;
-  glb_u32* v = gptr(reinterpret_cast<const uint32_t*>(c.cs.validity));
-  const int64_t W = b >> 5;
-  const uint32_t sh = (uint32_t)(b & 31);
-  const int64_t nw = (c.cs.rows + 31) >> 5;
-  const uint32_t lo = v[W];
-  const uint32_t hi = (sh && W + 1 < nw) ? v[W + 1] : 0u;
-  return (sh ? ((lo >> sh) | (hi << (32 - sh))) : lo) & tail;
-}
-
 // validity of the 64 rows of group g (word 2g: rows 64g .. 64g+31)
 __device__ __forceinline__ uint64_t group_mask(uint32_t vw, uint32_t g) {
   return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vw, (int)(2 * g)) |
          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)vw, (int)(2 * g + 1)) << 32);
-}
-
-// Writes the tile's validity words (s_valid, one wave) into the output bitmap.
-__device__ __forceinline__ void write_validity(const WaveTile& c, const uint32_t* s_valid, uint32_t lane) {
-  if (!c.cs.validity) return;
-  const int64_t out0 = c.out0;
-  const int64_t w_first = out0 >> 5;
-  const int64_t w_last = (out0 + c.nrows - 1) >> 5;
-  __attribute__((address_space(1))) uint32_t* vout = gptr(reinterpret_cast<uint32_t*>(c.cs.validity));
-  for (int64_t W = w_first + lane; W <= w_last; W += 64) {
-    const int64_t b0 = W * 32 - out0;
-    uint32_t word;
-    if (b0 >= 0) {
-      const uint32_t tw = (uint32_t)(b0 >> 5), sh = (uint32_t)(b0 & 31);
-      const uint32_t lo = s_valid[tw];
-      const uint32_t hi2 = (tw + 1 < NWORDS) ? s_valid[tw + 1] : 0u;
-      word = sh ? ((lo >> sh) | (hi2 << (32 - sh))) : lo;
-    } else {
-      word = s_valid[0] << (uint32_t)(-b0);
-    }
-    const int64_t lo_b = b0 < 0 ? -b0 : 0;
-    const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
-    const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
-    word &= mask;
-    if (mask == 0xffffffffu) __builtin_nontemporal_store(word, &vout[W]);
-    else if (word) atomicOr(reinterpret_cast<uint32_t*>(c.cs.validity) + W, word);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -349,6 +303,81 @@ __device__ __forceinline__ void lane_entry(const uint32_t* ck, uint32_t t, uint3
     p = pos;
     rs = -(int64_t)skip;
   }
+}
+
+// Definition levels of the tile: lane j (< 32) returns validity word j
+// (rows 32 j .. 32 j + 31; all ones over the tile's rows for a REQUIRED
+// column).  Lane l decodes rows [16 l, 16 l + 16) from its checkpoint; false
+// (wave-uniform) when the level stream is malformed.
+__device__ __forceinline__ bool tile_levels(const WaveTile& c, const uint32_t* ckd, uint32_t lane, uint32_t& vw) {
+  if (!c.cs.optional) {
+    const uint32_t j = lane;
+    vw = 0;
+    if (j < NWORDS && j * 32 < c.nrows) {
+      const uint32_t rem = c.nrows - j * 32;
+      vw = rem < 32 ? (1u << rem) - 1u : 0xffffffffu;
+    }
+    return true;
+  }
+  const GSrc ds = gsrc(c.st.dbase, c.st.doff, c.st.dend);
+  const int64_t a = (int64_t)lane * LPER, b = min((int64_t)c.nrows, a + LPER);
+  uint32_t half = 0;  // levels of rows [a, a + 16)
+  bool ok = true;
+  if (a < b) {
+    uint64_t p;
+    int64_t rs;
+    lane_entry(ckd, c.t, lane, c.td.def_pos, c.td.def_skip, p, rs);
+    ok = walk_runs(ds, p, rs, 1, true, a, b, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
+      const uint32_t n = (uint32_t)(hi - lo);
+      const uint32_t m = bp ? (uint32_t)ds.bits(x, n) : (x ? (uint32_t)((1ull << n) - 1) : 0u);
+      half |= m << (uint32_t)(lo - a);
+    });
+  }
+  const uint32_t lo16 = __shfl(half, (int)((2 * lane) & 63), 64);
+  const uint32_t hi16 = __shfl(half, (int)((2 * lane + 1) & 63), 64);
+  vw = lane < NWORDS ? (lo16 | (hi16 << 16)) : 0u;
+  return !__ballot(!ok);
+}
+
+// Writes the tile's validity words (lane j holds word j) into the output
+// bitmap: words wholly inside the tile are stored, the two edge words shared
+// with the neighbouring tiles are ORed in (k_prep cleared them).
+__device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, uint32_t lane) {
+  const int64_t out0 = c.out0;
+  const int64_t w_first = out0 >> 5;
+  const int64_t w_last = (out0 + c.nrows - 1) >> 5;
+  const int64_t W = w_first + lane;  // at most 33 words: one per lane
+  const int64_t b0 = W * 32 - out0;  // tile bit of the word's first bit
+  const int32_t tw = b0 < 0 ? 0 : (int32_t)min(b0 >> 5, (int64_t)NWORDS - 1);
+  const uint32_t lo = __shfl(vw, tw, 64);
+  const uint32_t hi = __shfl(vw, min(tw + 1, NWORDS - 1), 64);
+  if (W > w_last) return;
+  uint32_t word;
+  if (b0 >= 0) {
+    const uint32_t sh = (uint32_t)(b0 & 31);
+    word = sh ? ((lo >> sh) | ((tw + 1 < NWORDS ? hi : 0u) << (32 - sh))) : lo;
+  } else {
+    word = lo << (uint32_t)(-b0);
+  }
+  const int64_t lo_b = b0 < 0 ? -b0 : 0;
+  const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
+  const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
+  word &= mask;
+  __attribute__((address_space(1))) uint32_t* vout = gptr(reinterpret_cast<uint32_t*>(c.cs.validity));
+  if (mask == 0xffffffffu) __builtin_nontemporal_store(word, &vout[W]);
+  else if (word) atomicOr(reinterpret_cast<uint32_t*>(c.cs.validity) + W, word);
+}
+
+// Levels of the tile (validity word per lane, see tile_levels), written to
+// the output bitmap of an OPTIONAL column.  False after recording an error.
+__device__ __forceinline__ bool tile_validity(const WaveTile& c, const uint32_t* ckd, uint32_t lane, uint32_t* err,
+                                              uint32_t& vw) {
+  if (!tile_levels(c, ckd, lane, vw)) {
+    if (lane == 0) set_err(err, ERR_LEVELS, c.td.page);
+    return false;
+  }
+  if (c.cs.optional && c.cs.validity) write_validity(c, vw, lane);
+  return true;
 }
 
 // Dictionary indices of the tile's values [16 lane, 16 lane + 16) into
@@ -504,22 +533,73 @@ __device__ __forceinline__ void copy_string(glb_u8* sbase, uint64_t S, DU8* dst,
     for (int k = 0; k < 9; ++k) rr[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
     const uint32_t dd = (uint32_t)(d & 3);
     DU32* dw = reinterpret_cast<DU32*>(dst + (d & ~3ull));
-    const uint32_t ndw = (dd + n + 3) >> 2;
+    const uint32_t end = dd + n;
 #pragma unroll
     for (int m = 0; m < 10; ++m) {
-      if ((uint32_t)m >= ndw) break;
       const uint32_t prev = m == 0 ? 0u : rr[m - 1 < 9 ? m - 1 : 8];
       const uint32_t curw = m < 9 ? rr[m] : 0u;
       const uint32_t word = dd ? __builtin_amdgcn_alignbyte(curw, prev, 4 - dd) : curw;
-      // bytes of destination word m that belong to this string: [lo, hi)
-      const int lo = m == 0 ? (int)dd : 0;
-      const int hi = (int)min(4u, dd + n - 4u * (uint32_t)m);
-      if (lo == 0 && hi == 4) {
-        if constexpr (NT) __builtin_nontemporal_store(word, &dw[m]);
-        else dw[m] = word;
-      } else {
-        DU8* b = reinterpret_cast<DU8*>(dw + m);
-        for (int k = lo; k < hi; ++k) b[k] = (uint8_t)(word >> (8 * k));
+      const uint32_t b0 = 4u * m;
+      if (b0 < end) {
+        if ((m > 0 || dd == 0) && b0 + 4 <= end) {
+          if constexpr (NT) __builtin_nontemporal_store(word, &dw[m]);
+          else dw[m] = word;
+        } else {
+          DU8* b = reinterpret_cast<DU8*>(dw + m);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (b0 + k >= dd && b0 + k < end) b[k] = (uint8_t)(word >> (8 * k));
+        }
+      }
+    }
+  }
+}
+
+// One lane copies one string of L bytes from byte S of a 4-byte aligned
+// source base into the wave's LDS buffer at byte D, 44 bytes per step: the
+// source is read as at most three 16-byte pieces (one load instruction each),
+// realigned with byte funnel shifts and written as aligned LDS dwords (single
+// bytes at the string's two ends).  A step reads at most 15 bytes past the
+// string.
+__device__ __forceinline__ void copy_to_lds(glb_u8* sbase, uint64_t S, lds_u8* dst, uint32_t D, uint32_t L) {
+  typedef uint32_t v4a __attribute__((ext_vector_type(4), aligned(4)));
+  for (uint32_t j0 = 0; j0 < L; j0 += 44) {
+    const uint32_t n = min(44u, L - j0);
+    const uint64_t s = S + j0;
+    const uint32_t d = D + j0;
+    const uint32_t ss = (uint32_t)(s & 3);
+    const uint32_t nsw = (ss + n + 3) >> 2;  // source dwords, <= 12
+    const __attribute__((address_space(1))) v4a* q =
+        reinterpret_cast<const __attribute__((address_space(1))) v4a*>(sbase + (s & ~3ull));
+    uint32_t w[13];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v4a x = {0u, 0u, 0u, 0u};
+      if ((uint32_t)(4 * c) < nsw) x = q[c];
+      w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
+    }
+    w[12] = 0u;
+    uint32_t rr[12];  // string bytes [j0 + 4k, j0 + 4k + 4)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) rr[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
+    const uint32_t dd = d & 3;
+    lds_u32* dw = reinterpret_cast<lds_u32*>(dst + (d & ~3u));
+    const uint32_t end = dd + n;  // destination bytes [dd, end) of the words written
+    // every index below is a compile-time constant (no register indexing)
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+      const uint32_t prev = m == 0 ? 0u : rr[m - 1];
+      const uint32_t word = dd ? __builtin_amdgcn_alignbyte(rr[m], prev, 4 - dd) : rr[m];
+      const uint32_t b0 = 4u * m;
+      if (b0 < end) {
+        if ((m > 0 || dd == 0) && b0 + 4 <= end) {
+          dw[m] = word;
+        } else {
+          lds_u8* b = reinterpret_cast<lds_u8*>(dw + m);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (b0 + k >= dd && b0 + k < end) b[k] = (uint8_t)(word >> (8 * k));
+        }
       }
     }
   }
@@ -766,41 +846,6 @@ __global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* co
 
 
 // ---------------------------------------------------------------------------
-// k_levels: definition levels -> output validity bitmap
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_levels(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                               const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                               const TileDev* __restrict__ tiles, const uint32_t* __restrict__ ckd,
-                                               SegTable seg, uint32_t* __restrict__ err) {
-  __shared__ uint32_t s_valid[NWAVES][NWORDS];
-  WaveTile c;
-  if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const GSrc ds = gsrc(c.st.dbase, c.st.doff, c.st.dend);
-  const int64_t a = (int64_t)lane * LPER, b = min((int64_t)c.nrows, a + LPER);
-  uint32_t word = 0;  // levels of rows [a, a + 16)
-  bool ok = true;
-  if (a < b) {
-    uint64_t p;
-    int64_t rs;
-    lane_entry(ckd, c.t, lane, c.td.def_pos, c.td.def_skip, p, rs);
-    ok = walk_runs(ds, p, rs, 1, true, a, b, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
-      const uint32_t n = (uint32_t)(hi - lo);
-      const uint32_t m = bp ? (uint32_t)ds.bits(x, n) : (x ? (uint32_t)((1ull << n) - 1) : 0u);
-      word |= m << (uint32_t)(lo - a);
-    });
-  }
-  if (__ballot(!ok)) {
-    if (lane == 0) set_err(err, ERR_LEVELS, c.td.page);
-    return;
-  }
-  const uint32_t up = __shfl_down(word, 1, 64);
-  if (!(lane & 1)) s_valid[wave][lane >> 1] = word | (up << 16);
-  wave_sync();
-  write_validity(c, s_valid[wave], lane);
-}
-
-// ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
@@ -868,6 +913,7 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
 __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
+                                                     const uint32_t* __restrict__ ckd,
                                                      const uint32_t* __restrict__ ckv,
                                                      const DictSlot* __restrict__ slots, SegTable seg,
                                                      uint32_t* __restrict__ err) {
@@ -882,7 +928,8 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);
     return;
   }
-  const uint32_t vw = tile_valid_word(c, lane);
+  uint32_t vw;
+  if (!tile_validity(c, ckd, lane, err, vw)) return;
   lds_u32* idx = (lds_u32*)&s_idx[wave][0];
   glb_u8* ent = nullptr;
   if (is_dict) {
@@ -957,6 +1004,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
+                                                     const uint32_t* __restrict__ ckd,
                                                      const uint32_t* __restrict__ ckv, SegTable seg,
                                                      uint32_t* __restrict__ err) {
   __shared__ uint64_t s_vals[NWAVES][PADN];
@@ -964,7 +1012,8 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t vw = tile_valid_word(c, lane);
+  uint32_t vw;
+  if (!tile_validity(c, ckd, lane, err, vw)) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
   if (c.td.nn > 0) {
     uint64_t D[LPER];
@@ -1025,13 +1074,16 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
 __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                    const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                    const TileDev* __restrict__ tiles,
+                                                   const uint32_t* __restrict__ ckd,
                                                    const uint32_t* __restrict__ ckv,
                                                    const DictSlot* __restrict__ slots,
                                                    const uint32_t* __restrict__ strck, SegTable seg,
                                                    uint32_t* __restrict__ err) {
-  constexpr uint32_t CBW = GROUP_CHARS / 4 + 8;
-  __shared__ uint32_t s_idx[NWAVES][PADN];
-  __shared__ __align__(16) uint32_t s_chars[NWAVES][CBW];
+  // per wave: the value positions (indices) of the tile, then, once every
+  // row's (position, length) is in registers, the chars staging buffer
+  constexpr uint32_t BUFW = PADN + GROUP_CHARS / 4 + 8;
+  constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
+  __shared__ __align__(16) uint32_t s_buf[NWAVES][BUFW];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1042,8 +1094,9 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);
     return;
   }
-  const uint32_t vw = tile_valid_word(c, lane);
-  lds_u32* u = (lds_u32*)&s_idx[wave][0];
+  uint32_t vw;
+  if (!tile_validity(c, ckd, lane, err, vw)) return;
+  lds_u32* u = (lds_u32*)&s_buf[wave][0];
   const TileDev& td = c.td;
   glb_u8* sbase;
   uint64_t soff;
@@ -1104,54 +1157,86 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   const bool fits = c.cs.chars && tend <= c.cs.chars_capacity;
   gout_u8* chars = gptr(c.cs.chars);
   __attribute__((address_space(1))) int64_t* offs = gptr(c.cs.offsets);
-  lds_u32* cb = (lds_u32*)&s_chars[wave][0];
-  lds_u8* cb8 = (lds_u8*)cb;
-  const uint32_t ng = (c.nrows + 63) / 64;
 
-  // (pos, len) of row 64 g + lane, whose group starts at value kbg
-  auto fetch = [&](uint32_t g, uint32_t kbg, uint32_t& pos, uint32_t& len) {
-    const uint64_t m = group_mask(vw, g);
-    pos = 0;
-    len = 0;
-    const uint32_t k = kbg + rank_below(m);
-    if (((m >> lane) & 1) && k < td.nn) {
+  // (position, length) of row 64 g + lane for all groups: every gather of
+  // the tile is issued before the first store
+  uint32_t pos[NGROUPS], len[NGROUPS];
+  {
+    uint32_t kb = 0;
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+      const uint64_t m = group_mask(vw, g);
+      const uint32_t k = kb + rank_below(m);
+      kb += (uint32_t)__popcll(m);
+      const bool v = ((m >> lane) & 1) && k < td.nn;
+      const uint32_t kc = v ? k : 0u;
       if (is_plain) {
-        const uint32_t q0 = u[pad(k)], q1 = u[pad(k + 1)];
-        pos = q0 + 4;
-        len = q1 - q0 - 4;
+        const uint32_t q0 = u[pad(kc)], q1 = u[pad(kc + 1)];
+        pos[g] = q0 + 4;
+        len[g] = v ? q1 - q0 - 4 : 0u;
       } else {
-        const uint64_t pr = pairs[u[pad(k)]];
-        pos = (uint32_t)pr;
-        len = (uint32_t)(pr >> 32);
+        const uint64_t pr = td.nn ? pairs[u[pad(kc)]] : 0ull;
+        pos[g] = (uint32_t)pr;
+        len[g] = v ? (uint32_t)(pr >> 32) : 0u;
       }
     }
-  };
-
-  uint32_t pn, ln;
-  fetch(0, 0, pn, ln);
-  uint32_t kb = 0;  // values before group g
-  uint64_t tb = 0;  // chars before group g
-  for (uint32_t g = 0; g < ng; ++g) {
-    const uint32_t pos = pn, len = ln;
-    const uint32_t kn = kb + (uint32_t)__popcll(group_mask(vw, g));
-    if (g + 1 < ng) fetch(g + 1, kn, pn, ln);  // the next group's gathers overlap this group's copies
-    const uint32_t incl = wave_incl_scan_u32(len);
-    const uint32_t ex = incl - len;
-    const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    const uint32_t r = 64 * g + lane;
-    if (c.cs.offsets && r < c.nrows) __builtin_nontemporal_store((int64_t)(base + tb + ex), &offs[c.out0 + r]);
-    if (fits && T) {
-      if (T <= GROUP_CHARS) {
-        if (len) copy_string<lds_u8, lds_u32, false>(sbase, soff + pos, cb8, ex, len);
-        wave_sync();
-        store_group(cb, CBW, T, chars + base + tb, lane);
-        wave_sync();
-      } else if (len) {
-        copy_string<gout_u8, gout_u32, true>(sbase, soff + pos, chars, base + tb + ex, len);
-      }
+  }
+  // row offsets: exclusive scan per group, groups in row order; GB[g] is
+  // the tile-relative chars offset of group g
+  uint32_t ex[NGROUPS], T[NGROUPS], GB[NGROUPS];
+  {
+    uint32_t tb = 0;
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+      const uint32_t incl = wave_incl_scan_u32(len[g]);
+      T[g] = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      GB[g] = tb;
+      ex[g] = tb + incl - len[g];
+      tb += T[g];
     }
-    tb += T;
-    kb = kn;
+  }
+  if (c.cs.offsets) {
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+      const uint32_t r = 64 * g + lane;
+      if (r < c.nrows) __builtin_nontemporal_store((int64_t)(base + ex[g]), &offs[c.out0 + r]);
+    }
+  }
+  if (!fits) return;
+  // chars: consecutive groups are gathered into the wave's LDS buffer until
+  // it is full, then the batch is stored with aligned 16-byte chunks (one
+  // wait for earlier stores per batch, not per group); a group larger than
+  // the buffer is copied directly.  The buffer reuses the index area, whose
+  // every entry was read above.
+  wave_sync();
+  lds_u32* cb = (lds_u32*)&s_buf[wave][0];
+  lds_u8* cb8 = (lds_u8*)cb;
+  uint32_t bstart = 0, bfill = 0;  // the batch holds tile chars [bstart, bstart + bfill)
+  for (int g = 0; g < NGROUPS; ++g) {
+    if (T[g] == 0) continue;
+    if (T[g] > CB) {
+      if (bfill) {
+        wave_sync();
+        store_group(cb, BUFW, bfill, chars + base + bstart, lane);
+        wave_sync();
+        bfill = 0;
+      }
+      if (len[g]) copy_string<gout_u8, gout_u32, true>(sbase, soff + pos[g], chars, base + ex[g], len[g]);
+      continue;
+    }
+    if (bfill + T[g] > CB) {
+      wave_sync();
+      store_group(cb, BUFW, bfill, chars + base + bstart, lane);
+      wave_sync();
+      bfill = 0;
+    }
+    if (bfill == 0) bstart = GB[g];
+    if (len[g]) copy_to_lds(sbase, soff + pos[g], cb8, ex[g] - bstart, len[g]);
+    bfill += T[g];
+  }
+  if (bfill) {
+    wave_sync();
+    store_group(cb, BUFW, bfill, chars + base + bstart, lane);
   }
 }
 
