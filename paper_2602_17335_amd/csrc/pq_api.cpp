@@ -18,7 +18,7 @@ namespace pqk {
 __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckd, uint32_t* ckv,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, Ck* ckd, Ck* ckv,
                         uint32_t* err);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
@@ -26,17 +26,17 @@ __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev*
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
                        DictSlot* slots, const uint32_t* strck, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                          const TileDev* tiles, const uint32_t* ckv, const DictSlot* slots, SegTable seg,
+                          const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
                           uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, const DictSlot* slots,
+                               const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
                                SegTable seg, uint32_t* err);
 __global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, SegTable seg,
+                               const TileDev* tiles, const Ck* ckd, const Ck* ckv, SegTable seg,
                                uint32_t* err);
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                             const TileDev* tiles, const uint32_t* ckd, const uint32_t* ckv, const DictSlot* slots,
+                             const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
                              const uint32_t* strck, SegTable seg, uint32_t* err);
 }  // namespace pqk
 
@@ -262,8 +262,8 @@ struct pq_file_s {
   PageDev* d_pages = nullptr;
   TileDev* d_tiles = nullptr;
   uint32_t* d_strck = nullptr;
-  uint32_t* d_ckd = nullptr;  // level-stream checkpoints, NSUB per tile
-  uint32_t* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
+  Ck* d_ckd = nullptr;  // level-stream checkpoints, NSUB per tile
+  Ck* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
   ChunkDev* d_chunks = nullptr;
   uint32_t* d_err = nullptr;
   pq_file_stats stats{};
@@ -544,8 +544,8 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   }
   if (tiles) {
     if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess ||
-        hipMalloc(&f->d_ckd, sizeof(uint32_t) * NSUB * tiles) != hipSuccess ||
-        hipMalloc(&f->d_ckv, sizeof(uint32_t) * NSUB * tiles) != hipSuccess) {
+        hipMalloc(&f->d_ckd, sizeof(Ck) * NSUB * tiles) != hipSuccess ||
+        hipMalloc(&f->d_ckv, sizeof(Ck) * NSUB * tiles) != hipSuccess) {
       cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: tile index allocation");
     }
   }

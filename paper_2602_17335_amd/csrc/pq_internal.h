@@ -34,15 +34,26 @@ enum : uint32_t {
 
 // Tile = fixed number of rows of one data page.
 constexpr int TILE_ROWS = 1024;
-// Sub-tile checkpoints: every tile also records the entry points of its
-// level stream at every SUB_ROWS rows and of its value stream at every
-// SUB_ROWS values (dictionary indices) or at every block (DELTA), so that a
-// scan decodes the pieces of a tile independently.  Each checkpoint packs a
-// byte offset relative to the tile's entry and a skip count as two u16
-// (low: offset, high: skip); CK_NONE marks one that does not fit.
+// Sub-tile checkpoints: every tile also records, for its level stream at
+// every SUB_ROWS-th row and for its dictionary-index stream at every
+// SUB_ROWS-th value, the state of the hybrid run holding that row or value,
+// so that a scan decodes the pieces of a tile independently and reads the
+// payload directly.
+//   at:   byte offset from the tile's entry position of the byte holding the
+//         value's first bit (bit-packed run), or of the run header (RLE run)
+//   info: bit 31 set: bit-packed; bits 28..30 the bit within that byte.
+//         RLE runs of a level stream: bit 29 set, bit 30 the level.
+//         bits 0..27: values left in the run from this one (clamped).
+// DELTA streams record the byte offset of each block header in `at`.
+// at == CK_NONE: not recorded (the tile's entry point is used).
 constexpr int SUB_ROWS = 64;
 constexpr int NSUB = TILE_ROWS / SUB_ROWS;
 constexpr uint32_t CK_NONE = 0xffffffffu;
+constexpr uint32_t CK_LEFT = 0x0fffffffu;
+struct Ck {
+  uint32_t at;
+  uint32_t info;
+};
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;

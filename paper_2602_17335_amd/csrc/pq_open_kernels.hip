@@ -134,14 +134,47 @@ __device__ inline uint32_t bp_popcount(BR& r, uint64_t pay, uint64_t k) {
   return s;
 }
 
-// One lane per page.  `scratch` holds every compressed page decompressed at
-// its file-wide scratch offset.
-__device__ __forceinline__ uint32_t pack_ck(uint64_t delta, uint64_t skip) {
-  return (delta < 0xffffu && skip < 0xffffu) ? (uint32_t)(delta | (skip << 16)) : CK_NONE;
+// Checkpoint of value `target` inside run c of a w-bit hybrid stream whose
+// tile entry sits at absolute position `entry`.
+__device__ __forceinline__ Ck make_ck(const RunCur& c, int64_t target, uint32_t w, uint64_t entry, bool levels) {
+  Ck k;
+  k.at = CK_NONE;
+  k.info = 0;
+  const uint64_t skip = (uint64_t)(target - c.start);
+  const uint64_t left = min(c.n - skip, (uint64_t)CK_LEFT);
+  if (c.bp) {
+    const uint64_t bit = c.pay * 8 + skip * w;
+    const uint64_t off = (bit >> 3) - entry;
+    if (off >= CK_NONE) return k;
+    k.at = (uint32_t)off;
+    k.info = 0x80000000u | ((uint32_t)(bit & 7) << 28) | (uint32_t)left;
+  } else {
+    const uint64_t off = c.hp - entry;
+    if (off >= CK_NONE) return k;
+    k.at = (uint32_t)off;
+    k.info = (uint32_t)left | (levels ? ((1u << 29) | ((c.val & 1u) << 30)) : 0u);
+  }
+  return k;
 }
 
+__device__ __forceinline__ Ck ck_at(uint64_t off) {
+  Ck k;
+  k.at = off < CK_NONE ? (uint32_t)off : CK_NONE;
+  k.info = 0;
+  return k;
+}
+
+__device__ __forceinline__ Ck ck_none() {
+  Ck k;
+  k.at = CK_NONE;
+  k.info = 0;
+  return k;
+}
+
+// One lane per page.  `scratch` holds every compressed page decompressed at
+// its file-wide scratch offset.
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckd, uint32_t* ckv,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, Ck* ckd, Ck* ckv,
                         uint32_t* err) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npages) return;
@@ -248,9 +281,9 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
         td.val_pos = 0;
         td.val_skip = 0;
         tiles[pg.tile_begin + t] = td;
-        for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
+        for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
       }
-      ckd[(size_t)(pg.tile_begin + t) * NSUB + sub] = pack_ck(c.hp - def_off - td.def_pos, skip);
+      ckd[(size_t)(pg.tile_begin + t) * NSUB + sub] = make_ck(c, target, 1, def_off + td.def_pos, true);
     }
     if (nv > 0) {
       while (!have || c.start + (int64_t)c.n < nv) {
@@ -271,11 +304,11 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       td.nn = 0;
       td.def_pos = 0; td.def_skip = 0; td.val_pos = 0; td.val_skip = 0;
       tiles[pg.tile_begin + t] = td;
-      for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
+      for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
     }
   }
   for (uint32_t t = 0; t < ntiles; ++t)
-    for (int k = 0; k < NSUB; ++k) ckv[(size_t)(pg.tile_begin + t) * NSUB + k] = CK_NONE;
+    for (int k = 0; k < NSUB; ++k) ckv[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
   if (pg.kind == PAGE_DATA_V2 && (int64_t)pg.num_nulls != nv - (int64_t)nonnull) { set_err(err, ERR_V2, p); return; }
   pg.nonnull = nonnull;
   for (uint32_t t = 0; t < ntiles; ++t) {
@@ -332,8 +365,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
             tdr.val_pos = (uint32_t)(c.hp - val_off);
             tdr.val_skip = (uint32_t)(target - c.start);
           }
-          ckv[(size_t)(pg.tile_begin + t) * NSUB + sub] =
-              pack_ck(c.hp - val_off - tdr.val_pos, (uint64_t)(target - c.start));
+          ckv[(size_t)(pg.tile_begin + t) * NSUB + sub] = make_ck(c, target, w, val_off + tdr.val_pos, false);
         }
       }
       while (!have || c.start + (int64_t)c.n < (int64_t)nonnull) {
@@ -391,7 +423,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
         const uint64_t bu = (fu - 1) / B;                    // entry block of tile u
         const uint64_t lastb = ((uint64_t)tu.k0 + tu.nn - 2) / B;  // block of its last delta
         if (b >= bu && b <= lastb && b - bu < NSUB)
-          ckv[(size_t)(pg.tile_begin + u) * NSUB + (b - bu)] = pack_ck(q - val_off - tu.val_pos, 0);
+          ckv[(size_t)(pg.tile_begin + u) * NSUB + (b - bu)] = ck_at(q - val_off - tu.val_pos);
       }
       br_uleb(r, q, vend, bad);  // min delta
       if (bad || M > vend - q) { set_err(err, ERR_DELTA, p); return; }

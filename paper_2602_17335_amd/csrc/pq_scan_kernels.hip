@@ -290,26 +290,46 @@ __device__ __forceinline__ bool walk_runs(const GSrc& s, uint64_t p, int64_t rs,
   return true;
 }
 
-// Entry of lane `lane` into a tile's stream: the checkpoint of its sub-tile
-// when recorded, else the tile's own entry point.
-__device__ __forceinline__ void lane_entry(const uint32_t* ck, uint32_t t, uint32_t lane, uint32_t pos, uint32_t skip,
-                                           uint64_t& p, int64_t& rs) {
-  const uint32_t sub = lane >> 2;
-  const uint32_t k = ck[(size_t)t * NSUB + sub];
-  if (k != CK_NONE) {
-    p = (uint64_t)pos + (k & 0xffffu);
-    rs = (int64_t)sub * SUB_ROWS - (int64_t)(k >> 16);
+// Hands the pieces of values [a, b) of a hybrid stream to f (as walk_runs),
+// entering at checkpoint k of the sub-tile whose first value is numbered cr
+// (cr <= a): the run holding value cr is taken from the checkpoint itself, so
+// a lane whose values lie in that run reads only their payload.  `entry` is
+// the stream position the checkpoint offsets count from; without a recorded
+// checkpoint the walk starts at (fb_pos, fb_rs), the tile's entry point.
+template <class Src, class F>
+__device__ __forceinline__ bool ck_walk(const Src& s, uint64_t entry, Ck k, int64_t cr, uint32_t w, bool levels,
+                                        int64_t a, int64_t b, uint64_t fb_pos, int64_t fb_rs, F&& f) {
+  if (k.at == CK_NONE) return walk_runs(s, fb_pos, fb_rs, w, levels, a, b, f);
+  const int64_t rend = cr + (int64_t)(k.info & CK_LEFT);  // one past the run's last value
+  const uint64_t pos = entry + k.at;
+  const int64_t hi = min(b, rend);
+  uint64_t next;
+  if (k.info >> 31) {
+    const uint64_t bit0 = pos * 8 + ((k.info >> 28) & 7u);  // first bit of value cr
+    if (hi > a) {
+      if ((bit0 + (uint64_t)(hi - cr) * w + 7) / 8 > s.len) return false;
+      f(a, hi, true, bit0 + (uint64_t)(a - cr) * w);
+    }
+    if (rend >= b) return true;
+    next = (bit0 + (uint64_t)(rend - cr) * w) >> 3;
+  } else if (levels && (k.info & (1u << 29)) && rend >= b) {
+    f(a, b, false, (k.info >> 30) & 1u);
+    return true;
   } else {
-    p = pos;
-    rs = -(int64_t)skip;
+    const Hdr H = read_hdr(s, pos, w);
+    if (!H.ok || H.bp || (levels && H.pay > 1)) return false;
+    if (hi > a) f(a, hi, false, H.pay);
+    if (rend >= b) return true;
+    next = pos + H.adv;
   }
+  return walk_runs(s, next, rend, w, levels, max(a, rend), b, f);
 }
 
 // Definition levels of the tile: lane j (< 32) returns validity word j
 // (rows 32 j .. 32 j + 31; all ones over the tile's rows for a REQUIRED
 // column).  Lane l decodes rows [16 l, 16 l + 16) from its checkpoint; false
 // (wave-uniform) when the level stream is malformed.
-__device__ __forceinline__ bool tile_levels(const WaveTile& c, const uint32_t* ckd, uint32_t lane, uint32_t& vw) {
+__device__ __forceinline__ bool tile_levels(const WaveTile& c, Ck ck, uint32_t lane, uint32_t& vw) {
   if (!c.cs.optional) {
     const uint32_t j = lane;
     vw = 0;
@@ -324,10 +344,8 @@ __device__ __forceinline__ bool tile_levels(const WaveTile& c, const uint32_t* c
   uint32_t half = 0;  // levels of rows [a, a + 16)
   bool ok = true;
   if (a < b) {
-    uint64_t p;
-    int64_t rs;
-    lane_entry(ckd, c.t, lane, c.td.def_pos, c.td.def_skip, p, rs);
-    ok = walk_runs(ds, p, rs, 1, true, a, b, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
+    ok = ck_walk(ds, c.td.def_pos, ck, (int64_t)(lane >> 2) * SUB_ROWS, 1, true, a, b, c.td.def_pos,
+                 -(int64_t)c.td.def_skip, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
       const uint32_t n = (uint32_t)(hi - lo);
       const uint32_t m = bp ? (uint32_t)ds.bits(x, n) : (x ? (uint32_t)((1ull << n) - 1) : 0u);
       half |= m << (uint32_t)(lo - a);
@@ -370,9 +388,8 @@ __device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, u
 
 // Levels of the tile (validity word per lane, see tile_levels), written to
 // the output bitmap of an OPTIONAL column.  False after recording an error.
-__device__ __forceinline__ bool tile_validity(const WaveTile& c, const uint32_t* ckd, uint32_t lane, uint32_t* err,
-                                              uint32_t& vw) {
-  if (!tile_levels(c, ckd, lane, vw)) {
+__device__ __forceinline__ bool tile_validity(const WaveTile& c, Ck ck, uint32_t lane, uint32_t* err, uint32_t& vw) {
+  if (!tile_levels(c, ck, lane, vw)) {
     if (lane == 0) set_err(err, ERR_LEVELS, c.td.page);
     return false;
   }
@@ -382,17 +399,14 @@ __device__ __forceinline__ bool tile_validity(const WaveTile& c, const uint32_t*
 
 // Dictionary indices of the tile's values [16 lane, 16 lane + 16) into
 // idx[pad(j)].  Returns 0, ERR_VALUES or ERR_DICT_INDEX (wave-uniform).
-__device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, const uint32_t* ckv, uint32_t dn, uint32_t lane,
-                                                   lds_u32* idx) {
+__device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, Ck ck, uint32_t dn, uint32_t lane, lds_u32* idx) {
   const GSrc vs = gsrc(c.st.vbase, c.st.voff, c.st.vend);
   const uint32_t w = c.pg.enc_w;
   const int64_t a = (int64_t)lane * LPER, b = min((int64_t)c.td.nn, a + LPER);
   bool ok = true, bad_idx = false;
   if (a < b) {
-    uint64_t p;
-    int64_t rs;
-    lane_entry(ckv, c.t, lane, c.td.val_pos, c.td.val_skip, p, rs);
-    ok = walk_runs(vs, p, rs, w, false, a, b, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
+    ok = ck_walk(vs, c.td.val_pos, ck, (int64_t)(lane >> 2) * SUB_ROWS, w, false, a, b, c.td.val_pos,
+                 -(int64_t)c.td.val_skip, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
       for (int64_t v = lo; v < hi; ++v) {
         uint32_t id = bp ? (uint32_t)vs.bits(x + (uint64_t)(v - lo) * w, w) : (uint32_t)x;
         if (id >= dn) { bad_idx = true; id = 0; }
@@ -411,12 +425,12 @@ __device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, const uint
 // Block header position of page block `bb` for tile c, whose first delta
 // lies in block bu: the recorded checkpoint, else a walk over the blocks from
 // the tile's entry block.  False on a malformed block.
-__device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s, const uint32_t* ckv, uint64_t bb,
+__device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s, const Ck* ckv, uint64_t bb,
                                                 uint64_t bu, bool is32, uint64_t& hp) {
   const uint64_t slot = bb - bu;
   if (slot < NSUB) {
-    const uint32_t k = ckv[(size_t)c.t * NSUB + slot];
-    if (k != CK_NONE) { hp = (uint64_t)c.td.val_pos + (k & 0xffffu); return true; }
+    const uint32_t k = ckv[(size_t)c.t * NSUB + slot].at;
+    if (k != CK_NONE) { hp = (uint64_t)c.td.val_pos + k; return true; }
   }
   const uint64_t B = c.pg.enc_w, M = c.pg.enc_m, per = B / M, total = c.pg.nonnull;
   const uint32_t maxw = is32 ? 32 : 64;
@@ -447,7 +461,7 @@ __device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s
 // D of the tile's values [16 lane, 16 lane + 16): the page's first value for
 // value 0, else the delta that leads to the value.  Values past nn get 0.
 // Returns false on a malformed block (wave-uniform after a ballot by the caller).
-__device__ __forceinline__ bool delta_terms(const WaveTile& c, const uint32_t* ckv, uint32_t lane, uint64_t* D) {
+__device__ __forceinline__ bool delta_terms(const WaveTile& c, const Ck* ckv, uint32_t lane, uint64_t* D) {
   const GSrc s = gsrc(c.st.vbase, c.st.voff, c.st.vend);
   const bool is32 = c.cs.type == T_INT32;
   const uint32_t maxw = is32 ? 32 : 64;
@@ -850,12 +864,13 @@ __global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* co
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                 const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                                const TileDev* __restrict__ tiles, const uint32_t* __restrict__ ckv,
+                                                const TileDev* __restrict__ tiles, const Ck* __restrict__ ckv,
                                                 const DictSlot* __restrict__ slots, SegTable seg,
                                                 uint32_t* __restrict__ err) {
   __shared__ uint32_t s_idx[NWAVES][PADN];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
+  const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __attribute__((address_space(1))) uint64_t* aux =
       gptr(reinterpret_cast<uint64_t*>(ws + c.cs.ws_tile_aux)) + (c.t - c.cs.tile_begin);
@@ -887,7 +902,7 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
       return;
     }
     lds_u32* idx = (lds_u32*)&s_idx[wave][0];
-    const uint32_t e = decode_indices(c, ckv, sl.n, lane, idx);
+    const uint32_t e = decode_indices(c, ckx, sl.n, lane, idx);
     if (e) {
       if (lane == 0) set_err(err, e, c.td.page);
       return;
@@ -913,13 +928,16 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
 __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ ckd,
-                                                     const uint32_t* __restrict__ ckv,
+                                                     const Ck* __restrict__ ckd,
+                                                     const Ck* __restrict__ ckv,
                                                      const DictSlot* __restrict__ slots, SegTable seg,
                                                      uint32_t* __restrict__ err) {
   __shared__ uint32_t s_idx[NWAVES][PADN];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
+  // checkpoint words first: their loads overlap the tile's metadata loads
+  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -929,7 +947,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, ckd, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, vw)) return;
   lds_u32* idx = (lds_u32*)&s_idx[wave][0];
   glb_u8* ent = nullptr;
   if (is_dict) {
@@ -939,7 +957,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
       if (lane == 0) set_err(err, ERR_DICT_MISSING, c.td.page);
       return;
     }
-    const uint32_t e = decode_indices(c, ckv, sl.n, lane, idx);
+    const uint32_t e = decode_indices(c, ckx, sl.n, lane, idx);
     if (e) {
       if (lane == 0) set_err(err, e, c.td.page);
       return;
@@ -1004,16 +1022,17 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ ckd,
-                                                     const uint32_t* __restrict__ ckv, SegTable seg,
+                                                     const Ck* __restrict__ ckd,
+                                                     const Ck* __restrict__ ckv, SegTable seg,
                                                      uint32_t* __restrict__ err) {
   __shared__ uint64_t s_vals[NWAVES][PADN];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
+  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t vw;
-  if (!tile_validity(c, ckd, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, vw)) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
   if (c.td.nn > 0) {
     uint64_t D[LPER];
@@ -1074,8 +1093,8 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
 __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                    const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                    const TileDev* __restrict__ tiles,
-                                                   const uint32_t* __restrict__ ckd,
-                                                   const uint32_t* __restrict__ ckv,
+                                                   const Ck* __restrict__ ckd,
+                                                   const Ck* __restrict__ ckv,
                                                    const DictSlot* __restrict__ slots,
                                                    const uint32_t* __restrict__ strck, SegTable seg,
                                                    uint32_t* __restrict__ err) {
@@ -1086,6 +1105,9 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   __shared__ __align__(16) uint32_t s_buf[NWAVES][BUFW];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
+  // checkpoint words first: their loads overlap the tile's metadata loads
+  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int enc = c.pg.encoding;
   const bool is_plain = enc == E_PLAIN;
@@ -1095,7 +1117,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, ckd, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, vw)) return;
   lds_u32* u = (lds_u32*)&s_buf[wave][0];
   const TileDev& td = c.td;
   glb_u8* sbase;
@@ -1139,7 +1161,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     sbase = (glb_u8*)sl.body;
     soff = sl.body_off;
     pairs = reinterpret_cast<glb_u64*>(gptr(ws + sl.ws_entries));
-    const uint32_t e = decode_indices(c, ckv, sl.n, lane, u);
+    const uint32_t e = decode_indices(c, ckx, sl.n, lane, u);
     if (e) {
       if (lane == 0) set_err(err, e, td.page);
       return;
