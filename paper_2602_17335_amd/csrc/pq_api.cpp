@@ -23,6 +23,8 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
+__global__ void k_edges(const uint8_t* ws, const ColScan* cols, const PageDev* pages, const TileDev* tiles,
+                        SegTable seg);
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
                        DictSlot* slots, const uint32_t* strck, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
@@ -245,7 +247,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 8;  // kernels with a profiling slot
+constexpr int NKERN = 9;  // kernels with a profiling slot
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -277,7 +279,7 @@ struct pq_file_s {
 };
 
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
-                                          "k_decode_fixed", "k_decode_str", "k_decode_delta"};
+                                          "k_decode_fixed", "k_decode_str", "k_decode_delta", "k_edges"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -629,11 +631,12 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs, edge_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0;
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0,
+           edge_threads = 0;
   uint32_t dict_grid_x = 0;
   uint64_t ws_which = 0;
 };
@@ -699,6 +702,10 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
         else has_other = true;
       }
     const uint32_t nt = cs.tile_end - cs.tile_begin;
+    if (cs.optional && nt) {
+      cs.ws_edge = off;
+      off = align_up(off + 8ull * nt, 256);
+    }
     if (cs.type == T_BYTE_ARRAY || has_delta) {
       cs.ws_tile_aux = off;
       off = align_up(off + 8ull * (nt + 1), 256);
@@ -722,8 +729,13 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
           P.fixed_units += nt;
         }
       }
-      P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
-      P.prep_threads += nt;
+      if (!cs.optional) {
+        P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
+        P.prep_threads += nt;
+      } else {
+        P.edge_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.edge_threads});
+        P.edge_threads += nt;
+      }
     }
     if (cs.type == T_BYTE_ARRAY || has_delta) P.scan_cols.push_back((int32_t)idx);
     if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
@@ -794,6 +806,12 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     ProfScope ps_(f, 6, s);
     hipLaunchKernelGGL(k_decode_str, dim3((P.str_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.edge_threads) {
+    ProfScope ps_(f, 8, s);
+    hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, f->d_pages,
+                       f->d_tiles, make_segs(P.edge_segs));
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;

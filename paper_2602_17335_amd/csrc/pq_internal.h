@@ -155,6 +155,7 @@ struct ColScan {
   uint8_t* chars;
   int32_t nrg;            // row groups in the file (chunk = col * nrg + rg)
   int32_t pad_;
+  uint64_t ws_edge;       // workspace offset of per-tile validity edge words (OPTIONAL columns)
 };
 
 // A run of tiles handled by one launch: ColScan `cs`, tiles [t0, t1),

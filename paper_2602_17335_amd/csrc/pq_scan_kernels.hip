@@ -358,12 +358,14 @@ __device__ __forceinline__ bool tile_levels(const WaveTile& c, Ck ck, uint32_t l
 }
 
 // Writes the tile's validity words (lane j holds word j) into the output
-// bitmap: words wholly inside the tile are stored, the two edge words shared
-// with the neighbouring tiles are ORed in (k_prep cleared them).
-__device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, uint32_t lane) {
-  const int64_t out0 = c.out0;
+// bitmap.  Words that lie inside the tile (and the column's last word when it
+// starts inside the tile) are stored; a word shared with a neighbouring tile
+// is left to k_edges, which ORs the tiles' contributions: every tile records
+// its bits of the words holding its first and its last row.
+__device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, uint32_t lane, uint8_t* ws) {
+  const int64_t out0 = c.out0, E = out0 + c.nrows;
   const int64_t w_first = out0 >> 5;
-  const int64_t w_last = (out0 + c.nrows - 1) >> 5;
+  const int64_t w_last = (E - 1) >> 5;
   const int64_t W = w_first + lane;  // at most 33 words: one per lane
   const int64_t b0 = W * 32 - out0;  // tile bit of the word's first bit
   const int32_t tw = b0 < 0 ? 0 : (int32_t)min(b0 >> 5, (int64_t)NWORDS - 1);
@@ -381,19 +383,23 @@ __device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, u
   const int64_t hi_b = (int64_t)c.nrows - b0 < 32 ? (int64_t)c.nrows - b0 : 32;
   const uint32_t mask = (hi_b >= 32 ? 0xffffffffu : ((1u << hi_b) - 1)) & (0xffffffffu << lo_b);
   word &= mask;
-  __attribute__((address_space(1))) uint32_t* vout = gptr(reinterpret_cast<uint32_t*>(c.cs.validity));
-  if (mask == 0xffffffffu) __builtin_nontemporal_store(word, &vout[W]);
-  else if (word) atomicOr(reinterpret_cast<uint32_t*>(c.cs.validity) + W, word);
+  if (W * 32 >= out0 && (W * 32 + 32 <= E || E == c.cs.rows))
+    __builtin_nontemporal_store(word, &gptr(reinterpret_cast<uint32_t*>(c.cs.validity))[W]);
+  __attribute__((address_space(1))) uint32_t* edge =
+      gptr(reinterpret_cast<uint32_t*>(ws + c.cs.ws_edge)) + 2 * (size_t)(c.t - c.cs.tile_begin);
+  if (W == w_first) edge[0] = word;
+  if (W == w_last) edge[1] = word;
 }
 
 // Levels of the tile (validity word per lane, see tile_levels), written to
 // the output bitmap of an OPTIONAL column.  False after recording an error.
-__device__ __forceinline__ bool tile_validity(const WaveTile& c, Ck ck, uint32_t lane, uint32_t* err, uint32_t& vw) {
+__device__ __forceinline__ bool tile_validity(const WaveTile& c, Ck ck, uint32_t lane, uint32_t* err, uint8_t* ws,
+                                              uint32_t& vw) {
   if (!tile_levels(c, ck, lane, vw)) {
     if (lane == 0) set_err(err, ERR_LEVELS, c.td.page);
     return false;
   }
-  if (c.cs.optional && c.cs.validity) write_validity(c, vw, lane);
+  if (c.cs.optional && c.cs.validity) write_validity(c, vw, lane, ws);
   return true;
 }
 
@@ -770,17 +776,52 @@ __global__ __launch_bounds__(WG) void k_prep(const ColScan* cols, const PageDev*
   const uint32_t nrows = (uint32_t)min((int64_t)TILE_ROWS, (int64_t)pg.num_values - td.row0);
   const int64_t r0 = pg.row0 + td.row0 - cs.row_base;
   uint32_t* v = reinterpret_cast<uint32_t*>(cs.validity);
-  if (cs.optional) {
-    if (r0 & 31) v[r0 >> 5] = 0;
-    if ((r0 + nrows) & 31) v[(r0 + nrows) >> 5] = 0;
-  } else {
-    // REQUIRED: every word whose first row lies in this tile is written
-    // whole (ones for rows < rows, zeros past the end)
-    for (int64_t W = (r0 + 31) >> 5; W * 32 < r0 + (int64_t)nrows; ++W) {
-      const int64_t left = cs.rows - W * 32;
-      v[W] = left >= 32 ? 0xffffffffu : ((1u << left) - 1);
-    }
+  if (cs.optional) return;
+  // REQUIRED: every word whose first row lies in this tile is written whole
+  // (ones for rows < rows, zeros past the end)
+  for (int64_t W = (r0 + 31) >> 5; W * 32 < r0 + (int64_t)nrows; ++W) {
+    const int64_t left = cs.rows - W * 32;
+    v[W] = left >= 32 ? 0xffffffffu : ((1u << left) - 1);
   }
+}
+
+// ---------------------------------------------------------------------------
+// k_edges: validity words shared by neighbouring tiles.  One thread per tile;
+// the last tile touching a shared word (the word holding its first row, when
+// that word starts in an earlier tile) ORs the contributions the tiles
+// recorded (their bits of the words holding their first and last rows).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_edges(const uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                              const PageDev* __restrict__ pages, const TileDev* __restrict__ tiles,
+                                              SegTable seg) {
+  const uint32_t gid = blockIdx.x * WG + threadIdx.x;  // one thread per tile
+  int k = 0;
+  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
+  const uint32_t t = seg.s[k].t0 + (gid - seg.s[k].wg0);
+  if (t >= seg.s[k].t1) return;
+  const ColScan cs = cols[seg.s[k].cs];
+  if (!cs.validity || !cs.optional) return;
+  auto span = [&](uint32_t u, int64_t& r0) {
+    const TileDev td = tiles[u];
+    const PageDev pg = pages[td.page];
+    r0 = pg.row0 + td.row0 - cs.row_base;
+    return (uint32_t)min((int64_t)TILE_ROWS, (int64_t)pg.num_values - td.row0);
+  };
+  int64_t r0;
+  const uint32_t nrows = span(t, r0);
+  const int64_t E = r0 + nrows;
+  if ((r0 & 31) == 0) return;  // the word holding the first row starts in this tile, which stored it
+  const int64_t W = r0 >> 5;
+  if (E < (W + 1) * 32 && E != cs.rows) return;  // a later tile also ends inside that word
+  const uint32_t* edge = reinterpret_cast<const uint32_t*>(ws + cs.ws_edge);
+  uint32_t word = edge[2 * (t - cs.tile_begin)];
+  uint32_t u = t;
+  while (r0 > W * 32 && u > cs.tile_begin) {  // earlier tiles whose last rows are in the word
+    --u;
+    span(u, r0);
+    word |= edge[2 * (u - cs.tile_begin) + 1];
+  }
+  reinterpret_cast<uint32_t*>(cs.validity)[W] = word;
 }
 
 // ---------------------------------------------------------------------------
@@ -947,7 +988,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
   lds_u32* idx = (lds_u32*)&s_idx[wave][0];
   glb_u8* ent = nullptr;
   if (is_dict) {
@@ -1032,7 +1073,7 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
   if (c.td.nn > 0) {
     uint64_t D[LPER];
@@ -1117,7 +1158,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, vw)) return;
+  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
   lds_u32* u = (lds_u32*)&s_buf[wave][0];
   const TileDev& td = c.td;
   glb_u8* sbase;
