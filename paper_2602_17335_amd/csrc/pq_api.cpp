@@ -31,6 +31,7 @@ __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols,
                           const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
                           uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
+__global__ void k_dict_slots(uint8_t* ws, const DictSlot* slots);
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                                const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
                                SegTable seg, uint32_t* err);
@@ -638,6 +639,7 @@ struct Plan {
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0,
            edge_threads = 0;
   uint32_t dict_grid_x = 0;
+  uint32_t slot_grid_y = 0;  // k_dict_slots: chunks of 256 entries of the largest slotted dictionary
   uint64_t ws_which = 0;
 };
 
@@ -689,6 +691,17 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
         sl.ws_entries = off;
         const uint64_t bytes = cs.type == T_BYTE_ARRAY ? 8ull * sl.n : (uint64_t)cs.width * sl.n;
         off = align_up(off + bytes + 16, 256);
+        if (cs.type == T_BYTE_ARRAY) {
+          if (dp.dict_maxlen < 65536) sl.flags |= DICT_LENS16;
+          sl.ws_lens = off;
+          off = align_up(off + (uint64_t)((sl.flags & DICT_LENS16) ? 2 : 4) * sl.n + 16, 256);
+          if (dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32)) {
+            sl.flags |= DICT_SLOTS;
+            sl.ws_slots = off;
+            off = align_up(off + (uint64_t)SLOT_BYTES * sl.n, 256);
+            P.slot_grid_y = std::max(P.slot_grid_y, (sl.n + 255) / 256);
+          }
+        }
         const uint32_t gx = cs.type == T_BYTE_ARRAY ? (sl.n / STR_CK + 1 + 255) / 256 : (sl.n + 8191) / 8192;
         P.dict_grid_x = std::max(P.dict_grid_x, std::max(gx, 1u));
       }
@@ -784,6 +797,11 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     HIP_OR(hipGetLastError());
   }
   if (plan_only) return PQ_OK;
+  if (P.slot_grid_y) {
+    ProfScope ps_(f, 1, s);
+    hipLaunchKernelGGL(k_dict_slots, dim3((uint32_t)P.slots.size(), P.slot_grid_y), dim3(256), 0, s, ws, d_slots);
+    HIP_OR(hipGetLastError());
+  }
   if (P.prep_threads) {
     ProfScope ps_(f, 4, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,

@@ -103,7 +103,7 @@ struct PageDev {
   uint32_t enc_m;
   int64_t delta_first;
   uint32_t blocks_at;
-  uint32_t pad1;
+  uint32_t dict_maxlen;  // dictionary pages of strings: length of the longest entry
 };
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.
@@ -121,13 +121,25 @@ struct TileDev {
 };
 
 // Decoded dictionary of one column chunk inside the workspace.
+// String dictionaries also get an array of entry lengths (u16 when every
+// entry is shorter than 2^16 bytes, else u32) and, when every entry fits
+// SLOT_CHARS bytes, a copy of the entries in fixed SLOT_BYTES slots (chars
+// first, u32 length in the last four bytes), so that one row's gather touches
+// one aligned 64-byte piece of memory.
+constexpr uint32_t SLOT_BYTES = 64;
+constexpr uint32_t SLOT_CHARS = 60;
+enum : uint32_t { DICT_SLOTS = 1, DICT_LENS16 = 2 };
 struct DictSlot {
   const uint8_t* body;   // 16-byte aligned base holding the dictionary page body (file or
                          // scratch), set on the device
   uint64_t body_off;     // offset of the body from `body`, set on the device
   uint64_t ws_entries;   // workspace offset: fixed-width entries, or (pos,len) u32 pairs
+  uint64_t ws_lens;      // strings: workspace offset of the entry lengths
+  uint64_t ws_slots;     // strings with DICT_SLOTS: workspace offset of the slots
   uint32_t n;            // entries (0: chunk has no dictionary)
   uint32_t page;         // dictionary page index (~0u: none)
+  uint32_t flags;        // DICT_SLOTS, DICT_LENS16
+  uint32_t pad_;
 };
 
 // Per-scan, per-selected-column table (built on the host, copied into the

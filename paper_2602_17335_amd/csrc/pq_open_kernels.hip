@@ -70,8 +70,8 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
       p.rep_len = h.type == PAGE_DATA_V2 ? h.rep_len : 0;
       p.def_off = 0; p.val_off = 0; p.val_len = 0;
       p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
-      p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u;
-      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.pad1 = 0;
+      p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u; p.dict_maxlen = 0;
+      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0;
       pages[page_base[q] + n] = p;
     }
     ++n;
@@ -193,6 +193,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     if (ch.type == T_BYTE_ARRAY) {
       r.init(base);
       uint64_t q = 0;
+      uint32_t maxlen = 0;
       for (int64_t k = 0; k < pg.num_values; ++k) {
         if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = (uint32_t)q;
         if (blen - q < 4) { set_err(err, ERR_STRING, p); return; }
@@ -200,7 +201,9 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
         q += 4;
         if (l > blen - q) { set_err(err, ERR_STRING, p); return; }
         q += l;
+        maxlen = max(maxlen, l);
       }
+      pg.dict_maxlen = maxlen;
     } else {
       uint64_t w = ch.type == T_INT32 ? 4 : 8;
       if ((uint64_t)pg.num_values * w > blen) { set_err(err, ERR_VALUES, p); return; }

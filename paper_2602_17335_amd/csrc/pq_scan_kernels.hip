@@ -861,6 +861,8 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* file, uint8_t* ws, c
       if (l > (uint64_t)pg.val_len - q) { set_err(err, ERR_STRING, sl.page); return; }
       pairs[2 * e] = (uint32_t)q;
       pairs[2 * e + 1] = l;
+      if (sl.flags & DICT_LENS16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
+      else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e] = l;
       q += l;
     }
   } else {
@@ -869,6 +871,47 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* file, uint8_t* ws, c
       if (w == 4) reinterpret_cast<uint32_t*>(ws + sl.ws_entries)[e] = ld_u32(body, boff + (uint64_t)e * 4);
       else reinterpret_cast<uint64_t*>(ws + sl.ws_entries)[e] = ld_u64(body, boff + (uint64_t)e * 8);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_dict_slots: string dictionaries whose entries all fit SLOT_CHARS bytes
+// are copied into fixed slots (one thread per entry: the string's aligned
+// source dwords realigned with byte funnel shifts, chars zero-padded, length
+// in the slot's last dword, written as four 16-byte stores).
+// grid: (dictionary slots, chunks of WG entries)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_dict_slots(uint8_t* ws, const DictSlot* slots) {
+  const DictSlot sl = slots[blockIdx.x];
+  if (sl.page == ~0u || !(sl.flags & DICT_SLOTS)) return;
+  const uint32_t e = blockIdx.y * WG + threadIdx.x;
+  if (e >= sl.n) return;
+  const uint2 pr = reinterpret_cast<const uint2*>(ws + sl.ws_entries)[e];
+  const uint64_t s = sl.body_off + pr.x;
+  const uint32_t L = pr.y;  // <= SLOT_CHARS (checked at open)
+  glb_u32* q = reinterpret_cast<glb_u32*>((glb_u8*)sl.body + (s & ~3ull));
+  const uint32_t ss = (uint32_t)(s & 3);
+  const uint32_t nsw = (ss + L + 3) >> 2;  // <= 16
+  uint32_t w[17];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) w[k] = (uint32_t)k < nsw ? q[k] : 0u;
+  w[16] = 0u;
+  uint32_t o[16];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const uint32_t x = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
+    const int keep = (int)L - 4 * k;  // string bytes in this dword
+    o[k] = keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u)));
+  }
+  o[15] = L;
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  __attribute__((address_space(1))) v4u* dst =
+      reinterpret_cast<__attribute__((address_space(1))) v4u*>(gptr(ws + sl.ws_slots + (uint64_t)e * SLOT_BYTES));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v4u v;
+    v.x = o[4 * k]; v.y = o[4 * k + 1]; v.z = o[4 * k + 2]; v.w = o[4 * k + 3];
+    __builtin_nontemporal_store(v, &dst[k]);
   }
 }
 
@@ -949,12 +992,16 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
       return;
     }
     wave_sync();
-    glb_u32* pairs = reinterpret_cast<glb_u32*>(gptr(ws + sl.ws_entries));
+    const bool l16 = sl.flags & DICT_LENS16;
+    glb_u8* lens = gptr(ws + sl.ws_lens);
     uint32_t l[LPER];
 #pragma unroll
     for (int q = 0; q < LPER; ++q) {
       const uint32_t j = lane + 64 * q;
-      l[q] = j < c.td.nn ? pairs[2 * idx[pad(j)] + 1] : 0u;
+      const uint32_t e = j < c.td.nn ? idx[pad(j)] : 0u;
+      const uint32_t x = l16 ? (uint32_t)reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[e]
+                             : reinterpret_cast<glb_u32*>(lens)[e];
+      l[q] = j < c.td.nn ? x : 0u;
     }
 #pragma unroll
     for (int q = 0; q < LPER; ++q) acc += l[q];
@@ -1164,6 +1211,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   glb_u8* sbase;
   uint64_t soff;
   glb_u64* pairs = nullptr;
+  bool use_slots = false, lens16 = false;
+  glb_u8* lens = nullptr;
   if (is_plain) {
     // u[pad(j)]: offset (in the value stream) of the length prefix of the
     // tile's value j, j <= nn; one lane per STR_CK checkpoint
@@ -1199,9 +1248,17 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       if (lane == 0) set_err(err, ERR_DICT_MISSING, td.page);
       return;
     }
-    sbase = (glb_u8*)sl.body;
-    soff = sl.body_off;
-    pairs = reinterpret_cast<glb_u64*>(gptr(ws + sl.ws_entries));
+    if (sl.flags & DICT_SLOTS) {  // entry e's chars at slot e; lengths from the length array
+      sbase = gptr(ws + sl.ws_slots);
+      soff = 0;
+      use_slots = true;
+      lens16 = sl.flags & DICT_LENS16;
+      lens = gptr(ws + sl.ws_lens);
+    } else {
+      sbase = (glb_u8*)sl.body;
+      soff = sl.body_off;
+      pairs = reinterpret_cast<glb_u64*>(gptr(ws + sl.ws_entries));
+    }
     const uint32_t e = decode_indices(c, ckx, sl.n, lane, u);
     if (e) {
       if (lane == 0) set_err(err, e, td.page);
@@ -1237,6 +1294,12 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
         const uint32_t q0 = u[pad(kc)], q1 = u[pad(kc + 1)];
         pos[g] = q0 + 4;
         len[g] = v ? q1 - q0 - 4 : 0u;
+      } else if (use_slots) {
+        const uint32_t e = td.nn ? u[pad(kc)] : 0u;
+        const uint32_t l = lens16 ? (uint32_t)reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[e]
+                                  : reinterpret_cast<glb_u32*>(lens)[e];
+        pos[g] = e * SLOT_BYTES;
+        len[g] = v ? l : 0u;
       } else {
         const uint64_t pr = td.nn ? pairs[u[pad(kc)]] : 0ull;
         pos[g] = (uint32_t)pr;
