@@ -32,6 +32,8 @@ __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols,
                           uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
 __global__ void k_dict_slots(uint8_t* ws, const DictSlot* slots);
+enum : int { FX_DICT = 1, FX_WIDE = 2 };
+template <int KIND>
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                                const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
                                SegTable seg, uint32_t* err);
@@ -632,11 +634,11 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs, delta_segs, str_segs, edge_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs, edge_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units = 0, delta_units = 0, str_units = 0,
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units = 0,
            edge_threads = 0;
   uint32_t dict_grid_x = 0;
   uint32_t slot_grid_y = 0;  // k_dict_slots: chunks of 256 entries of the largest slotted dictionary
@@ -707,12 +709,14 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
       P.slots.push_back(sl);
     }
-    bool has_delta = false, has_other = false;
+    bool has_delta = false, has_plain = false, has_dict = false;
     if (cs.type != T_BYTE_ARRAY)
       for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
         if (f->pages[p].kind == PAGE_DICT) continue;
-        if (f->pages[p].encoding == E_DELTA) has_delta = true;
-        else has_other = true;
+        const int e = f->pages[p].encoding;
+        if (e == E_DELTA) has_delta = true;
+        else if (e == E_PLAIN_DICT || e == E_RLE_DICT) has_dict = true;
+        else has_plain = true;  // PLAIN, or an encoding the kernel reports as unsupported
       }
     const uint32_t nt = cs.tile_end - cs.tile_begin;
     if (cs.optional && nt) {
@@ -737,9 +741,12 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
           P.delta_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.delta_units});
           P.delta_units += nt;
         }
-        if (has_other) {
-          P.fixed_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_units});
-          P.fixed_units += nt;
+        const int wide = cs.width == 8 ? FX_WIDE : 0;
+        for (int kind = 0; kind < 2; ++kind) {
+          if (!(kind ? has_dict : has_plain)) continue;
+          const int K = kind | wide;
+          P.fixed_segs[K].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_units[K]});
+          P.fixed_units[K] += nt;
         }
       }
       if (!cs.optional) {
@@ -808,10 +815,13 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
   }
-  if (P.fixed_units) {
+  for (int K = 0; K < 4; ++K) {
+    if (!P.fixed_units[K]) continue;
+    if (P.fixed_segs[K].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, 5, s);
-    hipLaunchKernelGGL(k_decode_fixed, dim3((P.fixed_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, d_slots, make_segs(P.fixed_segs), f->d_err);
+    auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
+    hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
+                       f->d_tiles, f->d_ckd, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {

@@ -1013,6 +1013,11 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
 // ---------------------------------------------------------------------------
 // k_decode_fixed: PLAIN and dictionary INT32 / INT64 / DOUBLE tiles
 // ---------------------------------------------------------------------------
+// One instantiation per kind of tile (FX_DICT: dictionary pages, else PLAIN;
+// FX_WIDE: 8-byte values), so that each is compiled for its own register
+// needs; a wave whose tile is of another kind leaves at once.
+enum : int { FX_DICT = 1, FX_WIDE = 2 };
+template <int KIND>
 __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
@@ -1020,7 +1025,9 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
                                                      const Ck* __restrict__ ckv,
                                                      const DictSlot* __restrict__ slots, SegTable seg,
                                                      uint32_t* __restrict__ err) {
-  __shared__ uint32_t s_idx[NWAVES][PADN];
+  constexpr bool is_dict = KIND & FX_DICT;
+  constexpr bool w4 = !(KIND & FX_WIDE);
+  __shared__ uint32_t s_idx[NWAVES][is_dict ? PADN : 1];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   // checkpoint words first: their loads overlap the tile's metadata loads
@@ -1029,16 +1036,17 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
-  if (!is_dict && enc != E_PLAIN) {
-    if (lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);
+  const bool dict_page = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
+  if (!dict_page && enc != E_PLAIN) {
+    if (is_dict && lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);  // reported once
     return;
   }
+  if (dict_page != is_dict || (c.cs.width == 4) != w4) return;  // another instantiation's tile
   uint32_t vw;
   if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
   lds_u32* idx = (lds_u32*)&s_idx[wave][0];
   glb_u8* ent = nullptr;
-  if (is_dict) {
+  if constexpr (is_dict) {
     const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
     const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
     if (sl.page == ~0u) {
@@ -1075,16 +1083,23 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   }
   if (c.td.nn == 0) vmask = 0;
   const bool any = c.td.nn != 0;
-  if (is_dict && any) {
-#pragma unroll
-    for (int i = 0; i < NGROUPS; ++i) kk[i] = idx[pad(kk[i])];
-  }
-  if (c.cs.width == 4) {
+  // one branch per case outside the row loops, so that every load of a loop
+  // is issued before the first wait
+  if constexpr (w4) {
     __attribute__((address_space(1))) uint32_t* out = gptr(reinterpret_cast<uint32_t*>(c.cs.values));
     uint32_t x[NGROUPS];
+    if (!any) {
 #pragma unroll
-    for (int i = 0; i < NGROUPS; ++i)
-      x[i] = !any ? 0u : (is_dict ? reinterpret_cast<glb_u32*>(ent)[kk[i]] : vs.u32((k0 + kk[i]) * 4));
+      for (int i = 0; i < NGROUPS; ++i) x[i] = 0;
+    } else if constexpr (is_dict) {
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) kk[i] = idx[pad(kk[i])];
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) x[i] = reinterpret_cast<glb_u32*>(ent)[kk[i]];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) x[i] = vs.u32((k0 + kk[i]) * 4);
+    }
 #pragma unroll
     for (int i = 0; i < NGROUPS; ++i) {
       const uint32_t r = 64 * i + lane;
@@ -1093,9 +1108,18 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   } else {
     __attribute__((address_space(1))) uint64_t* out = gptr(reinterpret_cast<uint64_t*>(c.cs.values));
     uint64_t x[NGROUPS];
+    if (!any) {
 #pragma unroll
-    for (int i = 0; i < NGROUPS; ++i)
-      x[i] = !any ? 0ull : (is_dict ? reinterpret_cast<glb_u64*>(ent)[kk[i]] : vs.u64((k0 + kk[i]) * 8));
+      for (int i = 0; i < NGROUPS; ++i) x[i] = 0;
+    } else if constexpr (is_dict) {
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) kk[i] = idx[pad(kk[i])];
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) x[i] = reinterpret_cast<glb_u64*>(ent)[kk[i]];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) x[i] = vs.u64((k0 + kk[i]) * 8);
+    }
 #pragma unroll
     for (int i = 0; i < NGROUPS; ++i) {
       const uint32_t r = 64 * i + lane;
@@ -1365,5 +1389,15 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     store_group(cb, BUFW, bfill, chars + base + bstart, lane);
   }
 }
+
+template __global__ void k_decode_fixed<0>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
+                                          const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_DICT>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
+                                                const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
+                                                const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_DICT | FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*,
+                                                          const TileDev*, const Ck*, const Ck*, const DictSlot*, SegTable,
+                                                          uint32_t*);
 
 }  // namespace pqk
