@@ -925,13 +925,25 @@ __global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* co
   const ColScan cs = cols[which[blockIdx.x]];
   uint64_t* aux = reinterpret_cast<uint64_t*>(ws + cs.ws_tile_aux);
   const uint32_t n = cs.tile_end - cs.tile_begin;
+  // TS_PER consecutive tiles per thread and round: every load of a round is
+  // issued before its scan, and the rounds (two barriers each) are few
+  constexpr uint32_t TS_PER = 8;
   uint64_t carry = 0;
-  for (uint32_t b = 0; b < n; b += WG) {
-    const uint32_t i = b + threadIdx.x;
-    const uint64_t v = i < n ? aux[i] : 0;
+  for (uint32_t b = 0; b < n; b += WG * TS_PER) {
+    const uint32_t i0 = b + threadIdx.x * TS_PER;
+    uint64_t v[TS_PER];
+#pragma unroll
+    for (uint32_t q = 0; q < TS_PER; ++q) v[q] = i0 + q < n ? aux[i0 + q] : 0;
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < TS_PER; ++q) sum += v[q];
     uint64_t tot;
-    const uint64_t ex = wg_excl_scan_u64(v, s_tmp, &tot);
-    if (i < n) aux[i] = carry + ex;
+    uint64_t run = carry + wg_excl_scan_u64(sum, s_tmp, &tot);
+#pragma unroll
+    for (uint32_t q = 0; q < TS_PER; ++q) {
+      if (i0 + q < n) aux[i0 + q] = run;
+      run += v[q];
+    }
     carry += tot;
   }
   if (cs.type == T_BYTE_ARRAY && threadIdx.x == 0) {
@@ -1137,7 +1149,9 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
                                                      const Ck* __restrict__ ckd,
                                                      const Ck* __restrict__ ckv, SegTable seg,
                                                      uint32_t* __restrict__ err) {
-  __shared__ uint64_t s_vals[NWAVES][PADN];
+  // per wave: the values of one half of the tile's rows (at most TR / 2)
+  constexpr uint32_t HALF = TR / 2;
+  __shared__ uint64_t s_vals[NWAVES][HALF + HALF / 16 + 4];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
@@ -1146,9 +1160,13 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
   uint32_t vw;
   if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
-  if (c.td.nn > 0) {
-    uint64_t D[LPER];
-    const bool ok = delta_terms(c, ckv, lane, D);
+  const uint32_t nn = c.td.nn;
+  // lane l holds values 16 l .. 16 l + 15 (prefix sums, in registers)
+  uint64_t V[LPER];
+#pragma unroll
+  for (int q = 0; q < LPER; ++q) V[q] = 0;
+  if (nn > 0) {
+    const bool ok = delta_terms(c, ckv, lane, V);
     if (__ballot(!ok)) {
       if (lane == 0) set_err(err, ERR_DELTA, c.td.page);
       return;
@@ -1156,43 +1174,56 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
     uint64_t acc = 0;
 #pragma unroll
     for (int q = 0; q < LPER; ++q) {
-      acc += D[q];
-      D[q] = acc;
+      acc += V[q];
+      V[q] = acc;
     }
     const uint64_t ex = wave_incl_scan_u64(acc) - acc;
     glb_u64* aux = reinterpret_cast<glb_u64*>(gptr(ws + c.cs.ws_tile_aux));
     const uint64_t carry = aux[c.t - c.cs.tile_begin] - aux[c.pg.tile_begin - c.cs.tile_begin];
 #pragma unroll
-    for (int q = 0; q < LPER; ++q) {
-      const uint32_t j = lane * LPER + q;
-      if (j < c.td.nn) vals[pad(j)] = carry + ex + D[q];
-    }
-    wave_sync();
+    for (int q = 0; q < LPER; ++q) V[q] += carry + ex;
   }
   const uint32_t nrows = c.nrows;
   const int64_t out0 = c.out0;
-  uint64_t x[NGROUPS];
+  // rows [0, TR/2) use values [0, cntA), rows [TR/2, TR) the rest: each half
+  // goes through the LDS buffer in turn
+  uint32_t cntA = 0;
+#pragma unroll
+  for (int i = 0; i < NGROUPS / 2; ++i) cntA += (uint32_t)__popcll(group_mask(vw, i));
   uint32_t kb = 0;
 #pragma unroll
-  for (int i = 0; i < NGROUPS; ++i) {
-    const uint64_t m = group_mask(vw, i);
-    const uint32_t k = kb + rank_below(m);
-    kb += (uint32_t)__popcll(m);
-    x[i] = (((m >> lane) & 1) && k < c.td.nn) ? vals[pad(k)] : 0ull;
-  }
-  if (c.cs.width == 4) {
-    __attribute__((address_space(1))) uint32_t* out = gptr(reinterpret_cast<uint32_t*>(c.cs.values));
+  for (int half = 0; half < 2; ++half) {
+    const uint32_t lo = half ? cntA : 0u, hi = half ? nn : min(cntA, nn);
+    if (half) wave_sync();  // the first half's reads are done
 #pragma unroll
-    for (int i = 0; i < NGROUPS; ++i) {
-      const uint32_t r = 64 * i + lane;
-      if (r < nrows) __builtin_nontemporal_store((uint32_t)x[i], &out[out0 + r]);
+    for (int q = 0; q < LPER; ++q) {
+      const uint32_t j = lane * LPER + q;
+      if (j >= lo && j < hi) vals[pad(j - lo)] = V[q];
     }
-  } else {
-    __attribute__((address_space(1))) uint64_t* out = gptr(reinterpret_cast<uint64_t*>(c.cs.values));
+    wave_sync();
+    uint64_t x[NGROUPS / 2];
 #pragma unroll
-    for (int i = 0; i < NGROUPS; ++i) {
-      const uint32_t r = 64 * i + lane;
-      if (r < nrows) __builtin_nontemporal_store(x[i], &out[out0 + r]);
+    for (int ii = 0; ii < NGROUPS / 2; ++ii) {
+      const int i = half * (NGROUPS / 2) + ii;
+      const uint64_t m = group_mask(vw, i);
+      const uint32_t k = kb + rank_below(m);
+      kb += (uint32_t)__popcll(m);
+      x[ii] = (((m >> lane) & 1) && k < hi) ? vals[pad(k - lo)] : 0ull;
+    }
+    if (c.cs.width == 4) {
+      __attribute__((address_space(1))) uint32_t* out = gptr(reinterpret_cast<uint32_t*>(c.cs.values));
+#pragma unroll
+      for (int ii = 0; ii < NGROUPS / 2; ++ii) {
+        const uint32_t r = 64 * (half * (NGROUPS / 2) + ii) + lane;
+        if (r < nrows) __builtin_nontemporal_store((uint32_t)x[ii], &out[out0 + r]);
+      }
+    } else {
+      __attribute__((address_space(1))) uint64_t* out = gptr(reinterpret_cast<uint64_t*>(c.cs.values));
+#pragma unroll
+      for (int ii = 0; ii < NGROUPS / 2; ++ii) {
+        const uint32_t r = 64 * (half * (NGROUPS / 2) + ii) + lane;
+        if (r < nrows) __builtin_nontemporal_store(x[ii], &out[out0 + r]);
+      }
     }
   }
 }
