@@ -1004,17 +1004,23 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
       return;
     }
     wave_sync();
-    const bool l16 = sl.flags & DICT_LENS16;
     glb_u8* lens = gptr(ws + sl.ws_lens);
     uint32_t l[LPER];
 #pragma unroll
     for (int q = 0; q < LPER; ++q) {
       const uint32_t j = lane + 64 * q;
-      const uint32_t e = j < c.td.nn ? idx[pad(j)] : 0u;
-      const uint32_t x = l16 ? (uint32_t)reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[e]
-                             : reinterpret_cast<glb_u32*>(lens)[e];
-      l[q] = j < c.td.nn ? x : 0u;
+      l[q] = j < c.td.nn ? idx[pad(j)] : 0u;
     }
+    if (sl.flags & DICT_LENS16) {
+#pragma unroll
+      for (int q = 0; q < LPER; ++q) l[q] = reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[l[q]];
+    } else {
+#pragma unroll
+      for (int q = 0; q < LPER; ++q) l[q] = reinterpret_cast<glb_u32*>(lens)[l[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < LPER; ++q)
+      if (lane + 64 * q >= c.td.nn) l[q] = 0;
 #pragma unroll
     for (int q = 0; q < LPER; ++q) acc += l[q];
   }
@@ -1333,9 +1339,11 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   gout_u8* chars = gptr(c.cs.chars);
   __attribute__((address_space(1))) int64_t* offs = gptr(c.cs.offsets);
 
-  // (position, length) of row 64 g + lane for all groups: every gather of
-  // the tile is issued before the first store
-  uint32_t pos[NGROUPS], len[NGROUPS];
+  // (position, length) of row 64 g + lane for all groups: ranks first, then
+  // one loop per source kind (no branch inside, so every gather of the tile
+  // is issued before the first wait)
+  uint32_t pos[NGROUPS], len[NGROUPS], kk[NGROUPS];
+  uint32_t vmask = 0;
   {
     uint32_t kb = 0;
 #pragma unroll
@@ -1344,24 +1352,48 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       const uint32_t k = kb + rank_below(m);
       kb += (uint32_t)__popcll(m);
       const bool v = ((m >> lane) & 1) && k < td.nn;
-      const uint32_t kc = v ? k : 0u;
-      if (is_plain) {
-        const uint32_t q0 = u[pad(kc)], q1 = u[pad(kc + 1)];
-        pos[g] = q0 + 4;
-        len[g] = v ? q1 - q0 - 4 : 0u;
-      } else if (use_slots) {
-        const uint32_t e = td.nn ? u[pad(kc)] : 0u;
-        const uint32_t l = lens16 ? (uint32_t)reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[e]
-                                  : reinterpret_cast<glb_u32*>(lens)[e];
-        pos[g] = e * SLOT_BYTES;
-        len[g] = v ? l : 0u;
-      } else {
-        const uint64_t pr = td.nn ? pairs[u[pad(kc)]] : 0ull;
-        pos[g] = (uint32_t)pr;
-        len[g] = v ? (uint32_t)(pr >> 32) : 0u;
-      }
+      kk[g] = v ? k : 0u;
+      vmask |= (v ? 1u : 0u) << g;
     }
   }
+  if (td.nn == 0) {
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) { pos[g] = 0; len[g] = 0; }
+  } else if (is_plain) {
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+      const uint32_t q0 = u[pad(kk[g])], q1 = u[pad(kk[g] + 1)];
+      pos[g] = q0 + 4;
+      len[g] = q1 - q0 - 4;
+    }
+  } else if (use_slots) {
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) pos[g] = u[pad(kk[g])];
+    if (lens16) {
+#pragma unroll
+      for (int g = 0; g < NGROUPS; ++g)
+        len[g] = reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[pos[g]];
+    } else {
+#pragma unroll
+      for (int g = 0; g < NGROUPS; ++g) len[g] = reinterpret_cast<glb_u32*>(lens)[pos[g]];
+    }
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) pos[g] *= SLOT_BYTES;
+  } else {
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) pos[g] = u[pad(kk[g])];
+    uint64_t pr[NGROUPS];
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) pr[g] = pairs[pos[g]];
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+      pos[g] = (uint32_t)pr[g];
+      len[g] = (uint32_t)(pr[g] >> 32);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NGROUPS; ++g)
+    if (!((vmask >> g) & 1)) len[g] = 0;
   // row offsets: exclusive scan per group, groups in row order; GB[g] is
   // the tile-relative chars offset of group g
   uint32_t ex[NGROUPS], T[NGROUPS], GB[NGROUPS];
