@@ -625,6 +625,54 @@ __device__ __forceinline__ void copy_to_lds(glb_u8* sbase, uint64_t S, lds_u8* d
   }
 }
 
+// The first step of copy_to_lds split in two, so that a string's loads can
+// be issued one group ahead of its LDS writes: piece_load reads the (at most
+// three) 16-byte pieces holding bytes [0, min(L, 44)) of the string at byte
+// S; piece_write writes them to dst at byte D and copies the rest of a longer
+// string directly.
+__device__ __forceinline__ void piece_load(glb_u8* sbase, uint64_t S, uint32_t L, uint32_t* w) {
+  typedef uint32_t v4a __attribute__((ext_vector_type(4), aligned(4)));
+  const uint32_t n = min(44u, L);
+  const uint32_t nsw = L ? ((uint32_t)(S & 3) + n + 3) >> 2 : 0u;
+  const __attribute__((address_space(1))) v4a* q =
+      reinterpret_cast<const __attribute__((address_space(1))) v4a*>(sbase + (S & ~3ull));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    v4a x = {0u, 0u, 0u, 0u};
+    if ((uint32_t)(4 * c) < nsw) x = q[c];
+    w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
+  }
+}
+
+__device__ __forceinline__ void piece_write(const uint32_t* w, glb_u8* sbase, uint64_t S, lds_u8* dst, uint32_t D,
+                                            uint32_t L) {
+  const uint32_t n = min(44u, L);
+  const uint32_t ss = (uint32_t)(S & 3);
+  uint32_t rr[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) rr[k] = __builtin_amdgcn_alignbyte(k < 11 ? w[k + 1] : 0u, w[k], ss);
+  const uint32_t dd = D & 3;
+  lds_u32* dw = reinterpret_cast<lds_u32*>(dst + (D & ~3u));
+  const uint32_t end = dd + n;
+#pragma unroll
+  for (int m = 0; m < 12; ++m) {
+    const uint32_t prev = m == 0 ? 0u : rr[m - 1];
+    const uint32_t word = dd ? __builtin_amdgcn_alignbyte(rr[m], prev, 4 - dd) : rr[m];
+    const uint32_t b0 = 4u * m;
+    if (b0 < end) {
+      if ((m > 0 || dd == 0) && b0 + 4 <= end) {
+        dw[m] = word;
+      } else {
+        lds_u8* b = reinterpret_cast<lds_u8*>(dw + m);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (b0 + k >= dd && b0 + k < end) b[k] = (uint8_t)(word >> (8 * k));
+      }
+    }
+  }
+  if (L > 44) copy_to_lds(sbase, S + 44, dst, D + 44, L - 44);
+}
+
 typedef __attribute__((address_space(1))) uint8_t gout_u8;
 typedef __attribute__((address_space(1))) uint32_t gout_u32;
 
@@ -1425,7 +1473,12 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   lds_u32* cb = (lds_u32*)&s_buf[wave][0];
   lds_u8* cb8 = (lds_u8*)cb;
   uint32_t bstart = 0, bfill = 0;  // the batch holds tile chars [bstart, bstart + bfill)
+  uint32_t wc[12], wn[12];          // this group's and the next group's source pieces
+  piece_load(sbase, soff + pos[0], len[0], wn);
   for (int g = 0; g < NGROUPS; ++g) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) wc[k] = wn[k];
+    if (g + 1 < NGROUPS) piece_load(sbase, soff + pos[g + 1], len[g + 1], wn);
     if (T[g] == 0) continue;
     if (T[g] > CB) {
       if (bfill) {
@@ -1444,7 +1497,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       bfill = 0;
     }
     if (bfill == 0) bstart = GB[g];
-    if (len[g]) copy_to_lds(sbase, soff + pos[g], cb8, ex[g] - bstart, len[g]);
+    if (len[g]) piece_write(wc, sbase, soff + pos[g], cb8, ex[g] - bstart, len[g]);
     bfill += T[g];
   }
   if (bfill) {
