@@ -57,20 +57,46 @@ def decoded_bytes(out_tensors, types):
     return total
 
 
+ENC_PLAIN, ENC_PLAIN_DICT, ENC_DELTA, ENC_RLE_DICT = 0, 2, 5, 8
+
+
+def decode_kernel(f, c, types):
+    """The decode kernel that handles every data page of column c, or None
+    when its pages mix encodings that different kernels decode."""
+    if types[c] == 6:
+        return "k_decode_str"
+    m = f.column_encodings(c)
+    wide = 2 if types[c] != 1 else 0
+    if m == 1 << ENC_DELTA:
+        return "k_decode_delta"
+    if m == 1 << ENC_PLAIN:
+        return f"k_decode_fixed<{wide}>"
+    if m and not (m & ~((1 << ENC_PLAIN_DICT) | (1 << ENC_RLE_DICT))):
+        return f"k_decode_fixed<{wide + 1}>"
+    return None
+
+
 def algorithmic_bytes(kernel, f, cols, types, out_tensors, rows):
-    """Bytes one launch of `kernel` must move: encoded page bytes it reads
-    plus decoded bytes it writes (dictionary gathers served by the caches
-    are not counted)."""
-    b = 0
+    """Bytes one launch of `kernel` must move: the encoded data-page bytes of
+    the columns it decodes (levels and values) plus the decoded bytes it
+    writes (values or offsets + chars, and the validity bitmap).  Dictionary
+    gathers are served by the caches and not counted.  None when the kernel
+    has no such figure (or a column's pages are split between kernels)."""
+    b, any_col = 0, False
     for c in cols:
-        data, dic = f.column_bytes(c)
+        k = decode_kernel(f, c, types)
+        if k is None and types[c] != 6:
+            return None
+        if k != kernel:
+            continue
+        any_col = True
+        data, _ = f.column_bytes(c)
         t = out_tensors[c]
-        is_str = types[c] == 6
-        if kernel == "k_decode_fixed" and not is_str:
-            b += data + rows * (4 if types[c] == 1 else 8) + (rows + 7) // 8
-        elif kernel == "k_decode_str" and is_str:
+        if "offsets" in t:
             b += data + 8 * (rows + 1) + t["chars_bytes"] + (rows + 7) // 8
-    return b
+        else:
+            b += data + rows * (4 if types[c] == 1 else 8) + (rows + 7) // 8
+    return b if any_col else None
 
 
 def cpu_baseline(data, nbytes_label):
@@ -193,15 +219,24 @@ def main():
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"]):
         log(f"  {k:16s} {v['avg_ms']:8.3f} ms/launch  {v['share'] * 100:5.1f}% of the timed region")
 
-    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    n_l, t_l = prof[dom]
-    alg = algorithmic_bytes(dom, f, cols, types, tens, rows)
-    achieved = alg / (t_l / n_l / 1e3) / 1e9
-    traffic_key = f"{dom}:rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
-    traffic = read_traffic(traffic_key)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "algorithmic_bytes_per_launch": alg, "traffic_key": traffic_key}
+    key = f"rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
+    per = {}
+    for k, (n_l, t_l) in prof.items():
+        alg = algorithmic_bytes(k, f, cols, types, tens, rows)
+        if alg is None or n_l == 0:
+            continue
+        ach = alg / (t_l / n_l / 1e3) / 1e9
+        per[k] = {"achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4), "avg_ms": round(t_l / n_l, 4),
+                  "algorithmic_bytes_per_launch": alg, "traffic": read_traffic(f"{k}:{key}")}
+    roof = None
+    if per:
+        dom = max(per, key=lambda k: prof[k][1])
+        d = per[dom]
+        roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"],
+                "traffic": d["traffic"], "kernel": dom, "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                "traffic_key": f"{dom}:{key}", "decode_kernels": per}
+        for k, v in per.items():
+            log(f"  roofline {k:18s} {v['achieved']:8.1f} GB/s = {v['frac'] * 100:5.1f}% of HBM peak")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -166,6 +166,12 @@ pq_status pq_scan_check(pq_file f, pq_stream stream);
    (levels + values as stored) and dictionary-page payloads. */
 pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes);
 
+/* Encodings used by the data pages of column `col` over all row groups
+   (the page header's encoding field, Parquet's Encoding enum: PLAIN 0,
+   PLAIN_DICTIONARY 2, DELTA_BINARY_PACKED 5, RLE_DICTIONARY 8): bit e of
+   *mask is set when some data page uses encoding e.  Host-only. */
+pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask);
+
 /* Measurement hook.  While enabled, every kernel pq_scan enqueues on a
    handle is bracketed by a pair of HIP events on the scan's stream;
    pq_profile_read() waits for the recorded events and returns, per kernel

@@ -19,7 +19,7 @@ INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
 _WIDTH = {INT32: 4, INT64: 8, DOUBLE: 8}
 
 EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get", "pq_row_group_rows",
-           "pq_file_stats_get", "pq_column_bytes", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
+           "pq_file_stats_get", "pq_column_bytes", "pq_column_encodings", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
            "pq_profile_read", "pq_close", "pq_last_error")
 
 
@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         L.pq_file_stats_get.argtypes = [vp, ctypes.POINTER(FileStats)]
         L.pq_plan.argtypes = [vp, u64, i32, i32, vp, u64, ctypes.POINTER(ScanSizes), vp]
         L.pq_column_bytes.argtypes = [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.pq_column_encodings.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32)]
         L.pq_profile.argtypes = [vp, i32]
         L.pq_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
         L.pq_scan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp]
@@ -81,7 +82,7 @@ def lib() -> ctypes.CDLL:
         L.pq_last_error.restype = ctypes.c_char_p
         for name in ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get",
                      "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check",
-                     "pq_column_bytes", "pq_profile", "pq_profile_read"):
+                     "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -170,6 +171,13 @@ class DeviceFile:
         d, k = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().pq_column_bytes(self._h, col, ctypes.byref(d), ctypes.byref(k)))
         return d.value, k.value
+
+    def column_encodings(self, col: int) -> int:
+        """Bit mask of the Parquet encodings (Encoding enum values) used by the
+        column's data pages."""
+        m = ctypes.c_uint32()
+        _check(lib().pq_column_encodings(self._h, col, ctypes.byref(m)))
+        return m.value
 
     def profile(self, enable: bool):
         _check(lib().pq_profile(self._h, 1 if enable else 0))

@@ -250,7 +250,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 9;  // kernels with a profiling slot
+constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -281,8 +281,14 @@ struct pq_file_s {
   uint64_t prof_n[NKERN] = {0};
 };
 
+// Slot order; k_decode_fixed<K> for K = 0 PLAIN 4-byte, 1 dictionary 4-byte,
+// 2 PLAIN 8-byte, 3 dictionary 8-byte.
+enum { KP_SNAPPY, KP_DICT, KP_PREPASS, KP_TILE_SCAN, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA,
+       KP_EDGES, KP_DICT_SLOTS };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
-                                          "k_decode_fixed", "k_decode_str", "k_decode_delta", "k_edges"};
+                                          "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
+                                          "k_decode_fixed<3>", "k_decode_str", "k_decode_delta", "k_edges",
+                                          "k_dict_slots"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -781,36 +787,36 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   const uint8_t* file = f->file;
   if (P.snappy_waves) {
     if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
-    ProfScope ps_(f, 0, s);
+    ProfScope ps_(f, KP_SNAPPY, s);
     hipLaunchKernelGGL(k_snappy, dim3((P.snappy_waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cols,
                        make_segs(P.snappy_segs), ws, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.slots.empty() && P.dict_grid_x) {
-    ProfScope ps_(f, 1, s);
+    ProfScope ps_(f, KP_DICT, s);
     hipLaunchKernelGGL(k_dict, dim3((uint32_t)P.slots.size(), P.dict_grid_x), dim3(256), 0, s, file, ws, d_cols,
                        (int)P.cols.size(), f->d_pages, d_slots, f->d_strck, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.pre_units) {
-    ProfScope ps_(f, 2, s);
+    ProfScope ps_(f, KP_PREPASS, s);
     hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckv, d_slots, make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.scan_cols.empty()) {
-    ProfScope ps_(f, 3, s);
+    ProfScope ps_(f, KP_TILE_SCAN, s);
     hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, s, ws, d_cols, d_which, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (plan_only) return PQ_OK;
   if (P.slot_grid_y) {
-    ProfScope ps_(f, 1, s);
+    ProfScope ps_(f, KP_DICT_SLOTS, s);
     hipLaunchKernelGGL(k_dict_slots, dim3((uint32_t)P.slots.size(), P.slot_grid_y), dim3(256), 0, s, ws, d_slots);
     HIP_OR(hipGetLastError());
   }
   if (P.prep_threads) {
-    ProfScope ps_(f, 4, s);
+    ProfScope ps_(f, KP_PREP, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
                        make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
@@ -818,26 +824,26 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   for (int K = 0; K < 4; ++K) {
     if (!P.fixed_units[K]) continue;
     if (P.fixed_segs[K].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
-    ProfScope ps_(f, 5, s);
+    ProfScope ps_(f, KP_FIXED0 + K, s);
     auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
     hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckd, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {
-    ProfScope ps_(f, 7, s);
+    ProfScope ps_(f, KP_DELTA, s);
     hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
                        f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, make_segs(P.delta_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.str_units) {
-    ProfScope ps_(f, 6, s);
+    ProfScope ps_(f, KP_STR, s);
     hipLaunchKernelGGL(k_decode_str, dim3((P.str_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.edge_threads) {
-    ProfScope ps_(f, 8, s);
+    ProfScope ps_(f, KP_EDGES, s);
     hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, f->d_pages,
                        f->d_tiles, make_segs(P.edge_segs));
     HIP_OR(hipGetLastError());
@@ -927,6 +933,16 @@ extern "C" pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_byte
   }
   if (data_bytes) *data_bytes = d;
   if (dict_bytes) *dict_bytes = k;
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask) {
+  if (!f || !mask || col < 0 || col >= f->ncols) return fail(PQ_EINVAL, "bad argument");
+  uint32_t m = 0;
+  const uint32_t q0 = (uint32_t)(col * f->nrg), q1 = (uint32_t)((col + 1) * f->nrg);
+  for (uint32_t p = f->chunk_page0[q0]; p < f->chunk_page0[q1]; ++p)
+    if (f->pages[p].kind != PAGE_DICT && f->pages[p].encoding < 32) m |= 1u << f->pages[p].encoding;
+  *mask = m;
   return PQ_OK;
 }
 

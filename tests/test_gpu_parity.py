@@ -142,3 +142,30 @@ def test_bad_magic_rejected_before_gpu_work():
     with pytest.raises(pqs.PqError) as e:
         pqs.DeviceFile(buf, n)
     assert e.value.code == pqs.PQ_ECORRUPT
+
+
+def test_column_encodings_match_page_headers():
+    """pq_column_encodings equals the set of data-page encodings found by
+    walking every chunk's page headers with the oracle's header parser."""
+    import oracle
+    import paper_2602_17335_amd as pqs
+    spec = CASES["wide_snappy_v2_fallback"]
+    data = dg.write(spec)
+    md = pq.ParquetFile(io.BytesIO(data.tobytes())).metadata
+    raw = data.tobytes()
+    want = [0] * md.num_columns
+    for rg in range(md.num_row_groups):
+        for c in range(md.num_columns):
+            cm = md.row_group(rg).column(c)
+            at = cm.dictionary_page_offset if cm.has_dictionary_page else cm.data_page_offset
+            end = at + cm.total_compressed_size
+            while at < end:
+                h, n = oracle.page_header(raw[at:at + 256])
+                if h.type in (0, 3):  # DATA_PAGE, DATA_PAGE_V2
+                    want[c] |= 1 << h.encoding
+                at += n + h.compressed_size
+    buf, n = pqs.to_device(data)
+    f = pqs.DeviceFile(buf, n)
+    got = [f.column_encodings(c) for c in range(f.num_columns)]
+    assert got == want
+    assert any(bin(m).count("1") > 1 for m in want)  # the dictionary fallback mixes encodings
