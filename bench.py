@@ -64,7 +64,7 @@ def decode_kernel(f, c, types):
     """The decode kernel that handles every data page of column c, or None
     when its pages mix encodings that different kernels decode."""
     if types[c] == 6:
-        return "k_decode_str"
+        return "k_decode_str"  # k_decode_str<true> (slot dictionaries) or <false>
     m = f.column_encodings(c)
     wide = 2 if types[c] != 1 else 0
     if m == 1 << ENC_DELTA:
@@ -87,7 +87,7 @@ def algorithmic_bytes(kernel, f, cols, types, out_tensors, rows):
         k = decode_kernel(f, c, types)
         if k is None and types[c] != 6:
             return None
-        if k != kernel:
+        if k != kernel and not (k == "k_decode_str" and kernel.startswith("k_decode_str<")):
             continue
         any_col = True
         data, _ = f.column_bytes(c)
@@ -221,7 +221,10 @@ def main():
 
     key = f"rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
     per = {}
+    n_str = sum(1 for k in prof if k.startswith("k_decode_str"))
     for k, (n_l, t_l) in prof.items():
+        if k.startswith("k_decode_str") and n_str > 1:
+            continue  # string tiles split between the two instantiations: no per-launch figure
         alg = algorithmic_bytes(k, f, cols, types, tens, rows)
         if alg is None or n_l == 0:
             continue

@@ -40,6 +40,7 @@ __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* 
 __global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                                const TileDev* tiles, const Ck* ckd, const Ck* ckv, SegTable seg,
                                uint32_t* err);
+template <bool SLOTS>
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                              const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
                              const uint32_t* strck, SegTable seg, uint32_t* err);
@@ -250,7 +251,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -282,13 +283,14 @@ struct pq_file_s {
 };
 
 // Slot order; k_decode_fixed<K> for K = 0 PLAIN 4-byte, 1 dictionary 4-byte,
-// 2 PLAIN 8-byte, 3 dictionary 8-byte.
+// 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
+// of slot dictionaries, k_decode_str<false> the others.
 enum { KP_SNAPPY, KP_DICT, KP_PREPASS, KP_TILE_SCAN, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA,
-       KP_EDGES, KP_DICT_SLOTS };
+       KP_EDGES, KP_DICT_SLOTS, KP_STR_SLOTS };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
-                                          "k_decode_fixed<3>", "k_decode_str", "k_decode_delta", "k_edges",
-                                          "k_dict_slots"};
+                                          "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
+                                          "k_dict_slots", "k_decode_str<true>"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -640,11 +642,11 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs, edge_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs[2], edge_segs;
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units = 0,
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
   uint32_t dict_grid_x = 0;
   uint32_t slot_grid_y = 0;  // k_dict_slots: chunks of 256 entries of the largest slotted dictionary
@@ -715,15 +717,22 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
       P.slots.push_back(sl);
     }
-    bool has_delta = false, has_plain = false, has_dict = false;
-    if (cs.type != T_BYTE_ARRAY)
-      for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
-        if (f->pages[p].kind == PAGE_DICT) continue;
-        const int e = f->pages[p].encoding;
-        if (e == E_DELTA) has_delta = true;
-        else if (e == E_PLAIN_DICT || e == E_RLE_DICT) has_dict = true;
-        else has_plain = true;  // PLAIN, or an encoding the kernel reports as unsupported
+    bool has_delta = false, has_plain = false, has_dict = false, has_slots = false;
+    for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
+      if (f->pages[p].kind == PAGE_DICT) continue;
+      const int e = f->pages[p].encoding;
+      if (e == E_DELTA) {
+        has_delta = true;
+      } else if (e == E_PLAIN_DICT || e == E_RLE_DICT) {
+        const uint32_t g = f->pages[p].chunk % (uint32_t)f->nrg;
+        if (cs.type == T_BYTE_ARRAY && (P.slots[cs.dict_slot0 + (g - (uint32_t)rg_b)].flags & DICT_SLOTS))
+          has_slots = true;
+        else
+          has_dict = true;
+      } else {
+        has_plain = true;  // PLAIN, or an encoding the kernel reports as unsupported
       }
+    }
     const uint32_t nt = cs.tile_end - cs.tile_begin;
     if (cs.optional && nt) {
       cs.ws_edge = off;
@@ -738,8 +747,11 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       if (cs.type == T_BYTE_ARRAY) {
         P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
         P.pre_units += nt;
-        P.str_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units});
-        P.str_units += nt;
+        for (int k = 0; k < 2; ++k) {  // k_decode_str<k>: tiles of slot dictionaries (1) or the others (0)
+          if (!(k ? has_slots : (has_plain || has_dict || has_delta))) continue;
+          P.str_segs[k].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units[k]});
+          P.str_units[k] += nt;
+        }
       } else {
         if (has_delta) {
           P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
@@ -836,10 +848,13 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, make_segs(P.delta_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (P.str_units) {
-    ProfScope ps_(f, KP_STR, s);
-    hipLaunchKernelGGL(k_decode_str, dim3((P.str_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck, make_segs(P.str_segs), f->d_err);
+  for (int k = 0; k < 2; ++k) {
+    if (!P.str_units[k]) continue;
+    if (P.str_segs[k].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
+    ProfScope ps_(f, k ? KP_STR_SLOTS : KP_STR, s);
+    hipLaunchKernelGGL(k ? k_decode_str<true> : k_decode_str<false>, dim3((P.str_units[k] + 3) / 4), dim3(256), 0, s,
+                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck,
+                       make_segs(P.str_segs[k]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.edge_threads) {

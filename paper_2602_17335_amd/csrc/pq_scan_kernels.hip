@@ -714,6 +714,63 @@ __device__ __forceinline__ void store_group(const lds_u32* buf, uint32_t nbufw, 
 }
 
 
+// Slot dictionaries (entry e's chars at byte 64 e, zero-padded to the slot's
+// last dword, which holds the length).  slot_load reads the (at most three)
+// 16-byte pieces holding bytes [0, min(L, 48)) of the slot at byte `pos`;
+// pieces past the string read as zero.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gout_u32x4;
+
+__device__ __forceinline__ void slot_load(glb_u8* sbase, uint32_t pos, uint32_t L, uint32_t* w) {
+  const __attribute__((address_space(1))) u32x4* q =
+      reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(sbase + pos);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u32x4 x = {0u, 0u, 0u, 0u};
+    if ((uint32_t)(16 * c) < L) x = q[c];
+    w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
+  }
+}
+
+// ORs the L chars of a slot (pieces in w, from slot_load) into a zeroed LDS
+// buffer at byte D: dword m of the destination, counted from the aligned
+// dword at D - dd (dd in 1..4, so the shift below is 0..3), is string bytes
+// [4 m - dd, 4 m - dd + 4).  Bytes outside the string are zero, so the
+// neighbours' shared edge dwords combine by OR and no lane needs a mask.
+// Needs 4 bytes of room before D and 64 after it.
+__device__ __forceinline__ void slot_or(const uint32_t* w, glb_u8* sbase, uint32_t pos, uint32_t L, lds_u8* dst,
+                                        uint32_t D) {
+  const uint32_t dd = ((D - 1u) & 3u) + 1u;
+  const uint32_t sh = (4u - dd) & 3u;
+  lds_u32* dw = reinterpret_cast<lds_u32*>(dst + D - dd);
+  uint32_t prev = 0u;
+#pragma unroll
+  for (int m = 0; m < 12; ++m) {
+    __hip_atomic_fetch_or(&dw[m], __builtin_amdgcn_alignbyte(w[m], prev, sh), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    prev = w[m];
+  }
+  if (L > 44) {  // up to SLOT_CHARS: the slot's fourth piece, without its length dword
+    const u32x4 x = reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(sbase + pos)[3];
+    const uint32_t w4[4] = {x.x, x.y, x.z, 0u};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      __hip_atomic_fetch_or(&dw[12 + m], __builtin_amdgcn_alignbyte(w4[m], prev, sh), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_WORKGROUP);
+      prev = w4[m];
+    }
+  }
+}
+
+// Stores bytes [b0, b1) of a 16-byte chunk one by one.
+__device__ __forceinline__ void store_chunk_bytes(u32x4 v, gout_u8* dst, uint32_t b0, uint32_t b1) {
+  const uint32_t ow[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if ((uint32_t)i >= b0 && (uint32_t)i < b1) dst[i] = (uint8_t)(ow[i >> 2] >> (8 * (i & 3)));
+}
+
+
 // ---------------------------------------------------------------------------
 // k_snappy: one wave per compressed page
 // ---------------------------------------------------------------------------
@@ -1287,6 +1344,7 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
 // taken 64 at a time; the strings of a group are gathered into the wave's
 // LDS buffer at their output offsets and stored as aligned 16-byte chunks.
 // ---------------------------------------------------------------------------
+template <bool SLOTS>
 __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                    const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                    const TileDev* __restrict__ tiles,
@@ -1307,8 +1365,16 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int enc = c.pg.encoding;
-  const bool is_plain = enc == E_PLAIN;
+  const bool is_plain = !SLOTS && enc == E_PLAIN;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
+  DictSlot sl;
+  bool slot_tile = false;
+  if (is_dict) {
+    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
+    sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    slot_tile = sl.page != ~0u && (sl.flags & DICT_SLOTS);
+  }
+  if (slot_tile != SLOTS) return;  // the other instantiation decodes this tile
   if (!is_plain && !is_dict) {
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);
     return;
@@ -1320,7 +1386,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   glb_u8* sbase;
   uint64_t soff;
   glb_u64* pairs = nullptr;
-  bool use_slots = false, lens16 = false;
+  constexpr bool use_slots = SLOTS;
+  bool lens16 = false;
   glb_u8* lens = nullptr;
   if (is_plain) {
     // u[pad(j)]: offset (in the value stream) of the length prefix of the
@@ -1351,16 +1418,13 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       return;
     }
   } else {
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
     if (sl.page == ~0u) {
       if (lane == 0) set_err(err, ERR_DICT_MISSING, td.page);
       return;
     }
-    if (sl.flags & DICT_SLOTS) {  // entry e's chars at slot e; lengths from the length array
+    if (SLOTS) {  // entry e's chars at slot e; lengths from the length array
       sbase = gptr(ws + sl.ws_slots);
       soff = 0;
-      use_slots = true;
       lens16 = sl.flags & DICT_LENS16;
       lens = gptr(ws + sl.ws_lens);
     } else {
@@ -1414,7 +1478,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       pos[g] = q0 + 4;
       len[g] = q1 - q0 - 4;
     }
-  } else if (use_slots) {
+  } else if constexpr (use_slots) {
 #pragma unroll
     for (int g = 0; g < NGROUPS; ++g) pos[g] = u[pad(kk[g])];
     if (lens16) {
@@ -1464,48 +1528,118 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     }
   }
   if (!fits) return;
-  // chars: consecutive groups are gathered into the wave's LDS buffer until
-  // it is full, then the batch is stored with aligned 16-byte chunks (one
-  // wait for earlier stores per batch, not per group); a group larger than
-  // the buffer is copied directly.  The buffer reuses the index area, whose
-  // every entry was read above.
-  wave_sync();
-  lds_u32* cb = (lds_u32*)&s_buf[wave][0];
-  lds_u8* cb8 = (lds_u8*)cb;
-  uint32_t bstart = 0, bfill = 0;  // the batch holds tile chars [bstart, bstart + bfill)
-  uint32_t wc[12], wn[12];          // this group's and the next group's source pieces
-  piece_load(sbase, soff + pos[0], len[0], wn);
-  for (int g = 0; g < NGROUPS; ++g) {
+  if constexpr (SLOTS) {
+    // chars of slot dictionaries: every slot is zero past its string, so a
+    // lane ORs its string's realigned dwords into a zeroed LDS buffer with no
+    // masks (the neighbours' edge bytes combine by OR).  LDS byte j maps to
+    // the 16-byte aligned global address G0 + j, so the buffer is stored as
+    // aligned 16-byte chunks; when it fills, the full chunks are stored and
+    // cleared and the partial last chunk moves to the front.  Only the tile's
+    // first and last chunk are stored bytewise (they share bytes with the
+    // neighbouring tiles).
+    constexpr uint32_t HEAD = 16;                      // room for a string's dword before byte 0
+    constexpr uint32_t CAP = BUFW * 4 - HEAD - 64;     // chars + the realignment slack
+    wave_sync();
+    typedef __attribute__((address_space(3))) u32x4 lds_v4u;
+    lds_v4u* zb = (lds_v4u*)&s_buf[wave][0];
+    for (uint32_t i = lane; i < BUFW / 4; i += 64) zb[i] = u32x4{0u, 0u, 0u, 0u};
+    wave_sync();
+    lds_u8* cb8 = (lds_u8*)&s_buf[wave][0] + HEAD;
+    lds_v4u* cbv = reinterpret_cast<lds_v4u*>(cb8);
+    gout_u8* tile_chars = chars + base;
+    uint32_t lo = (uint32_t)((uintptr_t)tile_chars & 15);  // LDS byte of tile char bstart
+    uint32_t bstart = 0, bfill = 0;
+    bool head_foreign = lo != 0;  // LDS bytes [0, lo) of chunk 0 belong to the previous tile
+    uint32_t wc[12], wn[12];
+    slot_load(sbase, pos[0], len[0], wn);
+    for (int g = 0; g < NGROUPS; ++g) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) wc[k] = wn[k];
-    if (g + 1 < NGROUPS) piece_load(sbase, soff + pos[g + 1], len[g + 1], wn);
-    if (T[g] == 0) continue;
-    if (T[g] > CB) {
-      if (bfill) {
+      for (int k = 0; k < 12; ++k) wc[k] = wn[k];
+      if (g + 1 < NGROUPS) slot_load(sbase, pos[g + 1], len[g + 1], wn);
+      if (T[g] == 0) continue;
+      if (bfill && lo + bfill + T[g] > CAP) {
+        // store the full chunks, clear them, move the partial one to the front
+        wave_sync();
+        const uint32_t end = lo + bfill, nfull = end >> 4, tail = end & 15;
+        gout_u8* g0 = tile_chars + bstart - lo;
+        for (uint32_t k = lane; k < nfull; k += 64) {
+          const u32x4 v = cbv[k];
+          if (k == 0 && head_foreign) store_chunk_bytes(v, g0, lo, 16);
+          else __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
+          cbv[k] = u32x4{0u, 0u, 0u, 0u};
+        }
+        wave_sync();
+        if (lane == 0 && tail) {
+          cbv[0] = cbv[nfull];
+          cbv[nfull] = u32x4{0u, 0u, 0u, 0u};
+        }
+        wave_sync();
+        head_foreign = false;
+        bstart += bfill;
+        lo = tail;
+        bfill = 0;
+      }
+      if (len[g]) slot_or(wc, sbase, pos[g], len[g], cb8, lo + (ex[g] - bstart));
+      bfill += T[g];
+    }
+    wave_sync();
+    const uint32_t end = lo + bfill, nst = (end + 15) >> 4, tail = end & 15;
+    gout_u8* g0 = tile_chars + bstart - lo;
+    for (uint32_t k = lane; k < nst; k += 64) {
+      const u32x4 v = cbv[k];
+      const uint32_t b0 = (k == 0 && head_foreign) ? lo : 0u;
+      const uint32_t b1 = (k + 1 == nst && tail) ? tail : 16u;
+      if (b0 == 0 && b1 == 16) __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
+      else store_chunk_bytes(v, g0 + 16 * k, b0, b1);
+    }
+  } else {
+    // chars: consecutive groups are gathered into the wave's LDS buffer until
+    // it is full, then the batch is stored with aligned 16-byte chunks (one
+    // wait for earlier stores per batch, not per group); a group larger than
+    // the buffer is copied directly.  The buffer reuses the index area, whose
+    // every entry was read above.
+    wave_sync();
+    lds_u32* cb = (lds_u32*)&s_buf[wave][0];
+    lds_u8* cb8 = (lds_u8*)cb;
+    uint32_t bstart = 0, bfill = 0;  // the batch holds tile chars [bstart, bstart + bfill)
+    uint32_t wc[12], wn[12];          // this group's and the next group's source pieces
+    piece_load(sbase, soff + pos[0], len[0], wn);
+    for (int g = 0; g < NGROUPS; ++g) {
+  #pragma unroll
+      for (int k = 0; k < 12; ++k) wc[k] = wn[k];
+      if (g + 1 < NGROUPS) piece_load(sbase, soff + pos[g + 1], len[g + 1], wn);
+      if (T[g] == 0) continue;
+      if (T[g] > CB) {
+        if (bfill) {
+          wave_sync();
+          store_group(cb, BUFW, bfill, chars + base + bstart, lane);
+          wave_sync();
+          bfill = 0;
+        }
+        if (len[g]) copy_string<gout_u8, gout_u32, true>(sbase, soff + pos[g], chars, base + ex[g], len[g]);
+        continue;
+      }
+      if (bfill + T[g] > CB) {
         wave_sync();
         store_group(cb, BUFW, bfill, chars + base + bstart, lane);
         wave_sync();
         bfill = 0;
       }
-      if (len[g]) copy_string<gout_u8, gout_u32, true>(sbase, soff + pos[g], chars, base + ex[g], len[g]);
-      continue;
+      if (bfill == 0) bstart = GB[g];
+      if (len[g]) piece_write(wc, sbase, soff + pos[g], cb8, ex[g] - bstart, len[g]);
+      bfill += T[g];
     }
-    if (bfill + T[g] > CB) {
+    if (bfill) {
       wave_sync();
       store_group(cb, BUFW, bfill, chars + base + bstart, lane);
-      wave_sync();
-      bfill = 0;
     }
-    if (bfill == 0) bstart = GB[g];
-    if (len[g]) piece_write(wc, sbase, soff + pos[g], cb8, ex[g] - bstart, len[g]);
-    bfill += T[g];
-  }
-  if (bfill) {
-    wave_sync();
-    store_group(cb, BUFW, bfill, chars + base + bstart, lane);
   }
 }
 
+template __global__ void k_decode_str<false>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
+                                            const Ck*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
+template __global__ void k_decode_str<true>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
+                                           const Ck*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<0>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
                                           const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_DICT>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
