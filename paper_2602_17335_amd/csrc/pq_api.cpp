@@ -25,13 +25,12 @@ __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColSca
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, const PageDev* pages, const TileDev* tiles,
                         SegTable seg);
-__global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols, const PageDev* pages,
-                       DictSlot* slots, const uint32_t* strck, uint32_t* err);
+__global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages, DictSlot* slots,
+                       const uint32_t* strck, DictTable tab, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                           const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
                           uint32_t* err);
 __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
-__global__ void k_dict_slots(uint8_t* ws, const DictSlot* slots);
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
 template <int KIND>
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
@@ -251,7 +250,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -286,11 +285,11 @@ struct pq_file_s {
 // 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
 // of slot dictionaries, k_decode_str<false> the others.
 enum { KP_SNAPPY, KP_DICT, KP_PREPASS, KP_TILE_SCAN, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA,
-       KP_EDGES, KP_DICT_SLOTS, KP_STR_SLOTS };
+       KP_EDGES, KP_STR_SLOTS };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
                                           "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
-                                          "k_dict_slots", "k_decode_str<true>"};
+                                          "k_decode_str<true>"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -648,8 +647,7 @@ struct Plan {
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
-  uint32_t dict_grid_x = 0;
-  uint32_t slot_grid_y = 0;  // k_dict_slots: chunks of 256 entries of the largest slotted dictionary
+  std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
   uint64_t ws_which = 0;
 };
 
@@ -709,11 +707,11 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
             sl.flags |= DICT_SLOTS;
             sl.ws_slots = off;
             off = align_up(off + (uint64_t)SLOT_BYTES * sl.n, 256);
-            P.slot_grid_y = std::max(P.slot_grid_y, (sl.n + 255) / 256);
           }
         }
-        const uint32_t gx = cs.type == T_BYTE_ARRAY ? (sl.n / STR_CK + 1 + 255) / 256 : (sl.n + 8191) / 8192;
-        P.dict_grid_x = std::max(P.dict_grid_x, std::max(gx, 1u));
+        const uint32_t nu = cs.type == T_BYTE_ARRAY ? ((sl.n + STR_CK - 1) / STR_CK + DICT_CK_PER - 1) / DICT_CK_PER
+                                                    : (sl.n + DICT_FIXED_PER - 1) / DICT_FIXED_PER;
+        P.dict_work.push_back(DictWork{(uint32_t)P.cols.size(), (uint32_t)P.slots.size(), std::max(nu, 1u), 0});
       }
       P.slots.push_back(sl);
     }
@@ -804,10 +802,19 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        make_segs(P.snappy_segs), ws, f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (!P.slots.empty() && P.dict_grid_x) {
+  for (size_t w0 = 0; w0 < P.dict_work.size(); w0 += MAX_SEGS) {  // MAX_SEGS dictionaries per launch
+    DictTable tab;
+    memset(&tab, 0, sizeof(tab));
+    uint32_t units = 0;
+    for (size_t w = w0; w < P.dict_work.size() && w < w0 + MAX_SEGS; ++w) {
+      tab.w[tab.n] = P.dict_work[w];
+      tab.w[tab.n].unit0 = units;
+      units += tab.w[tab.n].units;
+      ++tab.n;
+    }
     ProfScope ps_(f, KP_DICT, s);
-    hipLaunchKernelGGL(k_dict, dim3((uint32_t)P.slots.size(), P.dict_grid_x), dim3(256), 0, s, file, ws, d_cols,
-                       (int)P.cols.size(), f->d_pages, d_slots, f->d_strck, f->d_err);
+    hipLaunchKernelGGL(k_dict, dim3((units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages, d_slots,
+                       f->d_strck, tab, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.pre_units) {
@@ -822,11 +829,6 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     HIP_OR(hipGetLastError());
   }
   if (plan_only) return PQ_OK;
-  if (P.slot_grid_y) {
-    ProfScope ps_(f, KP_DICT_SLOTS, s);
-    hipLaunchKernelGGL(k_dict_slots, dim3((uint32_t)P.slots.size(), P.slot_grid_y), dim3(256), 0, s, ws, d_slots);
-    HIP_OR(hipGetLastError());
-  }
   if (P.prep_threads) {
     ProfScope ps_(f, KP_PREP, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,

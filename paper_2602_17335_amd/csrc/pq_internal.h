@@ -182,4 +182,19 @@ struct SegTable {
   int32_t pad_;
 };
 
+// k_dict work: dictionary slot `slot` of selected column `col` is units
+// [unit0, unit0 + units) of the launch (one wave each).
+struct DictWork {
+  uint32_t col, slot, units, unit0;
+};
+struct DictTable {
+  DictWork w[MAX_SEGS];
+  int32_t n;
+  int32_t pad_;
+};
+// entries per k_dict wave: fixed-width dictionaries; string dictionaries
+// take DICT_CK_PER checkpoints of STR_CK entries
+constexpr uint32_t DICT_FIXED_PER = 1024;
+constexpr uint32_t DICT_CK_PER = 4;
+
 }  // namespace pqk

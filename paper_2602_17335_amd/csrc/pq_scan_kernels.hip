@@ -931,93 +931,161 @@ __global__ __launch_bounds__(WG) void k_edges(const uint8_t* __restrict__ ws, co
 
 // ---------------------------------------------------------------------------
 // k_dict: dictionary pages of the scanned chunks -> workspace dictionaries.
-// grid: (dictionary slots, chunks of entries)
+// One wave per unit of a DictTable entry.  Fixed-width dictionaries: 1024
+// PLAIN values per wave (16 per lane, all loads before the stores).  String
+// dictionaries: DICT_CK_PER checkpoints (STR_CK entries each, positions from
+// the open-time index) per wave; the wave copies their bytes into LDS with
+// coalesced loads, one lane per checkpoint walks the length prefixes there,
+// and for slot dictionaries the wave then writes every entry's 64-byte slot
+// (chars zero-padded, length in the last dword) from LDS.  A string region
+// larger than the LDS buffer (never for slot dictionaries: at most
+// DICT_CK_PER * STR_CK * SLOT_BYTES bytes) is walked in global memory.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, int ncols,
-                                             const PageDev* pages, DictSlot* slots, const uint32_t* strck, uint32_t* err) {
-  const uint32_t si = blockIdx.x;
-  const uint32_t part = blockIdx.y;
-  DictSlot sl = slots[si];
-  if (sl.page == ~0u) return;
-  // the column owning this slot
-  int c = 0;
-  for (int j = 1; j < ncols; ++j) if (cols[j].dict_slot0 <= si) c = j;
-  const ColScan cs = cols[c];
+__global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
+                                             const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
+                                             DictSlot* __restrict__ slots, const uint32_t* __restrict__ strck,
+                                             DictTable tab, uint32_t* __restrict__ err) {
+  constexpr uint32_t NE = DICT_CK_PER * STR_CK;      // entries per string unit
+  constexpr uint32_t RB = NE * SLOT_BYTES;           // LDS region bytes
+  constexpr uint32_t RW = RB / 4 + 32;               // + slack for the realigning reads
+  __shared__ __align__(16) uint32_t s_reg[NWAVES][RW];
+  __shared__ uint32_t s_pos[NWAVES][NE], s_len[NWAVES][NE];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVES + wave));
+  int k = 0;
+  for (int j = 1; j < tab.n; ++j)
+    if (tab.w[j].unit0 <= unit) k = j;
+  const uint32_t u = unit - tab.w[k].unit0;
+  if (u >= tab.w[k].units) return;
+  const uint32_t si = tab.w[k].slot;
+  const DictSlot sl = slots[si];
+  const ColScan cs = cols[tab.w[k].col];
   const PageDev pg = pages[sl.page];
   const uint8_t* body;
   uint64_t boff;
   if (pg.flags & 2) { body = ws + cs.ws_scratch; boff = pg.val_off - cs.scratch_base; }
   else { body = file; boff = pg.val_off; }
-  if (part == 0 && threadIdx.x == 0) { slots[si].body = body; slots[si].body_off = boff; }
+  if (u == 0 && lane == 0) { slots[si].body = body; slots[si].body_off = boff; }
   const uint32_t n = sl.n;
-  if (cs.type == T_BYTE_ARRAY) {
-    // one thread per checkpoint (STR_CK entries): (pos, len) pairs relative to the body
-    uint32_t* pairs = reinterpret_cast<uint32_t*>(ws + sl.ws_entries);
-    const uint32_t nck = (n + STR_CK - 1) / STR_CK;
-    const uint32_t ck = part * WG + threadIdx.x;
-    if (ck >= nck) return;
-    uint64_t q = strck[pg.strck_begin + ck];
+  if (cs.type != T_BYTE_ARRAY) {
+    const uint32_t e0 = u * DICT_FIXED_PER + lane;
+    if (cs.width == 4) {
+      uint32_t v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t e = e0 + 64 * j;
+        v[j] = e < n ? ld_u32(body, boff + (uint64_t)e * 4) : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t e = e0 + 64 * j;
+        if (e < n) reinterpret_cast<uint32_t*>(ws + sl.ws_entries)[e] = v[j];
+      }
+    } else {
+      uint64_t v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t e = e0 + 64 * j;
+        v[j] = e < n ? ld_u64(body, boff + (uint64_t)e * 8) : 0ull;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t e = e0 + 64 * j;
+        if (e < n) reinterpret_cast<uint64_t*>(ws + sl.ws_entries)[e] = v[j];
+      }
+    }
+    return;
+  }
+  // strings: (pos, len) pairs relative to the body, and the entry lengths
+  uint32_t* pairs = reinterpret_cast<uint32_t*>(ws + sl.ws_entries);
+  const bool l16 = sl.flags & DICT_LENS16;
+  const uint32_t nck = (n + STR_CK - 1) / STR_CK;
+  const uint32_t ck0 = u * DICT_CK_PER;
+  if (ck0 >= nck) return;
+  const uint32_t ck1 = min(ck0 + DICT_CK_PER, nck);
+  const uint32_t e0 = ck0 * STR_CK;
+  const uint64_t q0 = strck[pg.strck_begin + ck0];
+  const uint64_t q1 = ck1 < nck ? (uint64_t)strck[pg.strck_begin + ck1] : (uint64_t)pg.val_len;
+  if (q1 < q0 || q1 > pg.val_len) {
+    if (lane == 0) set_err(err, ERR_STRING, sl.page);
+    return;
+  }
+  const uint64_t R = q1 - q0;
+  bool bad = false;
+  if (R <= RB) {
+    const uint64_t a0 = boff + q0;
+    const uint32_t ss = (uint32_t)(a0 & 3);
+    const uint32_t nw = (uint32_t)((ss + R + 3) >> 2);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(body + (a0 & ~3ull));
+    lds_u32* reg = (lds_u32*)&s_reg[wave][0];
+    for (uint32_t i = lane; i < nw; i += 64) reg[i] = src[i];
+    wave_sync();
+    auto lds_word = [&](uint32_t y) {  // LDS bytes [y, y + 4)
+      return __builtin_amdgcn_alignbyte(reg[(y >> 2) + 1], reg[y >> 2], y & 3);
+    };
+    if (lane < ck1 - ck0) {
+      uint64_t x = (uint64_t)strck[pg.strck_begin + ck0 + lane] - q0;  // region-relative
+      for (uint32_t j = 0; j < STR_CK; ++j) {
+        const uint32_t e = (ck0 + lane) * STR_CK + j;
+        if (e >= n) break;
+        if (x + 4 > R) { bad = true; break; }
+        const uint32_t l = lds_word(ss + (uint32_t)x);
+        x += 4;
+        if ((uint64_t)l > R - x) { bad = true; break; }
+        pairs[2 * e] = (uint32_t)(q0 + x);
+        pairs[2 * e + 1] = l;
+        if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
+        else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e] = l;
+        s_pos[wave][e - e0] = ss + (uint32_t)x;
+        s_len[wave][e - e0] = l;
+        x += l;
+      }
+    }
+    if (__ballot(bad)) {
+      if (lane == 0) set_err(err, ERR_STRING, sl.page);
+      return;
+    }
+    if (!(sl.flags & DICT_SLOTS)) return;
+    wave_sync();
+    // slots: 16-byte chunk c of entry e per step (chars zero past the length;
+    // a slot's last dword is the length, which is at most SLOT_CHARS)
+    const uint32_t ne = min(ck1 * STR_CK, n) - e0;
+    glb_u8* sb = gptr(ws + sl.ws_slots);
+    for (uint32_t i = lane; i < 4 * ne; i += 64) {
+      const uint32_t ei = i >> 2, c = i & 3;
+      const uint32_t L = s_len[wave][ei];
+      const uint32_t y = s_pos[wave][ei] + 16 * c;
+      u32x4 o;
+      uint32_t ow[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t x = lds_word(y + 4 * m);
+        const int keep = (int)L - (int)(16 * c) - 4 * m;  // chars in this dword
+        ow[m] = keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u)));
+      }
+      o.x = ow[0]; o.y = ow[1]; o.z = ow[2]; o.w = c == 3 ? L : ow[3];
+      __builtin_nontemporal_store(o, (gout_u32x4*)(sb + (uint64_t)(e0 + ei) * SLOT_BYTES + 16 * c));
+    }
+    return;
+  }
+  // a region larger than the LDS buffer: one lane per checkpoint in global memory
+  if (lane < ck1 - ck0) {
+    uint64_t q = strck[pg.strck_begin + ck0 + lane];
     for (uint32_t j = 0; j < STR_CK; ++j) {
-      const uint32_t e = ck * STR_CK + j;
+      const uint32_t e = (ck0 + lane) * STR_CK + j;
       if (e >= n) break;
-      if ((uint64_t)pg.val_len - q < 4) { set_err(err, ERR_STRING, sl.page); return; }
+      if ((uint64_t)pg.val_len - q < 4) { bad = true; break; }
       const uint32_t l = ld_u32(body, boff + q);
       q += 4;
-      if (l > (uint64_t)pg.val_len - q) { set_err(err, ERR_STRING, sl.page); return; }
+      if (l > (uint64_t)pg.val_len - q) { bad = true; break; }
       pairs[2 * e] = (uint32_t)q;
       pairs[2 * e + 1] = l;
-      if (sl.flags & DICT_LENS16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
+      if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
       else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e] = l;
       q += l;
     }
-  } else {
-    const uint32_t w = cs.width;
-    for (uint32_t e = part * 8192 + threadIdx.x; e < n && e < (part + 1) * 8192; e += WG) {
-      if (w == 4) reinterpret_cast<uint32_t*>(ws + sl.ws_entries)[e] = ld_u32(body, boff + (uint64_t)e * 4);
-      else reinterpret_cast<uint64_t*>(ws + sl.ws_entries)[e] = ld_u64(body, boff + (uint64_t)e * 8);
-    }
   }
-}
-
-// ---------------------------------------------------------------------------
-// k_dict_slots: string dictionaries whose entries all fit SLOT_CHARS bytes
-// are copied into fixed slots (one thread per entry: the string's aligned
-// source dwords realigned with byte funnel shifts, chars zero-padded, length
-// in the slot's last dword, written as four 16-byte stores).
-// grid: (dictionary slots, chunks of WG entries)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_dict_slots(uint8_t* ws, const DictSlot* slots) {
-  const DictSlot sl = slots[blockIdx.x];
-  if (sl.page == ~0u || !(sl.flags & DICT_SLOTS)) return;
-  const uint32_t e = blockIdx.y * WG + threadIdx.x;
-  if (e >= sl.n) return;
-  const uint2 pr = reinterpret_cast<const uint2*>(ws + sl.ws_entries)[e];
-  const uint64_t s = sl.body_off + pr.x;
-  const uint32_t L = pr.y;  // <= SLOT_CHARS (checked at open)
-  glb_u32* q = reinterpret_cast<glb_u32*>((glb_u8*)sl.body + (s & ~3ull));
-  const uint32_t ss = (uint32_t)(s & 3);
-  const uint32_t nsw = (ss + L + 3) >> 2;  // <= 16
-  uint32_t w[17];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) w[k] = (uint32_t)k < nsw ? q[k] : 0u;
-  w[16] = 0u;
-  uint32_t o[16];
-#pragma unroll
-  for (int k = 0; k < 15; ++k) {
-    const uint32_t x = __builtin_amdgcn_alignbyte(w[k + 1], w[k], ss);
-    const int keep = (int)L - 4 * k;  // string bytes in this dword
-    o[k] = keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u)));
-  }
-  o[15] = L;
-  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-  __attribute__((address_space(1))) v4u* dst =
-      reinterpret_cast<__attribute__((address_space(1))) v4u*>(gptr(ws + sl.ws_slots + (uint64_t)e * SLOT_BYTES));
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v4u v;
-    v.x = o[4 * k]; v.y = o[4 * k + 1]; v.z = o[4 * k + 2]; v.w = o[4 * k + 3];
-    __builtin_nontemporal_store(v, &dst[k]);
-  }
+  if (__ballot(bad) && lane == 0) set_err(err, ERR_STRING, sl.page);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,6 +41,14 @@ def _spec_cases():
         dg.Col(dg.INT64, dg.DELTA_BINARY_PACKED, True, dg.SORTED, 0.9, lo=0, hi=1 << 40, gap_max=3),
         dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 0.999, lo=0, hi=100),
     ], num_rows=40_011, rg_rows=13_000, page_bytes=20_000, name="edge")
+    # string dictionaries: entries of 45..60 chars (slots, four pieces per
+    # slot), of 61..300 chars (no slots; 128-entry regions larger than the
+    # LDS buffer), and of 0..2 chars (slots holding empty strings)
+    cases["dict_strings"] = dg.FileSpec(cols=[
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.2, hi=3000, str_min=45, str_max=60),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=2000, str_min=61, str_max=300),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=700, str_min=0, str_max=2),
+    ], num_rows=70_001, rg_rows=30_000, page_bytes=256 * dg.KiB, name="dict_strings")
     return cases
 
 
