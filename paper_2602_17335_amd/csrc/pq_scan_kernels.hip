@@ -79,9 +79,13 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
 }
 
 struct GSrc {
+  using P = uint64_t;  // stream positions (bytes, bits)
+  using I = int64_t;   // value numbers
   glb_u8* base;
   uint64_t origin;  // absolute offset of position 0
   uint64_t len;
+  // bytes p .. p+7
+  __device__ __forceinline__ uint64_t window(uint64_t p) const { return bits(p * 8, 64); }
   __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)base[origin + i] : 0u; }
   // w (<= 64) bits at bit position `bit`
   __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const {
@@ -115,6 +119,49 @@ __device__ __forceinline__ GSrc gsrc(const uint8_t* base, uint64_t a0, uint64_t 
   s.base = (glb_u8*)base;
   s.origin = a0;
   s.len = a1 > a0 ? a1 - a0 : 0;
+  return s;
+}
+
+// The same stream with 32-bit positions, for streams shorter than NARROW_LEN
+// bytes of pages with fewer than NARROW_VALUES values (every bit position and
+// every value number of the walks below then fits 31 bits).  The base is the
+// dword holding stream byte 0 (wave-uniform), so loads take a 32-bit offset.
+constexpr uint32_t NARROW_LEN = 1u << 28;
+constexpr uint32_t NARROW_VALUES = 1u << 29;
+struct GSrc32 {
+  using P = uint32_t;
+  using I = int32_t;
+  glb_u32* abase;
+  uint32_t m;    // stream byte 0 is byte m of abase[0]
+  uint32_t len;
+  __device__ __forceinline__ uint32_t byte(uint32_t i) const {
+    const uint32_t a = i + m;
+    return i < len ? (abase[a >> 2] >> (8 * (a & 3))) & 0xffu : 0u;
+  }
+  // w (<= 32) bits at bit position `bit`
+  __device__ __forceinline__ uint32_t bits(uint32_t bit, uint32_t w) const {
+    const uint32_t b = bit + 8 * m;
+    const uint32_t d = b >> 5;
+    const uint32_t v = __builtin_amdgcn_alignbit(abase[d + 1], abase[d], b & 31);
+    return v & (w >= 32 ? 0xffffffffu : ((1u << w) - 1u));
+  }
+  __device__ __forceinline__ uint64_t window(uint32_t p) const {
+    const uint32_t a = p + m, d = a >> 2, sh = a & 3;
+    const uint32_t q0 = abase[d], q1 = abase[d + 1], q2 = abase[d + 2];
+    return (uint64_t)__builtin_amdgcn_alignbyte(q1, q0, sh) | ((uint64_t)__builtin_amdgcn_alignbyte(q2, q1, sh) << 32);
+  }
+};
+
+__device__ __forceinline__ bool narrow_ok(uint64_t a0, uint64_t a1, int32_t num_values) {
+  return a1 - a0 < NARROW_LEN && (uint32_t)num_values < NARROW_VALUES;
+}
+
+__device__ __forceinline__ GSrc32 gsrc32(const uint8_t* base, uint64_t a0, uint64_t a1) {
+  GSrc32 s;
+  const uintptr_t b = (uintptr_t)(base + a0);
+  s.abase = (glb_u32*)(b & ~(uintptr_t)3);
+  s.m = (uint32_t)(b & 3);
+  s.len = a1 > a0 ? (uint32_t)(a1 - a0) : 0u;
   return s;
 }
 
@@ -219,45 +266,65 @@ __device__ __forceinline__ uint64_t group_mask(uint32_t vw, uint32_t g) {
 // ---------------------------------------------------------------------------
 // RLE / bit-packed hybrid runs, decoded per lane
 // ---------------------------------------------------------------------------
+template <class P>
 struct Hdr {
-  uint64_t n;    // values of the run
-  uint64_t adv;  // header + payload bytes
-  uint64_t pay;  // bit-packed: bit position of the payload; RLE: the repeated value
+  P n;     // values of the run
+  P adv;   // header + payload bytes
+  P pay;   // bit-packed: bit position of the payload; RLE: the repeated value
   bool bp;
-  bool ok;       // header (and an RLE value) inside the stream
+  bool ok;  // header (and an RLE value) inside the stream
 };
 
-// Run header at stream byte p of a stream of w-bit values.
-__device__ __forceinline__ Hdr read_hdr(const GSrc& s, uint64_t p, uint32_t w) {
-  Hdr H;
+// Run header at stream byte p of a stream of w-bit values.  With 32-bit
+// positions a run's value count is capped at 2^30 and a bit-packed run whose
+// payload would pass the stream end advances just past it, which the walks
+// treat exactly as the uncapped run.
+template <class Src>
+__device__ __forceinline__ Hdr<typename Src::P> read_hdr(const Src& s, typename Src::P p, uint32_t w) {
+  using P = typename Src::P;
+  constexpr bool narrow = sizeof(P) == 4;
+  Hdr<P> H;
   H.n = 0; H.adv = 1; H.pay = 0; H.bp = false; H.ok = false;
   if (p >= s.len) return H;
-  const uint64_t a = s.bits(p * 8, 64);  // bytes p .. p+7
-  uint64_t h = 0;
-  uint32_t hl = 0;
+  const uint64_t a = s.window(p);  // bytes p .. p+7
+  uint64_t h;
+  uint32_t hl;
+  if (!(a & 0x80u)) {  // one-byte header (the common case)
+    h = a & 0x7fu;
+    hl = 1;
+  } else {
+    h = 0;
+    hl = 0;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const uint32_t b = (uint32_t)(a >> (8 * k)) & 0xffu;
-    if (hl == 0) {
-      h |= (uint64_t)(b & 0x7fu) << (7 * k);
-      if (!(b & 0x80u)) hl = k + 1;
+    for (int k = 0; k < 5; ++k) {
+      const uint32_t b = (uint32_t)(a >> (8 * k)) & 0xffu;
+      if (hl == 0) {
+        h |= (uint64_t)(b & 0x7fu) << (7 * k);
+        if (!(b & 0x80u)) hl = k + 1;
+      }
     }
   }
   H.bp = h & 1;
   const uint64_t g = h >> 1;
   const uint32_t vb = (w + 7) / 8;
-  H.ok = hl != 0 && p + hl <= s.len;
+  H.ok = hl != 0 && (uint64_t)p + hl <= s.len;
   if (H.bp) {
-    H.n = g * 8;
-    H.adv = hl + g * w;
+    const uint64_t n = g * 8, adv = hl + g * w;
+    if constexpr (narrow) {
+      H.n = (P)min(n, (uint64_t)1 << 30);
+      H.adv = (P)min(adv, (uint64_t)s.len - p + 1);
+    } else {
+      H.n = n;
+      H.adv = adv;
+    }
     H.pay = (p + hl) * 8;
   } else {
-    H.n = g;
+    H.n = narrow ? (P)min(g, (uint64_t)1 << 30) : (P)g;
     H.adv = hl + vb;
     uint64_t v = hl ? a >> (8 * hl) : 0;  // bytes hl .. 7
     if (hl + vb > 8) v |= (uint64_t)s.byte(p + 8) << (8 * (8 - hl));
-    H.pay = vb >= 4 ? (uint64_t)(uint32_t)v : (v & ((1ull << (8 * vb)) - 1));
-    if (p + hl + vb > s.len) H.ok = false;
+    H.pay = (P)(vb >= 4 ? (uint64_t)(uint32_t)v : (v & ((1ull << (8 * vb)) - 1)));
+    if ((uint64_t)p + hl + vb > s.len) H.ok = false;
   }
   if (hl == 0) H.adv = 1;
   return H;
@@ -268,18 +335,20 @@ __device__ __forceinline__ Hdr read_hdr(const GSrc& s, uint64_t p, uint32_t w) {
 // x is the bit position of value lo (bit-packed) or the repeated value (RLE).
 // Values of a bit-packed run past the stream end, and level values above 1,
 // make it return false.
-template <class F>
-__device__ __forceinline__ bool walk_runs(const GSrc& s, uint64_t p, int64_t rs, uint32_t w, bool levels, int64_t a,
-                                          int64_t b, F&& f) {
+template <class Src, class F>
+__device__ __forceinline__ bool walk_runs(const Src& s, typename Src::P p, typename Src::I rs, uint32_t w, bool levels,
+                                          typename Src::I a, typename Src::I b, F&& f) {
+  using P = typename Src::P;
+  using I = typename Src::I;
   while (rs < b) {
-    const Hdr H = read_hdr(s, p, w);
+    const Hdr<P> H = read_hdr(s, p, w);
     if (!H.ok || (levels && !H.bp && H.pay > 1)) return false;
-    const int64_t re = rs + (int64_t)H.n;
+    const I re = rs + (I)H.n;
     if (re > a) {
-      const int64_t lo = max(a, rs), hi = min(b, re);
+      const I lo = max(a, rs), hi = min(b, re);
       if (H.bp) {
-        if ((H.pay + (uint64_t)(hi - rs) * w + 7) / 8 > s.len) return false;
-        f(lo, hi, true, H.pay + (uint64_t)(lo - rs) * w);
+        if (((uint64_t)H.pay + (uint64_t)(hi - rs) * w + 7) / 8 > s.len) return false;
+        f(lo, hi, true, (P)(H.pay + (P)(lo - rs) * w));
       } else {
         f(lo, hi, false, H.pay);
       }
@@ -297,26 +366,29 @@ __device__ __forceinline__ bool walk_runs(const GSrc& s, uint64_t p, int64_t rs,
 // the stream position the checkpoint offsets count from; without a recorded
 // checkpoint the walk starts at (fb_pos, fb_rs), the tile's entry point.
 template <class Src, class F>
-__device__ __forceinline__ bool ck_walk(const Src& s, uint64_t entry, Ck k, int64_t cr, uint32_t w, bool levels,
-                                        int64_t a, int64_t b, uint64_t fb_pos, int64_t fb_rs, F&& f) {
+__device__ __forceinline__ bool ck_walk(const Src& s, typename Src::P entry, Ck k, typename Src::I cr, uint32_t w,
+                                        bool levels, typename Src::I a, typename Src::I b, typename Src::P fb_pos,
+                                        typename Src::I fb_rs, F&& f) {
+  using P = typename Src::P;
+  using I = typename Src::I;
   if (k.at == CK_NONE) return walk_runs(s, fb_pos, fb_rs, w, levels, a, b, f);
-  const int64_t rend = cr + (int64_t)(k.info & CK_LEFT);  // one past the run's last value
-  const uint64_t pos = entry + k.at;
-  const int64_t hi = min(b, rend);
-  uint64_t next;
+  const I rend = cr + (I)(k.info & CK_LEFT);  // one past the run's last value
+  const P pos = entry + k.at;
+  const I hi = min(b, rend);
+  P next;
   if (k.info >> 31) {
-    const uint64_t bit0 = pos * 8 + ((k.info >> 28) & 7u);  // first bit of value cr
+    const P bit0 = pos * 8 + ((k.info >> 28) & 7u);  // first bit of value cr
     if (hi > a) {
-      if ((bit0 + (uint64_t)(hi - cr) * w + 7) / 8 > s.len) return false;
-      f(a, hi, true, bit0 + (uint64_t)(a - cr) * w);
+      if (((uint64_t)bit0 + (uint64_t)(hi - cr) * w + 7) / 8 > s.len) return false;
+      f(a, hi, true, (P)(bit0 + (P)(a - cr) * w));
     }
     if (rend >= b) return true;
-    next = (bit0 + (uint64_t)(rend - cr) * w) >> 3;
+    next = (P)min(((uint64_t)bit0 + (uint64_t)(rend - cr) * w) >> 3, (uint64_t)s.len + 1);
   } else if (levels && (k.info & (1u << 29)) && rend >= b) {
-    f(a, b, false, (k.info >> 30) & 1u);
+    f(a, b, false, (P)((k.info >> 30) & 1u));
     return true;
   } else {
-    const Hdr H = read_hdr(s, pos, w);
+    const Hdr<P> H = read_hdr(s, pos, w);
     if (!H.ok || H.bp || (levels && H.pay > 1)) return false;
     if (hi > a) f(a, hi, false, H.pay);
     if (rend >= b) return true;
@@ -339,17 +411,22 @@ __device__ __forceinline__ bool tile_levels(const WaveTile& c, Ck ck, uint32_t l
     }
     return true;
   }
-  const GSrc ds = gsrc(c.st.dbase, c.st.doff, c.st.dend);
-  const int64_t a = (int64_t)lane * LPER, b = min((int64_t)c.nrows, a + LPER);
+  const int32_t a = (int32_t)lane * LPER, b = min((int32_t)c.nrows, a + LPER);
   uint32_t half = 0;  // levels of rows [a, a + 16)
   bool ok = true;
-  if (a < b) {
-    ok = ck_walk(ds, c.td.def_pos, ck, (int64_t)(lane >> 2) * SUB_ROWS, 1, true, a, b, c.td.def_pos,
-                 -(int64_t)c.td.def_skip, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
+  auto levels = [&](const auto& ds) {
+    using P = typename std::remove_reference_t<decltype(ds)>::P;
+    using I = typename std::remove_reference_t<decltype(ds)>::I;
+    return ck_walk(ds, (P)c.td.def_pos, ck, (I)(lane >> 2) * SUB_ROWS, 1, true, (I)a, (I)b, (P)c.td.def_pos,
+                   -(I)c.td.def_skip, [&](I lo, I hi, bool bp, P x) {
       const uint32_t n = (uint32_t)(hi - lo);
       const uint32_t m = bp ? (uint32_t)ds.bits(x, n) : (x ? (uint32_t)((1ull << n) - 1) : 0u);
       half |= m << (uint32_t)(lo - a);
     });
+  };
+  if (a < b) {
+    if (narrow_ok(c.st.doff, c.st.dend, c.pg.num_values)) ok = levels(gsrc32(c.st.dbase, c.st.doff, c.st.dend));
+    else ok = levels(gsrc(c.st.dbase, c.st.doff, c.st.dend));
   }
   const uint32_t lo16 = __shfl(half, (int)((2 * lane) & 63), 64);
   const uint32_t hi16 = __shfl(half, (int)((2 * lane + 1) & 63), 64);
@@ -406,19 +483,24 @@ __device__ __forceinline__ bool tile_validity(const WaveTile& c, Ck ck, uint32_t
 // Dictionary indices of the tile's values [16 lane, 16 lane + 16) into
 // idx[pad(j)].  Returns 0, ERR_VALUES or ERR_DICT_INDEX (wave-uniform).
 __device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, Ck ck, uint32_t dn, uint32_t lane, lds_u32* idx) {
-  const GSrc vs = gsrc(c.st.vbase, c.st.voff, c.st.vend);
   const uint32_t w = c.pg.enc_w;
-  const int64_t a = (int64_t)lane * LPER, b = min((int64_t)c.td.nn, a + LPER);
+  const int32_t a = (int32_t)lane * LPER, b = min((int32_t)c.td.nn, a + LPER);
   bool ok = true, bad_idx = false;
-  if (a < b) {
-    ok = ck_walk(vs, c.td.val_pos, ck, (int64_t)(lane >> 2) * SUB_ROWS, w, false, a, b, c.td.val_pos,
-                 -(int64_t)c.td.val_skip, [&](int64_t lo, int64_t hi, bool bp, uint64_t x) {
-      for (int64_t v = lo; v < hi; ++v) {
-        uint32_t id = bp ? (uint32_t)vs.bits(x + (uint64_t)(v - lo) * w, w) : (uint32_t)x;
+  auto indices = [&](const auto& vs) {
+    using P = typename std::remove_reference_t<decltype(vs)>::P;
+    using I = typename std::remove_reference_t<decltype(vs)>::I;
+    return ck_walk(vs, (P)c.td.val_pos, ck, (I)(lane >> 2) * SUB_ROWS, w, false, (I)a, (I)b, (P)c.td.val_pos,
+                   -(I)c.td.val_skip, [&](I lo, I hi, bool bp, P x) {
+      for (I v = lo; v < hi; ++v) {
+        uint32_t id = bp ? (uint32_t)vs.bits(x + (P)(v - lo) * w, w) : (uint32_t)x;
         if (id >= dn) { bad_idx = true; id = 0; }
         idx[pad((uint32_t)v)] = id;
       }
     });
+  };
+  if (a < b) {
+    if (narrow_ok(c.st.voff, c.st.vend, c.pg.num_values)) ok = indices(gsrc32(c.st.vbase, c.st.voff, c.st.vend));
+    else ok = indices(gsrc(c.st.vbase, c.st.voff, c.st.vend));
   }
   if (__ballot(!ok)) return ERR_VALUES;
   if (__ballot(bad_idx)) return ERR_DICT_INDEX;
