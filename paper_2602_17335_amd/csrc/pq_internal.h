@@ -128,6 +128,7 @@ struct TileDev {
 // one aligned 64-byte piece of memory.
 constexpr uint32_t SLOT_BYTES = 64;
 constexpr uint32_t SLOT_CHARS = 60;
+static_assert(SLOT_BYTES == 64 && SLOT_CHARS < 64, "a slot offset and a length share one word");
 enum : uint32_t { DICT_SLOTS = 1, DICT_LENS16 = 2 };
 struct DictSlot {
   const uint8_t* body;   // 16-byte aligned base holding the dictionary page body (file or

@@ -1505,7 +1505,9 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
                                                    uint32_t* __restrict__ err) {
   // per wave: the value positions (indices) of the tile, then, once every
   // row's (position, length) is in registers, the chars staging buffer
-  constexpr uint32_t BUFW = PADN + GROUP_CHARS / 4 + 8;
+  // (slot strings are staged in the index area itself: one group of at most
+  // 64 * SLOT_CHARS chars fits it)
+  constexpr uint32_t BUFW = SLOTS ? PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
   constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
   __shared__ __align__(16) uint32_t s_buf[NWAVES][BUFW];
   WaveTile c;
@@ -1689,6 +1691,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     // neighbouring tiles).
     constexpr uint32_t HEAD = 16;                      // room for a string's dword before byte 0
     constexpr uint32_t CAP = BUFW * 4 - HEAD - 64;     // chars + the realignment slack
+    static_assert(BUFW % 4 == 0 && CAP >= 64 * SLOT_CHARS + 15, "one group of slot strings fits the buffer");
     wave_sync();
     typedef __attribute__((address_space(3))) u32x4 lds_v4u;
     lds_v4u* zb = (lds_v4u*)&s_buf[wave][0];
@@ -1700,12 +1703,15 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     uint32_t lo = (uint32_t)((uintptr_t)tile_chars & 15);  // LDS byte of tile char bstart
     uint32_t bstart = 0, bfill = 0;
     bool head_foreign = lo != 0;  // LDS bytes [0, lo) of chunk 0 belong to the previous tile
+    // from here on pos[g] is the slot's byte offset | the string's length
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) pos[g] |= len[g];
     uint32_t wc[12], wn[12];
-    slot_load(sbase, pos[0], len[0], wn);
+    slot_load(sbase, pos[0] & ~63u, pos[0] & 63u, wn);
     for (int g = 0; g < NGROUPS; ++g) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) wc[k] = wn[k];
-      if (g + 1 < NGROUPS) slot_load(sbase, pos[g + 1], len[g + 1], wn);
+      if (g + 1 < NGROUPS) slot_load(sbase, pos[g + 1] & ~63u, pos[g + 1] & 63u, wn);
       if (T[g] == 0) continue;
       if (bfill && lo + bfill + T[g] > CAP) {
         // store the full chunks, clear them, move the partial one to the front
@@ -1729,7 +1735,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
         lo = tail;
         bfill = 0;
       }
-      if (len[g]) slot_or(wc, sbase, pos[g], len[g], cb8, lo + (ex[g] - bstart));
+      if (pos[g] & 63u) slot_or(wc, sbase, pos[g] & ~63u, pos[g] & 63u, cb8, lo + (ex[g] - bstart));
       bfill += T[g];
     }
     wave_sync();
