@@ -86,6 +86,7 @@ struct GSrc {
   uint64_t len;
   // bytes p .. p+7
   __device__ __forceinline__ uint64_t window(uint64_t p) const { return bits(p * 8, 64); }
+  __device__ __forceinline__ uint64_t bits64(uint64_t bit, uint32_t w) const { return bits(bit, w); }
   __device__ __forceinline__ uint32_t byte(uint64_t i) const { return i < len ? (uint32_t)base[origin + i] : 0u; }
   // w (<= 64) bits at bit position `bit`
   __device__ __forceinline__ uint64_t bits(uint64_t bit, uint32_t w) const {
@@ -144,6 +145,15 @@ struct GSrc32 {
     const uint32_t d = b >> 5;
     const uint32_t v = __builtin_amdgcn_alignbit(abase[d + 1], abase[d], b & 31);
     return v & (w >= 32 ? 0xffffffffu : ((1u << w) - 1u));
+  }
+  // w (<= 64) bits at bit position `bit`
+  __device__ __forceinline__ uint64_t bits64(uint32_t bit, uint32_t w) const {
+    const uint32_t b = bit + 8 * m;
+    const uint32_t d = b >> 5, sh = b & 31;
+    const uint32_t q0 = abase[d], q1 = abase[d + 1], q2 = abase[d + 2];
+    const uint64_t v = (uint64_t)__builtin_amdgcn_alignbit(q1, q0, sh) |
+                       ((uint64_t)__builtin_amdgcn_alignbit(q2, q1, sh) << 32);
+    return w >= 64 ? v : (v & ((1ull << w) - 1));
   }
   __device__ __forceinline__ uint64_t window(uint32_t p) const {
     const uint32_t a = p + m, d = a >> 2, sh = a & 3;
@@ -513,9 +523,10 @@ __device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, Ck ck, uin
 // Block header position of page block `bb` for tile c, whose first delta
 // lies in block bu: the recorded checkpoint, else a walk over the blocks from
 // the tile's entry block.  False on a malformed block.
-__device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s, const Ck* ckv, uint64_t bb,
-                                                uint64_t bu, bool is32, uint64_t& hp) {
-  const uint64_t slot = bb - bu;
+template <class Src>
+__device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const Src& s, const Ck* ckv, uint32_t bb,
+                                                uint32_t bu, bool is32, uint64_t& hp) {
+  const uint32_t slot = bb - bu;
   if (slot < NSUB) {
     const uint32_t k = ckv[(size_t)c.t * NSUB + slot].at;
     if (k != CK_NONE) { hp = (uint64_t)c.td.val_pos + k; return true; }
@@ -527,7 +538,7 @@ __device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s
     int sft = 0;
     for (;;) {  // min delta
       if (q >= s.len || sft > 63) return false;
-      const uint32_t x = s.byte(q++);
+      const uint32_t x = s.byte((typename Src::P)q++);
       sft += 7;
       if (!(x & 0x80)) break;
     }
@@ -536,7 +547,7 @@ __device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s
     const uint64_t used_mb = (used + per - 1) / per;
     uint64_t body = 0;
     for (uint64_t m = 0; m < used_mb; ++m) {
-      const uint32_t wm = s.byte(q + m);
+      const uint32_t wm = s.byte((typename Src::P)(q + m));
       if (wm > maxw) return false;
       body += per * wm / 8;
     }
@@ -546,71 +557,120 @@ __device__ __forceinline__ bool delta_block_pos(const WaveTile& c, const GSrc& s
   return true;
 }
 
+// A DELTA block: its min delta, the bit position of its first miniblock and
+// its (at most 16) miniblock widths.
+struct DBlk {
+  uint64_t md;
+  uint64_t body;
+  uint64_t W0, W1;
+  bool ok;
+};
+
+template <class Src>
+__device__ __forceinline__ DBlk delta_block(const WaveTile& c, const Src& s, const Ck* ckv, uint32_t bb, uint32_t bu,
+                                            bool is32, uint32_t M) {
+  DBlk k;
+  uint64_t hp = 0;
+  k.ok = delta_block_pos(c, s, ckv, bb, bu, is32, hp);
+  if (hp > s.len) hp = s.len;
+  // min delta (ULEB128, zigzag), then the miniblock widths
+  const uint64_t h0 = s.window((typename Src::P)hp);
+  const uint64_t h1 = (h0 & 0x8080808080808080ull) == 0x8080808080808080ull ? s.window((typename Src::P)(hp + 8)) : 0;
+  uint64_t u = 0;
+  uint32_t hl = 0;
+#pragma unroll
+  for (int j = 0; j < 10; ++j) {
+    const uint32_t byte = j < 8 ? (uint32_t)(h0 >> (8 * j)) & 0xffu : (uint32_t)(h1 >> (8 * (j - 8))) & 0xffu;
+    if (hl == 0) {
+      u |= (uint64_t)(byte & 0x7fu) << (7 * j);
+      if (!(byte & 0x80u)) hl = j + 1;
+    }
+  }
+  if (hl == 0 || hp + hl + M > s.len) k.ok = false;
+  k.md = (uint64_t)unzz(u);
+  const uint64_t wb = min(hp + hl, (uint64_t)s.len);
+  k.W0 = s.window((typename Src::P)wb);
+  k.W1 = M > 8 ? s.window((typename Src::P)(wb + 8)) : 0;
+  k.body = (wb + M) * 8;
+  return k;
+}
+
+// Width of miniblock m (< 16) of block k and the bit position of its first
+// value: the widths of the miniblocks before it summed with byte SADs.
+__device__ __forceinline__ void delta_mini(const DBlk& k, uint32_t m, uint32_t per, uint32_t& w, uint64_t& off) {
+  const uint64_t lo = m >= 8 ? ~0ull : ((1ull << (8 * m)) - 1);
+  const uint64_t hi = m <= 8 ? 0ull : ((1ull << (8 * (m - 8))) - 1);
+  const uint64_t a = k.W0 & lo, b = k.W1 & hi;
+  uint32_t sum = __builtin_amdgcn_sad_u8((uint32_t)a, 0u, 0u);
+  sum = __builtin_amdgcn_sad_u8((uint32_t)(a >> 32), 0u, sum);
+  sum = __builtin_amdgcn_sad_u8((uint32_t)b, 0u, sum);
+  sum = __builtin_amdgcn_sad_u8((uint32_t)(b >> 32), 0u, sum);
+  w = (uint32_t)((m < 8 ? k.W0 >> (8 * m) : k.W1 >> (8 * (m - 8))) & 0xffu);
+  off = k.body + (uint64_t)per * sum;
+}
+
 // D of the tile's values [16 lane, 16 lane + 16): the page's first value for
 // value 0, else the delta that leads to the value.  Values past nn get 0.
-// Returns false on a malformed block (wave-uniform after a ballot by the caller).
-__device__ __forceinline__ bool delta_terms(const WaveTile& c, const Ck* ckv, uint32_t lane, uint64_t* D) {
-  const GSrc s = gsrc(c.st.vbase, c.st.voff, c.st.vend);
+// A lane's deltas lie in at most two miniblocks (a miniblock holds a multiple
+// of 32 values), so it reads at most two block headers.  Returns false on a
+// malformed block (wave-uniform after a ballot by the caller).
+template <class Src>
+__device__ __forceinline__ bool delta_terms_in(const WaveTile& c, const Src& s, const Ck* ckv, uint32_t lane,
+                                               uint64_t* D) {
   const bool is32 = c.cs.type == T_INT32;
   const uint32_t maxw = is32 ? 32 : 64;
-  const uint64_t B = c.pg.enc_w, M = c.pg.enc_m, per = B / M;
-  const uint64_t first = c.td.k0 == 0 ? 1 : c.td.k0;
-  const uint64_t bu = (first - 1) / B;
-  uint64_t cur_b = ~0ull, md = 0, wb = 0, body = 0, W0 = 0, W1 = 0;
-  bool ok = true;
+  const uint32_t B = c.pg.enc_w, M = c.pg.enc_m, per = B / M;
+#pragma unroll
+  for (int q = 0; q < LPER; ++q) D[q] = 0;
+  const uint32_t nn = c.td.nn, j0 = lane * LPER;
+  if (j0 >= nn) return true;
+  const uint32_t kk0 = c.td.k0 + j0;
+  const uint32_t first = c.td.k0 == 0 ? 1u : c.td.k0;
+  const uint32_t bu = (first - 1) / B;
+  const uint32_t q0 = kk0 == 0 ? 1u : 0u;       // entry 0 of value 0 is the page's first value
+  const uint32_t d0 = kk0 == 0 ? 0u : kk0 - 1;  // delta number of entry q0
+  const uint32_t nq = min((uint32_t)LPER, nn - j0);
+  if (kk0 == 0) D[0] = (uint64_t)c.pg.delta_first;
+  if (q0 >= nq) return true;
+  const uint32_t bbA = d0 / B, oA = d0 - bbA * B, mA = oA / per, iA = oA - mA * per;
+  const DBlk A = delta_block(c, s, ckv, bbA, bu, is32, M);
+  bool ok = A.ok;
+  uint32_t wA, wB = 0;
+  uint64_t offA, offB = 0, mdB = A.md;
+  delta_mini(A, mA, per, wA, offA);
+  const uint32_t nA = per - iA;  // deltas of miniblock mA from entry q0 on
+  const bool needB = q0 + nA < nq;
+  if (needB) {
+    if (mA + 1 < M) {
+      delta_mini(A, mA + 1, per, wB, offB);
+    } else {
+      const DBlk Bk = delta_block(c, s, ckv, bbA + 1, bu, is32, M);
+      ok = ok && Bk.ok;
+      mdB = Bk.md;
+      delta_mini(Bk, 0, per, wB, offB);
+    }
+  }
+  if (wA > maxw || wB > maxw) ok = false;
+  const uint32_t usedA = min(nA, nq - q0);
+  if ((offA + (uint64_t)(iA + usedA) * wA + 7) / 8 > s.len) ok = false;
+  if (needB && (offB + (uint64_t)(nq - q0 - nA) * wB + 7) / 8 > s.len) ok = false;
+  if (!ok) return false;
 #pragma unroll
   for (int q = 0; q < LPER; ++q) {
-    const uint32_t j = lane * LPER + q;
-    uint64_t x = 0;
-    if (j < c.td.nn && ok) {
-      const uint64_t kk = (uint64_t)c.td.k0 + j;
-      if (kk == 0) {
-        x = (uint64_t)c.pg.delta_first;
-      } else {
-        const uint64_t d = kk - 1, bb = d / B;
-        if (bb != cur_b) {
-          uint64_t hp = 0;
-          if (!delta_block_pos(c, s, ckv, bb, bu, is32, hp)) { ok = false; }
-          // min delta (ULEB128, zigzag) and the miniblock widths after it
-          const uint64_t h0 = s.bits(hp * 8, 64);
-          const uint64_t h1 = (h0 & 0x8080808080808080ull) == 0x8080808080808080ull ? s.bits((hp + 8) * 8, 16) : 0;
-          uint64_t u = 0;
-          uint32_t hl = 0;
-#pragma unroll
-          for (int k = 0; k < 10; ++k) {
-            const uint32_t byte = k < 8 ? (uint32_t)(h0 >> (8 * k)) & 0xffu : (uint32_t)(h1 >> (8 * (k - 8))) & 0xffu;
-            if (hl == 0) {
-              u |= (uint64_t)(byte & 0x7fu) << (7 * k);
-              if (!(byte & 0x80u)) hl = k + 1;
-            }
-          }
-          if (hl == 0 || hp + hl + M > s.len) ok = false;
-          md = (uint64_t)unzz(u);
-          wb = hp + hl;
-          W0 = s.bits(wb * 8, 64);
-          W1 = M > 8 ? s.bits((wb + 8) * 8, 64) : 0;
-          body = (wb + M) * 8;
-          cur_b = bb;
-        }
-        const uint64_t o = d - bb * B;
-        const uint32_t m = (uint32_t)(o / per), i = (uint32_t)(o - (uint64_t)m * per);
-        uint64_t woff = 0;
-        uint32_t wm = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t wk = (uint32_t)((k < 8 ? W0 >> (8 * k) : W1 >> (8 * (k - 8))) & 0xffu);
-          if ((uint32_t)k < m) woff += per * wk;
-          if ((uint32_t)k == m) wm = wk;
-        }
-        if (wm > maxw) ok = false;
-        const uint64_t bit = body + woff + (uint64_t)i * wm;
-        if (wm && (bit + wm + 7) / 8 > s.len) ok = false;
-        x = ok ? md + s.bits(bit, wm) : 0;
-      }
-    }
-    D[q] = x;
+    if ((uint32_t)q < q0 || (uint32_t)q >= nq) continue;
+    const uint32_t r = q - q0;
+    const bool inA = r < nA;
+    const uint32_t w = inA ? wA : wB;
+    const uint64_t bit = inA ? offA + (uint64_t)(iA + r) * wA : offB + (uint64_t)(r - nA) * wB;
+    D[q] = (inA ? A.md : mdB) + s.bits64((typename Src::P)bit, w);
   }
-  return ok;
+  return true;
+}
+
+__device__ __forceinline__ bool delta_terms(const WaveTile& c, const Ck* ckv, uint32_t lane, uint64_t* D) {
+  if (narrow_ok(c.st.voff, c.st.vend, c.pg.num_values))
+    return delta_terms_in(c, gsrc32(c.st.vbase, c.st.voff, c.st.vend), ckv, lane, D);
+  return delta_terms_in(c, gsrc(c.st.vbase, c.st.voff, c.st.vend), ckv, lane, D);
 }
 
 // ---------------------------------------------------------------------------
