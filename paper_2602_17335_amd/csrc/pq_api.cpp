@@ -18,7 +18,7 @@ namespace pqk {
 __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, Ck* ckd, Ck* ckv,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* err);
@@ -34,14 +34,14 @@ __global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* whi
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
 template <int KIND>
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
+                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
                                SegTable seg, uint32_t* err);
 __global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const Ck* ckd, const Ck* ckv, SegTable seg,
+                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, SegTable seg,
                                uint32_t* err);
 template <bool SLOTS>
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                             const TileDev* tiles, const Ck* ckd, const Ck* ckv, const DictSlot* slots,
+                             const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
                              const uint32_t* strck, SegTable seg, uint32_t* err);
 }  // namespace pqk
 
@@ -267,7 +267,7 @@ struct pq_file_s {
   PageDev* d_pages = nullptr;
   TileDev* d_tiles = nullptr;
   uint32_t* d_strck = nullptr;
-  Ck* d_ckd = nullptr;  // level-stream checkpoints, NSUB per tile
+  uint32_t* d_ckl = nullptr;  // level checkpoints, NLCK per tile
   Ck* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
   ChunkDev* d_chunks = nullptr;
   uint32_t* d_err = nullptr;
@@ -330,7 +330,7 @@ static void free_handle(pq_file f) {
   if (f->d_pages) (void)hipFree(f->d_pages);
   if (f->d_tiles) (void)hipFree(f->d_tiles);
   if (f->d_strck) (void)hipFree(f->d_strck);
-  if (f->d_ckd) (void)hipFree(f->d_ckd);
+  if (f->d_ckl) (void)hipFree(f->d_ckl);
   if (f->d_ckv) (void)hipFree(f->d_ckv);
   if (f->d_chunks) (void)hipFree(f->d_chunks);
   if (f->d_err) (void)hipFree(f->d_err);
@@ -556,7 +556,7 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   }
   if (tiles) {
     if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess ||
-        hipMalloc(&f->d_ckd, sizeof(Ck) * NSUB * tiles) != hipSuccess ||
+        hipMalloc(&f->d_ckl, sizeof(uint32_t) * NLCK * tiles) != hipSuccess ||
         hipMalloc(&f->d_ckv, sizeof(Ck) * NSUB * tiles) != hipSuccess) {
       cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: tile index allocation");
     }
@@ -566,7 +566,7 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   }
   if (npages) {
     hipLaunchKernelGGL(k_index, dim3((npages + 63) / 64), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
-                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckd, f->d_ckv, f->d_err);
+                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
   }
   HIP_OR(hipEventRecord(e1, s));
@@ -841,13 +841,13 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     ProfScope ps_(f, KP_FIXED0 + K, s);
     auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
     hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckd, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
+                       f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {
     ProfScope ps_(f, KP_DELTA, s);
     hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, make_segs(P.delta_segs), f->d_err);
+                       f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, make_segs(P.delta_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   for (int k = 0; k < 2; ++k) {
@@ -855,7 +855,7 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
     if (P.str_segs[k].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, k ? KP_STR_SLOTS : KP_STR, s);
     hipLaunchKernelGGL(k ? k_decode_str<true> : k_decode_str<false>, dim3((P.str_units[k] + 3) / 4), dim3(256), 0, s,
-                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckd, f->d_ckv, d_slots, f->d_strck,
+                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, d_slots, f->d_strck,
                        make_segs(P.str_segs[k]), f->d_err);
     HIP_OR(hipGetLastError());
   }

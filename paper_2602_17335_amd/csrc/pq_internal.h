@@ -54,6 +54,19 @@ struct Ck {
   uint32_t at;
   uint32_t info;
 };
+// Level checkpoints: one word per LROWS rows of a tile (rows 16 l .. 16 l +
+// 15 are lane l's), the state of the level run holding that row:
+//   bits 0..15   byte offset from the tile's level entry: for a bit-packed run
+//                the byte holding the row's bit, for an RLE run the header of
+//                the run that follows it
+//   bits 16..18  the bit within that byte (bit-packed)
+//   bit 19       bit-packed
+//   bit 20       the level of an RLE run
+//   bits 21..25  values left in the run from this row, at most LROWS
+// LCK_NONE: not recorded (offset past 16 bits); the tile's entry is used.
+constexpr int LROWS = 16;
+constexpr int NLCK = TILE_ROWS / LROWS;
+constexpr uint32_t LCK_NONE = 0xffffffffu;
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;

@@ -157,6 +157,25 @@ __device__ __forceinline__ Ck make_ck(const RunCur& c, int64_t target, uint32_t 
   return k;
 }
 
+// Level checkpoint (format in pq_internal.h) of row `target` inside run c of
+// a level stream whose tile entry sits at absolute position `entry`.
+__device__ __forceinline__ uint32_t make_lck(const RunCur& c, int64_t target, uint64_t entry) {
+  const uint64_t skip = (uint64_t)(target - c.start);
+  const uint64_t left = min(c.n - skip, (uint64_t)LROWS);
+  uint64_t off;
+  uint32_t x;
+  if (c.bp) {
+    const uint64_t bit = c.pay * 8 + skip;
+    off = (bit >> 3) - entry;
+    x = (1u << 19) | ((uint32_t)(bit & 7) << 16);
+  } else {
+    off = c.next - entry;
+    x = (c.val & 1u) << 20;
+  }
+  if (off > 0xffffu) return LCK_NONE;
+  return (uint32_t)off | x | ((uint32_t)left << 21);
+}
+
 __device__ __forceinline__ Ck ck_at(uint64_t off) {
   Ck k;
   k.at = off < CK_NONE ? (uint32_t)off : CK_NONE;
@@ -174,7 +193,7 @@ __device__ __forceinline__ Ck ck_none() {
 // One lane per page.  `scratch` holds every compressed page decompressed at
 // its file-wide scratch offset.
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, Ck* ckd, Ck* ckv,
+                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npages) return;
@@ -266,14 +285,14 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     uint64_t before = 0;  // valid rows in runs before the current one
     bool have = false;
     TileDev td;
-    for (int64_t target = 0; target < nv; target += SUB_ROWS) {
+    for (int64_t target = 0; target < nv; target += LROWS) {
       while (!have || c.start + (int64_t)c.n <= target) {
         if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
         if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
         have = true;
       }
       const uint64_t skip = (uint64_t)(target - c.start);
-      const uint32_t t = (uint32_t)(target / TILE_ROWS), sub = (uint32_t)((target % TILE_ROWS) / SUB_ROWS);
+      const uint32_t t = (uint32_t)(target / TILE_ROWS), sub = (uint32_t)((target % TILE_ROWS) / LROWS);
       if (sub == 0) {
         td.page = (uint32_t)p;
         td.row0 = (uint32_t)target;
@@ -284,9 +303,9 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
         td.val_pos = 0;
         td.val_skip = 0;
         tiles[pg.tile_begin + t] = td;
-        for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
+        for (int k = 0; k < NLCK; ++k) ckl[(size_t)(pg.tile_begin + t) * NLCK + k] = LCK_NONE;
       }
-      ckd[(size_t)(pg.tile_begin + t) * NSUB + sub] = make_ck(c, target, 1, def_off + td.def_pos, true);
+      ckl[(size_t)(pg.tile_begin + t) * NLCK + sub] = make_lck(c, target, def_off + td.def_pos);
     }
     if (nv > 0) {
       while (!have || c.start + (int64_t)c.n < nv) {
@@ -307,7 +326,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
       td.nn = 0;
       td.def_pos = 0; td.def_skip = 0; td.val_pos = 0; td.val_skip = 0;
       tiles[pg.tile_begin + t] = td;
-      for (int k = 0; k < NSUB; ++k) ckd[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
+      for (int k = 0; k < NLCK; ++k) ckl[(size_t)(pg.tile_begin + t) * NLCK + k] = LCK_NONE;
     }
   }
   for (uint32_t t = 0; t < ntiles; ++t)

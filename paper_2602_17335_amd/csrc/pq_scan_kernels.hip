@@ -35,6 +35,7 @@ constexpr int NGROUPS = TR / 64;      // 64-row groups per tile
 constexpr int PADN = TR + TR / 16 + 4;  // padded per-wave LDS arrays (see pad())
 constexpr int GROUP_CHARS = 3072;     // per-wave LDS bytes for one 64-row group of strings
 static_assert(SUB_ROWS == 4 * LPER, "four lanes share one sub-tile checkpoint");
+static_assert(LROWS == LPER, "one level checkpoint per lane");
 static_assert(NWORDS == 32, "lane j < 32 holds validity word j");
 
 // Per-wave LDS arrays written lane-blocked (lane l writes entries 16 l ..)
@@ -409,9 +410,11 @@ __device__ __forceinline__ bool ck_walk(const Src& s, typename Src::P entry, Ck 
 
 // Definition levels of the tile: lane j (< 32) returns validity word j
 // (rows 32 j .. 32 j + 31; all ones over the tile's rows for a REQUIRED
-// column).  Lane l decodes rows [16 l, 16 l + 16) from its checkpoint; false
-// (wave-uniform) when the level stream is malformed.
-__device__ __forceinline__ bool tile_levels(const WaveTile& c, Ck ck, uint32_t lane, uint32_t& vw) {
+// column).  Lane l decodes rows [16 l, 16 l + 16): the run holding row 16 l
+// comes from its level checkpoint (no header read), later runs are walked
+// from the header after it.  False (wave-uniform) when the level stream is
+// malformed.
+__device__ __forceinline__ bool tile_levels(const WaveTile& c, uint32_t lk, uint32_t lane, uint32_t& vw) {
   if (!c.cs.optional) {
     const uint32_t j = lane;
     vw = 0;
@@ -427,12 +430,29 @@ __device__ __forceinline__ bool tile_levels(const WaveTile& c, Ck ck, uint32_t l
   auto levels = [&](const auto& ds) {
     using P = typename std::remove_reference_t<decltype(ds)>::P;
     using I = typename std::remove_reference_t<decltype(ds)>::I;
-    return ck_walk(ds, (P)c.td.def_pos, ck, (I)(lane >> 2) * SUB_ROWS, 1, true, (I)a, (I)b, (P)c.td.def_pos,
-                   -(I)c.td.def_skip, [&](I lo, I hi, bool bp, P x) {
+    auto put = [&](I lo, I hi, bool bp, P x) {
       const uint32_t n = (uint32_t)(hi - lo);
       const uint32_t m = bp ? (uint32_t)ds.bits(x, n) : (x ? (uint32_t)((1ull << n) - 1) : 0u);
       half |= m << (uint32_t)(lo - a);
-    });
+    };
+    if (lk == LCK_NONE)
+      return walk_runs(ds, (P)c.td.def_pos, -(I)c.td.def_skip, 1, true, (I)a, (I)b, put);
+    const P at = (P)c.td.def_pos + (P)(lk & 0xffffu);
+    const uint32_t left = (lk >> 21) & 31u;
+    const I hi = min((I)b, (I)(a + (int32_t)left));
+    P next;
+    if (lk & (1u << 19)) {  // bit-packed: the run ends on a byte boundary
+      const uint32_t bo = (lk >> 16) & 7u;
+      const P bit = at * 8 + bo;
+      if (((uint64_t)bit + (uint64_t)(hi - a) + 7) / 8 > ds.len) return false;
+      put((I)a, hi, true, bit);
+      next = at + (P)((bo + left) >> 3);
+    } else {
+      put((I)a, hi, false, (P)((lk >> 20) & 1u));
+      next = at;
+    }
+    if (hi >= (I)b) return true;
+    return walk_runs(ds, next, hi, 1, true, hi, (I)b, put);
   };
   if (a < b) {
     if (narrow_ok(c.st.doff, c.st.dend, c.pg.num_values)) ok = levels(gsrc32(c.st.dbase, c.st.doff, c.st.dend));
@@ -480,9 +500,9 @@ __device__ __forceinline__ void write_validity(const WaveTile& c, uint32_t vw, u
 
 // Levels of the tile (validity word per lane, see tile_levels), written to
 // the output bitmap of an OPTIONAL column.  False after recording an error.
-__device__ __forceinline__ bool tile_validity(const WaveTile& c, Ck ck, uint32_t lane, uint32_t* err, uint8_t* ws,
+__device__ __forceinline__ bool tile_validity(const WaveTile& c, uint32_t lck, uint32_t lane, uint32_t* err, uint8_t* ws,
                                               uint32_t& vw) {
-  if (!tile_levels(c, ck, lane, vw)) {
+  if (!tile_levels(c, lck, lane, vw)) {
     if (lane == 0) set_err(err, ERR_LEVELS, c.td.page);
     return false;
   }
@@ -1354,7 +1374,7 @@ template <int KIND>
 __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
-                                                     const Ck* __restrict__ ckd,
+                                                     const uint32_t* __restrict__ ckl,
                                                      const Ck* __restrict__ ckv,
                                                      const DictSlot* __restrict__ slots, SegTable seg,
                                                      uint32_t* __restrict__ err) {
@@ -1364,7 +1384,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
   const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
@@ -1376,7 +1396,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   }
   if (dict_page != is_dict || (c.cs.width == 4) != w4) return;  // another instantiation's tile
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
+  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
   lds_u32* idx = (lds_u32*)&s_idx[wave][0];
   glb_u8* ent = nullptr;
   if constexpr (is_dict) {
@@ -1467,7 +1487,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
 __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
-                                                     const Ck* __restrict__ ckd,
+                                                     const uint32_t* __restrict__ ckl,
                                                      const Ck* __restrict__ ckv, SegTable seg,
                                                      uint32_t* __restrict__ err) {
   // per wave: the values of one half of the tile's rows (at most TR / 2)
@@ -1475,11 +1495,11 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
   __shared__ uint64_t s_vals[NWAVES][HALF + HALF / 16 + 4];
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
-  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
+  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
   const uint32_t nn = c.td.nn;
   // lane l holds values 16 l .. 16 l + 15 (prefix sums, in registers)
@@ -1558,7 +1578,7 @@ template <bool SLOTS>
 __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                                    const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                    const TileDev* __restrict__ tiles,
-                                                   const Ck* __restrict__ ckd,
+                                                   const uint32_t* __restrict__ ckl,
                                                    const Ck* __restrict__ ckv,
                                                    const DictSlot* __restrict__ slots,
                                                    const uint32_t* __restrict__ strck, SegTable seg,
@@ -1573,7 +1593,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   WaveTile c;
   if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const Ck ckl = ckd[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
   const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int enc = c.pg.encoding;
@@ -1592,7 +1612,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, ckl, lane, err, ws, vw)) return;
+  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
   lds_u32* u = (lds_u32*)&s_buf[wave][0];
   const TileDev& td = c.td;
   glb_u8* sbase;
@@ -1853,17 +1873,17 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
 }
 
 template __global__ void k_decode_str<false>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                            const Ck*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
+                                            const uint32_t*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
 template __global__ void k_decode_str<true>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                           const Ck*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
+                                           const uint32_t*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<0>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                          const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+                                          const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_DICT>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                                const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+                                                const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                                const Ck*, const Ck*, const DictSlot*, SegTable, uint32_t*);
+                                                const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_DICT | FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*,
-                                                          const TileDev*, const Ck*, const Ck*, const DictSlot*, SegTable,
+                                                          const TileDev*, const uint32_t*, const Ck*, const DictSlot*, SegTable,
                                                           uint32_t*);
 
 }  // namespace pqk
