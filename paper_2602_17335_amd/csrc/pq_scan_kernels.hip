@@ -179,23 +179,38 @@ __device__ __forceinline__ GSrc32 gsrc32(const uint8_t* base, uint64_t a0, uint6
 // ---------------------------------------------------------------------------
 // wave and workgroup scans
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
+// Inclusive wave scans with DPP moves (no LDS): row_shr 1, 2, 4, 8 scan each
+// row of 16 lanes, then row_bcast:15 and row_bcast:31 carry the rows' totals
+// into rows 1, 3 and 2, 3.  Lanes whose source is outside the row read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+constexpr int DPP_ROW_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  v += dpp0<DPP_ROW_SHR | 1, 0xf>(v);
+  v += dpp0<DPP_ROW_SHR | 2, 0xf>(v);
+  v += dpp0<DPP_ROW_SHR | 4, 0xf>(v);
+  v += dpp0<DPP_ROW_SHR | 8, 0xf>(v);
+  v += dpp0<DPP_BCAST15, 0xa>(v);
+  v += dpp0<DPP_BCAST31, 0xc>(v);
   return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_add_u64(uint64_t v) {
+  const uint32_t lo = dpp0<CTRL, ROWS>((uint32_t)v), hi = dpp0<CTRL, ROWS>((uint32_t)(v >> 32));
+  return v + ((uint64_t)hi << 32 | lo);
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+  v = dpp_add_u64<DPP_ROW_SHR | 1, 0xf>(v);
+  v = dpp_add_u64<DPP_ROW_SHR | 2, 0xf>(v);
+  v = dpp_add_u64<DPP_ROW_SHR | 4, 0xf>(v);
+  v = dpp_add_u64<DPP_ROW_SHR | 8, 0xf>(v);
+  v = dpp_add_u64<DPP_BCAST15, 0xa>(v);
+  v = dpp_add_u64<DPP_BCAST31, 0xc>(v);
   return v;
 }
 
