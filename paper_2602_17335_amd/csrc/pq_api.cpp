@@ -279,6 +279,10 @@ struct pq_file_s {
   std::vector<hipEvent_t> event_pool;
   double prof_ms[NKERN] = {0};
   uint64_t prof_n[NKERN] = {0};
+  // second stream of a scan: the prefix passes run there, beside the
+  // fixed-width decode kernels (created at the first scan, default priority)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // Slot order; k_decode_fixed<K> for K = 0 PLAIN 4-byte, 1 dictionary 4-byte,
@@ -325,6 +329,12 @@ struct ProfScope {
 
 static void free_handle(pq_file f) {
   if (!f) return;
+  if (f->aux) {
+    (void)hipStreamSynchronize(f->aux);
+    (void)hipStreamDestroy(f->aux);
+  }
+  if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
+  if (f->ev_join) (void)hipEventDestroy(f->ev_join);
   for (auto& r : f->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : f->event_pool) (void)hipEventDestroy(e);
   if (f->d_pages) (void)hipFree(f->d_pages);
@@ -787,6 +797,14 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
 
 }  // namespace
 
+static hipError_t ensure_aux(pq_file f) {
+  if (f->aux) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&f->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->aux, hipStreamNonBlocking);
+  return e;
+}
+
 static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool plan_only) {
   ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
   DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
@@ -795,6 +813,9 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
   if (!P.scan_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.scan_cols.data(), sizeof(int32_t) * P.scan_cols.size(), hipMemcpyHostToDevice, s));
   const uint8_t* file = f->file;
+  for (const auto* v : {&P.snappy_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
+                        &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
+    if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
   if (P.snappy_waves) {
     if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, KP_SNAPPY, s);
@@ -817,18 +838,32 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        f->d_strck, tab, f->d_err);
     HIP_OR(hipGetLastError());
   }
+  // the prefix passes (k_prepass, k_tile_scan) feed only k_decode_delta and
+  // k_decode_str: in a scan they run on the handle's second stream, beside
+  // the fixed-width decode kernels, and the main stream waits for them
+  // before the kernels that read their results
+  const bool fork = !plan_only && (P.pre_units || !P.scan_cols.empty()) &&
+                    (P.fixed_units[0] || P.fixed_units[1] || P.fixed_units[2] || P.fixed_units[3]);
+  hipStream_t ps = s;
+  if (fork) {
+    HIP_OR(ensure_aux(f));
+    HIP_OR(hipEventRecord(f->ev_fork, s));
+    HIP_OR(hipStreamWaitEvent(f->aux, f->ev_fork, 0));
+    ps = f->aux;
+  }
   if (P.pre_units) {
-    ProfScope ps_(f, KP_PREPASS, s);
-    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
+    ProfScope ps_(f, KP_PREPASS, ps);
+    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, ps, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckv, d_slots, make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (!P.scan_cols.empty()) {
-    ProfScope ps_(f, KP_TILE_SCAN, s);
-    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, s, ws, d_cols, d_which, f->d_err);
+    ProfScope ps_(f, KP_TILE_SCAN, ps);
+    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, ps, ws, d_cols, d_which, f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (plan_only) return PQ_OK;
+  if (fork) HIP_OR(hipEventRecord(f->ev_join, ps));
   if (P.prep_threads) {
     ProfScope ps_(f, KP_PREP, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
@@ -844,6 +879,7 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
+  if (fork) HIP_OR(hipStreamWaitEvent(s, f->ev_join, 0));
   if (P.delta_units) {
     ProfScope ps_(f, KP_DELTA, s);
     hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
