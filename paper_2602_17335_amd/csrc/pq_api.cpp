@@ -21,7 +21,9 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
-                         uint32_t* err);
+                         uint32_t* sblk, int record, uint32_t* err);
+__global__ void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg,
+                             const uint32_t* sblk, const uint32_t* sblk_page, uint8_t* ws, uint32_t* err);
 __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, const PageDev* pages, const TileDev* tiles,
                         SegTable seg);
@@ -250,7 +252,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -267,6 +269,9 @@ struct pq_file_s {
   PageDev* d_pages = nullptr;
   TileDev* d_tiles = nullptr;
   uint32_t* d_strck = nullptr;
+  uint32_t* d_sblk = nullptr;       // Snappy block index (stream offset per 64 KiB output block)
+  uint32_t* d_sblk_page = nullptr;  // page of each block
+  uint64_t total_sblk = 0;
   uint32_t* d_ckl = nullptr;  // level checkpoints, NLCK per tile
   Ck* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
   ChunkDev* d_chunks = nullptr;
@@ -289,11 +294,11 @@ struct pq_file_s {
 // 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
 // of slot dictionaries, k_decode_str<false> the others.
 enum { KP_SNAPPY, KP_DICT, KP_PREPASS, KP_TILE_SCAN, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA,
-       KP_EDGES, KP_STR_SLOTS };
+       KP_EDGES, KP_STR_SLOTS, KP_SNAPPY_BLK };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
                                           "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
-                                          "k_decode_str<true>"};
+                                          "k_decode_str<true>", "k_snappy_blk"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -340,6 +345,8 @@ static void free_handle(pq_file f) {
   if (f->d_pages) (void)hipFree(f->d_pages);
   if (f->d_tiles) (void)hipFree(f->d_tiles);
   if (f->d_strck) (void)hipFree(f->d_strck);
+  if (f->d_sblk) (void)hipFree(f->d_sblk);
+  if (f->d_sblk_page) (void)hipFree(f->d_sblk_page);
   if (f->d_ckl) (void)hipFree(f->d_ckl);
   if (f->d_ckv) (void)hipFree(f->d_ckv);
   if (f->d_chunks) (void)hipFree(f->d_chunks);
@@ -495,7 +502,8 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   // ---- host layout: rows, dictionary links, tiles, scratch, checkpoints ----
   f->chunk_tile0.assign(nchunks + 1, 0);
   f->scratch_prefix.assign(npages + 1, 0);
-  uint64_t tiles = 0, strck = 0, scratch = 0;
+  uint64_t tiles = 0, strck = 0, scratch = 0, sblk = 0;
+  std::vector<uint32_t> sblk_page;
   for (int q = 0; q < nchunks; ++q) {
     const ChunkDev& cd = f->chunks[q];
     const int g = q % f->nrg;
@@ -515,6 +523,12 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
         if (slen == 0 && pg.kind != PAGE_DATA_V2) slen = 0;
       }
       pg.scratch_len = (uint32_t)slen;
+      pg.sblk_begin = (uint32_t)sblk;
+      if (slen) {
+        const uint64_t nb = (slen + SNAP_BLOCK - 1) / SNAP_BLOCK;
+        for (uint64_t j = 0; j < nb; ++j) sblk_page.push_back(p);
+        sblk += nb;
+      }
       if (cd.codec == 1 && (pg.kind != PAGE_DATA_V2 || pg.v2_compressed)) scratch += align_up(slen + SCRATCH_PAD, 16);
       if (pg.kind == PAGE_DICT) {
         dict = p;
@@ -552,6 +566,17 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     d_cs = nullptr;
   };
   if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
+  // Snappy block index, recorded by the decompression below
+  f->total_sblk = sblk;
+  if (sblk) {
+    if (hipMalloc(&f->d_sblk, sizeof(uint32_t) * sblk) != hipSuccess ||
+        hipMalloc(&f->d_sblk_page, sizeof(uint32_t) * sblk) != hipSuccess) {
+      cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: block index allocation");
+    }
+    if (hipMemcpy(f->d_sblk_page, sblk_page.data(), sizeof(uint32_t) * sblk, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup_open(); free_handle(f); return fail(PQ_EHIP, "open: block index upload");
+    }
+  }
   if (scratch > 0) {
     if (hipMalloc(&d_scratch, scratch) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for decompression"); }
     if (hipMalloc(&d_cs, sizeof(ColScan)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
@@ -561,7 +586,8 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     std::vector<Segment> segs{Segment{0, 0, npages, 0}};
     SegTable st2 = make_segs(segs);
     const uint32_t waves = npages;
-    hipLaunchKernelGGL(k_snappy, dim3((waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cs, st2, d_scratch, f->d_err);
+    hipLaunchKernelGGL(k_snappy, dim3(waves), dim3(64), 0, s, file, f->d_pages, d_cs, st2, d_scratch, f->d_sblk, 1,
+                       f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
   }
   if (tiles) {
@@ -655,6 +681,8 @@ struct Plan {
   std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
   std::vector<int32_t> str_cols;    // string ColScan indices
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
+  std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
+  uint32_t sblk_lanes = 0;
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
   std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
@@ -788,6 +816,12 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     if (sbytes) {
       P.snappy_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.snappy_waves});
       P.snappy_waves += cs.page_end - cs.page_begin;
+      const uint32_t b0 = f->pages[cs.page_begin].sblk_begin;
+      const uint32_t b1 = cs.page_end < (uint32_t)f->pages.size() ? f->pages[cs.page_end].sblk_begin : (uint32_t)f->total_sblk;
+      if (b1 > b0) {
+        P.sblk_segs.push_back(Segment{idx, b0, b1, P.sblk_lanes});
+        P.sblk_lanes += b1 - b0;
+      }
     }
     P.cols.push_back(cs);
   }
@@ -813,14 +847,20 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
   if (!P.scan_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.scan_cols.data(), sizeof(int32_t) * P.scan_cols.size(), hipMemcpyHostToDevice, s));
   const uint8_t* file = f->file;
-  for (const auto* v : {&P.snappy_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
+  for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
     if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
   if (P.snappy_waves) {
     if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, KP_SNAPPY, s);
-    hipLaunchKernelGGL(k_snappy, dim3((P.snappy_waves + 3) / 4), dim3(256), 0, s, file, f->d_pages, d_cols,
-                       make_segs(P.snappy_segs), ws, f->d_err);
+    hipLaunchKernelGGL(k_snappy, dim3(P.snappy_waves), dim3(64), 0, s, file, f->d_pages, d_cols,
+                       make_segs(P.snappy_segs), ws, f->d_sblk, 0, f->d_err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.sblk_lanes) {
+    ProfScope ps_(f, KP_SNAPPY_BLK, s);
+    hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 255) / 256), dim3(256), 0, s, file, f->d_pages, d_cols,
+                       make_segs(P.sblk_segs), f->d_sblk, f->d_sblk_page, ws, f->d_err);
     HIP_OR(hipGetLastError());
   }
   for (size_t w0 = 0; w0 < P.dict_work.size(); w0 += MAX_SEGS) {  // MAX_SEGS dictionaries per launch

@@ -117,7 +117,16 @@ struct PageDev {
   int64_t delta_first;
   uint32_t blocks_at;
   uint32_t dict_maxlen;  // dictionary pages of strings: length of the longest entry
+  uint32_t sblk_begin;   // compressed pages: first entry of the page in the Snappy block index
+  uint32_t pad2_;
 };
+// Snappy block index: a compressed page's output is cut into SNAP_BLOCK-byte
+// blocks; entry b holds the stream offset of the element that starts block
+// b.  A page's first entry is SBLK_NONE when some element straddles a block
+// boundary or a copy reaches before its block's start: such a page is
+// decompressed sequentially, the others one block per lane.
+constexpr uint32_t SNAP_BLOCK = 65536;
+constexpr uint32_t SBLK_NONE = 0xffffffffu;
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.
 struct TileDev {

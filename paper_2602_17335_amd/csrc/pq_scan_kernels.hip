@@ -949,18 +949,90 @@ __device__ __forceinline__ void store_chunk_bytes(u32x4 v, gout_u8* dst, uint32_
 
 
 // ---------------------------------------------------------------------------
-// k_snappy: one wave per compressed page
+// k_snappy: one wave per compressed page (a 64-thread workgroup, so that the
+// wave's 64 KiB output history fits beside another in a CU's LDS).
+//
+// The stream is a sequence of elements: literals (bytes copied from the
+// stream) and copies (len bytes from `off` bytes back in the output).  Every
+// element is written into an LDS ring holding the last SNAP_RING output
+// bytes, whose byte j maps to the 16-byte aligned global address G0 + j (mod
+// the ring); the ring is flushed to the page's scratch region as aligned
+// 16-byte chunks.  Copies read their source from the ring (one LDS round
+// trip, no wait on global stores); an offset past the ring reads the
+// flushed output in global memory.  Tags are parsed from a 512-byte window
+// of the stream held in two registers per lane (readlane, no memory
+// latency), prefetched 256 bytes ahead; short literals come from the same
+// window (ds_bpermute), long ones with 16-byte loads straight into the ring.
 // ---------------------------------------------------------------------------
+constexpr uint32_t SNAP_RING = 65536;
+constexpr uint32_t SNAP_MASK = SNAP_RING - 1;
+constexpr uint32_t SNAP_FLUSH = 4096;  // flush when this many bytes are pending
+constexpr uint32_t SNAP_PIECE = 240;   // literal bytes taken from the window per step
 
-// Copies n bytes dst[i] = src[i] with the lanes of one wave (no overlap).
-__device__ __forceinline__ void wave_copy(uint8_t* dst, const uint8_t* src, uint64_t n) {
-  const int lane = threadIdx.x & 63;
-  for (uint64_t i = lane; i < n; i += 64) dst[i] = src[i];
+// Stream staging: stream bytes [lo, lo + SNAP_IN) (offsets from the
+// dword-aligned stream base, lo a multiple of 16) copied into LDS with
+// coalesced 16-byte loads, refilled when the parse comes within SNAP_PIECE +
+// 16 bytes of its end.  Offsets are 32-bit (a page is below 2 GiB).
+constexpr uint32_t SNAP_IN = 2048;
+struct SnapIn {
+  glb_u32* base;  // dword holding stream byte 0 (minus m bytes)
+  uint32_t lim;   // dwords at byte offsets >= lim are not loaded (stream end)
+  uint32_t lo, hi;
+  lds_u32* buf;
+  __device__ __forceinline__ void fill(uint32_t a) {
+    lo = a & ~15u;
+    hi = lo + SNAP_IN;
+    const uint32_t lane = threadIdx.x & 63;
+    u32x4 v[SNAP_IN / 1024];
+#pragma unroll
+    for (int u = 0; u < (int)(SNAP_IN / 1024); ++u) {
+      const uint32_t x = lo + 1024 * u + 16 * lane;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[u][kk] = x + 4 * kk < lim ? base[(x >> 2) + kk] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < (int)(SNAP_IN / 1024); ++u)
+      *reinterpret_cast<__attribute__((address_space(3))) u32x4*>(buf + 256 * u + 4 * lane) = v[u];
+    wave_sync();
+  }
+  // stage offset of stream byte a, with at least SNAP_PIECE + 16 bytes after it staged
+  __device__ __forceinline__ uint32_t at(uint32_t a) {
+    if (a < lo || a + SNAP_PIECE + 16 > hi) fill(a);
+    return a - lo;
+  }
+  // staged bytes o .. o+4 (wave-uniform), low 5 bytes valid
+  __device__ __forceinline__ uint64_t bytes8(uint32_t o) const {
+    const uint32_t j = o >> 2;
+    return ((uint64_t)buf[j + 1] << 32 | buf[j]) >> (8 * (o & 3));
+  }
+};
+
+// Stores ring chunks [c0, c1) (16 bytes each) to g0 + 16 c: bytes [lo, hi) of
+// the ring space are the page's; chunks holding others are stored bytewise.
+__device__ __forceinline__ void snap_flush(const lds_u8* ring, uint8_t* g0, uint32_t c0, uint32_t c1, uint32_t lo,
+                                           uint32_t hi) {
+  typedef __attribute__((address_space(3))) const u32x4 lds_cv4;
+  for (uint32_t c = c0 + (threadIdx.x & 63); c < c1; c += 64) {
+    const u32x4 v = *reinterpret_cast<lds_cv4*>(ring + ((16 * c) & SNAP_MASK));
+    const uint32_t b0 = 16 * c, b1 = b0 + 16;
+    if (b0 >= lo && b1 <= hi) {
+      *(gout_u32x4*)(g0 + b0) = v;
+    } else {
+      const uint32_t ow[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (b0 + i >= lo && b0 + i < hi) g0[b0 + i] = (uint8_t)(ow[i >> 2] >> (8 * (i & 3)));
+    }
+  }
 }
 
-__global__ __launch_bounds__(WG) void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols,
-                                               SegTable seg, uint8_t* ws, uint32_t* err) {
-  const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;
+__global__ __launch_bounds__(64) void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols,
+                                               SegTable seg, uint8_t* ws, uint32_t* sblk, int record,
+                                               uint32_t* err) {
+  __shared__ __align__(16) uint8_t s_ring[SNAP_RING];
+  __shared__ __align__(16) uint32_t s_in[SNAP_IN / 4 + 4];
+  const uint32_t gw = blockIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
   int k = 0;
   for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gw) k = j;
   const uint32_t csi = seg.s[k].cs;
@@ -969,77 +1041,307 @@ __global__ __launch_bounds__(WG) void k_snappy(const uint8_t* file, const PageDe
   const ColScan cs = cols[csi];
   const PageDev pg = pages[p];
   if (pg.scratch_len == 0) return;
-  uint64_t src_off = pg.payload, src_len = pg.comp_size;
-  if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
+  if (!record && sblk[pg.sblk_begin] != SBLK_NONE) return;  // k_snappy_blk decodes it
+  uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
+  if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
   const uint8_t* src = file + src_off;
   uint8_t* dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
-  volatile uint8_t* vdst = dst;
-  const uint64_t total = pg.scratch_len;
-  uint64_t pos = 0, op = 0;
-  bool bad = false;
-  // stream length
-  {
+  lds_u8* ring = (lds_u8*)&s_ring[0];
+  const uint32_t total = pg.scratch_len;
+  // stream byte i is byte m + i of the dword-aligned base; ring-space byte
+  // s0 + o holds output byte o, at global address g0 + s0 + o
+  const uint32_t m = (uint32_t)((uintptr_t)src & 3);
+  const uint32_t s0 = (uint32_t)((uintptr_t)dst & 15);
+  uint8_t* g0 = dst - s0;
+  SnapIn in;
+  in.base = (glb_u32*)(src - m);
+  const uint32_t iend = m + (uint32_t)src_len64;  // stream bytes are [m, iend) from the base
+  in.lim = iend;
+  in.buf = (lds_u32*)&s_in[0];
+  uint32_t ip = m;
+  in.fill(ip);
+  uint32_t op = 0, fc = 0;  // output bytes produced; ring-space chunks flushed
+  bool bad = src_len64 >= 0x7fffffffull;
+  {  // stream length (varint)
     uint64_t v = 0;
-    int s = 0;
+    int sft = 0;
     for (;;) {
-      if (pos >= src_len || s > 28) { bad = true; break; }
-      uint32_t b = src[pos++];
-      v |= (uint64_t)(b & 0x7f) << s;
+      if (bad || ip >= iend || sft > 28) { bad = true; break; }
+      const uint32_t b = (uint32_t)in.bytes8(in.at(ip++)) & 0xffu;
+      v |= (uint64_t)(b & 0x7f) << sft;
       if (!(b & 0x80)) break;
-      s += 7;
+      sft += 7;
     }
     if (!bad && v != total) bad = true;
   }
-  while (!bad && pos < src_len) {
-    const uint32_t t = src[pos++];
-    uint64_t len, off = 0;
-    if ((t & 3) == 0) {
-      uint64_t l = t >> 2;
+  bool blk_ok = true;  // every block boundary starts an element and no copy leaves its block
+  if (record && lane == 0) sblk[pg.sblk_begin] = ip - m;
+  while (!bad && ip < iend) {
+    const uint32_t o = in.at(ip);
+    const uint64_t x = in.bytes8(o);
+    const uint32_t t = (uint32_t)x & 0xffu;
+    const uint32_t R = s0 + op;  // ring-space position of the element's first byte
+    if (record && op && (op & (SNAP_BLOCK - 1)) == 0 && lane == 0) sblk[pg.sblk_begin + op / SNAP_BLOCK] = ip - m;
+    if ((t & 3) == 0) {  // literal
+      uint32_t l = t >> 2, hl = 1;
       if (l >= 60) {
-        const uint32_t nb = (uint32_t)l - 59;
-        if (pos + nb > src_len) { bad = true; break; }
-        l = 0;
-        for (uint32_t k = 0; k < nb; ++k) l |= (uint64_t)src[pos + k] << (8 * k);
-        pos += nb;
+        const uint32_t nb = l - 59;
+        l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
+        hl += nb;
       }
-      len = l + 1;
-      if (len > src_len - pos || len > total - op) { bad = true; break; }
-      wave_copy(dst + op, src + pos, len);
-      pos += len;
+      const uint64_t L64 = (uint64_t)l + 1;
+      if ((uint64_t)ip + hl + L64 > iend || L64 > total - op) { bad = true; break; }
+      const uint32_t L = (uint32_t)L64;
+      ip += hl;
+      if (L <= SNAP_PIECE) {
+        // from the window: lane q writes ring dword (R - d) / 4 + q, literal
+        // bytes [4 q - d, 4 q - d + 4)
+        const uint32_t ow = in.at(ip);
+        const uint32_t d = R & 3;
+        // stage byte of the dword's first byte (ow >= 3 unless the stage
+        // starts at the literal; a negative byte is masked below)
+        const int32_t so = (int32_t)ow + 4 * (int32_t)lane - (int32_t)d;
+        const int32_t j0 = max(so, 0) >> 2;
+        const uint32_t x0 = in.buf[j0], x1 = in.buf[j0 + 1];
+        const uint32_t w = so < 0 ? x0 << (8 * (uint32_t)(-so)) : __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)so & 3u);
+        const int32_t b0 = 4 * (int32_t)lane - (int32_t)d;
+        const uint32_t ra = R - d + 4 * lane;
+        if (b0 >= 0 && b0 + 4 <= (int32_t)L) {
+          *reinterpret_cast<lds_u32*>(ring + (ra & SNAP_MASK)) = w;
+        } else if (b0 + 4 > 0 && b0 < (int32_t)L) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (b0 + i >= 0 && b0 + i < (int32_t)L) ring[(ra + i) & SNAP_MASK] = (uint8_t)(w >> (8 * i));
+        }
+      } else {
+        // 16-byte loads straight into the ring: chunk c covers ring space
+        // [Ra + 16 c, + 16); the literal's first and last chunks are written
+        // bytewise (they share bytes with the neighbouring elements)
+        const uint32_t Ra = R & ~15u, Rend = R + L;
+        const uint32_t nch = (Rend - Ra + 15) >> 4;
+        const uint32_t lo4 = ip & ~3u;
+        for (uint32_t c0 = 0; c0 < nch; c0 += 256) {
+          uint32_t wv[4][5];
+          uint32_t sh[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t c = c0 + 64 * u + lane;
+            const uint32_t sa = ip - (R - Ra) + 16 * c;  // stream byte (from the base) of the chunk's first byte
+            sh[u] = sa & 3;
+#pragma unroll
+            for (int kk = 0; kk < 5; ++kk) {
+              const uint32_t xo = (sa & ~3u) + 4 * kk;
+              wv[u][kk] = (c < nch && xo >= lo4 && xo < iend) ? in.base[xo >> 2] : 0u;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t c = c0 + 64 * u + lane;
+            if (c >= nch) continue;
+            u32x4 v;
+            v.x = __builtin_amdgcn_alignbyte(wv[u][1], wv[u][0], sh[u]);
+            v.y = __builtin_amdgcn_alignbyte(wv[u][2], wv[u][1], sh[u]);
+            v.z = __builtin_amdgcn_alignbyte(wv[u][3], wv[u][2], sh[u]);
+            v.w = __builtin_amdgcn_alignbyte(wv[u][4], wv[u][3], sh[u]);
+            const uint32_t b0 = Ra + 16 * c;
+            if (b0 >= R && b0 + 16 <= Rend) {
+              *reinterpret_cast<__attribute__((address_space(3))) u32x4*>(ring + (b0 & SNAP_MASK)) = v;
+            } else {
+              const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+              for (int i = 0; i < 16; ++i)
+                if (b0 + i >= R && b0 + i < Rend) ring[(b0 + i) & SNAP_MASK] = (uint8_t)(vw[i >> 2] >> (8 * (i & 3)));
+            }
+          }
+          // a long literal must not overrun the unflushed part of the ring
+          if (c0 + 256 < nch) {
+            wave_sync();
+            const uint32_t upto = (Ra >> 4) + c0 + 256;
+            if (upto > fc) {
+              snap_flush(ring, g0, fc, upto, s0, s0 + total);
+              fc = upto;
+            }
+          }
+        }
+      }
+      if (op / SNAP_BLOCK != (op + L - 1) / SNAP_BLOCK) blk_ok = false;
+      ip += L;
+      op += L;
+    } else {  // copy
+      uint32_t len, off, hl;
+      if ((t & 3) == 1) {
+        hl = 2;
+        len = 4 + ((t >> 2) & 7);
+        off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
+      } else if ((t & 3) == 2) {
+        hl = 3;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8) & 0xffffu;
+      } else {
+        hl = 5;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8);
+      }
+      if (ip + hl > iend || off == 0 || off > op || len > total - op) { bad = true; break; }
+      ip += hl;
+      // source byte of lane q: R - off + q, repeating with period off when
+      // the copy overlaps its own output
+      const uint32_t q = lane < len ? lane : 0u;
+      uint32_t sidx;
+      if (off >= len) sidx = R - off + q;
+      else sidx = R - off + q % off;
+      uint32_t b;
+      if (off <= SNAP_RING) {
+        b = ring[sidx & SNAP_MASK];
+      } else {  // past the ring: from the flushed output
+        __builtin_amdgcn_s_waitcnt(0);
+        __threadfence_block();
+        b = reinterpret_cast<volatile const uint8_t*>(g0)[sidx];
+      }
+      if (lane < len) ring[(R + lane) & SNAP_MASK] = (uint8_t)b;
+      if (op / SNAP_BLOCK != (op + len - 1) / SNAP_BLOCK || off > op % SNAP_BLOCK) blk_ok = false;
       op += len;
-      continue;
     }
-    if ((t & 3) == 1) {
-      if (pos + 1 > src_len) { bad = true; break; }
-      len = 4 + ((t >> 2) & 7);
-      off = ((uint64_t)(t >> 5) << 8) | src[pos];
-      pos += 1;
-    } else if ((t & 3) == 2) {
-      if (pos + 2 > src_len) { bad = true; break; }
-      len = (t >> 2) + 1;
-      off = (uint64_t)src[pos] | ((uint64_t)src[pos + 1] << 8);
-      pos += 2;
-    } else {
-      if (pos + 4 > src_len) { bad = true; break; }
-      len = (t >> 2) + 1;
-      off = (uint64_t)src[pos] | ((uint64_t)src[pos + 1] << 8) | ((uint64_t)src[pos + 2] << 16) | ((uint64_t)src[pos + 3] << 24);
-      pos += 4;
+    const uint32_t full = (s0 + op) >> 4;
+    if (full - fc >= SNAP_FLUSH / 16) {
+      wave_sync();
+      snap_flush(ring, g0, fc, full, s0, s0 + total);
+      fc = full;
     }
-    if (off == 0 || off > op || len > total - op) { bad = true; break; }
-    // make this wave's earlier stores visible to its own L1-bypassing reads
-    __builtin_amdgcn_s_waitcnt(0);
-    __threadfence_block();
-    const int lane = threadIdx.x & 63;
-    for (uint64_t i = lane; i < len; i += 64) {
-      // source byte op + i - off, repeating with period `off` when overlapping
-      const uint64_t s = off >= len ? op + i - off : op - off + (i % off);
-      vdst[op + i] = vdst[s];
-    }
-    op += len;
   }
   if (!bad && op != total) bad = true;
-  if (bad && (threadIdx.x & 63) == 0) set_err(err, ERR_SNAPPY, p);
+  if (!bad) {
+    wave_sync();
+    snap_flush(ring, g0, fc, (s0 + op + 15) >> 4, s0, s0 + op);
+  }
+  if (record && (bad || !blk_ok) && lane == 0) sblk[pg.sblk_begin] = SBLK_NONE;
+  if (bad && lane == 0) set_err(err, ERR_SNAPPY, p);
 }
+
+// One lane copies n bytes src -> dst (no overlap): bytes up to dst's next
+// dword boundary, then 32 bytes per step (the source realigned from aligned
+// dwords with byte funnel shifts, all nine loads before the stores), then the
+// tail.  Reads at most 3 bytes before and 7 after the source range.
+__device__ __forceinline__ void lane_copy(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  const uint32_t h = min(n, (uint32_t)((4 - ((uintptr_t)dst & 3)) & 3));
+  for (uint32_t i = 0; i < h; ++i) dst[i] = src[i];
+  dst += h;
+  src += h;
+  n -= h;
+  const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
+  glb_u32* q = (glb_u32*)((uintptr_t)src & ~(uintptr_t)3);
+  __attribute__((address_space(1))) uint32_t* d = (__attribute__((address_space(1))) uint32_t*)dst;
+  uint32_t i = 0;
+  for (; i + 32 <= n; i += 32) {
+    uint32_t w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = q[i / 4 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[i / 4 + k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+  }
+  for (; i + 4 <= n; i += 4) d[i / 4] = __builtin_amdgcn_alignbyte(q[i / 4 + 1], q[i / 4], sh);
+  for (; i < n; ++i) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// k_snappy_blk: the pages of the Snappy block index, one lane per 64 KiB
+// output block (a lane decodes its block's elements in order; 64 blocks of
+// one or several pages advance together in a wave).  Copies read their
+// source from the block's own output in global memory after this lane's
+// earlier stores have completed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols,
+                                                   SegTable seg, const uint32_t* sblk, const uint32_t* sblk_page,
+                                                   uint8_t* ws, uint32_t* err) {
+  const uint32_t gid = blockIdx.x * WG + threadIdx.x;
+  int k = 0;
+  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
+  const uint32_t b = seg.s[k].t0 + (gid - seg.s[k].wg0);
+  if (b >= seg.s[k].t1) return;
+  const uint32_t p = sblk_page[b];
+  const PageDev pg = pages[p];
+  if (pg.scratch_len == 0) return;
+  const uint32_t first = pg.sblk_begin;
+  if (sblk[first] == SBLK_NONE) return;  // decoded sequentially by k_snappy
+  const ColScan cs = cols[seg.s[k].cs];
+  uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
+  if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
+  const uint8_t* src = file + src_off;
+  uint8_t* dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
+  const uint32_t total = pg.scratch_len;
+  const uint32_t src_len = (uint32_t)src_len64;
+  const uint32_t kb = b - first, nblk = (total + SNAP_BLOCK - 1) / SNAP_BLOCK;
+  uint32_t ip = sblk[b];
+  const uint32_t iend = kb + 1 < nblk ? sblk[b + 1] : src_len;
+  const uint32_t ob = kb * SNAP_BLOCK;  // the block's first output byte
+  uint32_t op = ob;
+  const uint32_t oend = min(ob + SNAP_BLOCK, total);
+  bool bad = src_len64 >= 0x7fffffffull || ip > iend || iend > src_len;
+  while (!bad && op < oend) {
+    if (ip >= iend) { bad = true; break; }
+    // bytes ip .. ip+4 of the stream
+    const uintptr_t a = (uintptr_t)(src + ip);
+    glb_u32* q = (glb_u32*)(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3);
+    const uint32_t q0 = q[0], q1 = q[1], q2 = q[2];
+    const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(q1, q0, sh) |
+                       ((uint64_t)__builtin_amdgcn_alignbyte(q2, q1, sh) << 32);
+    const uint32_t t = (uint32_t)x & 0xffu;
+    if ((t & 3) == 0) {  // literal
+      uint32_t l = t >> 2, hl = 1;
+      if (l >= 60) {
+        const uint32_t nb = l - 59;
+        l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
+        hl += nb;
+      }
+      const uint64_t L = (uint64_t)l + 1;
+      if ((uint64_t)ip + hl + L > iend || L > oend - op) { bad = true; break; }
+      lane_copy(dst + op, src + ip + hl, (uint32_t)L);
+      ip += hl + (uint32_t)L;
+      op += (uint32_t)L;
+    } else {  // copy
+      uint32_t len, off, hl;
+      if ((t & 3) == 1) {
+        hl = 2;
+        len = 4 + ((t >> 2) & 7);
+        off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
+      } else if ((t & 3) == 2) {
+        hl = 3;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8) & 0xffffu;
+      } else {
+        hl = 5;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8);
+      }
+      if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
+      // this lane's earlier stores reach memory before it reads them back
+      // (device-scope loads, served by L2 rather than a stale L1 line)
+      __builtin_amdgcn_s_waitcnt(0);
+      const uintptr_t cs_ = (uintptr_t)(dst + op - off);
+      for (uint32_t k0 = 0; k0 < len; k0 += 8) {
+        uint32_t r = off >= len ? k0 : k0 % off;  // source byte of output byte k0
+        uint32_t bb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uintptr_t sa = cs_ + r;
+          const uint32_t w = __hip_atomic_load(reinterpret_cast<uint32_t*>(sa & ~(uintptr_t)3), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          bb[j] = (w >> (8 * (uint32_t)(sa & 3))) & 0xffu;
+          r = r + 1 == off ? 0u : r + 1;  // period off when the copy overlaps its output
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
+      }
+      ip += hl;
+      op += len;
+    }
+  }
+  if (!bad && (op != oend || ip != iend)) bad = true;
+  if (bad) set_err(err, ERR_SNAPPY, p);
+}
+
 
 // ---------------------------------------------------------------------------
 // k_prep: validity words shared by two tiles are cleared before any tile

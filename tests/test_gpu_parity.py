@@ -29,6 +29,12 @@ def _spec_cases():
     s.page_version = 2
     s.dict_cap = 32 * dg.KiB
     cases["wide_snappy_v2_fallback"] = s
+    # literal-only Snappy streams: one literal spans every 64 KiB output block
+    # of a 256 KiB page, so the pages are decompressed sequentially (no
+    # block index), beside the block-parallel path of the other files
+    lit = dg.snappy_wide_table(120_000, 120_000, 256 * dg.KiB)
+    lit.snappy_literal_only = True
+    cases["wide_snappy_literal_only"] = lit
     cases["edge"] = dg.FileSpec(cols=[
         dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 1.0),
         dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.CONST, 0.3, lo=-5),
