@@ -1218,29 +1218,50 @@ __global__ __launch_bounds__(64) void k_snappy(const uint8_t* file, const PageDe
   if (bad && lane == 0) set_err(err, ERR_SNAPPY, p);
 }
 
-// One lane copies n bytes src -> dst (no overlap): bytes up to dst's next
-// dword boundary, then 32 bytes per step (the source realigned from aligned
-// dwords with byte funnel shifts, all nine loads before the stores), then the
-// tail.  Reads at most 3 bytes before and 7 after the source range.
-__device__ __forceinline__ void lane_copy(uint8_t* dst, const uint8_t* src, uint32_t n) {
-  const uint32_t h = min(n, (uint32_t)((4 - ((uintptr_t)dst & 3)) & 3));
-  for (uint32_t i = 0; i < h; ++i) dst[i] = src[i];
-  dst += h;
-  src += h;
-  n -= h;
-  const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
+// One lane copies n <= 64 bytes src -> dst (no overlap) with one round of
+// loads: the (at most 17) aligned source dwords are loaded together, then
+// destination dword j (dword-aligned) gets bytes [4 j - d, 4 j - d + 4) of
+// the run, realigned with byte funnel shifts; the two edge dwords are
+// written bytewise.  Reads at most 3 bytes before and 4 after the range.
+// The source may be this lane's own earlier output: a lane's loads see its
+// earlier stores (program order), so no wait is needed.
+__device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  const uint32_t sh = (uint32_t)((uintptr_t)src & 3), d = (uint32_t)((uintptr_t)dst & 3);
   glb_u32* q = (glb_u32*)((uintptr_t)src & ~(uintptr_t)3);
-  __attribute__((address_space(1))) uint32_t* d = (__attribute__((address_space(1))) uint32_t*)dst;
-  uint32_t i = 0;
-  for (; i + 32 <= n; i += 32) {
-    uint32_t w[9];
+  const uint32_t nq = (sh + n + 3) >> 2;  // source dwords, <= 17
+  uint32_t w[18];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) w[k] = q[i / 4 + k];
+  for (int k = 0; k < 17; ++k) w[k] = (uint32_t)k < nq ? q[k] : 0u;
+  w[17] = 0u;
+  // byte r of the run is byte sh + r of w; destination byte (4 j + i) holds
+  // run byte 4 j + i - d, i.e. w byte 4 j + i + (sh - d)
+  const int32_t e = (int32_t)sh - (int32_t)d;  // -3 .. 3
+  const uint32_t fs = (uint32_t)e & 3u;
+  const int32_t fb = e >> 2;  // -1 or 0: dword of w holding the word's first byte, relative to j
+  __attribute__((address_space(1))) uint32_t* dw =
+      (__attribute__((address_space(1))) uint32_t*)((uintptr_t)dst & ~(uintptr_t)3);
+  const uint32_t nd = (d + n + 3) >> 2;  // destination dwords, <= 17
 #pragma unroll
-    for (int k = 0; k < 8; ++k) d[i / 4 + k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+  for (int j = 0; j < 17; ++j) {
+    const uint32_t lo = fb < 0 ? (j > 0 ? w[j - 1] : 0u) : w[j];
+    const uint32_t hi = fb < 0 ? w[j] : w[j + 1];
+    const uint32_t word = __builtin_amdgcn_alignbyte(hi, lo, fs);
+    const int32_t b0 = 4 * j - (int32_t)d;  // run byte of the word's byte 0
+    if ((uint32_t)j >= nd) {
+    } else if (b0 >= 0 && b0 + 4 <= (int32_t)n) {
+      dw[j] = word;
+    } else {
+      uint8_t* bp = (uint8_t*)(dw + j);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (b0 + i >= 0 && b0 + i < (int32_t)n) bp[i] = (uint8_t)(word >> (8 * i));
+    }
   }
-  for (; i + 4 <= n; i += 4) d[i / 4] = __builtin_amdgcn_alignbyte(q[i / 4 + 1], q[i / 4], sh);
-  for (; i < n; ++i) dst[i] = src[i];
+}
+
+// n bytes, 64 per step (each step one round of loads)
+__device__ __forceinline__ void lane_copy(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  for (uint32_t i = 0; i < n; i += 64) lane_copy64(dst + i, src + i, min(64u, n - i));
 }
 
 // ---------------------------------------------------------------------------
@@ -1315,24 +1336,21 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
         off = (uint32_t)(x >> 8);
       }
       if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
-      // this lane's earlier stores reach memory before it reads them back
-      // (device-scope loads, served by L2 rather than a stale L1 line)
-      __builtin_amdgcn_s_waitcnt(0);
-      const uintptr_t cs_ = (uintptr_t)(dst + op - off);
-      for (uint32_t k0 = 0; k0 < len; k0 += 8) {
-        uint32_t r = off >= len ? k0 : k0 % off;  // source byte of output byte k0
-        uint32_t bb[8];
+      if (off >= len) {
+        lane_copy64(dst + op, dst + op - off, len);  // reads this lane's earlier output
+      } else {  // the copy overlaps its output: bytes repeat with period off
+        for (uint32_t k0 = 0; k0 < len; k0 += 8) {
+          uint32_t r = k0 % off;
+          uint32_t bb[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uintptr_t sa = cs_ + r;
-          const uint32_t w = __hip_atomic_load(reinterpret_cast<uint32_t*>(sa & ~(uintptr_t)3), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          bb[j] = (w >> (8 * (uint32_t)(sa & 3))) & 0xffu;
-          r = r + 1 == off ? 0u : r + 1;  // period off when the copy overlaps its output
+          for (int j = 0; j < 8; ++j) {
+            bb[j] = dst[op - off + r];
+            r = r + 1 == off ? 0u : r + 1;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
         }
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
       }
       ip += hl;
       op += len;
