@@ -1219,42 +1219,66 @@ __global__ __launch_bounds__(64) void k_snappy(const uint8_t* file, const PageDe
 }
 
 // One lane copies n <= 64 bytes src -> dst (no overlap) with one round of
-// loads: the (at most 17) aligned source dwords are loaded together, then
-// destination dword j (dword-aligned) gets bytes [4 j - d, 4 j - d + 4) of
-// the run, realigned with byte funnel shifts; the two edge dwords are
-// written bytewise.  Reads at most 3 bytes before and 4 after the range.
-// The source may be this lane's own earlier output: a lane's loads see its
-// earlier stores (program order), so no wait is needed.
+// loads: five 16-byte loads from the source's dword (16-byte loads need only
+// dword alignment) give the run, destination dword j (dword-aligned) gets
+// bytes [4 j - d, 4 j - d + 4) of it, realigned with byte funnel shifts, and
+// is stored four dwords at a time; the two edge dwords are written bytewise.
+// Reads at most 3 bytes before and 16 after the range.  The source may be
+// this lane's own earlier output: a lane's loads see its earlier stores
+// (program order), so no wait is needed.
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
 __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, uint32_t n) {
   const uint32_t sh = (uint32_t)((uintptr_t)src & 3), d = (uint32_t)((uintptr_t)dst & 3);
-  glb_u32* q = (glb_u32*)((uintptr_t)src & ~(uintptr_t)3);
+  const __attribute__((address_space(1))) u32x4a* q =
+      (const __attribute__((address_space(1))) u32x4a*)((uintptr_t)src & ~(uintptr_t)3);
   const uint32_t nq = (sh + n + 3) >> 2;  // source dwords, <= 17
-  uint32_t w[18];
+  uint32_t w[21];
 #pragma unroll
-  for (int k = 0; k < 17; ++k) w[k] = (uint32_t)k < nq ? q[k] : 0u;
-  w[17] = 0u;
-  // byte r of the run is byte sh + r of w; destination byte (4 j + i) holds
-  // run byte 4 j + i - d, i.e. w byte 4 j + i + (sh - d)
+  for (int c = 0; c < 5; ++c) {
+    u32x4a x = {0u, 0u, 0u, 0u};
+    if ((uint32_t)(4 * c) < nq) x = q[c];
+    w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
+  }
+  w[20] = 0u;
+  // destination byte 4 j + i holds run byte 4 j + i - d = w byte 4 j + i + (sh - d)
   const int32_t e = (int32_t)sh - (int32_t)d;  // -3 .. 3
   const uint32_t fs = (uint32_t)e & 3u;
-  const int32_t fb = e >> 2;  // -1 or 0: dword of w holding the word's first byte, relative to j
+  const bool back = e < 0;  // the word's first byte is in w[j - 1]
   __attribute__((address_space(1))) uint32_t* dw =
       (__attribute__((address_space(1))) uint32_t*)((uintptr_t)dst & ~(uintptr_t)3);
   const uint32_t nd = (d + n + 3) >> 2;  // destination dwords, <= 17
+  uint32_t o[17];
 #pragma unroll
   for (int j = 0; j < 17; ++j) {
-    const uint32_t lo = fb < 0 ? (j > 0 ? w[j - 1] : 0u) : w[j];
-    const uint32_t hi = fb < 0 ? w[j] : w[j + 1];
-    const uint32_t word = __builtin_amdgcn_alignbyte(hi, lo, fs);
-    const int32_t b0 = 4 * j - (int32_t)d;  // run byte of the word's byte 0
-    if ((uint32_t)j >= nd) {
-    } else if (b0 >= 0 && b0 + 4 <= (int32_t)n) {
-      dw[j] = word;
-    } else {
-      uint8_t* bp = (uint8_t*)(dw + j);
+    const uint32_t lo = back ? (j > 0 ? w[j - 1] : 0u) : w[j];
+    const uint32_t hi = back ? w[j] : w[j + 1];
+    o[j] = __builtin_amdgcn_alignbyte(hi, lo, fs);
+  }
+  // whole dwords: j in [j0, j1); edges bytewise
+  const uint32_t j0 = d ? 1u : 0u;
+  const uint32_t j1 = (d + n) >> 2;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (b0 + i >= 0 && b0 + i < (int32_t)n) bp[i] = (uint8_t)(word >> (8 * i));
+  for (int c = 0; c < 5; ++c) {
+    const uint32_t jb = 4 * c;
+    if (jb >= j0 && jb + 4 <= j1) {
+      u32x4a v;
+      v.x = o[jb]; v.y = o[jb + 1]; v.z = o[jb + 2]; v.w = o[jb + 3];
+      *(__attribute__((address_space(1))) u32x4a*)(dw + jb) = v;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t j = jb + t;
+        if (j >= 17) continue;
+        if (j >= j0 && j < j1) {
+          dw[j] = o[j];
+        } else if (j < nd) {
+          const int32_t b0 = 4 * (int32_t)j - (int32_t)d;
+          uint8_t* bp = (uint8_t*)(dw + j);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (b0 + i >= 0 && b0 + i < (int32_t)n) bp[i] = (uint8_t)(o[j] >> (8 * i));
+        }
+      }
     }
   }
 }
@@ -1298,30 +1322,33 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
   uint32_t op = ob;
   const uint32_t oend = min(ob + SNAP_BLOCK, total);
   bool bad = src_len64 >= 0x7fffffffull || ip > iend || iend > src_len;
+  // the 16 stream bytes from the dword holding byte ip: loaded one element
+  // ahead (the next element's position is known once its tag is decoded), so
+  // its latency overlaps the current element's loads and stores
+  typedef const __attribute__((address_space(1))) u32x4a* gq4;
+  u32x4a qv = {0u, 0u, 0u, 0u};
+  if (!bad && ip < iend) qv = *(gq4)((uintptr_t)(src + ip) & ~(uintptr_t)3);
   while (!bad && op < oend) {
     if (ip >= iend) { bad = true; break; }
-    // bytes ip .. ip+4 of the stream
-    const uintptr_t a = (uintptr_t)(src + ip);
-    glb_u32* q = (glb_u32*)(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3);
-    const uint32_t q0 = q[0], q1 = q[1], q2 = q[2];
-    const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(q1, q0, sh) |
-                       ((uint64_t)__builtin_amdgcn_alignbyte(q2, q1, sh) << 32);
+    const uint32_t sh = (uint32_t)((uintptr_t)(src + ip) & 3);
+    const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(qv.y, qv.x, sh) |
+                       ((uint64_t)__builtin_amdgcn_alignbyte(qv.z, qv.y, sh) << 32);
     const uint32_t t = (uint32_t)x & 0xffu;
-    if ((t & 3) == 0) {  // literal
-      uint32_t l = t >> 2, hl = 1;
+    uint32_t nip, len = 0, off = 0, hl;
+    uint64_t L = 0;
+    const bool lit = (t & 3) == 0;
+    if (lit) {
+      uint32_t l = t >> 2;
+      hl = 1;
       if (l >= 60) {
         const uint32_t nb = l - 59;
         l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
         hl += nb;
       }
-      const uint64_t L = (uint64_t)l + 1;
+      L = (uint64_t)l + 1;
       if ((uint64_t)ip + hl + L > iend || L > oend - op) { bad = true; break; }
-      lane_copy(dst + op, src + ip + hl, (uint32_t)L);
-      ip += hl + (uint32_t)L;
-      op += (uint32_t)L;
-    } else {  // copy
-      uint32_t len, off, hl;
+      nip = ip + hl + (uint32_t)L;
+    } else {
       if ((t & 3) == 1) {
         hl = 2;
         len = 4 + ((t >> 2) & 7);
@@ -1336,6 +1363,13 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
         off = (uint32_t)(x >> 8);
       }
       if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
+      nip = ip + hl;
+    }
+    if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
+    if (lit) {
+      lane_copy(dst + op, src + ip + hl, (uint32_t)L);
+      op += (uint32_t)L;
+    } else {
       if (off >= len) {
         lane_copy64(dst + op, dst + op - off, len);  // reads this lane's earlier output
       } else {  // the copy overlaps its output: bytes repeat with period off
@@ -1352,9 +1386,9 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
             if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
         }
       }
-      ip += hl;
       op += len;
     }
+    ip = nip;
   }
   if (!bad && (op != oend || ip != iend)) bad = true;
   if (bad) set_err(err, ERR_SNAPPY, p);
