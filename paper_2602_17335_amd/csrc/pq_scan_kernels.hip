@@ -1220,12 +1220,15 @@ __global__ __launch_bounds__(64) void k_snappy(const uint8_t* file, const PageDe
 
 // One lane copies n <= 64 bytes src -> dst (no overlap) with one round of
 // loads: five 16-byte loads from the source's dword (16-byte loads need only
-// dword alignment) give the run, destination dword j (dword-aligned) gets
-// bytes [4 j - d, 4 j - d + 4) of it, realigned with byte funnel shifts, and
-// is stored four dwords at a time; the two edge dwords are written bytewise.
-// Reads at most 3 bytes before and 16 after the range.  The source may be
-// this lane's own earlier output: a lane's loads see its earlier stores
-// (program order), so no wait is needed.
+// dword alignment) give the run, and destination dword j (dword-aligned)
+// gets bytes [4 j - d, 4 j - d + 4) of it, realigned with byte funnel
+// shifts.  The lane writes its block front to back, so the bytes before the
+// run (the head of dword 0) are kept, written bytewise, while the at most 3
+// bytes after the run's last dword are left for the next element to
+// overwrite (a block ends on a 16-byte boundary, a page inside its scratch
+// padding).  Reads at most 3 bytes before and 16 after the range.  The
+// source may be this lane's own earlier output: a lane's loads see its
+// earlier stores (program order), so no wait is needed.
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
 __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, uint32_t n) {
   const uint32_t sh = (uint32_t)((uintptr_t)src & 3), d = (uint32_t)((uintptr_t)dst & 3);
@@ -1247,38 +1250,18 @@ __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, ui
   __attribute__((address_space(1))) uint32_t* dw =
       (__attribute__((address_space(1))) uint32_t*)((uintptr_t)dst & ~(uintptr_t)3);
   const uint32_t nd = (d + n + 3) >> 2;  // destination dwords, <= 17
-  uint32_t o[17];
 #pragma unroll
   for (int j = 0; j < 17; ++j) {
     const uint32_t lo = back ? (j > 0 ? w[j - 1] : 0u) : w[j];
     const uint32_t hi = back ? w[j] : w[j + 1];
-    o[j] = __builtin_amdgcn_alignbyte(hi, lo, fs);
-  }
-  // whole dwords: j in [j0, j1); edges bytewise
-  const uint32_t j0 = d ? 1u : 0u;
-  const uint32_t j1 = (d + n) >> 2;
+    const uint32_t o = __builtin_amdgcn_alignbyte(hi, lo, fs);
+    if (j == 0 && d) {
+      uint8_t* bp = (uint8_t*)dw;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const uint32_t jb = 4 * c;
-    if (jb >= j0 && jb + 4 <= j1) {
-      u32x4a v;
-      v.x = o[jb]; v.y = o[jb + 1]; v.z = o[jb + 2]; v.w = o[jb + 3];
-      *(__attribute__((address_space(1))) u32x4a*)(dw + jb) = v;
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const uint32_t j = jb + t;
-        if (j >= 17) continue;
-        if (j >= j0 && j < j1) {
-          dw[j] = o[j];
-        } else if (j < nd) {
-          const int32_t b0 = 4 * (int32_t)j - (int32_t)d;
-          uint8_t* bp = (uint8_t*)(dw + j);
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (b0 + i >= 0 && b0 + i < (int32_t)n) bp[i] = (uint8_t)(o[j] >> (8 * i));
-        }
-      }
+      for (int i = 1; i < 4; ++i)
+        if ((uint32_t)i >= d && (uint32_t)i - d < n) bp[i] = (uint8_t)(o >> (8 * i));
+    } else if ((uint32_t)j < nd) {
+      dw[j] = o;
     }
   }
 }
@@ -1366,13 +1349,15 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
       nip = ip + hl;
     }
     if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
+    // one copy routine for a literal's first 64 bytes and for a copy that
+    // does not overlap its output (which reads this lane's earlier output)
+    if (lit || off >= len)
+      lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)min(L, (uint64_t)64) : len);
     if (lit) {
-      lane_copy(dst + op, src + ip + hl, (uint32_t)L);
+      if (L > 64) lane_copy(dst + op + 64, src + ip + hl + 64, (uint32_t)L - 64);
       op += (uint32_t)L;
     } else {
-      if (off >= len) {
-        lane_copy64(dst + op, dst + op - off, len);  // reads this lane's earlier output
-      } else {  // the copy overlaps its output: bytes repeat with period off
+      if (off < len) {  // the copy overlaps its output: bytes repeat with period off
         for (uint32_t k0 = 0; k0 < len; k0 += 8) {
           uint32_t r = k0 % off;
           uint32_t bb[8];
