@@ -219,6 +219,33 @@ def main():
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"]):
         log(f"  {k:16s} {v['avg_ms']:8.3f} ms/launch  {v['share'] * 100:5.1f}% of the timed region")
 
+    # per-scan latency: each scan between its own events, warm (back to back)
+    # and cold (L2 and the 256 MB MALL evicted by a 512 MiB write first)
+    def timed_scans(n, flush):
+        out = []
+        scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda") if flush else None
+        for _ in range(n):
+            if flush:
+                scratch.fill_(1)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            f.scan_into(mask, 0, rg_end, outs, ws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        f.check()
+        return sorted(out)
+    warm = timed_scans(args.steps, False)
+    cold = timed_scans(max(3, args.steps // 4), True)
+    def pct(v, q):
+        return round(v[min(len(v) - 1, int(round(q * (len(v) - 1))))], 4)
+    latency = {"scans": len(warm), "p50_ms": pct(warm, 0.5), "p99_ms": pct(warm, 0.99),
+               "cold_scans": len(cold), "cold_p50_ms": pct(cold, 0.5), "cold_p99_ms": pct(cold, 0.99),
+               "cold_gbps": round(dec / (pct(cold, 0.5) / 1e3) / 1e9, 2)}
+    log(f"latency: warm p50 {latency['p50_ms']} ms, p99 {latency['p99_ms']} ms; "
+        f"cold (L2/MALL evicted) p50 {latency['cold_p50_ms']} ms = {latency['cold_gbps']} GB/s")
+
     key = f"rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
     per = {}
     n_str = sum(1 for k in prof if k.startswith("k_decode_str"))
@@ -258,7 +285,8 @@ def main():
                    "codec": args.codec, "columns": len(cols), "file_bytes": nbytes, "decoded_bytes_per_step": dec,
                    "pages": st.pages, "dict_pages": st.dict_pages, "tiles": st.tiles,
                    "open_ms": round(open_ms, 2), "open_ms_device": round(st.open_ms_device, 2),
-                   "form": "plain (one launch per kernel kind per scan)", "kernels": kern},
+                   "form": "plain (one launch per kernel kind per scan)", "kernels": kern,
+                   "latency": latency},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
