@@ -96,7 +96,8 @@ typedef struct {
   int64_t compressed_pages;
   uint64_t encoded_bytes; /* sum of compressed page payload sizes */
   uint64_t uncompressed_bytes;
-  double open_ms_device;  /* device time of the open-time kernels */
+  double open_ms_device;  /* time of the open-time passes: page walk and tile
+                             index (device events), tile prefix (host clock) */
 } pq_file_stats;
 
 /*
@@ -113,8 +114,16 @@ typedef struct {
  * then walks every column chunk's page headers into a device page table, and
  * a second kernel builds the tile index (entry positions of every fixed-size
  * row tile in the level and value streams of each page) that lets a scan
- * start decoding at any tile.  Returns PQ_ECORRUPT for a malformed file,
- * PQ_EUNSUPPORTED for valid files outside the supported subset.
+ * start decoding at any tile.  Last, the tile prefix: for every column with
+ * DELTA_BINARY_PACKED or BYTE_ARRAY pages, a pass over its tiles (after
+ * decompression and dictionary decode, in batches of row groups with at most
+ * 1 GiB of temporary device memory) counts each tile's DELTA sum or string
+ * bytes, and their exclusive prefix sum over the file's tiles is kept on the
+ * device and the host (8 bytes per tile).  A scan takes DELTA carries and
+ * string offsets from it, and pq_plan the chars sizes.  Returns PQ_ECORRUPT
+ * for a malformed file (including corrupt DELTA, dictionary-index or string
+ * data found by the prefix pass), PQ_EUNSUPPORTED for valid files outside the
+ * supported subset.
  */
 pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out);
 
@@ -126,12 +135,12 @@ pq_status pq_file_stats_get(pq_file f, pq_file_stats* out);
 
 /*
  * Sizes a scan of columns `col_mask` (bit i = leaf column i, at most 64
- * columns) over row groups [rg_begin, rg_end).
- *   workspace == NULL: fills rows and workspace_bytes only (host-only, no
- *     GPU work); chars_bytes of BYTE_ARRAY columns are -1.
- *   workspace != NULL (>= workspace_bytes): additionally runs the string
- *     length pass on `stream`, synchronises it, and fills chars_bytes.
- * chars_bytes of non-string columns are 0.
+ * columns) over row groups [rg_begin, rg_end): rows, workspace_bytes, and
+ * chars_bytes (exact chars bytes of each BYTE_ARRAY column, 0 for the
+ * others).  Host-only: the string byte counts come from the tile prefix
+ * that pq_open_device builds, so no GPU work is enqueued and nothing is
+ * synchronised.  `workspace`, `workspace_bytes` and `stream` are accepted
+ * for compatibility and not used (they may be NULL / 0).
  */
 pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
                   uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream);
@@ -144,9 +153,10 @@ pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
  *              by the caller, not used by anything else until the scan ends.
  * Steps enqueued: clear error word / validity edge words; Snappy
  * decompression of compressed pages into the workspace; dictionary pages ->
- * device dictionaries; DELTA tile sums and string sizes, with their prefix
- * scans; then the decode kernels (definition levels -> validity and ranks,
- * dictionary indices -> gather, PLAIN, DELTA_BINARY_PACKED, BYTE_ARRAY ->
+ * device dictionaries; offsets[rows] and the chars capacity check of string
+ * columns (from the tile prefix built at open); then the decode kernels
+ * (definition levels -> validity and ranks, dictionary indices -> gather,
+ * PLAIN, DELTA_BINARY_PACKED with carries from the tile prefix, BYTE_ARRAY ->
  * offsets and chars).  A chars buffer smaller than the decoded strings
  * is reported by pq_scan_check() as PQ_ECAPACITY (no chars
  * are written for the tiles that would overflow; nothing is written past

@@ -218,8 +218,6 @@ class DeviceFile:
         sz = self.plan(mask, rg_begin, rg_end, stream=stream)
         ws = torch.empty(max(int(sz.workspace_bytes), 256), dtype=torch.uint8, device="cuda")
         cols = sorted(columns)
-        if any(self.column_info(c).type == BYTE_ARRAY for c in cols):
-            sz = self.plan(mask, rg_begin, rg_end, workspace=ws, stream=stream)
         rows = int(sz.rows)
         outs, tensors = [], {}
         for k, c in enumerate(cols):

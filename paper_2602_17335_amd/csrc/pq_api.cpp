@@ -32,19 +32,19 @@ __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, co
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                           const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
                           uint32_t* err);
-__global__ void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err);
+__global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, const uint64_t* tpfx, uint32_t* err);
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
 template <int KIND>
 __global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                                const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
                                SegTable seg, uint32_t* err);
 __global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, SegTable seg,
-                               uint32_t* err);
+                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const uint64_t* tpfx,
+                               SegTable seg, uint32_t* err);
 template <bool SLOTS>
 __global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                              const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
-                             const uint32_t* strck, SegTable seg, uint32_t* err);
+                             const uint32_t* strck, const uint64_t* tpfx, SegTable seg, uint32_t* err);
 }  // namespace pqk
 
 using namespace pqk;
@@ -252,7 +252,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -276,6 +276,11 @@ struct pq_file_s {
   Ck* d_ckv = nullptr;  // value-stream checkpoints, NSUB per tile
   ChunkDev* d_chunks = nullptr;
   uint32_t* d_err = nullptr;
+  // tile prefix: exclusive prefix sum over the file's tiles of each tile's
+  // DELTA sum or string byte count (total_tiles + 1 entries), on the device
+  // and on the host
+  uint64_t* d_tpfx = nullptr;
+  std::vector<uint64_t> tpfx;
   pq_file_stats stats{};
   // measurement hook: event pairs around each launched kernel
   bool profiling = false;
@@ -284,18 +289,14 @@ struct pq_file_s {
   std::vector<hipEvent_t> event_pool;
   double prof_ms[NKERN] = {0};
   uint64_t prof_n[NKERN] = {0};
-  // second stream of a scan: the prefix passes run there, beside the
-  // fixed-width decode kernels (created at the first scan, default priority)
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // Slot order; k_decode_fixed<K> for K = 0 PLAIN 4-byte, 1 dictionary 4-byte,
 // 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
 // of slot dictionaries, k_decode_str<false> the others.
-enum { KP_SNAPPY, KP_DICT, KP_PREPASS, KP_TILE_SCAN, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA,
-       KP_EDGES, KP_STR_SLOTS, KP_SNAPPY_BLK };
-static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_prepass", "k_tile_scan", "k_prep",
+enum { KP_SNAPPY, KP_DICT, KP_STR_TOTAL, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA, KP_EDGES,
+       KP_STR_SLOTS, KP_SNAPPY_BLK };
+static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_str_total", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
                                           "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
                                           "k_decode_str<true>", "k_snappy_blk"};
@@ -334,12 +335,6 @@ struct ProfScope {
 
 static void free_handle(pq_file f) {
   if (!f) return;
-  if (f->aux) {
-    (void)hipStreamSynchronize(f->aux);
-    (void)hipStreamDestroy(f->aux);
-  }
-  if (f->ev_fork) (void)hipEventDestroy(f->ev_fork);
-  if (f->ev_join) (void)hipEventDestroy(f->ev_join);
   for (auto& r : f->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : f->event_pool) (void)hipEventDestroy(e);
   if (f->d_pages) (void)hipFree(f->d_pages);
@@ -351,6 +346,7 @@ static void free_handle(pq_file f) {
   if (f->d_ckv) (void)hipFree(f->d_ckv);
   if (f->d_chunks) (void)hipFree(f->d_chunks);
   if (f->d_err) (void)hipFree(f->d_err);
+  if (f->d_tpfx) (void)hipFree(f->d_tpfx);
   delete f;
 }
 
@@ -385,6 +381,8 @@ static SegTable make_segs(const std::vector<Segment>& v) {
   for (size_t i = 0; i < v.size(); ++i) t.s[i] = v[i];
   return t;
 }
+
+static pq_status build_tile_prefix(pq_file f, hipStream_t s);
 
 extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out) {
   if (!out) return fail(PQ_EINVAL, "out is NULL");
@@ -619,6 +617,14 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
 #undef OPEN_HIP
 #undef OPEN_ERR
 
+  // ---- tile prefix (per-tile DELTA sums and string byte counts) ----
+  const auto tp0 = std::chrono::steady_clock::now();
+  {
+    pq_status st4 = build_tile_prefix(f, s);
+    if (st4 != PQ_OK) { free_handle(f); return st4; }
+  }
+  const double prefix_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count();
+
   // ---- statistics ----
   pq_file_stats& S = f->stats;
   for (const PageDev& pg : f->pages) {
@@ -629,7 +635,7 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     S.uncompressed_bytes += pg.uncomp_size;
   }
   S.tiles = (int64_t)tiles;
-  S.open_ms_device = ms;
+  S.open_ms_device = ms + prefix_ms;
   (void)t0;
   *out = f;
   return PQ_OK;
@@ -678,8 +684,7 @@ struct Plan {
   uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
   // launch lists
   std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs[2], edge_segs;
-  std::vector<int32_t> scan_cols;   // ColScan indices needing k_tile_scan
-  std::vector<int32_t> str_cols;    // string ColScan indices
+  std::vector<int32_t> str_cols;    // string ColScan indices (k_str_total)
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
   uint32_t sblk_lanes = 0;
@@ -689,7 +694,11 @@ struct Plan {
   uint64_t ws_which = 0;
 };
 
-pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P) {
+// Work lists and workspace layout of a scan of `mask` over row groups
+// [rg_b, rg_e).  With `index`, the plan of the open-time prefix pass instead:
+// decompression, dictionaries and k_prepass of the columns that need a tile
+// prefix, with a per-tile array in the workspace.
+pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P, bool index = false) {
   if (rg_b < 0 || rg_e > f->nrg || rg_b > rg_e) return fail(PQ_EINVAL, "bad row-group range [%d, %d)", rg_b, rg_e);
   if (f->ncols < 64 && (mask >> f->ncols)) return fail(PQ_EINVAL, "column mask selects missing columns");
   P.rows = f->rg_row0[rg_e] - f->rg_row0[rg_b];
@@ -741,7 +750,7 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
           if (dp.dict_maxlen < 65536) sl.flags |= DICT_LENS16;
           sl.ws_lens = off;
           off = align_up(off + (uint64_t)((sl.flags & DICT_LENS16) ? 2 : 4) * sl.n + 16, 256);
-          if (dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32)) {
+          if (!index && dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32)) {
             sl.flags |= DICT_SLOTS;
             sl.ws_slots = off;
             off = align_up(off + (uint64_t)SLOT_BYTES * sl.n, 256);
@@ -774,15 +783,17 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       cs.ws_edge = off;
       off = align_up(off + 8ull * nt, 256);
     }
-    if (cs.type == T_BYTE_ARRAY || has_delta) {
+    const uint32_t idx = (uint32_t)P.cols.size();
+    if (index && (cs.type == T_BYTE_ARRAY || has_delta)) {
       cs.ws_tile_aux = off;
       off = align_up(off + 8ull * (nt + 1), 256);
-    }
-    const uint32_t idx = (uint32_t)P.cols.size();
-    if (nt) {
-      if (cs.type == T_BYTE_ARRAY) {
+      if (nt) {
         P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
         P.pre_units += nt;
+      }
+    }
+    if (nt) {
+      if (cs.type == T_BYTE_ARRAY) {
         for (int k = 0; k < 2; ++k) {  // k_decode_str<k>: tiles of slot dictionaries (1) or the others (0)
           if (!(k ? has_slots : (has_plain || has_dict || has_delta))) continue;
           P.str_segs[k].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units[k]});
@@ -790,8 +801,6 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
         }
       } else {
         if (has_delta) {
-          P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
-          P.pre_units += nt;
           P.delta_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.delta_units});
           P.delta_units += nt;
         }
@@ -811,7 +820,6 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
         P.edge_threads += nt;
       }
     }
-    if (cs.type == T_BYTE_ARRAY || has_delta) P.scan_cols.push_back((int32_t)idx);
     if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
     if (sbytes) {
       P.snappy_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.snappy_waves});
@@ -831,27 +839,20 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
 
 }  // namespace
 
-static hipError_t ensure_aux(pq_file f) {
-  if (f->aux) return hipSuccess;
-  hipError_t e = hipEventCreateWithFlags(&f->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&f->ev_join, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->aux, hipStreamNonBlocking);
-  return e;
-}
-
-static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool plan_only) {
+// Decompression and dictionaries of a plan: the steps the open-time prefix
+// pass and a scan share.
+static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
   ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
   DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
   int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
   if (!P.cols.empty()) HIP_OR(hipMemcpyAsync(d_cols, P.cols.data(), sizeof(ColScan) * P.cols.size(), hipMemcpyHostToDevice, s));
   if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
-  if (!P.scan_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.scan_cols.data(), sizeof(int32_t) * P.scan_cols.size(), hipMemcpyHostToDevice, s));
+  if (!P.str_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size(), hipMemcpyHostToDevice, s));
   const uint8_t* file = f->file;
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
     if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
   if (P.snappy_waves) {
-    if (P.snappy_segs.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, KP_SNAPPY, s);
     hipLaunchKernelGGL(k_snappy, dim3(P.snappy_waves), dim3(64), 0, s, file, f->d_pages, d_cols,
                        make_segs(P.snappy_segs), ws, f->d_sblk, 0, f->d_err);
@@ -878,32 +879,36 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
                        f->d_strck, tab, f->d_err);
     HIP_OR(hipGetLastError());
   }
-  // the prefix passes (k_prepass, k_tile_scan) feed only k_decode_delta and
-  // k_decode_str: in a scan they run on the handle's second stream, beside
-  // the fixed-width decode kernels, and the main stream waits for them
-  // before the kernels that read their results
-  const bool fork = !plan_only && (P.pre_units || !P.scan_cols.empty()) &&
-                    (P.fixed_units[0] || P.fixed_units[1] || P.fixed_units[2] || P.fixed_units[3]);
-  hipStream_t ps = s;
-  if (fork) {
-    HIP_OR(ensure_aux(f));
-    HIP_OR(hipEventRecord(f->ev_fork, s));
-    HIP_OR(hipStreamWaitEvent(f->aux, f->ev_fork, 0));
-    ps = f->aux;
-  }
+  return PQ_OK;
+}
+
+// The open-time prefix pass of a plan made with index = true: per-tile DELTA
+// sums and string byte counts into the workspace's tile arrays.
+static pq_status enqueue_index(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
+  pq_status st = enqueue_front(f, P, ws, s);
+  if (st != PQ_OK) return st;
   if (P.pre_units) {
-    ProfScope ps_(f, KP_PREPASS, ps);
-    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, ps, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckv, d_slots, make_segs(P.pre_segs), f->d_err);
+    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, f->file, ws,
+                       reinterpret_cast<ColScan*>(ws + P.ws_cols), f->d_pages, f->d_tiles, f->d_ckv,
+                       reinterpret_cast<DictSlot*>(ws + P.ws_slots), make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (!P.scan_cols.empty()) {
-    ProfScope ps_(f, KP_TILE_SCAN, ps);
-    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)P.scan_cols.size()), dim3(256), 0, ps, ws, d_cols, d_which, f->d_err);
+  return PQ_OK;
+}
+
+static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
+  pq_status st = enqueue_front(f, P, ws, s);
+  if (st != PQ_OK) return st;
+  ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
+  DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
+  int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
+  const uint8_t* file = f->file;
+  if (!P.str_cols.empty()) {
+    ProfScope ps_(f, KP_STR_TOTAL, s);
+    hipLaunchKernelGGL(k_str_total, dim3(1), dim3(64), 0, s, d_cols, d_which, (int32_t)P.str_cols.size(), f->d_tpfx,
+                       f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (plan_only) return PQ_OK;
-  if (fork) HIP_OR(hipEventRecord(f->ev_join, ps));
   if (P.prep_threads) {
     ProfScope ps_(f, KP_PREP, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
@@ -912,26 +917,23 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   }
   for (int K = 0; K < 4; ++K) {
     if (!P.fixed_units[K]) continue;
-    if (P.fixed_segs[K].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, KP_FIXED0 + K, s);
     auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
     hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
                        f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
-  if (fork) HIP_OR(hipStreamWaitEvent(s, f->ev_join, 0));
   if (P.delta_units) {
     ProfScope ps_(f, KP_DELTA, s);
     hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, make_segs(P.delta_segs), f->d_err);
+                       f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, f->d_tpfx, make_segs(P.delta_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   for (int k = 0; k < 2; ++k) {
     if (!P.str_units[k]) continue;
-    if (P.str_segs[k].size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
     ProfScope ps_(f, k ? KP_STR_SLOTS : KP_STR, s);
     hipLaunchKernelGGL(k ? k_decode_str<true> : k_decode_str<false>, dim3((P.str_units[k] + 3) / 4), dim3(256), 0, s,
-                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, d_slots, f->d_strck,
+                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, d_slots, f->d_strck, f->d_tpfx,
                        make_segs(P.str_segs[k]), f->d_err);
     HIP_OR(hipGetLastError());
   }
@@ -944,8 +946,58 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s, bool pl
   return PQ_OK;
 }
 
+// Builds the tile prefix at open: for every column with string or DELTA
+// pages, the prefix pass over its row groups (in batches whose workspace
+// stays below INDEX_WS_CAP), then the prefix sum on the host.
+constexpr uint64_t INDEX_WS_CAP = 1ull << 30;
+
+static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
+  const uint64_t nt = f->total_tiles;
+  std::vector<uint64_t> val(nt, 0);
+  for (int c = 0; c < f->ncols; ++c) {
+    bool need = f->cols[c].type == T_BYTE_ARRAY;
+    for (uint32_t p = f->chunk_page0[(size_t)c * f->nrg]; !need && p < f->chunk_page0[(size_t)(c + 1) * f->nrg]; ++p)
+      need = f->pages[p].kind != PAGE_DICT && f->pages[p].encoding == E_DELTA;
+    if (!need) continue;
+    for (int g0 = 0; g0 < f->nrg;) {
+      int n = f->nrg - g0;
+      Plan P;
+      for (;;) {
+        P = Plan();
+        pq_status st = make_plan(f, 1ull << c, g0, g0 + n, P, true);
+        if (st != PQ_OK) return st;
+        if (P.ws_total <= INDEX_WS_CAP || n == 1) break;
+        n = (n + 1) / 2;
+      }
+      const ColScan& cs = P.cols[0];
+      const uint32_t cnt = cs.tile_end - cs.tile_begin;
+      if (cnt) {
+        uint8_t* ws = nullptr;
+        if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
+        pq_status st = enqueue_index(f, P, ws, s);
+        if (st == PQ_OK && hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt,
+                                          hipMemcpyDeviceToHost, s) != hipSuccess)
+          st = fail(PQ_EHIP, "open: prefix pass copy");
+        if (st == PQ_OK) st = read_err(f, s);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+        if (st != PQ_OK) return st;
+      }
+      g0 += n;
+    }
+  }
+  f->tpfx.assign(nt + 1, 0);
+  for (uint64_t t = 0; t < nt; ++t) f->tpfx[t + 1] = f->tpfx[t] + val[t];
+  HIP_OR(hipMalloc(&f->d_tpfx, 8ull * (nt + 1)));
+  HIP_OR(hipMemcpy(f->d_tpfx, f->tpfx.data(), 8ull * (nt + 1), hipMemcpyHostToDevice));
+  return PQ_OK;
+}
+
 extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
                              uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream) {
+  (void)workspace;
+  (void)workspace_bytes;
+  (void)stream;
   if (!f || !out) return fail(PQ_EINVAL, "NULL argument");
   Plan P;
   pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
@@ -954,25 +1006,10 @@ extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
   out->rows = P.rows;
   out->workspace_bytes = P.ws_total;
   for (int k = 0; k < 64; ++k) out->chars_bytes[k] = 0;
-  for (size_t k = 0; k < P.cols.size(); ++k)
-    if (P.cols[k].type == T_BYTE_ARRAY) out->chars_bytes[k] = -1;
-  if (!workspace || P.str_cols.empty()) return PQ_OK;
-  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned");
-  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
-  hipStream_t s = (hipStream_t)stream;
-  // the plan pass must not trip the capacity check
-  for (ColScan& cs : P.cols) { cs.chars_capacity = ~0ull; cs.offsets = nullptr; }
-  st = enqueue(f, P, (uint8_t*)workspace, s, true);
-  if (st != PQ_OK) return st;
-  std::vector<uint64_t> tot(P.str_cols.size());
-  for (size_t k = 0; k < P.str_cols.size(); ++k) {
-    const ColScan& cs = P.cols[P.str_cols[k]];
-    HIP_OR(hipMemcpyAsync(&tot[k], (uint8_t*)workspace + cs.ws_tile_aux + 8ull * (cs.tile_end - cs.tile_begin), 8,
-                          hipMemcpyDeviceToHost, s));
+  for (int32_t k : P.str_cols) {
+    const ColScan& cs = P.cols[k];
+    out->chars_bytes[k] = (int64_t)(f->tpfx[cs.tile_end] - f->tpfx[cs.tile_begin]);
   }
-  st = read_err(f, s);
-  if (st != PQ_OK) return st;
-  for (size_t k = 0; k < P.str_cols.size(); ++k) out->chars_bytes[P.str_cols[k]] = (int64_t)tot[k];
   return PQ_OK;
 }
 
@@ -1008,7 +1045,7 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
     }
     cs.validity = o.validity;
   }
-  return enqueue(f, P, (uint8_t*)workspace, (hipStream_t)stream, false);
+  return enqueue(f, P, (uint8_t*)workspace, (hipStream_t)stream);
 }
 
 extern "C" pq_status pq_scan_check(pq_file f, pq_stream stream) {

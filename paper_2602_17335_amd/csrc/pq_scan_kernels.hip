@@ -1,13 +1,22 @@
-// pq_scan_kernels.hip -- kernels of one scan (everything pq_scan enqueues).
+// pq_scan_kernels.hip -- kernels of one scan (everything pq_scan enqueues),
+// and k_prepass, which pq_open_device runs once to build the tile prefix.
 //
 //   k_snappy        Snappy page bodies -> workspace (one wave per page)
+//   k_snappy_blk    Snappy page bodies with a block index (one lane per 64 KiB block)
 //   k_prep          validity edge words cleared / REQUIRED validity set to ones
 //   k_dict          dictionary pages -> device dictionaries
-//   k_prepass       per-tile DELTA sums and string byte counts
-//   k_tile_scan     exclusive prefix over tiles (DELTA carries, string bases)
+//   k_prepass       per-tile DELTA sums and string byte counts (at open)
+//   k_str_total     offsets[rows] and the chars capacity check of string columns
 //   k_decode_fixed  definition levels; PLAIN / dictionary INT32, INT64, DOUBLE values
 //   k_decode_delta  definition levels; DELTA_BINARY_PACKED INT32 / INT64 values
 //   k_decode_str    definition levels; PLAIN / dictionary BYTE_ARRAY values -> offsets and chars
+//
+// The tile prefix (one uint64 per tile of the file, plus one) is the
+// exclusive prefix sum, in file tile order, of each tile's DELTA sum or
+// string byte count (0 for other tiles).  A DELTA tile's carry is the
+// difference of the prefix at the tile and at its page's first tile; a
+// string tile's chars start is the difference at the tile and at the scan's
+// first tile of the column.  Both are exact modulo 2^64.
 //
 // Work unit of the prepass and decode kernels: one TILE_ROWS-row tile
 // of one page per wave, four independent tiles per 256-thread workgroup, no
@@ -217,25 +226,6 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
 __device__ __forceinline__ uint64_t wave_read_u64(uint64_t v, int lane) {
   return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane) |
          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane) << 32);
-}
-
-// exclusive scan of one u64 per thread over the workgroup (wrapping); the
-// total goes to *total.  Contains two barriers.
-__device__ __forceinline__ uint64_t wg_excl_scan_u64(uint64_t v, uint64_t* s_tmp, uint64_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t inc = wave_incl_scan_u64(v);
-  if (lane == 63) s_tmp[wave] = inc;
-  __syncthreads();
-  uint64_t base = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < NWAVES; ++k) {
-    uint64_t x = s_tmp[k];
-    if (k < wave) base += x;
-    tot += x;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + inc - v;
 }
 
 // Orders this wave's LDS accesses (no other wave takes part).
@@ -1605,44 +1595,18 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
 }
 
 // ---------------------------------------------------------------------------
-// k_tile_scan: exclusive prefix over each listed column's tile auxiliaries
-// (one workgroup per column); string columns also get offsets[rows] and the
-// capacity check.
+// k_str_total: offsets[rows] and the chars capacity check of each string
+// column of a scan (one thread per column), from the tile prefix.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_tile_scan(uint8_t* ws, const ColScan* cols, const int32_t* which, uint32_t* err) {
-  __shared__ uint64_t s_tmp[WG / 64];
-  const ColScan cs = cols[which[blockIdx.x]];
-  uint64_t* aux = reinterpret_cast<uint64_t*>(ws + cs.ws_tile_aux);
-  const uint32_t n = cs.tile_end - cs.tile_begin;
-  // TS_PER consecutive tiles per thread and round: every load of a round is
-  // issued before its scan, and the rounds (two barriers each) are few
-  constexpr uint32_t TS_PER = 8;
-  uint64_t carry = 0;
-  for (uint32_t b = 0; b < n; b += WG * TS_PER) {
-    const uint32_t i0 = b + threadIdx.x * TS_PER;
-    uint64_t v[TS_PER];
-#pragma unroll
-    for (uint32_t q = 0; q < TS_PER; ++q) v[q] = i0 + q < n ? aux[i0 + q] : 0;
-    uint64_t sum = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < TS_PER; ++q) sum += v[q];
-    uint64_t tot;
-    uint64_t run = carry + wg_excl_scan_u64(sum, s_tmp, &tot);
-#pragma unroll
-    for (uint32_t q = 0; q < TS_PER; ++q) {
-      if (i0 + q < n) aux[i0 + q] = run;
-      run += v[q];
-    }
-    carry += tot;
-  }
-  if (cs.type == T_BYTE_ARRAY && threadIdx.x == 0) {
-    if (cs.offsets) cs.offsets[cs.rows] = (int64_t)carry;
-    if (carry > cs.chars_capacity) set_err(err, ERR_CAPACITY, (uint32_t)cs.col);
-    // slot past the last tile: total (read by pq_plan)
-    aux[n] = carry;
-  }
+__global__ void k_str_total(const ColScan* __restrict__ cols, const int32_t* __restrict__ which, int32_t n,
+                            const uint64_t* __restrict__ tpfx, uint32_t* __restrict__ err) {
+  const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const ColScan& cs = cols[which[i]];
+  const uint64_t tot = tpfx[cs.tile_end] - tpfx[cs.tile_begin];
+  if (cs.offsets) cs.offsets[cs.rows] = (int64_t)tot;
+  if (tot > cs.chars_capacity) set_err(err, ERR_CAPACITY, (uint32_t)cs.col);
 }
-
 
 // ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
@@ -1665,7 +1629,9 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
     if (lane == 0) *aux = (uint64_t)c.td.val_skip - c.td.val_pos - 4ull * c.td.nn;
     return;
   }
-  if (c.td.nn == 0 || (!is_str && enc != E_DELTA)) {
+  // tiles without a count, and encodings the decode kernels report as
+  // unsupported when (and only when) their column is scanned
+  if (c.td.nn == 0 || (!is_str && enc != E_DELTA) || (is_str && enc != E_PLAIN_DICT && enc != E_RLE_DICT)) {
     if (lane == 0) *aux = 0;
     return;
   }
@@ -1842,7 +1808,8 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
                                                      const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                                      const TileDev* __restrict__ tiles,
                                                      const uint32_t* __restrict__ ckl,
-                                                     const Ck* __restrict__ ckv, SegTable seg,
+                                                     const Ck* __restrict__ ckv,
+                                                     const uint64_t* __restrict__ tpfx, SegTable seg,
                                                      uint32_t* __restrict__ err) {
   // per wave: the values of one half of the tile's rows (at most TR / 2)
   constexpr uint32_t HALF = TR / 2;
@@ -1873,8 +1840,7 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
       V[q] = acc;
     }
     const uint64_t ex = wave_incl_scan_u64(acc) - acc;
-    glb_u64* aux = reinterpret_cast<glb_u64*>(gptr(ws + c.cs.ws_tile_aux));
-    const uint64_t carry = aux[c.t - c.cs.tile_begin] - aux[c.pg.tile_begin - c.cs.tile_begin];
+    const uint64_t carry = tpfx[c.t] - tpfx[c.pg.tile_begin];
 #pragma unroll
     for (int q = 0; q < LPER; ++q) V[q] += carry + ex;
   }
@@ -1935,7 +1901,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
                                                    const uint32_t* __restrict__ ckl,
                                                    const Ck* __restrict__ ckv,
                                                    const DictSlot* __restrict__ slots,
-                                                   const uint32_t* __restrict__ strck, SegTable seg,
+                                                   const uint32_t* __restrict__ strck,
+                                                   const uint64_t* __restrict__ tpfx, SegTable seg,
                                                    uint32_t* __restrict__ err) {
   // per wave: the value positions (indices) of the tile, then, once every
   // row's (position, length) is in registers, the chars staging buffer
@@ -2026,9 +1993,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   }
   wave_sync();
 
-  glb_u64* aux = reinterpret_cast<glb_u64*>(gptr(ws + c.cs.ws_tile_aux));
-  const uint64_t base = aux[c.t - c.cs.tile_begin];
-  const uint64_t tend = aux[c.t - c.cs.tile_begin + 1];
+  const uint64_t base = tpfx[c.t] - tpfx[c.cs.tile_begin];
+  const uint64_t tend = tpfx[c.t + 1] - tpfx[c.cs.tile_begin];
   if (tend - base >= 0xffffffffull) {
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, td.page);
     return;
@@ -2227,9 +2193,11 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
 }
 
 template __global__ void k_decode_str<false>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                            const uint32_t*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
+                                            const uint32_t*, const Ck*, const DictSlot*, const uint32_t*,
+                                            const uint64_t*, SegTable, uint32_t*);
 template __global__ void k_decode_str<true>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                           const uint32_t*, const Ck*, const DictSlot*, const uint32_t*, SegTable, uint32_t*);
+                                           const uint32_t*, const Ck*, const DictSlot*, const uint32_t*,
+                                           const uint64_t*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<0>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
                                           const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_DICT>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
