@@ -526,10 +526,25 @@ __device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, Ck ck, uin
     using I = typename std::remove_reference_t<decltype(vs)>::I;
     return ck_walk(vs, (P)c.td.val_pos, ck, (I)(lane >> 2) * SUB_ROWS, w, false, (I)a, (I)b, (P)c.td.val_pos,
                    -(I)c.td.val_skip, [&](I lo, I hi, bool bp, P x) {
-      for (I v = lo; v < hi; ++v) {
-        uint32_t id = bp ? (uint32_t)vs.bits(x + (P)(v - lo) * w, w) : (uint32_t)x;
+      if (bp) {
+        // a piece holds at most LPER values: every load first (positions
+        // past the piece repeat value lo's, which lies in the stream), then
+        // the checks and the LDS stores
+        uint32_t id[LPER];
+#pragma unroll
+        for (int j = 0; j < LPER; ++j) id[j] = (uint32_t)vs.bits(lo + (I)j < hi ? x + (P)j * w : x, w);
+#pragma unroll
+        for (int j = 0; j < LPER; ++j) {
+          if (lo + (I)j < hi) {
+            uint32_t v = id[j];
+            if (v >= dn) { bad_idx = true; v = 0; }
+            idx[pad((uint32_t)(lo + (I)j))] = v;
+          }
+        }
+      } else {
+        uint32_t id = (uint32_t)x;
         if (id >= dn) { bad_idx = true; id = 0; }
-        idx[pad((uint32_t)v)] = id;
+        for (I v = lo; v < hi; ++v) idx[pad((uint32_t)v)] = id;
       }
     });
   };
