@@ -1920,10 +1920,11 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
                                                    const uint64_t* __restrict__ tpfx, SegTable seg,
                                                    uint32_t* __restrict__ err) {
   // per wave: the value positions (indices) of the tile, then, once every
-  // row's (position, length) is in registers, the chars staging buffer
-  // (slot strings are staged in the index area itself: one group of at most
-  // 64 * SLOT_CHARS chars fits it)
-  constexpr uint32_t BUFW = SLOTS ? PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
+  // row's (position, length) is in registers, the chars staging buffer.
+  // Slot strings are staged in the index area and as much again (about
+  // 8.7 KB per wave: a full buffer is stored about every 300 rows, and four
+  // workgroups still fit a CU's LDS).
+  constexpr uint32_t BUFW = SLOTS ? 2 * PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
   constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
   __shared__ __align__(16) uint32_t s_buf[NWAVES][BUFW];
   WaveTile c;
