@@ -145,9 +145,9 @@ struct TileDev {
 // Decoded dictionary of one column chunk inside the workspace.
 // String dictionaries also get an array of entry lengths (u16 when every
 // entry is shorter than 2^16 bytes, else u32) and, when every entry fits
-// SLOT_CHARS bytes, a copy of the entries in fixed SLOT_BYTES slots (chars
-// first, u32 length in the last four bytes), so that one row's gather touches
-// one aligned 64-byte piece of memory.
+// SLOT_CHARS bytes, a copy of the entries in fixed SLOT_BYTES slots (u32
+// length first, then the chars, zero-padded), so that one row's gather --
+// length and chars together -- touches one aligned 64-byte piece of memory.
 constexpr uint32_t SLOT_BYTES = 64;
 constexpr uint32_t SLOT_CHARS = 60;
 static_assert(SLOT_BYTES == 64 && SLOT_CHARS < 64, "a slot offset and a length share one word");

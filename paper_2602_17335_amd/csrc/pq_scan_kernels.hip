@@ -896,28 +896,29 @@ __device__ __forceinline__ void store_group(const lds_u32* buf, uint32_t nbufw, 
 }
 
 
-// Slot dictionaries (entry e's chars at byte 64 e, zero-padded to the slot's
-// last dword, which holds the length).  slot_load reads the (at most three)
-// 16-byte pieces holding bytes [0, min(L, 48)) of the slot at byte `pos`;
-// pieces past the string read as zero.
+// Slot dictionaries: entry e's slot is the 64 bytes at 64 e; dword 0 holds
+// the entry's length (at most SLOT_CHARS), its chars follow from byte 4,
+// zero-padded to the slot's end.  slot_load reads the slot's first 48 bytes
+// (the length and up to 44 chars) as three 16-byte pieces.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) u32x4 gout_u32x4;
 
-__device__ __forceinline__ void slot_load(glb_u8* sbase, uint32_t pos, uint32_t L, uint32_t* w) {
+__device__ __forceinline__ void slot_load(glb_u8* sbase, uint32_t pos, uint32_t* w) {
   const __attribute__((address_space(1))) u32x4* q =
       reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(sbase + pos);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    u32x4 x = {0u, 0u, 0u, 0u};
-    if ((uint32_t)(16 * c) < L) x = q[c];
+    const u32x4 x = q[c];
     w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
   }
 }
 
-// ORs the L chars of a slot (pieces in w, from slot_load) into a zeroed LDS
-// buffer at byte D: dword m of the destination, counted from the aligned
-// dword at D - dd (dd in 1..4, so the shift below is 0..3), is string bytes
-// [4 m - dd, 4 m - dd + 4).  Bytes outside the string are zero, so the
+// ORs the L chars of a slot (its first 12 dwords in w, from slot_load) into a
+// zeroed LDS buffer at byte D: dword m of the destination, counted from the
+// aligned dword at D - dd (dd in 1..4, so the shift below is 0..3), is
+// string bytes [4 m - dd, 4 m - dd + 4), i.e. slot bytes from 4 m + 4 - dd:
+// the high bytes of slot dword m and the low bytes of dword m + 1, with the
+// length dword read as zero.  Bytes outside the string are zero, so the
 // neighbours' shared edge dwords combine by OR and no lane needs a mask.
 // Needs 4 bytes of room before D and 64 after it.
 __device__ __forceinline__ void slot_or(const uint32_t* w, glb_u8* sbase, uint32_t pos, uint32_t L, lds_u8* dst,
@@ -925,21 +926,26 @@ __device__ __forceinline__ void slot_or(const uint32_t* w, glb_u8* sbase, uint32
   const uint32_t dd = ((D - 1u) & 3u) + 1u;
   const uint32_t sh = (4u - dd) & 3u;
   lds_u32* dw = reinterpret_cast<lds_u32*>(dst + D - dd);
-  uint32_t prev = 0u;
+  uint32_t w3[5] = {0u, 0u, 0u, 0u, 0u};  // slot dwords 12..15 (chars 44..59), then past the slot
+  if (L > 44) {
+    const u32x4 x = reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(sbase + pos)[3];
+    w3[0] = x.x; w3[1] = x.y; w3[2] = x.z; w3[3] = x.w;
+  }
+  uint32_t prev = 0u;  // slot dword 0 (the length) reads as zero
 #pragma unroll
   for (int m = 0; m < 12; ++m) {
-    __hip_atomic_fetch_or(&dw[m], __builtin_amdgcn_alignbyte(w[m], prev, sh), __ATOMIC_RELAXED,
+    const uint32_t cur = m < 11 ? w[m + 1] : w3[0];
+    __hip_atomic_fetch_or(&dw[m], __builtin_amdgcn_alignbyte(cur, prev, sh), __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_WORKGROUP);
-    prev = w[m];
+    prev = cur;
   }
-  if (L > 44) {  // up to SLOT_CHARS: the slot's fourth piece, without its length dword
-    const u32x4 x = reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(sbase + pos)[3];
-    const uint32_t w4[4] = {x.x, x.y, x.z, 0u};
+  if (L > 44) {  // up to SLOT_CHARS
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      __hip_atomic_fetch_or(&dw[12 + m], __builtin_amdgcn_alignbyte(w4[m], prev, sh), __ATOMIC_RELAXED,
+    for (int m = 12; m < 16; ++m) {
+      const uint32_t cur = w3[m - 11];
+      __hip_atomic_fetch_or(&dw[m], __builtin_amdgcn_alignbyte(cur, prev, sh), __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_WORKGROUP);
-      prev = w4[m];
+      prev = cur;
     }
   }
 }
@@ -1568,23 +1574,25 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
     }
     if (!(sl.flags & DICT_SLOTS)) return;
     wave_sync();
-    // slots: 16-byte chunk c of entry e per step (chars zero past the length;
-    // a slot's last dword is the length, which is at most SLOT_CHARS)
+    // slots: 16-byte chunk c of entry e per step (slot dword 0 is the
+    // length, at most SLOT_CHARS; slot dword D > 0 holds chars [4 D - 4,
+    // 4 D), zero past the length)
     const uint32_t ne = min(ck1 * STR_CK, n) - e0;
     glb_u8* sb = gptr(ws + sl.ws_slots);
     for (uint32_t i = lane; i < 4 * ne; i += 64) {
       const uint32_t ei = i >> 2, c = i & 3;
       const uint32_t L = s_len[wave][ei];
-      const uint32_t y = s_pos[wave][ei] + 16 * c;
+      const uint32_t y = s_pos[wave][ei];  // LDS byte of the entry's first char
       u32x4 o;
       uint32_t ow[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const uint32_t x = lds_word(y + 4 * m);
-        const int keep = (int)L - (int)(16 * c) - 4 * m;  // chars in this dword
-        ow[m] = keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u)));
+        const int D = 4 * (int)c + m;
+        const int keep = (int)L - (4 * D - 4);  // chars in this dword
+        const uint32_t x = (D > 0 && keep > 0) ? lds_word(y + 4 * (uint32_t)D - 4) : 0u;
+        ow[m] = D == 0 ? L : (keep >= 4 ? x : (keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u))));
       }
-      o.x = ow[0]; o.y = ow[1]; o.z = ow[2]; o.w = c == 3 ? L : ow[3];
+      o.x = ow[0]; o.y = ow[1]; o.z = ow[2]; o.w = ow[3];
       __builtin_nontemporal_store(o, (gout_u32x4*)(sb + (uint64_t)(e0 + ei) * SLOT_BYTES + 16 * c));
     }
     return;
@@ -1955,9 +1963,6 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   glb_u8* sbase;
   uint64_t soff;
   glb_u64* pairs = nullptr;
-  constexpr bool use_slots = SLOTS;
-  bool lens16 = false;
-  glb_u8* lens = nullptr;
   if (is_plain) {
     // u[pad(j)]: offset (in the value stream) of the length prefix of the
     // tile's value j, j <= nn; one lane per STR_CK checkpoint
@@ -1991,11 +1996,9 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       if (lane == 0) set_err(err, ERR_DICT_MISSING, td.page);
       return;
     }
-    if (SLOTS) {  // entry e's chars at slot e; lengths from the length array
+    if (SLOTS) {  // entry e's length and chars in slot e
       sbase = gptr(ws + sl.ws_slots);
       soff = 0;
-      lens16 = sl.flags & DICT_LENS16;
-      lens = gptr(ws + sl.ws_lens);
     } else {
       sbase = (glb_u8*)sl.body;
       soff = sl.body_off;
@@ -2019,10 +2022,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   gout_u8* chars = gptr(c.cs.chars);
   __attribute__((address_space(1))) int64_t* offs = gptr(c.cs.offsets);
 
-  // (position, length) of row 64 g + lane for all groups: ranks first, then
-  // one loop per source kind (no branch inside, so every gather of the tile
-  // is issued before the first wait)
-  uint32_t pos[NGROUPS], len[NGROUPS], kk[NGROUPS];
+  // ranks of row 64 g + lane for all groups (kk: value index, vmask: valid)
+  uint32_t kk[NGROUPS];
   uint32_t vmask = 0;
   {
     uint32_t kb = 0;
@@ -2036,6 +2037,109 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       vmask |= (v ? 1u : 0u) << g;
     }
   }
+  if constexpr (SLOTS) {
+    // Slot dictionaries, one group of 64 rows at a time: the group's slots
+    // (length in dword 0, chars from byte 4) are loaded one group ahead; the
+    // lengths give the group's offsets (a wave scan on top of the chars of
+    // the groups before it; stored after the chars, so that no load waits
+    // for them), and each lane ORs its string's realigned dwords
+    // into a zeroed LDS buffer with no masks (slots are zero past the
+    // string, so the neighbours' edge bytes combine by OR).  LDS byte j maps
+    // to the 16-byte aligned global address G0 + j, so the buffer is stored
+    // as aligned 16-byte chunks; when it fills, the full chunks are stored
+    // and cleared and the partial last chunk moves to the front.  Only the
+    // tile's first and last chunk are stored bytewise (they share bytes with
+    // the neighbouring tiles).
+    constexpr uint32_t HEAD = 16;                   // room for a string's dword before byte 0
+    constexpr uint32_t CAP = BUFW * 4 - HEAD - 64;  // chars + the realignment slack
+    static_assert(BUFW % 4 == 0 && CAP >= 64 * SLOT_CHARS + 15, "one group of slot strings fits the buffer");
+    uint32_t sp[NGROUPS];  // byte offset of row 64 g + lane's slot (a null row reads entry 0's)
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) sp[g] = td.nn ? u[pad(kk[g])] * SLOT_BYTES : 0u;
+    wave_sync();
+    typedef __attribute__((address_space(3))) u32x4 lds_v4u;
+    lds_v4u* zb = (lds_v4u*)&s_buf[wave][0];
+    if (fits)
+      for (uint32_t i = lane; i < BUFW / 4; i += 64) zb[i] = u32x4{0u, 0u, 0u, 0u};
+    wave_sync();
+    lds_u8* cb8 = (lds_u8*)&s_buf[wave][0] + HEAD;
+    lds_v4u* cbv = reinterpret_cast<lds_v4u*>(cb8);
+    gout_u8* tile_chars = chars + base;
+    uint32_t lo = (uint32_t)((uintptr_t)tile_chars & 15);  // LDS byte of tile char bstart
+    uint32_t bstart = 0, bfill = 0, tb = 0;                // tb: tile chars before group g
+    bool head_foreign = lo != 0;  // LDS bytes [0, lo) of chunk 0 belong to the previous tile
+    // an all-null tile reads no slot (the dictionary may be empty)
+    uint32_t wc[12], wn[12], ex[NGROUPS];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) wn[k] = 0u;
+    if (td.nn) slot_load(sbase, sp[0], wn);
+#pragma unroll
+    for (int g = 0; g < NGROUPS; ++g) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) wc[k] = wn[k];
+      if (td.nn && g + 1 < NGROUPS) slot_load(sbase, sp[g + 1], wn);
+      const uint32_t L = ((vmask >> g) & 1) ? wc[0] : 0u;
+      const uint32_t incl = wave_incl_scan_u32(L);
+      const uint32_t Tg = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      const uint32_t exg = tb + incl - L;
+      ex[g] = exg;
+      tb += Tg;
+      if (!fits || Tg == 0) continue;
+      if (bfill && lo + bfill + Tg > CAP) {
+        // store the full chunks, clear them, move the partial one to the front
+        wave_sync();
+        const uint32_t end = lo + bfill, nfull = end >> 4, tail = end & 15;
+        gout_u8* g0 = tile_chars + bstart - lo;
+        for (uint32_t k = lane; k < nfull; k += 64) {
+          const u32x4 v = cbv[k];
+          if (k == 0 && head_foreign) store_chunk_bytes(v, g0, lo, 16);
+          else __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
+          cbv[k] = u32x4{0u, 0u, 0u, 0u};
+        }
+        wave_sync();
+        if (lane == 0 && tail) {
+          cbv[0] = cbv[nfull];
+          cbv[nfull] = u32x4{0u, 0u, 0u, 0u};
+        }
+        wave_sync();
+        head_foreign = false;
+        bstart += bfill;
+        lo = tail;
+        bfill = 0;
+      }
+      if (L) slot_or(wc, sbase, sp[g], L, cb8, lo + (exg - bstart));
+      bfill += Tg;
+    }
+    if (c.cs.offsets) {
+#pragma unroll
+      for (int g = 0; g < NGROUPS; ++g) {
+        const uint32_t r = 64 * g + lane;
+        if (r < c.nrows) __builtin_nontemporal_store((int64_t)(base + ex[g]), &offs[c.out0 + r]);
+      }
+    }
+    // the slots' lengths and the tile prefix come from the same dictionary
+    // entries; a difference is reported, never hidden
+    if (tb != (uint32_t)(tend - base)) {
+      if (lane == 0) set_err(err, ERR_STRING, td.page);
+      return;
+    }
+    if (!fits) return;
+    wave_sync();
+    const uint32_t end = lo + bfill, nst = (end + 15) >> 4, tail = end & 15;
+    gout_u8* g0 = tile_chars + bstart - lo;
+    for (uint32_t k = lane; k < nst; k += 64) {
+      const u32x4 v = cbv[k];
+      const uint32_t b0 = (k == 0 && head_foreign) ? lo : 0u;
+      const uint32_t b1 = (k + 1 == nst && tail) ? tail : 16u;
+      if (b0 == 0 && b1 == 16) __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
+      else store_chunk_bytes(v, g0 + 16 * k, b0, b1);
+    }
+    return;
+  }
+  // (position, length) of row 64 g + lane for all groups, one loop per
+  // source kind (no branch inside, so every gather of the tile is issued
+  // before the first wait)
+  uint32_t pos[NGROUPS], len[NGROUPS];
   if (td.nn == 0) {
 #pragma unroll
     for (int g = 0; g < NGROUPS; ++g) { pos[g] = 0; len[g] = 0; }
@@ -2046,19 +2150,6 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       pos[g] = q0 + 4;
       len[g] = q1 - q0 - 4;
     }
-  } else if constexpr (use_slots) {
-#pragma unroll
-    for (int g = 0; g < NGROUPS; ++g) pos[g] = u[pad(kk[g])];
-    if (lens16) {
-#pragma unroll
-      for (int g = 0; g < NGROUPS; ++g)
-        len[g] = reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>(lens)[pos[g]];
-    } else {
-#pragma unroll
-      for (int g = 0; g < NGROUPS; ++g) len[g] = reinterpret_cast<glb_u32*>(lens)[pos[g]];
-    }
-#pragma unroll
-    for (int g = 0; g < NGROUPS; ++g) pos[g] *= SLOT_BYTES;
   } else {
 #pragma unroll
     for (int g = 0; g < NGROUPS; ++g) pos[g] = u[pad(kk[g])];
@@ -2096,75 +2187,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     }
   }
   if (!fits) return;
-  if constexpr (SLOTS) {
-    // chars of slot dictionaries: every slot is zero past its string, so a
-    // lane ORs its string's realigned dwords into a zeroed LDS buffer with no
-    // masks (the neighbours' edge bytes combine by OR).  LDS byte j maps to
-    // the 16-byte aligned global address G0 + j, so the buffer is stored as
-    // aligned 16-byte chunks; when it fills, the full chunks are stored and
-    // cleared and the partial last chunk moves to the front.  Only the tile's
-    // first and last chunk are stored bytewise (they share bytes with the
-    // neighbouring tiles).
-    constexpr uint32_t HEAD = 16;                      // room for a string's dword before byte 0
-    constexpr uint32_t CAP = BUFW * 4 - HEAD - 64;     // chars + the realignment slack
-    static_assert(BUFW % 4 == 0 && CAP >= 64 * SLOT_CHARS + 15, "one group of slot strings fits the buffer");
-    wave_sync();
-    typedef __attribute__((address_space(3))) u32x4 lds_v4u;
-    lds_v4u* zb = (lds_v4u*)&s_buf[wave][0];
-    for (uint32_t i = lane; i < BUFW / 4; i += 64) zb[i] = u32x4{0u, 0u, 0u, 0u};
-    wave_sync();
-    lds_u8* cb8 = (lds_u8*)&s_buf[wave][0] + HEAD;
-    lds_v4u* cbv = reinterpret_cast<lds_v4u*>(cb8);
-    gout_u8* tile_chars = chars + base;
-    uint32_t lo = (uint32_t)((uintptr_t)tile_chars & 15);  // LDS byte of tile char bstart
-    uint32_t bstart = 0, bfill = 0;
-    bool head_foreign = lo != 0;  // LDS bytes [0, lo) of chunk 0 belong to the previous tile
-    // from here on pos[g] is the slot's byte offset | the string's length
-#pragma unroll
-    for (int g = 0; g < NGROUPS; ++g) pos[g] |= len[g];
-    uint32_t wc[12], wn[12];
-    slot_load(sbase, pos[0] & ~63u, pos[0] & 63u, wn);
-    for (int g = 0; g < NGROUPS; ++g) {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) wc[k] = wn[k];
-      if (g + 1 < NGROUPS) slot_load(sbase, pos[g + 1] & ~63u, pos[g + 1] & 63u, wn);
-      if (T[g] == 0) continue;
-      if (bfill && lo + bfill + T[g] > CAP) {
-        // store the full chunks, clear them, move the partial one to the front
-        wave_sync();
-        const uint32_t end = lo + bfill, nfull = end >> 4, tail = end & 15;
-        gout_u8* g0 = tile_chars + bstart - lo;
-        for (uint32_t k = lane; k < nfull; k += 64) {
-          const u32x4 v = cbv[k];
-          if (k == 0 && head_foreign) store_chunk_bytes(v, g0, lo, 16);
-          else __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
-          cbv[k] = u32x4{0u, 0u, 0u, 0u};
-        }
-        wave_sync();
-        if (lane == 0 && tail) {
-          cbv[0] = cbv[nfull];
-          cbv[nfull] = u32x4{0u, 0u, 0u, 0u};
-        }
-        wave_sync();
-        head_foreign = false;
-        bstart += bfill;
-        lo = tail;
-        bfill = 0;
-      }
-      if (pos[g] & 63u) slot_or(wc, sbase, pos[g] & ~63u, pos[g] & 63u, cb8, lo + (ex[g] - bstart));
-      bfill += T[g];
-    }
-    wave_sync();
-    const uint32_t end = lo + bfill, nst = (end + 15) >> 4, tail = end & 15;
-    gout_u8* g0 = tile_chars + bstart - lo;
-    for (uint32_t k = lane; k < nst; k += 64) {
-      const u32x4 v = cbv[k];
-      const uint32_t b0 = (k == 0 && head_foreign) ? lo : 0u;
-      const uint32_t b1 = (k + 1 == nst && tail) ? tail : 16u;
-      if (b0 == 0 && b1 == 16) __builtin_nontemporal_store(v, reinterpret_cast<gout_u32x4*>(g0 + 16 * k));
-      else store_chunk_bytes(v, g0 + 16 * k, b0, b1);
-    }
-  } else {
+  {
     // chars: consecutive groups are gathered into the wave's LDS buffer until
     // it is full, then the batch is stored with aligned 16-byte chunks (one
     // wait for earlier stores per batch, not per group); a group larger than
