@@ -19,7 +19,7 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
-                        uint32_t* err);
+                        uint32_t* err, uint64_t file_lim, uint64_t scratch_lim);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* sblk, int record, uint32_t* err);
 __global__ void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg,
@@ -599,8 +599,10 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     if (hipMalloc(&f->d_strck, sizeof(uint32_t) * strck) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: checkpoint allocation"); }
   }
   if (npages) {
-    hipLaunchKernelGGL(k_index, dim3((npages + 63) / 64), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
-                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err);
+    // one wave per page; the file is readable up to len rounded up to 16
+    hipLaunchKernelGGL(k_index, dim3(npages), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
+                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
+                       (uint64_t)scratch);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
   }
   HIP_OR(hipEventRecord(e1, s));

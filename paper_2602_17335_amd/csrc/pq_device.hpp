@@ -41,8 +41,9 @@ struct BR {
   }
 };
 
-// ULEB128 (at most 10 bytes) from [pos, end)
-__device__ __forceinline__ uint64_t br_uleb(BR& r, uint64_t& pos, uint64_t end, bool& bad) {
+// ULEB128 (at most 10 bytes) from [pos, end), through any reader with byte()
+template <class R>
+__device__ __forceinline__ uint64_t br_uleb(R& r, uint64_t& pos, uint64_t end, bool& bad) {
   uint64_t v = 0;
   for (int s = 0; s < 70; s += 7) {
     if (pos >= end) { bad = true; return 0; }

@@ -91,9 +91,69 @@ struct RunCur {
   uint32_t val;    // RLE value
 };
 
+// Stream reader of one wave for k_index: all 64 lanes walk the same stream
+// in lockstep (the walk is sequential; every lane computes the same values),
+// served from a WIN-byte LDS window that the wave refills with coalesced
+// 16-byte loads (one memory round trip per window instead of one per 16
+// bytes); every read is an LDS read (all lanes read the same address, a
+// broadcast).  The window keeps
+// 256 bytes before the position that moved it, for the short look-backs of
+// the walk (a run's payload).  Bytes at or past `lim` read as zero.
+constexpr uint32_t WIN = 4096;
+typedef uint32_t wr_u4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) wr_u4 lds_u4;
+
+// Refills the window for position a (a multiple of 16); returns its start.
+__device__ __noinline__ uint64_t wr_refill(const uint8_t* base, uint64_t lim, lds_u4* win, uint64_t a) {
+  const uint64_t wpos = a > 256 ? a - 256 : 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (uint32_t j = 0; j < WIN / 16 / 64; ++j) {
+    const uint32_t k = lane + 64 * j;
+    const uint64_t g = wpos + 16ull * k;
+    wr_u4 v = {0u, 0u, 0u, 0u};
+    if (g + 16 <= lim) v = *reinterpret_cast<const wr_u4*>(base + g);
+    win[k] = v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return wpos;
+}
+
+struct WR {
+  const uint8_t* base;
+  uint64_t lim;   // bytes of base that may be read (a multiple of 16)
+  uint64_t wpos;  // window start (a multiple of 16)
+  lds_u4* win;
+  __device__ __forceinline__ void init(const uint8_t* b, uint64_t l, lds_u4* w) {
+    base = b;
+    lim = l;
+    win = w;
+    wpos = ~0ull;
+  }
+  // the window holds bytes [off, off + n)
+  __device__ __forceinline__ void ensure(uint64_t off, uint32_t n) {
+    if (off < wpos || off + n - wpos > WIN) wpos = wr_refill(base, lim, win, off & ~15ull);
+  }
+  __device__ __forceinline__ uint32_t byte(uint64_t off) {
+    ensure(off, 1);
+    return reinterpret_cast<__attribute__((address_space(3))) uint8_t*>(win)[off - wpos];
+  }
+  __device__ __forceinline__ uint32_t u32(uint64_t off) {
+    ensure(off, 8);  // both aligned dwords holding bytes [off, off + 4)
+    const uint32_t o = (uint32_t)(off - wpos);
+    const __attribute__((address_space(3))) uint32_t* w32 = reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(win);
+    return __builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3);
+  }
+};
+
 // Reads the run header at cur.next; returns false when the stream ends or a
 // run leaves it.
-__device__ inline bool run_next(BR& r, uint64_t end, uint32_t w, RunCur& c) {
+__device__ inline bool run_next(WR& r, uint64_t end, uint32_t w, RunCur& c) {
   uint64_t pos = c.next;
   c.start += (int64_t)c.n;
   c.hp = pos;
@@ -125,7 +185,7 @@ __device__ inline bool run_next(BR& r, uint64_t end, uint32_t w, RunCur& c) {
 }
 
 // number of set bits among the first `k` values of a bit-packed w=1 run
-__device__ inline uint32_t bp_popcount(BR& r, uint64_t pay, uint64_t k) {
+__device__ inline uint32_t bp_popcount(WR& r, uint64_t pay, uint64_t k) {
   uint32_t s = 0;
   uint64_t full = k >> 3;
   for (uint64_t i = 0; i < full; ++i) s += __popc(r.byte(pay + i));
@@ -190,17 +250,22 @@ __device__ __forceinline__ Ck ck_none() {
   return k;
 }
 
-// One lane per page.  `scratch` holds every compressed page decompressed at
-// its file-wide scratch offset.
-__global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
-                        const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
-                        uint32_t* err) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per page (a 64-thread workgroup; every lane runs the same walk
+// and stores the same values).  `scratch` holds every compressed page
+// decompressed at its file-wide scratch offset; file_lim and scratch_lim are
+// the readable bytes of the two buffers (multiples of 16).
+__global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
+                                              const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl,
+                                              Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim) {
+  __shared__ wr_u4 s_win[WIN / 16];
+  const int p = blockIdx.x;
   if (p >= npages) return;
   PageDev pg = pages[p];
   ChunkDev ch = chunks[pg.chunk];
   const bool in_scratch = pg.scratch_len > 0;
-  BR r;
+  WR r;
+  lds_u4* win = (lds_u4*)&s_win[0];
+  auto lim_of = [&](const uint8_t* b) { return b == file ? file_lim : scratch_lim; };
 
   if (pg.kind == PAGE_DICT) {
     const uint8_t* base = in_scratch ? scratch : file;
@@ -210,7 +275,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     pg.val_len = (uint32_t)blen;
     pg.flags = in_scratch ? 2 : 0;
     if (ch.type == T_BYTE_ARRAY) {
-      r.init(base);
+      r.init(base, lim_of(base), win);
       uint64_t q = 0;
       uint32_t maxlen = 0;
       for (int64_t k = 0; k < pg.num_values; ++k) {
@@ -240,7 +305,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
     uint64_t off = in_scratch ? pg.scratch_off : pg.payload;
     uint64_t blen = pg.uncomp_size;
     dbase = vbase = base;
-    r.init(base);
+    r.init(base, lim_of(base), win);
     if (ch.optional) {
       if (blen < 4) { set_err(err, ERR_LEVELS, p); return; }
       uint64_t L = r.u32(off);
@@ -278,7 +343,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
   // ---- definition levels: tile entry points, sub-tile checkpoints, non-null counts ----
   uint32_t nonnull = 0;
   if (ch.optional) {
-    r.init(dbase);
+    r.init(dbase, lim_of(dbase), win);
     const uint64_t end = def_off + def_len;
     RunCur c;
     c.next = def_off; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = def_off;
@@ -340,7 +405,7 @@ __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pa
   }
 
   // ---- value stream entry points ----
-  r.init(vbase);
+  r.init(vbase, lim_of(vbase), win);
   const uint64_t vend = val_off + val_len;
   const int enc = pg.encoding;
   if (enc == E_PLAIN && ch.type != T_BYTE_ARRAY) {
