@@ -100,6 +100,7 @@ struct RunCur {
 // 256 bytes before the position that moved it, for the short look-backs of
 // the walk (a run's payload).  Bytes at or past `lim` read as zero.
 constexpr uint32_t WIN = 4096;
+static_assert(NLCK == 64, "lane k of a wave writes level checkpoint k of a tile");
 typedef uint32_t wr_u4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) wr_u4 lds_u4;
 
@@ -258,6 +259,10 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
                                               const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl,
                                               Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim) {
   __shared__ wr_u4 s_win[WIN / 16];
+  // DELTA pages of at most TC tiles: first value, value count and value
+  // entry of every tile, so that the block walk reads no tile from memory
+  constexpr uint32_t TC = 2048;
+  __shared__ uint32_t s_k0[TC], s_nn[TC], s_vp[TC];
   const int p = blockIdx.x;
   if (p >= npages) return;
   PageDev pg = pages[p];
@@ -265,6 +270,11 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   const bool in_scratch = pg.scratch_len > 0;
   WR r;
   lds_u4* win = (lds_u4*)&s_win[0];
+  // Stores that nothing in this kernel reads back (checkpoints) come from
+  // lane 0 alone: 64 lanes storing to one address would be 64 writes.
+  // Tiles and the page entry are stored by every lane (each lane reads back
+  // its own stores).
+  const bool lead = (threadIdx.x & 63) == 0;
   auto lim_of = [&](const uint8_t* b) { return b == file ? file_lim : scratch_lim; };
 
   if (pg.kind == PAGE_DICT) {
@@ -275,17 +285,28 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
     pg.val_len = (uint32_t)blen;
     pg.flags = in_scratch ? 2 : 0;
     if (ch.type == T_BYTE_ARRAY) {
-      r.init(base, lim_of(base), win);
-      uint64_t q = 0;
-      uint32_t maxlen = 0;
-      for (int64_t k = 0; k < pg.num_values; ++k) {
-        if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = (uint32_t)q;
-        if (blen - q < 4) { set_err(err, ERR_STRING, p); return; }
-        uint32_t l = r.u32(off + q);
-        q += 4;
-        if (l > blen - q) { set_err(err, ERR_STRING, p); return; }
-        q += l;
-        maxlen = max(maxlen, l);
+      // the length-prefix chain in 32-bit positions (a page is below 4 GiB):
+      // q in the page body, o in the LDS window, one LDS read per entry; the
+      // window moves when an entry's length prefix would leave it
+      const uint64_t blim = lim_of(base);
+      const uint32_t n = pg.num_values > 0 ? (uint32_t)pg.num_values : 0u;
+      const uint32_t bl = (uint32_t)blen;
+      const __attribute__((address_space(3))) uint32_t* w32 =
+          reinterpret_cast<const __attribute__((address_space(3))) uint32_t*>(win);
+      uint32_t q = 0, maxlen = 0, k = 0;
+      while (k < n) {
+        const uint64_t wpos = wr_refill(base, blim, win, (off + q) & ~15ull);
+        uint32_t o = (uint32_t)(off + q - wpos);  // below 272
+        while (k < n && o + 8 <= WIN) {
+          if ((k % STR_CK) == 0 && lead) strck[pg.strck_begin + k / STR_CK] = q;
+          if (bl - q < 4) { set_err(err, ERR_STRING, p); return; }
+          const uint32_t l = __builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3);
+          if (l > bl - q - 4) { set_err(err, ERR_STRING, p); return; }
+          q += 4 + l;
+          o = l < WIN ? o + 4 + l : WIN;
+          maxlen = max(maxlen, l);
+          ++k;
+        }
       }
       pg.dict_maxlen = maxlen;
     } else {
@@ -368,10 +389,13 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
         td.val_pos = 0;
         td.val_skip = 0;
         tiles[pg.tile_begin + t] = td;
-        for (int k = 0; k < NLCK; ++k) ckl[(size_t)(pg.tile_begin + t) * NLCK + k] = LCK_NONE;
       }
-      ckl[(size_t)(pg.tile_begin + t) * NLCK + sub] = make_lck(c, target, def_off + td.def_pos);
+      if (lead) ckl[(size_t)(pg.tile_begin + t) * NLCK + sub] = make_lck(c, target, def_off + td.def_pos);
     }
+    // the last tile's checkpoints past the page's rows
+    if (nv > 0 && lead)
+      for (int64_t target = ((nv + LROWS - 1) / LROWS) * LROWS; target % TILE_ROWS != 0; target += LROWS)
+        ckl[(size_t)(pg.tile_begin + (uint32_t)(target / TILE_ROWS)) * NLCK + (target % TILE_ROWS) / LROWS] = LCK_NONE;
     if (nv > 0) {
       while (!have || c.start + (int64_t)c.n < nv) {
         if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
@@ -391,11 +415,12 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       td.nn = 0;
       td.def_pos = 0; td.def_skip = 0; td.val_pos = 0; td.val_skip = 0;
       tiles[pg.tile_begin + t] = td;
-      for (int k = 0; k < NLCK; ++k) ckl[(size_t)(pg.tile_begin + t) * NLCK + k] = LCK_NONE;
+      ckl[(size_t)(pg.tile_begin + t) * NLCK + (threadIdx.x & 63)] = LCK_NONE;  // lane k: checkpoint k
     }
   }
-  for (uint32_t t = 0; t < ntiles; ++t)
-    for (int k = 0; k < NSUB; ++k) ckv[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
+  if (lead)
+    for (uint32_t t = 0; t < ntiles; ++t)
+      for (int k = 0; k < NSUB; ++k) ckv[(size_t)(pg.tile_begin + t) * NSUB + k] = ck_none();
   if (pg.kind == PAGE_DATA_V2 && (int64_t)pg.num_nulls != nv - (int64_t)nonnull) { set_err(err, ERR_V2, p); return; }
   pg.nonnull = nonnull;
   for (uint32_t t = 0; t < ntiles; ++t) {
@@ -421,7 +446,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
         ++t;
       }
       if (k == nonnull) break;
-      if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = (uint32_t)(q - val_off);
+      if ((k % STR_CK) == 0 && lead) strck[pg.strck_begin + k / STR_CK] = (uint32_t)(q - val_off);
       if (vend - q < 4) { set_err(err, ERR_STRING, p); return; }
       uint32_t l = r.u32(q);
       q += 4;
@@ -452,7 +477,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
             tdr.val_pos = (uint32_t)(c.hp - val_off);
             tdr.val_skip = (uint32_t)(target - c.start);
           }
-          ckv[(size_t)(pg.tile_begin + t) * NSUB + sub] = make_ck(c, target, w, val_off + tdr.val_pos, false);
+          if (lead) ckv[(size_t)(pg.tile_begin + t) * NSUB + sub] = make_ck(c, target, w, val_off + tdr.val_pos, false);
         }
       }
       while (!have || c.start + (int64_t)c.n < (int64_t)nonnull) {
@@ -478,38 +503,51 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
     pg.blocks_at = (uint32_t)(q - val_off);
     // block b holds values [1 + b*B, 1 + (b+1)*B); value 0 is in the header
     const uint64_t nblocks = total > 1 ? (total - 1 + B - 1) / B : 0;
+    const bool cached = ntiles <= TC;
     for (uint32_t t = 0; t < ntiles; ++t) {
       tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
       tiles[pg.tile_begin + t].val_skip = 0;
+      if (cached) {  // every lane wrote every tile above, so each reads its own stores
+        s_k0[t] = tiles[pg.tile_begin + t].k0;
+        s_nn[t] = tiles[pg.tile_begin + t].nn;
+        s_vp[t] = (uint32_t)(q - val_off);
+      }
     }
+    auto tile_k0 = [&](uint32_t x) { return cached ? s_k0[x] : tiles[pg.tile_begin + x].k0; };
+    auto tile_nn = [&](uint32_t x) { return cached ? s_nn[x] : tiles[pg.tile_begin + x].nn; };
+    auto tile_vp = [&](uint32_t x) { return cached ? s_vp[x] : tiles[pg.tile_begin + x].val_pos; };
     uint32_t t = 0, ulo = 0;
     for (uint64_t b = 0; b < nblocks; ++b) {
       while (t < ntiles) {
-        const TileDev td = tiles[pg.tile_begin + t];
-        const uint64_t last = (uint64_t)td.k0 + td.nn;  // one past the tile's last value
-        if (td.nn == 0 || last <= 1) { ++t; continue; }  // needs no block
-        const uint64_t first = td.k0 == 0 ? 1 : td.k0;
+        const uint32_t k0t = tile_k0(t), nnt = tile_nn(t);
+        const uint64_t last = (uint64_t)k0t + nnt;  // one past the tile's last value
+        if (nnt == 0 || last <= 1) { ++t; continue; }  // needs no block
+        const uint64_t first = k0t == 0 ? 1 : k0t;
         const uint64_t nb = (first - 1) / B;
         if (nb != b) break;
         tiles[pg.tile_begin + t].val_pos = (uint32_t)(q - val_off);
         tiles[pg.tile_begin + t].val_skip = (uint32_t)((first - 1) % B);
+        if (cached) s_vp[t] = (uint32_t)(q - val_off);
         ++t;
       }
       // this block's header, as checkpoint (b - entry block) of every tile
       // entered so far whose deltas reach block b; tiles before `ulo` end
       // before it
       while (ulo < t) {
-        const TileDev tu = tiles[pg.tile_begin + ulo];
-        if (tu.nn != 0 && (uint64_t)tu.k0 + tu.nn > 1 && ((uint64_t)tu.k0 + tu.nn - 2) / B >= b) break;
+        const uint32_t k0u = tile_k0(ulo), nnu = tile_nn(ulo);
+        if (nnu != 0 && (uint64_t)k0u + nnu > 1 && ((uint64_t)k0u + nnu - 2) / B >= b) break;
         ++ulo;
       }
       for (uint32_t u = ulo; u < t; ++u) {
-        const TileDev tu = tiles[pg.tile_begin + u];
+        TileDev tu;
+        tu.k0 = tile_k0(u);
+        tu.nn = tile_nn(u);
+        tu.val_pos = tile_vp(u);
         if (tu.nn == 0 || (uint64_t)tu.k0 + tu.nn <= 1) continue;
         const uint64_t fu = tu.k0 == 0 ? 1 : tu.k0;
         const uint64_t bu = (fu - 1) / B;                    // entry block of tile u
         const uint64_t lastb = ((uint64_t)tu.k0 + tu.nn - 2) / B;  // block of its last delta
-        if (b >= bu && b <= lastb && b - bu < NSUB)
+        if (b >= bu && b <= lastb && b - bu < NSUB && lead)
           ckv[(size_t)(pg.tile_begin + u) * NSUB + (b - bu)] = ck_at(q - val_off - tu.val_pos);
       }
       br_uleb(r, q, vend, bad);  // min delta
