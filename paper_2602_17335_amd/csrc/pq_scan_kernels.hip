@@ -1277,9 +1277,41 @@ __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, ui
   }
 }
 
-// n bytes, 64 per step (each step one round of loads)
-__device__ __forceinline__ void lane_copy(uint8_t* dst, const uint8_t* src, uint32_t n) {
-  for (uint32_t i = 0; i < n; i += 64) lane_copy64(dst + i, src + i, min(64u, n - i));
+// The wave's active lanes (rank r of nact) copy n bytes s -> d together (a
+// literal: no overlap), 16 destination bytes per lane and step.  Destination
+// dword k (counted from d's dword) holds source bytes [4 k - sh, 4 k - sh +
+// 4), sh = d & 3; every dword is stored whole except dword 0 when d is not
+// dword-aligned (its bytes before d are earlier output, written bytewise), so
+// up to 3 bytes after d + n are overwritten, which the owning lane's next
+// element writes again (a block ends on a 16-byte boundary, a page inside its
+// scratch padding).  Reads at most 3 bytes before s and 7 after s + n.
+__device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t n, uint32_t r, uint32_t nact) {
+  const uint32_t sh = (uint32_t)((uintptr_t)d & 3);
+  __attribute__((address_space(1))) uint32_t* dw =
+      (__attribute__((address_space(1))) uint32_t*)((uintptr_t)d & ~(uintptr_t)3);
+  const uint32_t nd = (sh + n + 3) >> 2;       // destination dwords
+  const uintptr_t a0 = (uintptr_t)s - sh;      // source byte of destination dword 0's first byte
+  const uint32_t e = (uint32_t)(a0 & 3);
+  const __attribute__((address_space(1))) uint32_t* q =
+      (const __attribute__((address_space(1))) uint32_t*)(a0 & ~(uintptr_t)3);
+  for (uint32_t k0 = 4 * r; k0 < nd; k0 += 4 * nact) {
+    uint32_t w[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w[c] = k0 + c <= nd ? q[k0 + c] : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k = k0 + j;
+      const uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], e);
+      if (k == 0 && sh) {
+        uint8_t* bp = (uint8_t*)dw;
+#pragma unroll
+        for (int i = 1; i < 4; ++i)
+          if ((uint32_t)i >= sh && (uint32_t)i - sh < n) bp[i] = (uint8_t)(v >> (8 * i));
+      } else if (k < nd) {
+        dw[k] = v;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1360,12 +1392,14 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
       nip = ip + hl;
     }
     if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
-    // one copy routine for a literal's first 64 bytes and for a copy that
-    // does not overlap its output (which reads this lane's earlier output)
-    if (lit || off >= len)
-      lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)min(L, (uint64_t)64) : len);
+    // one copy routine for a literal of at most 64 bytes and for a copy that
+    // does not overlap its output (which reads this lane's earlier output);
+    // longer literals are copied by the whole wave below
+    const bool big = lit && L > 64;
+    const uint32_t op0 = op;
+    if ((lit && !big) || (!lit && off >= len))
+      lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)L : len);
     if (lit) {
-      if (L > 64) lane_copy(dst + op + 64, src + ip + hl + 64, (uint32_t)L - 64);
       op += (uint32_t)L;
     } else {
       if (off < len) {  // the copy overlaps its output: bytes repeat with period off
@@ -1383,6 +1417,25 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
         }
       }
       op += len;
+    }
+    // long literals of this step, one after the other, each copied by every
+    // active lane (a lane's later loads see them: the wave's stores are
+    // performed in order)
+    uint64_t m = __ballot(big);
+    if (m) {
+      const uint64_t act = __ballot(1);
+      const uint32_t nact = (uint32_t)__popcll(act), r = rank_below(act);
+      const uintptr_t bd = (uintptr_t)(dst + op0), bs = (uintptr_t)(src + ip + hl);
+      const uint32_t bn = (uint32_t)L;
+      while (m) {
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        uint8_t* d = (uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bd >> 32), l) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bd, l));
+        const uint8_t* s = (const uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bs >> 32), l) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bs, l));
+        wave_copy(d, s, (uint32_t)__builtin_amdgcn_readlane((int)bn, l), r, nact);
+      }
     }
     ip = nip;
   }
