@@ -1403,8 +1403,8 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
       op += (uint32_t)L;
     } else {
       if (off < len) {  // the copy overlaps its output: bytes repeat with period off
+        uint32_t r = 0;   // k0 mod off, carried from chunk to chunk
         for (uint32_t k0 = 0; k0 < len; k0 += 8) {
-          uint32_t r = k0 % off;
           uint32_t bb[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
