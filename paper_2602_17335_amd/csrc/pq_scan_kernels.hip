@@ -88,6 +88,9 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+typedef uint32_t u32x4w __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes at a dword address
+typedef const __attribute__((address_space(1))) u32x4w glb_u32x4w;
+
 struct GSrc {
   using P = uint64_t;  // stream positions (bytes, bits)
   using I = int64_t;   // value numbers
@@ -108,6 +111,13 @@ struct GSrc {
     uint64_t v = ((uint64_t)q[0] | ((uint64_t)q[1] << 32)) >> sh;
     if (sh + w > 64) v |= (uint64_t)q[2] << (64 - sh);
     return w == 64 ? v : (v & ((1ull << w) - 1));
+  }
+  // the 4 dwords from the one holding bit `bit` (16 bytes: reads at most 15
+  // past the bit's byte); s receives the bit's offset in the first
+  __device__ __forceinline__ u32x4w quad(uint64_t bit, uint32_t& s) const {
+    const uint64_t b = origin * 8 + bit;
+    s = (uint32_t)(b & 31);
+    return *(glb_u32x4w*)(reinterpret_cast<glb_u32*>(base) + (b >> 5));
   }
   // little-endian u32 / u64 at byte position pos: aligned dwords joined with
   // byte funnel shifts (no data-dependent branch, so a wave issues all its
@@ -155,6 +165,11 @@ struct GSrc32 {
     const uint32_t d = b >> 5;
     const uint32_t v = __builtin_amdgcn_alignbit(abase[d + 1], abase[d], b & 31);
     return v & (w >= 32 ? 0xffffffffu : ((1u << w) - 1u));
+  }
+  __device__ __forceinline__ u32x4w quad(uint32_t bit, uint32_t& s) const {
+    const uint32_t b = bit + 8 * m;
+    s = b & 31;
+    return *(glb_u32x4w*)(abase + (b >> 5));
   }
   // w (<= 64) bits at bit position `bit`
   __device__ __forceinline__ uint64_t bits64(uint32_t bit, uint32_t w) const {
@@ -527,12 +542,31 @@ __device__ __forceinline__ uint32_t decode_indices(const WaveTile& c, Ck ck, uin
     return ck_walk(vs, (P)c.td.val_pos, ck, (I)(lane >> 2) * SUB_ROWS, w, false, (I)a, (I)b, (P)c.td.val_pos,
                    -(I)c.td.val_skip, [&](I lo, I hi, bool bp, P x) {
       if (bp) {
-        // a piece holds at most LPER values: every load first (positions
-        // past the piece repeat value lo's, which lies in the stream), then
-        // the checks and the LDS stores
+        // a piece holds at most LPER values: every load first, then the
+        // checks and the LDS stores.  Up to 24 bits, four values lie in the
+        // 16 bytes from the dword holding the first one's bit (t < 104 and
+        // t + w <= 128 below): one load per four values.  Wider: one per
+        // value (positions past the piece repeat value lo's, which lies in
+        // the stream).
         uint32_t id[LPER];
+        if (w <= 24) {
+          const uint32_t mask = (1u << w) - 1u;
 #pragma unroll
-        for (int j = 0; j < LPER; ++j) id[j] = (uint32_t)vs.bits(lo + (I)j < hi ? x + (P)j * w : x, w);
+          for (int g = 0; g < LPER / 4; ++g) {
+            uint32_t sg = 0;
+            const u32x4w Q = vs.quad(lo + (I)(4 * g) < hi ? x + (P)(4 * g) * w : x, sg);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t t = sg + (uint32_t)j * w, k = t >> 5;
+              const uint32_t a = k == 0 ? Q.x : k == 1 ? Q.y : k == 2 ? Q.z : Q.w;
+              const uint32_t b = k == 0 ? Q.y : k == 1 ? Q.z : k == 2 ? Q.w : 0u;
+              id[4 * g + j] = __builtin_amdgcn_alignbit(b, a, t & 31) & mask;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < LPER; ++j) id[j] = (uint32_t)vs.bits(lo + (I)j < hi ? x + (P)j * w : x, w);
+        }
 #pragma unroll
         for (int j = 0; j < LPER; ++j) {
           if (lo + (I)j < hi) {
