@@ -183,3 +183,68 @@ def test_column_encodings_match_page_headers():
     got = [f.column_encodings(c) for c in range(f.num_columns)]
     assert got == want
     assert any(bin(m).count("1") > 1 for m in want)  # the dictionary fallback mixes encodings
+
+
+def _string_spec():
+    return dg.FileSpec(cols=[
+        dg.Col(dg.BYTE_ARRAY, dg.PLAIN, True, dg.STRINGS, 0.1, hi=5000, str_min=0, str_max=40),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=300, str_min=8, str_max=44),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=200, str_min=61, str_max=200),
+    ], num_rows=40_011, rg_rows=15_000, page_bytes=32 * dg.KiB, name="strings")
+
+
+def test_chars_capacity_reported_and_respected():
+    """A chars buffer below the planned size: pq_scan_check reports
+    PQ_ECAPACITY and no byte past chars_capacity is written (PLAIN strings,
+    slot dictionary, dictionary without slots)."""
+    import torch
+    import paper_2602_17335_amd as pqs
+    buf, n = pqs.to_device(dg.write(_string_spec()))
+    f = pqs.DeviceFile(buf, n)
+    for c in range(3):
+        mask, rg_end, ws, outs, tens = f.allocate([c])
+        need = tens[c]["chars_bytes"]
+        assert need > 1000, (c, need)
+        cap = need // 2 + 3
+        guard = torch.full((need + 4096,), 0xAB, dtype=torch.uint8, device="cuda")
+        outs[0].chars = guard.data_ptr()
+        outs[0].chars_capacity = cap
+        print(f"[gpu] capacity col{c}: need {need}, capacity {cap}", flush=True)
+        f.scan_into(mask, 0, rg_end, outs, ws)
+        with pytest.raises(pqs.PqError) as e:
+            f.check()
+        assert e.value.code == pqs.PQ_ECAPACITY, (c, e.value.code)
+        assert bool((guard[cap:] == 0xAB).all()), f"col{c}: bytes written past chars_capacity"
+        # the same handle scans correctly afterwards
+        out = f.scan([c])
+        assert int(out[c]["offsets"][-1]) == need
+
+
+def test_workspace_too_small_rejected_before_gpu_work():
+    import torch
+    import paper_2602_17335_amd as pqs
+    buf, n = pqs.to_device(dg.write(_string_spec()))
+    f = pqs.DeviceFile(buf, n)
+    mask, rg_end, ws, outs, tens = f.allocate([0, 1, 2])
+    small = torch.empty(max(ws.numel() // 2, 256), dtype=torch.uint8, device="cuda")
+    with pytest.raises(pqs.PqError) as e:
+        f.scan_into(mask, 0, rg_end, outs, small)
+    assert e.value.code == pqs.PQ_ECAPACITY
+    f.check()  # nothing was enqueued, so no device error either
+
+
+def test_plan_chars_bytes_match_oracle():
+    """pq_plan (host-only, from the tile prefix built at open) gives every
+    string column's exact chars size on every row-group range."""
+    import oracle
+    import paper_2602_17335_amd as pqs
+    data = dg.write(_string_spec())
+    buf, n = pqs.to_device(data)
+    f = pqs.DeviceFile(buf, n)
+    of = oracle.File(data)
+    nrg = f.num_row_groups
+    for rb in range(nrg + 1):
+        for re_ in range(rb, nrg + 1):
+            sz = f.plan(0b111, rb, re_)
+            for c in range(3):
+                assert int(sz.chars_bytes[c]) == of.read(c, rb, re_)["chars"].size, (c, rb, re_)
