@@ -106,7 +106,9 @@ typedef __attribute__((address_space(3))) wr_u4 lds_u4;
 
 // Refills the window for position a (a multiple of 16); returns its start.
 __device__ __noinline__ uint64_t wr_refill(const uint8_t* base, uint64_t lim, lds_u4* win, uint64_t a) {
-  const uint64_t wpos = a > 256 ? a - 256 : 0;
+  uint64_t wpos = a > 256 ? a - 256 : 0;
+  wpos = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(wpos >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wpos);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -140,15 +142,19 @@ struct WR {
   __device__ __forceinline__ void ensure(uint64_t off, uint32_t n) {
     if (off < wpos || off + n - wpos > WIN) wpos = wr_refill(base, lim, win, off & ~15ull);
   }
+  // every lane reads the same byte, so the value is moved to a scalar
+  // register: the walk that follows runs on the scalar unit, with scalar
+  // branches instead of exec-mask updates
   __device__ __forceinline__ uint32_t byte(uint64_t off) {
     ensure(off, 1);
-    return reinterpret_cast<__attribute__((address_space(3))) uint8_t*>(win)[off - wpos];
+    return (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)reinterpret_cast<__attribute__((address_space(3))) uint8_t*>(win)[off - wpos]);
   }
   __device__ __forceinline__ uint32_t u32(uint64_t off) {
     ensure(off, 8);  // both aligned dwords holding bytes [off, off + 4)
     const uint32_t o = (uint32_t)(off - wpos);
     const __attribute__((address_space(3))) uint32_t* w32 = reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(win);
-    return __builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3));
   }
 };
 
@@ -186,13 +192,24 @@ __device__ inline bool run_next(WR& r, uint64_t end, uint32_t w, RunCur& c) {
 }
 
 // number of set bits among the first `k` values of a bit-packed w=1 run
+// (1024 bits per window check, then a dword per 32 bits straight from LDS)
 __device__ inline uint32_t bp_popcount(WR& r, uint64_t pay, uint64_t k) {
   uint32_t s = 0;
-  uint64_t full = k >> 3;
-  for (uint64_t i = 0; i < full; ++i) s += __popc(r.byte(pay + i));
-  uint32_t rem = (uint32_t)(k & 7);
-  if (rem) s += __popc(r.byte(pay + full) & ((1u << rem) - 1));
-  return s;
+  const __attribute__((address_space(3))) uint32_t* w32 =
+      reinterpret_cast<const __attribute__((address_space(3))) uint32_t*>(r.win);
+  for (uint64_t b0 = 0; b0 < k; b0 += 1024) {
+    const uint32_t kk = (uint32_t)min(k - b0, (uint64_t)1024);
+    const uint64_t off = pay + (b0 >> 3);
+    r.ensure(off, 136);  // the 128 bytes and the dword after them
+    const uint32_t o = (uint32_t)(off - r.wpos), sh = o & 3, d = o >> 2;
+    for (uint32_t i = 0; 32 * i < kk; ++i) {
+      uint32_t v = __builtin_amdgcn_alignbyte(w32[d + i + 1], w32[d + i], sh);
+      const uint32_t left = kk - 32 * i;
+      if (left < 32) v &= (1u << left) - 1u;
+      s += __popc(v);
+    }
+  }
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)s);
 }
 
 // Checkpoint of value `target` inside run c of a w-bit hybrid stream whose
