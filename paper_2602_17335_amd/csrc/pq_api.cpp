@@ -19,7 +19,7 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
-                        uint32_t* err, uint64_t file_lim, uint64_t scratch_lim);
+                        uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order);
 __global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
                          uint32_t* sblk, int record, uint32_t* err);
 __global__ void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg,
@@ -557,11 +557,14 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   // ---- compressed pages decompressed once for the index pass ----
   uint8_t* d_scratch = nullptr;
   ColScan* d_cs = nullptr;
+  uint32_t* d_order = nullptr;
   auto cleanup_open = [&]() {
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_cs) (void)hipFree(d_cs);
+    if (d_order) (void)hipFree(d_order);
     d_scratch = nullptr;
     d_cs = nullptr;
+    d_order = nullptr;
   };
   if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
   // Snappy block index, recorded by the decompression below
@@ -599,10 +602,26 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     if (hipMalloc(&f->d_strck, sizeof(uint32_t) * strck) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: checkpoint allocation"); }
   }
   if (npages) {
-    // one wave per page; the file is readable up to len rounded up to 16
+    // one wave per page, the longest walks first (string dictionaries by
+    // bytes, then data pages by rows), so that they start at once instead of
+    // behind the waves of earlier pages; the file is readable up to len
+    // rounded up to 16
+    std::vector<uint32_t> order(npages);
+    std::vector<uint64_t> work(npages);
+    for (uint32_t p = 0; p < npages; ++p) {
+      const PageDev& pg = f->pages[p];
+      const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY;
+      work[p] = sdict ? 16ull * pg.uncomp_size : (uint64_t)(pg.num_values > 0 ? pg.num_values : 0);
+      order[p] = p;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
+    if (hipMalloc(&d_order, sizeof(uint32_t) * npages) != hipSuccess ||
+        hipMemcpy(d_order, order.data(), sizeof(uint32_t) * npages, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: page order");
+    }
     hipLaunchKernelGGL(k_index, dim3(npages), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
                        f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
-                       (uint64_t)scratch);
+                       (uint64_t)scratch, d_order);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
   }
   HIP_OR(hipEventRecord(e1, s));

@@ -274,14 +274,15 @@ __device__ __forceinline__ Ck ck_none() {
 // the readable bytes of the two buffers (multiples of 16).
 __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                                               const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl,
-                                              Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim) {
+                                              Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim,
+                                              const uint32_t* order) {
   __shared__ wr_u4 s_win[WIN / 16];
   // DELTA pages of at most TC tiles: first value, value count and value
   // entry of every tile, so that the block walk reads no tile from memory
   constexpr uint32_t TC = 2048;
   __shared__ uint32_t s_k0[TC], s_nn[TC], s_vp[TC];
-  const int p = blockIdx.x;
-  if (p >= npages) return;
+  if ((int)blockIdx.x >= npages) return;
+  const int p = (int)order[blockIdx.x];  // workgroup i walks page order[i]
   PageDev pg = pages[p];
   ChunkDev ch = chunks[pg.chunk];
   const bool in_scratch = pg.scratch_len > 0;
