@@ -374,10 +374,11 @@ static pq_status read_err(pq_file f, hipStream_t s) {
   return PQ_OK;
 }
 
-static SegTable make_segs(const std::vector<Segment>& v) {
+static SegTable make_segs(const std::vector<Segment>& v, bool spread = false) {
   SegTable t;
   memset(&t, 0, sizeof(t));
   t.n = (int32_t)v.size();
+  t.spread = spread ? 1 : 0;
   for (size_t i = 0; i < v.size(); ++i) t.s[i] = v[i];
   return t;
 }
@@ -709,44 +710,12 @@ struct Plan {
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
   uint32_t sblk_lanes = 0;
+  bool str_spread[2] = {false, false};  // k_decode_str<k>: columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
   std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
   uint64_t ws_which = 0;
 };
-
-// Interleaves the columns of one launch's work list: each column's tiles are
-// cut into chunks of at least IL_CHUNK tiles (within MAX_SEGS segments) and
-// the chunks are taken round-robin, so that the columns' waves run side by
-// side (a column bound by random dictionary gathers beside one bound by
-// instruction issue) instead of one column after another.
-constexpr uint32_t IL_CHUNK = 4096;
-
-static void interleave(std::vector<Segment>& v) {
-  if (v.size() < 2 || v.size() >= (size_t)MAX_SEGS) return;
-  const uint32_t per = (uint32_t)(MAX_SEGS / v.size());
-  std::vector<std::vector<Segment>> parts(v.size());
-  size_t most = 0;
-  for (size_t i = 0; i < v.size(); ++i) {
-    const uint32_t n = v[i].t1 - v[i].t0;
-    const uint32_t nc = std::max(1u, std::min(per, (n + IL_CHUNK - 1) / IL_CHUNK));
-    const uint32_t step = (n + nc - 1) / nc;
-    for (uint32_t a = v[i].t0; a < v[i].t1; a += step)
-      parts[i].push_back(Segment{v[i].cs, a, std::min(a + step, v[i].t1), 0});
-    most = std::max(most, parts[i].size());
-  }
-  std::vector<Segment> out;
-  uint32_t units = v[0].wg0;
-  for (size_t r = 0; r < most; ++r)
-    for (auto& pp : parts)
-      if (r < pp.size()) {
-        Segment sg = pp[r];
-        sg.wg0 = units;
-        units += sg.t1 - sg.t0;
-        out.push_back(sg);
-      }
-  v.swap(out);
-}
 
 // Work lists and workspace layout of a scan of `mask` over row groups
 // [rg_b, rg_e).  With `index`, the plan of the open-time prefix pass instead:
@@ -887,10 +856,17 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     }
     P.cols.push_back(cs);
   }
-  // (the string kernel only: its columns differ -- a 10^6-entry dictionary
-  // bound by gathers beside small ones bound by instruction issue -- while
-  // interleaving the streaming fixed-width columns made them 4-8 % slower)
-  for (int k = 0; k < 2; ++k) interleave(P.str_segs[k]);
+  // The string kernel's columns run side by side: wave u takes tile u / n of
+  // column u % n (a 10^6-entry dictionary bound by random gathers beside
+  // small ones bound by instruction issue).  Interleaving the streaming
+  // fixed-width columns made them 4-8 % slower, so they stay in order.
+  for (int k = 0; k < 2; ++k) {
+    if (P.str_segs[k].size() < 2) continue;
+    uint32_t most = 0;
+    for (const Segment& sg : P.str_segs[k]) most = std::max(most, sg.t1 - sg.t0);
+    P.str_spread[k] = true;
+    P.str_units[k] = (uint32_t)P.str_segs[k].size() * most;
+  }
   P.ws_total = std::max<uint64_t>(off, 256);
   return PQ_OK;
 }
@@ -992,7 +968,7 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
     ProfScope ps_(f, k ? KP_STR_SLOTS : KP_STR, s);
     hipLaunchKernelGGL(k ? k_decode_str<true> : k_decode_str<false>, dim3((P.str_units[k] + 3) / 4), dim3(256), 0, s,
                        file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, d_slots, f->d_strck, f->d_tpfx,
-                       make_segs(P.str_segs[k]), f->d_err);
+                       make_segs(P.str_segs[k], P.str_spread[k]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.edge_threads) {

@@ -199,10 +199,12 @@ struct Segment {
   uint32_t cs, t0, t1, wg0;
 };
 constexpr int MAX_SEGS = 64;
+// With spread set, unit u of the launch is tile u / n of segment u % n (the
+// segments' wg0 unused): consecutive waves take tiles of different segments.
 struct SegTable {
   Segment s[MAX_SEGS];
   int32_t n;
-  int32_t pad_;
+  int32_t spread;
 };
 
 // k_dict work: dictionary slot `slot` of selected column `col` is units

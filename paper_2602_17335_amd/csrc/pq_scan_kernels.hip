@@ -274,9 +274,15 @@ __device__ __forceinline__ bool wave_tile(const SegTable& seg, const ColScan* co
                                           const TileDev* tiles, const uint8_t* file, uint8_t* ws, WaveTile& c) {
   const uint32_t unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVES + (threadIdx.x >> 6)));
   int k = 0;
-  for (int j = 1; j < seg.n; ++j)
-    if (seg.s[j].wg0 <= unit) k = j;
-  const uint32_t t = seg.s[k].t0 + (unit - seg.s[k].wg0);
+  uint32_t t;
+  if (seg.spread) {
+    k = (int)(unit % (uint32_t)seg.n);
+    t = seg.s[k].t0 + unit / (uint32_t)seg.n;
+  } else {
+    for (int j = 1; j < seg.n; ++j)
+      if (seg.s[j].wg0 <= unit) k = j;
+    t = seg.s[k].t0 + (unit - seg.s[k].wg0);
+  }
   if (t >= seg.s[k].t1) return false;
   c.t = t;
   c.td = tiles[t];
