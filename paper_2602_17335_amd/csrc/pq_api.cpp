@@ -710,7 +710,7 @@ struct Plan {
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
   uint32_t sblk_lanes = 0;
-  bool str_spread[2] = {false, false};  // k_decode_str<k>: columns interleaved wave by wave
+  bool str_spread[2] = {false, false}, fixed_spread[4] = {false, false, false, false};  // columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
   std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
@@ -856,10 +856,18 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     }
     P.cols.push_back(cs);
   }
-  // The string kernel's columns run side by side: wave u takes tile u / n of
-  // column u % n (a 10^6-entry dictionary bound by random gathers beside
-  // small ones bound by instruction issue).  Interleaving the streaming
-  // fixed-width columns made them 4-8 % slower, so they stay in order.
+  // The string kernel's columns, and those of the 8-byte dictionary kernel,
+  // run side by side: wave u takes tile u / n of column u % n (a 10^6-entry
+  // dictionary bound by random gathers beside small ones bound by instruction
+  // issue).  Interleaving the other fixed-width kinds made them 1-3 % slower
+  // (streaming columns gain nothing from the mix), so they stay in order.
+  if (P.fixed_segs[FX_WIDE | FX_DICT].size() >= 2) {
+    const int K = FX_WIDE | FX_DICT;
+    uint32_t most = 0;
+    for (const Segment& sg : P.fixed_segs[K]) most = std::max(most, sg.t1 - sg.t0);
+    P.fixed_spread[K] = true;
+    P.fixed_units[K] = (uint32_t)P.fixed_segs[K].size() * most;
+  }
   for (int k = 0; k < 2; ++k) {
     if (P.str_segs[k].size() < 2) continue;
     uint32_t most = 0;
@@ -954,7 +962,7 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
     ProfScope ps_(f, KP_FIXED0 + K, s);
     auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
     hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K]), f->d_err);
+                       f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K], P.fixed_spread[K]), f->d_err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {
