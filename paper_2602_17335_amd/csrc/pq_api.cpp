@@ -902,7 +902,7 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
   }
   if (P.sblk_lanes) {
     ProfScope ps_(f, KP_SNAPPY_BLK, s);
-    hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 255) / 256), dim3(256), 0, s, file, f->d_pages, d_cols,
+    hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s, file, f->d_pages, d_cols,
                        make_segs(P.sblk_segs), f->d_sblk, f->d_sblk_page, ws, f->d_err);
     HIP_OR(hipGetLastError());
   }

@@ -1361,124 +1361,155 @@ __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t
 // source from the block's own output in global memory after this lane's
 // earlier stores have completed.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols,
-                                                   SegTable seg, const uint32_t* sblk, const uint32_t* sblk_page,
-                                                   uint8_t* ws, uint32_t* err) {
-  const uint32_t gid = blockIdx.x * WG + threadIdx.x;
+// One lane's block of k_snappy_blk: its page's compressed stream, output
+// region and element range.  False for a lane without a block (past the
+// segment, a page that is not compressed or is decoded by k_snappy).
+struct SnapLane {
+  const uint8_t* src;
+  uint8_t* dst;
+  uint32_t ip, iend, ob, oend, page, pad_;
+  bool bad;
+};
+__device__ __forceinline__ bool snap_lane(const uint8_t* file, const PageDev* pages, const ColScan* cols, const SegTable& seg,
+                                          const uint32_t* sblk, const uint32_t* sblk_page, uint8_t* ws, uint32_t gid,
+                                          SnapLane& sl) {
   int k = 0;
   for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
   const uint32_t b = seg.s[k].t0 + (gid - seg.s[k].wg0);
-  if (b >= seg.s[k].t1) return;
+  if (b >= seg.s[k].t1) return false;
   const uint32_t p = sblk_page[b];
   const PageDev pg = pages[p];
-  if (pg.scratch_len == 0) return;
+  if (pg.scratch_len == 0) return false;
   const uint32_t first = pg.sblk_begin;
-  if (sblk[first] == SBLK_NONE) return;  // decoded sequentially by k_snappy
+  if (sblk[first] == SBLK_NONE) return false;  // decoded sequentially by k_snappy
   const ColScan cs = cols[seg.s[k].cs];
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
-  const uint8_t* src = file + src_off;
-  uint8_t* dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
   const uint32_t total = pg.scratch_len;
   const uint32_t src_len = (uint32_t)src_len64;
   const uint32_t kb = b - first, nblk = (total + SNAP_BLOCK - 1) / SNAP_BLOCK;
-  uint32_t ip = sblk[b];
-  const uint32_t iend = kb + 1 < nblk ? sblk[b + 1] : src_len;
-  const uint32_t ob = kb * SNAP_BLOCK;  // the block's first output byte
-  uint32_t op = ob;
-  const uint32_t oend = min(ob + SNAP_BLOCK, total);
-  bool bad = src_len64 >= 0x7fffffffull || ip > iend || iend > src_len;
+  sl.src = file + src_off;
+  sl.dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
+  sl.ip = sblk[b];
+  sl.iend = kb + 1 < nblk ? sblk[b + 1] : src_len;
+  sl.ob = kb * SNAP_BLOCK;  // the block's first output byte
+  sl.oend = min(sl.ob + SNAP_BLOCK, total);
+  sl.page = p;
+  sl.bad = src_len64 >= 0x7fffffffull || sl.ip > sl.iend || sl.iend > src_len;
+  return true;
+}
+
+__global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols,
+                                                   SegTable seg, const uint32_t* sblk, const uint32_t* sblk_page,
+                                                   uint8_t* ws, uint32_t* err) {
+  const uint32_t lw = threadIdx.x & 63;
+  const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
+  // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
+  // copy long literals
+  SnapLane sl = {nullptr, nullptr, 0u, 0u, 0u, 0u, 0u, 0u, false};
+  const bool live = lw < SNAP_LANES && snap_lane(file, pages, cols, seg, sblk, sblk_page, ws, gid, sl);
+  const uint8_t* src = sl.src;
+  uint8_t* dst = sl.dst;
+  uint32_t ip = sl.ip, op = sl.ob;
+  const uint32_t iend = sl.iend, ob = sl.ob, oend = sl.oend, p = sl.page;
+  bool bad = sl.bad;
   // the 16 stream bytes from the dword holding byte ip: loaded one element
   // ahead (the next element's position is known once its tag is decoded), so
   // its latency overlaps the current element's loads and stores
   typedef const __attribute__((address_space(1))) u32x4a* gq4;
   u32x4a qv = {0u, 0u, 0u, 0u};
-  if (!bad && ip < iend) qv = *(gq4)((uintptr_t)(src + ip) & ~(uintptr_t)3);
-  while (!bad && op < oend) {
-    if (ip >= iend) { bad = true; break; }
-    const uint32_t sh = (uint32_t)((uintptr_t)(src + ip) & 3);
-    const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(qv.y, qv.x, sh) |
-                       ((uint64_t)__builtin_amdgcn_alignbyte(qv.z, qv.y, sh) << 32);
-    const uint32_t t = (uint32_t)x & 0xffu;
-    uint32_t nip, len = 0, off = 0, hl;
-    uint64_t L = 0;
-    const bool lit = (t & 3) == 0;
-    if (lit) {
-      uint32_t l = t >> 2;
-      hl = 1;
-      if (l >= 60) {
-        const uint32_t nb = l - 59;
-        l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
-        hl += nb;
-      }
-      L = (uint64_t)l + 1;
-      if ((uint64_t)ip + hl + L > iend || L > oend - op) { bad = true; break; }
-      nip = ip + hl + (uint32_t)L;
-    } else {
-      if ((t & 3) == 1) {
-        hl = 2;
-        len = 4 + ((t >> 2) & 7);
-        off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
-      } else if ((t & 3) == 2) {
-        hl = 3;
-        len = (t >> 2) + 1;
-        off = (uint32_t)(x >> 8) & 0xffffu;
-      } else {
-        hl = 5;
-        len = (t >> 2) + 1;
-        off = (uint32_t)(x >> 8);
-      }
-      if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
-      nip = ip + hl;
-    }
-    if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
-    // one copy routine for a literal of at most 64 bytes and for a copy that
-    // does not overlap its output (which reads this lane's earlier output);
-    // longer literals are copied by the whole wave below
-    const bool big = lit && L > 64;
-    const uint32_t op0 = op;
-    if ((lit && !big) || (!lit && off >= len))
-      lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)L : len);
-    if (lit) {
-      op += (uint32_t)L;
-    } else {
-      if (off < len) {  // the copy overlaps its output: bytes repeat with period off
-        uint32_t r = 0;   // k0 mod off, carried from chunk to chunk
-        for (uint32_t k0 = 0; k0 < len; k0 += 8) {
-          uint32_t bb[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            bb[j] = dst[op - off + r];
-            r = r + 1 == off ? 0u : r + 1;
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
+  if (live && !bad && ip < iend) qv = *(gq4)((uintptr_t)(src + ip) & ~(uintptr_t)3);
+  bool run = live && !bad && op < oend;
+  while (__ballot(run)) {
+    bool big = false;  // a literal longer than 64 bytes, copied by the whole wave below
+    uintptr_t bd = 0, bs = 0;
+    uint32_t bn = 0;
+    if (run) do {  // one element; a malformed one ends the lane's block
+      if (ip >= iend) { bad = true; break; }
+      const uint32_t sh = (uint32_t)((uintptr_t)(src + ip) & 3);
+      const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(qv.y, qv.x, sh) |
+                         ((uint64_t)__builtin_amdgcn_alignbyte(qv.z, qv.y, sh) << 32);
+      const uint32_t t = (uint32_t)x & 0xffu;
+      uint32_t nip, len = 0, off = 0, hl;
+      uint64_t L = 0;
+      const bool lit = (t & 3) == 0;
+      if (lit) {
+        uint32_t l = t >> 2;
+        hl = 1;
+        if (l >= 60) {
+          const uint32_t nb = l - 59;
+          l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
+          hl += nb;
         }
+        L = (uint64_t)l + 1;
+        if ((uint64_t)ip + hl + L > iend || L > oend - op) { bad = true; break; }
+        nip = ip + hl + (uint32_t)L;
+      } else {
+        if ((t & 3) == 1) {
+          hl = 2;
+          len = 4 + ((t >> 2) & 7);
+          off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
+        } else if ((t & 3) == 2) {
+          hl = 3;
+          len = (t >> 2) + 1;
+          off = (uint32_t)(x >> 8) & 0xffffu;
+        } else {
+          hl = 5;
+          len = (t >> 2) + 1;
+          off = (uint32_t)(x >> 8);
+        }
+        if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
+        nip = ip + hl;
       }
-      op += len;
-    }
-    // long literals of this step, one after the other, each copied by every
-    // active lane (a lane's later loads see them: the wave's stores are
-    // performed in order)
+      if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
+      // one copy routine for a literal of at most 64 bytes and for a copy that
+      // does not overlap its output (which reads this lane's earlier output);
+      // longer literals are copied by the whole wave below
+      big = lit && L > 64;
+      if (big) {
+        bd = (uintptr_t)(dst + op);
+        bs = (uintptr_t)(src + ip + hl);
+        bn = (uint32_t)L;
+      }
+      if ((lit && !big) || (!lit && off >= len))
+        lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)L : len);
+      if (lit) {
+        op += (uint32_t)L;
+      } else {
+        if (off < len) {  // the copy overlaps its output: bytes repeat with period off
+          uint32_t r = 0;   // k0 mod off, carried from chunk to chunk
+          for (uint32_t k0 = 0; k0 < len; k0 += 8) {
+            uint32_t bb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              bb[j] = dst[op - off + r];
+              r = r + 1 == off ? 0u : r + 1;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
+          }
+        }
+        op += len;
+      }
+      ip = nip;
+    } while (false);
+    // long literals of this step, one after the other, each copied by all 64
+    // lanes (a lane's later loads see them: the wave's stores are performed
+    // in order)
     uint64_t m = __ballot(big);
-    if (m) {
-      const uint64_t act = __ballot(1);
-      const uint32_t nact = (uint32_t)__popcll(act), r = rank_below(act);
-      const uintptr_t bd = (uintptr_t)(dst + op0), bs = (uintptr_t)(src + ip + hl);
-      const uint32_t bn = (uint32_t)L;
-      while (m) {
-        const int l = __builtin_ctzll(m);
-        m &= m - 1;
-        uint8_t* d = (uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bd >> 32), l) << 32) |
-                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bd, l));
-        const uint8_t* s = (const uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bs >> 32), l) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bs, l));
-        wave_copy(d, s, (uint32_t)__builtin_amdgcn_readlane((int)bn, l), r, nact);
-      }
+    while (m) {
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      uint8_t* d = (uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bd >> 32), l) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bd, l));
+      const uint8_t* s = (const uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bs >> 32), l) << 32) |
+                                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bs, l));
+      wave_copy(d, s, (uint32_t)__builtin_amdgcn_readlane((int)bn, l), lw, 64);
     }
-    ip = nip;
+    run = run && !bad && op < oend;
   }
+  if (!live) return;
   if (!bad && (op != oend || ip != iend)) bad = true;
   if (bad) set_err(err, ERR_SNAPPY, p);
 }
