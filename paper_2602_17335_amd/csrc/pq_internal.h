@@ -126,13 +126,12 @@ struct PageDev {
 // boundary or a copy reaches before its block's start: such a page is
 // decompressed sequentially, the others one block per lane.
 constexpr uint32_t SNAP_BLOCK = 65536;
-// k_snappy_blk: blocks per wave (the wave's other lanes idle).  A block is
-// a long chain of dependent steps, and a full wave per SIMD leaves nothing
-// to issue while it waits.
-#ifndef PQ_SNAP_LANES
-#define PQ_SNAP_LANES 8
-#endif
-constexpr uint32_t SNAP_LANES = PQ_SNAP_LANES;
+// k_snappy_blk: blocks decoded per wave; the wave's other lanes only help
+// copy long literals.  A block is a long chain of dependent steps: with one
+// block per lane a file's blocks fill less than one wave per SIMD, which
+// then has nothing to issue while its wave waits; 8 blocks per wave give
+// about eight waves per SIMD (16 and 4 were slower).
+constexpr uint32_t SNAP_LANES = 8;
 constexpr uint32_t SBLK_NONE = 0xffffffffu;
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.

@@ -2,7 +2,8 @@
 // and k_prepass, which pq_open_device runs once to build the tile prefix.
 //
 //   k_snappy        Snappy page bodies -> workspace (one wave per page)
-//   k_snappy_blk    Snappy page bodies with a block index (one lane per 64 KiB block)
+//   k_snappy_blk    Snappy page bodies with a block index (one lane per 64 KiB block,
+//                   SNAP_LANES blocks per wave)
 //   k_prep          validity edge words cleared / REQUIRED validity set to ones
 //   k_dict          dictionary pages -> device dictionaries
 //   k_prepass       per-tile DELTA sums and string byte counts (at open)
@@ -1356,10 +1357,11 @@ __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t
 
 // ---------------------------------------------------------------------------
 // k_snappy_blk: the pages of the Snappy block index, one lane per 64 KiB
-// output block (a lane decodes its block's elements in order; 64 blocks of
-// one or several pages advance together in a wave).  Copies read their
-// source from the block's own output in global memory after this lane's
-// earlier stores have completed.
+// output block (a lane decodes its block's elements in order; SNAP_LANES
+// blocks of one or several pages advance together in a wave, whose other
+// lanes join every copy of a literal longer than 64 bytes).  Copies read
+// their source from the block's own output in global memory after this
+// lane's earlier stores have completed.
 // ---------------------------------------------------------------------------
 // One lane's block of k_snappy_blk: its page's compressed stream, output
 // region and element range.  False for a lane without a block (past the
