@@ -28,7 +28,7 @@ __global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev*
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, const PageDev* pages, const TileDev* tiles,
                         SegTable seg);
 __global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages, DictSlot* slots,
-                       const uint32_t* strck, DictTable tab, uint32_t* err);
+                       const uint32_t* strck, const DictWork* works, uint32_t nworks, uint32_t* err);
 __global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
                           const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
                           uint32_t* err);
@@ -714,7 +714,8 @@ struct Plan {
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
   std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
-  uint64_t ws_which = 0;
+  uint64_t ws_which = 0, ws_dwork = 0;
+  uint32_t dict_units = 0;  // k_dict waves
 };
 
 // Work lists and workspace layout of a scan of `mask` over row groups
@@ -773,7 +774,8 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
           if (dp.dict_maxlen < 65536) sl.flags |= DICT_LENS16;
           sl.ws_lens = off;
           off = align_up(off + (uint64_t)((sl.flags & DICT_LENS16) ? 2 : 4) * sl.n + 16, 256);
-          if (!index && dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32)) {
+          if (!index && dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32) &&
+              (uint64_t)sl.n * SLOT_ROWS_PER_ENTRY <= (uint64_t)(f->rg_row0[g + 1] - f->rg_row0[g])) {
             sl.flags |= DICT_SLOTS;
             sl.ws_slots = off;
             off = align_up(off + (uint64_t)SLOT_BYTES * sl.n, 256);
@@ -875,6 +877,14 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     P.str_spread[k] = true;
     P.str_units[k] = (uint32_t)P.str_segs[k].size() * most;
   }
+  // k_dict's work table: first units set here, copied into the workspace by
+  // the scan (one launch for every dictionary of the scan)
+  for (DictWork& w : P.dict_work) {
+    w.unit0 = P.dict_units;
+    P.dict_units += w.units;
+  }
+  P.ws_dwork = off;
+  off = align_up(off + sizeof(DictWork) * (P.dict_work.empty() ? 1 : P.dict_work.size()), 256);
   P.ws_total = std::max<uint64_t>(off, 256);
   return PQ_OK;
 }
@@ -890,6 +900,9 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
   if (!P.cols.empty()) HIP_OR(hipMemcpyAsync(d_cols, P.cols.data(), sizeof(ColScan) * P.cols.size(), hipMemcpyHostToDevice, s));
   if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
   if (!P.str_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size(), hipMemcpyHostToDevice, s));
+  DictWork* d_dwork = reinterpret_cast<DictWork*>(ws + P.ws_dwork);
+  if (!P.dict_work.empty())
+    HIP_OR(hipMemcpyAsync(d_dwork, P.dict_work.data(), sizeof(DictWork) * P.dict_work.size(), hipMemcpyHostToDevice, s));
   const uint8_t* file = f->file;
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
@@ -906,19 +919,10 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
                        make_segs(P.sblk_segs), f->d_sblk, f->d_sblk_page, ws, f->d_err);
     HIP_OR(hipGetLastError());
   }
-  for (size_t w0 = 0; w0 < P.dict_work.size(); w0 += MAX_SEGS) {  // MAX_SEGS dictionaries per launch
-    DictTable tab;
-    memset(&tab, 0, sizeof(tab));
-    uint32_t units = 0;
-    for (size_t w = w0; w < P.dict_work.size() && w < w0 + MAX_SEGS; ++w) {
-      tab.w[tab.n] = P.dict_work[w];
-      tab.w[tab.n].unit0 = units;
-      units += tab.w[tab.n].units;
-      ++tab.n;
-    }
+  if (P.dict_units) {
     ProfScope ps_(f, KP_DICT, s);
-    hipLaunchKernelGGL(k_dict, dim3((units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages, d_slots,
-                       f->d_strck, tab, f->d_err);
+    hipLaunchKernelGGL(k_dict, dim3((P.dict_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages, d_slots,
+                       f->d_strck, d_dwork, (uint32_t)P.dict_work.size(), f->d_err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;

@@ -157,6 +157,11 @@ struct TileDev {
 constexpr uint32_t SLOT_BYTES = 64;
 constexpr uint32_t SLOT_CHARS = 60;
 static_assert(SLOT_BYTES == 64 && SLOT_CHARS < 64, "a slot offset and a length share one word");
+// Slots are built only for a dictionary that serves at least this many rows
+// of its row group per entry: building a slot costs about as much as the
+// gathers of a few rows save (a 10^6-distinct-value string column in 1M-row
+// row groups scans faster without slots, in 8M-row ones with them).
+constexpr uint64_t SLOT_ROWS_PER_ENTRY = 4;
 enum : uint32_t { DICT_SLOTS = 1, DICT_LENS16 = 2 };
 struct DictSlot {
   const uint8_t* body;   // 16-byte aligned base holding the dictionary page body (file or
@@ -214,14 +219,10 @@ struct SegTable {
 };
 
 // k_dict work: dictionary slot `slot` of selected column `col` is units
-// [unit0, unit0 + units) of the launch (one wave each).
+// [unit0, unit0 + units) of the launch (one wave each).  The scan's table of
+// them is copied into the workspace, ascending in unit0.
 struct DictWork {
   uint32_t col, slot, units, unit0;
-};
-struct DictTable {
-  DictWork w[MAX_SEGS];
-  int32_t n;
-  int32_t pad_;
 };
 // entries per k_dict wave: fixed-width dictionaries; string dictionaries
 // take DICT_CK_PER checkpoints of STR_CK entries

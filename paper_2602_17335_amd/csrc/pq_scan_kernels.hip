@@ -1584,20 +1584,21 @@ __global__ __launch_bounds__(WG) void k_edges(const uint8_t* __restrict__ ws, co
 
 // ---------------------------------------------------------------------------
 // k_dict: dictionary pages of the scanned chunks -> workspace dictionaries.
-// One wave per unit of a DictTable entry.  Fixed-width dictionaries: 1024
+// One wave per unit of a DictWork entry.  Fixed-width dictionaries: 1024
 // PLAIN values per wave (16 per lane, all loads before the stores).  String
 // dictionaries: DICT_CK_PER checkpoints (STR_CK entries each, positions from
 // the open-time index) per wave; the wave copies their bytes into LDS with
 // coalesced loads, one lane per checkpoint walks the length prefixes there,
 // and for slot dictionaries the wave then writes every entry's 64-byte slot
-// (chars zero-padded, length in the last dword) from LDS.  A string region
+// (length in the first dword, then the chars, zero-padded) from LDS.  A string region
 // larger than the LDS buffer (never for slot dictionaries: at most
 // DICT_CK_PER * STR_CK * SLOT_BYTES bytes) is walked in global memory.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
                                              const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
                                              DictSlot* __restrict__ slots, const uint32_t* __restrict__ strck,
-                                             DictTable tab, uint32_t* __restrict__ err) {
+                                             const DictWork* __restrict__ works, uint32_t nworks,
+                                             uint32_t* __restrict__ err) {
   constexpr uint32_t NE = DICT_CK_PER * STR_CK;      // entries per string unit
   constexpr uint32_t RB = NE * SLOT_BYTES;           // LDS region bytes
   constexpr uint32_t RW = RB / 4 + 32;               // + slack for the realigning reads
@@ -1605,14 +1606,19 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
   __shared__ uint32_t s_pos[NWAVES][NE], s_len[NWAVES][NE];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVES + wave));
-  int k = 0;
-  for (int j = 1; j < tab.n; ++j)
-    if (tab.w[j].unit0 <= unit) k = j;
-  const uint32_t u = unit - tab.w[k].unit0;
-  if (u >= tab.w[k].units) return;
-  const uint32_t si = tab.w[k].slot;
+  // the last work item whose first unit is at most `unit` (wave-uniform
+  // binary search)
+  uint32_t lo = 0, hi = nworks;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (works[mid].unit0 <= unit) lo = mid; else hi = mid;
+  }
+  const DictWork wk = works[lo];
+  const uint32_t u = unit - wk.unit0;
+  if (u >= wk.units) return;
+  const uint32_t si = wk.slot;
   const DictSlot sl = slots[si];
-  const ColScan cs = cols[tab.w[k].col];
+  const ColScan cs = cols[wk.col];
   const PageDev pg = pages[sl.page];
   const uint8_t* body;
   uint64_t boff;
