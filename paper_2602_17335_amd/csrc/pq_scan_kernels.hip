@@ -1691,10 +1691,6 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
         const uint32_t l = lds_word(ss + (uint32_t)x);
         x += 4;
         if ((uint64_t)l > R - x) { bad = true; break; }
-        pairs[2 * e] = (uint32_t)(q0 + x);
-        pairs[2 * e + 1] = l;
-        if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
-        else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e] = l;
         s_pos[wave][e - e0] = ss + (uint32_t)x;
         s_len[wave][e - e0] = l;
         x += l;
@@ -1704,12 +1700,20 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
       if (lane == 0) set_err(err, ERR_STRING, sl.page);
       return;
     }
-    if (!(sl.flags & DICT_SLOTS)) return;
     wave_sync();
+    // pairs and lengths of the unit's entries from LDS, all lanes, coalesced
+    const uint32_t ne = min(ck1 * STR_CK, n) - e0;
+    for (uint32_t i = lane; i < ne; i += 64) {
+      const uint32_t l = s_len[wave][i];
+      const uint32_t pos = (uint32_t)(q0 + (s_pos[wave][i] - ss));
+      reinterpret_cast<uint64_t*>(pairs)[e0 + i] = (uint64_t)pos | ((uint64_t)l << 32);
+      if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e0 + i] = (uint16_t)l;
+      else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e0 + i] = l;
+    }
+    if (!(sl.flags & DICT_SLOTS)) return;
     // slots: 16-byte chunk c of entry e per step (slot dword 0 is the
     // length, at most SLOT_CHARS; slot dword D > 0 holds chars [4 D - 4,
     // 4 D), zero past the length)
-    const uint32_t ne = min(ck1 * STR_CK, n) - e0;
     glb_u8* sb = gptr(ws + sl.ws_slots);
     for (uint32_t i = lane; i < 4 * ne; i += 64) {
       const uint32_t ei = i >> 2, c = i & 3;
