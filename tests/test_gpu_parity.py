@@ -49,11 +49,14 @@ def _spec_cases():
     ], num_rows=40_011, rg_rows=13_000, page_bytes=20_000, name="edge")
     # string dictionaries: entries of 45..60 chars (slots, four pieces per
     # slot), of 61..300 chars (no slots; 128-entry regions larger than the
-    # LDS buffer), and of 0..2 chars (slots holding empty strings)
+    # LDS buffer), of 0..2 chars (slots holding empty strings), and of 8..44
+    # chars with fewer than 4 rows per entry (short enough for slots, but
+    # decoded from (position, length) pairs)
     cases["dict_strings"] = dg.FileSpec(cols=[
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.2, hi=3000, str_min=45, str_max=60),
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=2000, str_min=61, str_max=300),
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=700, str_min=0, str_max=2),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=40_000, str_min=8, str_max=44),
     ], num_rows=70_001, rg_rows=30_000, page_bytes=256 * dg.KiB, name="dict_strings")
     return cases
 
