@@ -305,7 +305,9 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
     if (ch.type == T_BYTE_ARRAY) {
       // the length-prefix chain in 32-bit positions (a page is below 4 GiB):
       // q in the page body, o in the LDS window, one LDS read per entry; the
-      // window moves when an entry's length prefix would leave it
+      // window moves when an entry's length prefix would leave it.  Every
+      // lane reads the same length, which is moved to a scalar register, so
+      // the chain and its checks run on the scalar unit
       const uint64_t blim = lim_of(base);
       const uint32_t n = pg.num_values > 0 ? (uint32_t)pg.num_values : 0u;
       const uint32_t bl = (uint32_t)blen;
@@ -314,11 +316,12 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       uint32_t q = 0, maxlen = 0, k = 0;
       while (k < n) {
         const uint64_t wpos = wr_refill(base, blim, win, (off + q) & ~15ull);
-        uint32_t o = (uint32_t)(off + q - wpos);  // below 272
+        uint32_t o = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off + q - wpos));  // below 272
         while (k < n && o + 8 <= WIN) {
           if ((k % STR_CK) == 0 && lead) strck[pg.strck_begin + k / STR_CK] = q;
           if (bl - q < 4) { set_err(err, ERR_STRING, p); return; }
-          const uint32_t l = __builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3);
+          const uint32_t l = (uint32_t)__builtin_amdgcn_readfirstlane(
+              (int)__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3));
           if (l > bl - q - 4) { set_err(err, ERR_STRING, p); return; }
           q += 4 + l;
           o = l < WIN ? o + 4 + l : WIN;
