@@ -150,7 +150,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
-              "(shards would be scanned independently per GPU, see DESIGN.md)", file=sys.stderr)
+              "(each GPU would scan its own shard of the files or row groups independently)", file=sys.stderr)
         sys.exit(2)
 
     import torch
