@@ -198,7 +198,7 @@ def main():
 
     for _ in range(args.warmup):
         f.scan_into(mask, 0, rg_end, outs, ws)
-    f.check()
+    f.check(ws)
     log(f"warmup done ({args.warmup} scans)")
 
     f.profile(True)
@@ -211,7 +211,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    f.check()
+    f.check(ws)
     prof = f.profile_read()
     f.profile(False)
     ms = total_ms / args.steps
@@ -236,7 +236,7 @@ def main():
             b.record(stream)
             torch.cuda.synchronize()
             out.append(a.elapsed_time(b))
-        f.check()
+        f.check(ws)
         return sorted(out)
     warm = timed_scans(args.steps, False)
     cold = timed_scans(max(3, args.steps // 4), True)

@@ -51,7 +51,7 @@ class _Spec(ctypes.Structure):
         ("delta_block", ctypes.c_int32), ("delta_mini", ctypes.c_int32),
         ("max_bp_groups", ctypes.c_int32), ("rle_min", ctypes.c_int32),
         ("ncols", ctypes.c_int32), ("nthreads", ctypes.c_int32),
-        ("snappy_skip", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("snappy_skip", ctypes.c_int32), ("index_width", ctypes.c_int32),
     ]
 
 
@@ -88,6 +88,7 @@ class FileSpec:
     rle_min: int = 8
     seed: int = 0x5EED0000
     snappy_literal_only: bool = False
+    index_width: int = 0  # dictionary index bit width byte when wider than the minimum (legal; 0 = minimal)
     name: str = "custom"
 
     def _c(self, nthreads: int):
@@ -106,6 +107,7 @@ class FileSpec:
         sp.ncols = len(self.cols)
         sp.nthreads = nthreads
         sp.snappy_skip = 1 if self.snappy_literal_only else 0
+        sp.index_width = self.index_width
         arr = (_Col * len(self.cols))()
         for i, c in enumerate(self.cols):
             for f in dataclasses.fields(Col):

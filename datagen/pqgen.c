@@ -66,7 +66,7 @@ typedef struct {
   int32_t ncols;
   int32_t nthreads;
   int32_t snappy_skip;    /* 0: greedy matcher; 1: literal-only Snappy streams */
-  int32_t pad_;
+  int32_t index_width;    /* dictionary index bit width when wider than the minimum (0: minimal) */
 } pqg_spec;
 
 /* ------------------------------------------------------------------ */
@@ -796,6 +796,7 @@ static void encode_chunk(job_t* J, int rg, int col) {
       dict_insert(&dict, key, key, eb);
     }
     idx_w = dict.n <= 1 ? 0 : bits_needed((uint64_t)(dict.n - 1));
+    if (sp->index_width > idx_w && sp->index_width <= 32) idx_w = sp->index_width;
   }
 
   /* 3. dictionary page */

@@ -12,8 +12,10 @@
  * knobs), applied to files already in HBM.  Supported: flat schemas (no
  * nesting, no REPEATED), physical types INT32, INT64, DOUBLE, BYTE_ARRAY;
  * REQUIRED and OPTIONAL columns; V1 and V2 data pages; PLAIN,
- * PLAIN_DICTIONARY, RLE_DICTIONARY and DELTA_BINARY_PACKED (INT32/INT64);
- * codecs UNCOMPRESSED and SNAPPY.
+ * PLAIN_DICTIONARY, RLE_DICTIONARY and DELTA_BINARY_PACKED (INT32/INT64;
+ * blocks of at most 65536 values in at most 16 miniblocks -- larger blocks
+ * are valid Parquet and return PQ_EUNSUPPORTED); codecs UNCOMPRESSED and
+ * SNAPPY.
  *
  * Output layout (per selected column, rows of the selected row groups
  * concatenated in row-group order):
@@ -33,13 +35,15 @@
  *
  * Errors.  Functions return PQ_OK (0) or a negative pq_status.  Errors the
  * host can detect return before anything is enqueued.  Corruption found by a
- * kernel sets a sticky per-handle error word (first error wins); kernels
- * never write outside the caller's buffers, and outputs are undefined after
- * such an error.  pq_scan_check() synchronises the stream and reports it.
- * pq_last_error() gives a thread-local message for the last failure.
+ * kernel during a scan sets the error word in that scan's workspace (first
+ * error wins); kernels never write outside the caller's buffers, and outputs
+ * are undefined after such an error.  pq_scan_check() synchronises the
+ * stream and reports it.  pq_last_error() gives a thread-local message for
+ * the last failure.
  *
- * Concurrency.  One handle may be scanned concurrently on several streams
- * with separate workspaces; those scans share the handle's error word.
+ * Concurrency.  One handle may be scanned concurrently on several streams,
+ * each scan with its own workspace (and so its own error word).  The handle
+ * is read-only after pq_open_device returns.
  */
 #ifndef PQ_H
 #define PQ_H
@@ -88,7 +92,8 @@ typedef struct {
   uint64_t chars_capacity;
 } pq_column_out;
 
-/* Statistics of an opened file (page table and tile index built at open). */
+/* Statistics of an opened file (page table, tile index and resident
+   dictionaries built at open). */
 typedef struct {
   int64_t pages;          /* data pages */
   int64_t dict_pages;
@@ -97,24 +102,33 @@ typedef struct {
   uint64_t encoded_bytes; /* sum of compressed page payload sizes */
   uint64_t uncompressed_bytes;
   double open_ms_device;  /* time of the open-time passes: page walk and tile
-                             index (device events), tile prefix (host clock) */
+                             index (device events), dictionaries and tile
+                             prefix (host clock) */
+  uint64_t device_bytes;  /* device memory the handle holds until pq_close
+                             (index, checkpoints, resident dictionaries) */
 } pq_file_stats;
 
 /*
- * Opens a Parquet file that lies in device memory.
+ * Opens a Parquet file that lies in device memory (Sec. 2: the file is read
+ * as row groups of column chunks, each chunk a sequence of pages).
  *   dev_buf  device pointer to the whole file (borrowed: it must stay valid
  *            and unmodified until pq_close; it is never written).  It must be
  *            readable up to `len` rounded up to a multiple of 16 bytes, which
  *            every HIP and PyTorch allocation is.
  *   len      file length in bytes.
- *   stream   stream used for the open-time kernels; the call synchronises it.
+ *   stream   stream used for the open-time kernels; the call synchronises it
+ *            (a caller that owns its streams keeps the open off the default
+ *            stream).
  *   out      receives the handle.
  * The footer is copied to the host and decoded there (file layout and
  * Thrift-compact metadata, Sec. 2's row-group/chunk/page hierarchy); a kernel
  * then walks every column chunk's page headers into a device page table, and
  * a second kernel builds the tile index (entry positions of every fixed-size
  * row tile in the level and value streams of each page) that lets a scan
- * start decoding at any tile.  Last, the tile prefix: for every column with
+ * start decoding at any tile.  Every dictionary page is then decoded once
+ * into a resident dictionary kept by the handle (fixed-width arrays; string
+ * positions, lengths and 64-byte slots), so scans never rebuild one.  Last,
+ * the tile prefix: for every column with
  * DELTA_BINARY_PACKED or BYTE_ARRAY pages, a pass over its tiles (after
  * decompression and dictionary decode, in batches of row groups with at most
  * 1 GiB of temporary device memory) counts each tile's DELTA sum or string
@@ -127,33 +141,38 @@ typedef struct {
  */
 pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out);
 
+/* Metadata of an opened file (Sec. 2: row groups, one column chunk per
+   column and row group).  Host-only; PQ_EINVAL for a NULL argument or an
+   index out of range. */
 pq_status pq_num_row_groups(pq_file f, int32_t* n);
 pq_status pq_num_columns(pq_file f, int32_t* n);
 pq_status pq_column_info_get(pq_file f, int32_t col, pq_column_info* out);
 pq_status pq_row_group_rows(pq_file f, int32_t rg, int64_t* rows);
+/* Sizes and open time of the file's page table and index (Sec. 3: the page
+   count and row-group size knobs show up as pages and tiles). */
 pq_status pq_file_stats_get(pq_file f, pq_file_stats* out);
 
 /*
- * Sizes a scan of columns `col_mask` (bit i = leaf column i, at most 64
+ * Sizes a scan (Sec. 2: a scan reads the selected column chunks of a range
+ * of row groups) of columns `col_mask` (bit i = leaf column i, at most 64
  * columns) over row groups [rg_begin, rg_end): rows, workspace_bytes, and
  * chars_bytes (exact chars bytes of each BYTE_ARRAY column, 0 for the
  * others).  Host-only: the string byte counts come from the tile prefix
  * that pq_open_device builds, so no GPU work is enqueued and nothing is
- * synchronised.  `workspace`, `workspace_bytes` and `stream` are accepted
- * for compatibility and not used (they may be NULL / 0).
+ * synchronised.  PQ_EINVAL for a bad range or mask.
  */
-pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
-                  uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream);
+pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, pq_scan_sizes* out);
 
 /*
- * Enqueues the scan on `stream` and returns without synchronising.
+ * Enqueues the scan on `stream` and returns without synchronising (Sec. 2:
+ * decompression, then decoding, both as GPU kernels).
  *   outs       host array of n_outs descriptors; outs[k] belongs to the k-th
  *              set bit of col_mask in ascending order.
  *   workspace  device buffer of at least the planned workspace_bytes, owned
  *              by the caller, not used by anything else until the scan ends.
- * Steps enqueued: clear error word / validity edge words; Snappy
- * decompression of compressed pages into the workspace; dictionary pages ->
- * device dictionaries; offsets[rows] and the chars capacity check of string
+ * Steps enqueued: the workspace header (cleared error word, column table) in
+ * one host-to-device copy; Snappy decompression of compressed data pages
+ * into the workspace; offsets[rows] and the chars capacity check of string
  * columns (from the tile prefix built at open); then the decode kernels
  * (definition levels -> validity and ranks, dictionary indices -> gather,
  * PLAIN, DELTA_BINARY_PACKED with carries from the tile prefix, BYTE_ARRAY ->
@@ -168,21 +187,26 @@ pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
    value width.  Returns PQ_EINVAL / PQ_ECAPACITY (workspace) before
    enqueueing anything. */
 
-/* Synchronises `stream` and returns (then clears) the handle's error word:
-   PQ_OK, or PQ_ECORRUPT/PQ_EUNSUPPORTED found by a kernel. */
-pq_status pq_scan_check(pq_file f, pq_stream stream);
+/* Synchronises `stream` and returns (then clears) the error word of the
+   scan that last used `workspace` (Sec. 2: the decode kernels of that
+   scan): PQ_OK, or PQ_ECORRUPT / PQ_EUNSUPPORTED / PQ_ECAPACITY found by a
+   kernel.  Scans on other workspaces are not affected. */
+pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream);
 
-/* Encoded bytes of column `col` over all row groups: data-page payloads
+/* Encoded bytes of column `col` over all row groups (Sec. 3: the encoded
+   size that the encoding and compression knobs change): data-page payloads
    (levels + values as stored) and dictionary-page payloads. */
 pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes);
 
 /* Encodings used by the data pages of column `col` over all row groups
+   (Sec. 2: V1 and V2 encodings may differ page by page)
    (the page header's encoding field, Parquet's Encoding enum: PLAIN 0,
    PLAIN_DICTIONARY 2, DELTA_BINARY_PACKED 5, RLE_DICTIONARY 8): bit e of
    *mask is set when some data page uses encoding e.  Host-only. */
 pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask);
 
-/* Measurement hook.  While enabled, every kernel pq_scan enqueues on a
+/* Measurement hook (Sec. 3: the effective bandwidth of a scan is the decoded
+   bytes over its run time).  While enabled, every kernel pq_scan enqueues on a
    handle is bracketed by a pair of HIP events on the scan's stream;
    pq_profile_read() waits for the recorded events and returns, per kernel
    name, the number of launches and the summed device time since the last
@@ -195,10 +219,12 @@ typedef struct {
 pq_status pq_profile(pq_file f, int32_t enable);
 pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n);
 
-/* Frees the handle's host and device memory (not dev_buf). */
+/* Frees the handle's host and device memory (not dev_buf).  Sec. 2: the
+   handle is the reader's state for one file. */
 void pq_close(pq_file f);
 
-/* Thread-local description of the last error. */
+/* Thread-local description of the last error (Sec. 2: the reader's error
+   reporting; no paper passage constrains it further). */
 const char* pq_last_error(void);
 
 #ifdef __cplusplus

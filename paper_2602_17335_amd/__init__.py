@@ -49,7 +49,8 @@ class KernelTime(ctypes.Structure):
 class FileStats(ctypes.Structure):
     _fields_ = [("pages", ctypes.c_int64), ("dict_pages", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("compressed_pages", ctypes.c_int64), ("encoded_bytes", ctypes.c_uint64),
-                ("uncompressed_bytes", ctypes.c_uint64), ("open_ms_device", ctypes.c_double)]
+                ("uncompressed_bytes", ctypes.c_uint64), ("open_ms_device", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -70,13 +71,13 @@ def lib() -> ctypes.CDLL:
         L.pq_column_info_get.argtypes = [vp, i32, ctypes.POINTER(ColumnInfo)]
         L.pq_row_group_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.pq_file_stats_get.argtypes = [vp, ctypes.POINTER(FileStats)]
-        L.pq_plan.argtypes = [vp, u64, i32, i32, vp, u64, ctypes.POINTER(ScanSizes), vp]
+        L.pq_plan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ScanSizes)]
         L.pq_column_bytes.argtypes = [vp, i32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.pq_column_encodings.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32)]
         L.pq_profile.argtypes = [vp, i32]
         L.pq_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
         L.pq_scan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp]
-        L.pq_scan_check.argtypes = [vp, vp]
+        L.pq_scan_check.argtypes = [vp, vp, vp]
         L.pq_close.argtypes = [vp]
         L.pq_close.restype = None
         L.pq_last_error.restype = ctypes.c_char_p
@@ -189,12 +190,9 @@ class DeviceFile:
         _check(lib().pq_profile_read(self._h, arr, 16, ctypes.byref(n)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}
 
-    def plan(self, mask: int, rg_begin: int, rg_end: int, workspace=None, stream=None) -> ScanSizes:
+    def plan(self, mask: int, rg_begin: int, rg_end: int) -> ScanSizes:
         sz = ScanSizes()
-        wp = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else ctypes.c_void_p()
-        wb = workspace.numel() if workspace is not None else 0
-        _check(lib().pq_plan(self._h, mask, rg_begin, rg_end, wp, wb, ctypes.byref(sz),
-                             ctypes.c_void_p(_stream_ptr(stream))))
+        _check(lib().pq_plan(self._h, mask, rg_begin, rg_end, ctypes.byref(sz)))
         return sz
 
     def scan_into(self, mask: int, rg_begin: int, rg_end: int, outs: Sequence[ColumnOut], workspace, stream=None):
@@ -203,60 +201,86 @@ class DeviceFile:
         _check(lib().pq_scan(self._h, mask, rg_begin, rg_end, arr, len(outs), ctypes.c_void_p(workspace.data_ptr()),
                              workspace.numel(), ctypes.c_void_p(_stream_ptr(stream))))
 
-    def check(self, stream=None):
-        _check(lib().pq_scan_check(self._h, ctypes.c_void_p(_stream_ptr(stream))))
+    def check(self, workspace, stream=None):
+        """Synchronises `stream` and raises the device error of the scan that
+        last used `workspace`, if any."""
+        _check(lib().pq_scan_check(self._h, ctypes.c_void_p(workspace.data_ptr()),
+                                   ctypes.c_void_p(_stream_ptr(stream))))
 
-    def allocate(self, columns: Sequence[int], rg_begin: int = 0, rg_end: Optional[int] = None, stream=None):
+    def allocate(self, columns: Sequence[int], rg_begin: int = 0, rg_end: Optional[int] = None,
+                 poison: Optional[int] = None, guard: int = 0):
         """Plans a scan and allocates its workspace and output tensors.
-        Returns (mask, rg_end, workspace, outs, tensors)."""
+        `poison`: byte every output buffer is filled with first (None: left
+        uninitialised); `guard`: bytes after each buffer, filled with 0xAB,
+        that the scan must not touch.  Returns (mask, rg_end, workspace,
+        outs, tensors)."""
         import torch
         if rg_end is None:
             rg_end = self.num_row_groups
         mask = 0
         for c in columns:
             mask |= 1 << c
-        sz = self.plan(mask, rg_begin, rg_end, stream=stream)
+        sz = self.plan(mask, rg_begin, rg_end)
         ws = torch.empty(max(int(sz.workspace_bytes), 256), dtype=torch.uint8, device="cuda")
         cols = sorted(columns)
         rows = int(sz.rows)
+
+        def buf(nbytes):
+            t = torch.empty(nbytes + guard, dtype=torch.uint8, device="cuda")
+            if poison is not None:
+                t.fill_(poison)
+            if guard:
+                t[nbytes:].fill_(0xAB)
+            return t
+
         outs, tensors = [], {}
         for k, c in enumerate(cols):
             ci = self.column_info(c)
-            vb = torch.zeros(max(validity_bytes(rows), 4), dtype=torch.uint8, device="cuda")
+            vbytes = max(validity_bytes(rows), 4)
+            vb = buf(vbytes)
             o = ColumnOut()
             o.validity = vb.data_ptr()
-            t = {"validity_buf": vb, "rows": rows}
+            t = {"validity_buf": vb, "validity_bytes": vbytes, "rows": rows, "guard": guard}
             if ci.type == BYTE_ARRAY:
-                offs = torch.empty(rows + 1, dtype=torch.int64, device="cuda")
+                ob = buf(8 * (rows + 1))
                 nch = int(sz.chars_bytes[k])
-                chars = torch.empty(max(nch, 1), dtype=torch.uint8, device="cuda")
-                o.offsets, o.chars, o.chars_capacity = offs.data_ptr(), chars.data_ptr(), nch
-                t.update(offsets=offs, chars_buf=chars, chars_bytes=nch)
+                chars = buf(max(nch, 1))
+                o.offsets, o.chars, o.chars_capacity = ob.data_ptr(), chars.data_ptr(), nch
+                t.update(offsets_buf=ob, offsets=ob[: 8 * (rows + 1)].view(torch.int64), chars_buf=chars,
+                         chars_bytes=nch, chars_alloc=max(nch, 1))
             else:
                 dt = {INT32: torch.int32, INT64: torch.int64, DOUBLE: torch.float64}[ci.type]
-                vals = torch.empty(max(rows, 1), dtype=dt, device="cuda")
+                w = _WIDTH[ci.type]
+                vals = buf(max(rows, 1) * w)
                 o.values = vals.data_ptr()
-                t["values_buf"] = vals
+                t.update(values_raw=vals, values_buf=vals[: max(rows, 1) * w].view(dt), value_bytes=max(rows, 1) * w)
             outs.append(o)
             tensors[c] = t
         return mask, rg_end, ws, outs, tensors
 
     def scan(self, columns: Sequence[int], rg_begin: int = 0, rg_end: Optional[int] = None, stream=None,
-             check: bool = True) -> Dict[int, dict]:
+             check: bool = True, poison: Optional[int] = None, guard: int = 0) -> Dict[int, dict]:
         """Scans `columns` over row groups [rg_begin, rg_end) into new device
-        tensors: {col: {"values"| "offsets","chars", "validity"}}."""
-        mask, rg_end, ws, outs, tensors = self.allocate(columns, rg_begin, rg_end, stream)
+        tensors: {col: {"values"| "offsets","chars", "validity",
+        "validity_words"}} ("validity_words": all bytes the library writes,
+        whole 32-bit words)."""
+        mask, rg_end, ws, outs, tensors = self.allocate(columns, rg_begin, rg_end, poison, guard)
         self.scan_into(mask, rg_begin, rg_end, outs, ws, stream)
         if check:
-            self.check(stream)
+            self.check(ws, stream)
         res = {}
         for c, t in tensors.items():
             rows = t["rows"]
-            d = {"validity": t["validity_buf"][: (rows + 7) // 8], "rows": rows}
+            vb = t["validity_buf"]
+            d = {"validity": vb[: (rows + 7) // 8], "validity_words": vb[: validity_bytes(rows)], "rows": rows}
+            guards = [vb[t["validity_bytes"]:]]
             if "offsets" in t:
                 d["offsets"] = t["offsets"]
                 d["chars"] = t["chars_buf"][: t["chars_bytes"]]
+                guards += [t["offsets_buf"][8 * (rows + 1):], t["chars_buf"][t["chars_alloc"]:]]
             else:
                 d["values"] = t["values_buf"][:rows]
+                guards.append(t["values_raw"][t["value_bytes"]:])
+            d["guards"] = guards
             res[c] = d
         return res

@@ -20,31 +20,20 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order);
-__global__ void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg, uint8_t* ws,
-                         uint32_t* sblk, int record, uint32_t* err);
-__global__ void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols, SegTable seg,
-                             const uint32_t* sblk, const uint32_t* sblk_page, uint8_t* ws, uint32_t* err);
-__global__ void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg);
-__global__ void k_edges(const uint8_t* ws, const ColScan* cols, const PageDev* pages, const TileDev* tiles,
-                        SegTable seg);
-__global__ void k_dict(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages, DictSlot* slots,
-                       const uint32_t* strck, const DictWork* works, uint32_t nworks, uint32_t* err);
-__global__ void k_prepass(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                          const TileDev* tiles, const Ck* ckv, const DictSlot* slots, SegTable seg,
-                          uint32_t* err);
-__global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, const uint64_t* tpfx, uint32_t* err);
+__global__ void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record, uint32_t* err);
+__global__ void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err);
+__global__ void k_prep(const ColScan* cols, SegTable seg);
+__global__ void k_edges(const uint8_t* ws, const ColScan* cols, SegTable seg);
+__global__ void k_dict(const PageDev* pages, const uint32_t* strck, const DictSlot* slots, const DictWork* works,
+                       uint32_t nworks, uint32_t* err);
+__global__ void k_prepass(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
+__global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, uint32_t* err);
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
 template <int KIND>
-__global__ void k_decode_fixed(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
-                               SegTable seg, uint32_t* err);
-__global__ void k_decode_delta(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                               const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const uint64_t* tpfx,
-                               SegTable seg, uint32_t* err);
+__global__ void k_decode_fixed(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
+__global__ void k_decode_delta(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
 template <bool SLOTS>
-__global__ void k_decode_str(const uint8_t* file, uint8_t* ws, const ColScan* cols, const PageDev* pages,
-                             const TileDev* tiles, const uint32_t* ckl, const Ck* ckv, const DictSlot* slots,
-                             const uint32_t* strck, const uint64_t* tpfx, SegTable seg, uint32_t* err);
+__global__ void k_decode_str(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
 }  // namespace pqk
 
 using namespace pqk;
@@ -281,6 +270,13 @@ struct pq_file_s {
   // and on the host
   uint64_t* d_tpfx = nullptr;
   std::vector<uint64_t> tpfx;
+  // resident dictionaries: one DictSlot per chunk (device and host), their
+  // decoded arrays in one arena
+  DictSlot* d_dicts = nullptr;
+  uint8_t* d_dict_arena = nullptr;
+  std::vector<DictSlot> dicts;
+  uint64_t device_bytes = 0;  // device memory held by the handle
+  FileDev fd{};               // the device tables, as a scan's columns carry them
   pq_file_stats stats{};
   // measurement hook: event pairs around each launched kernel
   bool profiling = false;
@@ -347,6 +343,8 @@ static void free_handle(pq_file f) {
   if (f->d_chunks) (void)hipFree(f->d_chunks);
   if (f->d_err) (void)hipFree(f->d_err);
   if (f->d_tpfx) (void)hipFree(f->d_tpfx);
+  if (f->d_dicts) (void)hipFree(f->d_dicts);
+  if (f->d_dict_arena) (void)hipFree(f->d_dict_arena);
   delete f;
 }
 
@@ -362,17 +360,19 @@ static pq_status device_error(uint32_t code) {
   return fail(PQ_ECORRUPT, "device: corrupt %s (at %u)", nm, where);
 }
 
-static pq_status read_err(pq_file f, hipStream_t s) {
+// Reads (and on error clears) a device error word after synchronising s.
+static pq_status read_err_word(uint32_t* d_word, hipStream_t s) {
   uint32_t e = 0;
-  HIP_OR(hipMemcpyAsync(&e, f->d_err, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR(hipMemcpyAsync(&e, d_word, 4, hipMemcpyDeviceToHost, s));
   HIP_OR(hipStreamSynchronize(s));
   if (e) {
-    HIP_OR(hipMemsetAsync(f->d_err, 0, 4, s));
+    HIP_OR(hipMemsetAsync(d_word, 0, 4, s));
     HIP_OR(hipStreamSynchronize(s));
     return device_error(e);
   }
   return PQ_OK;
 }
+static pq_status read_err(pq_file f, hipStream_t s) { return read_err_word(f->d_err, s); }
 
 static SegTable make_segs(const std::vector<Segment>& v, bool spread = false) {
   SegTable t;
@@ -384,6 +384,7 @@ static SegTable make_segs(const std::vector<Segment>& v, bool spread = false) {
 }
 
 static pq_status build_tile_prefix(pq_file f, hipStream_t s);
+static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s);
 
 extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out) {
   if (!out) return fail(PQ_EINVAL, "out is NULL");
@@ -584,12 +585,15 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
     if (hipMalloc(&d_cs, sizeof(ColScan)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
     ColScan cs;
     memset(&cs, 0, sizeof(cs));
+    cs.fd.file = file;
+    cs.fd.pages = f->d_pages;
+    cs.fd.sblk = f->d_sblk;
+    cs.fd.sblk_page = f->d_sblk_page;
     (void)hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s);
     std::vector<Segment> segs{Segment{0, 0, npages, 0}};
     SegTable st2 = make_segs(segs);
     const uint32_t waves = npages;
-    hipLaunchKernelGGL(k_snappy, dim3(waves), dim3(64), 0, s, file, f->d_pages, d_cs, st2, d_scratch, f->d_sblk, 1,
-                       f->d_err);
+    hipLaunchKernelGGL(k_snappy, dim3(waves), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
   }
   if (tiles) {
@@ -635,6 +639,20 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (npages) OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
+  f->fd.file = file;
+  f->fd.pages = f->d_pages;
+  f->fd.tiles = f->d_tiles;
+  f->fd.ckl = f->d_ckl;
+  f->fd.ckv = f->d_ckv;
+  f->fd.strck = f->d_strck;
+  f->fd.sblk = f->d_sblk;
+  f->fd.sblk_page = f->d_sblk_page;
+  // ---- resident dictionaries (decompressed pages are still in d_scratch) ----
+  {
+    pq_status st5 = build_dicts(f, d_scratch, s);
+    if (st5 != PQ_OK) { cleanup_open(); free_handle(f); return st5; }
+  }
+  f->fd.dicts = f->d_dicts;
   cleanup_open();
 #undef OPEN_HIP
 #undef OPEN_ERR
@@ -658,6 +676,10 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   }
   S.tiles = (int64_t)tiles;
   S.open_ms_device = ms + prefix_ms;
+  f->device_bytes += 4 + sizeof(ChunkDev) * (uint64_t)nchunks + sizeof(PageDev) * (uint64_t)npages +
+                     (sizeof(TileDev) + 4ull * NLCK + sizeof(Ck) * NSUB) * tiles + 4ull * strck + 8ull * sblk +
+                     8ull * (tiles + 1) + sizeof(DictSlot) * (uint64_t)nchunks;
+  S.device_bytes = f->device_bytes;
   (void)t0;
   *out = f;
   return PQ_OK;
@@ -695,15 +717,137 @@ extern "C" pq_status pq_file_stats_get(pq_file f, pq_file_stats* out) {
 }
 
 // ---------------------------------------------------------------------------
+// resident dictionaries (built once, at open)
+// ---------------------------------------------------------------------------
+// Every dictionary page of the file becomes a DictSlot of its chunk: the
+// fixed-width array (the page body itself when it is uncompressed and
+// aligned, else a copy made by k_dict), or for strings the body (copied out
+// of the decompression buffer when the page is compressed), (position,
+// length) pairs, the length array and, for dictionaries that serve at least
+// SLOT_ROWS_PER_ENTRY rows of their row group per entry, 64-byte slots.
+// `scratch` holds the decompressed pages at their file-wide scratch offsets.
+static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s) {
+  const int nchunks = f->ncols * f->nrg;
+  f->dicts.assign((size_t)nchunks, DictSlot{});
+  std::vector<DictWork> work;
+  struct Copy { uint64_t dst; uint64_t src; uint64_t n; };
+  std::vector<Copy> copies;  // decompressed string dictionary bodies -> arena
+  uint64_t off = 0;
+  uint32_t units = 0;
+  for (int q = 0; q < nchunks; ++q) {
+    DictSlot& sl = f->dicts[(size_t)q];
+    memset(&sl, 0, sizeof(sl));
+    sl.page = ~0u;
+    sl.type = f->chunks[(size_t)q].type;
+    const uint32_t p0 = f->chunk_page0[(size_t)q];
+    if (p0 >= f->chunk_page0[(size_t)q + 1] || f->pages[p0].kind != PAGE_DICT) continue;
+    const PageDev& pg = f->pages[p0];
+    const bool comp = (pg.flags & 2) != 0;
+    sl.page = p0;
+    sl.n = (uint32_t)(pg.num_values > 0 ? pg.num_values : 0);
+    const uint64_t n = sl.n;
+    uint32_t nu = 0;
+    if (sl.type != T_BYTE_ARRAY) {
+      const uint64_t w = sl.type == T_INT32 ? 4 : 8;
+      if (!comp && ((uintptr_t)(f->file + pg.val_off) % w) == 0) {
+        sl.entries = const_cast<uint8_t*>(f->file + pg.val_off);  // the body is the array
+        continue;
+      }
+      sl.body = comp ? scratch : f->file;
+      sl.body_off = pg.val_off;
+      sl.entries = reinterpret_cast<uint8_t*>(off);  // arena offset until the arena exists
+      off = align_up(off + w * n + 16, 256);
+      nu = (uint32_t)((n + DICT_FIXED_PER - 1) / DICT_FIXED_PER);
+    } else {
+      if (comp) {
+        sl.body = reinterpret_cast<const uint8_t*>(off);
+        sl.body_off = 0;
+        copies.push_back(Copy{off, pg.val_off, pg.val_len});
+        off = align_up(off + pg.val_len + SCRATCH_PAD, 256);
+      } else {
+        sl.body = f->file;
+        sl.body_off = pg.val_off;
+      }
+      sl.entries = reinterpret_cast<uint8_t*>(off);
+      off = align_up(off + 8 * n + 16, 256);
+      if (pg.dict_maxlen < 65536) sl.flags |= DICT_LENS16;
+      sl.lens = reinterpret_cast<uint8_t*>(off);
+      off = align_up(off + ((sl.flags & DICT_LENS16) ? 2 : 4) * n + 16, 256);
+      const int g = q % f->nrg;
+      if (pg.dict_maxlen <= SLOT_CHARS && n * SLOT_BYTES < (1ull << 32) &&
+          n * SLOT_ROWS_PER_ENTRY <= (uint64_t)f->rg_rows[(size_t)g]) {
+        sl.flags |= DICT_SLOTS;
+        sl.slots = reinterpret_cast<uint8_t*>(off);
+        off = align_up(off + SLOT_BYTES * n, 256);
+      }
+      nu = (uint32_t)(((n + STR_CK - 1) / STR_CK + DICT_CK_PER - 1) / DICT_CK_PER);
+    }
+    if (nu) {
+      work.push_back(DictWork{(uint32_t)q, nu, units, 0});
+      units += nu;
+    }
+  }
+  if (off) {
+    if (hipMalloc(&f->d_dict_arena, off) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for dictionaries");
+    f->device_bytes += off;
+  }
+  auto rebase = [&](const uint8_t* x) { return f->d_dict_arena + reinterpret_cast<uintptr_t>(x); };
+  for (int q = 0; q < nchunks; ++q) {
+    DictSlot& sl = f->dicts[(size_t)q];
+    if (sl.page == ~0u) continue;
+    const PageDev& pg = f->pages[sl.page];
+    const bool comp = (pg.flags & 2) != 0;
+    if (sl.type != T_BYTE_ARRAY) {
+      if (sl.body) sl.entries = rebase(sl.entries);
+      continue;
+    }
+    if (comp) sl.body = rebase(sl.body);
+    sl.entries = rebase(sl.entries);
+    sl.lens = rebase(sl.lens);
+    if (sl.flags & DICT_SLOTS) sl.slots = rebase(sl.slots);
+  }
+  for (const Copy& c : copies)
+    HIP_OR(hipMemcpyAsync(f->d_dict_arena + c.dst, scratch + c.src, c.n, hipMemcpyDeviceToDevice, s));
+  HIP_OR(hipMalloc(&f->d_dicts, sizeof(DictSlot) * (size_t)(nchunks ? nchunks : 1)));
+  if (nchunks)
+    HIP_OR(hipMemcpyAsync(f->d_dicts, f->dicts.data(), sizeof(DictSlot) * (size_t)nchunks, hipMemcpyHostToDevice, s));
+  if (units) {
+    DictWork* d_work = nullptr;
+    HIP_OR(hipMalloc(&d_work, sizeof(DictWork) * work.size()));
+    hipError_t e = hipMemcpyAsync(d_work, work.data(), sizeof(DictWork) * work.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_dict, dim3((units + 3) / 4), dim3(256), 0, s, f->d_pages, f->d_strck, f->d_dicts, d_work,
+                         (uint32_t)work.size(), f->d_err);
+      e = hipGetLastError();
+    }
+    pq_status st = e == hipSuccess ? read_err(f, s) : fail(PQ_EHIP, "open: k_dict: %s", hipGetErrorString(e));
+    (void)hipFree(d_work);
+    if (st != PQ_OK) return st;
+  }
+  // fixed-width copies no longer need their source; the decompression buffer
+  // is freed after the open
+  bool changed = false;
+  for (DictSlot& sl : f->dicts)
+    if (sl.page != ~0u && sl.type != T_BYTE_ARRAY && sl.body) { sl.body = nullptr; sl.body_off = 0; changed = true; }
+  if (changed)
+    HIP_OR(hipMemcpyAsync(f->d_dicts, f->dicts.data(), sizeof(DictSlot) * (size_t)nchunks, hipMemcpyHostToDevice, s));
+  HIP_OR(hipStreamSynchronize(s));
+  return PQ_OK;
+}
+
+// ---------------------------------------------------------------------------
 // scan planning
 // ---------------------------------------------------------------------------
 namespace {
 
+// Workspace header: the scan's error word (first error wins; code | page << 8)
+// in the first 256 bytes, then the column table and the string-column list.
+constexpr uint64_t WS_HEADER = 256;
+
 struct Plan {
   std::vector<ColScan> cols;
-  std::vector<DictSlot> slots;
   int64_t rows = 0;
-  uint64_t ws_cols = 0, ws_slots = 0, ws_total = 0;
+  uint64_t ws_cols = 0, ws_which = 0, ws_total = 0;
   // launch lists
   std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs[2], edge_segs;
   std::vector<int32_t> str_cols;    // string ColScan indices (k_str_total)
@@ -713,33 +857,26 @@ struct Plan {
   bool str_spread[2] = {false, false}, fixed_spread[4] = {false, false, false, false};  // columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
-  std::vector<DictWork> dict_work;  // k_dict units, one entry per dictionary of the scan
-  uint64_t ws_which = 0, ws_dwork = 0;
-  uint32_t dict_units = 0;  // k_dict waves
 };
 
 // Work lists and workspace layout of a scan of `mask` over row groups
 // [rg_b, rg_e).  With `index`, the plan of the open-time prefix pass instead:
-// decompression, dictionaries and k_prepass of the columns that need a tile
-// prefix, with a per-tile array in the workspace.
+// decompression and k_prepass of the columns that need a tile prefix, with a
+// per-tile array in the workspace.
 pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P, bool index = false) {
   if (rg_b < 0 || rg_e > f->nrg || rg_b > rg_e) return fail(PQ_EINVAL, "bad row-group range [%d, %d)", rg_b, rg_e);
   if (f->ncols < 64 && (mask >> f->ncols)) return fail(PQ_EINVAL, "column mask selects missing columns");
   P.rows = f->rg_row0[rg_e] - f->rg_row0[rg_b];
-  uint64_t off = 0;
   int ncs = __builtin_popcountll(mask);
-  P.ws_cols = off;
-  off = align_up(off + sizeof(ColScan) * (ncs ? ncs : 1), 256);
+  P.ws_cols = WS_HEADER;
+  uint64_t off = align_up(P.ws_cols + sizeof(ColScan) * (ncs ? ncs : 1), 256);
   P.ws_which = off;
   off = align_up(off + sizeof(int32_t) * 64, 256);
-  // dictionary slots: one per scanned chunk
-  const int nch = rg_e - rg_b;
-  P.ws_slots = off;
-  off = align_up(off + sizeof(DictSlot) * (size_t)(ncs * nch ? ncs * nch : 1), 256);
   for (int c = 0; c < f->ncols; ++c) {
     if (!((mask >> c) & 1)) continue;
     ColScan cs;
     memset(&cs, 0, sizeof(cs));
+    cs.fd = f->fd;
     cs.type = f->cols[c].type;
     cs.optional = f->cols[c].optional;
     cs.width = cs.type == T_INT32 ? 4 : (cs.type == T_BYTE_ARRAY ? 0 : 8);
@@ -755,38 +892,6 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     const uint64_t sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
     cs.ws_scratch = off;
     off = align_up(off + sbytes, 256);
-    cs.dict_slot0 = (uint32_t)P.slots.size();
-    cs.rg_begin = rg_b;
-    cs.nrg = f->nrg;
-    for (int g = rg_b; g < rg_e; ++g) {
-      const uint32_t q = (uint32_t)(c * f->nrg + g);
-      DictSlot sl;
-      memset(&sl, 0, sizeof(sl));
-      sl.page = ~0u;
-      if (f->chunk_page0[q] < f->chunk_page0[q + 1] && f->pages[f->chunk_page0[q]].kind == PAGE_DICT) {
-        const PageDev& dp = f->pages[f->chunk_page0[q]];
-        sl.page = f->chunk_page0[q];
-        sl.n = (uint32_t)dp.num_values;
-        sl.ws_entries = off;
-        const uint64_t bytes = cs.type == T_BYTE_ARRAY ? 8ull * sl.n : (uint64_t)cs.width * sl.n;
-        off = align_up(off + bytes + 16, 256);
-        if (cs.type == T_BYTE_ARRAY) {
-          if (dp.dict_maxlen < 65536) sl.flags |= DICT_LENS16;
-          sl.ws_lens = off;
-          off = align_up(off + (uint64_t)((sl.flags & DICT_LENS16) ? 2 : 4) * sl.n + 16, 256);
-          if (!index && dp.dict_maxlen <= SLOT_CHARS && (uint64_t)sl.n * SLOT_BYTES < (1ull << 32) &&
-              (uint64_t)sl.n * SLOT_ROWS_PER_ENTRY <= (uint64_t)(f->rg_row0[g + 1] - f->rg_row0[g])) {
-            sl.flags |= DICT_SLOTS;
-            sl.ws_slots = off;
-            off = align_up(off + (uint64_t)SLOT_BYTES * sl.n, 256);
-          }
-        }
-        const uint32_t nu = cs.type == T_BYTE_ARRAY ? ((sl.n + STR_CK - 1) / STR_CK + DICT_CK_PER - 1) / DICT_CK_PER
-                                                    : (sl.n + DICT_FIXED_PER - 1) / DICT_FIXED_PER;
-        P.dict_work.push_back(DictWork{(uint32_t)P.cols.size(), (uint32_t)P.slots.size(), std::max(nu, 1u), 0});
-      }
-      P.slots.push_back(sl);
-    }
     bool has_delta = false, has_plain = false, has_dict = false, has_slots = false;
     for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
       if (f->pages[p].kind == PAGE_DICT) continue;
@@ -794,8 +899,7 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       if (e == E_DELTA) {
         has_delta = true;
       } else if (e == E_PLAIN_DICT || e == E_RLE_DICT) {
-        const uint32_t g = f->pages[p].chunk % (uint32_t)f->nrg;
-        if (cs.type == T_BYTE_ARRAY && (P.slots[cs.dict_slot0 + (g - (uint32_t)rg_b)].flags & DICT_SLOTS))
+        if (cs.type == T_BYTE_ARRAY && (f->dicts[f->pages[p].chunk].flags & DICT_SLOTS))
           has_slots = true;
         else
           has_dict = true;
@@ -877,52 +981,33 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     P.str_spread[k] = true;
     P.str_units[k] = (uint32_t)P.str_segs[k].size() * most;
   }
-  // k_dict's work table: first units set here, copied into the workspace by
-  // the scan (one launch for every dictionary of the scan)
-  for (DictWork& w : P.dict_work) {
-    w.unit0 = P.dict_units;
-    P.dict_units += w.units;
-  }
-  P.ws_dwork = off;
-  off = align_up(off + sizeof(DictWork) * (P.dict_work.empty() ? 1 : P.dict_work.size()), 256);
   P.ws_total = std::max<uint64_t>(off, 256);
   return PQ_OK;
 }
 
 }  // namespace
 
-// Decompression and dictionaries of a plan: the steps the open-time prefix
-// pass and a scan share.
-static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
+// The workspace header (cleared error word, column table, string columns) in
+// one host-to-device copy, then decompression: the steps the open-time
+// prefix pass and a scan share.
+static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, hipStream_t s) {
   ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
-  DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
-  int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
-  if (!P.cols.empty()) HIP_OR(hipMemcpyAsync(d_cols, P.cols.data(), sizeof(ColScan) * P.cols.size(), hipMemcpyHostToDevice, s));
-  if (!P.slots.empty()) HIP_OR(hipMemcpyAsync(d_slots, P.slots.data(), sizeof(DictSlot) * P.slots.size(), hipMemcpyHostToDevice, s));
-  if (!P.str_cols.empty()) HIP_OR(hipMemcpyAsync(d_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size(), hipMemcpyHostToDevice, s));
-  DictWork* d_dwork = reinterpret_cast<DictWork*>(ws + P.ws_dwork);
-  if (!P.dict_work.empty())
-    HIP_OR(hipMemcpyAsync(d_dwork, P.dict_work.data(), sizeof(DictWork) * P.dict_work.size(), hipMemcpyHostToDevice, s));
-  const uint8_t* file = f->file;
+  std::vector<uint8_t> hdr(P.ws_which + sizeof(int32_t) * P.str_cols.size(), 0);
+  if (!P.cols.empty()) memcpy(hdr.data() + P.ws_cols, P.cols.data(), sizeof(ColScan) * P.cols.size());
+  if (!P.str_cols.empty()) memcpy(hdr.data() + P.ws_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size());
+  HIP_OR(hipMemcpyAsync(ws, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
     if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
   if (P.snappy_waves) {
     ProfScope ps_(f, KP_SNAPPY, s);
-    hipLaunchKernelGGL(k_snappy, dim3(P.snappy_waves), dim3(64), 0, s, file, f->d_pages, d_cols,
-                       make_segs(P.snappy_segs), ws, f->d_sblk, 0, f->d_err);
+    hipLaunchKernelGGL(k_snappy, dim3(P.snappy_waves), dim3(64), 0, s, d_cols, make_segs(P.snappy_segs), ws, 0, err);
     HIP_OR(hipGetLastError());
   }
   if (P.sblk_lanes) {
     ProfScope ps_(f, KP_SNAPPY_BLK, s);
-    hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s, file, f->d_pages, d_cols,
-                       make_segs(P.sblk_segs), f->d_sblk, f->d_sblk_page, ws, f->d_err);
-    HIP_OR(hipGetLastError());
-  }
-  if (P.dict_units) {
-    ProfScope ps_(f, KP_DICT, s);
-    hipLaunchKernelGGL(k_dict, dim3((P.dict_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages, d_slots,
-                       f->d_strck, d_dwork, (uint32_t)P.dict_work.size(), f->d_err);
+    hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
+                       d_cols, make_segs(P.sblk_segs), ws, err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
@@ -931,62 +1016,56 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
 // The open-time prefix pass of a plan made with index = true: per-tile DELTA
 // sums and string byte counts into the workspace's tile arrays.
 static pq_status enqueue_index(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
-  pq_status st = enqueue_front(f, P, ws, s);
+  pq_status st = enqueue_front(f, P, ws, f->d_err, s);
   if (st != PQ_OK) return st;
   if (P.pre_units) {
-    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, f->file, ws,
-                       reinterpret_cast<ColScan*>(ws + P.ws_cols), f->d_pages, f->d_tiles, f->d_ckv,
-                       reinterpret_cast<DictSlot*>(ws + P.ws_slots), make_segs(P.pre_segs), f->d_err);
+    hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, ws,
+                       reinterpret_cast<ColScan*>(ws + P.ws_cols), make_segs(P.pre_segs), f->d_err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
 }
 
 static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
-  pq_status st = enqueue_front(f, P, ws, s);
+  uint32_t* err = reinterpret_cast<uint32_t*>(ws);  // the scan's error word
+  pq_status st = enqueue_front(f, P, ws, err, s);
   if (st != PQ_OK) return st;
   ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
-  DictSlot* d_slots = reinterpret_cast<DictSlot*>(ws + P.ws_slots);
   int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
-  const uint8_t* file = f->file;
   if (!P.str_cols.empty()) {
     ProfScope ps_(f, KP_STR_TOTAL, s);
-    hipLaunchKernelGGL(k_str_total, dim3(1), dim3(64), 0, s, d_cols, d_which, (int32_t)P.str_cols.size(), f->d_tpfx,
-                       f->d_err);
+    hipLaunchKernelGGL(k_str_total, dim3(1), dim3(64), 0, s, d_cols, d_which, (int32_t)P.str_cols.size(), err);
     HIP_OR(hipGetLastError());
   }
   if (P.prep_threads) {
     ProfScope ps_(f, KP_PREP, s);
-    hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, f->d_pages, f->d_tiles,
-                       make_segs(P.prep_segs));
+    hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
   }
   for (int K = 0; K < 4; ++K) {
     if (!P.fixed_units[K]) continue;
     ProfScope ps_(f, KP_FIXED0 + K, s);
     auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
-    hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, file, ws, d_cols, f->d_pages,
-                       f->d_tiles, f->d_ckl, f->d_ckv, d_slots, make_segs(P.fixed_segs[K], P.fixed_spread[K]), f->d_err);
+    hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, ws, d_cols,
+                       make_segs(P.fixed_segs[K], P.fixed_spread[K]), err);
     HIP_OR(hipGetLastError());
   }
   if (P.delta_units) {
     ProfScope ps_(f, KP_DELTA, s);
-    hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, file, ws, d_cols,
-                       f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, f->d_tpfx, make_segs(P.delta_segs), f->d_err);
+    hipLaunchKernelGGL(k_decode_delta, dim3((P.delta_units + 3) / 4), dim3(256), 0, s, ws, d_cols,
+                       make_segs(P.delta_segs), err);
     HIP_OR(hipGetLastError());
   }
   for (int k = 0; k < 2; ++k) {
     if (!P.str_units[k]) continue;
     ProfScope ps_(f, k ? KP_STR_SLOTS : KP_STR, s);
     hipLaunchKernelGGL(k ? k_decode_str<true> : k_decode_str<false>, dim3((P.str_units[k] + 3) / 4), dim3(256), 0, s,
-                       file, ws, d_cols, f->d_pages, f->d_tiles, f->d_ckl, f->d_ckv, d_slots, f->d_strck, f->d_tpfx,
-                       make_segs(P.str_segs[k], P.str_spread[k]), f->d_err);
+                       ws, d_cols, make_segs(P.str_segs[k], P.str_spread[k]), err);
     HIP_OR(hipGetLastError());
   }
   if (P.edge_threads) {
     ProfScope ps_(f, KP_EDGES, s);
-    hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, f->d_pages,
-                       f->d_tiles, make_segs(P.edge_segs));
+    hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, make_segs(P.edge_segs));
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
@@ -1000,6 +1079,8 @@ constexpr uint64_t INDEX_WS_CAP = 1ull << 30;
 static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
   const uint64_t nt = f->total_tiles;
   std::vector<uint64_t> val(nt, 0);
+  // the prefix pass reads the tile prefix of no column, but every ColScan
+  // carries the file's tables
   for (int c = 0; c < f->ncols; ++c) {
     bool need = f->cols[c].type == T_BYTE_ARRAY;
     for (uint32_t p = f->chunk_page0[(size_t)c * f->nrg]; !need && p < f->chunk_page0[(size_t)(c + 1) * f->nrg]; ++p)
@@ -1036,14 +1117,11 @@ static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
   for (uint64_t t = 0; t < nt; ++t) f->tpfx[t + 1] = f->tpfx[t] + val[t];
   HIP_OR(hipMalloc(&f->d_tpfx, 8ull * (nt + 1)));
   HIP_OR(hipMemcpy(f->d_tpfx, f->tpfx.data(), 8ull * (nt + 1), hipMemcpyHostToDevice));
+  f->fd.tpfx = f->d_tpfx;
   return PQ_OK;
 }
 
-extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, void* workspace,
-                             uint64_t workspace_bytes, pq_scan_sizes* out, pq_stream stream) {
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)stream;
+extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, pq_scan_sizes* out) {
   if (!f || !out) return fail(PQ_EINVAL, "NULL argument");
   Plan P;
   pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
@@ -1059,26 +1137,17 @@ extern "C" pq_status pq_plan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
   return PQ_OK;
 }
 
-extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
-                             int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream) {
-  if (!f) return fail(PQ_EINVAL, "NULL handle");
-  Plan P;
-  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
-  if (st != PQ_OK) return st;
-  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+// Checks the caller's output descriptors against a plan and stores their
+// pointers in its column table.
+static pq_status bind_outputs(Plan& P, const pq_column_out* outs, int32_t n_outs) {
   if ((int32_t)P.cols.size() != n_outs) return fail(PQ_EINVAL, "n_outs (%d) differs from the mask's columns (%d)", n_outs, (int)P.cols.size());
   if (n_outs && !outs) return fail(PQ_EINVAL, "outs is NULL");
-  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
-  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned (%llu < %llu)",
-                                                (unsigned long long)workspace_bytes, (unsigned long long)P.ws_total);
-  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
   for (size_t k = 0; k < P.cols.size(); ++k) {
     ColScan& cs = P.cols[k];
     const pq_column_out& o = outs[k];
     if (o.validity && ((uintptr_t)o.validity & 3)) return fail(PQ_EINVAL, "column %d: validity must be 4-byte aligned", cs.col);
     if (cs.optional && !o.validity && P.rows > 0) return fail(PQ_EINVAL, "column %d: OPTIONAL column needs a validity buffer", cs.col);
     if (cs.type == T_BYTE_ARRAY) {
-      if (P.rows > 0 && !o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);
       if (!o.offsets) return fail(PQ_EINVAL, "column %d: offsets is NULL", cs.col);
       if (o.chars_capacity && !o.chars) return fail(PQ_EINVAL, "column %d: chars is NULL", cs.col);
       cs.offsets = o.offsets;
@@ -1091,12 +1160,29 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
     }
     cs.validity = o.validity;
   }
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
+                             int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  Plan P;
+  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
+  if (st != PQ_OK) return st;
+  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned (%llu < %llu)",
+                                                (unsigned long long)workspace_bytes, (unsigned long long)P.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
+  st = bind_outputs(P, outs, n_outs);
+  if (st != PQ_OK) return st;
   return enqueue(f, P, (uint8_t*)workspace, (hipStream_t)stream);
 }
 
-extern "C" pq_status pq_scan_check(pq_file f, pq_stream stream) {
+extern "C" pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream) {
   if (!f) return fail(PQ_EINVAL, "NULL handle");
-  return read_err(f, (hipStream_t)stream);
+  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  return read_err_word(reinterpret_cast<uint32_t*>(const_cast<void*>(workspace)), (hipStream_t)stream);
 }
 
 extern "C" pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes) {

@@ -148,37 +148,57 @@ struct TileDev {
                       // PLAIN strings: byte offset just past the tile's last value
 };
 
-// Decoded dictionary of one column chunk inside the workspace.
-// String dictionaries also get an array of entry lengths (u16 when every
-// entry is shorter than 2^16 bytes, else u32) and, when every entry fits
-// SLOT_CHARS bytes, a copy of the entries in fixed SLOT_BYTES slots (u32
-// length first, then the chars, zero-padded), so that one row's gather --
-// length and chars together -- touches one aligned 64-byte piece of memory.
+// Decoded dictionary of one column chunk, built once when the file is
+// opened and kept by the handle (one entry per chunk; n == 0 and page == ~0u
+// for a chunk without a dictionary page).  Fixed-width entries are the page
+// body itself when it is uncompressed and aligned to the value width, else a
+// copy.  String dictionaries keep their body (a copy when the page is
+// compressed), (position, length) u32 pairs relative to the body, an array of
+// entry lengths (u16 when every entry is shorter than 2^16 bytes, else u32)
+// and, when every entry fits SLOT_CHARS bytes, a copy of the entries in fixed
+// SLOT_BYTES slots (u32 length first, then the chars, zero-padded), so that
+// one row's gather -- length and chars together -- touches one aligned
+// 64-byte piece of memory.
 constexpr uint32_t SLOT_BYTES = 64;
 constexpr uint32_t SLOT_CHARS = 60;
 static_assert(SLOT_BYTES == 64 && SLOT_CHARS < 64, "a slot offset and a length share one word");
 // Slots are built only for a dictionary that serves at least this many rows
-// of its row group per entry: building a slot costs about as much as the
-// gathers of a few rows save (a 10^6-distinct-value string column in 1M-row
-// row groups scans faster without slots, in 8M-row ones with them).
+// of its row group per entry: a slot costs 64 bytes of device memory per
+// entry for as long as the file is open, which pays only when entries are
+// gathered several times.
 constexpr uint64_t SLOT_ROWS_PER_ENTRY = 4;
 enum : uint32_t { DICT_SLOTS = 1, DICT_LENS16 = 2 };
 struct DictSlot {
-  const uint8_t* body;   // 16-byte aligned base holding the dictionary page body (file or
-                         // scratch), set on the device
-  uint64_t body_off;     // offset of the body from `body`, set on the device
-  uint64_t ws_entries;   // workspace offset: fixed-width entries, or (pos,len) u32 pairs
-  uint64_t ws_lens;      // strings: workspace offset of the entry lengths
-  uint64_t ws_slots;     // strings with DICT_SLOTS: workspace offset of the slots
+  const uint8_t* body;   // 16-byte aligned base holding the dictionary page body
+  uint64_t body_off;     // offset of the body's first byte from `body`
+  uint8_t* entries;      // fixed width: the n entries; strings: (pos, len) u32 pairs
+  uint8_t* lens;         // strings: entry lengths
+  uint8_t* slots;        // strings with DICT_SLOTS: the slots
   uint32_t n;            // entries (0: chunk has no dictionary)
   uint32_t page;         // dictionary page index (~0u: none)
   uint32_t flags;        // DICT_SLOTS, DICT_LENS16
-  uint32_t pad_;
+  int32_t type;          // physical type of the column
+};
+
+// Device tables of one opened file, as the kernels of a scan see them (a
+// scan over several files carries one copy per selected column).
+struct FileDev {
+  const uint8_t* file;         // the file bytes (borrowed device buffer)
+  const PageDev* pages;        // page table
+  const TileDev* tiles;        // tile index
+  const uint32_t* ckl;         // level checkpoints, NLCK per tile
+  const Ck* ckv;               // value-stream checkpoints, NSUB per tile
+  const uint32_t* strck;       // string checkpoints
+  const uint64_t* tpfx;        // tile prefix (tiles + 1 entries)
+  uint32_t* sblk;              // Snappy block index (written by the open-time pass)
+  const uint32_t* sblk_page;   // page of each Snappy block
+  const DictSlot* dicts;       // resident dictionaries, one per chunk (col * nrg + rg)
 };
 
 // Per-scan, per-selected-column table (built on the host, copied into the
 // caller's workspace before the kernels run).
 struct ColScan {
+  FileDev fd;             // the tables of the file this column belongs to
   int32_t type;
   int32_t optional;
   int32_t width;          // 4 or 8 (fixed width); 0 for BYTE_ARRAY
@@ -191,16 +211,12 @@ struct ColScan {
   int64_t rows;           // output rows
   uint64_t scratch_base;  // file-wide scratch offset of this column's first scanned page
   uint64_t ws_scratch;    // workspace offset where this column's decompressed pages start
-  uint32_t dict_slot0;    // first DictSlot of this column (one per scanned chunk)
-  int32_t rg_begin;       // first scanned row group
   uint64_t ws_tile_aux;   // workspace offset of per-tile int64 auxiliaries
   uint64_t chars_capacity;
   void* values;
   uint8_t* validity;
   int64_t* offsets;
   uint8_t* chars;
-  int32_t nrg;            // row groups in the file (chunk = col * nrg + rg)
-  int32_t pad_;
   uint64_t ws_edge;       // workspace offset of per-tile validity edge words (OPTIONAL columns)
 };
 
@@ -216,13 +232,25 @@ struct SegTable {
   Segment s[MAX_SEGS];
   int32_t n;
   int32_t spread;
+  const Segment* ptr;  // n > MAX_SEGS: the segments in device memory, ascending in wg0
 };
 
-// k_dict work: dictionary slot `slot` of selected column `col` is units
-// [unit0, unit0 + units) of the launch (one wave each).  The scan's table of
-// them is copied into the workspace, ascending in unit0.
+// Batched scans (several files, requests and columns in one launch): every
+// unit of work is a run of tiles of one column that one decoder handles.
+// The persistent kernel takes units from NQUEUE work queues, queue q first
+// for the workgroups dispatched to XCD q (workgroup i runs on XCD i mod 8),
+// then the others.
+enum : uint32_t { TK_FIXED0 = 0, TK_FIXED1, TK_FIXED2, TK_FIXED3, TK_DELTA, TK_STR, TK_STRSLOT, TK_KINDS };
+struct BUnit {
+  uint32_t cs, t0, t1, kind;
+};
+constexpr int NQUEUE = 8;
+
+// k_dict work (one launch at open for every dictionary page of the file):
+// dictionary `slot` (a chunk index) is units [unit0, unit0 + units) of the
+// launch, one wave each; the table is ascending in unit0.
 struct DictWork {
-  uint32_t col, slot, units, unit0;
+  uint32_t slot, units, unit0, pad_;
 };
 // entries per k_dict wave: fixed-width dictionaries; string dictionaries
 // take DICT_CK_PER checkpoints of STR_CK entries

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   WR r;
   lds_u4* win = (lds_u4*)&s_win[0];
   // Stores that nothing in this kernel reads back (checkpoints) come from
-  // lane 0 alone, except in the string dictionary walk (see there).
+  // lane 0 alone.
   // Tiles and the page entry are stored by every lane (each lane reads back
   // its own stores).
   const bool lead = (threadIdx.x & 63) == 0;
@@ -318,10 +318,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
         const uint64_t wpos = wr_refill(base, blim, win, (off + q) & ~15ull);
         uint32_t o = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off + q - wpos));  // below 272
         while (k < n && o + 8 <= WIN) {
-          // every lane stores the same checkpoint (one write after
-          // coalescing): a store from lane 0 alone would make the test a
-          // vector compare and an exec-mask change on every entry
-          if ((k % STR_CK) == 0) strck[pg.strck_begin + k / STR_CK] = q;
+          if ((k % STR_CK) == 0 && lead) strck[pg.strck_begin + k / STR_CK] = q;
           if (bl - q < 4) { set_err(err, ERR_STRING, p); return; }
           const uint32_t l = (uint32_t)__builtin_amdgcn_readfirstlane(
               (int)__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3));

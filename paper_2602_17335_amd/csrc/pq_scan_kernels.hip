@@ -53,6 +53,24 @@ static_assert(NWORDS == 32, "lane j < 32 holds validity word j");
 // patterns free of bank conflicts.
 __device__ __forceinline__ uint32_t pad(uint32_t j) { return j + (j >> 4); }
 
+// Wave-uniform reads of tables that no kernel of a scan writes (the column
+// table, the file's page table, tile index, dictionaries and tile prefix).
+// Every lane reads the same address; the value is then moved dword by dword
+// into scalar registers, so that it does not hold vector registers for the
+// rest of the tile (the compiler cannot prove these tables unwritten and so
+// would keep a vector load's result in VGPRs).
+template <class T>
+__device__ __forceinline__ T sload(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized tables");
+  const T v = *p;
+  T r;
+  const uint32_t* a = reinterpret_cast<const uint32_t*>(&v);
+  uint32_t* b = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(T) / 4; ++i) b[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)a[i]);
+  return r;
+}
+
 struct Streams {
   const uint8_t* dbase;
   uint64_t doff, dend;
@@ -60,7 +78,8 @@ struct Streams {
   uint64_t voff, vend;
 };
 
-__device__ __forceinline__ Streams page_streams(const PageDev& pg, const ColScan& cs, const uint8_t* file, uint8_t* ws) {
+__device__ __forceinline__ Streams page_streams(const PageDev& pg, const ColScan& cs, uint8_t* ws) {
+  const uint8_t* file = cs.fd.file;
   Streams s;
   const uint8_t* sb = ws + cs.ws_scratch;
   if (pg.flags & 1) { s.dbase = sb; s.doff = pg.def_off - cs.scratch_base; }
@@ -269,29 +288,56 @@ struct WaveTile {
   int64_t out0;    // output row of the tile's first row
 };
 
-// Unit (tile) of this wave: unit b * NWAVES + w of the launch, mapped to
-// (column, tile) through the segment table.  False past the last unit.
-__device__ __forceinline__ bool wave_tile(const SegTable& seg, const ColScan* cols, const PageDev* pages,
-                                          const TileDev* tiles, const uint8_t* file, uint8_t* ws, WaveTile& c) {
-  const uint32_t unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVES + (threadIdx.x >> 6)));
-  int k = 0;
-  uint32_t t;
-  if (seg.spread) {
-    k = (int)(unit % (uint32_t)seg.n);
-    t = seg.s[k].t0 + unit / (uint32_t)seg.n;
-  } else {
+// The segment holding `unit` (the last one whose first unit is at most
+// `unit`): a scan of the inline table, or a binary search of the device
+// table of a launch with more than MAX_SEGS segments.
+__device__ __forceinline__ Segment seg_lookup(const SegTable& seg, uint32_t unit) {
+  if (seg.n <= MAX_SEGS) {
+    int k = 0;
     for (int j = 1; j < seg.n; ++j)
       if (seg.s[j].wg0 <= unit) k = j;
-    t = seg.s[k].t0 + (unit - seg.s[k].wg0);
+    return seg.s[k];
   }
-  if (t >= seg.s[k].t1) return false;
+  uint32_t lo = 0, hi = (uint32_t)seg.n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg.ptr[mid].wg0 <= unit) lo = mid; else hi = mid;
+  }
+  return seg.ptr[lo];
+}
+
+// A condition the caller knows to be the same in every lane, as the compiler
+// sees it too: an early exit on it is a uniform branch (a divergent one
+// would, inside the persistent kernel's tile loop, make every value that
+// lives across the loop a vector register).
+__device__ __forceinline__ bool uniform_bool(bool v) { return __builtin_amdgcn_readfirstlane((int)v) != 0; }
+
+// Tile t of column table entry cs.
+__device__ __forceinline__ void load_tile(const ColScan* cols, uint32_t cs, uint32_t t, uint8_t* ws, WaveTile& c) {
   c.t = t;
-  c.td = tiles[t];
-  c.cs = cols[seg.s[k].cs];
-  c.pg = pages[c.td.page];
+  c.cs = sload(cols + cs);
+  c.td = sload(c.cs.fd.tiles + t);
+  c.pg = sload(c.cs.fd.pages + c.td.page);
   c.nrows = (uint32_t)min((int64_t)TR, (int64_t)c.pg.num_values - c.td.row0);
   c.out0 = c.pg.row0 + c.td.row0 - c.cs.row_base;
-  c.st = page_streams(c.pg, c.cs, file, ws);
+  c.st = page_streams(c.pg, c.cs, ws);
+}
+
+// Unit (tile) of this wave: unit b * NWAVES + w of the launch, mapped to
+// (column, tile) through the segment table.  False past the last unit.
+__device__ __forceinline__ bool wave_tile(const SegTable& seg, const ColScan* cols, uint8_t* ws, WaveTile& c) {
+  const uint32_t unit = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * NWAVES + (threadIdx.x >> 6)));
+  Segment sg;
+  uint32_t t;
+  if (seg.spread) {
+    sg = seg.s[unit % (uint32_t)seg.n];
+    t = sg.t0 + unit / (uint32_t)seg.n;
+  } else {
+    sg = seg_lookup(seg, unit);
+    t = sg.t0 + (unit - sg.wg0);
+  }
+  if (t >= sg.t1) return false;
+  load_tile(cols, sg.cs, t, ws, c);
   return true;
 }
 
@@ -1078,25 +1124,25 @@ __device__ __forceinline__ void snap_flush(const lds_u8* ring, uint8_t* g0, uint
   }
 }
 
-__global__ __launch_bounds__(64) void k_snappy(const uint8_t* file, const PageDev* pages, const ColScan* cols,
-                                               SegTable seg, uint8_t* ws, uint32_t* sblk, int record,
+__global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record,
                                                uint32_t* err) {
   __shared__ __align__(16) uint8_t s_ring[SNAP_RING];
   __shared__ __align__(16) uint32_t s_in[SNAP_IN / 4 + 4];
   const uint32_t gw = blockIdx.x;
   const uint32_t lane = threadIdx.x & 63;
-  int k = 0;
-  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gw) k = j;
-  const uint32_t csi = seg.s[k].cs;
-  const uint32_t p = seg.s[k].t0 + (gw - seg.s[k].wg0);
-  if (p >= seg.s[k].t1) return;
+  const Segment sg = seg_lookup(seg, gw);
+  const uint32_t csi = sg.cs;
+  const uint32_t p = sg.t0 + (gw - sg.wg0);
+  if (p >= sg.t1) return;
   const ColScan cs = cols[csi];
-  const PageDev pg = pages[p];
+  const PageDev pg = cs.fd.pages[p];
+  uint32_t* sblk = cs.fd.sblk;
   if (pg.scratch_len == 0) return;
-  if (!record && sblk[pg.sblk_begin] != SBLK_NONE) return;  // k_snappy_blk decodes it
+  // dictionaries are decompressed once, at open
+  if (!record && (pg.kind == PAGE_DICT || sblk[pg.sblk_begin] != SBLK_NONE)) return;  // or k_snappy_blk decodes it
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
-  const uint8_t* src = file + src_off;
+  const uint8_t* src = cs.fd.file + src_off;
   uint8_t* dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
   lds_u8* ring = (lds_u8*)&s_ring[0];
   const uint32_t total = pg.scratch_len;
@@ -1372,25 +1418,24 @@ struct SnapLane {
   uint32_t ip, iend, ob, oend, page, pad_;
   bool bad;
 };
-__device__ __forceinline__ bool snap_lane(const uint8_t* file, const PageDev* pages, const ColScan* cols, const SegTable& seg,
-                                          const uint32_t* sblk, const uint32_t* sblk_page, uint8_t* ws, uint32_t gid,
+__device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& seg, uint8_t* ws, uint32_t gid,
                                           SnapLane& sl) {
-  int k = 0;
-  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
-  const uint32_t b = seg.s[k].t0 + (gid - seg.s[k].wg0);
-  if (b >= seg.s[k].t1) return false;
-  const uint32_t p = sblk_page[b];
-  const PageDev pg = pages[p];
-  if (pg.scratch_len == 0) return false;
+  const Segment sg = seg_lookup(seg, gid);
+  const uint32_t b = sg.t0 + (gid - sg.wg0);
+  if (b >= sg.t1) return false;
+  const ColScan cs = cols[sg.cs];
+  const uint32_t* sblk = cs.fd.sblk;
+  const uint32_t p = cs.fd.sblk_page[b];
+  const PageDev pg = cs.fd.pages[p];
+  if (pg.scratch_len == 0 || pg.kind == PAGE_DICT) return false;  // dictionaries: decompressed at open
   const uint32_t first = pg.sblk_begin;
   if (sblk[first] == SBLK_NONE) return false;  // decoded sequentially by k_snappy
-  const ColScan cs = cols[seg.s[k].cs];
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
   const uint32_t total = pg.scratch_len;
   const uint32_t src_len = (uint32_t)src_len64;
   const uint32_t kb = b - first, nblk = (total + SNAP_BLOCK - 1) / SNAP_BLOCK;
-  sl.src = file + src_off;
+  sl.src = cs.fd.file + src_off;
   sl.dst = ws + cs.ws_scratch + (pg.scratch_off - cs.scratch_base);
   sl.ip = sblk[b];
   sl.iend = kb + 1 < nblk ? sblk[b + 1] : src_len;
@@ -1401,15 +1446,13 @@ __device__ __forceinline__ bool snap_lane(const uint8_t* file, const PageDev* pa
   return true;
 }
 
-__global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const PageDev* pages, const ColScan* cols,
-                                                   SegTable seg, const uint32_t* sblk, const uint32_t* sblk_page,
-                                                   uint8_t* ws, uint32_t* err) {
+__global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err) {
   const uint32_t lw = threadIdx.x & 63;
   const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
   // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
   // copy long literals
   SnapLane sl = {nullptr, nullptr, 0u, 0u, 0u, 0u, 0u, 0u, false};
-  const bool live = lw < SNAP_LANES && snap_lane(file, pages, cols, seg, sblk, sblk_page, ws, gid, sl);
+  const bool live = lw < SNAP_LANES && snap_lane(cols, seg, ws, gid, sl);
   const uint8_t* src = sl.src;
   uint8_t* dst = sl.dst;
   uint32_t ip = sl.ip, op = sl.ob;
@@ -1521,16 +1564,15 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const uint8_t* file, const Pa
 // k_prep: validity words shared by two tiles are cleared before any tile
 // ORs into them; REQUIRED columns with a validity buffer get all ones.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_prep(const ColScan* cols, const PageDev* pages, const TileDev* tiles, SegTable seg) {
+__global__ __launch_bounds__(WG) void k_prep(const ColScan* cols, SegTable seg) {
   const uint32_t gid = blockIdx.x * WG + threadIdx.x;  // one thread per tile
-  int k = 0;
-  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
-  const uint32_t t = seg.s[k].t0 + (gid - seg.s[k].wg0);
-  if (t >= seg.s[k].t1) return;
-  const ColScan cs = cols[seg.s[k].cs];
+  const Segment sg = seg_lookup(seg, gid);
+  const uint32_t t = sg.t0 + (gid - sg.wg0);
+  if (t >= sg.t1) return;
+  const ColScan cs = cols[sg.cs];
   if (!cs.validity) return;
-  const TileDev td = tiles[t];
-  const PageDev pg = pages[td.page];
+  const TileDev td = cs.fd.tiles[t];
+  const PageDev pg = cs.fd.pages[td.page];
   const uint32_t nrows = (uint32_t)min((int64_t)TILE_ROWS, (int64_t)pg.num_values - td.row0);
   const int64_t r0 = pg.row0 + td.row0 - cs.row_base;
   uint32_t* v = reinterpret_cast<uint32_t*>(cs.validity);
@@ -1550,18 +1592,16 @@ __global__ __launch_bounds__(WG) void k_prep(const ColScan* cols, const PageDev*
 // recorded (their bits of the words holding their first and last rows).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_edges(const uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
-                                              const PageDev* __restrict__ pages, const TileDev* __restrict__ tiles,
                                               SegTable seg) {
   const uint32_t gid = blockIdx.x * WG + threadIdx.x;  // one thread per tile
-  int k = 0;
-  for (int j = 1; j < seg.n; ++j) if (seg.s[j].wg0 <= gid) k = j;
-  const uint32_t t = seg.s[k].t0 + (gid - seg.s[k].wg0);
-  if (t >= seg.s[k].t1) return;
-  const ColScan cs = cols[seg.s[k].cs];
+  const Segment sg = seg_lookup(seg, gid);
+  const uint32_t t = sg.t0 + (gid - sg.wg0);
+  if (t >= sg.t1) return;
+  const ColScan cs = cols[sg.cs];
   if (!cs.validity || !cs.optional) return;
   auto span = [&](uint32_t u, int64_t& r0) {
-    const TileDev td = tiles[u];
-    const PageDev pg = pages[td.page];
+    const TileDev td = cs.fd.tiles[u];
+    const PageDev pg = cs.fd.pages[td.page];
     r0 = pg.row0 + td.row0 - cs.row_base;
     return (uint32_t)min((int64_t)TILE_ROWS, (int64_t)pg.num_values - td.row0);
   };
@@ -1583,22 +1623,26 @@ __global__ __launch_bounds__(WG) void k_edges(const uint8_t* __restrict__ ws, co
 }
 
 // ---------------------------------------------------------------------------
-// k_dict: dictionary pages of the scanned chunks -> workspace dictionaries.
-// One wave per unit of a DictWork entry.  Fixed-width dictionaries: 1024
-// PLAIN values per wave (16 per lane, all loads before the stores).  String
+// k_dict: dictionary pages -> the handle's resident dictionaries (run once,
+// when the file is opened).  One wave per unit of a DictWork entry.
+// Fixed-width dictionaries whose page body cannot serve as the array (a
+// compressed page, or a body not aligned to the value width): 1024 PLAIN
+// values per wave (16 per lane, all loads before the stores).  String
 // dictionaries: DICT_CK_PER checkpoints (STR_CK entries each, positions from
 // the open-time index) per wave; the wave copies their bytes into LDS with
 // coalesced loads, one lane per checkpoint walks the length prefixes there,
 // and for slot dictionaries the wave then writes every entry's 64-byte slot
-// (length in the first dword, then the chars, zero-padded) from LDS.  A string region
-// larger than the LDS buffer (never for slot dictionaries: at most
-// DICT_CK_PER * STR_CK * SLOT_BYTES bytes) is walked in global memory.
+// (length in the first dword, then the chars, zero-padded) from LDS.  A
+// string region larger than the LDS buffer (never for slot dictionaries: at
+// most DICT_CK_PER * STR_CK * SLOT_BYTES bytes) is walked in global memory.
+// Every lane's walk must end exactly where the next checkpoint starts (the
+// last checkpoint's walk may end before the body does: trailing bytes are
+// ignored), so a wrong checkpoint is reported instead of yielding wrong
+// dictionary strings.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                             const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                             DictSlot* __restrict__ slots, const uint32_t* __restrict__ strck,
-                                             const DictWork* __restrict__ works, uint32_t nworks,
-                                             uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(WG) void k_dict(const PageDev* __restrict__ pages, const uint32_t* __restrict__ strck,
+                                             const DictSlot* __restrict__ slots, const DictWork* __restrict__ works,
+                                             uint32_t nworks, uint32_t* __restrict__ err) {
   constexpr uint32_t NE = DICT_CK_PER * STR_CK;      // entries per string unit
   constexpr uint32_t RB = NE * SLOT_BYTES;           // LDS region bytes
   constexpr uint32_t RW = RB / 4 + 32;               // + slack for the realigning reads
@@ -1616,19 +1660,14 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
   const DictWork wk = works[lo];
   const uint32_t u = unit - wk.unit0;
   if (u >= wk.units) return;
-  const uint32_t si = wk.slot;
-  const DictSlot sl = slots[si];
-  const ColScan cs = cols[wk.col];
+  const DictSlot sl = slots[wk.slot];
   const PageDev pg = pages[sl.page];
-  const uint8_t* body;
-  uint64_t boff;
-  if (pg.flags & 2) { body = ws + cs.ws_scratch; boff = pg.val_off - cs.scratch_base; }
-  else { body = file; boff = pg.val_off; }
-  if (u == 0 && lane == 0) { slots[si].body = body; slots[si].body_off = boff; }
+  const uint8_t* body = sl.body;
+  const uint64_t boff = sl.body_off;
   const uint32_t n = sl.n;
-  if (cs.type != T_BYTE_ARRAY) {
+  if (sl.type != T_BYTE_ARRAY) {
     const uint32_t e0 = u * DICT_FIXED_PER + lane;
-    if (cs.width == 4) {
+    if (sl.type == T_INT32) {
       uint32_t v[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -1638,7 +1677,7 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const uint32_t e = e0 + 64 * j;
-        if (e < n) reinterpret_cast<uint32_t*>(ws + sl.ws_entries)[e] = v[j];
+        if (e < n) reinterpret_cast<uint32_t*>(sl.entries)[e] = v[j];
       }
     } else {
       uint64_t v[16];
@@ -1650,13 +1689,13 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const uint32_t e = e0 + 64 * j;
-        if (e < n) reinterpret_cast<uint64_t*>(ws + sl.ws_entries)[e] = v[j];
+        if (e < n) reinterpret_cast<uint64_t*>(sl.entries)[e] = v[j];
       }
     }
     return;
   }
   // strings: (pos, len) pairs relative to the body, and the entry lengths
-  uint32_t* pairs = reinterpret_cast<uint32_t*>(ws + sl.ws_entries);
+  uint32_t* pairs = reinterpret_cast<uint32_t*>(sl.entries);
   const bool l16 = sl.flags & DICT_LENS16;
   const uint32_t nck = (n + STR_CK - 1) / STR_CK;
   const uint32_t ck0 = u * DICT_CK_PER;
@@ -1669,6 +1708,10 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
     if (lane == 0) set_err(err, ERR_STRING, sl.page);
     return;
   }
+  // where lane's walk (checkpoint ck0 + lane) must end, relative to q0
+  const uint32_t my_ck = ck0 + lane;
+  const bool last_ck = my_ck + 1 >= nck;
+  const uint64_t my_end = my_ck < ck1 ? (last_ck ? q1 : (uint64_t)strck[pg.strck_begin + my_ck + 1]) - q0 : 0;
   const uint64_t R = q1 - q0;
   bool bad = false;
   if (R <= RB) {
@@ -1695,6 +1738,7 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
         s_len[wave][e - e0] = l;
         x += l;
       }
+      if (last_ck ? x > my_end : x != my_end) bad = true;
     }
     if (__ballot(bad)) {
       if (lane == 0) set_err(err, ERR_STRING, sl.page);
@@ -1707,14 +1751,14 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
       const uint32_t l = s_len[wave][i];
       const uint32_t pos = (uint32_t)(q0 + (s_pos[wave][i] - ss));
       reinterpret_cast<uint64_t*>(pairs)[e0 + i] = (uint64_t)pos | ((uint64_t)l << 32);
-      if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e0 + i] = (uint16_t)l;
-      else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e0 + i] = l;
+      if (l16) reinterpret_cast<uint16_t*>(sl.lens)[e0 + i] = (uint16_t)l;
+      else reinterpret_cast<uint32_t*>(sl.lens)[e0 + i] = l;
     }
     if (!(sl.flags & DICT_SLOTS)) return;
     // slots: 16-byte chunk c of entry e per step (slot dword 0 is the
     // length, at most SLOT_CHARS; slot dword D > 0 holds chars [4 D - 4,
     // 4 D), zero past the length)
-    glb_u8* sb = gptr(ws + sl.ws_slots);
+    glb_u8* sb = gptr(sl.slots);
     for (uint32_t i = lane; i < 4 * ne; i += 64) {
       const uint32_t ei = i >> 2, c = i & 3;
       const uint32_t L = s_len[wave][ei];
@@ -1745,10 +1789,11 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
       if (l > (uint64_t)pg.val_len - q) { bad = true; break; }
       pairs[2 * e] = (uint32_t)q;
       pairs[2 * e + 1] = l;
-      if (l16) reinterpret_cast<uint16_t*>(ws + sl.ws_lens)[e] = (uint16_t)l;
-      else reinterpret_cast<uint32_t*>(ws + sl.ws_lens)[e] = l;
+      if (l16) reinterpret_cast<uint16_t*>(sl.lens)[e] = (uint16_t)l;
+      else reinterpret_cast<uint32_t*>(sl.lens)[e] = l;
       q += l;
     }
+    if (!bad && (last_ck ? q - q0 > my_end : q - q0 != my_end)) bad = true;
   }
   if (__ballot(bad) && lane == 0) set_err(err, ERR_STRING, sl.page);
 }
@@ -1758,11 +1803,11 @@ __global__ __launch_bounds__(WG) void k_dict(const uint8_t* __restrict__ file, u
 // column of a scan (one thread per column), from the tile prefix.
 // ---------------------------------------------------------------------------
 __global__ void k_str_total(const ColScan* __restrict__ cols, const int32_t* __restrict__ which, int32_t n,
-                            const uint64_t* __restrict__ tpfx, uint32_t* __restrict__ err) {
+                            uint32_t* __restrict__ err) {
   const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= n) return;
   const ColScan& cs = cols[which[i]];
-  const uint64_t tot = tpfx[cs.tile_end] - tpfx[cs.tile_begin];
+  const uint64_t tot = cs.fd.tpfx[cs.tile_end] - cs.fd.tpfx[cs.tile_begin];
   if (cs.offsets) cs.offsets[cs.rows] = (int64_t)tot;
   if (tot > cs.chars_capacity) set_err(err, ERR_CAPACITY, (uint32_t)cs.col);
 }
@@ -1770,14 +1815,12 @@ __global__ void k_str_total(const ColScan* __restrict__ cols, const int32_t* __r
 // ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                                const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                                const TileDev* __restrict__ tiles, const Ck* __restrict__ ckv,
-                                                const DictSlot* __restrict__ slots, SegTable seg,
-                                                uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                                SegTable seg, uint32_t* __restrict__ err) {
   __shared__ uint32_t s_idx[NWAVES][PADN];
   WaveTile c;
-  if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
+  if (!wave_tile(seg, cols, ws, c)) return;
+  const Ck* ckv = c.cs.fd.ckv;
   const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __attribute__((address_space(1))) uint64_t* aux =
@@ -1805,20 +1848,19 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
 #pragma unroll
     for (int q = 0; q < LPER; ++q) acc += D[q];
   } else {  // dictionary strings: sum of entry lengths over the tile's indices
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    const DictSlot sl = sload(c.cs.fd.dicts + c.pg.chunk);
     if (sl.page == ~0u) {
       if (lane == 0) set_err(err, ERR_DICT_MISSING, c.td.page);
       return;
     }
     lds_u32* idx = (lds_u32*)&s_idx[wave][0];
-    const uint32_t e = decode_indices(c, ckx, sl.n, lane, idx);
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)decode_indices(c, ckx, sl.n, lane, idx));
     if (e) {
       if (lane == 0) set_err(err, e, c.td.page);
       return;
     }
     wave_sync();
-    glb_u8* lens = gptr(ws + sl.ws_lens);
+    glb_u8* lens = gptr(sl.lens);
     uint32_t l[LPER];
 #pragma unroll
     for (int q = 0; q < LPER; ++q) {
@@ -1850,24 +1892,16 @@ __global__ __launch_bounds__(WG) void k_prepass(const uint8_t* __restrict__ file
 // needs; a wave whose tile is of another kind leaves at once.
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
 template <int KIND>
-__global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                                     const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                                     const TileDev* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ ckl,
-                                                     const Ck* __restrict__ ckv,
-                                                     const DictSlot* __restrict__ slots, SegTable seg,
-                                                     uint32_t* __restrict__ err) {
+__device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
+                                           lds_u32* wl) {
   constexpr bool is_dict = KIND & FX_DICT;
   constexpr bool w4 = !(KIND & FX_WIDE);
-  __shared__ uint32_t s_idx[NWAVES][is_dict ? PADN : 1];
-  WaveTile c;
-  if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
-  const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t lane = threadIdx.x & 63;
   const bool dict_page = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   if (!dict_page && enc != E_PLAIN) {
     if (is_dict && lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);  // reported once
@@ -1875,22 +1909,21 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   }
   if (dict_page != is_dict || (c.cs.width == 4) != w4) return;  // another instantiation's tile
   uint32_t vw;
-  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
-  lds_u32* idx = (lds_u32*)&s_idx[wave][0];
+  if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
+  lds_u32* idx = wl;
   glb_u8* ent = nullptr;
   if constexpr (is_dict) {
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    const DictSlot sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    const DictSlot sl = sload(c.cs.fd.dicts + c.pg.chunk);
     if (sl.page == ~0u) {
       if (lane == 0) set_err(err, ERR_DICT_MISSING, c.td.page);
       return;
     }
-    const uint32_t e = decode_indices(c, ckx, sl.n, lane, idx);
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)decode_indices(c, ckx, sl.n, lane, idx));
     if (e) {
       if (lane == 0) set_err(err, e, c.td.page);
       return;
     }
-    ent = gptr(ws + sl.ws_entries);
+    ent = gptr(sl.entries);
     wave_sync();
   }
   const GSrc vs = gsrc(c.st.vbase, c.st.voff, c.st.vend);
@@ -1960,34 +1993,37 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(const uint8_t* __restrict__
   }
 }
 
+template <int KIND>
+__global__ __launch_bounds__(WG) void k_decode_fixed(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                                     SegTable seg, uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_idx[NWAVES][(KIND & FX_DICT) ? PADN : 1];
+  WaveTile c;
+  if (!wave_tile(seg, cols, ws, c)) return;
+  tile_fixed<KIND>(c, ws, err, (lds_u32*)&s_idx[threadIdx.x >> 6][0]);
+}
+
 // ---------------------------------------------------------------------------
 // k_decode_delta: DELTA_BINARY_PACKED INT32 / INT64 tiles
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                                     const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                                     const TileDev* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ ckl,
-                                                     const Ck* __restrict__ ckv,
-                                                     const uint64_t* __restrict__ tpfx, SegTable seg,
-                                                     uint32_t* __restrict__ err) {
-  // per wave: the values of one half of the tile's rows (at most TR / 2)
-  constexpr uint32_t HALF = TR / 2;
-  __shared__ uint64_t s_vals[NWAVES][HALF + HALF / 16 + 4];
-  WaveTile c;
-  if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
-  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
+// per wave: the values of one half of the tile's rows (at most TR / 2)
+constexpr uint32_t DHALF = TR / 2;
+constexpr uint32_t DELTA_LDS_WORDS = 2 * (DHALF + DHALF / 16 + 4);
+__device__ __forceinline__ void tile_delta(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
+                                           lds_u32* wl) {
+  constexpr uint32_t HALF = DHALF;
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t lane = threadIdx.x & 63;
   uint32_t vw;
-  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
-  __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)&s_vals[wave][0];
+  if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
+  __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)wl;
   const uint32_t nn = c.td.nn;
   // lane l holds values 16 l .. 16 l + 15 (prefix sums, in registers)
   uint64_t V[LPER];
 #pragma unroll
   for (int q = 0; q < LPER; ++q) V[q] = 0;
   if (nn > 0) {
-    const bool ok = delta_terms(c, ckv, lane, V);
+    const bool ok = delta_terms(c, c.cs.fd.ckv, lane, V);
     if (__ballot(!ok)) {
       if (lane == 0) set_err(err, ERR_DELTA, c.td.page);
       return;
@@ -1999,7 +2035,7 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
       V[q] = acc;
     }
     const uint64_t ex = wave_incl_scan_u64(acc) - acc;
-    const uint64_t carry = tpfx[c.t] - tpfx[c.pg.tile_begin];
+    const uint64_t carry = sload(c.cs.fd.tpfx + c.t) - sload(c.cs.fd.tpfx + c.pg.tile_begin);
 #pragma unroll
     for (int q = 0; q < LPER; ++q) V[q] += carry + ex;
   }
@@ -2048,43 +2084,44 @@ __global__ __launch_bounds__(WG) void k_decode_delta(const uint8_t* __restrict__
   }
 }
 
+__global__ __launch_bounds__(WG) void k_decode_delta(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                                     SegTable seg, uint32_t* __restrict__ err) {
+  __shared__ uint64_t s_vals[NWAVES][DELTA_LDS_WORDS / 2];
+  WaveTile c;
+  if (!wave_tile(seg, cols, ws, c)) return;
+  tile_delta(c, ws, err, (lds_u32*)&s_vals[threadIdx.x >> 6][0]);
+}
+
 // ---------------------------------------------------------------------------
 // k_decode_str: BYTE_ARRAY tiles -> offsets and chars.  The tile's rows are
 // taken 64 at a time; the strings of a group are gathered into the wave's
 // LDS buffer at their output offsets and stored as aligned 16-byte chunks.
 // ---------------------------------------------------------------------------
+// LDS words per wave of the string tiles: the value positions (indices) of
+// the tile, then, once every row's (position, length) is in registers, the
+// chars staging buffer.  Slot strings are staged in the index area and as
+// much again (about 8.7 KB per wave: a full buffer is stored about every 300
+// rows, and four workgroups still fit a CU's LDS).
 template <bool SLOTS>
-__global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ file, uint8_t* __restrict__ ws,
-                                                   const ColScan* __restrict__ cols, const PageDev* __restrict__ pages,
-                                                   const TileDev* __restrict__ tiles,
-                                                   const uint32_t* __restrict__ ckl,
-                                                   const Ck* __restrict__ ckv,
-                                                   const DictSlot* __restrict__ slots,
-                                                   const uint32_t* __restrict__ strck,
-                                                   const uint64_t* __restrict__ tpfx, SegTable seg,
-                                                   uint32_t* __restrict__ err) {
-  // per wave: the value positions (indices) of the tile, then, once every
-  // row's (position, length) is in registers, the chars staging buffer.
-  // Slot strings are staged in the index area and as much again (about
-  // 8.7 KB per wave: a full buffer is stored about every 300 rows, and four
-  // workgroups still fit a CU's LDS).
-  constexpr uint32_t BUFW = SLOTS ? 2 * PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
+struct StrLds {
+  static constexpr uint32_t BUFW = SLOTS ? 2 * PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
+};
+template <bool SLOTS>
+__device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
+                                         lds_u32* wl) {
+  constexpr uint32_t BUFW = StrLds<SLOTS>::BUFW;
   constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
-  __shared__ __align__(16) uint32_t s_buf[NWAVES][BUFW];
-  WaveTile c;
-  if (!wave_tile(seg, cols, pages, tiles, file, ws, c)) return;
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
-  const Ck ckx = ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lane = threadIdx.x & 63;
   const int enc = c.pg.encoding;
   const bool is_plain = !SLOTS && enc == E_PLAIN;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   DictSlot sl;
   bool slot_tile = false;
   if (is_dict) {
-    const uint32_t rg = c.pg.chunk % (uint32_t)c.cs.nrg;
-    sl = slots[c.cs.dict_slot0 + (rg - (uint32_t)c.cs.rg_begin)];
+    sl = sload(c.cs.fd.dicts + c.pg.chunk);
     slot_tile = sl.page != ~0u && (sl.flags & DICT_SLOTS);
   }
   if (slot_tile != SLOTS) return;  // the other instantiation decodes this tile
@@ -2093,8 +2130,8 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     return;
   }
   uint32_t vw;
-  if (!tile_validity(c, lck, lane, err, ws, vw)) return;
-  lds_u32* u = (lds_u32*)&s_buf[wave][0];
+  if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
+  lds_u32* u = wl;
   const TileDev& td = c.td;
   glb_u8* sbase;
   uint64_t soff;
@@ -2110,7 +2147,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     if (td.nn) {
       const uint32_t ck_lo = td.k0 / STR_CK, ck_hi = (td.k0 + td.nn - 1) / STR_CK;
       for (uint32_t ck = ck_lo + lane; ck <= ck_hi; ck += 64) {
-        uint64_t q = strck[c.pg.strck_begin + ck];
+        uint64_t q = c.cs.fd.strck[c.pg.strck_begin + ck];
         for (uint32_t j = 0; j < STR_CK; ++j) {
           const uint32_t k = ck * STR_CK + j;
           if (k >= td.k0 + td.nn) break;
@@ -2133,14 +2170,14 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
       return;
     }
     if (SLOTS) {  // entry e's length and chars in slot e
-      sbase = gptr(ws + sl.ws_slots);
+      sbase = gptr(sl.slots);
       soff = 0;
     } else {
       sbase = (glb_u8*)sl.body;
       soff = sl.body_off;
-      pairs = reinterpret_cast<glb_u64*>(gptr(ws + sl.ws_entries));
+      pairs = reinterpret_cast<glb_u64*>(gptr(sl.entries));
     }
-    const uint32_t e = decode_indices(c, ckx, sl.n, lane, u);
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane((int)decode_indices(c, ckx, sl.n, lane, u));
     if (e) {
       if (lane == 0) set_err(err, e, td.page);
       return;
@@ -2148,8 +2185,9 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   }
   wave_sync();
 
-  const uint64_t base = tpfx[c.t] - tpfx[c.cs.tile_begin];
-  const uint64_t tend = tpfx[c.t + 1] - tpfx[c.cs.tile_begin];
+  const uint64_t* tpfx = c.cs.fd.tpfx;
+  const uint64_t base = sload(tpfx + c.t) - sload(tpfx + c.cs.tile_begin);
+  const uint64_t tend = sload(tpfx + c.t + 1) - sload(tpfx + c.cs.tile_begin);
   if (tend - base >= 0xffffffffull) {
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, td.page);
     return;
@@ -2194,11 +2232,11 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     for (int g = 0; g < NGROUPS; ++g) sp[g] = td.nn ? u[pad(kk[g])] * SLOT_BYTES : 0u;
     wave_sync();
     typedef __attribute__((address_space(3))) u32x4 lds_v4u;
-    lds_v4u* zb = (lds_v4u*)&s_buf[wave][0];
+    lds_v4u* zb = (lds_v4u*)wl;
     if (fits)
       for (uint32_t i = lane; i < BUFW / 4; i += 64) zb[i] = u32x4{0u, 0u, 0u, 0u};
     wave_sync();
-    lds_u8* cb8 = (lds_u8*)&s_buf[wave][0] + HEAD;
+    lds_u8* cb8 = (lds_u8*)wl + HEAD;
     lds_v4u* cbv = reinterpret_cast<lds_v4u*>(cb8);
     gout_u8* tile_chars = chars + base;
     uint32_t lo = (uint32_t)((uintptr_t)tile_chars & 15);  // LDS byte of tile char bstart
@@ -2255,7 +2293,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     }
     // the slots' lengths and the tile prefix come from the same dictionary
     // entries; a difference is reported, never hidden
-    if (tb != (uint32_t)(tend - base)) {
+    if ((uint32_t)__builtin_amdgcn_readfirstlane((int)tb) != (uint32_t)(tend - base)) {
       if (lane == 0) set_err(err, ERR_STRING, td.page);
       return;
     }
@@ -2330,7 +2368,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
     // the buffer is copied directly.  The buffer reuses the index area, whose
     // every entry was read above.
     wave_sync();
-    lds_u32* cb = (lds_u32*)&s_buf[wave][0];
+    lds_u32* cb = wl;
     lds_u8* cb8 = (lds_u8*)cb;
     uint32_t bstart = 0, bfill = 0;  // the batch holds tile chars [bstart, bstart + bfill)
     uint32_t wc[12], wn[12];          // this group's and the next group's source pieces
@@ -2367,20 +2405,86 @@ __global__ __launch_bounds__(WG) void k_decode_str(const uint8_t* __restrict__ f
   }
 }
 
-template __global__ void k_decode_str<false>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                            const uint32_t*, const Ck*, const DictSlot*, const uint32_t*,
-                                            const uint64_t*, SegTable, uint32_t*);
-template __global__ void k_decode_str<true>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                           const uint32_t*, const Ck*, const DictSlot*, const uint32_t*,
-                                           const uint64_t*, SegTable, uint32_t*);
-template __global__ void k_decode_fixed<0>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                          const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
-template __global__ void k_decode_fixed<FX_DICT>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                                const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
-template __global__ void k_decode_fixed<FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*, const TileDev*,
-                                                const uint32_t*, const Ck*, const DictSlot*, SegTable, uint32_t*);
-template __global__ void k_decode_fixed<FX_DICT | FX_WIDE>(const uint8_t*, uint8_t*, const ColScan*, const PageDev*,
-                                                          const TileDev*, const uint32_t*, const Ck*, const DictSlot*, SegTable,
-                                                          uint32_t*);
+template <bool SLOTS>
+__global__ __launch_bounds__(WG) void k_decode_str(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                                   SegTable seg, uint32_t* __restrict__ err) {
+  __shared__ __align__(16) uint32_t s_buf[NWAVES][StrLds<SLOTS>::BUFW];
+  WaveTile c;
+  if (!wave_tile(seg, cols, ws, c)) return;
+  tile_str<SLOTS>(c, ws, err, (lds_u32*)&s_buf[threadIdx.x >> 6][0]);
+}
+
+// ---------------------------------------------------------------------------
+// k_batch: the decode step of a batched scan (many files, requests and
+// columns) in one persistent launch.  Each wave takes units (a run of tiles
+// of one column with one decoder) from the work queues, its workgroup's home
+// queue first (queue i mod NQUEUE for workgroup i, the XCD it is dispatched
+// to), then the others in turn, and decodes their tiles one after the other
+// with the same tile functions as the one-launch-per-kind form.  REQUIRED
+// columns get their validity words here (the work of k_prep); OPTIONAL
+// columns' shared edge words are left to k_edges, launched after.  Every
+// wave leaves once all NQUEUE queues are drained.
+// ---------------------------------------------------------------------------
+constexpr uint32_t cmax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+constexpr uint32_t BATCH_LDS_WORDS =
+    cmax(cmax((uint32_t)PADN, DELTA_LDS_WORDS), cmax(StrLds<true>::BUFW, StrLds<false>::BUFW));
+
+// Validity words of a REQUIRED column whose first row lies in tile c: ones
+// for rows below the column's rows, zeros past them (lane j: word j).
+__device__ __forceinline__ void tile_required_validity(const WaveTile& c, uint32_t lane) {
+  if (c.cs.optional || !c.cs.validity) return;
+  const int64_t r0 = c.out0;
+  const int64_t W = ((r0 + 31) >> 5) + (int64_t)lane;
+  if (lane < 33 && W * 32 < r0 + (int64_t)c.nrows) {
+    const int64_t left = c.cs.rows - W * 32;
+    reinterpret_cast<uint32_t*>(c.cs.validity)[W] = left >= 32 ? 0xffffffffu : ((1u << left) - 1);
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_batch(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
+                                              const BUnit* __restrict__ units, const uint32_t* __restrict__ qbeg,
+                                              uint32_t* __restrict__ qhead, uint32_t* __restrict__ err) {
+  __shared__ __align__(16) uint32_t s_lds[NWAVES][BATCH_LDS_WORDS];
+  lds_u32* wl = (lds_u32*)&s_lds[threadIdx.x >> 6][0];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t home = blockIdx.x % (uint32_t)NQUEUE;
+#pragma unroll 1
+  for (uint32_t k = 0; k < (uint32_t)NQUEUE; ++k) {
+    const uint32_t q = (home + k) % (uint32_t)NQUEUE;
+    const uint32_t qb = sload(qbeg + q), qe = sload(qbeg + q + 1);
+    if (qb >= qe) continue;
+#pragma unroll 1
+    for (;;) {
+      uint32_t u = 0;
+      if (lane == 0) u = atomicAdd(qhead + q, 1u);
+      u = qb + (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
+      if (u >= qe) break;
+      const BUnit bu = sload(units + u);
+#pragma unroll 1
+      for (uint32_t t = bu.t0; t < bu.t1; ++t) {
+        WaveTile c;
+        load_tile(cols, bu.cs, t, ws, c);
+        wave_sync();  // the previous tile's LDS reads come first
+        switch (bu.kind) {
+          case TK_FIXED0: tile_fixed<0>(c, ws, err, wl); break;
+          case TK_FIXED1: tile_fixed<FX_DICT>(c, ws, err, wl); break;
+          case TK_FIXED2: tile_fixed<FX_WIDE>(c, ws, err, wl); break;
+          case TK_FIXED3: tile_fixed<FX_DICT | FX_WIDE>(c, ws, err, wl); break;
+          case TK_DELTA: tile_delta(c, ws, err, wl); break;
+          case TK_STR: tile_str<false>(c, ws, err, wl); break;
+          default: tile_str<true>(c, ws, err, wl); break;
+        }
+        tile_required_validity(c, lane);
+      }
+    }
+  }
+}
+
+template __global__ void k_decode_str<false>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_str<true>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<0>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_DICT>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_WIDE>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_DICT | FX_WIDE>(uint8_t*, const ColScan*, SegTable, uint32_t*);
 
 }  // namespace pqk

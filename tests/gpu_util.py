@@ -1,10 +1,18 @@
 """Helpers shared by the GPU tests: run the HIP scan through the C ABI and
-compare every output buffer with the CPU oracle, byte for byte."""
+compare every output buffer with the CPU oracle, byte for byte.
+
+Every output buffer is pre-filled with 0xAB and followed by a 4 KiB guard
+region of 0xAB, so a byte the scan should write and does not (a skipped
+validity word, a null slot, an offset) differs from the oracle, and a byte
+written past a buffer shows up in its guard."""
 import sys
 
 import numpy as np
 
 import oracle
+
+POISON = 0xAB
+GUARD = 4096
 
 
 def gpu_scan(data, columns=None, rg_begin=0, rg_end=None):
@@ -13,8 +21,16 @@ def gpu_scan(data, columns=None, rg_begin=0, rg_end=None):
     f = pqs.DeviceFile(buf, n)
     if columns is None:
         columns = list(range(f.num_columns))
-    out = f.scan(columns, rg_begin, rg_end)
+    out = f.scan(columns, rg_begin, rg_end, poison=POISON, guard=GUARD)
     return f, out
+
+
+def check_guards(g, name=""):
+    for k, gd in enumerate(g.get("guards", [])):
+        a = gd.cpu().numpy()
+        if not (a == 0xAB).all():
+            bad = np.nonzero(a != 0xAB)[0]
+            raise AssertionError(f"{name}: guard region {k} written at bytes {bad[:10]} (of {bad.size})")
 
 
 def compare_column(o, g, name=""):
@@ -26,6 +42,14 @@ def compare_column(o, g, name=""):
     if not (gv == o["validity"]).all():
         bad = np.nonzero(gv != o["validity"])[0]
         raise AssertionError(f"{name}: validity differs at bytes {bad[:10]} (of {bad.size})")
+    if "validity_words" in g:
+        # the whole 32-bit words the library writes: bits past `rows` are 0
+        words = g["validity_words"].cpu().numpy()
+        exp = np.zeros(words.size, dtype=np.uint8)
+        exp[: o["validity"].size] = o["validity"]
+        if not (words == exp).all():
+            bad = np.nonzero(words != exp)[0]
+            raise AssertionError(f"{name}: validity word tail differs at bytes {bad[:10]} (of {bad.size})")
     if "offsets" in o:
         goff = g["offsets"].cpu().numpy()
         if not (goff == o["offsets"]).all():
@@ -45,6 +69,7 @@ def compare_column(o, g, name=""):
             bad = np.nonzero((gvals != ov).reshape(-1, w).any(axis=1))[0]
             raise AssertionError(f"{name}: values differ at rows {bad[:10]} (of {bad.size}): "
                                  f"gpu {g['values'].cpu().numpy()[bad[:5]]} oracle {o['values'][bad[:5]]}")
+    check_guards(g, name)
 
 
 def check_file(data, columns=None, rg_begin=0, rg_end=None, label=""):

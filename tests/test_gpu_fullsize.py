@@ -15,7 +15,7 @@ import pytest
 
 import datagen as dg
 import oracle
-from tests.gpu_util import compare_column
+from tests.gpu_util import GUARD, POISON, compare_column
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def _full_parity(spec, label):
     buf, n = pqs.to_device(data)
     f = pqs.DeviceFile(buf, n)
     cols = list(range(f.num_columns))
-    out = f.scan(cols)
+    out = f.scan(cols, poison=POISON, guard=GUARD)
     of = oracle.File(data)
     with ThreadPoolExecutor(max_workers=8) as ex:
         for c, o in zip(cols, ex.map(of.read, cols)):

@@ -215,7 +215,7 @@ def test_chars_capacity_reported_and_respected():
         print(f"[gpu] capacity col{c}: need {need}, capacity {cap}", flush=True)
         f.scan_into(mask, 0, rg_end, outs, ws)
         with pytest.raises(pqs.PqError) as e:
-            f.check()
+            f.check(ws)
         assert e.value.code == pqs.PQ_ECAPACITY, (c, e.value.code)
         assert bool((guard[cap:] == 0xAB).all()), f"col{c}: bytes written past chars_capacity"
         # the same handle scans correctly afterwards
@@ -229,11 +229,13 @@ def test_workspace_too_small_rejected_before_gpu_work():
     buf, n = pqs.to_device(dg.write(_string_spec()))
     f = pqs.DeviceFile(buf, n)
     mask, rg_end, ws, outs, tens = f.allocate([0, 1, 2])
-    small = torch.empty(max(ws.numel() // 2, 256), dtype=torch.uint8, device="cuda")
+    small = torch.zeros(max(ws.numel() // 2, 256), dtype=torch.uint8, device="cuda")
     with pytest.raises(pqs.PqError) as e:
         f.scan_into(mask, 0, rg_end, outs, small)
     assert e.value.code == pqs.PQ_ECAPACITY
-    f.check()  # nothing was enqueued, so no device error either
+    torch.cuda.synchronize()
+    assert int(small.count_nonzero()) == 0  # nothing was enqueued: the workspace is untouched
+    f.check(small)
 
 
 def test_plan_chars_bytes_match_oracle():

@@ -108,7 +108,23 @@ def _writer_specs():
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, hi=1, str_min=5, str_max=5),
     ], num_rows=20_011, rg_rows=7_000, page_bytes=1000, name="edge")
     tiny_pages = dg.wide_table(5_000, 5_000, 300)
-    return [small, wide, wide_v2, snap, snap_v2, edge, tiny_pages]
+    # DELTA blocks of 512 values in 8 miniblocks and of 1024 in 32, and
+    # dictionary indices stored wider than needed (25 and 32 bits): legal
+    # files the GPU tests also use
+    delta_shapes = []
+    for block, mini in ((512, 8), (1024, 32)):
+        delta_shapes.append(dg.FileSpec(cols=[
+            dg.Col(dg.INT64, dg.DELTA_BINARY_PACKED, True, dg.SORTED, 0.1, lo=0, hi=1 << 40, gap_max=8),
+            dg.Col(dg.INT32, dg.DELTA_BINARY_PACKED, False, dg.UNIFORM, lo=-2**31, hi=2**31),
+        ], num_rows=9_011, rg_rows=4_000, page_bytes=8 * dg.KiB, delta_block=block, delta_mini=mini,
+            name=f"delta{block}_{mini}"))
+    wide_idx = []
+    for w in (25, 32):
+        wide_idx.append(dg.FileSpec(cols=[
+            dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.1, hi=1000),
+            dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.2, hi=300, str_min=8, str_max=44),
+        ], num_rows=12_007, rg_rows=5_000, page_bytes=8 * dg.KiB, index_width=w, name=f"idxw{w}"))
+    return [small, wide, wide_v2, snap, snap_v2, edge, tiny_pages] + delta_shapes + wide_idx
 
 
 @pytest.mark.parametrize("spec", _writer_specs(), ids=lambda s: f"{s.name}-v{s.page_version}-c{s.codec}-p{s.page_bytes}")
