@@ -257,3 +257,45 @@ def wide_table(rows: int = 64_000_000, rg_rows: int = 64_000_000, page_bytes: in
 def snappy_wide_table(rows: int = 64_000_000, rg_rows: int = 64_000_000, page_bytes: int = 1 * MiB,
                       seed: int = 0x5EED0002) -> FileSpec:
     return wide_table(rows, rg_rows, page_bytes, seed, codec=SNAPPY, dict_cap=1 * MiB)
+
+
+def batch_cols(null_prob: float = 0.05) -> List[Col]:
+    """The 8 columns of the many-files workload: INT32 uniform PLAIN, INT32
+    Zipf(1.1) ranks over [1, 2^16] dictionary, INT64 sorted keys DELTA,
+    INT64 10^4-distinct dictionary, 2 x DOUBLE uniform PLAIN, 2 x BYTE_ARRAY
+    dictionary strings (10^2 and 10^4 distinct, length 8..44); every column
+    OPTIONAL with Bernoulli(null_prob) nulls."""
+    p = null_prob
+    return [
+        Col(INT32, PLAIN, True, UNIFORM, p, lo=-(1 << 31), hi=1 << 31),
+        Col(INT32, RLE_DICTIONARY, True, ZIPF, p, hi=1 << 16, zipf_s=1.1),
+        Col(INT64, DELTA_BINARY_PACKED, True, SORTED, p, lo=0, hi=1 << 40, gap_max=8),
+        Col(INT64, RLE_DICTIONARY, True, DICTVALS, p, hi=10_000),
+        Col(DOUBLE, PLAIN, True, UNIFORM, p, dlo=0.0, dhi=1e6),
+        Col(DOUBLE, PLAIN, True, UNIFORM, p, dlo=0.0, dhi=1e6),
+        Col(BYTE_ARRAY, RLE_DICTIONARY, True, STRINGS, p, hi=100, str_min=8, str_max=44),
+        Col(BYTE_ARRAY, RLE_DICTIONARY, True, STRINGS, p, hi=10_000, str_min=8, str_max=44),
+    ]
+
+
+def batch_specs(nfiles: int = 4096, max_rows: int = 4_000_000, min_rows: int = 10_000,
+                rg_rows: int = 1_000_000, page_kib=(8, 16, 32, 64, 128, 256, 512, 1024),
+                seed: int = 0x5EED0003) -> List[FileSpec]:
+    """The many-files workload: file of Zipf rank i (1-based) holds
+    max(min_rows, floor(max_rows * i^-1.1)) rows, the files in a seeded
+    random order; each file's page-size target is drawn uniformly from
+    `page_kib` (a log-uniform choice over 8 KiB .. 1 MiB by default), and a
+    seeded half of the files is Snappy-compressed.  File i's values come from
+    seed + 0x1000 * (i + 1)."""
+    rng = np.random.default_rng(seed)
+    ranks = np.arange(1, nfiles + 1, dtype=np.float64)
+    rows = np.maximum(min_rows, np.floor(max_rows * ranks ** -1.1)).astype(np.int64)
+    rows = rows[rng.permutation(nfiles)]
+    pages = rng.integers(0, len(page_kib), nfiles)
+    snappy = rng.random(nfiles) < 0.5
+    out = []
+    for i in range(nfiles):
+        out.append(FileSpec(cols=batch_cols(), num_rows=int(rows[i]), rg_rows=rg_rows,
+                            page_bytes=int(page_kib[pages[i]]) * KiB, codec=SNAPPY if snappy[i] else UNCOMPRESSED,
+                            seed=(seed + 0x1000 * (i + 1)) & 0xFFFFFFFFFFFFFFFF, name=f"batch{i}"))
+    return out

@@ -190,7 +190,8 @@ pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
 /* Synchronises `stream` and returns (then clears) the error word of the
    scan that last used `workspace` (Sec. 2: the decode kernels of that
    scan): PQ_OK, or PQ_ECORRUPT / PQ_EUNSUPPORTED / PQ_ECAPACITY found by a
-   kernel.  Scans on other workspaces are not affected. */
+   kernel.  Scans on other workspaces are not affected.  `f` may be NULL
+   (a batch over several files). */
 pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream);
 
 /* Encoded bytes of column `col` over all row groups (Sec. 3: the encoded
@@ -207,7 +208,8 @@ pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask);
 
 /* Measurement hook (Sec. 3: the effective bandwidth of a scan is the decoded
    bytes over its run time).  While enabled, every kernel pq_scan enqueues on a
-   handle is bracketed by a pair of HIP events on the scan's stream;
+   handle (f NULL: every kernel of a batched scan) is bracketed by a pair of
+   HIP events on the scan's stream;
    pq_profile_read() waits for the recorded events and returns, per kernel
    name, the number of launches and the summed device time since the last
    pq_profile(f, 1).  pq_profile(f, 0) stops recording. */
@@ -218,6 +220,77 @@ typedef struct {
 } pq_kernel_time;
 pq_status pq_profile(pq_file f, int32_t enable);
 pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n);
+
+/*
+ * Batched scans: several requests, over one or several opened files, in one
+ * set of launches (Sec. 3, Insight 1: a GPU decoder needs many independent
+ * pages in one launch to fill the chip; files with small row groups offer
+ * few pages each).
+ *
+ * One request: columns `col_mask` of row groups [rg_begin, rg_end) of
+ * `file`, into `outs` (one descriptor per set bit, ascending, as for
+ * pq_scan; may be NULL for pq_plan_batch).
+ */
+typedef struct {
+  pq_file file;
+  uint64_t col_mask;
+  int32_t rg_begin, rg_end;
+  const pq_column_out* outs;
+} pq_request;
+
+/* Work classes of the schedule: decoder kind (7: PLAIN / dictionary 4- and
+   8-byte values, DELTA_BINARY_PACKED, strings, strings of slot
+   dictionaries) x dictionary-index width (2: up to 12 bits, wider) x page
+   size (3: one tile, 2-16 tiles, more). */
+#define PQ_TUNE_CLASSES 42
+#define PQ_FORM_BATCHED 0  /* one persistent decode launch over a work queue */
+#define PQ_FORM_PER_PAGE 1 /* one launch per page and decoder (the plain form) */
+typedef struct {
+  int32_t form;          /* PQ_FORM_BATCHED or PQ_FORM_PER_PAGE */
+  int32_t waves_per_cu;  /* persistent grid: waves per compute unit, 1..16 (0: 8) */
+  int32_t queues;        /* 8: one work queue per XCD, column chunks spread over them by
+                            cost (longest first); 1: one shared queue in request order
+                            (0: 8) */
+  int32_t pad_;
+  uint8_t tiles_per_unit[PQ_TUNE_CLASSES]; /* tiles a wave takes per queue grab, per
+                                              class, 1..64 (0: 2) */
+  uint8_t pad2_[6];
+} pq_tuning;
+
+/* The default schedule (every field at its default). */
+pq_status pq_tuning_default(pq_tuning* out);
+
+/* Sizes a batch (Sec. 2: each request reads the selected column chunks of
+   its row groups): the workspace bytes and, for every selected column of
+   every request in order (request 0's columns ascending, then request 1's,
+   ...), its exact chars bytes (0 for fixed-width columns) in chars_bytes
+   (capacity n_chars entries; PQ_EINVAL if it is smaller).  Host-only. */
+pq_status pq_plan_batch(const pq_request* reqs, int32_t n, uint64_t* workspace_bytes, int64_t* chars_bytes,
+                        int32_t n_chars);
+
+/* Enqueues a batch on `stream` (Sec. 2: decompression, then decoding, as GPU
+   kernels; Sec. 3, Insight 1: the pages of every request form one grid of
+   work).  With PQ_FORM_BATCHED: Snappy decompression of every compressed
+   data page (one launch for the page-sequential decoder, one for the
+   block-parallel one), the string totals, one persistent decode launch
+   whose waves take work units from the queues, and the shared validity
+   words of OPTIONAL columns.  With PQ_FORM_PER_PAGE the same work is one
+   launch per page instead.  `tuning` NULL = the default schedule.  Errors
+   as for pq_scan; pq_scan_check(NULL, workspace, stream) reports device
+   errors.  Requests must not write overlapping outputs. */
+pq_status pq_scan_batch(const pq_request* reqs, int32_t n, const pq_tuning* tuning, void* workspace,
+                        uint64_t workspace_bytes, pq_stream stream);
+
+/* Autotuner of the batched form's schedule (Sec. 3, Insight 1: the page to
+   grid mapping decides how well a decode launch fills the GPU).  Runs the
+   batch with candidate schedules on `stream` -- coordinate descent over the
+   queue layout, the waves per CU, and the tiles per unit of every work class
+   present, largest classes first -- timing each candidate as the median of
+   `reps` runs between HIP events, and returns the fastest in *best with its
+   time (and the default schedule's) in milliseconds.  Synchronises the
+   stream; the outputs hold the batch's result afterwards. */
+pq_status pq_autotune_batch(const pq_request* reqs, int32_t n, void* workspace, uint64_t workspace_bytes,
+                            pq_stream stream, int32_t reps, pq_tuning* best, double* best_ms, double* default_ms);
 
 /* Frees the handle's host and device memory (not dev_buf).  Sec. 2: the
    handle is the reader's state for one file. */

@@ -20,7 +20,10 @@ _WIDTH = {INT32: 4, INT64: 8, DOUBLE: 8}
 
 EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get", "pq_row_group_rows",
            "pq_file_stats_get", "pq_column_bytes", "pq_column_encodings", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
-           "pq_profile_read", "pq_close", "pq_last_error")
+           "pq_profile_read", "pq_close", "pq_last_error", "pq_tuning_default", "pq_plan_batch", "pq_scan_batch",
+           "pq_autotune_batch")
+FORM_BATCHED, FORM_PER_PAGE = 0, 1
+TUNE_CLASSES = 42
 
 
 class PqError(RuntimeError):
@@ -53,6 +56,29 @@ class FileStats(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("file", ctypes.c_void_p), ("col_mask", ctypes.c_uint64), ("rg_begin", ctypes.c_int32),
+                ("rg_end", ctypes.c_int32), ("outs", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("queues", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("tiles_per_unit", ctypes.c_uint8 * TUNE_CLASSES),
+                ("pad2_", ctypes.c_uint8 * 6)]
+
+    def to_dict(self):
+        return {"form": self.form, "waves_per_cu": self.waves_per_cu, "queues": self.queues,
+                "tiles_per_unit": list(self.tiles_per_unit)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = tuning_default()
+        t.form, t.waves_per_cu, t.queues = d["form"], d["waves_per_cu"], d["queues"]
+        for i, v in enumerate(d["tiles_per_unit"]):
+            t.tiles_per_unit[i] = v
+        return t
+
+
 _lib = None
 
 
@@ -78,12 +104,18 @@ def lib() -> ctypes.CDLL:
         L.pq_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
         L.pq_scan.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp]
         L.pq_scan_check.argtypes = [vp, vp, vp]
+        L.pq_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
+        L.pq_plan_batch.argtypes = [ctypes.POINTER(Request), i32, ctypes.POINTER(u64), ctypes.POINTER(i64), i32]
+        L.pq_scan_batch.argtypes = [ctypes.POINTER(Request), i32, ctypes.POINTER(Tuning), vp, u64, vp]
+        L.pq_autotune_batch.argtypes = [ctypes.POINTER(Request), i32, vp, u64, vp, i32, ctypes.POINTER(Tuning),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.pq_close.argtypes = [vp]
         L.pq_close.restype = None
         L.pq_last_error.restype = ctypes.c_char_p
         for name in ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get",
                      "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check",
-                     "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read"):
+                     "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read",
+                     "pq_tuning_default", "pq_plan_batch", "pq_scan_batch", "pq_autotune_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -284,3 +316,121 @@ class DeviceFile:
             d["guards"] = guards
             res[c] = d
         return res
+
+
+# ---------------------------------------------------------------------------
+# batched scans
+# ---------------------------------------------------------------------------
+
+def tuning_default() -> Tuning:
+    t = Tuning()
+    _check(lib().pq_tuning_default(ctypes.byref(t)))
+    return t
+
+
+def batch_profile(enable: bool):
+    """Per-kernel HIP-event timing of batched scans (pq_profile(NULL, ..))."""
+    _check(lib().pq_profile(None, 1 if enable else 0))
+
+
+def batch_profile_read() -> Dict[str, tuple]:
+    arr = (KernelTime * 16)()
+    n = ctypes.c_int32()
+    _check(lib().pq_profile_read(None, arr, 16, ctypes.byref(n)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 16))}
+
+
+class Batch:
+    """Several scan requests (file, columns, row-group range), over one or
+    more DeviceFiles, planned and scanned together through pq_scan_batch.
+    `requests`: [(DeviceFile, columns, rg_begin, rg_end or None)]."""
+
+    def __init__(self, requests, poison: Optional[int] = None, guard: int = 0):
+        import torch
+        self.requests = []
+        self._keep = []
+        for f, cols, rb, re_ in requests:
+            if re_ is None:
+                re_ = f.num_row_groups
+            mask = 0
+            for c in cols:
+                mask |= 1 << c
+            self.requests.append((f, sorted(cols), rb, re_, mask))
+        n = len(self.requests)
+        self._reqs = (Request * max(n, 1))()
+        for i, (f, cols, rb, re_, mask) in enumerate(self.requests):
+            self._reqs[i].file = f._h.value
+            self._reqs[i].col_mask = mask
+            self._reqs[i].rg_begin = rb
+            self._reqs[i].rg_end = re_
+        ncols = sum(len(r[1]) for r in self.requests)
+        ws = ctypes.c_uint64()
+        chars = (ctypes.c_int64 * max(ncols, 1))()
+        _check(lib().pq_plan_batch(self._reqs, n, ctypes.byref(ws), chars, ncols))
+        self.workspace = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device="cuda")
+        self.outputs = []  # per request {col: tensors}
+        self._outs = []
+        self.decoded_bytes = 0
+        k = 0
+
+        def buf(nbytes):
+            t = torch.empty(nbytes + guard, dtype=torch.uint8, device="cuda")
+            if poison is not None:
+                t.fill_(poison)
+            if guard:
+                t[nbytes:].fill_(0xAB)
+            return t
+
+        for i, (f, cols, rb, re_, mask) in enumerate(self.requests):
+            rows = sum(f.row_group_rows(g) for g in range(rb, re_))
+            arr = (ColumnOut * max(len(cols), 1))()
+            res = {}
+            for j, c in enumerate(cols):
+                ci = f.column_info(c)
+                vbytes = max(validity_bytes(rows), 4)
+                vb = buf(vbytes)
+                o = arr[j]
+                o.validity = vb.data_ptr()
+                d = {"rows": rows, "validity": vb[: (rows + 7) // 8], "validity_words": vb[: validity_bytes(rows)],
+                     "guards": [vb[vbytes:]]}
+                self.decoded_bytes += (rows + 7) // 8
+                if ci.type == BYTE_ARRAY:
+                    ob = buf(8 * (rows + 1))
+                    nch = int(chars[k])
+                    ch = buf(max(nch, 1))
+                    o.offsets, o.chars, o.chars_capacity = ob.data_ptr(), ch.data_ptr(), nch
+                    d.update(offsets=ob[: 8 * (rows + 1)].view(torch.int64), chars=ch[:nch])
+                    d["guards"] += [ob[8 * (rows + 1):], ch[max(nch, 1):]]
+                    self.decoded_bytes += 8 * (rows + 1) + nch
+                else:
+                    dt = {INT32: torch.int32, INT64: torch.int64, DOUBLE: torch.float64}[ci.type]
+                    w = _WIDTH[ci.type]
+                    vals = buf(max(rows, 1) * w)
+                    o.values = vals.data_ptr()
+                    d["values"] = vals[: max(rows, 1) * w].view(dt)[:rows]
+                    d["guards"].append(vals[max(rows, 1) * w:])
+                    self.decoded_bytes += rows * w
+                res[c] = d
+                k += 1
+            self._outs.append(arr)
+            self._reqs[i].outs = ctypes.cast(arr, ctypes.c_void_p).value
+            self.outputs.append(res)
+
+    def scan(self, tuning: Optional[Tuning] = None, stream=None):
+        """Enqueues the batch (no synchronisation)."""
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        _check(lib().pq_scan_batch(self._reqs, len(self.requests), tp, ctypes.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+
+    def check(self, stream=None):
+        _check(lib().pq_scan_check(None, ctypes.c_void_p(self.workspace.data_ptr()),
+                                   ctypes.c_void_p(_stream_ptr(stream))))
+
+    def autotune(self, reps: int = 3, stream=None):
+        """Runs the library's autotuner; returns (best Tuning, best ms, default ms)."""
+        best = Tuning()
+        bms, dms = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pq_autotune_batch(self._reqs, len(self.requests), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), ctypes.c_void_p(_stream_ptr(stream)), reps,
+                                       ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms)))
+        return best, bms.value, dms.value

@@ -34,6 +34,8 @@ __global__ void k_decode_fixed(uint8_t* ws, const ColScan* cols, SegTable seg, u
 __global__ void k_decode_delta(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
 template <bool SLOTS>
 __global__ void k_decode_str(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
+__global__ void k_batch(uint8_t* ws, const ColScan* cols, const BUnit* units, const uint32_t* qbeg, uint32_t* qhead,
+                        uint32_t* err);
 }  // namespace pqk
 
 using namespace pqk;
@@ -241,7 +243,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 13;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -291,11 +293,11 @@ struct pq_file_s {
 // 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
 // of slot dictionaries, k_decode_str<false> the others.
 enum { KP_SNAPPY, KP_DICT, KP_STR_TOTAL, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA, KP_EDGES,
-       KP_STR_SLOTS, KP_SNAPPY_BLK };
+       KP_STR_SLOTS, KP_SNAPPY_BLK, KP_BATCH };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_str_total", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
                                           "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
-                                          "k_decode_str<true>", "k_snappy_blk"};
+                                          "k_decode_str<true>", "k_snappy_blk", "k_batch"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -863,6 +865,64 @@ struct Plan {
 // [rg_b, rg_e).  With `index`, the plan of the open-time prefix pass instead:
 // decompression and k_prepass of the columns that need a tile prefix, with a
 // per-tile array in the workspace.
+// One selected column of a scan: its table entry (workspace offsets from
+// `off` on) and which decoders its pages need.
+struct ColSetup {
+  ColScan cs;
+  bool has_delta = false, has_plain = false, has_dict = false, has_slots = false;
+  uint32_t nt = 0;        // tiles
+  uint64_t sbytes = 0;    // decompressed bytes of its compressed pages
+  uint32_t b0 = 0, b1 = 0;  // its Snappy blocks
+};
+
+void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint64_t& off, bool index, ColSetup& k) {
+  ColScan& cs = k.cs;
+  memset(&cs, 0, sizeof(cs));
+  cs.fd = f->fd;
+  cs.type = f->cols[c].type;
+  cs.optional = f->cols[c].optional;
+  cs.width = cs.type == T_INT32 ? 4 : (cs.type == T_BYTE_ARRAY ? 0 : 8);
+  cs.col = c;
+  const uint32_t q0 = (uint32_t)(c * f->nrg + rg_b), q1 = (uint32_t)(c * f->nrg + rg_e);
+  cs.tile_begin = f->chunk_tile0[q0];
+  cs.tile_end = f->chunk_tile0[q1];
+  cs.page_begin = f->chunk_page0[q0];
+  cs.page_end = f->chunk_page0[q1];
+  cs.row_base = f->rg_row0[rg_b];
+  cs.rows = rows;
+  cs.scratch_base = f->scratch_prefix[cs.page_begin];
+  k.sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
+  cs.ws_scratch = off;
+  off = align_up(off + k.sbytes, 256);
+  for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
+    if (f->pages[p].kind == PAGE_DICT) continue;
+    const int e = f->pages[p].encoding;
+    if (e == E_DELTA) {
+      k.has_delta = true;
+    } else if (e == E_PLAIN_DICT || e == E_RLE_DICT) {
+      if (cs.type == T_BYTE_ARRAY && (f->dicts[f->pages[p].chunk].flags & DICT_SLOTS))
+        k.has_slots = true;
+      else
+        k.has_dict = true;
+    } else {
+      k.has_plain = true;  // PLAIN, or an encoding the kernel reports as unsupported
+    }
+  }
+  k.nt = cs.tile_end - cs.tile_begin;
+  if (cs.optional && k.nt) {
+    cs.ws_edge = off;
+    off = align_up(off + 8ull * k.nt, 256);
+  }
+  if (index && (cs.type == T_BYTE_ARRAY || k.has_delta)) {
+    cs.ws_tile_aux = off;
+    off = align_up(off + 8ull * (k.nt + 1), 256);
+  }
+  if (k.sbytes) {
+    k.b0 = f->pages[cs.page_begin].sblk_begin;
+    k.b1 = cs.page_end < (uint32_t)f->pages.size() ? f->pages[cs.page_end].sblk_begin : (uint32_t)f->total_sblk;
+  }
+}
+
 pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P, bool index = false) {
   if (rg_b < 0 || rg_e > f->nrg || rg_b > rg_e) return fail(PQ_EINVAL, "bad row-group range [%d, %d)", rg_b, rg_e);
   if (f->ncols < 64 && (mask >> f->ncols)) return fail(PQ_EINVAL, "column mask selects missing columns");
@@ -874,68 +934,30 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
   off = align_up(off + sizeof(int32_t) * 64, 256);
   for (int c = 0; c < f->ncols; ++c) {
     if (!((mask >> c) & 1)) continue;
-    ColScan cs;
-    memset(&cs, 0, sizeof(cs));
-    cs.fd = f->fd;
-    cs.type = f->cols[c].type;
-    cs.optional = f->cols[c].optional;
-    cs.width = cs.type == T_INT32 ? 4 : (cs.type == T_BYTE_ARRAY ? 0 : 8);
-    cs.col = c;
-    const uint32_t q0 = (uint32_t)(c * f->nrg + rg_b), q1 = (uint32_t)(c * f->nrg + rg_e);
-    cs.tile_begin = f->chunk_tile0[q0];
-    cs.tile_end = f->chunk_tile0[q1];
-    cs.page_begin = f->chunk_page0[q0];
-    cs.page_end = f->chunk_page0[q1];
-    cs.row_base = f->rg_row0[rg_b];
-    cs.rows = P.rows;
-    cs.scratch_base = f->scratch_prefix[cs.page_begin];
-    const uint64_t sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
-    cs.ws_scratch = off;
-    off = align_up(off + sbytes, 256);
-    bool has_delta = false, has_plain = false, has_dict = false, has_slots = false;
-    for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
-      if (f->pages[p].kind == PAGE_DICT) continue;
-      const int e = f->pages[p].encoding;
-      if (e == E_DELTA) {
-        has_delta = true;
-      } else if (e == E_PLAIN_DICT || e == E_RLE_DICT) {
-        if (cs.type == T_BYTE_ARRAY && (f->dicts[f->pages[p].chunk].flags & DICT_SLOTS))
-          has_slots = true;
-        else
-          has_dict = true;
-      } else {
-        has_plain = true;  // PLAIN, or an encoding the kernel reports as unsupported
-      }
-    }
-    const uint32_t nt = cs.tile_end - cs.tile_begin;
-    if (cs.optional && nt) {
-      cs.ws_edge = off;
-      off = align_up(off + 8ull * nt, 256);
-    }
+    ColSetup k;
+    col_setup(f, c, rg_b, rg_e, P.rows, off, index, k);
+    const ColScan& cs = k.cs;
+    const uint32_t nt = k.nt;
     const uint32_t idx = (uint32_t)P.cols.size();
-    if (index && (cs.type == T_BYTE_ARRAY || has_delta)) {
-      cs.ws_tile_aux = off;
-      off = align_up(off + 8ull * (nt + 1), 256);
-      if (nt) {
-        P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
-        P.pre_units += nt;
-      }
+    if (index && cs.ws_tile_aux && nt) {
+      P.pre_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.pre_units});
+      P.pre_units += nt;
     }
     if (nt) {
       if (cs.type == T_BYTE_ARRAY) {
-        for (int k = 0; k < 2; ++k) {  // k_decode_str<k>: tiles of slot dictionaries (1) or the others (0)
-          if (!(k ? has_slots : (has_plain || has_dict || has_delta))) continue;
-          P.str_segs[k].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units[k]});
-          P.str_units[k] += nt;
+        for (int kk = 0; kk < 2; ++kk) {  // k_decode_str<kk>: tiles of slot dictionaries (1) or the others (0)
+          if (!(kk ? k.has_slots : (k.has_plain || k.has_dict || k.has_delta))) continue;
+          P.str_segs[kk].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.str_units[kk]});
+          P.str_units[kk] += nt;
         }
       } else {
-        if (has_delta) {
+        if (k.has_delta) {
           P.delta_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.delta_units});
           P.delta_units += nt;
         }
         const int wide = cs.width == 8 ? FX_WIDE : 0;
         for (int kind = 0; kind < 2; ++kind) {
-          if (!(kind ? has_dict : has_plain)) continue;
+          if (!(kind ? k.has_dict : k.has_plain)) continue;
           const int K = kind | wide;
           P.fixed_segs[K].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_units[K]});
           P.fixed_units[K] += nt;
@@ -950,14 +972,12 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
       }
     }
     if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
-    if (sbytes) {
+    if (k.sbytes) {
       P.snappy_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.snappy_waves});
       P.snappy_waves += cs.page_end - cs.page_begin;
-      const uint32_t b0 = f->pages[cs.page_begin].sblk_begin;
-      const uint32_t b1 = cs.page_end < (uint32_t)f->pages.size() ? f->pages[cs.page_end].sblk_begin : (uint32_t)f->total_sblk;
-      if (b1 > b0) {
-        P.sblk_segs.push_back(Segment{idx, b0, b1, P.sblk_lanes});
-        P.sblk_lanes += b1 - b0;
+      if (k.b1 > k.b0) {
+        P.sblk_segs.push_back(Segment{idx, k.b0, k.b1, P.sblk_lanes});
+        P.sblk_lanes += k.b1 - k.b0;
       }
     }
     P.cols.push_back(cs);
@@ -1180,9 +1200,499 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
 }
 
 extern "C" pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream) {
-  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  (void)f;
   if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
   return read_err_word(reinterpret_cast<uint32_t*>(const_cast<void*>(workspace)), (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// batched scans
+// ---------------------------------------------------------------------------
+// The measurement recorder of batched scans (pq_profile(NULL, ...)).
+static pq_file_s g_batch_prof;
+
+namespace {
+
+constexpr int NWCLASS = 2, NPCLASS = 3;
+static_assert((int)TK_KINDS * NWCLASS * NPCLASS == PQ_TUNE_CLASSES, "work classes");
+constexpr uint32_t DEFAULT_TPU = 2, DEFAULT_WPC = 8;
+constexpr uint32_t NUM_CUS = 256;  // MI355X compute units (8 XCDs x 32)
+// relative cost of one tile per decoder kind (roughly the bytes it moves),
+// used only to balance the queues
+constexpr uint64_t KIND_COST[TK_KINDS] = {8, 7, 16, 11, 9, 40, 40};
+
+// The decoder kind of a data page's tiles.
+uint32_t tile_kind(pq_file f, const PageDev& pg, const ColScan& cs) {
+  const bool dict = pg.encoding == E_PLAIN_DICT || pg.encoding == E_RLE_DICT;
+  if (cs.type == T_BYTE_ARRAY) return dict && (f->dicts[pg.chunk].flags & DICT_SLOTS) ? TK_STRSLOT : TK_STR;
+  if (pg.encoding == E_DELTA) return TK_DELTA;
+  if (pg.encoding != E_PLAIN && !dict) return TK_FIXED1;  // its decoder reports the encoding as unsupported
+  return (dict ? 1u : 0u) | (cs.width == 8 ? 2u : 0u);
+}
+
+uint32_t tune_class(uint32_t kind, const PageDev& pg, uint32_t ntiles) {
+  const bool dict_kind = kind == TK_FIXED1 || kind == TK_FIXED3 || kind == TK_STR || kind == TK_STRSLOT;
+  const uint32_t w = dict_kind && pg.enc_w > 12 ? 1 : 0;
+  const uint32_t pc = ntiles <= 1 ? 0 : (ntiles <= 16 ? 1 : 2);
+  return (kind * NWCLASS + w) * NPCLASS + pc;
+}
+
+struct BatchPlan {
+  std::vector<ColScan> cols;
+  std::vector<int32_t> str_cols;
+  std::vector<int64_t> chars;  // per column, in request order
+  std::vector<Segment> snappy_segs, sblk_segs, edge_segs, prep_segs;
+  uint32_t snappy_waves = 0, sblk_lanes = 0, edge_threads = 0, prep_threads = 0;
+  // same-kind tile runs: consecutive pages of one column with one decoder
+  // and work class
+  struct Run { uint32_t cs, t0, t1, kind, cls, chunk; };
+  std::vector<Run> runs;
+  std::vector<uint32_t> run_file;  // request index of each run (chunk keys are per file)
+  std::vector<Run> page_runs;      // one per data page (the per-page form's launches)
+  struct SnapPage { uint32_t cs, page, b0, b1; };
+  std::vector<SnapPage> snap_pages;  // compressed data pages and their Snappy blocks
+  uint64_t total_tiles = 0;
+  uint64_t ws_cols = 0, ws_which = 0, ws_snappy = 0, ws_sblk = 0, ws_edge = 0, ws_prep = 0, ws_units = 0,
+           ws_qbeg = 0, ws_qhead = 0, ws_hdr_end = 0, ws_total = 0;
+};
+
+pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
+  if (n < 0 || (n > 0 && !reqs)) return fail(PQ_EINVAL, "bad request list");
+  uint64_t ncols = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    if (!reqs[r].file) return fail(PQ_EINVAL, "request %d: NULL file", r);
+    ncols += (uint64_t)__builtin_popcountll(reqs[r].col_mask);
+  }
+  if (ncols >= (1ull << 31)) return fail(PQ_EUNSUPPORTED, "too many columns in one batch");
+  // tiles of the whole batch bound the units the header must hold
+  uint64_t tiles = 0, snappy_segs = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    pq_file f = reqs[r].file;
+    const pq_request& q = reqs[r];
+    if (q.rg_begin < 0 || q.rg_end > f->nrg || q.rg_begin > q.rg_end)
+      return fail(PQ_EINVAL, "request %d: bad row-group range [%d, %d)", r, q.rg_begin, q.rg_end);
+    if (f->ncols < 64 && (q.col_mask >> f->ncols)) return fail(PQ_EINVAL, "request %d: mask selects missing columns", r);
+    for (int c = 0; c < f->ncols; ++c) {
+      if (!((q.col_mask >> c) & 1)) continue;
+      tiles += f->chunk_tile0[(size_t)c * f->nrg + q.rg_end] - f->chunk_tile0[(size_t)c * f->nrg + q.rg_begin];
+      snappy_segs += 1;
+    }
+  }
+  P.total_tiles = tiles;
+  uint64_t off = WS_HEADER;
+  P.ws_cols = off;
+  off = align_up(off + sizeof(ColScan) * (ncols ? ncols : 1), 256);
+  P.ws_which = off;
+  off = align_up(off + sizeof(int32_t) * (ncols ? ncols : 1), 256);
+  P.ws_snappy = off;
+  off = align_up(off + sizeof(Segment) * (snappy_segs ? snappy_segs : 1), 256);
+  P.ws_sblk = off;
+  off = align_up(off + sizeof(Segment) * (snappy_segs ? snappy_segs : 1), 256);
+  P.ws_edge = off;
+  off = align_up(off + sizeof(Segment) * (ncols ? ncols : 1), 256);
+  P.ws_prep = off;
+  off = align_up(off + sizeof(Segment) * (ncols ? ncols : 1), 256);
+  P.ws_units = off;
+  off = align_up(off + sizeof(BUnit) * (tiles ? tiles : 1), 256);
+  P.ws_qbeg = off;
+  off = align_up(off + sizeof(uint32_t) * (NQUEUE + 1), 256);
+  P.ws_qhead = off;
+  off = align_up(off + sizeof(uint32_t) * NQUEUE, 256);
+  P.ws_hdr_end = off;
+  for (int32_t r = 0; r < n; ++r) {
+    pq_file f = reqs[r].file;
+    const pq_request& q = reqs[r];
+    const int64_t rows = f->rg_row0[q.rg_end] - f->rg_row0[q.rg_begin];
+    for (int c = 0; c < f->ncols; ++c) {
+      if (!((q.col_mask >> c) & 1)) continue;
+      ColSetup k;
+      col_setup(f, c, q.rg_begin, q.rg_end, rows, off, false, k);
+      const ColScan& cs = k.cs;
+      const uint32_t idx = (uint32_t)P.cols.size();
+      P.chars.push_back(cs.type == T_BYTE_ARRAY ? (int64_t)(f->tpfx[cs.tile_end] - f->tpfx[cs.tile_begin]) : 0);
+      if (cs.type == T_BYTE_ARRAY) P.str_cols.push_back((int32_t)idx);
+      if (k.sbytes) {
+        P.snappy_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.snappy_waves});
+        P.snappy_waves += cs.page_end - cs.page_begin;
+        if (k.b1 > k.b0) {
+          P.sblk_segs.push_back(Segment{idx, k.b0, k.b1, P.sblk_lanes});
+          P.sblk_lanes += k.b1 - k.b0;
+        }
+      }
+      if (k.nt) {
+        if (cs.optional) {
+          P.edge_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.edge_threads});
+          P.edge_threads += k.nt;
+        } else {
+          P.prep_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.prep_threads});
+          P.prep_threads += k.nt;
+        }
+      }
+      for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
+        const PageDev& pg = f->pages[p];
+        if (pg.kind == PAGE_DICT) continue;
+        if (pg.scratch_len) {
+          const uint32_t nb = (uint32_t)(((uint64_t)pg.scratch_len + SNAP_BLOCK - 1) / SNAP_BLOCK);
+          P.snap_pages.push_back(BatchPlan::SnapPage{idx, p, pg.sblk_begin, pg.sblk_begin + nb});
+        }
+        const uint32_t nt = (uint32_t)(((uint64_t)(pg.num_values > 0 ? pg.num_values : 0) + TILE_ROWS - 1) / TILE_ROWS);
+        if (!nt) continue;
+        const uint32_t kind = tile_kind(f, pg, cs), cls = tune_class(kind, pg, nt);
+        P.page_runs.push_back(BatchPlan::Run{idx, pg.tile_begin, pg.tile_begin + nt, kind, cls, pg.chunk});
+        if (!P.runs.empty()) {
+          BatchPlan::Run& b = P.runs.back();
+          if (b.cs == idx && b.kind == kind && b.cls == cls && b.t1 == pg.tile_begin && b.chunk == pg.chunk) {
+            b.t1 += nt;
+            continue;
+          }
+        }
+        P.runs.push_back(BatchPlan::Run{idx, pg.tile_begin, pg.tile_begin + nt, kind, cls, pg.chunk});
+        P.run_file.push_back((uint32_t)r);
+      }
+      P.cols.push_back(cs);
+    }
+  }
+  P.ws_total = std::max<uint64_t>(off, 256);
+  return PQ_OK;
+}
+
+// Work units and queue bounds of a plan under a schedule.  With one queue
+// per XCD, the chunks (all units of one column chunk) are dealt to the
+// queues longest first, each to the least loaded one, so that a chunk's
+// dictionary is gathered through one XCD's L2; a queue then serves its
+// costliest units first.
+void make_units(const BatchPlan& P, const pq_tuning& T, std::vector<BUnit>& units, uint32_t qbeg[NQUEUE + 1]) {
+  struct U { BUnit u; uint64_t cost; uint64_t key; };
+  std::vector<U> all;
+  all.reserve(P.total_tiles);
+  for (size_t i = 0; i < P.runs.size(); ++i) {
+    const BatchPlan::Run& r = P.runs[i];
+    uint32_t tpu = T.tiles_per_unit[r.cls] ? T.tiles_per_unit[r.cls] : DEFAULT_TPU;
+    tpu = std::min<uint32_t>(std::max<uint32_t>(tpu, 1), 64);
+    for (uint32_t t = r.t0; t < r.t1; t += tpu) {
+      const uint32_t t1 = std::min(r.t1, t + tpu);
+      all.push_back(U{BUnit{r.cs, t, t1, r.kind}, (uint64_t)(t1 - t) * KIND_COST[r.kind],
+                      ((uint64_t)P.run_file[i] << 32) | r.chunk});
+    }
+  }
+  units.clear();
+  const int nq = T.queues == 1 ? 1 : NQUEUE;
+  if (nq == 1) {
+    for (const U& u : all) units.push_back(u.u);
+    qbeg[0] = 0;
+    for (int q = 1; q <= NQUEUE; ++q) qbeg[q] = (uint32_t)units.size();
+    return;
+  }
+  // chunks, longest first, to the least loaded queue
+  std::vector<std::pair<uint64_t, uint64_t>> chunks;  // (key, cost)
+  {
+    std::vector<U> sorted = all;
+    std::stable_sort(sorted.begin(), sorted.end(), [](const U& a, const U& b) { return a.key < b.key; });
+    for (size_t i = 0; i < sorted.size();) {
+      size_t j = i;
+      uint64_t c = 0;
+      while (j < sorted.size() && sorted[j].key == sorted[i].key) c += sorted[j++].cost;
+      chunks.push_back({sorted[i].key, c});
+      i = j;
+    }
+  }
+  std::stable_sort(chunks.begin(), chunks.end(), [](const std::pair<uint64_t, uint64_t>& a, const std::pair<uint64_t, uint64_t>& b) {
+    return a.second > b.second;
+  });
+  std::vector<uint64_t> load(NQUEUE, 0);
+  std::vector<std::pair<uint64_t, int>> qof;  // chunk key -> queue
+  qof.reserve(chunks.size());
+  for (const auto& ch : chunks) {
+    int best = 0;
+    for (int q = 1; q < NQUEUE; ++q)
+      if (load[q] < load[best]) best = q;
+    load[best] += ch.second;
+    qof.push_back({ch.first, best});
+  }
+  std::sort(qof.begin(), qof.end());
+  std::vector<std::vector<U>> per(NQUEUE);
+  for (const U& u : all) {
+    auto it = std::lower_bound(qof.begin(), qof.end(), std::make_pair(u.key, -1));
+    per[it->second].push_back(u);
+  }
+  qbeg[0] = 0;
+  for (int q = 0; q < NQUEUE; ++q) {
+    std::stable_sort(per[q].begin(), per[q].end(), [](const U& a, const U& b) { return a.cost > b.cost; });
+    for (const U& u : per[q]) units.push_back(u.u);
+    qbeg[q + 1] = (uint32_t)units.size();
+  }
+}
+
+SegTable seg_table(const std::vector<Segment>& v, uint8_t* ws, uint64_t ws_off) {
+  SegTable t;
+  memset(&t, 0, sizeof(t));
+  t.n = (int32_t)v.size();
+  if (v.size() <= (size_t)MAX_SEGS) {
+    for (size_t i = 0; i < v.size(); ++i) t.s[i] = v[i];
+  } else {
+    t.ptr = reinterpret_cast<const Segment*>(ws + ws_off);
+  }
+  return t;
+}
+
+pq_status bind_batch_outputs(const pq_request* reqs, int32_t n, BatchPlan& P) {
+  size_t k = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    const int nc = __builtin_popcountll(reqs[r].col_mask);
+    if (nc && !reqs[r].outs) return fail(PQ_EINVAL, "request %d: outs is NULL", r);
+    Plan one;
+    one.rows = P.cols[k].rows;
+    one.cols.assign(P.cols.begin() + (long)k, P.cols.begin() + (long)k + nc);
+    if (nc) {
+      pq_status st = bind_outputs(one, reqs[r].outs, nc);
+      if (st != PQ_OK) return st;
+      std::copy(one.cols.begin(), one.cols.end(), P.cols.begin() + (long)k);
+    }
+    k += (size_t)nc;
+  }
+  return PQ_OK;
+}
+
+pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hipStream_t s) {
+  pq_file prof = &g_batch_prof;
+  uint32_t* err = reinterpret_cast<uint32_t*>(ws);
+  std::vector<BUnit> units;
+  uint32_t qbeg[NQUEUE + 1];
+  const bool per_page = T.form == PQ_FORM_PER_PAGE;
+  if (!per_page) make_units(P, T, units, qbeg);
+  // the header: error word, column table, string columns, segment tables,
+  // units, queue bounds and heads, in one copy
+  std::vector<uint8_t> hdr(P.ws_hdr_end, 0);
+  auto put = [&](uint64_t at, const void* src, size_t n) { if (n) memcpy(hdr.data() + at, src, n); };
+  put(P.ws_cols, P.cols.data(), sizeof(ColScan) * P.cols.size());
+  put(P.ws_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size());
+  put(P.ws_snappy, P.snappy_segs.data(), sizeof(Segment) * P.snappy_segs.size());
+  put(P.ws_sblk, P.sblk_segs.data(), sizeof(Segment) * P.sblk_segs.size());
+  put(P.ws_edge, P.edge_segs.data(), sizeof(Segment) * P.edge_segs.size());
+  put(P.ws_prep, P.prep_segs.data(), sizeof(Segment) * P.prep_segs.size());
+  if (!per_page) {
+    put(P.ws_units, units.data(), sizeof(BUnit) * units.size());
+    put(P.ws_qbeg, qbeg, sizeof(qbeg));
+  }
+  HIP_OR(hipMemcpyAsync(ws, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+  const ColScan* d_cols = reinterpret_cast<const ColScan*>(ws + P.ws_cols);
+  // decompression
+  if (!per_page) {
+    if (P.snappy_waves) {
+      ProfScope ps_(prof, KP_SNAPPY, s);
+      hipLaunchKernelGGL(k_snappy, dim3(P.snappy_waves), dim3(64), 0, s, d_cols, seg_table(P.snappy_segs, ws, P.ws_snappy),
+                         ws, 0, err);
+      HIP_OR(hipGetLastError());
+    }
+    if (P.sblk_lanes) {
+      ProfScope ps_(prof, KP_SNAPPY_BLK, s);
+      hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
+                         d_cols, seg_table(P.sblk_segs, ws, P.ws_sblk), ws, err);
+      HIP_OR(hipGetLastError());
+    }
+  } else {
+    // one launch per compressed page: the page-sequential decoder (which
+    // leaves at once for a page with a block index) and the block decoder
+    for (const BatchPlan::SnapPage& sp : P.snap_pages) {
+      {
+        ProfScope ps_(prof, KP_SNAPPY, s);
+        std::vector<Segment> one{Segment{sp.cs, sp.page, sp.page + 1, 0}};
+        hipLaunchKernelGGL(k_snappy, dim3(1), dim3(64), 0, s, d_cols, make_segs(one), ws, 0, err);
+        HIP_OR(hipGetLastError());
+      }
+      if (sp.b1 > sp.b0) {
+        ProfScope ps_(prof, KP_SNAPPY_BLK, s);
+        std::vector<Segment> one{Segment{sp.cs, sp.b0, sp.b1, 0}};
+        hipLaunchKernelGGL(k_snappy_blk, dim3((sp.b1 - sp.b0 + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
+                           d_cols, make_segs(one), ws, err);
+        HIP_OR(hipGetLastError());
+      }
+    }
+  }
+  if (!P.str_cols.empty()) {
+    ProfScope ps_(prof, KP_STR_TOTAL, s);
+    hipLaunchKernelGGL(k_str_total, dim3(((uint32_t)P.str_cols.size() + 63) / 64), dim3(64), 0, s, d_cols,
+                       reinterpret_cast<const int32_t*>(ws + P.ws_which), (int32_t)P.str_cols.size(), err);
+    HIP_OR(hipGetLastError());
+  }
+  if (!per_page) {
+    if (!units.empty()) {
+      ProfScope ps_(prof, KP_BATCH, s);
+      const uint32_t wpc = T.waves_per_cu > 0 ? (uint32_t)std::min(T.waves_per_cu, 16) : DEFAULT_WPC;
+      const uint32_t wgs = std::max<uint32_t>(1, std::min<uint32_t>(NUM_CUS * wpc / 4, ((uint32_t)units.size() + 3) / 4));
+      hipLaunchKernelGGL(k_batch, dim3(wgs), dim3(256), 0, s, ws, d_cols,
+                         reinterpret_cast<const BUnit*>(ws + P.ws_units), reinterpret_cast<const uint32_t*>(ws + P.ws_qbeg),
+                         reinterpret_cast<uint32_t*>(ws + P.ws_qhead), err);
+      HIP_OR(hipGetLastError());
+    }
+  } else {
+    if (P.prep_threads) {
+      for (const Segment& sg : P.prep_segs) {
+        ProfScope ps_(prof, KP_PREP, s);
+        std::vector<Segment> one{Segment{sg.cs, sg.t0, sg.t1, 0}};
+        hipLaunchKernelGGL(k_prep, dim3((sg.t1 - sg.t0 + 255) / 256), dim3(256), 0, s, d_cols, make_segs(one));
+        HIP_OR(hipGetLastError());
+      }
+    }
+    for (const BatchPlan::Run& r : P.page_runs) {
+      std::vector<Segment> one{Segment{r.cs, r.t0, r.t1, 0}};
+      const uint32_t wg = (r.t1 - r.t0 + 3) / 4;
+      switch (r.kind) {
+        case TK_FIXED0: case TK_FIXED1: case TK_FIXED2: case TK_FIXED3: {
+          ProfScope ps_(prof, KP_FIXED0 + (int)r.kind, s);
+          auto kern = r.kind == 0 ? k_decode_fixed<0> : r.kind == 1 ? k_decode_fixed<1> : r.kind == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
+          hipLaunchKernelGGL(kern, dim3(wg), dim3(256), 0, s, ws, d_cols, make_segs(one), err);
+          break;
+        }
+        case TK_DELTA: {
+          ProfScope ps_(prof, KP_DELTA, s);
+          hipLaunchKernelGGL(k_decode_delta, dim3(wg), dim3(256), 0, s, ws, d_cols, make_segs(one), err);
+          break;
+        }
+        default: {
+          ProfScope ps_(prof, r.kind == TK_STRSLOT ? KP_STR_SLOTS : KP_STR, s);
+          hipLaunchKernelGGL(r.kind == TK_STRSLOT ? k_decode_str<true> : k_decode_str<false>, dim3(wg), dim3(256), 0, s,
+                             ws, d_cols, make_segs(one), err);
+        }
+      }
+      HIP_OR(hipGetLastError());
+    }
+  }
+  if (P.edge_threads) {
+    ProfScope ps_(prof, KP_EDGES, s);
+    hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols,
+                       seg_table(P.edge_segs, ws, P.ws_edge));
+    HIP_OR(hipGetLastError());
+  }
+  return PQ_OK;
+}
+
+}  // namespace
+
+extern "C" pq_status pq_tuning_default(pq_tuning* out) {
+  if (!out) return fail(PQ_EINVAL, "NULL argument");
+  memset(out, 0, sizeof(*out));
+  out->form = PQ_FORM_BATCHED;
+  out->waves_per_cu = (int32_t)DEFAULT_WPC;
+  out->queues = NQUEUE;
+  for (int c = 0; c < PQ_TUNE_CLASSES; ++c) out->tiles_per_unit[c] = (uint8_t)DEFAULT_TPU;
+  return PQ_OK;
+}
+
+extern "C" pq_status pq_plan_batch(const pq_request* reqs, int32_t n, uint64_t* workspace_bytes, int64_t* chars_bytes,
+                                   int32_t n_chars) {
+  if (!workspace_bytes) return fail(PQ_EINVAL, "NULL argument");
+  BatchPlan P;
+  pq_status st = make_batch_plan(reqs, n, P);
+  if (st != PQ_OK) return st;
+  *workspace_bytes = P.ws_total;
+  if (chars_bytes) {
+    if ((size_t)n_chars < P.chars.size()) return fail(PQ_EINVAL, "chars_bytes holds %d entries, the batch has %zu columns", n_chars, P.chars.size());
+    for (size_t k = 0; k < P.chars.size(); ++k) chars_bytes[k] = P.chars[k];
+  }
+  return PQ_OK;
+}
+
+static pq_status scan_batch(const pq_request* reqs, int32_t n, const pq_tuning* tuning, void* workspace,
+                            uint64_t workspace_bytes, hipStream_t s, BatchPlan* cached) {
+  BatchPlan local;
+  BatchPlan& P = cached ? *cached : local;
+  if (!cached) {
+    pq_status st = make_batch_plan(reqs, n, P);
+    if (st != PQ_OK) return st;
+    st = bind_batch_outputs(reqs, n, P);
+    if (st != PQ_OK) return st;
+  }
+  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned (%llu < %llu)",
+                                                (unsigned long long)workspace_bytes, (unsigned long long)P.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
+  pq_tuning T;
+  pq_tuning_default(&T);
+  if (tuning) T = *tuning;
+  if (T.form != PQ_FORM_BATCHED && T.form != PQ_FORM_PER_PAGE) return fail(PQ_EINVAL, "unknown form %d", T.form);
+  return enqueue_batch(P, T, (uint8_t*)workspace, s);
+}
+
+extern "C" pq_status pq_scan_batch(const pq_request* reqs, int32_t n, const pq_tuning* tuning, void* workspace,
+                                   uint64_t workspace_bytes, pq_stream stream) {
+  return scan_batch(reqs, n, tuning, workspace, workspace_bytes, (hipStream_t)stream, nullptr);
+}
+
+extern "C" pq_status pq_autotune_batch(const pq_request* reqs, int32_t n, void* workspace, uint64_t workspace_bytes,
+                                       pq_stream stream, int32_t reps, pq_tuning* best, double* best_ms,
+                                       double* default_ms) {
+  if (!best) return fail(PQ_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  BatchPlan P;
+  pq_status st = make_batch_plan(reqs, n, P);
+  if (st != PQ_OK) return st;
+  st = bind_batch_outputs(reqs, n, P);
+  if (st != PQ_OK) return st;
+  if (reps < 1) reps = 3;
+  hipEvent_t e0, e1;
+  HIP_OR(hipEventCreate(&e0));
+  HIP_OR(hipEventCreate(&e1));
+  auto timed = [&](const pq_tuning& T, double& ms) -> pq_status {
+    std::vector<double> v;
+    for (int r = 0; r < reps; ++r) {
+      HIP_OR(hipEventRecord(e0, s));
+      pq_status st2 = scan_batch(reqs, n, &T, workspace, workspace_bytes, s, &P);
+      if (st2 != PQ_OK) return st2;
+      HIP_OR(hipEventRecord(e1, s));
+      HIP_OR(hipEventSynchronize(e1));
+      float f = 0;
+      HIP_OR(hipEventElapsedTime(&f, e0, e1));
+      v.push_back(f);
+    }
+    std::sort(v.begin(), v.end());
+    ms = v[v.size() / 2];
+    return read_err_word(reinterpret_cast<uint32_t*>(workspace), s);
+  };
+  pq_tuning cur;
+  pq_tuning_default(&cur);
+  double cur_ms = 0;
+  pq_status rs = timed(cur, cur_ms);  // warms the caches and the code too
+  if (rs == PQ_OK) rs = timed(cur, cur_ms);
+  if (rs != PQ_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rs; }
+  if (default_ms) *default_ms = cur_ms;
+  auto consider = [&](const pq_tuning& T) -> pq_status {
+    double ms = 0;
+    pq_status st2 = timed(T, ms);
+    if (st2 != PQ_OK) return st2;
+    if (ms < cur_ms) { cur = T; cur_ms = ms; }
+    return PQ_OK;
+  };
+  // 1. queue layout, 2. waves per CU
+  for (int q : {1}) {
+    pq_tuning T = cur;
+    T.queues = q;
+    if (rs == PQ_OK) rs = consider(T);
+  }
+  for (int w : {4, 12, 16}) {
+    pq_tuning T = cur;
+    T.waves_per_cu = w;
+    if (rs == PQ_OK) rs = consider(T);
+  }
+  // 3. tiles per unit of each class present, the classes with most tiles first
+  std::vector<std::pair<uint64_t, int>> cls(PQ_TUNE_CLASSES);
+  for (int c = 0; c < PQ_TUNE_CLASSES; ++c) cls[c] = {0, c};
+  for (const BatchPlan::Run& r : P.runs) cls[r.cls].first += r.t1 - r.t0;
+  std::stable_sort(cls.begin(), cls.end(), [](const std::pair<uint64_t, int>& a, const std::pair<uint64_t, int>& b) { return a.first > b.first; });
+  for (const auto& c : cls) {
+    if (!c.first) break;
+    for (int tpu : {1, 4, 8, 16}) {
+      pq_tuning T = cur;
+      T.tiles_per_unit[c.second] = (uint8_t)tpu;
+      if (rs == PQ_OK) rs = consider(T);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != PQ_OK) return rs;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return PQ_OK;
 }
 
 extern "C" pq_status pq_column_bytes(pq_file f, int32_t col, uint64_t* data_bytes, uint64_t* dict_bytes) {
@@ -1208,8 +1718,10 @@ extern "C" pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask)
   return PQ_OK;
 }
 
+static pq_file prof_of(pq_file f) { return f ? f : &g_batch_prof; }
+
 extern "C" pq_status pq_profile(pq_file f, int32_t enable) {
-  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  f = prof_of(f);
   for (auto& r : f->recs) { f->event_pool.push_back(r.a); f->event_pool.push_back(r.b); }
   f->recs.clear();
   for (int k = 0; k < NKERN; ++k) { f->prof_ms[k] = 0; f->prof_n[k] = 0; }
@@ -1218,7 +1730,8 @@ extern "C" pq_status pq_profile(pq_file f, int32_t enable) {
 }
 
 extern "C" pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n) {
-  if (!f || !n) return fail(PQ_EINVAL, "NULL argument");
+  f = prof_of(f);
+  if (!n) return fail(PQ_EINVAL, "NULL argument");
   for (auto& r : f->recs) {
     HIP_OR(hipEventSynchronize(r.b));
     float ms = 0;

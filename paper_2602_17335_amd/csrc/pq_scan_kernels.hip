@@ -312,6 +312,17 @@ __device__ __forceinline__ Segment seg_lookup(const SegTable& seg, uint32_t unit
 // lives across the loop a vector register).
 __device__ __forceinline__ bool uniform_bool(bool v) { return __builtin_amdgcn_readfirstlane((int)v) != 0; }
 
+// This lane's thread index, recomputed where it is used: inside the
+// persistent kernel's tile loop the compiler would otherwise compute every
+// per-lane constant of the tile functions (LDS addresses, row numbers) once,
+// before the loop, and hold them all in vector registers for its whole
+// length (twice the registers of the one-tile kernels).
+__device__ __forceinline__ uint32_t lane_id() {
+  uint32_t v = threadIdx.x;
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Tile t of column table entry cs.
 __device__ __forceinline__ void load_tile(const ColScan* cols, uint32_t cs, uint32_t t, uint8_t* ws, WaveTile& c) {
   c.t = t;
@@ -1897,11 +1908,11 @@ __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restric
   constexpr bool is_dict = KIND & FX_DICT;
   constexpr bool w4 = !(KIND & FX_WIDE);
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
-  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id() & 63) >> 2)];
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = lane_id() & 63;
   const bool dict_page = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   if (!dict_page && enc != E_PLAIN) {
     if (is_dict && lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);  // reported once
@@ -2010,10 +2021,9 @@ constexpr uint32_t DHALF = TR / 2;
 constexpr uint32_t DELTA_LDS_WORDS = 2 * (DHALF + DHALF / 16 + 4);
 __device__ __forceinline__ void tile_delta(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
                                            lds_u32* wl) {
-  constexpr uint32_t HALF = DHALF;
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = lane_id() & 63;
   uint32_t vw;
   if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)wl;
@@ -2112,9 +2122,9 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
   constexpr uint32_t BUFW = StrLds<SLOTS>::BUFW;
   constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (threadIdx.x & 63)];
-  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((threadIdx.x & 63) >> 2)];
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id() & 63) >> 2)];
+  const uint32_t lane = lane_id() & 63;
   const int enc = c.pg.encoding;
   const bool is_plain = !SLOTS && enc == E_PLAIN;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
@@ -2462,8 +2472,12 @@ __global__ __launch_bounds__(WG) void k_batch(uint8_t* __restrict__ ws, const Co
       const BUnit bu = sload(units + u);
 #pragma unroll 1
       for (uint32_t t = bu.t0; t < bu.t1; ++t) {
+        // the column's table is read again for every tile, not held in
+        // registers across the loop
+        uint32_t csi = bu.cs;
+        asm volatile("" : "+s"(csi));
         WaveTile c;
-        load_tile(cols, bu.cs, t, ws, c);
+        load_tile(cols, csi, t, ws, c);
         wave_sync();  // the previous tile's LDS reads come first
         switch (bu.kind) {
           case TK_FIXED0: tile_fixed<0>(c, ws, err, wl); break;

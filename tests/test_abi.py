@@ -95,5 +95,17 @@ def test_null_handle_is_rejected(lib):
     assert lib.pq_num_row_groups(None, ctypes.byref(n)) == PQ_EINVAL
     assert lib.pq_plan(None, 1, 0, 1, None) == PQ_EINVAL
     assert lib.pq_scan_check(None, None, None) == PQ_EINVAL
-    assert lib.pq_profile(None, 1) == PQ_EINVAL
+    assert lib.pq_profile(None, 0) == PQ_OK  # NULL: the recorder of batched scans
     lib.pq_close(None)  # a no-op
+
+
+def test_batch_calls_reject_bad_arguments_on_the_host(lib):
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    lib.pq_plan_batch.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(u64), vp, ctypes.c_int32]
+    lib.pq_scan_batch.argtypes = [vp, ctypes.c_int32, vp, vp, u64, vp]
+    ws = u64(0)
+    assert lib.pq_plan_batch(None, 0, ctypes.byref(ws), None, 0) == PQ_OK  # an empty batch
+    assert ws.value >= 256
+    assert lib.pq_plan_batch(None, 1, ctypes.byref(ws), None, 0) == PQ_EINVAL
+    assert lib.pq_plan_batch(None, 0, None, None, 0) == PQ_EINVAL
+    assert lib.pq_scan_batch(None, 0, None, None, 0, None) == PQ_EINVAL  # NULL workspace
