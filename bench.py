@@ -134,6 +134,100 @@ def read_traffic(key):
     return None
 
 
+def bench_batch(nfiles, reps, log):
+    """The many-files workload (Zipf row counts, 8 OPTIONAL columns, mixed
+    page sizes, Snappy on half the files) scanned three ways, every column of
+    every file, into the same output buffers: one batched scan (one persistent
+    decode launch; default and autotuned schedule), the per-page form (one
+    launch per page and decoder), and one pq_scan per file (one launch per
+    decoder per file).  Each time is the median over `reps` runs between HIP
+    events on one stream, inputs resident in HBM."""
+    import torch
+    import datagen as dg
+    import paper_2602_17335_amd as pqs
+    t0 = time.perf_counter()
+    specs = dg.batch_specs(nfiles)
+    total_rows = sum(sp.num_rows for sp in specs)
+    datas = [dg.write(sp, nthreads=min(16, os.cpu_count() or 1)) for sp in specs]
+    log(f"batch: generated {nfiles} files, {sum(d.size for d in datas) / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    files = []
+    for d in datas:
+        buf, n = pqs.to_device(d)
+        files.append(pqs.DeviceFile(buf, n))
+    torch.cuda.synchronize()
+    open_s = time.perf_counter() - t0
+    file_bytes = sum(d.size for d in datas)
+    del datas
+    pages = sum(f.stats().pages for f in files)
+    tiles = sum(f.stats().tiles for f in files)
+    log(f"batch: opened {nfiles} files ({pages} data pages, {tiles} tiles) in {open_s:.1f} s")
+    b = pqs.Batch([(f, list(range(8)), 0, None) for f in files])
+    dec = b.decoded_bytes
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        v = []
+        for _ in range(n):
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            z.record(stream)
+            torch.cuda.synchronize()
+            v.append(a.elapsed_time(z))
+        v.sort()
+        return v[len(v) // 2]
+
+    batched_ms = timed(lambda: b.scan(), reps)
+    b.check()
+    best, tuned_ms_at_tune, default_ms_at_tune = b.autotune(reps=3)
+    tuned_ms = timed(lambda: b.scan(best), reps)
+    b.check()
+    pqs.batch_profile(True)
+    b.scan(best)
+    torch.cuda.synchronize()
+    prof = pqs.batch_profile_read()
+    pqs.batch_profile(False)
+    pp = pqs.tuning_default()
+    pp.form = pqs.FORM_PER_PAGE
+    per_page_ms = timed(lambda: b.scan(pp), max(2, reps // 4))
+    b.check()
+    # one pq_scan per file, into the batch's own output buffers
+    need = max(f.plan(mask, rb, re_).workspace_bytes for f, cols, rb, re_, mask in b.requests)
+    ws = torch.empty(max(int(need), 256), dtype=torch.uint8, device="cuda")
+
+    def per_file():
+        for i, (f, cols, rb, re_, mask) in enumerate(b.requests):
+            f.scan_into(mask, rb, re_, list(b._outs[i])[: len(cols)], ws)
+
+    per_file_ms = timed(per_file, max(2, reps // 4))
+    files[0].check(ws)
+    gbps = lambda ms: round(dec / (ms / 1e3) / 1e9, 2)
+    out = {
+        "workload": f"{nfiles} files, Zipf(1.1) row counts 10,000..4,000,000 ({total_rows:,} rows), "
+                    "8 OPTIONAL columns with 5% nulls (INT32 PLAIN, INT32 dictionary, INT64 DELTA, INT64 dictionary, "
+                    "2 DOUBLE PLAIN, 2 string dictionary), pages 8 KiB..1 MiB, Snappy on half the files, 1M-row row groups",
+        "file_bytes": file_bytes, "pages": pages, "tiles": tiles, "decoded_bytes": dec, "open_s": round(open_s, 2),
+        "batched_ms": round(batched_ms, 3), "batched_gbps": gbps(batched_ms),
+        "autotuned_ms": round(tuned_ms, 3), "autotuned_gbps": gbps(tuned_ms),
+        "per_page_ms": round(per_page_ms, 3), "per_page_gbps": gbps(per_page_ms),
+        "per_file_ms": round(per_file_ms, 3), "per_file_gbps": gbps(per_file_ms),
+        "speedup_vs_per_page": round(per_page_ms / tuned_ms, 2), "speedup_vs_per_file": round(per_file_ms / tuned_ms, 2),
+        "autotuner": {"default_ms": round(default_ms_at_tune, 3), "best_ms": round(tuned_ms_at_tune, 3),
+                      "waves_per_cu": best.waves_per_cu, "queues": best.queues,
+                      "tiles_per_unit": list(best.tiles_per_unit)},
+        "kernels": {k: {"launches": n, "avg_ms": round(t / max(n, 1), 4)} for k, (n, t) in prof.items()},
+    }
+    log(f"batch: batched {batched_ms:.2f} ms (autotuned {tuned_ms:.2f}), per-page {per_page_ms:.2f} ms, "
+        f"per-file {per_file_ms:.2f} ms for {dec / 1e9:.2f} GB decoded")
+    for f in files:
+        f.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +241,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--batch-files", type=int, default=4096,
+                    help="files of the many-files workload (batched vs plain forms); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
@@ -270,6 +366,14 @@ def main():
         for k, v in per.items():
             log(f"  roofline {k:18s} {v['achieved']:8.1f} GB/s = {v['frac'] * 100:5.1f}% of HBM peak")
 
+    batch = None
+    if args.batch_files > 0:
+        del ws, outs, tens
+        f.close()
+        del buf
+        torch.cuda.empty_cache()
+        batch = bench_batch(args.batch_files, max(5, args.steps // 2), log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle over the same file ...")
@@ -290,6 +394,7 @@ def main():
                    "form": "plain (one launch per kernel kind per scan)", "kernels": kern,
                    "latency": latency},
         "roofline": roof,
+        "batched_vs_plain": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

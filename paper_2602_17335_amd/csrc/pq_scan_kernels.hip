@@ -312,14 +312,17 @@ __device__ __forceinline__ Segment seg_lookup(const SegTable& seg, uint32_t unit
 // lives across the loop a vector register).
 __device__ __forceinline__ bool uniform_bool(bool v) { return __builtin_amdgcn_readfirstlane((int)v) != 0; }
 
-// This lane's thread index, recomputed where it is used: inside the
-// persistent kernel's tile loop the compiler would otherwise compute every
-// per-lane constant of the tile functions (LDS addresses, row numbers) once,
-// before the loop, and hold them all in vector registers for its whole
-// length (twice the registers of the one-tile kernels).
+// This lane's thread index.  With LOOP (the tile functions inside the
+// persistent kernel's tile loop) it is recomputed where it is used: the
+// compiler would otherwise compute every per-lane constant of the tile
+// functions (LDS addresses, row numbers) once, before the loop, and hold
+// them all in vector registers for its whole length (twice the registers of
+// the one-tile kernels).  The one-tile kernels keep the plain index, which
+// the compiler may schedule freely.
+template <bool LOOP>
 __device__ __forceinline__ uint32_t lane_id() {
   uint32_t v = threadIdx.x;
-  asm volatile("" : "+v"(v));
+  if constexpr (LOOP) asm volatile("" : "+v"(v));
   return v;
 }
 
@@ -1902,17 +1905,17 @@ __global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const 
 // FX_WIDE: 8-byte values), so that each is compiled for its own register
 // needs; a wave whose tile is of another kind leaves at once.
 enum : int { FX_DICT = 1, FX_WIDE = 2 };
-template <int KIND>
+template <int KIND, bool LOOP>
 __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
                                            lds_u32* wl) {
   constexpr bool is_dict = KIND & FX_DICT;
   constexpr bool w4 = !(KIND & FX_WIDE);
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
-  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id() & 63) >> 2)];
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id<LOOP>() & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id<LOOP>() & 63) >> 2)];
   const int enc = c.pg.encoding;
   if (enc == E_DELTA) return;  // k_decode_delta
-  const uint32_t lane = lane_id() & 63;
+  const uint32_t lane = lane_id<LOOP>() & 63;
   const bool dict_page = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   if (!dict_page && enc != E_PLAIN) {
     if (is_dict && lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);  // reported once
@@ -2010,7 +2013,7 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(uint8_t* __restrict__ ws, c
   __shared__ uint32_t s_idx[NWAVES][(KIND & FX_DICT) ? PADN : 1];
   WaveTile c;
   if (!wave_tile(seg, cols, ws, c)) return;
-  tile_fixed<KIND>(c, ws, err, (lds_u32*)&s_idx[threadIdx.x >> 6][0]);
+  tile_fixed<KIND, false>(c, ws, err, (lds_u32*)&s_idx[threadIdx.x >> 6][0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2019,11 +2022,12 @@ __global__ __launch_bounds__(WG) void k_decode_fixed(uint8_t* __restrict__ ws, c
 // per wave: the values of one half of the tile's rows (at most TR / 2)
 constexpr uint32_t DHALF = TR / 2;
 constexpr uint32_t DELTA_LDS_WORDS = 2 * (DHALF + DHALF / 16 + 4);
+template <bool LOOP>
 __device__ __forceinline__ void tile_delta(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
                                            lds_u32* wl) {
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id<LOOP>() & 63)];
   if (c.pg.encoding != E_DELTA) return;  // k_decode_fixed
-  const uint32_t lane = lane_id() & 63;
+  const uint32_t lane = lane_id<LOOP>() & 63;
   uint32_t vw;
   if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
   __attribute__((address_space(3))) uint64_t* vals = (__attribute__((address_space(3))) uint64_t*)wl;
@@ -2099,7 +2103,7 @@ __global__ __launch_bounds__(WG) void k_decode_delta(uint8_t* __restrict__ ws, c
   __shared__ uint64_t s_vals[NWAVES][DELTA_LDS_WORDS / 2];
   WaveTile c;
   if (!wave_tile(seg, cols, ws, c)) return;
-  tile_delta(c, ws, err, (lds_u32*)&s_vals[threadIdx.x >> 6][0]);
+  tile_delta<false>(c, ws, err, (lds_u32*)&s_vals[threadIdx.x >> 6][0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2116,15 +2120,15 @@ template <bool SLOTS>
 struct StrLds {
   static constexpr uint32_t BUFW = SLOTS ? 2 * PADN + 8 : PADN + GROUP_CHARS / 4 + 8;
 };
-template <bool SLOTS>
+template <bool SLOTS, bool LOOP>
 __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
                                          lds_u32* wl) {
   constexpr uint32_t BUFW = StrLds<SLOTS>::BUFW;
   constexpr uint32_t CB = (BUFW - 8) * 4;  // staged chars per batch
   // checkpoint words first: their loads overlap the tile's metadata loads
-  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id() & 63)];
-  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id() & 63) >> 2)];
-  const uint32_t lane = lane_id() & 63;
+  const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id<LOOP>() & 63)];
+  const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id<LOOP>() & 63) >> 2)];
+  const uint32_t lane = lane_id<LOOP>() & 63;
   const int enc = c.pg.encoding;
   const bool is_plain = !SLOTS && enc == E_PLAIN;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
@@ -2421,7 +2425,7 @@ __global__ __launch_bounds__(WG) void k_decode_str(uint8_t* __restrict__ ws, con
   __shared__ __align__(16) uint32_t s_buf[NWAVES][StrLds<SLOTS>::BUFW];
   WaveTile c;
   if (!wave_tile(seg, cols, ws, c)) return;
-  tile_str<SLOTS>(c, ws, err, (lds_u32*)&s_buf[threadIdx.x >> 6][0]);
+  tile_str<SLOTS, false>(c, ws, err, (lds_u32*)&s_buf[threadIdx.x >> 6][0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2480,13 +2484,13 @@ __global__ __launch_bounds__(WG) void k_batch(uint8_t* __restrict__ ws, const Co
         load_tile(cols, csi, t, ws, c);
         wave_sync();  // the previous tile's LDS reads come first
         switch (bu.kind) {
-          case TK_FIXED0: tile_fixed<0>(c, ws, err, wl); break;
-          case TK_FIXED1: tile_fixed<FX_DICT>(c, ws, err, wl); break;
-          case TK_FIXED2: tile_fixed<FX_WIDE>(c, ws, err, wl); break;
-          case TK_FIXED3: tile_fixed<FX_DICT | FX_WIDE>(c, ws, err, wl); break;
-          case TK_DELTA: tile_delta(c, ws, err, wl); break;
-          case TK_STR: tile_str<false>(c, ws, err, wl); break;
-          default: tile_str<true>(c, ws, err, wl); break;
+          case TK_FIXED0: tile_fixed<0, true>(c, ws, err, wl); break;
+          case TK_FIXED1: tile_fixed<FX_DICT, true>(c, ws, err, wl); break;
+          case TK_FIXED2: tile_fixed<FX_WIDE, true>(c, ws, err, wl); break;
+          case TK_FIXED3: tile_fixed<FX_DICT | FX_WIDE, true>(c, ws, err, wl); break;
+          case TK_DELTA: tile_delta<true>(c, ws, err, wl); break;
+          case TK_STR: tile_str<false, true>(c, ws, err, wl); break;
+          default: tile_str<true, true>(c, ws, err, wl); break;
         }
         tile_required_validity(c, lane);
       }
