@@ -187,11 +187,32 @@ pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
    value width.  Returns PQ_EINVAL / PQ_ECAPACITY (workspace) before
    enqueueing anything. */
 
+/*
+ * pq_scan without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same scan as pq_scan, with the workspace taken
+ * from a file-scope device array of 64 MiB that every GPU the library runs
+ * on holds until the process ends; its device address is looked up once per
+ * device (hipGetSymbolAddress) on the first call made with that device
+ * current.  The caller still passes the outputs.  Calls no hipMalloc,
+ * hipFree or other device-memory allocator.  Returns PQ_ECAPACITY, before
+ * enqueueing anything, when the scan's planned workspace (pq_plan) exceeds
+ * 64 MiB -- a scan of compressed pages needs their decompressed bytes there.
+ * Every call on one GPU shares that GPU's array (the last call's contents
+ * stay; the scan's header, with its cleared error word, is rewritten by
+ * each call): calls that overlap on one GPU race, so a caller serialises
+ * them (one stream, or its own ordering).  pq_scan_check(f, NULL, stream)
+ * reports the error word of the last such scan on the current device.
+ */
+pq_status pq_scan_noalloc(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
+                          int32_t n_outs, pq_stream stream);
+
 /* Synchronises `stream` and returns (then clears) the error word of the
    scan that last used `workspace` (Sec. 2: the decode kernels of that
    scan): PQ_OK, or PQ_ECORRUPT / PQ_EUNSUPPORTED / PQ_ECAPACITY found by a
    kernel.  Scans on other workspaces are not affected.  `f` may be NULL
-   (a batch over several files). */
+   (a batch over several files); `workspace` NULL means the scratch array of
+   pq_scan_noalloc on the current device. */
 pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream);
 
 /* Encoded bytes of column `col` over all row groups (Sec. 3: the encoded

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1199,9 +1200,66 @@ extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int
   return enqueue(f, P, (uint8_t*)workspace, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free scans
+// ---------------------------------------------------------------------------
+// The workspace of pq_scan_noalloc: a file-scope device array of
+// NOALLOC_BYTES on every GPU the library runs on, held until the process
+// ends.  Host code never passes its name to a kernel or a copy (that is a
+// host-side stand-in); it takes the array's device address, per device,
+// from hipGetSymbolAddress on the first call made on that device.
+constexpr uint64_t NOALLOC_BYTES = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static uint8_t* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array (nullptr on error,
+// with the message set).
+static uint8_t* scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    fail(PQ_EHIP, "pq_scan_noalloc: no current device (or device id %d out of range)", dev);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fail(PQ_EHIP, "pq_scan_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<uint8_t*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+extern "C" pq_status pq_scan_noalloc(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end,
+                                     const pq_column_out* outs, int32_t n_outs, pq_stream stream) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  Plan P;
+  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
+  if (st != PQ_OK) return st;
+  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+  if (P.ws_total > NOALLOC_BYTES)
+    return fail(PQ_ECAPACITY, "pq_scan_noalloc: the scan needs %llu bytes of workspace, above the %llu-byte scratch array "
+                "(use pq_scan with a caller workspace)", (unsigned long long)P.ws_total, (unsigned long long)NOALLOC_BYTES);
+  st = bind_outputs(P, outs, n_outs);
+  if (st != PQ_OK) return st;
+  uint8_t* ws = scratch_of_current_device();
+  if (!ws) return PQ_EHIP;
+  return enqueue(f, P, ws, (hipStream_t)stream);
+}
+
 extern "C" pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream) {
   (void)f;
-  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  if (!workspace) {
+    // the scratch array of pq_scan_noalloc on the current device
+    uint8_t* p = scratch_of_current_device();
+    if (!p) return PQ_EHIP;
+    return read_err_word(reinterpret_cast<uint32_t*>(p), (hipStream_t)stream);
+  }
   return read_err_word(reinterpret_cast<uint32_t*>(const_cast<void*>(workspace)), (hipStream_t)stream);
 }
 
