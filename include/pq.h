@@ -65,7 +65,8 @@ typedef enum {
   PQ_EUNSUPPORTED = -3, /* valid Parquet outside the supported subset */
   PQ_ENOMEM = -4,       /* device or host allocation failed */
   PQ_EHIP = -5,         /* a HIP runtime call failed */
-  PQ_ECAPACITY = -7     /* an output or workspace buffer is smaller than planned */
+  PQ_ECAPACITY = -7,    /* an output or workspace buffer is smaller than planned */
+  PQ_EBUSY = -8         /* the server has not finished the request within the wait */
 } pq_status;
 
 typedef enum { PQ_INT32 = 1, PQ_INT64 = 2, PQ_DOUBLE = 5, PQ_BYTE_ARRAY = 6 } pq_type;
@@ -312,6 +313,68 @@ pq_status pq_scan_batch(const pq_request* reqs, int32_t n, const pq_tuning* tuni
    stream; the outputs hold the batch's result afterwards. */
 pq_status pq_autotune_batch(const pq_request* reqs, int32_t n, void* workspace, uint64_t workspace_bytes,
                             pq_stream stream, int32_t reps, pq_tuning* best, double* best_ms, double* default_ms);
+
+/*
+ * The scan server: a request loop over a catalog of opened (resident) files
+ * for many concurrent clients (Sec. 4: overlapping the reader's stages with
+ * other GPU work; Sec. 4.2: consumers take row groups as they are
+ * produced).  Requests -- columns of a row-group range of one catalog file
+ * -- are admitted in arrival order against a device-memory budget: each
+ * needs its outputs and its share of a batch workspace in the server's one
+ * arena of budget_bytes.  A scheduler thread keeps up to `slots` batched
+ * scans (pq_scan_batch, at most max_batch requests each, `tuning` NULL = the
+ * default schedule) in flight, one per stream: requests that arrive while
+ * batches run are batched as soon as a slot and memory are free, so their
+ * work overlaps on the device (continuous batching).  Results stay resident
+ * in the arena until released; a request identical to a resident (or
+ * in-flight) one shares its result.  Unreferenced resident results are
+ * evicted, least recently used first, when memory is needed.  Dictionaries
+ * are those the handles keep resident.
+ */
+typedef struct pq_server_s* pq_server;
+typedef struct {
+  int32_t status;          /* PQ_OK or the request's error */
+  int32_t n_outs;          /* selected columns */
+  int32_t shared;          /* 1: served by a resident (or in-flight) identical result */
+  int32_t pad_;
+  int64_t rows;
+  uint64_t decoded_bytes;  /* values (null slots included), validity, offsets, chars */
+  double queue_ms;         /* submit -> admitted into a batch */
+  double latency_ms;       /* submit -> the batch that decoded it finished on the device */
+  pq_column_out outs[64];  /* device pointers into the server's arena (layout as pq_scan's),
+                              valid until pq_server_release */
+} pq_served;
+typedef struct {
+  uint64_t submitted, completed, failed, batches, cache_hits, evictions;
+  uint64_t decoded_bytes;  /* of completed requests */
+  uint64_t budget_bytes, used_bytes, resident_results;
+} pq_server_stats;
+
+/* Creates a server over n_files opened files (borrowed: they must outlive
+   the server), allocating its arena of budget_bytes and `slots` streams
+   (1..16). */
+pq_status pq_server_create(const pq_file* files, int32_t n_files, uint64_t budget_bytes, int32_t slots,
+                           int32_t max_batch, const pq_tuning* tuning, pq_server* out);
+/* Queues a request (Sec. 2: columns of a row-group range); thread-safe.
+   PQ_EINVAL for a bad file index, range or mask. */
+pq_status pq_server_submit(pq_server s, int32_t file, uint64_t col_mask, int32_t rg_begin, int32_t rg_end,
+                           uint64_t* id);
+/* Waits up to timeout_ms (negative: an hour) for request `id` (Sec. 3: the
+   scan's run time is what the effective bandwidth divides by) and fills
+   *out; returns the request's status, or PQ_EBUSY on time-out. */
+pq_status pq_server_wait(pq_server s, uint64_t id, int32_t timeout_ms, pq_served* out);
+/* Releases a finished request's hold on its result, which stays resident
+   until evicted (Sec. 4: results stay in GPU memory for the operators that
+   consume them). */
+pq_status pq_server_release(pq_server s, uint64_t id);
+/* Counters of the server (Sec. 3: decoded bytes over time). */
+pq_status pq_server_stats_get(pq_server s, pq_server_stats* out);
+/* Drains the requests in flight, then frees the arena and the streams
+   (Sec. 2: the reader's state). */
+void pq_server_destroy(pq_server s);
+/* Thread-local message of the server's last failure (Sec. 2: the reader's
+   error reporting). */
+const char* pq_server_last_error(void);
 
 /* Frees the handle's host and device memory (not dev_buf).  Sec. 2: the
    handle is the reader's state for one file. */

@@ -14,14 +14,15 @@ from typing import Dict, List, Optional, Sequence
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpqscan.so")
 
-PQ_OK, PQ_EINVAL, PQ_ECORRUPT, PQ_EUNSUPPORTED, PQ_ENOMEM, PQ_EHIP, PQ_ECAPACITY = 0, -1, -2, -3, -4, -5, -7
+PQ_OK, PQ_EINVAL, PQ_ECORRUPT, PQ_EUNSUPPORTED, PQ_ENOMEM, PQ_EHIP, PQ_ECAPACITY, PQ_EBUSY = 0, -1, -2, -3, -4, -5, -7, -8
 INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
 _WIDTH = {INT32: 4, INT64: 8, DOUBLE: 8}
 
 EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get", "pq_row_group_rows",
            "pq_file_stats_get", "pq_column_bytes", "pq_column_encodings", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
            "pq_profile_read", "pq_close", "pq_last_error", "pq_tuning_default", "pq_plan_batch", "pq_scan_batch",
-           "pq_autotune_batch")
+           "pq_autotune_batch", "pq_scan_noalloc", "pq_server_create", "pq_server_submit", "pq_server_wait",
+           "pq_server_release", "pq_server_stats_get", "pq_server_destroy", "pq_server_last_error")
 FORM_BATCHED, FORM_PER_PAGE = 0, 1
 TUNE_CLASSES = 42
 
@@ -79,6 +80,17 @@ class Tuning(ctypes.Structure):
         return t
 
 
+class Served(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_outs", ctypes.c_int32), ("shared", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("rows", ctypes.c_int64), ("decoded_bytes", ctypes.c_uint64),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("outs", ColumnOut * 64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "batches", "cache_hits", "evictions",
+                                               "decoded_bytes", "budget_bytes", "used_bytes", "resident_results")]
+
+
 _lib = None
 
 
@@ -109,13 +121,23 @@ def lib() -> ctypes.CDLL:
         L.pq_scan_batch.argtypes = [ctypes.POINTER(Request), i32, ctypes.POINTER(Tuning), vp, u64, vp]
         L.pq_autotune_batch.argtypes = [ctypes.POINTER(Request), i32, vp, u64, vp, i32, ctypes.POINTER(Tuning),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.pq_server_create.argtypes = [ctypes.POINTER(vp), i32, u64, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
+        L.pq_server_submit.argtypes = [vp, i32, u64, i32, i32, ctypes.POINTER(u64)]
+        L.pq_server_wait.argtypes = [vp, u64, i32, ctypes.POINTER(Served)]
+        L.pq_server_release.argtypes = [vp, u64]
+        L.pq_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.pq_server_destroy.argtypes = [vp]
+        L.pq_server_destroy.restype = None
+        L.pq_server_last_error.restype = ctypes.c_char_p
         L.pq_close.argtypes = [vp]
         L.pq_close.restype = None
         L.pq_last_error.restype = ctypes.c_char_p
         for name in ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_info_get",
                      "pq_row_group_rows", "pq_file_stats_get", "pq_plan", "pq_scan", "pq_scan_check",
                      "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read",
-                     "pq_tuning_default", "pq_plan_batch", "pq_scan_batch", "pq_autotune_batch"):
+                     "pq_tuning_default", "pq_plan_batch", "pq_scan_batch", "pq_autotune_batch",
+                     "pq_server_create", "pq_server_submit", "pq_server_wait", "pq_server_release",
+                     "pq_server_stats_get"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -434,3 +456,111 @@ class Batch:
                                        self.workspace.numel(), ctypes.c_void_p(_stream_ptr(stream)), reps,
                                        ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms)))
         return best, bms.value, dms.value
+
+
+# ---------------------------------------------------------------------------
+# the scan server
+# ---------------------------------------------------------------------------
+
+_hip = None
+
+
+def _hip_memcpy_d2h(dst_numpy, src_ptr: int):
+    """Copies device bytes into a host numpy array (HIP runtime, which torch
+    has already loaded)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    if dst_numpy.nbytes:
+        rc = _hip.hipMemcpy(dst_numpy.ctypes.data, ctypes.c_void_p(src_ptr), dst_numpy.nbytes, 2)
+        if rc != 0:
+            raise PqError(PQ_EHIP, f"hipMemcpy failed ({rc})")
+
+
+def _server_check(rc: int):
+    if rc != PQ_OK:
+        raise PqError(rc, lib().pq_server_last_error().decode(errors="replace"))
+
+
+class Server:
+    """pq_server over a catalog of DeviceFiles: submit(file index, columns,
+    rg range) -> id; wait(id) -> Served; fetch(id) copies a result to host
+    numpy arrays; release(id)."""
+
+    def __init__(self, files, budget_bytes: int, slots: int = 4, max_batch: int = 64,
+                 tuning: Optional[Tuning] = None):
+        self.files = list(files)
+        arr = (ctypes.c_void_p * len(self.files))(*[f._h.value for f in self.files])
+        h = ctypes.c_void_p()
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        _server_check(lib().pq_server_create(arr, len(self.files), budget_bytes, slots, max_batch, tp,
+                                             ctypes.byref(h)))
+        self._h = h
+        self._cols = {}
+
+    def close(self):
+        if self._h:
+            lib().pq_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, file: int, columns: Sequence[int], rg_begin: int, rg_end: int) -> int:
+        mask = 0
+        for c in columns:
+            mask |= 1 << c
+        rid = ctypes.c_uint64()
+        _server_check(lib().pq_server_submit(self._h, file, mask, rg_begin, rg_end, ctypes.byref(rid)))
+        self._cols[rid.value] = (file, sorted(columns))
+        return rid.value
+
+    def wait(self, rid: int, timeout_ms: int = -1) -> Served:
+        out = Served()
+        rc = lib().pq_server_wait(self._h, rid, timeout_ms, ctypes.byref(out))
+        if rc != PQ_OK:
+            _server_check(rc)
+        return out
+
+    def fetch(self, rid: int, served: Served) -> Dict[int, dict]:
+        """The request's columns as host numpy arrays: validity (whole words),
+        values or offsets + chars."""
+        import numpy as np
+        file, cols = self._cols[rid]
+        f = self.files[file]
+        rows = served.rows
+        res = {}
+        for k, c in enumerate(cols):
+            o = served.outs[k]
+            d = {"rows": rows}
+            vw = np.empty(validity_bytes(rows), dtype=np.uint8)
+            _hip_memcpy_d2h(vw, o.validity)
+            d["validity_words"] = vw
+            d["validity"] = vw[: (rows + 7) // 8]
+            t = f.column_info(c).type
+            if t == BYTE_ARRAY:
+                off = np.empty(rows + 1, dtype=np.int64)
+                _hip_memcpy_d2h(off, o.offsets)
+                ch = np.empty(int(off[-1]) if rows >= 0 else 0, dtype=np.uint8)
+                _hip_memcpy_d2h(ch, o.chars)
+                d["offsets"], d["chars"] = off, ch
+            else:
+                v = np.empty(rows, dtype={INT32: np.int32, INT64: np.int64, DOUBLE: np.float64}[t])
+                _hip_memcpy_d2h(v, o.values)
+                d["values"] = v
+            res[c] = d
+        return res
+
+    def release(self, rid: int):
+        _server_check(lib().pq_server_release(self._h, rid))
+        self._cols.pop(rid, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _server_check(lib().pq_server_stats_get(self._h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libpqscan.so")
-SOURCES = ["csrc/pq_api.cpp", "csrc/pq_open_kernels.hip", "csrc/pq_scan_kernels.hip"]
+SOURCES = ["csrc/pq_api.cpp", "csrc/pq_serve.cpp", "csrc/pq_open_kernels.hip", "csrc/pq_scan_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

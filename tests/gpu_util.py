@@ -33,42 +33,46 @@ def check_guards(g, name=""):
             raise AssertionError(f"{name}: guard region {k} written at bytes {bad[:10]} (of {bad.size})")
 
 
+def _np(x):
+    return x if isinstance(x, np.ndarray) else x.cpu().numpy()
+
+
 def compare_column(o, g, name=""):
-    """o: oracle dict, g: GPU dict of torch tensors."""
+    """o: oracle dict, g: GPU dict of torch tensors (or host numpy arrays)."""
     rows = o["rows"]
     assert g["rows"] == rows, (name, g["rows"], rows)
-    gv = g["validity"].cpu().numpy()
+    gv = _np(g["validity"])
     assert gv.size == o["validity"].size
     if not (gv == o["validity"]).all():
         bad = np.nonzero(gv != o["validity"])[0]
         raise AssertionError(f"{name}: validity differs at bytes {bad[:10]} (of {bad.size})")
     if "validity_words" in g:
         # the whole 32-bit words the library writes: bits past `rows` are 0
-        words = g["validity_words"].cpu().numpy()
+        words = _np(g["validity_words"])
         exp = np.zeros(words.size, dtype=np.uint8)
         exp[: o["validity"].size] = o["validity"]
         if not (words == exp).all():
             bad = np.nonzero(words != exp)[0]
             raise AssertionError(f"{name}: validity word tail differs at bytes {bad[:10]} (of {bad.size})")
     if "offsets" in o:
-        goff = g["offsets"].cpu().numpy()
+        goff = _np(g["offsets"])
         if not (goff == o["offsets"]).all():
             bad = np.nonzero(goff != o["offsets"])[0]
             raise AssertionError(f"{name}: offsets differ at rows {bad[:10]} (of {bad.size}): "
                                  f"gpu {goff[bad[:5]]} oracle {o['offsets'][bad[:5]]}")
-        gch = g["chars"].cpu().numpy()
+        gch = _np(g["chars"])
         assert gch.size == o["chars"].size, (name, gch.size, o["chars"].size)
         if not (gch == o["chars"]).all():
             bad = np.nonzero(gch != o["chars"])[0]
             raise AssertionError(f"{name}: chars differ at {bad[:10]} (of {bad.size})")
     else:
-        gvals = g["values"].cpu().numpy().view(np.uint8)
+        gvals = _np(g["values"]).view(np.uint8)
         ov = o["values"].view(np.uint8)
         if not (gvals == ov).all():
             w = o["values"].itemsize
             bad = np.nonzero((gvals != ov).reshape(-1, w).any(axis=1))[0]
             raise AssertionError(f"{name}: values differ at rows {bad[:10]} (of {bad.size}): "
-                                 f"gpu {g['values'].cpu().numpy()[bad[:5]]} oracle {o['values'][bad[:5]]}")
+                                 f"gpu {_np(g['values'])[bad[:5]]} oracle {o['values'][bad[:5]]}")
     check_guards(g, name)
 
 
