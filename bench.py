@@ -228,6 +228,97 @@ def bench_batch(nfiles, reps, log):
     return out
 
 
+def bench_serve(nfiles, max_bytes, budget_bytes, qps_list, seconds, log, seed=0x5EED0006):
+    """The scan server under Poisson load: a catalog of resident files
+    (encoded sizes log-uniform in [1 MB, max_bytes]; plain and Snappy wide
+    tables and the 8-column recipe), requests of 1-8 random columns over a
+    random contiguous row-group range of a random file, arriving as a Poisson
+    process at each rate of `qps_list` for `seconds`.  Latency is the
+    server's submit-to-completion time (completion = the stream callback after
+    the batch that decoded the request); decoded GB/s = decoded bytes of the
+    completed requests over the wall time of the run."""
+    import queue
+    import threading
+    import numpy as np
+    import torch
+    import datagen as dg
+    import paper_2602_17335_amd as pqs
+    t0 = time.perf_counter()
+    files, enc = [], 0
+    for sp in dg.serve_catalog(nfiles, max_bytes=max_bytes):
+        d = dg.write(sp, nthreads=min(16, os.cpu_count() or 1))
+        enc += d.size
+        buf, n = pqs.to_device(d)
+        del d
+        files.append(pqs.DeviceFile(buf, n))
+    torch.cuda.synchronize()
+    log(f"serve: {nfiles} files, {enc / 1e9:.2f} GB encoded, generated and opened in {time.perf_counter() - t0:.1f} s")
+    meta = [(f.num_columns, f.num_row_groups) for f in files]
+    srv = pqs.Server(files, budget_bytes, slots=4, max_batch=64)
+    rng = np.random.default_rng(seed)
+    points = []
+    for qps in qps_list:
+        n = max(1, int(rng.poisson(qps * seconds)))
+        gaps = rng.exponential(1.0 / qps, n)
+        reqs = []
+        for _ in range(n):
+            i = int(rng.integers(0, nfiles))
+            nc, nrg = meta[i]
+            cols = sorted(rng.choice(nc, size=int(rng.integers(1, min(8, nc) + 1)), replace=False).tolist())
+            b = int(rng.integers(0, nrg))
+            e = int(rng.integers(b + 1, nrg + 1))
+            reqs.append((i, cols, b, e))
+        ids = queue.Queue()
+        lat, qms, dec, bad = [], [], [0], [0]
+
+        def waiter():
+            while True:
+                rid = ids.get()
+                if rid is None:
+                    return
+                sv = srv.wait(rid)
+                lat.append(sv.latency_ms)
+                qms.append(sv.queue_ms)
+                dec[0] += sv.decoded_bytes
+                bad[0] += sv.status != 0
+                srv.release(rid)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        at = start
+        for g, r in zip(gaps, reqs):
+            at += g
+            while True:
+                dt = at - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.0005))
+            ids.put(srv.submit(*r))
+        ids.put(None)
+        th.join()
+        wall = time.perf_counter() - start
+        lat.sort()
+        qms.sort()
+        pct = lambda v, q: round(v[min(len(v) - 1, int(round(q * (len(v) - 1))))], 3)
+        offered = n / (at - start) if at > start else 0.0
+        pt = {"qps_offered": round(offered, 1), "requests": n, "failed": bad[0],
+              "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "queue_p50_ms": pct(qms, 0.5),
+              "queue_p99_ms": pct(qms, 0.99), "decoded_gbps": round(dec[0] / wall / 1e9, 2),
+              "qps_served": round(n / wall, 1)}
+        log(f"serve: {qps} QPS offered -> p50 {pt['p50_ms']} ms, p99 {pt['p99_ms']} ms, {pt['decoded_gbps']} GB/s decoded")
+        points.append(pt)
+    st = srv.stats()
+    srv.close()
+    for f in files:
+        f.close()
+    return {"workload": f"{nfiles} resident files, {enc / 1e9:.2f} GB encoded (sizes log-uniform 1 MB..{max_bytes / 1e6:.0f} MB; "
+                        "wide tables plain and Snappy, 8-column recipe), Poisson arrivals, 1-8 random columns over a random "
+                        "row-group range per request",
+            "budget_bytes": budget_bytes, "slots": 4, "max_batch": 64, "seconds_per_point": seconds, "points": points,
+            "batches": st["batches"], "shared_results": st["cache_hits"], "evictions": st["evictions"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +334,13 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--batch-files", type=int, default=4096,
                     help="files of the many-files workload (batched vs plain forms); 0 skips it")
+    ap.add_argument("--serve-files", type=int, default=64,
+                    help="files of the serving catalog (0 skips the serving run; 256 with --serve-max-mb 2000 "
+                         "is the full catalog)")
+    ap.add_argument("--serve-max-mb", type=int, default=256, help="largest catalog file, MB")
+    ap.add_argument("--serve-budget-gb", type=int, default=64, help="device-memory budget of the server, GB")
+    ap.add_argument("--serve-qps", default="200,1000,4000", help="offered request rates")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
@@ -374,6 +472,11 @@ def main():
         torch.cuda.empty_cache()
         batch = bench_batch(args.batch_files, max(5, args.steps // 2), log)
 
+    serve = None
+    if args.serve_files > 0:
+        serve = bench_serve(args.serve_files, args.serve_max_mb * 1_000_000, args.serve_budget_gb << 30,
+                            [float(x) for x in args.serve_qps.split(",")], args.serve_seconds, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle over the same file ...")
@@ -395,6 +498,7 @@ def main():
                    "latency": latency},
         "roofline": roof,
         "batched_vs_plain": batch,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

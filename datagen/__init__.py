@@ -299,3 +299,34 @@ def batch_specs(nfiles: int = 4096, max_rows: int = 4_000_000, min_rows: int = 1
                             page_bytes=int(page_kib[pages[i]]) * KiB, codec=SNAPPY if snappy[i] else UNCOMPRESSED,
                             seed=(seed + 0x1000 * (i + 1)) & 0xFFFFFFFFFFFFFFFF, name=f"batch{i}"))
     return out
+
+
+def serve_catalog(nfiles: int = 256, min_bytes: int = 1_000_000, max_bytes: int = 2_000_000_000,
+                  seed: int = 0x5EED0004) -> List[FileSpec]:
+    """The serving catalog: file i's target encoded size is log-uniform in
+    [min_bytes, max_bytes]; its recipe cycles through the wide table
+    (uncompressed), the wide table Snappy-compressed with a 1 MiB dictionary
+    cap, and the 8-column many-files recipe, with rows set from the size at
+    the recipe's measured bytes per row (about 50, 48 and 42), 1M-row row
+    groups (smaller files: at least 4 row groups), and a page-size target
+    drawn from 64 KiB .. 1 MiB."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(min_bytes), np.log(max_bytes), nfiles))
+    pages = rng.integers(0, 5, nfiles)
+    out = []
+    for i in range(nfiles):
+        kind = i % 3
+        bpr = (50.0, 48.0, 42.0)[kind]
+        rows = max(4_000, int(sizes[i] / bpr))
+        rg = min(1_000_000, max(1_000, rows // 4))
+        pb = (64 << (int(pages[i]))) * KiB
+        s = (seed + 0x1000 * (i + 1)) & 0xFFFFFFFFFFFFFFFF
+        if kind == 0:
+            sp = wide_table(rows, rg, pb, seed=s)
+        elif kind == 1:
+            sp = snappy_wide_table(rows, rg, pb, seed=s)
+        else:
+            sp = FileSpec(cols=batch_cols(), num_rows=rows, rg_rows=rg, page_bytes=pb, seed=s)
+        sp.name = f"serve{i}"
+        out.append(sp)
+    return out
