@@ -81,6 +81,12 @@ def lib():
         L.orc_hybrid_decode.restype = i64
         L.orc_delta_decode.argtypes = [vp, u64, ctypes.c_int, i64, vp]
         L.orc_delta_decode.restype = i64
+        L.orc_byte_stream_split_decode.argtypes = [vp, u64, ctypes.c_int, i64, vp]
+        L.orc_byte_stream_split_decode.restype = i64
+        L.orc_delta_length_decode.argtypes = [vp, u64, i64, vp, vp]
+        L.orc_delta_length_decode.restype = i64
+        L.orc_delta_byte_array_decode.argtypes = [vp, u64, i64, ctypes.POINTER(vp), ctypes.POINTER(u64), vp, vp]
+        L.orc_delta_byte_array_decode.restype = i64
         L.orc_snappy_decompress.argtypes = [vp, u64, vp, u64]
         L.orc_snappy_decompress.restype = i64
         L.orc_page_header_parse.argtypes = [vp, u64, ctypes.POINTER(PageHeader)]
@@ -116,6 +122,47 @@ def delta_decode(data, is32: bool, count: int):
     if n < 0:
         raise OracleError(int(n), "delta stream")
     return out[:count], int(n)
+
+
+def byte_stream_split_decode(data, width: int, count: int):
+    """(values as uint64 array, bytes used) of a BYTE_STREAM_SPLIT stream."""
+    b = _buf(data)
+    out = np.zeros(max(count, 1), dtype=np.uint64)
+    n = lib().orc_byte_stream_split_decode(b.ctypes.data, b.size, width, count, out.ctypes.data)
+    if n < 0:
+        _err(n)
+    return out[:count], n
+
+
+def delta_length_decode(data, count: int):
+    """(list of byte strings, bytes used) of a DELTA_LENGTH_BYTE_ARRAY stream."""
+    b = _buf(data)
+    pos = np.zeros(max(count, 1), dtype=np.uint64)
+    ln = np.zeros(max(count, 1), dtype=np.uint32)
+    n = lib().orc_delta_length_decode(b.ctypes.data, b.size, count, pos.ctypes.data, ln.ctypes.data)
+    if n < 0:
+        _err(n)
+    raw = b.tobytes()
+    return [raw[int(pos[k]):int(pos[k]) + int(ln[k])] for k in range(count)], n
+
+
+def delta_byte_array_decode(data, count: int):
+    """(list of byte strings, bytes used) of a DELTA_BYTE_ARRAY stream."""
+    b = _buf(data)
+    pos = np.zeros(max(count, 1), dtype=np.uint64)
+    ln = np.zeros(max(count, 1), dtype=np.uint32)
+    mat = ctypes.c_void_p()
+    cap = ctypes.c_uint64(0)
+    n = lib().orc_delta_byte_array_decode(b.ctypes.data, b.size, count, ctypes.byref(mat), ctypes.byref(cap),
+                                          pos.ctypes.data, ln.ctypes.data)
+    try:
+        if n < 0:
+            _err(n)
+        raw = ctypes.string_at(mat.value, cap.value) if mat.value else b""
+        return [raw[int(pos[k]):int(pos[k]) + int(ln[k])] for k in range(count)], n
+    finally:
+        if mat.value:
+            ctypes.CDLL(None).free(mat)
 
 
 def snappy_decompress(data, cap: int) -> bytes:

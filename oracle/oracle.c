@@ -17,10 +17,14 @@
  * groups, a row group holds one column chunk per column, a chunk is divided
  * into pages, pages carry V1 or V2 encodings, and compression (here Snappy)
  * applies per chunk.  Sec. 3 (Encoding Flexibility) names the encodings
- * decoded here: PLAIN, dictionary (V1) and DELTA_BINARY_PACKED (V2).  The
- * byte-level rules come from the public Apache Parquet format description
- * (Thrift compact footer and page headers, RLE/bit-packed hybrid,
- * DELTA_BINARY_PACKED, PLAIN) and the public Snappy raw-format description.
+ * decoded here: PLAIN, dictionary (V1) and DELTA_BINARY_PACKED (V2), and
+ * asks for every valid Parquet encoding of a type to be a candidate, which
+ * adds DELTA_LENGTH_BYTE_ARRAY and DELTA_BYTE_ARRAY for strings and
+ * BYTE_STREAM_SPLIT for fixed-width values.  The byte-level rules come from
+ * the public Apache Parquet format description (Thrift compact footer and
+ * page headers, RLE/bit-packed hybrid, DELTA_BINARY_PACKED, the string delta
+ * encodings, BYTE_STREAM_SPLIT, PLAIN) and the public Snappy raw-format
+ * description.
  *
  * Everything is deliberately slow and literal: bits are read one at a time,
  * every length is checked before it is used, and no step is fused.
@@ -502,6 +506,98 @@ int64_t orc_delta_decode(const uint8_t* p, uint64_t n, int is32, int64_t count, 
 }
 
 /* ------------------------------------------------------------------ */
+/* BYTE_STREAM_SPLIT                                                    */
+/* ------------------------------------------------------------------ */
+
+/* The page's `count` values of `w` bytes are stored as w streams of
+   `count` bytes each: stream b holds byte b (little-endian position) of
+   every value, so value k's byte b is p[b * count + k].  Returns the bytes
+   used or a negative code. */
+int64_t orc_byte_stream_split_decode(const uint8_t* p, uint64_t n, int w, int64_t count, uint64_t* out) {
+  if (w < 1 || w > 8 || count < 0) return ORC_EINVAL;
+  if ((uint64_t)count * (uint64_t)w > n) return ORC_ECORRUPT;
+  for (int64_t k = 0; k < count; ++k) {
+    uint64_t v = 0;
+    for (int b = 0; b < w; ++b) v |= (uint64_t)p[(uint64_t)b * (uint64_t)count + (uint64_t)k] << (8 * b);
+    out[k] = v;
+  }
+  return count * w;
+}
+
+/* ------------------------------------------------------------------ */
+/* DELTA_LENGTH_BYTE_ARRAY and DELTA_BYTE_ARRAY                         */
+/* ------------------------------------------------------------------ */
+
+/* DELTA_LENGTH_BYTE_ARRAY: the `count` lengths as one DELTA_BINARY_PACKED
+   stream of 32-bit values, then all the strings' bytes back to back.  Gives
+   each string's position (from p) and length; a negative length or bytes
+   past the stream are corrupt.  Returns the bytes used. */
+int64_t orc_delta_length_decode(const uint8_t* p, uint64_t n, int64_t count, uint64_t* pos, uint32_t* len) {
+  uint64_t* lens = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(count > 0 ? count : 1));
+  if (!lens) return ORC_ENOMEM;
+  int64_t used = orc_delta_decode(p, n, 1, count, lens);
+  if (used < 0) { free(lens); return used; }
+  uint64_t q = (uint64_t)used;
+  for (int64_t k = 0; k < count; ++k) {
+    int32_t l = (int32_t)(uint32_t)lens[k];
+    if (l < 0 || (uint64_t)l > n - q) { free(lens); return ORC_ECORRUPT; }
+    pos[k] = q;
+    len[k] = (uint32_t)l;
+    q += (uint64_t)l;
+  }
+  free(lens);
+  return (int64_t)q;
+}
+
+/* DELTA_BYTE_ARRAY: the `count` prefix lengths as a DELTA_BINARY_PACKED
+   stream of 32-bit values, then the suffixes as DELTA_LENGTH_BYTE_ARRAY.
+   String k is the first prefix[k] bytes of string k-1 followed by suffix k
+   (string 0 has no predecessor: its prefix length must be 0; every prefix
+   length must lie in [0, length of the previous string]).  The strings are
+   written one after the other into *mat (grown with realloc, *mat_cap bytes
+   allocated), with their positions in *mat and lengths.  Returns the bytes
+   used. */
+int64_t orc_delta_byte_array_decode(const uint8_t* p, uint64_t n, int64_t count, uint8_t** mat, uint64_t* mat_cap,
+                                    uint64_t* pos, uint32_t* len) {
+  size_t m = (size_t)(count > 0 ? count : 1);
+  uint64_t* pre = (uint64_t*)malloc(sizeof(uint64_t) * m);
+  uint64_t* spos = (uint64_t*)malloc(sizeof(uint64_t) * m);
+  uint32_t* slen = (uint32_t*)malloc(sizeof(uint32_t) * m);
+  int64_t rc = ORC_OK;
+  if (!pre || !spos || !slen) { rc = ORC_ENOMEM; goto done; }
+  int64_t used = orc_delta_decode(p, n, 1, count, pre);
+  if (used < 0) { rc = used; goto done; }
+  int64_t used2 = orc_delta_length_decode(p + used, n - (uint64_t)used, count, spos, slen);
+  if (used2 < 0) { rc = used2; goto done; }
+  uint64_t at = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    int32_t pk = (int32_t)(uint32_t)pre[k];
+    uint64_t prev_len = k > 0 ? len[k - 1] : 0;
+    if (pk < 0 || (uint64_t)pk > prev_len) { rc = ORC_ECORRUPT; goto done; }
+    uint64_t total = (uint64_t)pk + slen[k];
+    if (total > 0xffffffffull) { rc = ORC_ECORRUPT; goto done; }
+    if (at + total > *mat_cap) {
+      uint64_t cap = (*mat_cap ? *mat_cap : 1024);
+      while (cap < at + total) cap *= 2;
+      uint8_t* nm = (uint8_t*)realloc(*mat, (size_t)cap);
+      if (!nm) { rc = ORC_ENOMEM; goto done; }
+      *mat = nm;
+      *mat_cap = cap;
+    }
+    /* the prefix from the previous string, then the suffix */
+    for (uint64_t j = 0; j < (uint64_t)pk; ++j) (*mat)[at + j] = (*mat)[pos[k - 1] + j];
+    for (uint64_t j = 0; j < slen[k]; ++j) (*mat)[at + (uint64_t)pk + j] = p[(uint64_t)used + spos[k] + j];
+    pos[k] = at;
+    len[k] = (uint32_t)total;
+    at += total;
+  }
+  rc = used + used2;
+done:
+  free(pre); free(spos); free(slen);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* column read                                                          */
 /* ------------------------------------------------------------------ */
 
@@ -569,6 +665,8 @@ int orc_read_column(orc_file* f, int col, int rg_b, int rg_e, orc_column* out) {
   uint32_t* idx = NULL;
   uint64_t* dvals = NULL;
   uint8_t* body = NULL;
+  uint8_t* mat = NULL;    /* DELTA_BYTE_ARRAY strings, materialised */
+  uint64_t mat_cap = 0;
   orc_dict dict;
   memset(&dict, 0, sizeof(dict));
 
@@ -750,6 +848,21 @@ int orc_read_column(orc_file* f, int col, int rg_b, int rg_e, orc_column* out) {
       } else if (enc == 5) { /* DELTA_BINARY_PACKED */
         if (type != 1 && type != 2) { rc = fail(ORC_EUNSUPPORTED, "DELTA_BINARY_PACKED on a non-integer column"); break; }
         if (orc_delta_decode(vals, vals_len, type == 1, nn, dvals) < 0) { rc = fail(ORC_ECORRUPT, "bad DELTA_BINARY_PACKED data"); break; }
+      } else if (enc == 6) { /* DELTA_LENGTH_BYTE_ARRAY */
+        if (type != 6) { rc = fail(ORC_EUNSUPPORTED, "DELTA_LENGTH_BYTE_ARRAY on a non-string column"); break; }
+        spos = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nn > 0 ? nn : 1));
+        slen = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+        if (orc_delta_length_decode(vals, vals_len, nn, spos, slen) < 0) { rc = fail(ORC_ECORRUPT, "bad DELTA_LENGTH_BYTE_ARRAY data"); free(spos); free(slen); break; }
+        sbase = vals;
+      } else if (enc == 7) { /* DELTA_BYTE_ARRAY */
+        if (type != 6) { rc = fail(ORC_EUNSUPPORTED, "DELTA_BYTE_ARRAY on a non-string column"); break; }
+        spos = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nn > 0 ? nn : 1));
+        slen = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(nn > 0 ? nn : 1));
+        if (orc_delta_byte_array_decode(vals, vals_len, nn, &mat, &mat_cap, spos, slen) < 0) { rc = fail(ORC_ECORRUPT, "bad DELTA_BYTE_ARRAY data"); free(spos); free(slen); break; }
+        sbase = mat;
+      } else if (enc == 9) { /* BYTE_STREAM_SPLIT */
+        if (type == 6) { rc = fail(ORC_EUNSUPPORTED, "BYTE_STREAM_SPLIT on a string column"); break; }
+        if (orc_byte_stream_split_decode(vals, vals_len, width_of(type), nn, dvals) < 0) { rc = fail(ORC_ECORRUPT, "BYTE_STREAM_SPLIT values truncated"); break; }
       } else {
         rc = fail(ORC_EUNSUPPORTED, "unsupported value encoding");
         break;
@@ -779,7 +892,7 @@ int orc_read_column(orc_file* f, int col, int rg_b, int rg_e, orc_column* out) {
     if (rc == ORC_OK && chunk_rows != f->rg_rows[g]) rc = fail(ORC_ECORRUPT, "pages do not cover the row group");
   }
   if (type == 6 && out->offsets) out->offsets[rows] = out->chars_len;
-  free(defs); free(idx); free(dvals); free(body);
+  free(defs); free(idx); free(dvals); free(body); free(mat);
   dict_clear(&dict);
   if (rc != ORC_OK) orc_column_free(out);
   return rc;

@@ -26,6 +26,12 @@ MUTANTS = {
     "delta_miniblock_width_index": ("int w = widths[m];", "int w = widths[0];"),
     "plain_width_int32_as_8": ("static int width_of(int type) { return type == 1 ? 4 : 8; }",
                                "static int width_of(int type) { return type == 1 ? 8 : 8; }"),
+    "bss_row_major": ("v |= (uint64_t)p[(uint64_t)b * (uint64_t)count + (uint64_t)k] << (8 * b);",
+                      "v |= (uint64_t)p[(uint64_t)k * (uint64_t)w + (uint64_t)b] << (8 * b);"),
+    "dlba_lengths_skipped": ("  uint64_t q = (uint64_t)used;\n  for (int64_t k = 0; k < count; ++k) {\n    int32_t l",
+                             "  uint64_t q = 0;\n  for (int64_t k = 0; k < count; ++k) {\n    int32_t l"),
+    "dba_prefix_from_first_string": ("(*mat)[at + j] = (*mat)[pos[k - 1] + j];", "(*mat)[at + j] = (*mat)[pos[0] + j];"),
+    "dba_suffix_offset": ("p[(uint64_t)used + spos[k] + j]", "p[spos[k] + j]"),
 }
 
 

@@ -5,7 +5,10 @@ arithmetic, and pyarrow's independent Snappy codec."""
 import itertools
 
 import numpy as np
+import io
+
 import pyarrow as pa
+import pyarrow.parquet as pq
 import pytest
 
 import oracle
@@ -240,3 +243,75 @@ def test_snappy_vs_pyarrow(data):
     codec = pa.Codec("snappy")
     comp = codec.compress(data, asbytes=True)
     assert oracle.snappy_decompress(comp, len(data) + 16) == data
+
+
+# ---------------------------------------------------------------------------
+# BYTE_STREAM_SPLIT, DELTA_LENGTH_BYTE_ARRAY, DELTA_BYTE_ARRAY
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fx", golden_io.fixtures("bss"), ids=lambda d: d["_name"])
+def test_byte_stream_split_golden(fx):
+    vals, used = oracle.byte_stream_split_decode(fx["bytes"], int(fx["width"]), int(fx["count"]))
+    assert [int(v) for v in vals] == [int(x) for x in fx["values"].split()]
+    assert used == len(fx["bytes"])
+
+
+def test_byte_stream_split_is_a_transpose():
+    """Brute force: the decode is the byte transpose of the value matrix
+    (numpy's own view of the little-endian bytes)."""
+    rng = np.random.default_rng(11)
+    for w, dt in ((4, np.uint32), (8, np.uint64)):
+        for n in (0, 1, 7, 100):
+            v = rng.integers(0, np.iinfo(dt).max, n, dtype=dt, endpoint=True)
+            enc = v.view(np.uint8).reshape(n, w).T.copy().tobytes()
+            got, used = oracle.byte_stream_split_decode(enc, w, n)
+            assert (got.astype(dt) == v).all() and used == n * w
+    with pytest.raises(oracle.OracleError):
+        oracle.byte_stream_split_decode(b"\x00" * 7, 4, 2)
+
+
+@pytest.mark.parametrize("fx", golden_io.fixtures("dlba"), ids=lambda d: d["_name"])
+def test_delta_length_golden(fx):
+    strs, used = oracle.delta_length_decode(fx["bytes"], int(fx["count"]))
+    assert strs == [s.encode() for s in fx["strings"].split()]
+    assert used == len(fx["bytes"])
+
+
+@pytest.mark.parametrize("fx", golden_io.fixtures("dba"), ids=lambda d: d["_name"])
+def test_delta_byte_array_golden(fx):
+    strs, used = oracle.delta_byte_array_decode(fx["bytes"], int(fx["count"]))
+    assert strs == [s.encode() for s in fx["strings"].split()]
+    assert used == len(fx["bytes"])
+
+
+def test_delta_byte_array_rejects_bad_prefixes():
+    """A first prefix length above 0, or a prefix longer than the previous
+    string, is corrupt (the golden stream with its prefix lengths edited)."""
+    fx = golden_io.fixtures("dba")[0]
+    b = bytearray(fx["bytes"])
+    b[4] = 0x02  # first prefix length 1 (zigzag 2)
+    with pytest.raises(oracle.OracleError):
+        oracle.delta_byte_array_decode(bytes(b), 4)
+    b = bytearray(fx["bytes"])
+    b[5] = 0x05  # min delta -3: prefix lengths 0 1 1 -2
+    with pytest.raises(oracle.OracleError):
+        oracle.delta_byte_array_decode(bytes(b), 4)
+
+
+def test_string_delta_encodings_vs_pyarrow():
+    """Random strings with long shared prefixes (sorted), empty strings and
+    repeats, written by pyarrow as DELTA_LENGTH_BYTE_ARRAY and
+    DELTA_BYTE_ARRAY: the oracle's column equals pyarrow's read."""
+    rng = np.random.default_rng(12)
+    words = sorted(("%s/%d/%s" % ("p" * int(rng.integers(0, 30)), int(rng.integers(0, 1000)),
+                                 "x" * int(rng.integers(0, 5)))).encode() for _ in range(5000))
+    words += [b"", b"", words[3], words[3]]
+    t = pa.table({"dlba": pa.array(words, type=pa.binary()), "dba": pa.array(words, type=pa.binary())})
+    bio = io.BytesIO()
+    pq.write_table(t, bio, use_dictionary=False, data_page_size=4096, data_page_version="2.0",
+                   column_encoding={"dlba": "DELTA_LENGTH_BYTE_ARRAY", "dba": "DELTA_BYTE_ARRAY"})
+    f = oracle.File(np.frombuffer(bio.getvalue(), dtype=np.uint8))
+    for c in range(2):
+        o = f.read(c)
+        ch, off = o["chars"].tobytes(), o["offsets"]
+        assert [ch[off[i]:off[i + 1]] for i in range(len(words))] == words
