@@ -25,6 +25,7 @@ _SO = os.path.join(_HERE, "libpqgen.so")
 
 INT32, INT64, DOUBLE, BYTE_ARRAY = 1, 2, 5, 6
 PLAIN, PLAIN_DICTIONARY, RLE, DELTA_BINARY_PACKED, RLE_DICTIONARY = 0, 2, 3, 5, 8
+DELTA_LENGTH_BYTE_ARRAY, DELTA_BYTE_ARRAY, BYTE_STREAM_SPLIT = 6, 7, 9
 UNIFORM, ZIPF, SORTED, DICTVALS, STRINGS, CONST, RUNS = 0, 1, 2, 3, 4, 5, 6
 UNCOMPRESSED, SNAPPY = 0, 1
 
@@ -52,6 +53,7 @@ class _Spec(ctypes.Structure):
         ("max_bp_groups", ctypes.c_int32), ("rle_min", ctypes.c_int32),
         ("ncols", ctypes.c_int32), ("nthreads", ctypes.c_int32),
         ("snappy_skip", ctypes.c_int32), ("index_width", ctypes.c_int32),
+        ("encoding_search", ctypes.c_int32), ("min_saving_pct", ctypes.c_int32),
     ]
 
 
@@ -89,6 +91,8 @@ class FileSpec:
     seed: int = 0x5EED0000
     snappy_literal_only: bool = False
     index_width: int = 0  # dictionary index bit width byte when wider than the minimum (legal; 0 = minimal)
+    encoding_search: bool = False  # per chunk, the candidate encoding of smallest encoded size
+    min_saving_pct: int = 0  # >0: chunks whose Snappy pages save no more than this stay uncompressed
     name: str = "custom"
 
     def _c(self, nthreads: int):
@@ -108,6 +112,8 @@ class FileSpec:
         sp.nthreads = nthreads
         sp.snappy_skip = 1 if self.snappy_literal_only else 0
         sp.index_width = self.index_width
+        sp.encoding_search = 1 if self.encoding_search else 0
+        sp.min_saving_pct = self.min_saving_pct
         arr = (_Col * len(self.cols))()
         for i, c in enumerate(self.cols):
             for f in dataclasses.fields(Col):

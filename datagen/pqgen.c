@@ -26,7 +26,7 @@
 /* ------------------------------------------------------------------ */
 
 enum { PT_INT32 = 1, PT_INT64 = 2, PT_DOUBLE = 5, PT_BYTE_ARRAY = 6 };
-enum { EN_PLAIN = 0, EN_PLAIN_DICT = 2, EN_RLE = 3, EN_DELTA = 5, EN_RLE_DICT = 8 };
+enum { EN_PLAIN = 0, EN_PLAIN_DICT = 2, EN_RLE = 3, EN_DELTA = 5, EN_DLBA = 6, EN_DBA = 7, EN_RLE_DICT = 8, EN_BSS = 9 };
 enum {
   D_UNIFORM = 0,  /* ints: U[lo, hi); double: U[dlo, dhi)                  */
   D_ZIPF = 1,     /* rank in [1, hi] with exponent zipf_s                    */
@@ -67,6 +67,8 @@ typedef struct {
   int32_t nthreads;
   int32_t snappy_skip;    /* 0: greedy matcher; 1: literal-only Snappy streams */
   int32_t index_width;    /* dictionary index bit width when wider than the minimum (0: minimal) */
+  int32_t encoding_search; /* 1: per chunk, the candidate encoding of smallest encoded size */
+  int32_t min_saving_pct;  /* >0: a chunk stays uncompressed unless Snappy saves more than this many percent */
 } pqg_spec;
 
 /* ------------------------------------------------------------------ */
@@ -564,6 +566,7 @@ typedef struct {
   int encs[4];
   int nencs;
   int64_t npages;
+  int codec;            /* the chunk's codec (a chunk whose compression saves too little is left uncompressed) */
 } chunk_out_t;
 
 typedef struct {
@@ -674,6 +677,53 @@ static void encode_values(buf_t* vb, const colgen_t* g, const rows_t* R, int64_t
     for (int64_t r = r0; r < r1; ++r) if (R->valid[r]) vals[k++] = R->v[r];
     delta_encode(vb, vals, (size_t)nnn, c->ptype == PT_INT32, sp->delta_block, sp->delta_mini);
     free(vals);
+  } else if (enc == EN_BSS) {
+    /* w streams of nnn bytes: stream b holds byte b of every value */
+    int w = ptype_width(c->ptype);
+    buf_reserve(vb, (size_t)(nnn * w));
+    uint8_t* o = vb->p + vb->n;
+    int64_t k = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+      if (!R->valid[r]) continue;
+      uint64_t x = R->v[r];
+      for (int b = 0; b < w; ++b) o[(size_t)b * (size_t)nnn + (size_t)k] = (uint8_t)(x >> (8 * b));
+      ++k;
+    }
+    vb->n += (size_t)(nnn * w);
+  } else if (enc == EN_DLBA || enc == EN_DBA) {
+    /* strings: lengths (DLBA) or prefix lengths against the previous string
+       of the page and suffix lengths (DBA) as DELTA_BINARY_PACKED, then the
+       (suffix) bytes */
+    uint64_t* pre = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnn > 0 ? nnn : 1));
+    uint64_t* len = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(nnn > 0 ? nnn : 1));
+    buf_t chars = {0};
+    uint8_t* prev = (uint8_t*)malloc(1u << 16);
+    uint8_t* cur = (uint8_t*)malloc(1u << 16);
+    int prev_len = 0;
+    int64_t k = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+      if (!R->valid[r]) continue;
+      int l = string_len(g, R->v[r]);
+      string_fill(g, R->v[r], cur, l);
+      int p = 0;
+      if (enc == EN_DBA) {
+        while (p < l && p < prev_len && cur[p] == prev[p]) ++p;
+      }
+      pre[k] = (uint64_t)p;
+      len[k] = (uint64_t)(l - p);
+      put_bytes(&chars, cur + p, (size_t)(l - p));
+      memcpy(prev, cur, (size_t)l);
+      prev_len = l;
+      ++k;
+    }
+    if (enc == EN_DBA) delta_encode(vb, pre, (size_t)nnn, 1, sp->delta_block, sp->delta_mini);
+    delta_encode(vb, len, (size_t)nnn, 1, sp->delta_block, sp->delta_mini);
+    put_bytes(vb, chars.p, chars.n);
+    buf_free(&chars);
+    free(pre);
+    free(len);
+    free(prev);
+    free(cur);
   }
 }
 
@@ -744,8 +794,56 @@ static int64_t rows_per_page(const colgen_t* g, const rows_t* R, int64_t r0, int
   return (int64_t)rp;
 }
 
+/* Encoded bytes of a whole chunk's values with encoding `enc` (one page; a
+   dictionary encoding counts its dictionary page), or -1 when `enc` does
+   not apply to the column. */
+static int64_t chunk_encoded_size(const colgen_t* g, const rows_t* R, int64_t nr, int enc, const pqg_spec* sp) {
+  const pqg_col* c = g->c;
+  buf_t vb = {0};
+  int64_t extra = 0;
+  if (enc == EN_RLE_DICT) {
+    dict_t d;
+    int64_t id_space = (c->ptype == PT_BYTE_ARRAY && c->dist == D_STRINGS && c->hi > 0) ? c->hi : 0;
+    dict_init(&d, id_space);
+    for (int64_t i = 0; i < nr; ++i) {
+      if (!R->valid[i] || dict_find(&d, R->v[i]) >= 0) continue;
+      int64_t eb = c->ptype == PT_BYTE_ARRAY ? 4 + string_len(g, R->v[i]) : ptype_width(c->ptype);
+      dict_insert(&d, R->v[i], R->v[i], eb);
+    }
+    int w = d.n <= 1 ? 0 : bits_needed((uint64_t)(d.n - 1));
+    extra = d.plain_bytes;
+    encode_values(&vb, g, R, 0, nr, enc, &d, w, sp);
+    dict_free(&d);
+  } else {
+    encode_values(&vb, g, R, 0, nr, enc, NULL, 0, sp);
+  }
+  int64_t n = (int64_t)vb.n + extra;
+  buf_free(&vb);
+  return n;
+}
+
+static void encode_chunk_with(job_t* J, int rg, int col, const pqg_spec* sp);
+
+/* One column chunk; with a minimum Snappy saving, a chunk whose compressed
+   pages save too little is written again uncompressed. */
 static void encode_chunk(job_t* J, int rg, int col) {
   const pqg_spec* sp = J->sp;
+  encode_chunk_with(J, rg, col, sp);
+  chunk_out_t* co = &J->outs[(size_t)rg * (size_t)sp->ncols + (size_t)col];
+  co->codec = sp->codec;
+  if (sp->codec == 1 && sp->min_saving_pct > 0) {
+    const int64_t comp = (int64_t)co->bytes.n, unc = co->uncompressed_total;
+    if ((double)comp > (double)unc * (1.0 - sp->min_saving_pct / 100.0)) {
+      pqg_spec plain = *sp;
+      plain.codec = 0;
+      buf_free(&co->bytes);
+      encode_chunk_with(J, rg, col, &plain);
+      co->codec = 0;
+    }
+  }
+}
+
+static void encode_chunk_with(job_t* J, int rg, int col, const pqg_spec* sp) {
   const pqg_col* c = &J->cols[col];
   const colgen_t* g = &J->gens[col];
   chunk_out_t* co = &J->outs[(size_t)rg * (size_t)sp->ncols + (size_t)col];
@@ -778,8 +876,27 @@ static void encode_chunk(job_t* J, int rg, int col) {
     R.v[i] = R.valid[i] ? x : 0;
   }
 
+  /* the chunk's encoding: the column's, or with the encoding search the
+     candidate of smallest encoded size (PLAIN first on ties) */
+  int cenc = c->encoding;
+  if (sp->encoding_search) {
+    int cands[4], nc = 0;
+    cands[nc++] = EN_PLAIN;
+    cands[nc++] = EN_RLE_DICT;
+    if (c->ptype == PT_BYTE_ARRAY) { cands[nc++] = EN_DLBA; cands[nc++] = EN_DBA; }
+    else {
+      if (c->ptype == PT_INT32 || c->ptype == PT_INT64) cands[nc++] = EN_DELTA;
+      cands[nc++] = EN_BSS;
+    }
+    int64_t best = -1;
+    for (int i = 0; i < nc; ++i) {
+      int64_t z = chunk_encoded_size(g, &R, nr, cands[i], sp);
+      if (z >= 0 && (best < 0 || z < best)) { best = z; cenc = cands[i]; }
+    }
+  }
+
   /* 2. dictionary (built in first-occurrence order) */
-  int is_dict = (c->encoding == EN_RLE_DICT || c->encoding == EN_PLAIN_DICT);
+  int is_dict = (cenc == EN_RLE_DICT || cenc == EN_PLAIN_DICT);
   dict_t dict;
   int64_t fallback = nr; /* rows >= fallback are PLAIN */
   int idx_w = 0;
@@ -815,7 +932,7 @@ static void encode_chunk(job_t* J, int rg, int col) {
       }
     }
     co->dict_page_rel = (int64_t)co->bytes.n;
-    int dict_enc = c->encoding == EN_PLAIN_DICT ? EN_PLAIN_DICT : EN_PLAIN;
+    int dict_enc = cenc == EN_PLAIN_DICT ? EN_PLAIN_DICT : EN_PLAIN;
     if (sp->codec == 1) {
       buf_t cb = {0};
       pqg_snappy_compress(dp.p, dp.n, &cb, sp->snappy_skip);
@@ -835,14 +952,14 @@ static void encode_chunk(job_t* J, int rg, int col) {
   /* 4. data pages */
   int64_t r = 0;
   if (is_dict && fallback > 0) {
-    int64_t rpp = rows_per_page(g, &R, 0, fallback, c->encoding, &dict, idx_w, sp);
+    int64_t rpp = rows_per_page(g, &R, 0, fallback, cenc, &dict, idx_w, sp);
     while (r < fallback) {
       int64_t e = r + rpp < fallback ? r + rpp : fallback;
-      emit_data_page(co, g, &R, r, e, c->encoding, &dict, idx_w, sp);
+      emit_data_page(co, g, &R, r, e, cenc, &dict, idx_w, sp);
       r = e;
     }
   }
-  int rest_enc = is_dict ? EN_PLAIN : c->encoding;
+  int rest_enc = is_dict ? EN_PLAIN : cenc;
   if (r < nr || nr == 0) {
     int64_t rpp = rows_per_page(g, &R, r, nr, rest_enc, NULL, 0, sp);
     if (nr == 0) emit_data_page(co, g, &R, 0, 0, rest_enc, NULL, 0, sp);
@@ -966,7 +1083,7 @@ uint8_t* pqg_write(const pqg_spec* sp, const pqg_col* cols, size_t* out_len) {
       for (int e = 0; e < co->nencs; ++e) put_uleb(&f, zz64(co->encs[e]));
       tw_list_begin(&t, 3, TT_BIN, 1);
       put_uleb(&f, strlen(nm)); put_bytes(&f, nm, strlen(nm));
-      tw_i32(&t, 4, sp->codec);
+      tw_i32(&t, 4, co->codec);
       tw_i64(&t, 5, co->num_values);
       tw_i64(&t, 6, co->uncompressed_total);
       tw_i64(&t, 7, (int64_t)co->bytes.n);

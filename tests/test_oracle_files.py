@@ -124,7 +124,24 @@ def _writer_specs():
             dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.1, hi=1000),
             dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.2, hi=300, str_min=8, str_max=44),
         ], num_rows=12_007, rg_rows=5_000, page_bytes=8 * dg.KiB, index_width=w, name=f"idxw{w}"))
-    return [small, wide, wide_v2, snap, snap_v2, edge, tiny_pages] + delta_shapes + wide_idx
+    # the string delta encodings and BYTE_STREAM_SPLIT (V1 and V2, Snappy)
+    new_encodings = []
+    for v, codec in ((1, dg.UNCOMPRESSED), (2, dg.SNAPPY)):
+        new_encodings.append(dg.FileSpec(cols=[
+            dg.Col(dg.BYTE_ARRAY, dg.DELTA_LENGTH_BYTE_ARRAY, True, dg.STRINGS, 0.1, hi=1000, str_min=0, str_max=60),
+            dg.Col(dg.BYTE_ARRAY, dg.DELTA_BYTE_ARRAY, True, dg.STRINGS, 0.1, hi=50, str_min=8, str_max=44),
+            dg.Col(dg.INT32, dg.BYTE_STREAM_SPLIT, True, dg.UNIFORM, 0.1, lo=-2**31, hi=2**31),
+            dg.Col(dg.INT64, dg.BYTE_STREAM_SPLIT, False, dg.UNIFORM, lo=-2**62, hi=2**62),
+            dg.Col(dg.DOUBLE, dg.BYTE_STREAM_SPLIT, True, dg.UNIFORM, 0.2),
+        ], num_rows=15_007, rg_rows=6_000, page_bytes=8 * dg.KiB, page_version=v, codec=codec,
+            name=f"newenc-v{v}-c{codec}"))
+    # the paper's writer presets: per-chunk encoding search, compression kept
+    # only where it saves more than 10%
+    search = dg.wide_table(30_000, 12_000, 16 * dg.KiB, codec=dg.SNAPPY)
+    search.encoding_search = True
+    search.min_saving_pct = 10
+    search.name = "wide-search"
+    return [small, wide, wide_v2, snap, snap_v2, edge, tiny_pages] + delta_shapes + wide_idx + new_encodings + [search]
 
 
 @pytest.mark.parametrize("spec", _writer_specs(), ids=lambda s: f"{s.name}-v{s.page_version}-c{s.codec}-p{s.page_bytes}")
@@ -239,3 +256,34 @@ def test_truncated_page_payload():
     with pytest.raises(oracle.OracleError):
         oracle.File(b2).read(1)
     f.read(1)
+
+
+def test_encoding_search_and_compression_threshold():
+    """With the encoding search, each chunk carries the candidate encoding of
+    smallest encoded size: the sorted INT64 keys DELTA_BINARY_PACKED, the
+    low-cardinality columns a dictionary, the 10^6-distinct random strings a
+    string delta encoding.  With a 10% threshold the random-value chunks of
+    the wide table stay uncompressed (Snappy saves almost nothing on them),
+    while a column of long runs stored PLAIN keeps its Snappy pages."""
+    spec = dg.wide_table(60_000, 60_000, 64 * dg.KiB, codec=dg.SNAPPY)
+    spec.encoding_search = True
+    spec.min_saving_pct = 10
+    buf = dg.write(spec)
+    md = pq.ParquetFile(pa.BufferReader(buf.tobytes())).metadata
+    cm = [md.row_group(0).column(c) for c in range(16)]
+    enc = [set(c.encodings) - {"RLE"} for c in cm]
+    assert "DELTA_BINARY_PACKED" in enc[6]
+    assert enc[7] & {"RLE_DICTIONARY", "PLAIN_DICTIONARY"} and enc[13] & {"RLE_DICTIONARY", "PLAIN_DICTIONARY"}
+    assert enc[15] & {"DELTA_LENGTH_BYTE_ARRAY", "DELTA_BYTE_ARRAY"}
+    assert all(c.compression == "UNCOMPRESSED" for c in cm)
+    # the smallest candidate really is smaller than the column's default
+    plain = dg.wide_table(60_000, 60_000, 64 * dg.KiB)
+    pmd = pq.ParquetFile(pa.BufferReader(dg.write(plain).tobytes())).metadata
+    assert cm[15].total_uncompressed_size < pmd.row_group(0).column(15).total_uncompressed_size
+    # a compressible chunk keeps Snappy under the same threshold
+    runs = dg.FileSpec(cols=[dg.Col(dg.INT64, dg.PLAIN, False, dg.RUNS, lo=0, hi=1 << 40, run_len=400),
+                             dg.Col(dg.DOUBLE, dg.PLAIN, False, dg.UNIFORM)],
+                       num_rows=50_000, rg_rows=50_000, page_bytes=64 * dg.KiB, codec=dg.SNAPPY, min_saving_pct=10)
+    rmd = pq.ParquetFile(pa.BufferReader(dg.write(runs).tobytes())).metadata
+    assert rmd.row_group(0).column(0).compression == "SNAPPY"
+    assert rmd.row_group(0).column(1).compression == "UNCOMPRESSED"
