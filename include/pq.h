@@ -260,11 +260,11 @@ typedef struct {
   const pq_column_out* outs;
 } pq_request;
 
-/* Work classes of the schedule: decoder kind (7: PLAIN / dictionary 4- and
-   8-byte values, DELTA_BINARY_PACKED, strings, strings of slot
-   dictionaries) x dictionary-index width (2: up to 12 bits, wider) x page
-   size (3: one tile, 2-16 tiles, more). */
-#define PQ_TUNE_CLASSES 42
+/* Work classes of the schedule: decoder kind (9: PLAIN / dictionary /
+   BYTE_STREAM_SPLIT 4- and 8-byte values, DELTA_BINARY_PACKED, strings,
+   strings of slot dictionaries) x dictionary-index width (2: up to 12 bits,
+   wider) x page size (3: one tile, 2-16 tiles, more). */
+#define PQ_TUNE_CLASSES 54
 #define PQ_FORM_BATCHED 0  /* one persistent decode launch over a work queue */
 #define PQ_FORM_PER_PAGE 1 /* one launch per page and decoder (the plain form) */
 typedef struct {
@@ -276,7 +276,7 @@ typedef struct {
   int32_t pad_;
   uint8_t tiles_per_unit[PQ_TUNE_CLASSES]; /* tiles a wave takes per queue grab, per
                                               class, 1..64 (0: 2) */
-  uint8_t pad2_[6];
+  uint8_t pad2_[2];
 } pq_tuning;
 
 /* The default schedule (every field at its default). */

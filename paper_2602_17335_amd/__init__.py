@@ -24,7 +24,7 @@ EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_i
            "pq_autotune_batch", "pq_scan_noalloc", "pq_server_create", "pq_server_submit", "pq_server_wait",
            "pq_server_release", "pq_server_stats_get", "pq_server_destroy", "pq_server_last_error")
 FORM_BATCHED, FORM_PER_PAGE = 0, 1
-TUNE_CLASSES = 42
+TUNE_CLASSES = 54
 
 
 class PqError(RuntimeError):
@@ -65,7 +65,7 @@ class Request(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("queues", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("tiles_per_unit", ctypes.c_uint8 * TUNE_CLASSES),
-                ("pad2_", ctypes.c_uint8 * 6)]
+                ("pad2_", ctypes.c_uint8 * 2)]
 
     def to_dict(self):
         return {"form": self.form, "waves_per_cu": self.waves_per_cu, "queues": self.queues,

@@ -27,9 +27,9 @@ __global__ void k_prep(const ColScan* cols, SegTable seg);
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, SegTable seg);
 __global__ void k_dict(const PageDev* pages, const uint32_t* strck, const DictSlot* slots, const DictWork* works,
                        uint32_t nworks, uint32_t* err);
-__global__ void k_prepass(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
+__global__ void k_prepass(uint8_t* ws, const ColScan* cols, SegTable seg, int mode, uint32_t* err);
 __global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, uint32_t* err);
-enum : int { FX_DICT = 1, FX_WIDE = 2 };
+enum : int { FX_DICT = 1, FX_WIDE = 2, FX_BSS = 4 };
 template <int KIND>
 __global__ void k_decode_fixed(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
 __global__ void k_decode_delta(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
@@ -244,7 +244,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
-constexpr int NKERN = 14;  // kernels with a profiling slot (each fixed-width instantiation has its own)
+constexpr int NKERN = 18;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
   const uint8_t* file = nullptr;
@@ -273,6 +273,7 @@ struct pq_file_s {
   // and on the host
   uint64_t* d_tpfx = nullptr;
   std::vector<uint64_t> tpfx;
+  uint64_t* d_tpfx2 = nullptr;  // second tile prefix (DELTA_LENGTH_BYTE_ARRAY length streams)
   // resident dictionaries: one DictSlot per chunk (device and host), their
   // decoded arrays in one arena
   DictSlot* d_dicts = nullptr;
@@ -293,12 +294,13 @@ struct pq_file_s {
 // Slot order; k_decode_fixed<K> for K = 0 PLAIN 4-byte, 1 dictionary 4-byte,
 // 2 PLAIN 8-byte, 3 dictionary 8-byte; k_decode_str<true> decodes the tiles
 // of slot dictionaries, k_decode_str<false> the others.
-enum { KP_SNAPPY, KP_DICT, KP_STR_TOTAL, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 4, KP_DELTA, KP_EDGES,
+enum { KP_SNAPPY, KP_DICT, KP_STR_TOTAL, KP_PREP, KP_FIXED0, KP_STR = KP_FIXED0 + 8, KP_DELTA, KP_EDGES,
        KP_STR_SLOTS, KP_SNAPPY_BLK, KP_BATCH };
 static const char* kKernelNames[NKERN] = {"k_snappy", "k_dict", "k_str_total", "k_prep",
                                           "k_decode_fixed<0>", "k_decode_fixed<1>", "k_decode_fixed<2>",
-                                          "k_decode_fixed<3>", "k_decode_str<false>", "k_decode_delta", "k_edges",
-                                          "k_decode_str<true>", "k_snappy_blk", "k_batch"};
+                                          "k_decode_fixed<3>", "k_decode_fixed<4>", "k_decode_fixed<5>",
+                                          "k_decode_fixed<6>", "k_decode_fixed<7>", "k_decode_str<false>",
+                                          "k_decode_delta", "k_edges", "k_decode_str<true>", "k_snappy_blk", "k_batch"};
 
 static hipEvent_t pool_get(pq_file f) {
   if (!f->event_pool.empty()) {
@@ -346,6 +348,7 @@ static void free_handle(pq_file f) {
   if (f->d_chunks) (void)hipFree(f->d_chunks);
   if (f->d_err) (void)hipFree(f->d_err);
   if (f->d_tpfx) (void)hipFree(f->d_tpfx);
+  if (f->d_tpfx2) (void)hipFree(f->d_tpfx2);
   if (f->d_dicts) (void)hipFree(f->d_dicts);
   if (f->d_dict_arena) (void)hipFree(f->d_dict_arena);
   delete f;
@@ -852,13 +855,13 @@ struct Plan {
   int64_t rows = 0;
   uint64_t ws_cols = 0, ws_which = 0, ws_total = 0;
   // launch lists
-  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[4], delta_segs, str_segs[2], edge_segs;
+  std::vector<Segment> snappy_segs, prep_segs, pre_segs, fixed_segs[8], delta_segs, str_segs[2], edge_segs;
   std::vector<int32_t> str_cols;    // string ColScan indices (k_str_total)
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
   uint32_t sblk_lanes = 0;
-  bool str_spread[2] = {false, false}, fixed_spread[4] = {false, false, false, false};  // columns interleaved wave by wave
-  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[4] = {0, 0, 0, 0}, delta_units = 0, str_units[2] = {0, 0},
+  bool str_spread[2] = {false, false}, fixed_spread[8] = {};  // columns interleaved wave by wave
+  uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[8] = {}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
 };
 
@@ -870,7 +873,7 @@ struct Plan {
 // `off` on) and which decoders its pages need.
 struct ColSetup {
   ColScan cs;
-  bool has_delta = false, has_plain = false, has_dict = false, has_slots = false;
+  bool has_delta = false, has_plain = false, has_dict = false, has_slots = false, has_bss = false;
   uint32_t nt = 0;        // tiles
   uint64_t sbytes = 0;    // decompressed bytes of its compressed pages
   uint32_t b0 = 0, b1 = 0;  // its Snappy blocks
@@ -900,6 +903,8 @@ void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint6
     const int e = f->pages[p].encoding;
     if (e == E_DELTA) {
       k.has_delta = true;
+    } else if (e == E_BSS && cs.type != T_BYTE_ARRAY) {
+      k.has_bss = true;
     } else if (e == E_PLAIN_DICT || e == E_RLE_DICT) {
       if (cs.type == T_BYTE_ARRAY && (f->dicts[f->pages[p].chunk].flags & DICT_SLOTS))
         k.has_slots = true;
@@ -957,8 +962,8 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
           P.delta_units += nt;
         }
         const int wide = cs.width == 8 ? FX_WIDE : 0;
-        for (int kind = 0; kind < 2; ++kind) {
-          if (!(kind ? k.has_dict : k.has_plain)) continue;
+        for (int kind : {0, (int)FX_DICT, (int)FX_BSS}) {
+          if (!(kind == FX_DICT ? k.has_dict : kind == FX_BSS ? k.has_bss : k.has_plain)) continue;
           const int K = kind | wide;
           P.fixed_segs[K].push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.fixed_units[K]});
           P.fixed_units[K] += nt;
@@ -1008,6 +1013,19 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
 
 }  // namespace
 
+using FixedKernel = void (*)(uint8_t*, const ColScan*, SegTable, uint32_t*);
+// The k_decode_fixed instantiation for kind K (FX_DICT | FX_WIDE | FX_BSS bits).
+static FixedKernel fixed_kernel(int K) {
+  switch (K) {
+    case 0: return k_decode_fixed<0>;
+    case FX_DICT: return k_decode_fixed<FX_DICT>;
+    case FX_WIDE: return k_decode_fixed<FX_WIDE>;
+    case FX_DICT | FX_WIDE: return k_decode_fixed<FX_DICT | FX_WIDE>;
+    case FX_BSS: return k_decode_fixed<FX_BSS>;
+    default: return k_decode_fixed<FX_BSS | FX_WIDE>;
+  }
+}
+
 // The workspace header (cleared error word, column table, string columns) in
 // one host-to-device copy, then decompression: the steps the open-time
 // prefix pass and a scan share.
@@ -1018,7 +1036,8 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, h
   if (!P.str_cols.empty()) memcpy(hdr.data() + P.ws_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size());
   HIP_OR(hipMemcpyAsync(ws, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
-                        &P.fixed_segs[3], &P.delta_segs, &P.str_segs[0], &P.str_segs[1], &P.edge_segs})
+                        &P.fixed_segs[3], &P.fixed_segs[4], &P.fixed_segs[6], &P.delta_segs, &P.str_segs[0], &P.str_segs[1],
+                        &P.edge_segs})
     if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
   if (P.snappy_waves) {
     ProfScope ps_(f, KP_SNAPPY, s);
@@ -1035,13 +1054,14 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, h
 }
 
 // The open-time prefix pass of a plan made with index = true: per-tile DELTA
-// sums and string byte counts into the workspace's tile arrays.
-static pq_status enqueue_index(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
+// sums and string byte counts into the workspace's tile arrays (mode 1: the
+// DELTA sums of DELTA_LENGTH_BYTE_ARRAY length streams only).
+static pq_status enqueue_index(pq_file f, Plan& P, uint8_t* ws, int mode, hipStream_t s) {
   pq_status st = enqueue_front(f, P, ws, f->d_err, s);
   if (st != PQ_OK) return st;
   if (P.pre_units) {
     hipLaunchKernelGGL(k_prepass, dim3((P.pre_units + 3) / 4), dim3(256), 0, s, ws,
-                       reinterpret_cast<ColScan*>(ws + P.ws_cols), make_segs(P.pre_segs), f->d_err);
+                       reinterpret_cast<ColScan*>(ws + P.ws_cols), make_segs(P.pre_segs), mode, f->d_err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
@@ -1063,10 +1083,10 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, make_segs(P.prep_segs));
     HIP_OR(hipGetLastError());
   }
-  for (int K = 0; K < 4; ++K) {
+  for (int K = 0; K < 8; ++K) {
     if (!P.fixed_units[K]) continue;
     ProfScope ps_(f, KP_FIXED0 + K, s);
-    auto kern = K == 0 ? k_decode_fixed<0> : K == 1 ? k_decode_fixed<1> : K == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
+    auto kern = fixed_kernel(K);
     hipLaunchKernelGGL(kern, dim3((P.fixed_units[K] + 3) / 4), dim3(256), 0, s, ws, d_cols,
                        make_segs(P.fixed_segs[K], P.fixed_spread[K]), err);
     HIP_OR(hipGetLastError());
@@ -1097,16 +1117,12 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
 // stays below INDEX_WS_CAP), then the prefix sum on the host.
 constexpr uint64_t INDEX_WS_CAP = 1ull << 30;
 
-static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
-  const uint64_t nt = f->total_tiles;
-  std::vector<uint64_t> val(nt, 0);
-  // the prefix pass reads the tile prefix of no column, but every ColScan
-  // carries the file's tables
+// One prefix pass (k_prepass in `mode`) over the tiles of every column that
+// `need` selects, in row-group batches; fills val[t] for their tiles.
+static pq_status prefix_pass(pq_file f, int mode, const std::vector<bool>& need, std::vector<uint64_t>& val,
+                             hipStream_t s) {
   for (int c = 0; c < f->ncols; ++c) {
-    bool need = f->cols[c].type == T_BYTE_ARRAY;
-    for (uint32_t p = f->chunk_page0[(size_t)c * f->nrg]; !need && p < f->chunk_page0[(size_t)(c + 1) * f->nrg]; ++p)
-      need = f->pages[p].kind != PAGE_DICT && f->pages[p].encoding == E_DELTA;
-    if (!need) continue;
+    if (!need[(size_t)c]) continue;
     for (int g0 = 0; g0 < f->nrg;) {
       int n = f->nrg - g0;
       Plan P;
@@ -1122,7 +1138,7 @@ static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
       if (cnt) {
         uint8_t* ws = nullptr;
         if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
-        pq_status st = enqueue_index(f, P, ws, s);
+        pq_status st = enqueue_index(f, P, ws, mode, s);
         if (st == PQ_OK && hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt,
                                           hipMemcpyDeviceToHost, s) != hipSuccess)
           st = fail(PQ_EHIP, "open: prefix pass copy");
@@ -1134,6 +1150,37 @@ static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
       g0 += n;
     }
   }
+  return PQ_OK;
+}
+
+static pq_status build_tile_prefix(pq_file f, hipStream_t s) {
+  const uint64_t nt = f->total_tiles;
+  std::vector<bool> need((size_t)f->ncols, false), need_dlba((size_t)f->ncols, false);
+  bool any_dlba = false;
+  for (int c = 0; c < f->ncols; ++c) {
+    need[(size_t)c] = f->cols[c].type == T_BYTE_ARRAY;
+    for (uint32_t p = f->chunk_page0[(size_t)c * f->nrg]; p < f->chunk_page0[(size_t)(c + 1) * f->nrg]; ++p) {
+      if (f->pages[p].kind == PAGE_DICT) continue;
+      if (f->pages[p].encoding == E_DELTA) need[(size_t)c] = true;
+      if (f->pages[p].encoding == E_DLBA && f->cols[c].type == T_BYTE_ARRAY) need_dlba[(size_t)c] = any_dlba = true;
+    }
+  }
+  // the DELTA sums of DELTA_LENGTH_BYTE_ARRAY length streams first: the
+  // string-byte pass needs their carries
+  if (any_dlba) {
+    std::vector<uint64_t> val2(nt, 0);
+    pq_status st = prefix_pass(f, 1, need_dlba, val2, s);
+    if (st != PQ_OK) return st;
+    std::vector<uint64_t> p2(nt + 1, 0);
+    for (uint64_t t = 0; t < nt; ++t) p2[t + 1] = p2[t] + val2[t];
+    HIP_OR(hipMalloc(&f->d_tpfx2, 8ull * (nt + 1)));
+    HIP_OR(hipMemcpy(f->d_tpfx2, p2.data(), 8ull * (nt + 1), hipMemcpyHostToDevice));
+    f->fd.tpfx2 = f->d_tpfx2;
+    f->device_bytes += 8ull * (nt + 1);
+  }
+  std::vector<uint64_t> val(nt, 0);
+  pq_status st = prefix_pass(f, 0, need, val, s);
+  if (st != PQ_OK) return st;
   f->tpfx.assign(nt + 1, 0);
   for (uint64_t t = 0; t < nt; ++t) f->tpfx[t + 1] = f->tpfx[t] + val[t];
   HIP_OR(hipMalloc(&f->d_tpfx, 8ull * (nt + 1)));
@@ -1277,13 +1324,14 @@ constexpr uint32_t DEFAULT_TPU = 2, DEFAULT_WPC = 8;
 constexpr uint32_t NUM_CUS = 256;  // MI355X compute units (8 XCDs x 32)
 // relative cost of one tile per decoder kind (roughly the bytes it moves),
 // used only to balance the queues
-constexpr uint64_t KIND_COST[TK_KINDS] = {8, 7, 16, 11, 9, 40, 40};
+constexpr uint64_t KIND_COST[TK_KINDS] = {8, 7, 16, 11, 9, 40, 40, 8, 16};
 
 // The decoder kind of a data page's tiles.
 uint32_t tile_kind(pq_file f, const PageDev& pg, const ColScan& cs) {
   const bool dict = pg.encoding == E_PLAIN_DICT || pg.encoding == E_RLE_DICT;
   if (cs.type == T_BYTE_ARRAY) return dict && (f->dicts[pg.chunk].flags & DICT_SLOTS) ? TK_STRSLOT : TK_STR;
   if (pg.encoding == E_DELTA) return TK_DELTA;
+  if (pg.encoding == E_BSS) return cs.width == 8 ? TK_BSS8 : TK_BSS4;
   if (pg.encoding != E_PLAIN && !dict) return TK_FIXED1;  // its decoder reports the encoding as unsupported
   return (dict ? 1u : 0u) | (cs.width == 8 ? 2u : 0u);
 }
@@ -1596,10 +1644,10 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
       std::vector<Segment> one{Segment{r.cs, r.t0, r.t1, 0}};
       const uint32_t wg = (r.t1 - r.t0 + 3) / 4;
       switch (r.kind) {
-        case TK_FIXED0: case TK_FIXED1: case TK_FIXED2: case TK_FIXED3: {
-          ProfScope ps_(prof, KP_FIXED0 + (int)r.kind, s);
-          auto kern = r.kind == 0 ? k_decode_fixed<0> : r.kind == 1 ? k_decode_fixed<1> : r.kind == 2 ? k_decode_fixed<2> : k_decode_fixed<3>;
-          hipLaunchKernelGGL(kern, dim3(wg), dim3(256), 0, s, ws, d_cols, make_segs(one), err);
+        case TK_FIXED0: case TK_FIXED1: case TK_FIXED2: case TK_FIXED3: case TK_BSS4: case TK_BSS8: {
+          const int K = r.kind == TK_BSS4 ? FX_BSS : r.kind == TK_BSS8 ? (FX_BSS | FX_WIDE) : (int)r.kind;
+          ProfScope ps_(prof, KP_FIXED0 + K, s);
+          hipLaunchKernelGGL(fixed_kernel(K), dim3(wg), dim3(256), 0, s, ws, d_cols, make_segs(one), err);
           break;
         }
         case TK_DELTA: {

@@ -10,7 +10,8 @@ namespace pqk {
 // format constants (Apache Parquet format description)
 // ---------------------------------------------------------------------------
 enum : int32_t { T_INT32 = 1, T_INT64 = 2, T_DOUBLE = 5, T_BYTE_ARRAY = 6 };
-enum : int32_t { E_PLAIN = 0, E_PLAIN_DICT = 2, E_RLE = 3, E_DELTA = 5, E_RLE_DICT = 8 };
+enum : int32_t { E_PLAIN = 0, E_PLAIN_DICT = 2, E_RLE = 3, E_DELTA = 5, E_DLBA = 6, E_DBA = 7, E_RLE_DICT = 8,
+                 E_BSS = 9 };
 enum : int32_t { PAGE_DATA = 0, PAGE_INDEX = 1, PAGE_DICT = 2, PAGE_DATA_V2 = 3 };
 
 // device error codes (first error wins; stored as code | (where << 8))
@@ -118,7 +119,8 @@ struct PageDev {
   uint32_t blocks_at;
   uint32_t dict_maxlen;  // dictionary pages of strings: length of the longest entry
   uint32_t sblk_begin;   // compressed pages: first entry of the page in the Snappy block index
-  uint32_t pad2_;
+  uint32_t chars_at;     // DELTA_LENGTH_BYTE_ARRAY pages: value-stream offset of the chars
+                         // (the end of the lengths' DELTA_BINARY_PACKED stream)
 };
 // Snappy block index: a compressed page's output is cut into SNAP_BLOCK-byte
 // blocks; entry b holds the stream offset of the element that starts block
@@ -190,6 +192,8 @@ struct FileDev {
   const Ck* ckv;               // value-stream checkpoints, NSUB per tile
   const uint32_t* strck;       // string checkpoints
   const uint64_t* tpfx;        // tile prefix (tiles + 1 entries)
+  const uint64_t* tpfx2;       // second tile prefix: DELTA sums of the length streams of
+                               // DELTA_LENGTH_BYTE_ARRAY tiles (NULL when the file has none)
   uint32_t* sblk;              // Snappy block index (written by the open-time pass)
   const uint32_t* sblk_page;   // page of each Snappy block
   const DictSlot* dicts;       // resident dictionaries, one per chunk (col * nrg + rg)
@@ -240,7 +244,8 @@ struct SegTable {
 // The persistent kernel takes units from NQUEUE work queues, queue q first
 // for the workgroups dispatched to XCD q (workgroup i runs on XCD i mod 8),
 // then the others.
-enum : uint32_t { TK_FIXED0 = 0, TK_FIXED1, TK_FIXED2, TK_FIXED3, TK_DELTA, TK_STR, TK_STRSLOT, TK_KINDS };
+enum : uint32_t { TK_FIXED0 = 0, TK_FIXED1, TK_FIXED2, TK_FIXED3, TK_DELTA, TK_STR, TK_STRSLOT, TK_BSS4, TK_BSS8,
+                  TK_KINDS };
 struct BUnit {
   uint32_t cs, t0, t1, kind;
 };

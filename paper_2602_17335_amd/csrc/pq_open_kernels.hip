@@ -39,7 +39,11 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
     } else if (h.type == PAGE_DATA || h.type == PAGE_DATA_V2) {
       if (!h.has_sub || h.nv < 0) { set_err(err, ERR_HEADER, q); return; }
       bool enc_ok = h.enc == E_PLAIN || h.enc == E_PLAIN_DICT || h.enc == E_RLE_DICT ||
-                    (h.enc == E_DELTA && (c.type == T_INT32 || c.type == T_INT64));
+                    (h.enc == E_DELTA && (c.type == T_INT32 || c.type == T_INT64)) ||
+                    (h.enc == E_BSS && c.type != T_BYTE_ARRAY) ||
+                    ((h.enc == E_DLBA || h.enc == E_DBA) && c.type == T_BYTE_ARRAY);
+      // (DELTA_BYTE_ARRAY pages open, and are reported as unsupported only
+      // when a scan selects their column)
       if (!enc_ok) { set_err(err, ERR_UNSUPPORTED, q); return; }
       if (h.type == PAGE_DATA_V2) {
         if (h.rep_len != 0) { set_err(err, ERR_UNSUPPORTED, q); return; }
@@ -71,7 +75,7 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
       p.def_off = 0; p.val_off = 0; p.val_len = 0;
       p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
       p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u; p.dict_maxlen = 0;
-      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0;
+      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.sblk_begin = 0; p.chars_at = 0;
       pages[page_base[q] + n] = p;
     }
     ++n;
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   r.init(vbase, lim_of(vbase), win);
   const uint64_t vend = val_off + val_len;
   const int enc = pg.encoding;
-  if (enc == E_PLAIN && ch.type != T_BYTE_ARRAY) {
+  if ((enc == E_PLAIN || enc == E_BSS) && ch.type != T_BYTE_ARRAY) {
     uint64_t w = ch.type == T_INT32 ? 4 : 8;
     if ((uint64_t)nonnull * w > val_len) { set_err(err, ERR_VALUES, p); return; }
   } else if (enc == E_PLAIN) {
@@ -506,7 +510,9 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
         have = true;
       }
     }
-  } else if (enc == E_DELTA) {
+  } else if (enc == E_DELTA || (enc == E_DLBA && ch.type == T_BYTE_ARRAY)) {
+    // DELTA_BINARY_PACKED values, or the lengths of DELTA_LENGTH_BYTE_ARRAY
+    // strings (32-bit), whose chars follow the stream
     bool bad = false;
     uint64_t q = val_off;
     uint64_t B = br_uleb(r, q, vend, bad), M = br_uleb(r, q, vend, bad), total = br_uleb(r, q, vend, bad);
@@ -516,7 +522,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       return;
     }
     if (M > 16 || B > 65536) { set_err(err, ERR_UNSUPPORTED, p); return; }
-    const uint32_t maxw = ch.type == T_INT32 ? 32 : 64;
+    const uint32_t maxw = ch.type == T_INT64 ? 64 : 32;
     const uint64_t per = B / M;
     pg.enc_w = (uint32_t)B;
     pg.enc_m = (uint32_t)M;
@@ -586,6 +592,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       if (body > vend - q) { set_err(err, ERR_DELTA, p); return; }
       q += body;
     }
+    pg.chars_at = (uint32_t)(q - val_off);
   }
   pages[p] = pg;
 }

@@ -758,7 +758,7 @@ __device__ __forceinline__ void delta_mini(const DBlk& k, uint32_t m, uint32_t p
 template <class Src>
 __device__ __forceinline__ bool delta_terms_in(const WaveTile& c, const Src& s, const Ck* ckv, uint32_t lane,
                                                uint64_t* D) {
-  const bool is32 = c.cs.type == T_INT32;
+  const bool is32 = c.cs.type != T_INT64;  // INT32 values, or DELTA_LENGTH_BYTE_ARRAY lengths
   const uint32_t maxw = is32 ? 32 : 64;
   const uint32_t B = c.pg.enc_w, M = c.pg.enc_m, per = B / M;
 #pragma unroll
@@ -1829,8 +1829,10 @@ __global__ void k_str_total(const ColScan* __restrict__ cols, const int32_t* __r
 // ---------------------------------------------------------------------------
 // k_prepass: per-tile auxiliaries (DELTA sums, string byte counts)
 // ---------------------------------------------------------------------------
+// mode 1: only the DELTA sums of DELTA_LENGTH_BYTE_ARRAY length streams (the
+// second tile prefix, which mode 0 then reads for their carries)
 __global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const ColScan* __restrict__ cols,
-                                                SegTable seg, uint32_t* __restrict__ err) {
+                                                SegTable seg, int mode, uint32_t* __restrict__ err) {
   __shared__ uint32_t s_idx[NWAVES][PADN];
   WaveTile c;
   if (!wave_tile(seg, cols, ws, c)) return;
@@ -1841,6 +1843,48 @@ __global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const 
       gptr(reinterpret_cast<uint64_t*>(ws + c.cs.ws_tile_aux)) + (c.t - c.cs.tile_begin);
   const bool is_str = c.cs.type == T_BYTE_ARRAY;
   const int enc = c.pg.encoding;
+  if (is_str && enc == E_DLBA) {
+    // DELTA_LENGTH_BYTE_ARRAY: the tile's length terms; mode 1 sums them, mode
+    // 0 sums the lengths (the terms' prefix on top of the tile's carry)
+    uint64_t D[LPER];
+    bool ok = c.td.nn == 0 || delta_terms(c, ckv, lane, D);
+    if (c.td.nn == 0) {
+#pragma unroll
+      for (int q = 0; q < LPER; ++q) D[q] = 0;
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < LPER; ++q) {
+      acc += D[q];
+      D[q] = acc;
+    }
+    uint64_t tot;
+    if (mode == 1) {
+      tot = wave_read_u64(wave_incl_scan_u64(acc), 63);
+    } else {
+      const uint64_t carry = sload(c.cs.fd.tpfx2 + c.t) - sload(c.cs.fd.tpfx2 + c.pg.tile_begin);
+      const uint64_t ex = wave_incl_scan_u64(acc) - acc;
+      uint64_t sum = 0;
+#pragma unroll
+      for (int q = 0; q < LPER; ++q) {
+        if (lane * LPER + q >= c.td.nn) continue;
+        const uint32_t l = (uint32_t)(carry + ex + D[q]);
+        if (l >> 31) ok = false;  // a negative length
+        sum += l;
+      }
+      tot = wave_read_u64(wave_incl_scan_u64(sum), 63);
+    }
+    if (__ballot(!ok)) {
+      if (lane == 0) set_err(err, ERR_STRING, c.td.page);
+      return;
+    }
+    if (lane == 0) *aux = tot;
+    return;
+  }
+  if (mode == 1) {
+    if (lane == 0) *aux = 0;
+    return;
+  }
   if (is_str && enc == E_PLAIN) {
     if (lane == 0) *aux = (uint64_t)c.td.val_skip - c.td.val_pos - 4ull * c.td.nn;
     return;
@@ -1901,14 +1945,17 @@ __global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const 
 // ---------------------------------------------------------------------------
 // k_decode_fixed: PLAIN and dictionary INT32 / INT64 / DOUBLE tiles
 // ---------------------------------------------------------------------------
-// One instantiation per kind of tile (FX_DICT: dictionary pages, else PLAIN;
-// FX_WIDE: 8-byte values), so that each is compiled for its own register
+// One instantiation per kind of tile (FX_DICT: dictionary pages; FX_BSS:
+// BYTE_STREAM_SPLIT pages, value k's byte b at stream byte b * (the page's
+// non-null values) + k; else PLAIN; FX_WIDE: 8-byte values), so that each is
+// compiled for its own register
 // needs; a wave whose tile is of another kind leaves at once.
-enum : int { FX_DICT = 1, FX_WIDE = 2 };
+enum : int { FX_DICT = 1, FX_WIDE = 2, FX_BSS = 4 };
 template <int KIND, bool LOOP>
 __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restrict__ ws, uint32_t* __restrict__ err,
                                            lds_u32* wl) {
   constexpr bool is_dict = KIND & FX_DICT;
+  constexpr bool is_bss = KIND & FX_BSS;
   constexpr bool w4 = !(KIND & FX_WIDE);
   // checkpoint words first: their loads overlap the tile's metadata loads
   const uint32_t lck = c.cs.fd.ckl[(size_t)c.t * NLCK + (lane_id<LOOP>() & 63)];
@@ -1917,11 +1964,12 @@ __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restric
   if (enc == E_DELTA) return;  // k_decode_delta
   const uint32_t lane = lane_id<LOOP>() & 63;
   const bool dict_page = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
-  if (!dict_page && enc != E_PLAIN) {
+  const bool bss_page = enc == E_BSS;
+  if (!dict_page && !bss_page && enc != E_PLAIN) {
     if (is_dict && lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);  // reported once
     return;
   }
-  if (dict_page != is_dict || (c.cs.width == 4) != w4) return;  // another instantiation's tile
+  if (dict_page != is_dict || bss_page != is_bss || (c.cs.width == 4) != w4) return;  // another instantiation's tile
   uint32_t vw;
   if (!uniform_bool(tile_validity(c, lck, lane, err, ws, vw))) return;
   lds_u32* idx = wl;
@@ -1975,6 +2023,16 @@ __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restric
       for (int i = 0; i < NGROUPS; ++i) kk[i] = idx[pad(kk[i])];
 #pragma unroll
       for (int i = 0; i < NGROUPS; ++i) x[i] = reinterpret_cast<glb_u32*>(ent)[kk[i]];
+    } else if constexpr (is_bss) {
+      const uint64_t nnp = c.pg.nonnull;
+      glb_u8* b0 = vs.base + vs.origin + k0;
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v |= (uint32_t)b0[(uint64_t)b * nnp + kk[i]] << (8 * b);
+        x[i] = v;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < NGROUPS; ++i) x[i] = vs.u32((k0 + kk[i]) * 4);
@@ -1995,6 +2053,16 @@ __device__ __forceinline__ void tile_fixed(const WaveTile& c, uint8_t* __restric
       for (int i = 0; i < NGROUPS; ++i) kk[i] = idx[pad(kk[i])];
 #pragma unroll
       for (int i = 0; i < NGROUPS; ++i) x[i] = reinterpret_cast<glb_u64*>(ent)[kk[i]];
+    } else if constexpr (is_bss) {
+      const uint64_t nnp = c.pg.nonnull;
+      glb_u8* b0 = vs.base + vs.origin + k0;
+#pragma unroll
+      for (int i = 0; i < NGROUPS; ++i) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) v |= (uint64_t)b0[(uint64_t)b * nnp + kk[i]] << (8 * b);
+        x[i] = v;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < NGROUPS; ++i) x[i] = vs.u64((k0 + kk[i]) * 8);
@@ -2131,6 +2199,7 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
   const uint32_t lane = lane_id<LOOP>() & 63;
   const int enc = c.pg.encoding;
   const bool is_plain = !SLOTS && enc == E_PLAIN;
+  const bool is_dlba = !SLOTS && enc == E_DLBA;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   DictSlot sl;
   bool slot_tile = false;
@@ -2139,7 +2208,7 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
     slot_tile = sl.page != ~0u && (sl.flags & DICT_SLOTS);
   }
   if (slot_tile != SLOTS) return;  // the other instantiation decodes this tile
-  if (!is_plain && !is_dict) {
+  if (!is_plain && !is_dict && !is_dlba) {
     if (lane == 0) set_err(err, ERR_UNSUPPORTED, c.td.page);
     return;
   }
@@ -2175,6 +2244,54 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
     }
     if (lane == 0) u[pad(td.nn)] = td.val_skip;
     if (__ballot(bad)) {
+      if (lane == 0) set_err(err, ERR_STRING, td.page);
+      return;
+    }
+  } else if (is_dlba) {
+    // u[pad(j)]: stream position of the first char of the tile's value j,
+    // j <= nn.  Lengths: the page's DELTA_BINARY_PACKED length stream, whose
+    // carry into this tile comes from the second tile prefix; positions: the
+    // page's chars start, the string bytes of the page's earlier tiles (tile
+    // prefix), then a scan of the lengths (lane l holds values 16 l ..)
+    sbase = (glb_u8*)c.st.vbase;
+    soff = c.st.voff;
+    const uint64_t vlen = c.st.vend - c.st.voff;
+    uint64_t D[LPER];
+    bool ok = td.nn == 0 || delta_terms(c, c.cs.fd.ckv, lane, D);
+    if (td.nn == 0) {
+#pragma unroll
+      for (int q = 0; q < LPER; ++q) D[q] = 0;
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < LPER; ++q) {
+      acc += D[q];
+      D[q] = acc;
+    }
+    const uint64_t carry = sload(c.cs.fd.tpfx2 + c.t) - sload(c.cs.fd.tpfx2 + c.pg.tile_begin);
+    const uint64_t ex = wave_incl_scan_u64(acc) - acc;
+    const uint32_t j0 = lane * LPER;
+    uint64_t lsum = 0;
+#pragma unroll
+    for (int q = 0; q < LPER; ++q) {
+      const uint32_t l = j0 + q < td.nn ? (uint32_t)(carry + ex + D[q]) : 0u;
+      if (l >> 31) ok = false;
+      D[q] = l;
+      lsum += l;
+    }
+    const uint64_t incl = wave_incl_scan_u64(lsum);
+    const uint64_t total = wave_read_u64(incl, 63);
+    const uint64_t* tp = c.cs.fd.tpfx;
+    const uint64_t cbase = (uint64_t)c.pg.chars_at + (sload(tp + c.t) - sload(tp + c.pg.tile_begin));
+    if (cbase + total > vlen || cbase + total >= 0xffffffffull) ok = false;
+    uint64_t at = cbase + incl - lsum;
+#pragma unroll
+    for (int q = 0; q < LPER; ++q) {
+      if (j0 + q < td.nn) u[pad(j0 + q)] = (uint32_t)at;
+      at += D[q];
+    }
+    if (lane == 0) u[pad(td.nn)] = (uint32_t)(cbase + total);
+    if (__ballot(!ok)) {
       if (lane == 0) set_err(err, ERR_STRING, td.page);
       return;
     }
@@ -2331,12 +2448,13 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
   if (td.nn == 0) {
 #pragma unroll
     for (int g = 0; g < NGROUPS; ++g) { pos[g] = 0; len[g] = 0; }
-  } else if (is_plain) {
+  } else if (is_plain || is_dlba) {
+    const uint32_t hdr = is_plain ? 4u : 0u;  // PLAIN: a u32 length before each string
 #pragma unroll
     for (int g = 0; g < NGROUPS; ++g) {
       const uint32_t q0 = u[pad(kk[g])], q1 = u[pad(kk[g] + 1)];
-      pos[g] = q0 + 4;
-      len[g] = q1 - q0 - 4;
+      pos[g] = q0 + hdr;
+      len[g] = q1 - q0 - hdr;
     }
   } else {
 #pragma unroll
@@ -2488,6 +2606,8 @@ __global__ __launch_bounds__(WG) void k_batch(uint8_t* __restrict__ ws, const Co
           case TK_FIXED1: tile_fixed<FX_DICT, true>(c, ws, err, wl); break;
           case TK_FIXED2: tile_fixed<FX_WIDE, true>(c, ws, err, wl); break;
           case TK_FIXED3: tile_fixed<FX_DICT | FX_WIDE, true>(c, ws, err, wl); break;
+          case TK_BSS4: tile_fixed<FX_BSS, true>(c, ws, err, wl); break;
+          case TK_BSS8: tile_fixed<FX_BSS | FX_WIDE, true>(c, ws, err, wl); break;
           case TK_DELTA: tile_delta<true>(c, ws, err, wl); break;
           case TK_STR: tile_str<false, true>(c, ws, err, wl); break;
           default: tile_str<true, true>(c, ws, err, wl); break;
@@ -2504,5 +2624,7 @@ template __global__ void k_decode_fixed<0>(uint8_t*, const ColScan*, SegTable, u
 template __global__ void k_decode_fixed<FX_DICT>(uint8_t*, const ColScan*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_WIDE>(uint8_t*, const ColScan*, SegTable, uint32_t*);
 template __global__ void k_decode_fixed<FX_DICT | FX_WIDE>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_BSS>(uint8_t*, const ColScan*, SegTable, uint32_t*);
+template __global__ void k_decode_fixed<FX_BSS | FX_WIDE>(uint8_t*, const ColScan*, SegTable, uint32_t*);
 
 }  // namespace pqk
