@@ -319,6 +319,59 @@ def bench_serve(nfiles, max_bytes, budget_bytes, qps_list, seconds, log, seed=0x
             "batches": st["batches"], "shared_results": st["cache_hits"], "evictions": st["evictions"]}
 
 
+def bench_presets(rows, reps, log):
+    """The paper's file-configuration sequence (Sec. 3, Insights 1-4, its
+    ablation of effective bandwidth) on the wide table with the file in HBM:
+    for each cumulative step, the encoded file size, the compression ratio
+    (decoded bytes / encoded bytes), the median GPU scan time of all 16
+    columns, and the effective bandwidth (decoded bytes / scan time).  With
+    storage instead of HBM the file would arrive at a link rate R; the
+    'at_link' figures model an overlapped reader, decoded bytes /
+    max(scan time, file bytes / R), for R of the paper's 1-4 SSDs (about 6.5
+    GB/s each) and of a PCIe 5 x16 link (64 GB/s)."""
+    import torch
+    import datagen as dg
+    import paper_2602_17335_amd as pqs
+    out = []
+    for name in dg.PRESETS:
+        spec = dg.preset(name, rows)
+        data = dg.write(spec, nthreads=min(16, os.cpu_count() or 1))
+        buf, n = pqs.to_device(data)
+        del data
+        f = pqs.DeviceFile(buf, n)
+        st = f.stats()
+        mask, rg_end, ws, outs, tens = f.allocate(list(range(16)))
+        dec = decoded_bytes(tens, {c: f.column_info(c).type for c in range(16)})
+        v = []
+        for i in range(reps + 1):
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record()
+            f.scan_into(mask, 0, rg_end, outs, ws)
+            z.record()
+            torch.cuda.synchronize()
+            if i:
+                v.append(a.elapsed_time(z))
+        f.check(ws)
+        v.sort()
+        ms = v[len(v) // 2]
+        encs = sorted({e for c in range(16) for e in range(32) if (f.column_encodings(c) >> e) & 1})
+        row = {"preset": name, "file_bytes": n, "decoded_bytes": dec, "ratio": round(dec / n, 3),
+               "pages": st.pages, "row_groups": f.num_row_groups, "compressed_pages": st.compressed_pages,
+               "encodings": encs, "scan_ms": round(ms, 3), "effective_gbps": round(dec / ms / 1e6, 1),
+               "at_link_gbps": {str(r): round(dec / max(ms / 1e3, n / (r * 1e9)) / 1e9, 1)
+                                for r in (6.5, 13.0, 26.0, 64.0)}}
+        log(f"preset {name:16s} {n / 1e9:6.3f} GB file, ratio {row['ratio']:5.2f}, scan {ms:7.2f} ms, "
+            f"{row['effective_gbps']:7.1f} GB/s effective")
+        out.append(row)
+        del ws, outs, tens
+        f.close()
+        del buf
+        torch.cuda.empty_cache()
+    return {"workload": f"wide16 table, {rows:,} rows, 16 OPTIONAL columns with 10% nulls, all columns scanned",
+            "steps": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +394,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=64, help="device-memory budget of the server, GB")
     ap.add_argument("--serve-qps", default="200,1000,4000", help="offered request rates")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--preset-rows", type=int, default=16_000_000,
+                    help="rows of the file-configuration sequence (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
@@ -472,6 +527,10 @@ def main():
         torch.cuda.empty_cache()
         batch = bench_batch(args.batch_files, max(5, args.steps // 2), log)
 
+    presets = None
+    if args.preset_rows > 0:
+        presets = bench_presets(args.preset_rows, 5, log)
+
     serve = None
     if args.serve_files > 0:
         serve = bench_serve(args.serve_files, args.serve_max_mb * 1_000_000, args.serve_budget_gb << 30,
@@ -499,6 +558,7 @@ def main():
         "roofline": roof,
         "batched_vs_plain": batch,
         "serving": serve,
+        "file_configurations": presets,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -336,3 +336,37 @@ def serve_catalog(nfiles: int = 256, min_bytes: int = 1_000_000, max_bytes: int 
         sp.name = f"serve{i}"
         out.append(sp)
     return out
+
+
+# The paper's file-configuration steps (Sec. 3) on the wide table, cumulative
+# as in its ablation: the DuckDB-like baseline, then more pages per chunk
+# (Insight 1), million-row row groups (Insight 2), the per-chunk encoding
+# search (Insight 3) and compression kept only where it saves more than 10%
+# (Insight 4).
+PRESETS = ("baseline", "+pages", "+rowgroups", "+encodings", "+no_compression")
+
+
+def preset(name: str, rows: int = 16_000_000, seed: int = 0x5EED0005) -> FileSpec:
+    """The wide table under one step of the paper's configuration sequence.
+    baseline: 122,880-row row groups, one page per column chunk, V1 pages,
+    PLAIN or dictionary encodings only (the sorted key column PLAIN),
+    Snappy everywhere.  +pages: pages of about 1/100 of a chunk (4 KiB).
+    +rowgroups: 10M-row row groups with 256 KiB pages (still >= 100 pages
+    per chunk).  +encodings: every chunk takes its smallest candidate
+    encoding (V2 encodings included).  +no_compression: Snappy is kept only
+    where it saves more than 10%."""
+    steps = PRESETS[: PRESETS.index(name) + 1]
+    cols = wide_cols()
+    cols[6] = dataclasses.replace(cols[6], encoding=PLAIN)  # V1 defaults: no DELTA
+    spec = FileSpec(cols=cols, num_rows=rows, rg_rows=122_880, page_bytes=1 << 30, codec=SNAPPY,
+                    seed=seed, name=f"preset {name}")
+    if "+pages" in steps:
+        spec.page_bytes = 4 * KiB
+    if "+rowgroups" in steps:
+        spec.rg_rows = 10_000_000
+        spec.page_bytes = 256 * KiB
+    if "+encodings" in steps:
+        spec.encoding_search = True
+    if "+no_compression" in steps:
+        spec.min_saving_pct = 10
+    return spec
