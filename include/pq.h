@@ -208,6 +208,33 @@ pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end
 pq_status pq_scan_noalloc(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
                           int32_t n_outs, pq_stream stream);
 
+/*
+ * A file held in host memory, scanned with its row groups streamed to the
+ * device (Sec. 4.1: an overlapped reader decodes row group by row group
+ * while the next row group is transferred, instead of waiting for the whole
+ * file).  pq_open_host copies the file to a temporary device buffer for the
+ * open-time passes (page table, tile index, dictionaries -- all copied into
+ * the handle -- and tile prefix) and frees it; host_buf is borrowed until
+ * pq_close and should be pinned (hipHostMalloc, or a pinned torch tensor),
+ * or the copies cannot overlap.  pq_plan of such a handle includes in
+ * workspace_bytes two staging slots (each the largest row group's selected
+ * chunks) and a column table per row group.  pq_scan, pq_scan_noalloc and
+ * the batch calls refuse such a handle (PQ_EINVAL).
+ */
+pq_status pq_open_host(const void* host_buf, uint64_t len, pq_stream stream, pq_file* out);
+
+/* The scan of a host-resident file (Sec. 4.1, overlapped reading): the
+   selected column chunks of each row group are copied into a staging slot
+   of the workspace on `copy_stream`, while `stream` decompresses and
+   decodes the previous row group from the other slot; events order each
+   slot's reuse.  Outputs, errors and pq_scan_check as for pq_scan.  With
+   the two streams equal nothing overlaps (still correct); every copy is waited on by `stream`, so the scan
+   is complete once `stream` is.  Calls on one handle are issued from one
+   host thread at a time (the handle keeps the slot events). */
+pq_status pq_scan_streamed(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
+                           int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream copy_stream,
+                           pq_stream stream);
+
 /* Synchronises `stream` and returns (then clears) the error word of the
    scan that last used `workspace` (Sec. 2: the decode kernels of that
    scan): PQ_OK, or PQ_ECORRUPT / PQ_EUNSUPPORTED / PQ_ECAPACITY found by a

@@ -22,7 +22,8 @@ EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_i
            "pq_file_stats_get", "pq_column_bytes", "pq_column_encodings", "pq_plan", "pq_scan", "pq_scan_check", "pq_profile",
            "pq_profile_read", "pq_close", "pq_last_error", "pq_tuning_default", "pq_plan_batch", "pq_scan_batch",
            "pq_autotune_batch", "pq_scan_noalloc", "pq_server_create", "pq_server_submit", "pq_server_wait",
-           "pq_server_release", "pq_server_stats_get", "pq_server_destroy", "pq_server_last_error")
+           "pq_server_release", "pq_server_stats_get", "pq_server_destroy", "pq_server_last_error",
+           "pq_open_host", "pq_scan_streamed")
 FORM_BATCHED, FORM_PER_PAGE = 0, 1
 TUNE_CLASSES = 54
 
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         vp, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
         L.pq_open_device.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.pq_open_host.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.pq_scan_streamed.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp, vp]
         L.pq_num_row_groups.argtypes = [vp, ctypes.POINTER(i32)]
         L.pq_num_columns.argtypes = [vp, ctypes.POINTER(i32)]
         L.pq_column_info_get.argtypes = [vp, i32, ctypes.POINTER(ColumnInfo)]
@@ -137,7 +140,7 @@ def lib() -> ctypes.CDLL:
                      "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read",
                      "pq_tuning_default", "pq_plan_batch", "pq_scan_batch", "pq_autotune_batch",
                      "pq_server_create", "pq_server_submit", "pq_server_wait", "pq_server_release",
-                     "pq_server_stats_get"):
+                     "pq_server_stats_get", "pq_open_host", "pq_scan_streamed"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -338,6 +341,41 @@ class DeviceFile:
             d["guards"] = guards
             res[c] = d
         return res
+
+
+class HostFile(DeviceFile):
+    """A Parquet file resident in pinned host memory (pq_open_host), scanned
+    with its row groups streamed to the device while the previous one is
+    decoded (pq_scan_streamed).  The copies run on `copy_stream` (a stream of
+    the handle's own unless given)."""
+
+    def __init__(self, data, stream=None, pinned: bool = True):
+        import numpy as np
+        import torch
+        a = np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else np.asarray(data, dtype=np.uint8)
+        n = a.size
+        buf = torch.empty(max(n, 1), dtype=torch.uint8, pin_memory=pinned)
+        buf[:n].copy_(torch.from_numpy(a))
+        self._buf = buf  # borrowed by the handle until close
+        self._copy_stream = None
+        h = ctypes.c_void_p()
+        _check(lib().pq_open_host(ctypes.c_void_p(buf.data_ptr()), n, ctypes.c_void_p(_stream_ptr(stream)),
+                                  ctypes.byref(h)))
+        self._h = h
+        self.nbytes = n
+
+    def scan_into(self, mask: int, rg_begin: int, rg_end: int, outs: Sequence[ColumnOut], workspace, stream=None,
+                  copy_stream=None):
+        """Enqueues pq_scan_streamed (no synchronisation)."""
+        import torch
+        if copy_stream is None:
+            if self._copy_stream is None:
+                self._copy_stream = torch.cuda.Stream()
+            copy_stream = self._copy_stream
+        arr = (ColumnOut * max(len(outs), 1))(*outs)
+        _check(lib().pq_scan_streamed(self._h, mask, rg_begin, rg_end, arr, len(outs),
+                                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                      ctypes.c_void_p(copy_stream.cuda_stream), ctypes.c_void_p(_stream_ptr(stream))))
 
 
 # ---------------------------------------------------------------------------

@@ -247,7 +247,8 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 constexpr int NKERN = 18;  // kernels with a profiling slot (each fixed-width instantiation has its own)
 
 struct pq_file_s {
-  const uint8_t* file = nullptr;
+  const uint8_t* file = nullptr;  // the device-resident file (NULL for a host-resident one)
+  const uint8_t* host = nullptr;  // a host-resident file (pq_open_host), borrowed
   uint64_t len = 0;
   int ncols = 0, nrg = 0;
   std::vector<ColMeta> cols;
@@ -287,6 +288,8 @@ struct pq_file_s {
   struct Rec { int kernel; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+  // pq_scan_streamed: per staging slot, "copied" and "free again" events
+  hipEvent_t stage_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   double prof_ms[NKERN] = {0};
   uint64_t prof_n[NKERN] = {0};
 };
@@ -338,6 +341,8 @@ static void free_handle(pq_file f) {
   if (!f) return;
   for (auto& r : f->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : f->event_pool) (void)hipEventDestroy(e);
+  for (auto e : f->stage_ev)
+    if (e) (void)hipEventDestroy(e);
   if (f->d_pages) (void)hipFree(f->d_pages);
   if (f->d_tiles) (void)hipFree(f->d_tiles);
   if (f->d_strck) (void)hipFree(f->d_strck);
@@ -390,9 +395,12 @@ static SegTable make_segs(const std::vector<Segment>& v, bool spread = false) {
 }
 
 static pq_status build_tile_prefix(pq_file f, hipStream_t s);
-static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s);
+static pq_status build_dicts(pq_file f, const uint8_t* scratch, bool copy_all, hipStream_t s);
 
-extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out) {
+// The open of a file in device memory; with host_copy the buffer is a
+// temporary device copy of a host-resident file, so every dictionary is
+// copied into the handle's arena (none may point into the buffer).
+static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, bool host_copy, pq_file* out) {
   if (!out) return fail(PQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (!dev_buf) return fail(PQ_EINVAL, "dev_buf is NULL");
@@ -655,7 +663,7 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   f->fd.sblk_page = f->d_sblk_page;
   // ---- resident dictionaries (decompressed pages are still in d_scratch) ----
   {
-    pq_status st5 = build_dicts(f, d_scratch, s);
+    pq_status st5 = build_dicts(f, d_scratch, host_copy, s);
     if (st5 != PQ_OK) { cleanup_open(); free_handle(f); return st5; }
   }
   f->fd.dicts = f->d_dicts;
@@ -689,6 +697,35 @@ extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream
   (void)t0;
   *out = f;
   return PQ_OK;
+}
+
+extern "C" pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out) {
+  return open_impl(dev_buf, len, stream, false, out);
+}
+
+extern "C" pq_status pq_open_host(const void* host_buf, uint64_t len, pq_stream stream, pq_file* out) {
+  if (!out) return fail(PQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!host_buf) return fail(PQ_EINVAL, "host_buf is NULL");
+  if (len < 12) return fail(PQ_ECORRUPT, "file shorter than 12 bytes");
+  hipStream_t s = (hipStream_t)stream;
+  // the open-time passes read the file on the device: a temporary copy,
+  // freed when the index is built
+  uint8_t* tmp = nullptr;
+  if (hipMalloc(&tmp, (len + 15) / 16 * 16 + 16) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the file");
+  pq_status st = PQ_OK;
+  if (hipMemcpyAsync(tmp, host_buf, len, hipMemcpyHostToDevice, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    st = fail(PQ_EHIP, "open: copy of the host file");
+  if (st == PQ_OK) st = open_impl(tmp, len, stream, true, out);
+  if (st == PQ_OK) {
+    (void)hipStreamSynchronize(s);
+    pq_file f = *out;
+    f->file = nullptr;
+    f->fd.file = nullptr;
+    f->host = static_cast<const uint8_t*>(host_buf);
+  }
+  (void)hipFree(tmp);
+  return st;
 }
 
 extern "C" void pq_close(pq_file f) { free_handle(f); }
@@ -732,11 +769,11 @@ extern "C" pq_status pq_file_stats_get(pq_file f, pq_file_stats* out) {
 // length) pairs, the length array and, for dictionaries that serve at least
 // SLOT_ROWS_PER_ENTRY rows of their row group per entry, 64-byte slots.
 // `scratch` holds the decompressed pages at their file-wide scratch offsets.
-static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s) {
+static pq_status build_dicts(pq_file f, const uint8_t* scratch, bool copy_all, hipStream_t s) {
   const int nchunks = f->ncols * f->nrg;
   f->dicts.assign((size_t)nchunks, DictSlot{});
   std::vector<DictWork> work;
-  struct Copy { uint64_t dst; uint64_t src; uint64_t n; };
+  struct Copy { uint64_t dst; uint64_t src; uint64_t n; bool from_scratch; };
   std::vector<Copy> copies;  // decompressed string dictionary bodies -> arena
   uint64_t off = 0;
   uint32_t units = 0;
@@ -755,7 +792,7 @@ static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s) {
     uint32_t nu = 0;
     if (sl.type != T_BYTE_ARRAY) {
       const uint64_t w = sl.type == T_INT32 ? 4 : 8;
-      if (!comp && ((uintptr_t)(f->file + pg.val_off) % w) == 0) {
+      if (!comp && !copy_all && ((uintptr_t)(f->file + pg.val_off) % w) == 0) {
         sl.entries = const_cast<uint8_t*>(f->file + pg.val_off);  // the body is the array
         continue;
       }
@@ -765,10 +802,10 @@ static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s) {
       off = align_up(off + w * n + 16, 256);
       nu = (uint32_t)((n + DICT_FIXED_PER - 1) / DICT_FIXED_PER);
     } else {
-      if (comp) {
+      if (comp || copy_all) {
         sl.body = reinterpret_cast<const uint8_t*>(off);
         sl.body_off = 0;
-        copies.push_back(Copy{off, pg.val_off, pg.val_len});
+        copies.push_back(Copy{off, pg.val_off, pg.val_len, comp});
         off = align_up(off + pg.val_len + SCRATCH_PAD, 256);
       } else {
         sl.body = f->file;
@@ -807,13 +844,14 @@ static pq_status build_dicts(pq_file f, const uint8_t* scratch, hipStream_t s) {
       if (sl.body) sl.entries = rebase(sl.entries);
       continue;
     }
-    if (comp) sl.body = rebase(sl.body);
+    if (comp || copy_all) sl.body = rebase(sl.body);
     sl.entries = rebase(sl.entries);
     sl.lens = rebase(sl.lens);
     if (sl.flags & DICT_SLOTS) sl.slots = rebase(sl.slots);
   }
   for (const Copy& c : copies)
-    HIP_OR(hipMemcpyAsync(f->d_dict_arena + c.dst, scratch + c.src, c.n, hipMemcpyDeviceToDevice, s));
+    HIP_OR(hipMemcpyAsync(f->d_dict_arena + c.dst, (c.from_scratch ? scratch : f->file) + c.src, c.n,
+                          hipMemcpyDeviceToDevice, s));
   HIP_OR(hipMalloc(&f->d_dicts, sizeof(DictSlot) * (size_t)(nchunks ? nchunks : 1)));
   if (nchunks)
     HIP_OR(hipMemcpyAsync(f->d_dicts, f->dicts.data(), sizeof(DictSlot) * (size_t)nchunks, hipMemcpyHostToDevice, s));
@@ -863,6 +901,10 @@ struct Plan {
   bool str_spread[2] = {false, false}, fixed_spread[8] = {};  // columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[8] = {}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
+  // a host-resident file: two staging slots for row groups in flight and
+  // one column table per row group (its file base in its slot)
+  uint64_t ws_stage = 0, stage_bytes = 0, ws_rgcols = 0;
+  std::vector<uint64_t> rg_lo;  // per scanned row group: the lowest file offset of its selected chunks
 };
 
 // Work lists and workspace layout of a scan of `mask` over row groups
@@ -1007,6 +1049,24 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     P.str_spread[k] = true;
     P.str_units[k] = (uint32_t)P.str_segs[k].size() * most;
   }
+  if (f->host && !index && !P.cols.empty()) {
+    uint64_t most = 0;
+    for (int g = rg_b; g < rg_e; ++g) {
+      uint64_t lo = ~0ull, hi = 0;
+      for (const ColScan& cs : P.cols) {
+        const ChunkDev& ch = f->chunks[(size_t)cs.col * f->nrg + g];
+        lo = std::min(lo, ch.start);
+        hi = std::max(hi, ch.end);
+      }
+      P.rg_lo.push_back(lo);
+      most = std::max(most, hi - lo);
+    }
+    P.stage_bytes = align_up(most + 64, 256);  // reads may run 16 bytes past a stream
+    P.ws_stage = off;
+    off += 2 * P.stage_bytes;
+    P.ws_rgcols = off;
+    off = align_up(off + sizeof(ColScan) * P.cols.size() * (size_t)(rg_e - rg_b), 256);
+  }
   P.ws_total = std::max<uint64_t>(off, 256);
   return PQ_OK;
 }
@@ -1026,15 +1086,20 @@ static FixedKernel fixed_kernel(int K) {
   }
 }
 
-// The workspace header (cleared error word, column table, string columns) in
-// one host-to-device copy, then decompression: the steps the open-time
-// prefix pass and a scan share.
-static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, hipStream_t s) {
-  ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
+// The workspace header of a plan: the cleared error word, the column table
+// and the string-column list, in one host-to-device copy.
+static pq_status upload_header(Plan& P, uint8_t* ws, hipStream_t s) {
   std::vector<uint8_t> hdr(P.ws_which + sizeof(int32_t) * P.str_cols.size(), 0);
   if (!P.cols.empty()) memcpy(hdr.data() + P.ws_cols, P.cols.data(), sizeof(ColScan) * P.cols.size());
   if (!P.str_cols.empty()) memcpy(hdr.data() + P.ws_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size());
   HIP_OR(hipMemcpyAsync(ws, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s));
+  return PQ_OK;
+}
+
+// Snappy decompression of the plan's compressed data pages (column table
+// d_cols).
+static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_cols, uint8_t* ws, uint32_t* err,
+                                    hipStream_t s) {
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.fixed_segs[4], &P.fixed_segs[6], &P.delta_segs, &P.str_segs[0], &P.str_segs[1],
                         &P.edge_segs})
@@ -1053,6 +1118,14 @@ static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, h
   return PQ_OK;
 }
 
+// Decompression and the upload: the steps the open-time prefix pass and a
+// scan share.
+static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, hipStream_t s) {
+  pq_status st = upload_header(P, ws, s);
+  if (st != PQ_OK) return st;
+  return enqueue_decompress(f, P, reinterpret_cast<ColScan*>(ws + P.ws_cols), ws, err, s);
+}
+
 // The open-time prefix pass of a plan made with index = true: per-tile DELTA
 // sums and string byte counts into the workspace's tile arrays (mode 1: the
 // DELTA sums of DELTA_LENGTH_BYTE_ARRAY length streams only).
@@ -1067,17 +1140,10 @@ static pq_status enqueue_index(pq_file f, Plan& P, uint8_t* ws, int mode, hipStr
   return PQ_OK;
 }
 
-static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
-  uint32_t* err = reinterpret_cast<uint32_t*>(ws);  // the scan's error word
-  pq_status st = enqueue_front(f, P, ws, err, s);
-  if (st != PQ_OK) return st;
-  ColScan* d_cols = reinterpret_cast<ColScan*>(ws + P.ws_cols);
-  int32_t* d_which = reinterpret_cast<int32_t*>(ws + P.ws_which);
-  if (!P.str_cols.empty()) {
-    ProfScope ps_(f, KP_STR_TOTAL, s);
-    hipLaunchKernelGGL(k_str_total, dim3(1), dim3(64), 0, s, d_cols, d_which, (int32_t)P.str_cols.size(), err);
-    HIP_OR(hipGetLastError());
-  }
+// REQUIRED validity and the decode kernels of a plan's tiles (column table
+// d_cols), one launch per kernel kind.
+static pq_status enqueue_decode(pq_file f, const Plan& P, const ColScan* d_cols, uint8_t* ws, uint32_t* err,
+                                hipStream_t s) {
   if (P.prep_threads) {
     ProfScope ps_(f, KP_PREP, s);
     hipLaunchKernelGGL(k_prep, dim3((P.prep_threads + 255) / 256), dim3(256), 0, s, d_cols, make_segs(P.prep_segs));
@@ -1104,6 +1170,41 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
                        ws, d_cols, make_segs(P.str_segs[k], P.str_spread[k]), err);
     HIP_OR(hipGetLastError());
   }
+  return PQ_OK;
+}
+
+// offsets[rows] of string columns and the validity words tiles share.
+static pq_status enqueue_finish(pq_file f, const Plan& P, const ColScan* d_cols, uint8_t* ws, uint32_t* err,
+                                hipStream_t s) {
+  if (!P.str_cols.empty()) {
+    ProfScope ps_(f, KP_STR_TOTAL, s);
+    hipLaunchKernelGGL(k_str_total, dim3(((uint32_t)P.str_cols.size() + 63) / 64), dim3(64), 0, s, d_cols,
+                       reinterpret_cast<const int32_t*>(ws + P.ws_which), (int32_t)P.str_cols.size(), err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.edge_threads) {
+    ProfScope ps_(f, KP_EDGES, s);
+    hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, make_segs(P.edge_segs));
+    HIP_OR(hipGetLastError());
+  }
+  return PQ_OK;
+}
+
+static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
+  uint32_t* err = reinterpret_cast<uint32_t*>(ws);  // the scan's error word
+  pq_status st = enqueue_front(f, P, ws, err, s);
+  if (st != PQ_OK) return st;
+  const ColScan* d_cols = reinterpret_cast<const ColScan*>(ws + P.ws_cols);
+  // the string totals first (they read only the tile prefix), then the
+  // decode kernels, then the shared validity words
+  if (!P.str_cols.empty()) {
+    ProfScope ps_(f, KP_STR_TOTAL, s);
+    hipLaunchKernelGGL(k_str_total, dim3(((uint32_t)P.str_cols.size() + 63) / 64), dim3(64), 0, s, d_cols,
+                       reinterpret_cast<const int32_t*>(ws + P.ws_which), (int32_t)P.str_cols.size(), err);
+    HIP_OR(hipGetLastError());
+  }
+  st = enqueue_decode(f, P, d_cols, ws, err, s);
+  if (st != PQ_OK) return st;
   if (P.edge_threads) {
     ProfScope ps_(f, KP_EDGES, s);
     hipLaunchKernelGGL(k_edges, dim3((P.edge_threads + 255) / 256), dim3(256), 0, s, ws, d_cols, make_segs(P.edge_segs));
@@ -1234,6 +1335,7 @@ static pq_status bind_outputs(Plan& P, const pq_column_out* outs, int32_t n_outs
 extern "C" pq_status pq_scan(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end, const pq_column_out* outs,
                              int32_t n_outs, void* workspace, uint64_t workspace_bytes, pq_stream stream) {
   if (!f) return fail(PQ_EINVAL, "NULL handle");
+  if (f->host) return fail(PQ_EINVAL, "a host-resident file is scanned with pq_scan_streamed");
   Plan P;
   pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
   if (st != PQ_OK) return st;
@@ -1285,6 +1387,7 @@ static uint8_t* scratch_of_current_device() {
 extern "C" pq_status pq_scan_noalloc(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end,
                                      const pq_column_out* outs, int32_t n_outs, pq_stream stream) {
   if (!f) return fail(PQ_EINVAL, "NULL handle");
+  if (f->host) return fail(PQ_EINVAL, "a host-resident file is scanned with pq_scan_streamed");
   Plan P;
   pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
   if (st != PQ_OK) return st;
@@ -1297,6 +1400,79 @@ extern "C" pq_status pq_scan_noalloc(pq_file f, uint64_t col_mask, int32_t rg_be
   uint8_t* ws = scratch_of_current_device();
   if (!ws) return PQ_EHIP;
   return enqueue(f, P, ws, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// streamed scans of host-resident files
+// ---------------------------------------------------------------------------
+extern "C" pq_status pq_scan_streamed(pq_file f, uint64_t col_mask, int32_t rg_begin, int32_t rg_end,
+                                      const pq_column_out* outs, int32_t n_outs, void* workspace, uint64_t workspace_bytes,
+                                      pq_stream copy_stream, pq_stream stream) {
+  if (!f) return fail(PQ_EINVAL, "NULL handle");
+  if (!f->host) return fail(PQ_EINVAL, "pq_scan_streamed needs a host-resident file (pq_open_host)");
+  Plan P;
+  pq_status st = make_plan(f, col_mask, rg_begin, rg_end, P);
+  if (st != PQ_OK) return st;
+  if (P.cols.size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many columns");
+  if (!workspace) return fail(PQ_EINVAL, "workspace is NULL");
+  if (workspace_bytes < P.ws_total) return fail(PQ_ECAPACITY, "workspace smaller than planned (%llu < %llu)",
+                                                (unsigned long long)workspace_bytes, (unsigned long long)P.ws_total);
+  if (((uintptr_t)workspace & 255) != 0) return fail(PQ_EINVAL, "workspace must be 256-byte aligned");
+  st = bind_outputs(P, outs, n_outs);
+  if (st != PQ_OK) return st;
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  hipStream_t s = (hipStream_t)stream, cs = (hipStream_t)copy_stream;
+  uint32_t* err = reinterpret_cast<uint32_t*>(ws);
+  st = upload_header(P, ws, s);
+  if (st != PQ_OK) return st;
+  const int nrg = rg_end - rg_begin;
+  if (nrg == 0 || P.cols.empty()) return enqueue_finish(f, P, reinterpret_cast<ColScan*>(ws + P.ws_cols), ws, err, s);
+  // one column table per row group: the file base of its slot
+  std::vector<ColScan> tables(P.cols.size() * (size_t)nrg);
+  for (int i = 0; i < nrg; ++i)
+    for (size_t k = 0; k < P.cols.size(); ++k) {
+      ColScan t = P.cols[k];
+      t.fd.file = ws + P.ws_stage + (uint64_t)(i % 2) * P.stage_bytes - P.rg_lo[(size_t)i];
+      tables[(size_t)i * P.cols.size() + k] = t;
+    }
+  HIP_OR(hipMemcpyAsync(ws + P.ws_rgcols, tables.data(), sizeof(ColScan) * tables.size(), hipMemcpyHostToDevice, s));
+  for (hipEvent_t& e : f->stage_ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return fail(PQ_EHIP, "event creation failed");
+    }
+  hipEvent_t* copied = f->stage_ev;
+  hipEvent_t* freed = f->stage_ev + 2;
+  // the first slot's copy waits for the upload that precedes it on `stream`
+  (void)hipEventRecord(freed[1], s);
+  (void)hipStreamWaitEvent(cs, freed[1], 0);
+  for (int i = 0; i < nrg && st == PQ_OK; ++i) {
+    const int g = rg_begin + i, slot = i % 2;
+    if (i >= 2 && hipStreamWaitEvent(cs, freed[slot], 0) != hipSuccess) { st = fail(PQ_EHIP, "stream wait failed"); break; }
+    uint8_t* base = ws + P.ws_stage + (uint64_t)slot * P.stage_bytes;
+    for (const ColScan& c : P.cols) {
+      const ChunkDev& ch = f->chunks[(size_t)c.col * f->nrg + g];
+      if (ch.end > ch.start &&
+          hipMemcpyAsync(base + (ch.start - P.rg_lo[(size_t)i]), f->host + ch.start, ch.end - ch.start,
+                         hipMemcpyHostToDevice, cs) != hipSuccess) {
+        st = fail(PQ_EHIP, "row group %d: host-to-device copy failed", g);
+        break;
+      }
+    }
+    if (st != PQ_OK) break;
+    if (hipEventRecord(copied[slot], cs) != hipSuccess || hipStreamWaitEvent(s, copied[slot], 0) != hipSuccess) {
+      st = fail(PQ_EHIP, "event record failed");
+      break;
+    }
+    Plan Pg;  // the launch lists of row group g alone (same column order)
+    st = make_plan(f, col_mask, g, g + 1, Pg);
+    const ColScan* d_cols = reinterpret_cast<const ColScan*>(ws + P.ws_rgcols + sizeof(ColScan) * P.cols.size() * (size_t)i);
+    if (st == PQ_OK) st = enqueue_decompress(f, Pg, d_cols, ws, err, s);
+    if (st == PQ_OK) st = enqueue_decode(f, Pg, d_cols, ws, err, s);
+    if (st == PQ_OK && hipEventRecord(freed[slot], s) != hipSuccess) st = fail(PQ_EHIP, "event record failed");
+  }
+  if (st == PQ_OK) st = enqueue_finish(f, P, reinterpret_cast<ColScan*>(ws + P.ws_cols), ws, err, s);
+  return st;
 }
 
 extern "C" pq_status pq_scan_check(pq_file f, const void* workspace, pq_stream stream) {
@@ -1367,6 +1543,7 @@ pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
   uint64_t ncols = 0;
   for (int32_t r = 0; r < n; ++r) {
     if (!reqs[r].file) return fail(PQ_EINVAL, "request %d: NULL file", r);
+    if (reqs[r].file->host) return fail(PQ_EINVAL, "request %d: a host-resident file", r);
     ncols += (uint64_t)__builtin_popcountll(reqs[r].col_mask);
   }
   if (ncols >= (1ull << 31)) return fail(PQ_EUNSUPPORTED, "too many columns in one batch");

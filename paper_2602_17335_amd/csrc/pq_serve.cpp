@@ -470,6 +470,14 @@ extern "C" pq_status pq_server_create(const pq_file* files, int32_t n_files, uin
       delete s;
       return sfail(PQ_EINVAL, "file %d is not an open handle", i);
     }
+    // batched scans need device-resident files: a one-request plan refuses
+    // a host-resident handle
+    pq_request probe{files[i], 0, 0, 0, nullptr};
+    uint64_t probe_ws = 0;
+    if (pq_plan_batch(&probe, 1, &probe_ws, nullptr, 0) != PQ_OK) {
+      delete s;
+      return sfail(PQ_EINVAL, "file %d cannot be served: %s", i, pq_last_error());
+    }
     s->files.push_back(files[i]);
     std::vector<int32_t> t((size_t)nc);
     for (int32_t c = 0; c < nc; ++c) { pq_column_info ci; pq_column_info_get(files[i], c, &ci); t[(size_t)c] = ci.type; }
