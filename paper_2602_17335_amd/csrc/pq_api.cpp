@@ -21,6 +21,13 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order);
+__global__ void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand);
+__global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
+                              uint32_t* seg_base, uint32_t* ok);
+__global__ void k_schain_fill(const SChainPage* pgs, const uint32_t* seg_page, const uint32_t* seg_start,
+                              const uint32_t* seg_base, const uint32_t* ok, uint32_t* strck, PageDev* pages, uint32_t* err);
+__global__ void k_schain_seq(const SChainPage* pgs, int npg, const uint32_t* ok, uint32_t* strck, PageDev* pages,
+                             uint32_t* err);
 __global__ void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record, uint32_t* err);
 __global__ void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err);
 __global__ void k_prep(const ColScan* cols, SegTable seg);
@@ -574,13 +581,16 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   uint8_t* d_scratch = nullptr;
   ColScan* d_cs = nullptr;
   uint32_t* d_order = nullptr;
+  uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
   auto cleanup_open = [&]() {
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_cs) (void)hipFree(d_cs);
     if (d_order) (void)hipFree(d_order);
+    if (d_schain) (void)hipFree(d_schain);
     d_scratch = nullptr;
     d_cs = nullptr;
     d_order = nullptr;
+    d_schain = nullptr;
   };
   if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
   // Snappy block index, recorded by the decompression below
@@ -629,7 +639,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     std::vector<uint64_t> work(npages);
     for (uint32_t p = 0; p < npages; ++p) {
       const PageDev& pg = f->pages[p];
-      const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY;
+      const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY && pg.uncomp_size <= SCHAIN_MIN;
       work[p] = sdict ? 16ull * pg.uncomp_size : (uint64_t)(pg.num_values > 0 ? pg.num_values : 0);
       order[p] = p;
     }
@@ -642,6 +652,50 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
                        f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
                        (uint64_t)scratch, d_order);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
+    // long string dictionaries: their length chains, segments side by side
+    std::vector<SChainPage> scp;
+    std::vector<uint32_t> seg_page;
+    for (uint32_t p = 0; p < npages; ++p) {
+      const PageDev& pg = f->pages[p];
+      if (pg.kind != PAGE_DICT || f->chunks[pg.chunk].type != T_BYTE_ARRAY || pg.uncomp_size <= SCHAIN_MIN) continue;
+      const bool in_scratch = pg.scratch_len > 0;
+      SChainPage x;
+      x.base = in_scratch ? d_scratch : file;
+      x.off = in_scratch ? pg.scratch_off : pg.payload;
+      x.lim = in_scratch ? (uint64_t)scratch : (len + 15) & ~15ull;
+      x.len = (uint32_t)pg.uncomp_size;
+      x.n = pg.num_values > 0 ? (uint32_t)pg.num_values : 0u;
+      x.page = p;
+      x.seg0 = (uint32_t)seg_page.size();
+      x.nseg = (uint32_t)(((uint64_t)x.len + SCHAIN_SEG - 1) / SCHAIN_SEG);
+      x.strck_begin = pg.strck_begin;
+      for (uint32_t j = 0; j < x.nseg; ++j) seg_page.push_back((uint32_t)scp.size());
+      scp.push_back(x);
+    }
+    if (!scp.empty()) {
+      const size_t npg = scp.size(), nseg = seg_page.size();
+      const size_t o_seg = align_up(sizeof(SChainPage) * npg, 256), o_cand = align_up(o_seg + 4 * nseg, 256),
+                   o_start = align_up(o_cand + sizeof(SChainCand) * SCHAIN_CAND * nseg, 256),
+                   o_base = align_up(o_start + 4 * nseg, 256), o_ok = align_up(o_base + 4 * nseg, 256),
+                   total = o_ok + 4 * npg;
+      if (hipMalloc(&d_schain, total) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: dictionary chain tables"); }
+      SChainPage* d_pgs = reinterpret_cast<SChainPage*>(d_schain);
+      uint32_t* d_segp = reinterpret_cast<uint32_t*>(d_schain + o_seg);
+      SChainCand* d_cand = reinterpret_cast<SChainCand*>(d_schain + o_cand);
+      uint32_t* d_start = reinterpret_cast<uint32_t*>(d_schain + o_start);
+      uint32_t* d_base = reinterpret_cast<uint32_t*>(d_schain + o_base);
+      uint32_t* d_ok = reinterpret_cast<uint32_t*>(d_schain + o_ok);
+      OPEN_HIP(hipMemcpyAsync(d_pgs, scp.data(), sizeof(SChainPage) * npg, hipMemcpyHostToDevice, s));
+      OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_schain_cand, dim3((uint32_t)nseg), dim3(64), 0, s, d_pgs, d_segp, d_cand);
+      hipLaunchKernelGGL(k_schain_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_pgs, (int)npg, d_cand, d_start,
+                         d_base, d_ok);
+      hipLaunchKernelGGL(k_schain_fill, dim3((uint32_t)nseg), dim3(64), 0, s, d_pgs, d_segp, d_start, d_base, d_ok,
+                         f->d_strck, f->d_pages, f->d_err);
+      hipLaunchKernelGGL(k_schain_seq, dim3((uint32_t)npg), dim3(64), 0, s, d_pgs, (int)npg, d_ok, f->d_strck, f->d_pages,
+                         f->d_err);
+      if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_schain launch failed"); }
+    }
   }
   HIP_OR(hipEventRecord(e1, s));
   {

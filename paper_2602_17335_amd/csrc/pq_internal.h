@@ -71,6 +71,32 @@ constexpr uint32_t LCK_NONE = 0xffffffffu;
 // BYTE_ARRAY checkpoint spacing (values) inside PLAIN string streams and
 // string dictionary pages.
 constexpr int STR_CK = 32;
+// String dictionary pages longer than SCHAIN_MIN bytes have their length
+// chain walked at open in SCHAIN_SEG-byte segments side by side (candidate
+// chains from each of the first SCHAIN_CAND byte positions of a segment,
+// linked segment by segment afterwards); shorter ones by k_index's walk.
+constexpr uint32_t SCHAIN_MIN = 256 * 1024;
+constexpr uint32_t SCHAIN_SEG = 32768;
+constexpr uint32_t SCHAIN_CAND = 64;
+constexpr uint32_t SCHAIN_NONE = 0xffffffffu;
+struct SChainPage {
+  const uint8_t* base;  // buffer holding the page body (the file, or the decompression buffer)
+  uint64_t off;         // body offset in base
+  uint64_t lim;         // readable bytes of base (a multiple of 16)
+  uint32_t len;         // body bytes
+  uint32_t n;           // entries
+  uint32_t page;        // page index
+  uint32_t seg0;        // first segment (in the segment arrays)
+  uint32_t nseg;
+  uint32_t strck_begin;
+};
+// A candidate chain of one segment: where it leaves the segment, the
+// entries that start in the segment, their longest length, and how it
+// ended (0: left the segment; 1: fewer than 4 bytes left; 2: a length past
+// the body's end).
+struct SChainCand {
+  uint32_t exit, count, maxlen, state;
+};
 // Bytes of slack after every decompressed region (reads run up to 12 bytes
 // past a stream end).
 constexpr int SCRATCH_PAD = 16;

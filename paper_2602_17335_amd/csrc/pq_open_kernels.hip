@@ -2,6 +2,8 @@
 //   k_walk   page-header walk of every column chunk -> device page table
 //   k_index  tile index: entry positions of every TILE_ROWS-row tile in the
 //            level and value streams of each data page, string checkpoints.
+//   k_schain_cand / k_schain_link / k_schain_fill / k_schain_seq
+//            string checkpoints of long dictionary pages, segments side by side
 #include <hip/hip_runtime.h>
 
 #include "pq_device.hpp"
@@ -306,7 +308,9 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
     pg.val_off = off;
     pg.val_len = (uint32_t)blen;
     pg.flags = in_scratch ? 2 : 0;
-    if (ch.type == T_BYTE_ARRAY) {
+    if (ch.type == T_BYTE_ARRAY && blen > SCHAIN_MIN) {
+      pg.dict_maxlen = 0;  // the chain is walked by the k_schain kernels
+    } else if (ch.type == T_BYTE_ARRAY) {
       // the length-prefix chain in 32-bit positions (a page is below 4 GiB):
       // q in the page body, o in the LDS window, one LDS read per entry; the
       // window moves when an entry's length prefix would leave it.  Every
@@ -595,6 +599,152 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
     pg.chars_at = (uint32_t)(q - val_off);
   }
   pages[p] = pg;
+}
+
+
+// ---------------------------------------------------------------------------
+// Long string dictionary pages.  The body is a chain of (u32 length, bytes)
+// entries whose positions are only known by walking it from the start.  The
+// body is cut into SCHAIN_SEG-byte segments; in each segment, lane c walks
+// the chain that starts at byte c of the segment until it leaves the
+// segment (k_schain_cand).  The true chain enters a segment at most
+// SCHAIN_CAND - 1 bytes past its start unless an entry longer than that
+// crosses the boundary, so one of the candidates is the true chain's walk;
+// k_schain_link follows the true chain from segment to segment through the
+// candidates' exits and gives each segment its entry position and entry
+// index, and k_schain_fill walks each segment once more from there, storing
+// a checkpoint every STR_CK entries.  A page whose true chain enters a
+// segment past the candidates (or breaks) is walked whole by k_schain_seq.
+// ---------------------------------------------------------------------------
+constexpr uint32_t SCHAIN_LDS = SCHAIN_SEG + 64;
+
+// Stages body bytes [s0, s0 + SCHAIN_SEG + 8) into LDS (16-byte chunks from
+// the one holding byte s0; bytes at or past the readable limit read as
+// zero); returns the LDS offset of byte s0.
+__device__ __forceinline__ uint32_t schain_stage(const SChainPage& sp, uint32_t s0, uint8_t* lds) {
+  const uint64_t g = sp.off + s0;
+  const uint64_t a0 = g & ~15ull;
+  for (uint32_t c = threadIdx.x; 16 * c < SCHAIN_SEG + 32; c += 64) {
+    const uint64_t a = a0 + 16ull * c;
+    wr_u4 v = {0u, 0u, 0u, 0u};
+    if (a + 16 <= sp.lim) v = *reinterpret_cast<const wr_u4*>(sp.base + a);
+    *(lds_u4*)(lds + 16 * c) = v;
+  }
+  __syncthreads();
+  return (uint32_t)(g - a0);
+}
+
+__device__ __forceinline__ uint32_t schain_u32(const uint8_t* lds, uint32_t o) {
+  const __attribute__((address_space(3))) uint32_t* w = (const __attribute__((address_space(3))) uint32_t*)lds;
+  return __builtin_amdgcn_alignbyte(w[(o >> 2) + 1], w[o >> 2], o & 3);
+}
+
+__global__ __launch_bounds__(64) void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand) {
+  __shared__ __align__(16) uint8_t s_seg[SCHAIN_LDS];
+  const uint32_t sg = blockIdx.x, c = threadIdx.x;
+  const SChainPage sp = pgs[seg_page[sg]];
+  const uint32_t s0 = (sg - sp.seg0) * SCHAIN_SEG;
+  const uint32_t se = min(s0 + SCHAIN_SEG, sp.len);
+  const uint8_t* lds = (const uint8_t*)&s_seg[0];
+  const uint32_t lead = schain_stage(sp, s0, &s_seg[0]);
+  uint32_t q = s0 + c, count = 0, maxlen = 0, state = q < se ? 0u : 1u;
+  while (q < se) {
+    if (sp.len - q < 4) { state = 1; break; }
+    const uint32_t l = schain_u32(lds, lead + (q - s0));
+    if (l > sp.len - q - 4) { state = 2; break; }
+    q += 4 + l;
+    ++count;
+    maxlen = max(maxlen, l);
+  }
+  cand[(size_t)sg * SCHAIN_CAND + c] = SChainCand{q, count, maxlen, state};
+}
+
+// One thread per page.  ok[page] = 1 when every segment's entry was found
+// among the candidates (then seg_start / seg_base hold each segment's first
+// entry position and index, SCHAIN_NONE where no entry starts).
+__global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
+                              uint32_t* seg_base, uint32_t* ok) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npg) return;
+  const SChainPage sp = pgs[i];
+  uint32_t q = 0, k = 0, good = 1;
+  for (uint32_t j = 0; j < sp.nseg; ++j) {
+    const uint32_t s0 = j * SCHAIN_SEG, se = min(s0 + SCHAIN_SEG, sp.len);
+    seg_start[sp.seg0 + j] = SCHAIN_NONE;
+    if (k >= sp.n || q >= se) continue;  // the chain has ended, or an entry covers the segment
+    const uint32_t c = q - s0;
+    if (c >= SCHAIN_CAND) { good = 0; break; }
+    seg_start[sp.seg0 + j] = q;
+    seg_base[sp.seg0 + j] = k;
+    const SChainCand cd = cand[(size_t)(sp.seg0 + j) * SCHAIN_CAND + c];
+    if (sp.n - k <= cd.count) { k = sp.n; continue; }  // the chain's last entry starts here
+    if (cd.state != 0) { good = 0; break; }             // broken before its last entry
+    q = cd.exit;
+    k += cd.count;
+  }
+  if (k < sp.n) good = 0;  // ran out of body: the sequential walk reports it
+  ok[i] = good;
+}
+
+// One workgroup per segment of a linked page: lane 0 walks the segment's
+// entries from its first one, storing the checkpoints; the page's longest
+// length is the maximum over its segments.
+__global__ __launch_bounds__(64) void k_schain_fill(const SChainPage* pgs, const uint32_t* seg_page,
+                                                    const uint32_t* seg_start, const uint32_t* seg_base,
+                                                    const uint32_t* ok, uint32_t* strck, PageDev* pages, uint32_t* err) {
+  __shared__ __align__(16) uint8_t s_seg[SCHAIN_LDS];
+  const uint32_t sg = blockIdx.x;
+  const uint32_t pi = seg_page[sg];
+  if (!ok[pi] || seg_start[sg] == SCHAIN_NONE) return;
+  const SChainPage sp = pgs[pi];
+  const uint32_t s0 = (sg - sp.seg0) * SCHAIN_SEG;
+  const uint32_t se = min(s0 + SCHAIN_SEG, sp.len);
+  const uint8_t* lds = (const uint8_t*)&s_seg[0];
+  const uint32_t lead = schain_stage(sp, s0, &s_seg[0]);
+  if (threadIdx.x != 0) return;
+  uint32_t q = seg_start[sg], k = seg_base[sg], maxlen = 0;
+  while (q < se && k < sp.n) {
+    if ((k % STR_CK) == 0) strck[sp.strck_begin + k / STR_CK] = q;
+    if (sp.len - q < 4) { set_err(err, ERR_STRING, sp.page); return; }
+    const uint32_t l = schain_u32(lds, lead + (q - s0));
+    if (l > sp.len - q - 4) { set_err(err, ERR_STRING, sp.page); return; }
+    q += 4 + l;
+    maxlen = max(maxlen, l);
+    ++k;
+  }
+  atomicMax(&pages[sp.page].dict_maxlen, maxlen);
+}
+
+// One wave per page that could not be linked: the whole chain, front to
+// back, through an LDS window (as k_index walks the short pages).
+__global__ __launch_bounds__(64) void k_schain_seq(const SChainPage* pgs, int npg, const uint32_t* ok, uint32_t* strck,
+                                                   PageDev* pages, uint32_t* err) {
+  __shared__ wr_u4 s_win[WIN / 16];
+  const int i = blockIdx.x;
+  if (i >= npg || ok[i]) return;
+  const SChainPage sp = pgs[i];
+  lds_u4* win = (lds_u4*)&s_win[0];
+  const bool lead = (threadIdx.x & 63) == 0;
+  const __attribute__((address_space(3))) uint32_t* w32 =
+      reinterpret_cast<const __attribute__((address_space(3))) uint32_t*>(win);
+  uint32_t q = 0, maxlen = 0, k = 0;
+  const uint32_t n = sp.n, bl = sp.len;
+  while (k < n) {
+    const uint64_t wpos = wr_refill(sp.base, sp.lim, win, (sp.off + q) & ~15ull);
+    uint32_t o = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(sp.off + q - wpos));
+    while (k < n && o + 8 <= WIN) {
+      if ((k % STR_CK) == 0 && lead) strck[sp.strck_begin + k / STR_CK] = q;
+      if (bl - q < 4) { set_err(err, ERR_STRING, sp.page); return; }
+      const uint32_t l = (uint32_t)__builtin_amdgcn_readfirstlane(
+          (int)__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3));
+      if (l > bl - q - 4) { set_err(err, ERR_STRING, sp.page); return; }
+      q += 4 + l;
+      o = l < WIN ? o + 4 + l : WIN;
+      maxlen = max(maxlen, l);
+      ++k;
+    }
+  }
+  if (lead) pages[sp.page].dict_maxlen = maxlen;
 }
 
 }  // namespace pqk

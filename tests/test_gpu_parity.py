@@ -58,6 +58,18 @@ def _spec_cases():
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=700, str_min=0, str_max=2),
         dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=40_000, str_min=8, str_max=44),
     ], num_rows=70_001, rg_rows=30_000, page_bytes=256 * dg.KiB, name="dict_strings")
+    # string dictionaries past the size whose length chain is walked in
+    # segments side by side at open: short entries (thousands per segment),
+    # 50-70-char entries (the chain often enters a segment past the
+    # candidate positions, so the page is walked whole), one with a single
+    # huge segment count; uncompressed and Snappy (dictionary in the
+    # decompression buffer)
+    for codec, tag in ((dg.UNCOMPRESSED, ""), (dg.SNAPPY, "_snappy")):
+        cases["dict_chains" + tag] = dg.FileSpec(cols=[
+            dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=300_000, str_min=0, str_max=6),
+            dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=20_000, str_min=50, str_max=70),
+            dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.3, hi=400_000, str_min=8, str_max=44),
+        ], num_rows=400_003, rg_rows=400_003, page_bytes=1 * dg.MiB, codec=codec, name="dict_chains" + tag)
     return cases
 
 
