@@ -101,21 +101,72 @@ def algorithmic_bytes(kernel, f, cols, types, out_tensors, rows):
     return b if any_col else None
 
 
+def host_cpu():
+    """Model name and core counts of the host the benchmark runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def oracle_seconds(data, columns=None, reps=1):
+    """The oracle (single-threaded C) decoding `columns` of a file held in
+    host memory, pinned to one host core (the second of this process's
+    allowed cores): per rep the sum of the per-column decode calls, the
+    median over reps.  Returns (seconds, decoded bytes, core)."""
+    import oracle
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[2] if len(allowed) > 2 else allowed[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        f = oracle.File(data)
+        cols = list(range(f.num_columns)) if columns is None else columns
+        times, nbytes = [], 0
+        for _ in range(reps):
+            tot, nbytes = 0.0, 0
+            for c in cols:
+                dt, nb = f.decode_seconds(c)
+                tot += dt
+                nbytes += nb
+            times.append(tot)
+        f.close()
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    times.sort()
+    return times[len(times) // 2], nbytes, core
+
+
+def pyarrow_seconds(data, reps=3):
+    """pyarrow.parquet.read_table over the whole file on all host cores
+    (third-party context, not the oracle): median seconds."""
+    import io
+    import pyarrow.parquet as papq
+    raw = bytes(data)
+    v = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        papq.read_table(io.BytesIO(raw), use_threads=True)
+        v.append(time.perf_counter() - t0)
+    v.sort()
+    return v[len(v) // 2]
+
+
 def cpu_baseline(data, nbytes_label):
     """The oracle (single-threaded) over every column of the benchmark file
-    itself, in host memory."""
-    import oracle
-    f = oracle.File(data)
-    t0 = time.perf_counter()
-    tot = 0
-    for c in range(f.num_columns):
-        o = f.read(c)
-        tot += o["validity"].nbytes
-        tot += o["values"].nbytes if "values" in o else o["offsets"].nbytes + o["chars"].nbytes
-    dt = time.perf_counter() - t0
+    itself, in host memory, pinned to one host core; only the decode calls
+    are timed."""
+    dt, tot, core = oracle_seconds(data)
+    cpu = host_cpu()
     return {"value": round(tot / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"the benchmark file itself ({nbytes_label}), all columns, {tot / 1e9:.2f} GB decoded "
-                      f"in {dt:.1f} s on one host core"}
+                      f"in {dt:.1f} s on host core {core}",
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cores_allowed": cpu["affinity"]}
 
 
 def read_traffic(key):
@@ -438,6 +489,140 @@ def bench_streamed(rows, rg_rows, reps, log):
     return row
 
 
+def bench_configs(path, reps, log, with_oracle=True):
+    """One JSON line per configuration (written to `path`): the 2-column
+    table at 1,000,000 rows; the 16-column table over the row-group x
+    page-size sweep (1M / 8M / 64M-row row groups x 64 KiB / 1 MiB / 8 MiB
+    pages); the Snappy table (64M-row row group, 1 MiB pages, 1 MiB
+    dictionary cap) for the projections P1 = {c15}, P4 = {c0, c6, c10,
+    c13} and P16 = all columns.  Per configuration: open time, the warm
+    and cold (L2 and MALL evicted by a 512 MiB write before each scan)
+    median scan times over `reps` scans, the open-inclusive cold figure
+    (open + first scan), decoded GB/s, algorithmic bytes (encoded read +
+    decoded written; for Snappy also the staged form, decompression and
+    decode each reading and writing its own bytes) as a fraction of 8 TB/s
+    and of the library's plain copy of the same byte count, decompression
+    and decode time apart (per-kernel events), the oracle on one pinned
+    host core and pyarrow on all host cores (context)."""
+    import io
+    import json
+    import torch
+    import pyarrow.parquet as papq
+    import datagen as dg
+    import paper_2602_17335_amd as pqs
+    nth = min(16, os.cpu_count() or 1)
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    cpu = host_cpu()
+
+    def timed(fn, n, cold):
+        v = []
+        for _ in range(n):
+            if cold:
+                flush.fill_(1)
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            z.record()
+            torch.cuda.synchronize()
+            v.append(a.elapsed_time(z))
+        v.sort()
+        return v[len(v) // 2]
+
+    def copy_gbps(nbytes):
+        nbytes = max(16, nbytes // 16 * 16)
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        pqs.copy_probe(dst, src, nbytes)
+        ms = timed(lambda: pqs.copy_probe(dst, src, nbytes), 5, False)
+        del src, dst
+        return 2 * nbytes / ms / 1e6
+
+    out = open(path, "w")
+
+    def run(name, spec, projections, workload):
+        t0 = time.perf_counter()
+        data = dg.write(spec, nthreads=nth)
+        md = papq.ParquetFile(io.BytesIO(bytes(data))).metadata
+        buf, n = pqs.to_device(data)
+        torch.cuda.synchronize()
+        log(f"config {name}: {n / 1e9:.3f} GB file generated in {time.perf_counter() - t0:.1f} s")
+        flush.fill_(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = pqs.DeviceFile(buf, n)
+        torch.cuda.synchronize()
+        open_ms = (time.perf_counter() - t0) * 1e3
+        st = f.stats()
+        types = {c: f.column_info(c).type for c in range(f.num_columns)}
+        pya_s = pyarrow_seconds(data, 3)
+        for pname, cols in projections:
+            mask, rg_end, ws, outs, tens = f.allocate(cols)
+            dec = decoded_bytes(tens, types)
+            scan = lambda: f.scan_into(mask, 0, rg_end, outs, ws)
+            first_ms = timed(scan, 1, False) if pname == projections[0][0] else None
+            for _ in range(3):
+                scan()
+            f.check(ws)
+            warm = timed(scan, reps, False)
+            cold = timed(scan, reps, True)
+            f.check(ws)
+            f.profile(True)
+            scan()
+            torch.cuda.synchronize()
+            prof = f.profile_read()
+            f.profile(False)
+            dec_ms = sum(t for k, (nl, t) in prof.items() if not k.startswith("k_snappy"))
+            dcmp_ms = sum(t for k, (nl, t) in prof.items() if k.startswith("k_snappy"))
+            comp = sum(sum(f.column_bytes(c)) for c in cols)
+            unc = sum(md.row_group(g).column(c).total_uncompressed_size for g in range(md.num_row_groups) for c in cols)
+            alg = comp + dec
+            row = {"config": name, "projection": pname, "workload": workload, "columns": cols,
+                   "file_bytes": n, "pages": st.pages, "dict_pages": st.dict_pages, "row_groups": f.num_row_groups,
+                   "decoded_bytes": dec, "encoded_bytes": comp, "open_ms": round(open_ms, 2),
+                   "warm_p50_ms": round(warm, 4), "cold_p50_ms": round(cold, 4), "reps": reps,
+                   "decoded_gbps_warm": round(dec / warm / 1e6, 1), "decoded_gbps_cold": round(dec / cold / 1e6, 1),
+                   "algorithmic_bytes": alg, "algorithmic_gbps": round(alg / warm / 1e6, 1),
+                   "frac_of_8tbs": round(alg / warm / 1e6 / HBM_PEAK_GBS, 4)}
+            cg = copy_gbps(alg // 2)
+            row["copy_gbps_same_bytes"] = round(cg, 1)
+            row["pct_of_copy"] = round(100 * (alg / warm / 1e6) / cg, 1)
+            if first_ms is not None:
+                row["open_inclusive_cold_ms"] = round(open_ms + first_ms, 2)
+                row["open_inclusive_gbps"] = round(dec / (open_ms + first_ms) / 1e6, 2)
+            if dcmp_ms > 0:
+                row.update({"uncompressed_bytes": unc, "decompress_ms": round(dcmp_ms, 3),
+                            "decode_ms": round(dec_ms, 3),
+                            "staged_algorithmic_bytes": (comp + unc) + (unc + dec),
+                            "decompress_gbps": round((comp + unc) / dcmp_ms / 1e6, 1),
+                            "decode_gbps": round((unc + dec) / dec_ms / 1e6, 1)})
+            if with_oracle:
+                osec, ob, core = oracle_seconds(data, cols)
+                row["oracle"] = {"seconds": round(osec, 3), "gbps": round(ob / osec / 1e9, 4), "core": core,
+                                 "cpu_model": cpu["model"], "nproc": cpu["nproc"]}
+            row["pyarrow_all_cores_s"] = round(pya_s, 3)
+            log(f"config {name} {pname}: warm {warm:.3f} ms, cold {cold:.3f} ms, {row['decoded_gbps_warm']} GB/s "
+                f"decoded, {row['pct_of_copy']}% of copy" + (f", oracle {row['oracle']['gbps']} GB/s" if with_oracle else ""))
+            out.write(json.dumps(row) + "\n")
+            out.flush()
+            del ws, outs, tens
+        f.close()
+        del buf, data
+        torch.cuda.empty_cache()
+
+    run("C0", dg.small_table(), [("all", [0, 1])],
+        "2 REQUIRED columns, 1,000,000 rows, 1 row group, 1 MiB pages, uncompressed")
+    for rg in (1_000_000, 8_000_000, 64_000_000):
+        for page in (64 * 1024, 1 << 20, 8 << 20):
+            run(f"C1 rg{rg // 1_000_000}M page{page // 1024}KiB", dg.wide_table(64_000_000, rg, page),
+                [("P16", list(range(16)))],
+                f"wide16, 64,000,000 rows, row groups of {rg:,}, {page // 1024} KiB pages, uncompressed")
+    run("C2", dg.snappy_wide_table(64_000_000, 64_000_000, 1 << 20),
+        [("P1", [15]), ("P4", [0, 6, 10, 13]), ("P16", list(range(16)))],
+        "wide16, 64,000,000 rows, one row group, 1 MiB pages, Snappy, 1 MiB dictionary cap")
+    out.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,6 +650,9 @@ def main():
     ap.add_argument("--stream-rows", type=int, default=64_000_000,
                     help="rows of the streamed-from-host-memory run (0 skips it)")
     ap.add_argument("--stream-rg-rows", type=int, default=4_000_000, help="row-group rows of the streamed run")
+    ap.add_argument("--configs-report", default=None,
+                    help="write one JSON line per configuration (sweep, Snappy projections, C0) to this path "
+                         "and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this scanner is built and measured on one GPU "
@@ -476,6 +664,9 @@ def main():
     import paper_2602_17335_amd as pqs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.configs_report:
+        bench_configs(args.configs_report, args.steps, log, not args.no_cpu_baseline)
+        return
     if args.codec == "snappy":
         def spec_fn(rows, rg):
             return dg.snappy_wide_table(rows, rg, args.page_bytes)
@@ -514,10 +705,18 @@ def main():
     dec = decoded_bytes(tens, types)
     stream = torch.cuda.current_stream()
 
+    # the first scan after the open, timed alone (the open-inclusive figure)
+    e_a = torch.cuda.Event(enable_timing=True)
+    e_b = torch.cuda.Event(enable_timing=True)
+    e_a.record(stream)
+    f.scan_into(mask, 0, rg_end, outs, ws)
+    e_b.record(stream)
+    torch.cuda.synchronize()
+    first_ms = e_a.elapsed_time(e_b)
     for _ in range(args.warmup):
         f.scan_into(mask, 0, rg_end, outs, ws)
     f.check(ws)
-    log(f"warmup done ({args.warmup} scans)")
+    log(f"warmup done ({args.warmup} scans; the first scan after the open took {first_ms:.3f} ms)")
 
     f.profile(True)
     torch.cuda.synchronize()
@@ -561,10 +760,37 @@ def main():
     def pct(v, q):
         return round(v[min(len(v) - 1, int(round(q * (len(v) - 1))))], 4)
     latency = {"scans": len(warm), "p50_ms": pct(warm, 0.5), "p99_ms": pct(warm, 0.99),
-               "cold_scans": len(cold), "cold_p50_ms": pct(cold, 0.5), "cold_p99_ms": pct(cold, 0.99),
-               "cold_gbps": round(dec / (pct(cold, 0.5) / 1e3) / 1e9, 2)}
+               "evicted_scans": len(cold), "evicted_p50_ms": pct(cold, 0.5), "evicted_p99_ms": pct(cold, 0.99),
+               "evicted_gbps": round(dec / (pct(cold, 0.5) / 1e3) / 1e9, 2),
+               "open_inclusive_ms": round(open_ms + first_ms, 2),
+               "open_inclusive_gbps": round(dec / ((open_ms + first_ms) / 1e3) / 1e9, 2)}
     log(f"latency: warm p50 {latency['p50_ms']} ms, p99 {latency['p99_ms']} ms; "
-        f"cold (L2/MALL evicted) p50 {latency['cold_p50_ms']} ms = {latency['cold_gbps']} GB/s")
+        f"L2/MALL evicted before each scan p50 {latency['evicted_p50_ms']} ms = {latency['evicted_gbps']} GB/s; "
+        f"open + first scan {latency['open_inclusive_ms']} ms = {latency['open_inclusive_gbps']} GB/s")
+    # the practical ceiling: the library's plain copy of the scan's
+    # algorithmic bytes (encoded read + decoded written), moved as a copy
+    enc = sum(sum(f.column_bytes(c)) for c in cols)
+    half = (enc + dec) // 32 * 16
+    csrc = torch.empty(half, dtype=torch.uint8, device="cuda")
+    cdst = torch.empty(half, dtype=torch.uint8, device="cuda")
+    pqs.copy_probe(cdst, csrc, half)
+    cv = []
+    for _ in range(5):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pqs.copy_probe(cdst, csrc, half)
+        b.record(stream)
+        torch.cuda.synchronize()
+        cv.append(a.elapsed_time(b))
+    del csrc, cdst
+    cv.sort()
+    copy_gbps = 2 * half / cv[2] / 1e6
+    scan_alg_gbps = (enc + dec) / ms / 1e6
+    copy_ref = {"bytes_moved": 2 * half, "ms": round(cv[2], 4), "gbps": round(copy_gbps, 1),
+                "scan_algorithmic_gbps": round(scan_alg_gbps, 1), "pct_of_copy": round(100 * scan_alg_gbps / copy_gbps, 1)}
+    log(f"copy of the same {2 * half / 1e9:.2f} GB: {copy_gbps:.0f} GB/s; the scan moves its algorithmic bytes at "
+        f"{scan_alg_gbps:.0f} GB/s = {copy_ref['pct_of_copy']}% of copy")
 
     key = f"rows={args.rows}:rg={args.rg_rows}:page={args.page_bytes}:codec={args.codec}:cols={args.columns}"
     per = {}
@@ -627,7 +853,7 @@ def main():
                    "pages": st.pages, "dict_pages": st.dict_pages, "tiles": st.tiles,
                    "open_ms": round(open_ms, 2), "open_ms_device": round(st.open_ms_device, 2),
                    "form": "plain (one launch per kernel kind per scan)", "kernels": kern,
-                   "latency": latency},
+                   "latency": latency, "copy_reference": copy_ref},
         "roofline": roof,
         "batched_vs_plain": batch,
         "serving": serve,

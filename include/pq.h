@@ -270,6 +270,15 @@ typedef struct {
 pq_status pq_profile(pq_file f, int32_t enable);
 pq_status pq_profile_read(pq_file f, pq_kernel_time* out, int32_t capacity, int32_t* n);
 
+/* Measurement reference (Sec. 3's effective bandwidth is compared with what
+   the memory system sustains): enqueues a plain streaming copy of `bytes`
+   bytes from device buffer src to device buffer dst on `stream` (16-byte
+   loads, non-temporal 16-byte stores; the buffers must not overlap and
+   should be 16-byte aligned).  The copy's bytes over its time are the
+   practical ceiling a scan's encoded-plus-decoded bytes are reported
+   against ("% of copy"). */
+pq_status pq_copy_probe(void* dst, const void* src, uint64_t bytes, pq_stream stream);
+
 /*
  * Batched scans: several requests, over one or several opened files, in one
  * set of launches (Sec. 3, Insight 1: a GPU decoder needs many independent

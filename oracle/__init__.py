@@ -225,6 +225,28 @@ class File:
     def column_optional(self, col: int) -> bool:
         return bool(lib().orc_column_optional(self._h, col))
 
+    def decode_seconds(self, col: int, rg_begin: int = 0, rg_end: Optional[int] = None):
+        """Times one call of the oracle's column decode (its own output
+        allocation included, no copy into Python arrays); returns (seconds,
+        decoded bytes: validity + values, or offsets + chars)."""
+        import time
+        if rg_end is None:
+            rg_end = self.num_row_groups
+        c = _Column()
+        t0 = time.perf_counter()
+        rc = lib().orc_read_column(self._h, col, rg_begin, rg_end, ctypes.byref(c))
+        dt = time.perf_counter() - t0
+        if rc != 0:
+            _err(rc)
+        try:
+            rows = c.rows
+            t = self.column_type(col)
+            n = (rows + 7) // 8
+            n += 8 * (rows + 1) + c.chars_len if t == 6 else rows * np.dtype(_NP[t]).itemsize
+            return dt, n
+        finally:
+            lib().orc_column_free(ctypes.byref(c))
+
     def read(self, col: int, rg_begin: int = 0, rg_end: Optional[int] = None) -> dict:
         """Decoded rows of `col` over [rg_begin, rg_end): a dict with
         "values" (fixed width) or "offsets"+"chars" (BYTE_ARRAY), "validity",

@@ -23,7 +23,7 @@ EXPORTS = ("pq_open_device", "pq_num_row_groups", "pq_num_columns", "pq_column_i
            "pq_profile_read", "pq_close", "pq_last_error", "pq_tuning_default", "pq_plan_batch", "pq_scan_batch",
            "pq_autotune_batch", "pq_scan_noalloc", "pq_server_create", "pq_server_submit", "pq_server_wait",
            "pq_server_release", "pq_server_stats_get", "pq_server_destroy", "pq_server_last_error",
-           "pq_open_host", "pq_scan_streamed")
+           "pq_open_host", "pq_scan_streamed", "pq_copy_probe")
 FORM_BATCHED, FORM_PER_PAGE = 0, 1
 TUNE_CLASSES = 54
 
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         vp, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
         L.pq_open_device.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
         L.pq_open_host.argtypes = [vp, u64, vp, ctypes.POINTER(vp)]
+        L.pq_copy_probe.argtypes = [vp, vp, u64, vp]
         L.pq_scan_streamed.argtypes = [vp, u64, i32, i32, ctypes.POINTER(ColumnOut), i32, vp, u64, vp, vp]
         L.pq_num_row_groups.argtypes = [vp, ctypes.POINTER(i32)]
         L.pq_num_columns.argtypes = [vp, ctypes.POINTER(i32)]
@@ -140,7 +141,7 @@ def lib() -> ctypes.CDLL:
                      "pq_column_bytes", "pq_column_encodings", "pq_profile", "pq_profile_read",
                      "pq_tuning_default", "pq_plan_batch", "pq_scan_batch", "pq_autotune_batch",
                      "pq_server_create", "pq_server_submit", "pq_server_wait", "pq_server_release",
-                     "pq_server_stats_get", "pq_open_host", "pq_scan_streamed"):
+                     "pq_server_stats_get", "pq_open_host", "pq_scan_streamed", "pq_copy_probe"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -155,6 +156,13 @@ def _stream_ptr(stream) -> Optional[int]:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def copy_probe(dst, src, nbytes: int, stream=None):
+    """Enqueues the library's plain streaming copy of nbytes from device
+    tensor src to device tensor dst (the "% of copy" reference)."""
+    _check(lib().pq_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                               ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def validity_bytes(rows: int) -> int:

@@ -36,6 +36,7 @@ __global__ void k_dict(const PageDev* pages, const uint32_t* strck, const DictSl
                        uint32_t nworks, uint32_t* err);
 __global__ void k_prepass(uint8_t* ws, const ColScan* cols, SegTable seg, int mode, uint32_t* err);
 __global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, uint32_t* err);
+__global__ void k_copy(uint8_t* dst, const uint8_t* src, uint64_t n);
 enum : int { FX_DICT = 1, FX_WIDE = 2, FX_BSS = 4 };
 template <int KIND>
 __global__ void k_decode_fixed(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
@@ -2056,6 +2057,17 @@ extern "C" pq_status pq_column_encodings(pq_file f, int32_t col, uint32_t* mask)
 }
 
 static pq_file prof_of(pq_file f) { return f ? f : &g_batch_prof; }
+
+extern "C" pq_status pq_copy_probe(void* dst, const void* src, uint64_t bytes, pq_stream stream) {
+  if (!bytes) return PQ_OK;
+  if (!dst || !src) return fail(PQ_EINVAL, "NULL buffer");
+  const uint64_t chunks = bytes >> 4;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(16384, (chunks + 1023) / 1024));
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream, static_cast<uint8_t*>(dst),
+                     static_cast<const uint8_t*>(src), bytes);
+  HIP_OR(hipGetLastError());
+  return PQ_OK;
+}
 
 extern "C" pq_status pq_profile(pq_file f, int32_t enable) {
   f = prof_of(f);

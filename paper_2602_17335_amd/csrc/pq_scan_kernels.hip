@@ -1575,6 +1575,28 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
 
 
 // ---------------------------------------------------------------------------
+// k_copy: a plain streaming copy (16-byte loads and non-temporal stores,
+// grid-stride, four chunks in flight per thread), the practical ceiling a
+// scan's bytes are compared with; bytes past the last whole 16-byte chunk
+// are copied one by one.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_copy(uint8_t* dst, const uint8_t* src, uint64_t n) {
+  typedef const __attribute__((address_space(1))) u32x4 gv4;
+  const uint64_t nch = n >> 4;
+  const uint64_t stride = (uint64_t)gridDim.x * WG;
+  uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+  for (; i + 3 * stride < nch; i += 4 * stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = *((gv4*)src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], (gout_u32x4*)dst + i + u * stride);
+  }
+  for (; i < nch; i += stride) __builtin_nontemporal_store(*((gv4*)src + i), (gout_u32x4*)dst + i);
+  if (blockIdx.x == 0 && threadIdx.x < (n & 15)) dst[(nch << 4) + threadIdx.x] = src[(nch << 4) + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // k_prep: validity words shared by two tiles are cleared before any tile
 // ORs into them; REQUIRED columns with a validity buffer get all ones.
 // ---------------------------------------------------------------------------

@@ -9,7 +9,8 @@ compared with the CPU oracle byte for byte through the C ABI:
   (1024 values in 32 miniblocks), which must be refused at open;
 - the small two-column table at its full size (1,000,000 rows, 1 MiB pages);
 - one handle scanned on two streams at once, each scan with its own
-  workspace, against the single-stream result.
+  workspace, against the single-stream result;
+- the library's streaming copy used as the bench's practical ceiling.
 """
 import sys
 
@@ -108,3 +109,18 @@ def test_two_streams_one_handle():
     for (cols, b, e), res in zip(jobs, alone):
         for c in cols:
             compare_column(of.read(c, b, e), res[c], f"two-streams col{c} rg[{b},{e})")
+
+
+def test_copy_probe():
+    """The library's streaming copy (the bench's "% of copy" reference)
+    copies every byte, including a ragged tail past the last 16-byte chunk,
+    and leaves the bytes after the destination range alone."""
+    import torch
+    import paper_2602_17335_amd as pqs
+    for n in (1, 15, 16, 4097, (3 << 20) + 7, 64 << 20):
+        src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.full((n + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+        pqs.copy_probe(dst, src, n)
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:n], src), n
+        assert bool((dst[n:] == 0xAB).all()), n
