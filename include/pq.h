@@ -14,7 +14,10 @@
  * REQUIRED and OPTIONAL columns; V1 and V2 data pages; PLAIN,
  * PLAIN_DICTIONARY, RLE_DICTIONARY and DELTA_BINARY_PACKED (INT32/INT64;
  * blocks of at most 65536 values in at most 16 miniblocks -- larger blocks
- * are valid Parquet and return PQ_EUNSUPPORTED); codecs UNCOMPRESSED and
+ * are valid Parquet and return PQ_EUNSUPPORTED); BYTE_STREAM_SPLIT (INT32,
+ * INT64, DOUBLE); DELTA_LENGTH_BYTE_ARRAY and DELTA_BYTE_ARRAY (strings; a
+ * DELTA_BYTE_ARRAY page holding a value longer than 16 KiB returns
+ * PQ_EUNSUPPORTED when its column is scanned); codecs UNCOMPRESSED and
  * SNAPPY.
  *
  * Output layout (per selected column, rows of the selected row groups

@@ -20,7 +20,8 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
                        const uint32_t* page_base, PageDev* pages, uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
-                        uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order);
+                        uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order,
+                        const uint8_t* xscratch, uint64_t xscratch_lim);
 __global__ void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand);
 __global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
                               uint32_t* seg_base, uint32_t* ok);
@@ -37,6 +38,8 @@ __global__ void k_dict(const PageDev* pages, const uint32_t* strck, const DictSl
 __global__ void k_prepass(uint8_t* ws, const ColScan* cols, SegTable seg, int mode, uint32_t* err);
 __global__ void k_str_total(const ColScan* cols, const int32_t* which, int32_t n, uint32_t* err);
 __global__ void k_copy(uint8_t* dst, const uint8_t* src, uint64_t n);
+__global__ void k_dba(const ColScan* cols, SegTable seg, uint8_t* ws, const uint8_t* open_scratch, uint8_t* open_out,
+                      PageDev* pages_out, int mode, uint32_t* err);
 enum : int { FX_DICT = 1, FX_WIDE = 2, FX_BSS = 4 };
 template <int KIND>
 __global__ void k_decode_fixed(uint8_t* ws, const ColScan* cols, SegTable seg, uint32_t* err);
@@ -266,6 +269,7 @@ struct pq_file_s {
   std::vector<uint32_t> chunk_tile0;     // first tile of each chunk (+ sentinel)
   std::vector<PageDev> pages;            // host copy (after the index pass)
   std::vector<uint64_t> scratch_prefix;  // per page (+ sentinel): file-wide scratch offset
+  std::vector<uint64_t> xscratch_prefix; // per page (+ sentinel): expansion-layout offset (DELTA_BYTE_ARRAY pages)
   uint64_t total_tiles = 0, total_strck = 0;
   PageDev* d_pages = nullptr;
   TileDev* d_tiles = nullptr;
@@ -566,7 +570,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       row += pg.num_values;
       pg.tile_begin = (uint32_t)tiles;
       tiles += ((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS;
-      if (cd.type == T_BYTE_ARRAY && pg.encoding == E_PLAIN) {
+      if (cd.type == T_BYTE_ARRAY && (pg.encoding == E_PLAIN || pg.encoding == E_DBA)) {
         pg.strck_begin = (uint32_t)strck;
         strck += (uint64_t)pg.num_values / STR_CK + 1;
       }
@@ -574,6 +578,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   }
   f->chunk_tile0[nchunks] = (uint32_t)tiles;
   f->scratch_prefix[npages] = scratch;
+  f->xscratch_prefix.assign(npages + 1, 0);
   if (tiles > 0xffffffffull) { free_handle(f); return fail(PQ_EUNSUPPORTED, "too many tiles"); }
   f->total_tiles = tiles;
   f->total_strck = strck;
@@ -583,15 +588,22 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   ColScan* d_cs = nullptr;
   uint32_t* d_order = nullptr;
   uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
+  uint8_t* d_xscratch = nullptr;  // DELTA_BYTE_ARRAY pages expanded to the PLAIN layout
+  ColScan* d_xcols = nullptr;     // their column tables
+  uint64_t xscratch = 0;          // bytes of the expansion layout
   auto cleanup_open = [&]() {
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_cs) (void)hipFree(d_cs);
     if (d_order) (void)hipFree(d_order);
     if (d_schain) (void)hipFree(d_schain);
+    if (d_xscratch) (void)hipFree(d_xscratch);
+    if (d_xcols) (void)hipFree(d_xcols);
     d_scratch = nullptr;
     d_cs = nullptr;
     d_order = nullptr;
     d_schain = nullptr;
+    d_xscratch = nullptr;
+    d_xcols = nullptr;
   };
   if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
   // Snappy block index, recorded by the decompression below
@@ -620,6 +632,61 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     const uint32_t waves = npages;
     hipLaunchKernelGGL(k_snappy, dim3(waves), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
+  }
+  // ---- DELTA_BYTE_ARRAY pages: facts, expansion layout, expansion ----
+  {
+    std::vector<ColScan> xc;
+    std::vector<Segment> xs;
+    uint32_t xw = 0;
+    for (int c = 0; c < f->ncols; ++c) {
+      if (f->cols[c].type != T_BYTE_ARRAY) continue;
+      const uint32_t p0 = f->chunk_page0[(size_t)c * f->nrg], p1 = f->chunk_page0[(size_t)(c + 1) * f->nrg];
+      bool any = false;
+      for (uint32_t pp = p0; pp < p1 && !any; ++pp) any = f->pages[pp].kind != PAGE_DICT && f->pages[pp].encoding == E_DBA;
+      if (!any) continue;
+      ColScan cs;
+      memset(&cs, 0, sizeof(cs));
+      cs.fd.file = file;
+      cs.fd.pages = f->d_pages;
+      cs.type = T_BYTE_ARRAY;
+      cs.optional = f->cols[c].optional;
+      cs.col = c;
+      cs.page_begin = p0;
+      cs.page_end = p1;
+      xs.push_back(Segment{(uint32_t)xc.size(), p0, p1, xw});
+      xw += p1 - p0;
+      xc.push_back(cs);
+    }
+    if (!xc.empty()) {
+      if (xs.size() > MAX_SEGS) { cleanup_open(); free_handle(f); return fail(PQ_EUNSUPPORTED, "too many DELTA_BYTE_ARRAY columns"); }
+      if (hipMalloc(&d_xcols, sizeof(ColScan) * xc.size()) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
+      OPEN_HIP(hipMemcpyAsync(d_xcols, xc.data(), sizeof(ColScan) * xc.size(), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, d_scratch,
+                         (uint8_t*)nullptr, f->d_pages, 0, f->d_err);
+      if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
+      {
+        pq_status stx = read_err(f, s);
+        if (stx != PQ_OK) { cleanup_open(); free_handle(f); return stx; }
+      }
+      OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
+      for (uint32_t pp = 0; pp < npages; ++pp) {
+        PageDev& pg = f->pages[pp];
+        f->xscratch_prefix[pp] = xscratch;
+        if (pg.kind == PAGE_DICT || pg.encoding != E_DBA || f->chunks[pg.chunk].type != T_BYTE_ARRAY ||
+            pg.x_total == DBA_UNSUPPORTED)
+          continue;
+        pg.x_off = xscratch;
+        xscratch += align_up((uint64_t)pg.xlen + SCRATCH_PAD, 16);
+      }
+      f->xscratch_prefix[npages] = xscratch;
+      OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
+      if (xscratch) {
+        if (hipMalloc(&d_xscratch, xscratch) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for expansion"); }
+        hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, d_scratch,
+                           d_xscratch, f->d_pages, 1, f->d_err);
+        if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
+      }
+    }
   }
   if (tiles) {
     if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess ||
@@ -651,7 +718,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     }
     hipLaunchKernelGGL(k_index, dim3(npages), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
                        f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
-                       (uint64_t)scratch, d_order);
+                       (uint64_t)scratch, d_order, d_xscratch, xscratch);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
     // long string dictionaries: their length chains, segments side by side
     std::vector<SChainPage> scp;
@@ -952,6 +1019,8 @@ struct Plan {
   std::vector<int32_t> str_cols;    // string ColScan indices (k_str_total)
   // units: pages (k_snappy), tiles (k_prep threads; one wave per tile elsewhere)
   std::vector<Segment> sblk_segs;  // k_snappy_blk: blocks of the compressed pages, one lane each
+  std::vector<Segment> dba_segs;   // k_dba: pages of columns with DELTA_BYTE_ARRAY pages, one wave each
+  uint32_t dba_waves = 0;
   uint32_t sblk_lanes = 0;
   bool str_spread[2] = {false, false}, fixed_spread[8] = {};  // columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[8] = {}, delta_units = 0, str_units[2] = {0, 0},
@@ -973,6 +1042,7 @@ struct ColSetup {
   bool has_delta = false, has_plain = false, has_dict = false, has_slots = false, has_bss = false;
   uint32_t nt = 0;        // tiles
   uint64_t sbytes = 0;    // decompressed bytes of its compressed pages
+  uint64_t xbytes = 0;    // expansion bytes of its DELTA_BYTE_ARRAY pages
   uint32_t b0 = 0, b1 = 0;  // its Snappy blocks
 };
 
@@ -995,6 +1065,10 @@ void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint6
   k.sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
   cs.ws_scratch = off;
   off = align_up(off + k.sbytes, 256);
+  cs.xscratch_base = f->xscratch_prefix[cs.page_begin];
+  k.xbytes = f->xscratch_prefix[cs.page_end] - cs.xscratch_base;
+  cs.ws_xscratch = off;
+  off = align_up(off + k.xbytes, 256);
   for (uint32_t p = cs.page_begin; p < cs.page_end; ++p) {
     if (f->pages[p].kind == PAGE_DICT) continue;
     const int e = f->pages[p].encoding;
@@ -1083,6 +1157,10 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
         P.sblk_lanes += k.b1 - k.b0;
       }
     }
+    if (k.xbytes) {
+      P.dba_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.dba_waves});
+      P.dba_waves += cs.page_end - cs.page_begin;
+    }
     P.cols.push_back(cs);
   }
   // The string kernel's columns, and those of the 8-byte dictionary kernel,
@@ -1155,7 +1233,7 @@ static pq_status upload_header(Plan& P, uint8_t* ws, hipStream_t s) {
 // d_cols).
 static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_cols, uint8_t* ws, uint32_t* err,
                                     hipStream_t s) {
-  for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
+  for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.dba_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.fixed_segs[4], &P.fixed_segs[6], &P.delta_segs, &P.str_segs[0], &P.str_segs[1],
                         &P.edge_segs})
     if (v->size() > MAX_SEGS) return fail(PQ_EUNSUPPORTED, "too many segments");
@@ -1168,6 +1246,11 @@ static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_c
     ProfScope ps_(f, KP_SNAPPY_BLK, s);
     hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
                        d_cols, make_segs(P.sblk_segs), ws, err);
+    HIP_OR(hipGetLastError());
+  }
+  if (P.dba_waves) {  // DELTA_BYTE_ARRAY pages (after their decompression) to the PLAIN layout
+    hipLaunchKernelGGL(k_dba, dim3(P.dba_waves), dim3(64), 0, s, d_cols, make_segs(P.dba_segs), ws,
+                       (const uint8_t*)nullptr, (uint8_t*)nullptr, (PageDev*)nullptr, 1, err);
     HIP_OR(hipGetLastError());
   }
   return PQ_OK;
@@ -1578,8 +1661,8 @@ struct BatchPlan {
   std::vector<ColScan> cols;
   std::vector<int32_t> str_cols;
   std::vector<int64_t> chars;  // per column, in request order
-  std::vector<Segment> snappy_segs, sblk_segs, edge_segs, prep_segs;
-  uint32_t snappy_waves = 0, sblk_lanes = 0, edge_threads = 0, prep_threads = 0;
+  std::vector<Segment> snappy_segs, sblk_segs, edge_segs, prep_segs, dba_segs;
+  uint32_t snappy_waves = 0, sblk_lanes = 0, edge_threads = 0, prep_threads = 0, dba_waves = 0;
   // same-kind tile runs: consecutive pages of one column with one decoder
   // and work class
   struct Run { uint32_t cs, t0, t1, kind, cls, chunk; };
@@ -1588,9 +1671,10 @@ struct BatchPlan {
   std::vector<Run> page_runs;      // one per data page (the per-page form's launches)
   struct SnapPage { uint32_t cs, page, b0, b1; };
   std::vector<SnapPage> snap_pages;  // compressed data pages and their Snappy blocks
+  std::vector<std::pair<uint32_t, uint32_t>> dba_pages;  // (column, page) of DELTA_BYTE_ARRAY pages
   uint64_t total_tiles = 0;
   uint64_t ws_cols = 0, ws_which = 0, ws_snappy = 0, ws_sblk = 0, ws_edge = 0, ws_prep = 0, ws_units = 0,
-           ws_qbeg = 0, ws_qhead = 0, ws_hdr_end = 0, ws_total = 0;
+           ws_qbeg = 0, ws_qhead = 0, ws_hdr_end = 0, ws_total = 0, ws_dba = 0;
 };
 
 pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
@@ -1626,6 +1710,8 @@ pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
   off = align_up(off + sizeof(Segment) * (snappy_segs ? snappy_segs : 1), 256);
   P.ws_sblk = off;
   off = align_up(off + sizeof(Segment) * (snappy_segs ? snappy_segs : 1), 256);
+  P.ws_dba = off;
+  off = align_up(off + sizeof(Segment) * (snappy_segs ? snappy_segs : 1), 256);
   P.ws_edge = off;
   off = align_up(off + sizeof(Segment) * (ncols ? ncols : 1), 256);
   P.ws_prep = off;
@@ -1657,6 +1743,10 @@ pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
           P.sblk_lanes += k.b1 - k.b0;
         }
       }
+      if (k.xbytes) {
+        P.dba_segs.push_back(Segment{idx, cs.page_begin, cs.page_end, P.dba_waves});
+        P.dba_waves += cs.page_end - cs.page_begin;
+      }
       if (k.nt) {
         if (cs.optional) {
           P.edge_segs.push_back(Segment{idx, cs.tile_begin, cs.tile_end, P.edge_threads});
@@ -1673,6 +1763,7 @@ pq_status make_batch_plan(const pq_request* reqs, int32_t n, BatchPlan& P) {
           const uint32_t nb = (uint32_t)(((uint64_t)pg.scratch_len + SNAP_BLOCK - 1) / SNAP_BLOCK);
           P.snap_pages.push_back(BatchPlan::SnapPage{idx, p, pg.sblk_begin, pg.sblk_begin + nb});
         }
+        if (pg.encoding == E_DBA && cs.type == T_BYTE_ARRAY) P.dba_pages.push_back({idx, p});
         const uint32_t nt = (uint32_t)(((uint64_t)(pg.num_values > 0 ? pg.num_values : 0) + TILE_ROWS - 1) / TILE_ROWS);
         if (!nt) continue;
         const uint32_t kind = tile_kind(f, pg, cs), cls = tune_class(kind, pg, nt);
@@ -1806,6 +1897,7 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
   put(P.ws_which, P.str_cols.data(), sizeof(int32_t) * P.str_cols.size());
   put(P.ws_snappy, P.snappy_segs.data(), sizeof(Segment) * P.snappy_segs.size());
   put(P.ws_sblk, P.sblk_segs.data(), sizeof(Segment) * P.sblk_segs.size());
+  put(P.ws_dba, P.dba_segs.data(), sizeof(Segment) * P.dba_segs.size());
   put(P.ws_edge, P.edge_segs.data(), sizeof(Segment) * P.edge_segs.size());
   put(P.ws_prep, P.prep_segs.data(), sizeof(Segment) * P.prep_segs.size());
   if (!per_page) {
@@ -1845,6 +1937,21 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
                            d_cols, make_segs(one), ws, err);
         HIP_OR(hipGetLastError());
       }
+    }
+  }
+  // DELTA_BYTE_ARRAY pages to the PLAIN layout (after their decompression)
+  if (!per_page) {
+    if (P.dba_waves) {
+      hipLaunchKernelGGL(k_dba, dim3(P.dba_waves), dim3(64), 0, s, d_cols, seg_table(P.dba_segs, ws, P.ws_dba), ws,
+                         (const uint8_t*)nullptr, (uint8_t*)nullptr, (PageDev*)nullptr, 1, err);
+      HIP_OR(hipGetLastError());
+    }
+  } else {
+    for (const auto& dp : P.dba_pages) {
+      std::vector<Segment> one{Segment{dp.first, dp.second, dp.second + 1, 0}};
+      hipLaunchKernelGGL(k_dba, dim3(1), dim3(64), 0, s, d_cols, make_segs(one), ws, (const uint8_t*)nullptr,
+                         (uint8_t*)nullptr, (PageDev*)nullptr, 1, err);
+      HIP_OR(hipGetLastError());
     }
   }
   if (!P.str_cols.empty()) {

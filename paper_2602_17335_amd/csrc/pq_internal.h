@@ -122,7 +122,8 @@ struct PageDev {
   uint8_t kind;          // PAGE_DATA, PAGE_DICT, PAGE_DATA_V2 (index pages are dropped)
   uint8_t encoding;
   uint8_t v2_compressed; // V2 is_compressed flag (default 1)
-  uint8_t flags;         // bit0: level stream in scratch; bit1: value stream in scratch
+  uint8_t flags;         // bit0: level stream in scratch; bit1: value stream in scratch;
+                         // bit2: value stream in the expansion region (DELTA_BYTE_ARRAY)
   int32_t def_len;       // level bytes (V2 header; V1 from the body)
   int32_t rep_len;       // V2 header
   uint64_t def_off;      // file offset, or offset inside the page's scratch region
@@ -147,7 +148,22 @@ struct PageDev {
   uint32_t sblk_begin;   // compressed pages: first entry of the page in the Snappy block index
   uint32_t chars_at;     // DELTA_LENGTH_BYTE_ARRAY pages: value-stream offset of the chars
                          // (the end of the lengths' DELTA_BINARY_PACKED stream)
+  // DELTA_BYTE_ARRAY string pages (found by the open-time pass of k_dba):
+  // the encoded value stream (x_src: offset in the file, or in the
+  // decompression layout when x_scratch), its prefix-length stream from 0,
+  // suffix-length stream from x_sfx and suffix bytes from x_chars; the
+  // page's values laid out as PLAIN (u32 length + bytes, xlen bytes) at
+  // x_off of the expansion layout
+  uint64_t x_src;
+  uint32_t x_len, x_sfx, x_chars, xlen, x_total, x_scratch;
+  uint64_t x_off;
 };
+// x_total of a DELTA_BYTE_ARRAY page the scan does not decode (a value longer
+// than the expansion's LDS buffer, or a DELTA block shape outside the
+// supported one): its tiles report PQ_EUNSUPPORTED when its column is scanned
+constexpr uint32_t DBA_UNSUPPORTED = 0xffffffffu;
+// page encoding given to such a page by the index pass
+constexpr uint8_t E_UNDECODED = 0xff;
 // Snappy block index: a compressed page's output is cut into SNAP_BLOCK-byte
 // blocks; entry b holds the stream offset of the element that starts block
 // b.  A page's first entry is SBLK_NONE when some element straddles a block
@@ -229,6 +245,8 @@ struct FileDev {
 // caller's workspace before the kernels run).
 struct ColScan {
   FileDev fd;             // the tables of the file this column belongs to
+  uint64_t ws_xscratch;   // workspace offset of the expansion region of its DELTA_BYTE_ARRAY pages
+  uint64_t xscratch_base; // expansion-layout offset of the region's first byte
   int32_t type;
   int32_t optional;
   int32_t width;          // 4 or 8 (fixed width); 0 for BYTE_ARRAY

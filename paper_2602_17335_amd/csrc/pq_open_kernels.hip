@@ -78,6 +78,7 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
       p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
       p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u; p.dict_maxlen = 0;
       p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.sblk_begin = 0; p.chars_at = 0;
+      p.x_src = 0; p.x_len = 0; p.x_sfx = 0; p.x_chars = 0; p.xlen = 0; p.x_total = 0; p.x_scratch = 0; p.x_off = 0;
       pages[page_base[q] + n] = p;
     }
     ++n;
@@ -281,7 +282,7 @@ __device__ __forceinline__ Ck ck_none() {
 __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                                               const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl,
                                               Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim,
-                                              const uint32_t* order) {
+                                              const uint32_t* order, const uint8_t* xscratch, uint64_t xscratch_lim) {
   __shared__ wr_u4 s_win[WIN / 16];
   // DELTA pages of at most TC tiles: first value, value count and value
   // entry of every tile, so that the block walk reads no tile from memory
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   // Tiles and the page entry are stored by every lane (each lane reads back
   // its own stores).
   const bool lead = (threadIdx.x & 63) == 0;
-  auto lim_of = [&](const uint8_t* b) { return b == file ? file_lim : scratch_lim; };
+  auto lim_of = [&](const uint8_t* b) { return b == file ? file_lim : (b == xscratch ? xscratch_lim : scratch_lim); };
 
   if (pg.kind == PAGE_DICT) {
     const uint8_t* base = in_scratch ? scratch : file;
@@ -381,6 +382,16 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       val_len = pg.comp_size - (uint64_t)pg.rep_len - def_len;
       pg.flags = 0;
     }
+  }
+  if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY && pg.x_total == DBA_UNSUPPORTED) {
+    pg.encoding = E_UNDECODED;  // reported by the decode kernels when the column is scanned
+  } else if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY) {
+    // DELTA_BYTE_ARRAY: the values, expanded to the PLAIN layout by k_dba,
+    // are indexed and decoded like a PLAIN page
+    vbase = xscratch;
+    val_off = pg.x_off;
+    val_len = pg.xlen;
+    pg.flags = (uint8_t)((pg.flags & 1) | 4);
   }
   pg.def_off = def_off;
   pg.def_len = (int32_t)def_len;
@@ -465,7 +476,8 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   if ((enc == E_PLAIN || enc == E_BSS) && ch.type != T_BYTE_ARRAY) {
     uint64_t w = ch.type == T_INT32 ? 4 : 8;
     if ((uint64_t)nonnull * w > val_len) { set_err(err, ERR_VALUES, p); return; }
-  } else if (enc == E_PLAIN) {
+  } else if (enc == E_PLAIN || enc == E_DBA) {
+    if (enc == E_DBA && pg.x_total != nonnull) { set_err(err, ERR_VALUES, p); return; }
     uint64_t q = val_off;
     uint32_t t = 0;
     for (uint32_t k = 0; k <= nonnull; ++k) {

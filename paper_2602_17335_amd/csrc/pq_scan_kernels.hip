@@ -2,6 +2,7 @@
 // and k_prepass, which pq_open_device runs once to build the tile prefix.
 //
 //   k_snappy        Snappy page bodies -> workspace (one wave per page)
+//   k_dba           DELTA_BYTE_ARRAY pages -> PLAIN layout (one wave per page)
 //   k_snappy_blk    Snappy page bodies with a block index (one lane per 64 KiB block,
 //                   SNAP_LANES blocks per wave)
 //   k_prep          validity edge words cleared / REQUIRED validity set to ones
@@ -85,7 +86,8 @@ __device__ __forceinline__ Streams page_streams(const PageDev& pg, const ColScan
   if (pg.flags & 1) { s.dbase = sb; s.doff = pg.def_off - cs.scratch_base; }
   else { s.dbase = file; s.doff = pg.def_off; }
   s.dend = s.doff + (uint64_t)pg.def_len;
-  if (pg.flags & 2) { s.vbase = sb; s.voff = pg.val_off - cs.scratch_base; }
+  if (pg.flags & 4) { s.vbase = ws + cs.ws_xscratch; s.voff = pg.val_off - cs.xscratch_base; }
+  else if (pg.flags & 2) { s.vbase = sb; s.voff = pg.val_off - cs.scratch_base; }
   else { s.vbase = file; s.voff = pg.val_off; }
   s.vend = s.voff + pg.val_len;
   return s;
@@ -1575,6 +1577,284 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
 
 
 // ---------------------------------------------------------------------------
+// k_dba: DELTA_BYTE_ARRAY string pages, one wave per page.  Value k is the
+// first prefix[k] bytes of value k - 1 followed by suffix k, a chain through
+// the page, so a wave walks the page's values in order: the prefix lengths
+// and the suffix lengths (two DELTA_BINARY_PACKED streams) are decoded 64 at
+// a time, the previous value is kept in LDS and the suffix bytes pass
+// through an LDS window.
+//   mode 0 (at open): finds the page's value stream (as the index pass
+//     does) and the start of its second stream and of the suffix bytes,
+//     checks every prefix against the previous value's length, and stores
+//     the page's facts in pages_out (x_src, x_len, x_sfx, x_chars, xlen,
+//     x_total, x_scratch);
+//   mode 1: writes the values in the PLAIN layout (u32 length, then the
+//     bytes) into the page's expansion region, where the index pass and the
+//     string kernels read them as a PLAIN page.
+// At open the decompression layout and the expansion region are passed
+// directly (open_scratch, open_out); in a scan they lie in the workspace.
+// ---------------------------------------------------------------------------
+constexpr uint32_t DBA_PREV = 16384;  // longest value (a page with a longer one: PQ_EUNSUPPORTED when scanned)
+constexpr uint32_t DBA_WIN = 16384;   // suffix-byte window
+
+// Wave-uniform byte read.
+__device__ __forceinline__ uint32_t ubyte(const uint8_t* p) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)*p);
+}
+
+// A DELTA_BINARY_PACKED stream of 32-bit values read in order, every field
+// wave-uniform.
+struct DeltaSeq {
+  const uint8_t* s;  // stream start
+  uint32_t end;      // stream bytes
+  uint32_t q;        // next byte after the blocks read so far
+  uint32_t B, per, M, total, done, blocks;
+  uint32_t last, mind;
+  uint32_t mb, used_mb, in_mb, mbq, wq, w;
+  bool bad, unsupported;
+
+  __device__ uint64_t uleb() {
+    uint64_t v = 0;
+    for (uint32_t sh = 0;; sh += 7) {
+      if (q >= end || sh > 63) { bad = true; return 0; }
+      const uint32_t b = ubyte(s + q++);
+      v |= (uint64_t)(b & 0x7f) << sh;
+      if (!(b & 0x80)) return v;
+    }
+  }
+  __device__ void init(const uint8_t* stream, uint32_t len) {
+    s = stream; end = len; q = 0; bad = false; unsupported = false;
+    const uint64_t b = uleb(), m = uleb(), t = uleb(), f = uleb();
+    if (bad || b == 0 || b % 128 != 0 || m == 0 || b % m != 0 || (b / m) % 32 != 0 || t > 0x7fffffffull) { bad = true; return; }
+    if (m > 16 || b > 65536) { unsupported = true; bad = true; return; }
+    B = (uint32_t)b; M = (uint32_t)m; per = B / M; total = (uint32_t)t;
+    last = (uint32_t)(f >> 1) ^ (0u - (uint32_t)(f & 1));  // zigzag, 32-bit
+    done = 0; blocks = 0; mb = used_mb = 0; in_mb = 0; mbq = q; wq = q; w = 0;
+  }
+  __device__ void start_mb() {
+    w = ubyte(s + wq + mb);
+    if (w > 32 || (uint64_t)mbq + (uint64_t)per * w / 8 > end) bad = true;
+  }
+  __device__ void next_block() {
+    const uint64_t md = uleb();
+    mind = (uint32_t)(md >> 1) ^ (0u - (uint32_t)(md & 1));
+    if (bad || M > end - q) { bad = true; return; }
+    wq = q;
+    q += M;
+    const uint32_t left = total - 1 - blocks * B;
+    const uint32_t used = left < B ? left : B;
+    used_mb = (used + per - 1) / per;
+    mb = 0; in_mb = 0; mbq = q;
+    ++blocks;
+    start_mb();
+  }
+  // the next n (<= 64, <= total - done) values into buf[0, n)
+  __device__ void fill(__attribute__((address_space(3))) uint32_t* buf, uint32_t n, uint32_t lane) {
+    uint32_t o = 0;
+    if (done == 0 && n) {
+      if (lane == 0) buf[0] = last;
+      o = 1;
+      done = 1;
+    }
+    while (o < n && !bad) {
+      if (mb >= used_mb) { next_block(); if (bad) break; }
+      const uint32_t cnt = min(n - o, per - in_mb);
+      uint32_t d = 0;
+      if (lane < cnt && w) {
+        const uint64_t bit = (uint64_t)(in_mb + lane) * w;
+        const uintptr_t a = (uintptr_t)(s + mbq + (bit >> 3));
+        const __attribute__((address_space(1))) uint32_t* al = (const __attribute__((address_space(1))) uint32_t*)(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3) * 8 + (uint32_t)(bit & 7);
+        const uint64_t x = (((uint64_t)al[1] << 32) | al[0]) >> sh;
+        d = w == 32 ? (uint32_t)x : (uint32_t)x & ((1u << w) - 1u);
+      }
+      const uint32_t incl = wave_incl_scan_u32(lane < cnt ? mind + d : 0u);
+      const uint32_t v = last + incl;
+      if (lane < cnt) buf[o + lane] = v;
+      last = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(cnt - 1));
+      o += cnt; done += cnt; in_mb += cnt;
+      if (in_mb == per) {
+        mbq += per * w / 8;
+        ++mb;
+        in_mb = 0;
+        if (mb < used_mb) start_mb();
+        else q = mbq;
+      }
+    }
+  }
+};
+
+__global__ __launch_bounds__(64) void k_dba(const ColScan* cols, SegTable seg, uint8_t* ws, const uint8_t* open_scratch,
+                                            uint8_t* open_out, PageDev* pages_out, int mode, uint32_t* err) {
+  __shared__ uint32_t s_p[64], s_s[64];
+  __shared__ __align__(16) uint8_t s_prev[DBA_PREV];
+  __shared__ __align__(16) uint8_t s_win[DBA_WIN + 32];
+  const uint32_t lane = threadIdx.x & 63;
+  const Segment sg = seg_lookup(seg, blockIdx.x);
+  const uint32_t p = sg.t0 + (blockIdx.x - sg.wg0);
+  if (p >= sg.t1) return;
+  const ColScan* csp = cols + sg.cs;
+  const FileDev fd = csp->fd;
+  const PageDev pg = fd.pages[p];
+  if (pg.kind == PAGE_DICT || pg.encoding != E_DBA || csp->type != T_BYTE_ARRAY) return;
+  // the decompression layout (file-wide offsets)
+  const uint8_t* sbase = open_scratch ? open_scratch : ws + csp->ws_scratch - csp->scratch_base;
+  typedef __attribute__((address_space(3))) uint32_t lds_w32;
+  lds_w32* bp = (lds_w32*)&s_p[0];
+  lds_w32* bs = (lds_w32*)&s_s[0];
+  if (mode == 0) {
+    // the value stream, as the index pass finds it
+    const bool in_scratch = pg.scratch_len > 0;
+    uint64_t vo = 0, vl = 0;
+    bool bad = false;
+    const uint8_t* base = in_scratch ? sbase : fd.file;
+    if (pg.kind == PAGE_DATA) {
+      const uint64_t off = in_scratch ? pg.scratch_off : pg.payload, blen = pg.uncomp_size;
+      if (csp->optional) {
+        if (blen < 4) bad = true;
+        else {
+          const uint64_t L = ubyte(base + off) | ubyte(base + off + 1) << 8 | ubyte(base + off + 2) << 16 |
+                             (uint64_t)ubyte(base + off + 3) << 24;
+          if (L > blen - 4) bad = true;
+          vo = off + 4 + L;
+          vl = blen - 4 - L;
+        }
+      } else {
+        vo = off;
+        vl = blen;
+      }
+    } else if (in_scratch) {
+      vo = pg.scratch_off;
+      vl = pg.scratch_len;
+    } else {
+      const uint64_t lv = (uint64_t)pg.rep_len + (uint64_t)pg.def_len;
+      vo = pg.payload + lv;
+      vl = lv <= pg.comp_size ? pg.comp_size - lv : 0;
+    }
+    if (bad || vl >= 0x80000000ull) { if (lane == 0) set_err(err, ERR_STRING, p); return; }
+    const uint8_t* src = base + vo;
+    DeltaSeq P, S;
+    P.init(src, (uint32_t)vl);
+    // the prefix stream to its end: the suffix-length stream starts there
+    while (!P.bad && P.done < P.total) P.fill(bp, min(64u, P.total - P.done), lane);
+    // a stream ends after the miniblock holding its last value (padded)
+    if (!P.bad && P.mb < P.used_mb) P.q = P.mbq + P.per * P.w / 8;
+    const uint32_t sfx = P.q;
+    if (!P.bad) S.init(src + sfx, (uint32_t)vl - sfx);
+    while (!P.bad && !S.bad && S.done < S.total) S.fill(bs, min(64u, S.total - S.done), lane);
+    if (!S.bad && S.mb < S.used_mb) S.q = S.mbq + S.per * S.w / 8;
+    const uint32_t chars = sfx + S.q;
+    if (P.unsupported || S.unsupported) {  // valid, but not decoded here: reported when scanned
+      if (lane == 0) pages_out[p].x_total = DBA_UNSUPPORTED;
+      return;
+    }
+    if (P.bad || S.bad || S.total != P.total) {
+      if (lane == 0) set_err(err, ERR_DELTA, p);
+      return;
+    }
+    // again side by side: every prefix within the previous value, every
+    // value at most DBA_PREV bytes, the suffix bytes within the stream
+    P.init(src, (uint32_t)vl);
+    S.init(src + sfx, (uint32_t)vl - sfx);
+    uint64_t prevlen = 0, sum = 0, sfx_sum = 0;
+    uint32_t code = 0;
+    while (P.done < P.total && !code) {
+      const uint32_t n = min(64u, P.total - P.done);
+      P.fill(bp, n, lane);
+      S.fill(bs, n, lane);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t j = 0; j < n; ++j) {
+        const uint64_t pl = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[j]);
+        const uint64_t sl = (uint32_t)__builtin_amdgcn_readfirstlane((int)bs[j]);
+        if (pl > prevlen || (int32_t)pl < 0 || (int32_t)sl < 0) { code = ERR_STRING; break; }
+        if (pl + sl > DBA_PREV) { code = ERR_UNSUPPORTED; break; }
+        prevlen = pl + sl;
+        sum += 4 + pl + sl;
+        sfx_sum += sl;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (!code && ((uint64_t)chars + sfx_sum > vl || sum >= 0x80000000ull)) code = ERR_STRING;
+    if (code == ERR_UNSUPPORTED) { if (lane == 0) pages_out[p].x_total = DBA_UNSUPPORTED; return; }
+    if (code) { if (lane == 0) set_err(err, code, p); return; }
+    if (lane == 0) {
+      PageDev& o = pages_out[p];
+      o.x_src = vo;
+      o.x_len = (uint32_t)vl;
+      o.x_sfx = sfx;
+      o.x_chars = chars;
+      o.xlen = (uint32_t)sum;
+      o.x_total = P.total;
+      o.x_scratch = in_scratch ? 1u : 0u;
+    }
+    return;
+  }
+  // mode 1: the values in the PLAIN layout
+  if (pg.x_total == DBA_UNSUPPORTED) return;
+  const uint8_t* src = (pg.x_scratch ? sbase : fd.file) + pg.x_src;
+  uint8_t* out = open_out ? open_out + pg.x_off : ws + csp->ws_xscratch + (pg.x_off - csp->xscratch_base);
+  DeltaSeq P, S;
+  P.init(src, pg.x_len);
+  S.init(src + pg.x_sfx, pg.x_len - pg.x_sfx);
+  if (P.bad || S.bad) { if (lane == 0) set_err(err, ERR_DELTA, p); return; }
+  const uint8_t* chars = src + pg.x_chars;
+  const uint32_t nchars = pg.x_len - pg.x_chars;
+  lds_u8* prev = (lds_u8*)&s_prev[0];
+  lds_u8* win = (lds_u8*)&s_win[0];
+  uint32_t wlo = 0, whi = 0;  // window: suffix bytes [wlo, whi) at win[0..]
+  uint32_t pos = 0, c = 0;
+  while (P.done < P.total) {
+    const uint32_t n = min(64u, P.total - P.done);
+    P.fill(bp, n, lane);
+    S.fill(bs, n, lane);
+    if (P.bad || S.bad) { if (lane == 0) set_err(err, ERR_DELTA, p); return; }
+    wave_sync();
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint32_t pl = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp[j]);
+      const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane((int)bs[j]);
+      const uint32_t L = pl + sl;
+      if (L > DBA_PREV || (uint64_t)c + sl > nchars) { if (lane == 0) set_err(err, ERR_STRING, p); return; }
+      if (c < wlo || c + sl > whi) {
+        // refill: suffix bytes from c (16-byte chunks from the one holding it)
+        const uintptr_t g0 = (uintptr_t)(chars + c) & ~(uintptr_t)15;
+        const uint32_t lead = (uint32_t)((uintptr_t)(chars + c) - g0);
+        typedef const __attribute__((address_space(1))) u32x4 gv4;
+        wave_sync();
+        // chunks past the stream's last byte are not read (a chunk holding
+        // it reads at most 15 bytes past it, inside the page's padding or
+        // the bytes that follow it in the file)
+        const uintptr_t gend = (uintptr_t)(chars + nchars);
+        for (uint32_t k = lane; 16 * k < DBA_WIN + 16; k += 64) {
+          u32x4 v = {0u, 0u, 0u, 0u};
+          if (g0 + 16 * k < gend) v = *(gv4*)(g0 + 16 * k);
+          *reinterpret_cast<__attribute__((address_space(3))) u32x4*>(win + 16 * k) = v;
+        }
+        wave_sync();
+        wlo = c - lead;  // window byte i holds suffix byte wlo + i (wlo may lie before the stream: never read)
+        whi = wlo + DBA_WIN + 16;
+      }
+      for (uint32_t i = lane; i < 4 + L; i += 64) {
+        uint32_t b;
+        if (i < 4) {
+          b = (L >> (8 * i)) & 0xffu;
+        } else if (i - 4 < pl) {
+          b = prev[i - 4];
+        } else {
+          b = win[c - wlo + (i - 4 - pl)];
+          prev[i - 4] = (uint8_t)b;
+        }
+        out[pos + i] = (uint8_t)b;
+      }
+      wave_sync();
+      pos += 4 + L;
+      c += sl;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_copy: a plain streaming copy (16-byte loads and non-temporal stores,
 // grid-stride, four chunks in flight per thread), the practical ceiling a
 // scan's bytes are compared with; bytes past the last whole 16-byte chunk
@@ -1907,7 +2187,7 @@ __global__ __launch_bounds__(WG) void k_prepass(uint8_t* __restrict__ ws, const 
     if (lane == 0) *aux = 0;
     return;
   }
-  if (is_str && enc == E_PLAIN) {
+  if (is_str && (enc == E_PLAIN || enc == E_DBA)) {
     if (lane == 0) *aux = (uint64_t)c.td.val_skip - c.td.val_pos - 4ull * c.td.nn;
     return;
   }
@@ -2220,7 +2500,7 @@ __device__ __forceinline__ void tile_str(const WaveTile& c, uint8_t* __restrict_
   const Ck ckx = c.cs.fd.ckv[(size_t)c.t * NSUB + ((lane_id<LOOP>() & 63) >> 2)];
   const uint32_t lane = lane_id<LOOP>() & 63;
   const int enc = c.pg.encoding;
-  const bool is_plain = !SLOTS && enc == E_PLAIN;
+  const bool is_plain = !SLOTS && (enc == E_PLAIN || enc == E_DBA);  // DELTA_BYTE_ARRAY: expanded to PLAIN
   const bool is_dlba = !SLOTS && enc == E_DLBA;
   const bool is_dict = enc == E_PLAIN_DICT || enc == E_RLE_DICT;
   DictSlot sl;

@@ -3,9 +3,9 @@ overlapped reading): the file stays in pinned host memory, each row group's
 selected column chunks are copied into one of two device staging slots while
 the previous row group decodes, and every output buffer must equal the
 oracle's byte for byte -- uncompressed and Snappy, V1 and V2 pages,
-dictionary, PLAIN, DELTA, BYTE_STREAM_SPLIT and DELTA_LENGTH_BYTE_ARRAY
-columns, column subsets, row-group sub-ranges (so that a slot is reused many
-times) and the single-row-group file.  A host handle is refused by the
+dictionary, PLAIN, DELTA, BYTE_STREAM_SPLIT, DELTA_LENGTH_BYTE_ARRAY and
+DELTA_BYTE_ARRAY columns, column subsets, row-group sub-ranges (so that a
+slot is reused many times) and the single-row-group file.  A host handle is refused by the
 device-resident scan calls."""
 import numpy as np
 import pytest
@@ -42,6 +42,7 @@ def _mixed(version, codec, rows=300_017, rg=40_000, page=32 * dg.KiB):
         dg.Col(dg.DOUBLE, dg.BYTE_STREAM_SPLIT, True, dg.UNIFORM, 0.3),
         dg.Col(dg.BYTE_ARRAY, dg.DELTA_LENGTH_BYTE_ARRAY, True, dg.STRINGS, 0.1, hi=100_000, str_min=8, str_max=44),
         dg.Col(dg.DOUBLE, dg.RLE_DICTIONARY, False, dg.DICTVALS, hi=40_000),
+        dg.Col(dg.BYTE_ARRAY, dg.DELTA_BYTE_ARRAY, True, dg.STRINGS, 0.1, hi=3000, str_min=0, str_max=30),
     ], num_rows=rows, rg_rows=rg, page_bytes=page, page_version=version, codec=codec,
         name=f"streamed-v{version}-c{codec}")
 
@@ -53,7 +54,7 @@ def test_streamed_all_columns(version, codec):
 
 def test_streamed_subsets_and_ranges():
     data = dg.write(_mixed(1, dg.SNAPPY))
-    _streamed(data, [0, 3, 6], 2, 7, label="cols 0,3,6 rg[2,7)")
+    _streamed(data, [0, 3, 6, 8], 2, 7, label="cols 0,3,6,8 rg[2,7)")
     _streamed(data, [5], 7, 8, label="col 5 last row group")
     _streamed(data, [1, 4], 3, 3, label="empty range")
 
@@ -67,9 +68,9 @@ def test_streamed_equals_device_scan():
     import paper_2602_17335_amd as pqs
     data = dg.write(_mixed(2, dg.SNAPPY, rows=200_003, rg=25_000))
     buf, n = pqs.to_device(data)
-    d = pqs.DeviceFile(buf, n).scan(list(range(8)))
-    h = pqs.HostFile(data).scan(list(range(8)))
-    for c in range(8):
+    d = pqs.DeviceFile(buf, n).scan(list(range(9)))
+    h = pqs.HostFile(data).scan(list(range(9)))
+    for c in range(9):
         for k in ("values", "offsets", "chars", "validity_words"):
             if k in d[c]:
                 assert np.array_equal(d[c][k].cpu().numpy(), h[c][k].cpu().numpy()), (c, k)
