@@ -21,7 +21,17 @@ __global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks,
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order,
-                        const uint8_t* xscratch, uint64_t xscratch_lim);
+                        const uint8_t* xscratch, uint64_t xscratch_lim, int phase);
+__global__ void k_lv_cand(const LvPage* lps, const uint32_t* seg_page, const PageDev* pages, const uint8_t* file,
+                          const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim, LvCand* cand);
+__global__ void k_lv_link(const LvPage* lps, int npg, const PageDev* pages, const LvCand* cand, LvEntry* ent,
+                          uint32_t* ok, uint32_t* err);
+__global__ void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const LvEntry* ent, const uint32_t* ok,
+                           PageDev* pages, const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                           uint64_t scratch_lim, TileDev* tiles, uint32_t* err, int mode);
+__global__ void k_lv_ckpt(const LvPage* lps, const uint32_t* tile_lp, const PageDev* pages, const TileDev* tiles,
+                          const uint8_t* file, const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                          uint32_t* ckl, const uint32_t* err);
 __global__ void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand);
 __global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
                               uint32_t* seg_base, uint32_t* ok);
@@ -588,6 +598,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   ColScan* d_cs = nullptr;
   uint32_t* d_order = nullptr;
   uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
+  uint8_t* d_lv = nullptr;      // long level streams: segment and tile tables of their walk
   uint8_t* d_xscratch = nullptr;  // DELTA_BYTE_ARRAY pages expanded to the PLAIN layout
   ColScan* d_xcols = nullptr;     // their column tables
   uint64_t xscratch = 0;          // bytes of the expansion layout
@@ -596,12 +607,14 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     if (d_cs) (void)hipFree(d_cs);
     if (d_order) (void)hipFree(d_order);
     if (d_schain) (void)hipFree(d_schain);
+    if (d_lv) (void)hipFree(d_lv);
     if (d_xscratch) (void)hipFree(d_xscratch);
     if (d_xcols) (void)hipFree(d_xcols);
     d_scratch = nullptr;
     d_cs = nullptr;
     d_order = nullptr;
     d_schain = nullptr;
+    d_lv = nullptr;
     d_xscratch = nullptr;
     d_xcols = nullptr;
   };
@@ -705,11 +718,13 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     // rounded up to 16
     std::vector<uint32_t> order(npages);
     std::vector<uint64_t> work(npages);
+    std::vector<uint32_t> lv_list;  // pages whose levels the k_lv kernels walk
     for (uint32_t p = 0; p < npages; ++p) {
       const PageDev& pg = f->pages[p];
       const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY && pg.uncomp_size <= SCHAIN_MIN;
       work[p] = sdict ? 16ull * pg.uncomp_size : (uint64_t)(pg.num_values > 0 ? pg.num_values : 0);
       order[p] = p;
+      if (pg.kind != PAGE_DICT && lv_page(pg, f->chunks[pg.chunk].optional != 0)) lv_list.push_back(p);
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
     if (hipMalloc(&d_order, sizeof(uint32_t) * npages) != hipSuccess ||
@@ -718,8 +733,65 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     }
     hipLaunchKernelGGL(k_index, dim3(npages), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
                        f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
-                       (uint64_t)scratch, d_order, d_xscratch, xscratch);
+                       (uint64_t)scratch, d_order, d_xscratch, xscratch, 1);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
+    // long level streams: their exact lengths (stored by the launch above),
+    // then candidates, link, tile entries, checkpoints and the value streams
+    if (!lv_list.empty()) {
+      OPEN_HIP(hipMemcpyAsync(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost, s));
+      OPEN_HIP(hipStreamSynchronize(s));
+      std::vector<LvPage> lps;
+      std::vector<uint32_t> seg_page, tile_lp, order2;
+      for (uint32_t p : lv_list) {
+        const PageDev& pg = f->pages[p];
+        LvPage x;
+        x.page = p;
+        x.seg0 = (uint32_t)seg_page.size();
+        x.nseg = (uint32_t)(((uint64_t)(pg.def_len > 0 ? pg.def_len : 0) + LV_SEG - 1) / LV_SEG);
+        x.tl0 = (uint32_t)tile_lp.size();
+        const uint32_t nt = (uint32_t)(((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS);
+        for (uint32_t j = 0; j < x.nseg; ++j) seg_page.push_back((uint32_t)lps.size());
+        for (uint32_t j = 0; j < nt; ++j) tile_lp.push_back((uint32_t)lps.size());
+        lps.push_back(x);
+        order2.push_back(p);
+      }
+      std::stable_sort(order2.begin(), order2.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
+      const size_t npg = lps.size(), nseg = seg_page.size(), ntl = tile_lp.size();
+      const size_t o_seg = align_up(sizeof(LvPage) * npg, 256), o_tl = align_up(o_seg + 4 * nseg, 256),
+                   o_ord = align_up(o_tl + 4 * ntl, 256), o_cand = align_up(o_ord + 4 * npg, 256),
+                   o_ent = align_up(o_cand + sizeof(LvCand) * LV_CAND * nseg, 256),
+                   o_ok = align_up(o_ent + sizeof(LvEntry) * nseg, 256), total = o_ok + 4 * npg;
+      if (hipMalloc(&d_lv, total) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: level walk tables"); }
+      LvPage* d_lps = reinterpret_cast<LvPage*>(d_lv);
+      uint32_t* d_segp = reinterpret_cast<uint32_t*>(d_lv + o_seg);
+      uint32_t* d_tlp = reinterpret_cast<uint32_t*>(d_lv + o_tl);
+      uint32_t* d_ord2 = reinterpret_cast<uint32_t*>(d_lv + o_ord);
+      LvCand* d_cand = reinterpret_cast<LvCand*>(d_lv + o_cand);
+      LvEntry* d_ent = reinterpret_cast<LvEntry*>(d_lv + o_ent);
+      uint32_t* d_ok = reinterpret_cast<uint32_t*>(d_lv + o_ok);
+      OPEN_HIP(hipMemcpyAsync(d_lps, lps.data(), sizeof(LvPage) * npg, hipMemcpyHostToDevice, s));
+      if (nseg) OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
+      if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_lp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
+      OPEN_HIP(hipMemcpyAsync(d_ord2, order2.data(), 4 * npg, hipMemcpyHostToDevice, s));
+      const uint64_t flim = (len + 15) & ~15ull;
+      if (nseg)
+        hipLaunchKernelGGL(k_lv_cand, dim3((uint32_t)nseg), dim3(LV_CAND), 0, s, d_lps, d_segp, f->d_pages, file,
+                           d_scratch, flim, (uint64_t)scratch, d_cand);
+      hipLaunchKernelGGL(k_lv_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_lps, (int)npg, f->d_pages,
+                         d_cand, d_ent, d_ok, f->d_err);
+      if (nseg)
+        hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)nseg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages,
+                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 0);
+      hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)npg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages, file,
+                         d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 1);
+      if (ntl)
+        hipLaunchKernelGGL(k_lv_ckpt, dim3((uint32_t)ntl), dim3(64), 0, s, d_lps, d_tlp, f->d_pages, f->d_tiles, file,
+                           d_scratch, flim, (uint64_t)scratch, f->d_ckl, f->d_err);
+      hipLaunchKernelGGL(k_index, dim3((uint32_t)npg), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npg,
+                         f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, (uint64_t)scratch,
+                         d_ord2, d_xscratch, xscratch, 2);
+      if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_lv launch failed"); }
+    }
     // long string dictionaries: their length chains, segments side by side
     std::vector<SChainPage> scp;
     std::vector<uint32_t> seg_page;

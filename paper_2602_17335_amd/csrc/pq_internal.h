@@ -158,6 +158,40 @@ struct PageDev {
   uint32_t x_len, x_sfx, x_chars, xlen, x_total, x_scratch;
   uint64_t x_off;
 };
+
+// Definition-level streams of OPTIONAL data pages (the levels before the
+// values, Sec. 3.3) are hybrid RLE/bit-packed run chains whose run headers
+// are only found by walking from the start.  Pages whose body may hold more
+// than LV_MIN level bytes are indexed in LV_SEG-byte segments side by side:
+// LV_CAND candidate chains per segment (one from each of its first LV_CAND
+// bytes), a per-page link through the candidates' exits, then the tile
+// entries per segment and the level checkpoints per tile.
+constexpr uint32_t LV_MIN = 8192;
+constexpr uint32_t LV_SEG = 16384;
+constexpr uint32_t LV_CAND = 128;
+constexpr uint32_t LV_NONE = 0xffffffffu;
+__host__ __device__ inline bool lv_page(const PageDev& pg, bool optional) {
+  if (!optional || pg.num_values <= 0) return false;
+  if (pg.kind == PAGE_DATA) return pg.uncomp_size >= 4u + LV_MIN;  // level bytes <= body - 4
+  if (pg.kind == PAGE_DATA_V2) return pg.def_len > (int32_t)LV_MIN;
+  return false;
+}
+struct LvPage {
+  uint32_t page, seg0, nseg;  // segments [seg0, seg0 + nseg) of the segment list
+  uint32_t tl0;               // first entry of the page in the tile list
+};
+// A candidate chain of one segment: stream offset where it leaves the
+// segment, rows and valid rows of the runs that start in it (saturating at
+// 2^32 - 1), and how it ended (0: left the segment or reached the stream end;
+// 1: at an invalid run; 2: at a run not held by the staged bytes).
+struct LvCand {
+  uint32_t exit, state, rows, valid;
+};
+// The true chain's entry into a segment (stream offset; LV_NONE: the segment
+// is not walked) with the rows and valid rows before it.
+struct LvEntry {
+  uint32_t q, rows, valid, pad_;
+};
 // x_total of a DELTA_BYTE_ARRAY page the scan does not decode (a value longer
 // than the expansion's LDS buffer, or a DELTA block shape outside the
 // supported one): its tiles report PQ_EUNSUPPORTED when its column is scanned

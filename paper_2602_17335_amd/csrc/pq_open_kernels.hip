@@ -4,6 +4,9 @@
 //            level and value streams of each data page, string checkpoints.
 //   k_schain_cand / k_schain_link / k_schain_fill / k_schain_seq
 //            string checkpoints of long dictionary pages, segments side by side
+//   k_lv_cand / k_lv_link / k_lv_tiles / k_lv_ckpt
+//            tile entries, level checkpoints and non-null counts of pages
+//            with long definition-level streams, segments side by side
 #include <hip/hip_runtime.h>
 
 #include "pq_device.hpp"
@@ -282,7 +285,8 @@ __device__ __forceinline__ Ck ck_none() {
 __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                                               const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl,
                                               Ck* ckv, uint32_t* err, uint64_t file_lim, uint64_t scratch_lim,
-                                              const uint32_t* order, const uint8_t* xscratch, uint64_t xscratch_lim) {
+                                              const uint32_t* order, const uint8_t* xscratch, uint64_t xscratch_lim,
+                                              int phase) {
   __shared__ wr_u4 s_win[WIN / 16];
   // DELTA pages of at most TC tiles: first value, value count and value
   // entry of every tile, so that the block walk reads no tile from memory
@@ -348,62 +352,82 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
   }
 
   // ---- stream layout of a data page ----
-  const uint8_t* dbase;
-  const uint8_t* vbase;
+  // Pages with long level streams (lv_page) are indexed in two launches:
+  // phase 1 stores their stream layout and leaves the levels to the k_lv
+  // kernels, which store the tile entries, level checkpoints and non-null
+  // count; phase 2 then indexes their value streams.
+  const uint8_t* dbase = file;
+  const uint8_t* vbase = file;
   uint64_t def_off = 0, def_len = 0, val_off = 0, val_len = 0;
-  if (pg.kind == PAGE_DATA) {
-    const uint8_t* base = in_scratch ? scratch : file;
-    uint64_t off = in_scratch ? pg.scratch_off : pg.payload;
-    uint64_t blen = pg.uncomp_size;
-    dbase = vbase = base;
-    r.init(base, lim_of(base), win);
-    if (ch.optional) {
-      if (blen < 4) { set_err(err, ERR_LEVELS, p); return; }
-      uint64_t L = r.u32(off);
-      if (L > blen - 4) { set_err(err, ERR_LEVELS, p); return; }
-      def_off = off + 4; def_len = L;
-      val_off = off + 4 + L; val_len = blen - 4 - L;
-    } else {
-      val_off = off; val_len = blen;
-    }
-    pg.flags = in_scratch ? 3 : 0;
-  } else {
-    dbase = file;
-    def_off = pg.payload + (uint64_t)pg.rep_len;
+  const bool lvp = lv_page(pg, ch.optional);
+  if (phase == 2) {
+    if (*(volatile uint32_t*)err != 0) return;  // the open has failed already
+    vbase = (pg.flags & 4) ? xscratch : ((pg.flags & 2) ? scratch : file);
+    def_off = pg.def_off;
     def_len = (uint64_t)pg.def_len;
-    if (in_scratch) {
-      vbase = scratch;
-      val_off = pg.scratch_off;
-      val_len = pg.scratch_len;
-      pg.flags = 2;
+    val_off = pg.val_off;
+    val_len = pg.val_len;
+  } else {
+    if (pg.kind == PAGE_DATA) {
+      const uint8_t* base = in_scratch ? scratch : file;
+      uint64_t off = in_scratch ? pg.scratch_off : pg.payload;
+      uint64_t blen = pg.uncomp_size;
+      dbase = vbase = base;
+      r.init(base, lim_of(base), win);
+      if (ch.optional) {
+        if (blen < 4) { set_err(err, ERR_LEVELS, p); return; }
+        uint64_t L = r.u32(off);
+        if (L > blen - 4) { set_err(err, ERR_LEVELS, p); return; }
+        def_off = off + 4; def_len = L;
+        val_off = off + 4 + L; val_len = blen - 4 - L;
+      } else {
+        val_off = off; val_len = blen;
+      }
+      pg.flags = in_scratch ? 3 : 0;
     } else {
-      vbase = file;
-      val_off = def_off + def_len;
-      val_len = pg.comp_size - (uint64_t)pg.rep_len - def_len;
-      pg.flags = 0;
+      dbase = file;
+      def_off = pg.payload + (uint64_t)pg.rep_len;
+      def_len = (uint64_t)pg.def_len;
+      if (in_scratch) {
+        vbase = scratch;
+        val_off = pg.scratch_off;
+        val_len = pg.scratch_len;
+        pg.flags = 2;
+      } else {
+        vbase = file;
+        val_off = def_off + def_len;
+        val_len = pg.comp_size - (uint64_t)pg.rep_len - def_len;
+        pg.flags = 0;
+      }
+    }
+    if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY && pg.x_total == DBA_UNSUPPORTED) {
+      pg.encoding = E_UNDECODED;  // reported by the decode kernels when the column is scanned
+    } else if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY) {
+      // DELTA_BYTE_ARRAY: the values, expanded to the PLAIN layout by k_dba,
+      // are indexed and decoded like a PLAIN page
+      vbase = xscratch;
+      val_off = pg.x_off;
+      val_len = pg.xlen;
+      pg.flags = (uint8_t)((pg.flags & 1) | 4);
+    }
+    pg.def_off = def_off;
+    pg.def_len = (int32_t)def_len;
+    pg.val_off = val_off;
+    pg.val_len = (uint32_t)val_len;
+    if (lvp) {
+      pages[p] = pg;
+      return;
     }
   }
-  if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY && pg.x_total == DBA_UNSUPPORTED) {
-    pg.encoding = E_UNDECODED;  // reported by the decode kernels when the column is scanned
-  } else if (pg.encoding == E_DBA && ch.type == T_BYTE_ARRAY) {
-    // DELTA_BYTE_ARRAY: the values, expanded to the PLAIN layout by k_dba,
-    // are indexed and decoded like a PLAIN page
-    vbase = xscratch;
-    val_off = pg.x_off;
-    val_len = pg.xlen;
-    pg.flags = (uint8_t)((pg.flags & 1) | 4);
-  }
-  pg.def_off = def_off;
-  pg.def_len = (int32_t)def_len;
-  pg.val_off = val_off;
-  pg.val_len = (uint32_t)val_len;
 
   const int64_t nv = pg.num_values;
   const uint32_t ntiles = (uint32_t)((nv + TILE_ROWS - 1) / TILE_ROWS);
 
   // ---- definition levels: tile entry points, sub-tile checkpoints, non-null counts ----
   uint32_t nonnull = 0;
-  if (ch.optional) {
+  if (phase == 2) {
+    nonnull = pg.nonnull;
+  } else if (ch.optional) {
     r.init(dbase, lim_of(dbase), win);
     const uint64_t end = def_off + def_len;
     RunCur c;
@@ -757,6 +781,307 @@ __global__ __launch_bounds__(64) void k_schain_seq(const SChainPage* pgs, int np
     }
   }
   if (lead) pages[sp.page].dict_maxlen = maxlen;
+}
+
+// ---------------------------------------------------------------------------
+// Long definition-level streams.  The levels of an OPTIONAL page are a chain
+// of hybrid runs of 1-bit values (a ULEB128 header; bit-packed: groups of 8
+// values, one byte each; RLE: a count and one value byte), cut here into
+// LV_SEG-byte segments.  k_lv_cand: lane c of a segment's workgroup walks the
+// chain that starts at byte c of the segment, summing the rows and valid rows
+// of the runs whose header lies in the segment, until it leaves it.  Runs are
+// short (a bit-packed run of 63 groups takes 65 bytes), so the true chain
+// enters each segment within its first LV_CAND bytes; k_lv_link follows it
+// from segment to segment through the candidates' exits, up to the run that
+// covers the page's last row.  k_lv_tiles walks each segment's true chain
+// once more from its entry, storing the entries of the tiles whose first row
+// lies in its runs and, in the segment of the last row, the page's non-null
+// count; a page whose chain leaves the candidates is walked whole by one wave
+// (mode 1).  k_lv_ckpt then derives each tile's level checkpoints from its
+// entry, one checkpoint per lane.
+// ---------------------------------------------------------------------------
+constexpr uint32_t LV_XTRA = 1024;  // bytes staged past a segment, for the runs that leave it
+constexpr uint32_t LV_LDS = LV_SEG + LV_XTRA + 64;
+static_assert(LV_CAND <= LV_SEG && LV_CAND % 64 == 0, "candidates: whole waves inside a segment");
+
+struct LvStream {
+  const uint8_t* base;
+  uint64_t lim;  // readable bytes of base (a multiple of 16)
+  uint64_t off;  // stream offset in base
+  uint32_t len;  // stream bytes
+  int64_t nv;    // rows of the page
+};
+__device__ __forceinline__ LvStream lv_stream(const PageDev* pages, uint32_t p, const uint8_t* file,
+                                              const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim) {
+  LvStream st;
+  const bool sc = (pages[p].flags & 1) != 0;  // V1 page body decompressed to scratch
+  st.base = sc ? scratch : file;
+  st.lim = sc ? scratch_lim : file_lim;
+  st.off = pages[p].def_off;
+  st.len = pages[p].def_len > 0 ? (uint32_t)pages[p].def_len : 0u;
+  st.nv = pages[p].num_values;
+  return st;
+}
+__device__ __forceinline__ uint32_t lv_sat(uint32_t a, uint64_t b) {
+  const uint64_t x = (uint64_t)a + b;  // b < 2^63
+  return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x;
+}
+
+// One workgroup of LV_CAND lanes per segment; the segment and LV_XTRA bytes
+// after it are staged in LDS.
+__global__ __launch_bounds__(LV_CAND) void k_lv_cand(const LvPage* lps, const uint32_t* seg_page, const PageDev* pages,
+                                                     const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                                                     uint64_t scratch_lim, LvCand* cand) {
+  __shared__ __align__(16) uint8_t s_seg[LV_LDS];
+  const uint32_t sg = blockIdx.x, c = threadIdx.x;
+  const LvPage lp = lps[seg_page[sg]];
+  const LvStream st = lv_stream(pages, lp.page, file, scratch, file_lim, scratch_lim);
+  const uint32_t s0 = (sg - lp.seg0) * LV_SEG;
+  LvCand out = {s0 + c, 0u, 0u, 0u};
+  if (s0 < st.len) {
+    const uint32_t se = min(s0 + LV_SEG, st.len);           // run headers of this segment: [s0, se)
+    const uint32_t sh = min(s0 + LV_SEG + LV_XTRA, st.len);  // staged stream bytes: [s0, sh)
+    const bool to_end = sh == st.len;                        // the staged bytes reach the stream's end
+    const uint64_t g0 = st.off + s0, a0 = g0 & ~15ull, ga = st.off + sh;
+    for (uint32_t k = c; a0 + 16ull * k < ga; k += LV_CAND) {
+      const uint64_t a = a0 + 16ull * k;
+      wr_u4 v = {0u, 0u, 0u, 0u};
+      if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
+      *(lds_u4*)(&s_seg[16 * k]) = v;
+    }
+    __syncthreads();
+    const uint32_t d = (uint32_t)(g0 - a0);  // LDS offset of stream byte s0
+    const __attribute__((address_space(3))) uint32_t* w32 = (const __attribute__((address_space(3))) uint32_t*)&s_seg[0];
+    uint32_t q = s0 + c, rows = 0, valid = 0, state = 0;
+    while (q < se) {
+      uint64_t h = 0;
+      uint32_t x = q;
+      bool whole = false;
+      for (uint32_t b7 = 0; b7 < 70; b7 += 7) {
+        if (x >= sh) { state = to_end ? 1u : 2u; break; }
+        const uint32_t b = s_seg[d + (x - s0)];
+        ++x;
+        if (b7 == 63 && (b & 0x7e)) { state = 1; break; }
+        h |= (uint64_t)(b & 0x7f) << b7;
+        if (!(b & 0x80)) { whole = true; break; }
+      }
+      if (!whole) {
+        if (state == 0) state = 1;
+        break;
+      }
+      if (h & 1) {
+        const uint64_t g = h >> 1;  // payload bytes
+        if (g > (1ull << 28) || g > st.len - x) { state = 1; break; }
+        if (x + g > sh) { state = 2; break; }
+        uint32_t cnt = 0;
+        const uint32_t o = d + (x - s0);
+        for (uint32_t i = 0; i < (uint32_t)g; i += 4) {
+          uint32_t v = __builtin_amdgcn_alignbyte(w32[((o + i) >> 2) + 1], w32[(o + i) >> 2], (o + i) & 3);
+          if ((uint32_t)g - i < 4) v &= (1u << (8 * ((uint32_t)g - i))) - 1u;
+          cnt += __popc(v);
+        }
+        rows = lv_sat(rows, 8 * g);
+        valid = lv_sat(valid, cnt);
+        q = x + (uint32_t)g;
+      } else {
+        if (x >= st.len) { state = 1; break; }
+        if (x >= sh) { state = 2; break; }
+        const uint32_t v = s_seg[d + (x - s0)];
+        if (v > 1) { state = 1; break; }
+        rows = lv_sat(rows, h >> 1);
+        if (v) valid = lv_sat(valid, h >> 1);
+        q = x + 1;
+      }
+    }
+    out = LvCand{q, state, rows, valid};
+  }
+  cand[(size_t)sg * LV_CAND + c] = out;
+}
+
+// One thread per page: the true chain's entry into each segment it crosses,
+// up to the run covering the page's last row.  ok[page] = 0 when the chain
+// enters a segment past its candidates or meets a run the candidates could
+// not follow; then no segment is walked and k_lv_tiles walks the page whole.
+__global__ void k_lv_link(const LvPage* lps, int npg, const PageDev* pages, const LvCand* cand, LvEntry* ent,
+                          uint32_t* ok, uint32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npg) return;
+  const LvPage lp = lps[i];
+  const uint32_t len = pages[lp.page].def_len > 0 ? (uint32_t)pages[lp.page].def_len : 0u;
+  const uint64_t nv = (uint64_t)pages[lp.page].num_values;
+  for (uint32_t j = 0; j < lp.nseg; ++j) ent[lp.seg0 + j].q = LV_NONE;
+  uint32_t q = 0, good = 1;
+  uint64_t R = 0, V = 0;
+  for (;;) {
+    if (q >= len) { set_err(err, ERR_LEVELS, lp.page); break; }  // the levels end before the last row
+    const uint32_t j = q / LV_SEG, c = q % LV_SEG;
+    if (j >= lp.nseg || c >= LV_CAND) { good = 0; break; }
+    const LvCand cd = cand[(size_t)(lp.seg0 + j) * LV_CAND + c];
+    ent[lp.seg0 + j] = LvEntry{q, (uint32_t)R, (uint32_t)V, 0u};
+    if (R + cd.rows >= nv) break;  // the run covering the last row starts in this segment
+    if (cd.state == 1) { set_err(err, ERR_LEVELS, lp.page); break; }
+    if (cd.state != 0) { good = 0; break; }
+    R += cd.rows;
+    V += cd.valid;
+    q = cd.exit;
+  }
+  if (!good)
+    for (uint32_t j = 0; j < lp.nseg; ++j) ent[lp.seg0 + j].q = LV_NONE;
+  ok[i] = good;
+}
+
+// mode 0: one wave per segment, from its entry; mode 1: one wave per page
+// that could not be linked, the whole chain.  The walk reads through an LDS
+// window (as k_index's) and stops at the first run whose header lies past the
+// segment, or at the run covering the page's last row.
+__global__ __launch_bounds__(64) void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const LvEntry* ent,
+                                                 const uint32_t* ok, PageDev* pages, const uint8_t* file,
+                                                 const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                                                 TileDev* tiles, uint32_t* err, int mode) {
+  __shared__ wr_u4 s_win[WIN / 16];
+  if (*(volatile uint32_t*)err != 0) return;
+  uint32_t li, q, hdr_end;
+  uint64_t before;
+  int64_t R;
+  if (mode == 0) {
+    const LvEntry e = ent[blockIdx.x];
+    if (e.q == LV_NONE) return;
+    li = seg_page[blockIdx.x];
+    q = e.q;
+    R = e.rows;
+    before = e.valid;
+    hdr_end = (blockIdx.x - lps[li].seg0 + 1) * LV_SEG;
+  } else {
+    li = blockIdx.x;
+    if (ok[li]) return;
+    q = 0;
+    R = 0;
+    before = 0;
+    hdr_end = 0xffffffffu;
+  }
+  const uint32_t p = lps[li].page;
+  const LvStream st = lv_stream(pages, p, file, scratch, file_lim, scratch_lim);
+  const uint32_t tile_begin = pages[p].tile_begin;
+  const bool lead = threadIdx.x == 0;
+  WR r;
+  r.init(st.base, st.lim, (lds_u4*)&s_win[0]);
+  const uint64_t end = st.off + st.len;
+  RunCur c;
+  c.next = st.off + q; c.start = R; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = c.next;
+  for (;;) {
+    if (c.next - st.off >= hdr_end) return;  // the next run belongs to a later segment
+    if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
+    const int64_t lo = c.start, n = (int64_t)min(c.n, 1ull << 40);
+    const int64_t hi = min(lo + n, st.nv);
+    // valid rows among the run's first k values; bit-packed runs count their
+    // payload bytes once, front to back (k does not decrease)
+    uint64_t acc_b = 0, acc_c = 0;
+    auto pop = [&](uint64_t k) -> uint64_t {
+      if (!c.bp) return (uint64_t)c.val * k;
+      const uint64_t kb = k >> 3;
+      if (kb > acc_b) {
+        acc_c += bp_popcount(r, c.pay + acc_b, (kb - acc_b) * 8);
+        acc_b = kb;
+      }
+      return acc_c + ((k & 7) ? (uint64_t)__popc(r.byte(c.pay + kb) & ((1u << (k & 7)) - 1u)) : 0u);
+    };
+    for (int64_t t = (lo + TILE_ROWS - 1) / TILE_ROWS; t * TILE_ROWS < hi; ++t) {
+      const uint64_t skip = (uint64_t)(t * TILE_ROWS - lo);
+      TileDev td;
+      td.page = p;
+      td.row0 = (uint32_t)(t * TILE_ROWS);
+      td.k0 = (uint32_t)(before + pop(skip));
+      td.nn = 0;
+      td.def_pos = (uint32_t)(c.hp - st.off);
+      td.def_skip = (uint32_t)skip;
+      td.val_pos = 0;
+      td.val_skip = 0;
+      if (lead) tiles[tile_begin + (uint32_t)t] = td;
+    }
+    if (lo + n >= st.nv) {
+      const uint32_t nonnull = (uint32_t)(before + pop((uint64_t)(st.nv - lo)));
+      if (lead) pages[p].nonnull = nonnull;
+      return;
+    }
+    before += pop((uint64_t)n);
+  }
+}
+
+// The next run of a 1-bit hybrid stream for one lane (run_next's rules);
+// byte(x) reads stream byte x (x < end).
+template <class Byte>
+__device__ __forceinline__ bool lv_run_next(const Byte& byte, uint64_t end, RunCur& c) {
+  uint64_t pos = c.next;
+  c.start += (int64_t)min(c.n, 1ull << 40);
+  c.hp = pos;
+  uint64_t h = 0;
+  bool whole = false;
+  for (int s = 0; s < 70; s += 7) {
+    if (pos >= end) return false;
+    const uint32_t b = byte(pos++);
+    if (s == 63 && (b & 0x7e)) return false;
+    h |= (uint64_t)(b & 0x7f) << s;
+    if (!(b & 0x80)) { whole = true; break; }
+  }
+  if (!whole) return false;
+  c.pay = pos;
+  if (h & 1) {
+    const uint64_t g = h >> 1;
+    if (g > (1ull << 28) || g > end - pos) return false;
+    c.bp = 1;
+    c.n = g * 8;
+    c.val = 0;
+    c.next = pos + g;
+  } else {
+    if (pos >= end) return false;
+    c.bp = 0;
+    c.n = h >> 1;
+    c.val = byte(pos);
+    if (c.val > 1) return false;
+    c.next = pos + 1;
+  }
+  return true;
+}
+
+// One wave per tile of the pages above: lane k computes level checkpoint k
+// (row row0 + 16k) by walking the runs from the tile's entry; the first KiB
+// from the entry is staged in LDS, later bytes are read from memory.
+__global__ __launch_bounds__(64) void k_lv_ckpt(const LvPage* lps, const uint32_t* tile_lp, const PageDev* pages,
+                                                const TileDev* tiles, const uint8_t* file, const uint8_t* scratch,
+                                                uint64_t file_lim, uint64_t scratch_lim, uint32_t* ckl,
+                                                const uint32_t* err) {
+  __shared__ __align__(16) uint8_t s_buf[1024];
+  if (*(const volatile uint32_t*)err != 0) return;
+  const uint32_t lane = threadIdx.x;
+  const LvPage lp = lps[tile_lp[blockIdx.x]];
+  const LvStream st = lv_stream(pages, lp.page, file, scratch, file_lim, scratch_lim);
+  const uint32_t t = blockIdx.x - lp.tl0;
+  const uint32_t T = pages[lp.page].tile_begin + t;
+  const TileDev td = tiles[T];
+  const uint64_t entry = st.off + td.def_pos, end = st.off + st.len;
+  const uint64_t a0 = entry & ~15ull;
+  {
+    const uint64_t a = a0 + 16ull * lane;
+    wr_u4 v = {0u, 0u, 0u, 0u};
+    if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
+    *(lds_u4*)(&s_buf[16 * lane]) = v;
+  }
+  __syncthreads();
+  const uint8_t* base = st.base;
+  auto byte = [&](uint64_t x) -> uint32_t { return x - a0 < 1024 ? (uint32_t)s_buf[x - a0] : (uint32_t)base[x]; };
+  const int64_t target = (int64_t)t * TILE_ROWS + (int64_t)LROWS * lane;
+  uint32_t lck = LCK_NONE;
+  if (target < st.nv && entry < end) {
+    RunCur c;
+    c.next = entry; c.start = (int64_t)td.row0 - (int64_t)td.def_skip; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0;
+    c.hp = entry;
+    bool good = true;
+    do {
+      if (!lv_run_next(byte, end, c)) { good = false; break; }
+    } while (c.start + (int64_t)min(c.n, 1ull << 40) <= target);
+    if (good) lck = make_lck(c, target, entry);
+  }
+  ckl[(size_t)T * NLCK + lane] = lck;
 }
 
 }  // namespace pqk

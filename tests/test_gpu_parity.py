@@ -70,6 +70,30 @@ def _spec_cases():
             dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, False, dg.STRINGS, 0.0, hi=20_000, str_min=50, str_max=70),
             dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.3, hi=400_000, str_min=8, str_max=44),
         ], num_rows=400_003, rg_rows=400_003, page_bytes=1 * dg.MiB, codec=codec, name="dict_chains" + tag)
+    # long definition-level streams (pages of 10^5 optional rows and more),
+    # walked in segments side by side at open: bit-packed runs (50% nulls),
+    # long RLE runs (0.1% nulls), pages of few values (99.9% nulls), all
+    # null, strings; V1 and V2, uncompressed and Snappy (V1 levels in the
+    # decompression buffer)
+    ll_cols = [
+        dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 0.5, lo=-(1 << 31), hi=1 << 31),
+        dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.001, hi=100),
+        dg.Col(dg.INT64, dg.DELTA_BINARY_PACKED, True, dg.SORTED, 0.999, lo=0, hi=1 << 40, gap_max=8),
+        dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 1.0),
+        dg.Col(dg.BYTE_ARRAY, dg.PLAIN, True, dg.STRINGS, 0.3, hi=0, str_min=0, str_max=12),
+    ]
+    for ver in (1, 2):
+        for codec, tag in ((dg.UNCOMPRESSED, ""), (dg.SNAPPY, "_snappy")):
+            cases[f"long_levels_v{ver}{tag}"] = dg.FileSpec(
+                cols=ll_cols, num_rows=600_011, rg_rows=300_007, page_bytes=1 * dg.MiB, codec=codec,
+                page_version=ver, name=f"long_levels_v{ver}{tag}")
+    # bit-packed level runs of 1000 and 3000 groups (no RLE runs): the chain enters
+    # segments past the candidate positions (1000) or leaves the staged bytes
+    # (3000), so those pages are walked whole by one wave
+    for groups in (1000, 3000):
+        cases[f"long_levels_bp{groups}"] = dg.FileSpec(
+            cols=[ll_cols[0], ll_cols[4]], num_rows=300_007, rg_rows=300_007, page_bytes=1 * dg.MiB,
+            max_bp_groups=groups, rle_min=1 << 30, name=f"long_levels_bp{groups}")
     return cases
 
 
@@ -161,6 +185,45 @@ def test_corrupt_dictionary_index_reported():
         raise AssertionError("corruption not reported")
     except pqs.PqError as e:
         assert e.code == pqs.PQ_ECORRUPT
+
+
+def _level_page(data):
+    """(body offset, level bytes) of the first page of a one-column V1
+    uncompressed file without a dictionary page."""
+    import oracle
+    raw = data.tobytes()
+    h, n = oracle.page_header(raw[4:4 + 256])
+    assert h.type == 0 and h.compressed_size == h.uncompressed_size
+    body = 4 + n
+    return body, int.from_bytes(raw[body:body + 4], "little")
+
+
+@pytest.mark.parametrize("how", ["truncated", "empty", "bad_run"])
+def test_corrupt_long_level_stream_reported(how):
+    """A long definition-level stream that ends before the page's last row
+    (length prefix halved, or zero) or holds an RLE run of value 5 is
+    reported as corrupt at open, as the oracle reports it."""
+    import oracle
+    import paper_2602_17335_amd as pqs
+    spec = dg.FileSpec(cols=[dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 0.5, lo=0, hi=1000)],
+                       num_rows=500_000, rg_rows=500_000, page_bytes=4 * dg.MiB)
+    b = dg.write(spec).copy()
+    body, L = _level_page(b)
+    assert L > 3 * 16384  # several segments of the parallel walk
+    if how == "truncated":
+        b[body:body + 4] = np.frombuffer((L // 2).to_bytes(4, "little"), dtype=np.uint8)
+    elif how == "empty":
+        b[body:body + 4] = 0
+    else:
+        at = body + 4 + L // 2
+        b[at:at + 200] = np.tile(np.array([0x02, 0x05], dtype=np.uint8), 100)
+    with pytest.raises(oracle.OracleError):
+        oracle.File(b).read(0)
+    buf, n = pqs.to_device(b)
+    with pytest.raises(pqs.PqError) as e:
+        f = pqs.DeviceFile(buf, n)
+        f.scan([0])
+    assert e.value.code == pqs.PQ_ECORRUPT
 
 
 def test_bad_magic_rejected_before_gpu_work():
