@@ -32,6 +32,16 @@ __global__ void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const Lv
 __global__ void k_lv_ckpt(const LvPage* lps, const uint32_t* tile_lp, const PageDev* pages, const TileDev* tiles,
                           const uint8_t* file, const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
                           uint32_t* ckl, const uint32_t* err);
+__global__ void k_dl_cand(const DlPage* dps, const uint32_t* seg_page, const PageDev* pages, const uint8_t* file,
+                          const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim, DlCand* cand,
+                          const uint32_t* err);
+__global__ void k_dl_link(const DlPage* dps, int npg, PageDev* pages, const DlCand* cand, DlEntry* ent, uint32_t* ok,
+                          uint32_t* err);
+__global__ void k_dl_fill(const DlPage* dps, const uint32_t* seg_page, const DlEntry* ent, const uint32_t* ok,
+                          PageDev* pages, const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                          uint64_t scratch_lim, uint32_t* blkpos, uint32_t* err, int mode);
+__global__ void k_dl_tiles(const DlPage* dps, const uint32_t* tile_dp, int ntl, const PageDev* pages, TileDev* tiles,
+                           Ck* ckv, const uint32_t* blkpos, const uint32_t* err);
 __global__ void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand);
 __global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
                               uint32_t* seg_base, uint32_t* ok);
@@ -599,6 +609,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   uint32_t* d_order = nullptr;
   uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
   uint8_t* d_lv = nullptr;      // long level streams: segment and tile tables of their walk
+  uint8_t* d_dl = nullptr;      // long DELTA streams: segment, block and tile tables of their walk
   uint8_t* d_xscratch = nullptr;  // DELTA_BYTE_ARRAY pages expanded to the PLAIN layout
   ColScan* d_xcols = nullptr;     // their column tables
   uint64_t xscratch = 0;          // bytes of the expansion layout
@@ -608,6 +619,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     if (d_order) (void)hipFree(d_order);
     if (d_schain) (void)hipFree(d_schain);
     if (d_lv) (void)hipFree(d_lv);
+    if (d_dl) (void)hipFree(d_dl);
     if (d_xscratch) (void)hipFree(d_xscratch);
     if (d_xcols) (void)hipFree(d_xcols);
     d_scratch = nullptr;
@@ -615,6 +627,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     d_order = nullptr;
     d_schain = nullptr;
     d_lv = nullptr;
+    d_dl = nullptr;
     d_xscratch = nullptr;
     d_xcols = nullptr;
   };
@@ -719,12 +732,14 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     std::vector<uint32_t> order(npages);
     std::vector<uint64_t> work(npages);
     std::vector<uint32_t> lv_list;  // pages whose levels the k_lv kernels walk
+    bool any_delta = false;         // pages that may have their blocks walked by the k_dl kernels
     for (uint32_t p = 0; p < npages; ++p) {
       const PageDev& pg = f->pages[p];
       const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY && pg.uncomp_size <= SCHAIN_MIN;
       work[p] = sdict ? 16ull * pg.uncomp_size : (uint64_t)(pg.num_values > 0 ? pg.num_values : 0);
       order[p] = p;
       if (pg.kind != PAGE_DICT && lv_page(pg, f->chunks[pg.chunk].optional != 0)) lv_list.push_back(p);
+      if (pg.kind != PAGE_DICT && (pg.encoding == E_DELTA || pg.encoding == E_DLBA)) any_delta = true;
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
     if (hipMalloc(&d_order, sizeof(uint32_t) * npages) != hipSuccess ||
@@ -737,9 +752,12 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
     // long level streams: their exact lengths (stored by the launch above),
     // then candidates, link, tile entries, checkpoints and the value streams
-    if (!lv_list.empty()) {
+    const uint64_t flim = (len + 15) & ~15ull;
+    if (!lv_list.empty() || any_delta) {
       OPEN_HIP(hipMemcpyAsync(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost, s));
       OPEN_HIP(hipStreamSynchronize(s));
+    }
+    if (!lv_list.empty()) {
       std::vector<LvPage> lps;
       std::vector<uint32_t> seg_page, tile_lp, order2;
       for (uint32_t p : lv_list) {
@@ -773,7 +791,6 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       if (nseg) OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
       if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_lp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
       OPEN_HIP(hipMemcpyAsync(d_ord2, order2.data(), 4 * npg, hipMemcpyHostToDevice, s));
-      const uint64_t flim = (len + 15) & ~15ull;
       if (nseg)
         hipLaunchKernelGGL(k_lv_cand, dim3((uint32_t)nseg), dim3(LV_CAND), 0, s, d_lps, d_segp, f->d_pages, file,
                            d_scratch, flim, (uint64_t)scratch, d_cand);
@@ -791,6 +808,63 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
                          f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, (uint64_t)scratch,
                          d_ord2, d_xscratch, xscratch, 2);
       if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_lv launch failed"); }
+    }
+    // long DELTA block chains (headers parsed by the index pass above): block
+    // positions, then every tile's entry block and checkpoints
+    if (any_delta) {
+      std::vector<DlPage> dps;
+      std::vector<uint32_t> seg_page, tile_dp;
+      uint64_t nblk = 0;
+      for (uint32_t p = 0; p < npages; ++p) {
+        const PageDev& pg = f->pages[p];
+        if (!dl_page(pg, f->chunks[pg.chunk].type)) continue;
+        DlPage x;
+        x.page = p;
+        x.seg0 = (uint32_t)seg_page.size();
+        x.nseg = (uint32_t)(((uint64_t)pg.val_len + DL_SEG - 1) / DL_SEG);
+        x.blk0 = (uint32_t)nblk;
+        x.tl0 = (uint32_t)tile_dp.size();
+        x.maxw = f->chunks[pg.chunk].type == T_INT64 ? 64 : 32;
+        nblk += ((uint64_t)pg.num_values + 127) / 128 + 1;  // blocks hold 128 values or more
+        const uint32_t nt = (uint32_t)(((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS);
+        for (uint32_t j = 0; j < x.nseg; ++j) seg_page.push_back((uint32_t)dps.size());
+        for (uint32_t j = 0; j < nt; ++j) tile_dp.push_back((uint32_t)dps.size());
+        dps.push_back(x);
+      }
+      if (nblk > 0xffffffffull) { cleanup_open(); free_handle(f); return fail(PQ_EUNSUPPORTED, "too many DELTA blocks"); }
+      if (!dps.empty()) {
+        const size_t npg = dps.size(), nseg = seg_page.size(), ntl = tile_dp.size();
+        const size_t o_seg = align_up(sizeof(DlPage) * npg, 256), o_tl = align_up(o_seg + 4 * nseg, 256),
+                     o_cand = align_up(o_tl + 4 * ntl, 256),
+                     o_ent = align_up(o_cand + sizeof(DlCand) * DL_CAND * nseg, 256),
+                     o_ok = align_up(o_ent + sizeof(DlEntry) * nseg, 256), o_blk = align_up(o_ok + 4 * npg, 256),
+                     total = o_blk + 4 * (size_t)nblk;
+        if (hipMalloc(&d_dl, total) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: DELTA walk tables"); }
+        DlPage* d_dps = reinterpret_cast<DlPage*>(d_dl);
+        uint32_t* d_segp = reinterpret_cast<uint32_t*>(d_dl + o_seg);
+        uint32_t* d_tlp = reinterpret_cast<uint32_t*>(d_dl + o_tl);
+        DlCand* d_cand = reinterpret_cast<DlCand*>(d_dl + o_cand);
+        DlEntry* d_ent = reinterpret_cast<DlEntry*>(d_dl + o_ent);
+        uint32_t* d_ok = reinterpret_cast<uint32_t*>(d_dl + o_ok);
+        uint32_t* d_blk = reinterpret_cast<uint32_t*>(d_dl + o_blk);
+        OPEN_HIP(hipMemcpyAsync(d_dps, dps.data(), sizeof(DlPage) * npg, hipMemcpyHostToDevice, s));
+        if (nseg) OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
+        if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_dp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
+        if (nseg)
+          hipLaunchKernelGGL(k_dl_cand, dim3((uint32_t)nseg), dim3(DL_CAND), 0, s, d_dps, d_segp, f->d_pages, file,
+                             d_scratch, flim, (uint64_t)scratch, d_cand, f->d_err);
+        hipLaunchKernelGGL(k_dl_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_dps, (int)npg, f->d_pages,
+                           d_cand, d_ent, d_ok, f->d_err);
+        if (nseg)
+          hipLaunchKernelGGL(k_dl_fill, dim3((uint32_t)nseg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
+                             file, d_scratch, flim, (uint64_t)scratch, d_blk, f->d_err, 0);
+        hipLaunchKernelGGL(k_dl_fill, dim3((uint32_t)npg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
+                           file, d_scratch, flim, (uint64_t)scratch, d_blk, f->d_err, 1);
+        if (ntl)
+          hipLaunchKernelGGL(k_dl_tiles, dim3((uint32_t)((ntl + 255) / 256)), dim3(256), 0, s, d_dps, d_tlp, (int)ntl,
+                             f->d_pages, f->d_tiles, f->d_ckv, d_blk, f->d_err);
+        if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dl launch failed"); }
+      }
     }
     // long string dictionaries: their length chains, segments side by side
     std::vector<SChainPage> scp;

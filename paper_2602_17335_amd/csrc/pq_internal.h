@@ -192,6 +192,37 @@ struct LvCand {
 struct LvEntry {
   uint32_t q, rows, valid, pad_;
 };
+// DELTA_BINARY_PACKED value streams (and the length streams of
+// DELTA_LENGTH_BYTE_ARRAY pages) are chains of blocks whose sizes follow
+// from their headers.  Pages whose value stream is longer than DL_MIN bytes
+// have the chain walked at open in DL_SEG-byte segments side by side (DL_CAND
+// candidate chains per segment, as for level streams); the position of every
+// block is stored, and each tile's entry and checkpoints are read from them.
+constexpr uint32_t DL_MIN = 16384;
+constexpr uint32_t DL_SEG = 16384;
+constexpr uint32_t DL_CAND = 256;
+__host__ __device__ inline bool dl_page(const PageDev& pg, int32_t type) {
+  return pg.kind != PAGE_DICT && pg.num_values > 0 &&
+         (pg.encoding == E_DELTA || (pg.encoding == E_DLBA && type == T_BYTE_ARRAY)) && pg.val_len > DL_MIN;
+}
+struct DlPage {
+  uint32_t page, seg0, nseg;  // segments [seg0, seg0 + nseg) of the segment list
+  uint32_t blk0;              // first entry of the page in the block-position list
+  uint32_t tl0;               // first entry of the page in the tile list
+  uint32_t maxw;              // widest miniblock bit width of the column's type
+};
+// A candidate block chain of one segment: where it leaves the segment, the
+// blocks whose header lies in it (every one taken as a full block), and how
+// it ended (0: left the segment; 1: at a block that is invalid as a full
+// block).
+struct DlCand {
+  uint32_t exit, count, state, pad_;
+};
+// The true chain's entry into a segment (value-stream offset; LV_NONE: not
+// walked) and the index of the block there.
+struct DlEntry {
+  uint32_t q, k;
+};
 // x_total of a DELTA_BYTE_ARRAY page the scan does not decode (a value longer
 // than the expansion's LDS buffer, or a DELTA block shape outside the
 // supported one): its tiles report PQ_EUNSUPPORTED when its column is scanned

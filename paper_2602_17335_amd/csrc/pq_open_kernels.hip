@@ -7,6 +7,9 @@
 //   k_lv_cand / k_lv_link / k_lv_tiles / k_lv_ckpt
 //            tile entries, level checkpoints and non-null counts of pages
 //            with long definition-level streams, segments side by side
+//   k_dl_cand / k_dl_link / k_dl_fill / k_dl_tiles
+//            block positions, tile entries and block checkpoints of long
+//            DELTA_BINARY_PACKED streams, segments side by side
 #include <hip/hip_runtime.h>
 
 #include "pq_device.hpp"
@@ -580,6 +583,10 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
         s_vp[t] = (uint32_t)(q - val_off);
       }
     }
+    if (dl_page(pg, ch.type)) {  // long chain: walked by the k_dl kernels
+      pages[p] = pg;
+      return;
+    }
     auto tile_k0 = [&](uint32_t x) { return cached ? s_k0[x] : tiles[pg.tile_begin + x].k0; };
     auto tile_nn = [&](uint32_t x) { return cached ? s_nn[x] : tiles[pg.tile_begin + x].nn; };
     auto tile_vp = [&](uint32_t x) { return cached ? s_vp[x] : tiles[pg.tile_begin + x].val_pos; };
@@ -1082,6 +1089,216 @@ __global__ __launch_bounds__(64) void k_lv_ckpt(const LvPage* lps, const uint32_
     if (good) lck = make_lck(c, target, entry);
   }
   ckl[(size_t)T * NLCK + lane] = lck;
+}
+
+// ---------------------------------------------------------------------------
+// Long DELTA_BINARY_PACKED block chains.  A block is a ULEB128 zigzag
+// minimum delta, M miniblock bit widths (a byte each) and the miniblocks'
+// packed deltas, so its size follows from its header, and the blocks form a
+// chain from the stream's block 0.  As for level streams: k_dl_cand walks
+// DL_CAND candidate chains per DL_SEG-byte segment (every block taken as a
+// full block), k_dl_link follows the true chain through them, k_dl_fill
+// walks each segment's blocks from its entry -- exactly, the last block
+// holding only the miniblocks its values use -- storing every block's
+// position and, after the last block, the stream's end (or walks a page
+// whole when its chain cannot be linked, mode 1), and k_dl_tiles gives each
+// tile its entry block and block checkpoints from the stored positions.
+// ---------------------------------------------------------------------------
+constexpr uint32_t DL_LDS = DL_SEG + 64;
+static_assert(DL_CAND <= DL_SEG && DL_CAND % 64 == 0, "candidates: whole waves inside a segment");
+
+struct DlStream {
+  const uint8_t* base;
+  uint64_t lim;       // readable bytes of base (a multiple of 16)
+  uint64_t off;       // value-stream offset in base
+  uint32_t len;       // value-stream bytes
+  uint32_t at;        // stream offset of block 0
+  uint32_t B, M, per; // values per block, miniblocks per block, values per miniblock
+  uint64_t total;     // values in the stream (the page's non-null count)
+  uint64_t nblocks;   // blocks: value 0 is in the stream header
+};
+__device__ __forceinline__ DlStream dl_stream(const PageDev* pages, uint32_t p, const uint8_t* file,
+                                              const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim) {
+  DlStream st;
+  const bool sc = (pages[p].flags & 2) != 0;
+  st.base = sc ? scratch : file;
+  st.lim = sc ? scratch_lim : file_lim;
+  st.off = pages[p].val_off;
+  st.len = pages[p].val_len;
+  st.at = pages[p].blocks_at;
+  st.B = pages[p].enc_w;
+  st.M = pages[p].enc_m;
+  st.per = st.M ? st.B / st.M : 0;
+  st.total = pages[p].nonnull;
+  st.nblocks = (st.total > 1 && st.B) ? (st.total - 1 + st.B - 1) / st.B : 0;
+  return st;
+}
+
+// One workgroup of DL_CAND lanes per segment; the segment and the longest
+// block header after it are staged in LDS.
+__global__ __launch_bounds__(DL_CAND) void k_dl_cand(const DlPage* dps, const uint32_t* seg_page, const PageDev* pages,
+                                                     const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                                                     uint64_t scratch_lim, DlCand* cand, const uint32_t* err) {
+  __shared__ __align__(16) uint8_t s_seg[DL_LDS];
+  const uint32_t sg = blockIdx.x, c = threadIdx.x;
+  DlCand out = {0u, 0u, 1u, 0u};
+  if (*(const volatile uint32_t*)err == 0) {
+    const DlPage dp = dps[seg_page[sg]];
+    const DlStream st = dl_stream(pages, dp.page, file, scratch, file_lim, scratch_lim);
+    const uint64_t s0 = (uint64_t)st.at + (uint64_t)(sg - dp.seg0) * DL_SEG;
+    out.exit = (uint32_t)(s0 + c);
+    if (s0 < st.len) {
+      const uint32_t se = (uint32_t)min(s0 + DL_SEG, (uint64_t)st.len);       // block headers of this segment: [s0, se)
+      const uint32_t sh = (uint32_t)min(s0 + DL_SEG + 32, (uint64_t)st.len);  // staged: [s0, sh)
+      const uint64_t g0 = st.off + s0, a0 = g0 & ~15ull, ga = st.off + sh;
+      for (uint32_t k = c; a0 + 16ull * k < ga; k += DL_CAND) {
+        const uint64_t a = a0 + 16ull * k;
+        wr_u4 v = {0u, 0u, 0u, 0u};
+        if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
+        *(lds_u4*)(&s_seg[16 * k]) = v;
+      }
+      __syncthreads();
+      const uint32_t d = (uint32_t)(g0 - a0) - (uint32_t)s0;  // LDS offset of stream byte x: d + x
+      uint32_t q = (uint32_t)s0 + c, count = 0, state = 0;
+      while (q < se) {
+        uint32_t x = q;
+        bool whole = false;
+        for (uint32_t b7 = 0; b7 < 70; b7 += 7) {  // minimum delta (a header a block of 10 bytes at most)
+          if (x >= st.len) break;
+          const uint32_t b = s_seg[d + x];
+          ++x;
+          if (b7 == 63 && (b & 0x7e)) break;
+          if (!(b & 0x80)) { whole = true; break; }
+        }
+        if (!whole || st.M > st.len - x) { state = 1; break; }
+        uint64_t body = 0;
+        bool bad = false;
+        for (uint32_t m = 0; m < st.M; ++m) {
+          const uint32_t w = s_seg[d + x + m];
+          bad |= w > dp.maxw;
+          body += (uint64_t)st.per * w / 8;
+        }
+        x += st.M;
+        if (bad || body > st.len - x) { state = 1; break; }
+        q = x + (uint32_t)body;
+        ++count;
+      }
+      out = DlCand{q, count, state, 0u};
+    }
+  }
+  cand[(size_t)sg * DL_CAND + c] = out;
+}
+
+// One thread per page (see k_lv_link): ent[segment] = (entry offset, block
+// index) along the true chain, up to the segment of the last block.
+__global__ void k_dl_link(const DlPage* dps, int npg, PageDev* pages, const DlCand* cand, DlEntry* ent, uint32_t* ok,
+                          uint32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npg) return;
+  const DlPage dp = dps[i];
+  for (uint32_t j = 0; j < dp.nseg; ++j) ent[dp.seg0 + j].q = LV_NONE;
+  ok[i] = 1;
+  if (*(volatile uint32_t*)err != 0) return;
+  const DlStream st = dl_stream(pages, dp.page, nullptr, nullptr, 0, 0);
+  if (st.nblocks == 0) {
+    pages[dp.page].chars_at = st.at;
+    return;
+  }
+  uint32_t q = st.at, good = 1;
+  uint64_t k = 0;
+  for (;;) {
+    if (q >= st.len) { set_err(err, ERR_DELTA, dp.page); break; }  // the stream ends before the last block
+    const uint32_t j = (q - st.at) / DL_SEG, c = (q - st.at) % DL_SEG;
+    if (j >= dp.nseg || c >= DL_CAND) { good = 0; break; }
+    const DlCand cd = cand[(size_t)(dp.seg0 + j) * DL_CAND + c];
+    ent[dp.seg0 + j] = DlEntry{q, (uint32_t)k};
+    if (k + cd.count >= st.nblocks) break;  // the last block starts in this segment
+    if (cd.state != 0) {
+      if (k + cd.count + 1 == st.nblocks) break;  // at the last block, which need not be full
+      set_err(err, ERR_DELTA, dp.page);
+      break;
+    }
+    k += cd.count;
+    q = cd.exit;
+  }
+  if (!good) {
+    for (uint32_t j = 0; j < dp.nseg; ++j) ent[dp.seg0 + j].q = LV_NONE;
+    ok[i] = 0;
+  }
+}
+
+// mode 0: one wave per segment, from its entry, over the blocks whose header
+// lies in it; mode 1: one wave per page that could not be linked.
+__global__ __launch_bounds__(64) void k_dl_fill(const DlPage* dps, const uint32_t* seg_page, const DlEntry* ent,
+                                                const uint32_t* ok, PageDev* pages, const uint8_t* file,
+                                                const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                                                uint32_t* blkpos, uint32_t* err, int mode) {
+  __shared__ wr_u4 s_win[WIN / 16];
+  if (*(volatile uint32_t*)err != 0) return;
+  uint32_t di, q, seg_end;
+  uint64_t k;
+  if (mode == 0) {
+    const DlEntry e = ent[blockIdx.x];
+    if (e.q == LV_NONE) return;
+    di = seg_page[blockIdx.x];
+    q = e.q;
+    k = e.k;
+    seg_end = pages[dps[di].page].blocks_at + (blockIdx.x - dps[di].seg0 + 1) * DL_SEG;
+  } else {
+    di = blockIdx.x;
+    if (ok[di]) return;
+    q = pages[dps[di].page].blocks_at;
+    k = 0;
+    seg_end = 0xffffffffu;
+  }
+  const DlPage dp = dps[di];
+  const DlStream st = dl_stream(pages, dp.page, file, scratch, file_lim, scratch_lim);
+  const bool lead = threadIdx.x == 0;
+  WR r;
+  r.init(st.base, st.lim, (lds_u4*)&s_win[0]);
+  const uint64_t vend = st.off + st.len;
+  uint64_t qa = st.off + q;
+  for (; k < st.nblocks && qa - st.off < seg_end; ++k) {
+    if (lead) blkpos[dp.blk0 + k] = (uint32_t)(qa - st.off);
+    bool bad = false;
+    br_uleb(r, qa, vend, bad);  // minimum delta
+    if (bad || st.M > vend - qa) { set_err(err, ERR_DELTA, dp.page); return; }
+    const uint64_t left = st.total - 1 - k * st.B;  // values from this block on
+    const uint64_t used = left < st.B ? left : st.B;
+    const uint64_t used_mb = (used + st.per - 1) / st.per;
+    uint64_t body = 0;
+    for (uint64_t m = 0; m < used_mb; ++m) {
+      const uint32_t w = r.byte(qa + m);
+      if (w > dp.maxw) { set_err(err, ERR_DELTA, dp.page); return; }
+      body += (uint64_t)st.per * w / 8;
+    }
+    qa += st.M;
+    if (body > vend - qa) { set_err(err, ERR_DELTA, dp.page); return; }
+    qa += body;
+  }
+  if (k == st.nblocks && lead) pages[dp.page].chars_at = (uint32_t)(qa - st.off);
+}
+
+// One thread per tile of the pages above: the block holding the tile's
+// first delta is its entry; blocks from there to the one holding its last
+// delta are its checkpoints.  Tiles that need no block keep the entry the
+// index pass gave them (block 0, no checkpoints).
+__global__ void k_dl_tiles(const DlPage* dps, const uint32_t* tile_dp, int ntl, const PageDev* pages, TileDev* tiles,
+                           Ck* ckv, const uint32_t* blkpos, const uint32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntl || *(const volatile uint32_t*)err != 0) return;
+  const DlPage dp = dps[tile_dp[i]];
+  const uint32_t T = pages[dp.page].tile_begin + ((uint32_t)i - dp.tl0);
+  const uint64_t B = pages[dp.page].enc_w;
+  const uint64_t k0 = tiles[T].k0, nn = tiles[T].nn;
+  if (nn == 0 || k0 + nn <= 1) return;
+  const uint64_t first = k0 == 0 ? 1 : k0;
+  const uint64_t bu = (first - 1) / B, lastb = (k0 + nn - 2) / B;
+  const uint32_t vp = blkpos[dp.blk0 + bu];
+  tiles[T].val_pos = vp;
+  tiles[T].val_skip = (uint32_t)((first - 1) % B);
+  for (uint64_t b = bu; b <= lastb && b - bu < (uint64_t)NSUB; ++b)
+    ckv[(size_t)T * NSUB + (b - bu)] = ck_at((uint64_t)(blkpos[dp.blk0 + b] - vp));
 }
 
 }  // namespace pqk

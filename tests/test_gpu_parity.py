@@ -94,6 +94,23 @@ def _spec_cases():
         cases[f"long_levels_bp{groups}"] = dg.FileSpec(
             cols=[ll_cols[0], ll_cols[4]], num_rows=300_007, rg_rows=300_007, page_bytes=1 * dg.MiB,
             max_bp_groups=groups, rle_min=1 << 30, name=f"long_levels_bp{groups}")
+    # long DELTA_BINARY_PACKED streams, whose block chains are walked in
+    # segments side by side at open: narrow blocks (sorted keys), wide
+    # blocks of about 1 KiB (uniform 64-bit values: chains enter segments
+    # past the candidate positions, so those pages are walked whole), and
+    # the length streams of DELTA_LENGTH_BYTE_ARRAY strings; blocks of
+    # 128 x 4, 256 x 8 and 1024 x 1 values; V1 and V2 Snappy
+    dl_cols = [
+        dg.Col(dg.INT32, dg.DELTA_BINARY_PACKED, False, dg.SORTED, 0.0, lo=0, hi=1 << 30, gap_max=8),
+        dg.Col(dg.INT64, dg.DELTA_BINARY_PACKED, True, dg.SORTED, 0.1, lo=0, hi=1 << 40, gap_max=1000),
+        dg.Col(dg.INT64, dg.DELTA_BINARY_PACKED, True, dg.UNIFORM, 0.2, lo=-2**62, hi=2**62),
+        dg.Col(dg.BYTE_ARRAY, dg.DELTA_LENGTH_BYTE_ARRAY, True, dg.STRINGS, 0.1, hi=0, str_min=0, str_max=20),
+    ]
+    for blk, mini in ((128, 4), (256, 8), (1024, 1)):
+        for ver, codec, tag in ((1, dg.UNCOMPRESSED, ""), (2, dg.SNAPPY, "_v2_snappy")):
+            cases[f"long_delta_{blk}x{mini}{tag}"] = dg.FileSpec(
+                cols=dl_cols, num_rows=400_003, rg_rows=400_003, page_bytes=1 * dg.MiB, codec=codec,
+                page_version=ver, delta_block=blk, delta_mini=mini, name=f"long_delta_{blk}x{mini}{tag}")
     return cases
 
 
@@ -224,6 +241,60 @@ def test_corrupt_long_level_stream_reported(how):
         f = pqs.DeviceFile(buf, n)
         f.scan([0])
     assert e.value.code == pqs.PQ_ECORRUPT
+
+
+def _uleb(raw, pos):
+    v = sh = 0
+    while True:
+        b = raw[pos]
+        pos += 1
+        v |= (b & 0x7F) << sh
+        sh += 7
+        if not b & 0x80:
+            return v, pos
+
+
+@pytest.mark.parametrize("how", ["bad_width", "unused_width"])
+def test_long_delta_stream_widths(how):
+    """A miniblock bit width above 32 in the middle of a long INT32 DELTA
+    stream is reported as corrupt at open, as the oracle reports it; a width
+    of 255 for a miniblock of the last block that holds no values is
+    ignored, by both."""
+    import oracle
+    import paper_2602_17335_amd as pqs
+    spec = dg.FileSpec(cols=[dg.Col(dg.INT32, dg.DELTA_BINARY_PACKED, False, dg.SORTED, 0.0, lo=0, hi=1 << 30,
+                                    gap_max=8)], num_rows=300_000, rg_rows=300_000, page_bytes=4 * dg.MiB)
+    b = dg.write(spec).copy()
+    raw = b.tobytes()
+    h, n = oracle.page_header(raw[4:4 + 256])
+    assert h.type == 0 and h.compressed_size == h.uncompressed_size
+    pos = 4 + n
+    B, pos = _uleb(raw, pos)
+    M, pos = _uleb(raw, pos)
+    total, pos = _uleb(raw, pos)
+    _, pos = _uleb(raw, pos)
+    per, nblocks = B // M, (total - 1 + B - 1) // B
+    blocks = []
+    for k in range(nblocks):
+        _, pos = _uleb(raw, pos)
+        used_mb = (min(total - 1 - k * B, B) + per - 1) // per
+        blocks.append((pos, used_mb))
+        pos += M + sum(per * w // 8 for w in raw[pos:pos + used_mb])
+    assert pos - (4 + n) > 4 * 16384  # several segments of the parallel walk
+    if how == "bad_width":
+        b[blocks[nblocks // 2][0]] = 0xFF
+        with pytest.raises(oracle.OracleError):
+            oracle.File(b).read(0)
+        buf, n2 = pqs.to_device(b)
+        with pytest.raises(pqs.PqError) as e:
+            f = pqs.DeviceFile(buf, n2)
+            f.scan([0])
+        assert e.value.code == pqs.PQ_ECORRUPT
+    else:
+        wpos, used_mb = blocks[-1]
+        assert used_mb < M
+        b[wpos + used_mb] = 0xFF
+        check_file(b, label="unused-width")
 
 
 def test_bad_magic_rejected_before_gpu_work():
