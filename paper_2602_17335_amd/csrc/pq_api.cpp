@@ -42,6 +42,17 @@ __global__ void k_dl_fill(const DlPage* dps, const uint32_t* seg_page, const DlE
                           uint64_t scratch_lim, uint32_t* blkpos, uint32_t* err, int mode);
 __global__ void k_dl_tiles(const DlPage* dps, const uint32_t* tile_dp, int ntl, const PageDev* pages, TileDev* tiles,
                            Ck* ckv, const uint32_t* blkpos, const uint32_t* err);
+__global__ void k_di_cand(const DiPage* dps, const uint32_t* seg_page, const PageDev* pages, const uint8_t* file,
+                          const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim, DiCand* cand,
+                          const uint32_t* err);
+__global__ void k_di_link(const DiPage* dps, int npg, const PageDev* pages, const DiCand* cand, DlEntry* ent,
+                          uint32_t* ok, uint32_t* err);
+__global__ void k_di_fill(const DiPage* dps, const uint32_t* seg_page, const DlEntry* ent, const uint32_t* ok,
+                          const PageDev* pages, const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                          uint64_t scratch_lim, TileDev* tiles, uint32_t* err, int mode);
+__global__ void k_di_ckpt(const DiPage* dps, const uint32_t* tile_dp, int ntl, const PageDev* pages,
+                          const TileDev* tiles, const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                          uint64_t scratch_lim, Ck* ckv, const uint32_t* err);
 __global__ void k_schain_cand(const SChainPage* pgs, const uint32_t* seg_page, SChainCand* cand);
 __global__ void k_schain_link(const SChainPage* pgs, int npg, const SChainCand* cand, uint32_t* seg_start,
                               uint32_t* seg_base, uint32_t* ok);
@@ -610,6 +621,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
   uint8_t* d_lv = nullptr;      // long level streams: segment and tile tables of their walk
   uint8_t* d_dl = nullptr;      // long DELTA streams: segment, block and tile tables of their walk
+  uint8_t* d_di = nullptr;      // long dictionary-index streams: segment and tile tables of their walk
   uint8_t* d_xscratch = nullptr;  // DELTA_BYTE_ARRAY pages expanded to the PLAIN layout
   ColScan* d_xcols = nullptr;     // their column tables
   uint64_t xscratch = 0;          // bytes of the expansion layout
@@ -620,6 +632,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     if (d_schain) (void)hipFree(d_schain);
     if (d_lv) (void)hipFree(d_lv);
     if (d_dl) (void)hipFree(d_dl);
+    if (d_di) (void)hipFree(d_di);
     if (d_xscratch) (void)hipFree(d_xscratch);
     if (d_xcols) (void)hipFree(d_xcols);
     d_scratch = nullptr;
@@ -628,6 +641,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     d_schain = nullptr;
     d_lv = nullptr;
     d_dl = nullptr;
+    d_di = nullptr;
     d_xscratch = nullptr;
     d_xcols = nullptr;
   };
@@ -733,6 +747,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     std::vector<uint64_t> work(npages);
     std::vector<uint32_t> lv_list;  // pages whose levels the k_lv kernels walk
     bool any_delta = false;         // pages that may have their blocks walked by the k_dl kernels
+    bool any_dict = false;          // pages that may have their indices walked by the k_di kernels
     for (uint32_t p = 0; p < npages; ++p) {
       const PageDev& pg = f->pages[p];
       const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY && pg.uncomp_size <= SCHAIN_MIN;
@@ -740,6 +755,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       order[p] = p;
       if (pg.kind != PAGE_DICT && lv_page(pg, f->chunks[pg.chunk].optional != 0)) lv_list.push_back(p);
       if (pg.kind != PAGE_DICT && (pg.encoding == E_DELTA || pg.encoding == E_DLBA)) any_delta = true;
+      if (pg.kind != PAGE_DICT && (pg.encoding == E_PLAIN_DICT || pg.encoding == E_RLE_DICT)) any_dict = true;
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
     if (hipMalloc(&d_order, sizeof(uint32_t) * npages) != hipSuccess ||
@@ -753,7 +769,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     // long level streams: their exact lengths (stored by the launch above),
     // then candidates, link, tile entries, checkpoints and the value streams
     const uint64_t flim = (len + 15) & ~15ull;
-    if (!lv_list.empty() || any_delta) {
+    if (!lv_list.empty() || any_delta || any_dict) {
       OPEN_HIP(hipMemcpyAsync(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost, s));
       OPEN_HIP(hipStreamSynchronize(s));
     }
@@ -864,6 +880,56 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
           hipLaunchKernelGGL(k_dl_tiles, dim3((uint32_t)((ntl + 255) / 256)), dim3(256), 0, s, d_dps, d_tlp, (int)ntl,
                              f->d_pages, f->d_tiles, f->d_ckv, d_blk, f->d_err);
         if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dl launch failed"); }
+      }
+    }
+    // long dictionary-index streams (widths parsed by the index pass above):
+    // every tile's entry run and value checkpoints
+    if (any_dict) {
+      std::vector<DiPage> dps;
+      std::vector<uint32_t> seg_page, tile_dp;
+      for (uint32_t p = 0; p < npages; ++p) {
+        const PageDev& pg = f->pages[p];
+        if (!di_page(pg)) continue;
+        DiPage x;
+        x.page = p;
+        x.seg0 = (uint32_t)seg_page.size();
+        x.nseg = (uint32_t)(((uint64_t)pg.val_len + DI_SEG - 1) / DI_SEG);
+        x.tl0 = (uint32_t)tile_dp.size();
+        const uint32_t nt = (uint32_t)(((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS);
+        for (uint32_t j = 0; j < x.nseg; ++j) seg_page.push_back((uint32_t)dps.size());
+        for (uint32_t j = 0; j < nt; ++j) tile_dp.push_back((uint32_t)dps.size());
+        dps.push_back(x);
+      }
+      if (!dps.empty()) {
+        const size_t npg = dps.size(), nseg = seg_page.size(), ntl = tile_dp.size();
+        const size_t o_seg = align_up(sizeof(DiPage) * npg, 256), o_tl = align_up(o_seg + 4 * nseg, 256),
+                     o_cand = align_up(o_tl + 4 * ntl, 256),
+                     o_ent = align_up(o_cand + sizeof(DiCand) * DI_CAND_MAX * nseg, 256),
+                     o_ok = align_up(o_ent + sizeof(DlEntry) * nseg, 256), total = o_ok + 4 * npg;
+        if (hipMalloc(&d_di, total) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: index walk tables"); }
+        DiPage* d_dps = reinterpret_cast<DiPage*>(d_di);
+        uint32_t* d_segp = reinterpret_cast<uint32_t*>(d_di + o_seg);
+        uint32_t* d_tlp = reinterpret_cast<uint32_t*>(d_di + o_tl);
+        DiCand* d_cand = reinterpret_cast<DiCand*>(d_di + o_cand);
+        DlEntry* d_ent = reinterpret_cast<DlEntry*>(d_di + o_ent);
+        uint32_t* d_ok = reinterpret_cast<uint32_t*>(d_di + o_ok);
+        OPEN_HIP(hipMemcpyAsync(d_dps, dps.data(), sizeof(DiPage) * npg, hipMemcpyHostToDevice, s));
+        if (nseg) OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
+        if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_dp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
+        if (nseg)
+          hipLaunchKernelGGL(k_di_cand, dim3((uint32_t)nseg), dim3(256), 0, s, d_dps, d_segp, f->d_pages, file,
+                             d_scratch, flim, (uint64_t)scratch, d_cand, f->d_err);
+        hipLaunchKernelGGL(k_di_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_dps, (int)npg, f->d_pages,
+                           d_cand, d_ent, d_ok, f->d_err);
+        if (nseg)
+          hipLaunchKernelGGL(k_di_fill, dim3((uint32_t)nseg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
+                             file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 0);
+        hipLaunchKernelGGL(k_di_fill, dim3((uint32_t)npg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
+                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 1);
+        if (ntl)
+          hipLaunchKernelGGL(k_di_ckpt, dim3((uint32_t)((ntl + 3) / 4)), dim3(64), 0, s, d_dps, d_tlp, (int)ntl,
+                             f->d_pages, f->d_tiles, file, d_scratch, flim, (uint64_t)scratch, f->d_ckv, f->d_err);
+        if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_di launch failed"); }
       }
     }
     // long string dictionaries: their length chains, segments side by side

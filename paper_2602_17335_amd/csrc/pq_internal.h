@@ -223,6 +223,33 @@ struct DlCand {
 struct DlEntry {
   uint32_t q, k;
 };
+// Dictionary-index streams (a bit width byte, then hybrid runs of that
+// width) of pages longer than DI_MIN bytes are indexed in DI_SEG-byte
+// segments side by side, with di_cand(w) candidate chains per segment: a
+// bit-packed run of 63 groups of width w takes 1 + 63 w bytes, so the true
+// chain enters a segment within that many bytes of its start (wider runs
+// and more than 1024 bytes: the page is walked whole by one wave).
+constexpr uint32_t DI_MIN = 16384;
+constexpr uint32_t DI_SEG = 32768;
+constexpr uint32_t DI_CAND_MAX = 1024;
+__host__ __device__ inline bool di_page(const PageDev& pg) {
+  return pg.kind != PAGE_DICT && (pg.encoding == E_PLAIN_DICT || pg.encoding == E_RLE_DICT) && pg.num_values > 0 &&
+         pg.val_len > DI_MIN;
+}
+__host__ __device__ inline uint32_t di_cand(uint32_t w) {
+  const uint32_t c = (16 + 64 * w + 63) / 64 * 64;
+  return c > DI_CAND_MAX ? DI_CAND_MAX : c;
+}
+struct DiPage {
+  uint32_t page, seg0, nseg;  // segments [seg0, seg0 + nseg) of the segment list
+  uint32_t tl0;               // first entry of the page in the tile list
+};
+// A candidate of a dictionary-index stream: where it leaves the segment
+// (DI_BAD: at an invalid run) and the values of the runs before (saturating).
+constexpr uint32_t DI_BAD = 0xffffffffu;
+struct DiCand {
+  uint32_t exit, count;
+};
 // x_total of a DELTA_BYTE_ARRAY page the scan does not decode (a value longer
 // than the expansion's LDS buffer, or a DELTA block shape outside the
 // supported one): its tiles report PQ_EUNSUPPORTED when its column is scanned

@@ -10,6 +10,9 @@
 //   k_dl_cand / k_dl_link / k_dl_fill / k_dl_tiles
 //            block positions, tile entries and block checkpoints of long
 //            DELTA_BINARY_PACKED streams, segments side by side
+//   k_di_cand / k_di_link / k_di_fill / k_di_ckpt
+//            tile entries and value checkpoints of long dictionary-index
+//            streams, segments side by side
 #include <hip/hip_runtime.h>
 
 #include "pq_device.hpp"
@@ -529,6 +532,10 @@ __global__ __launch_bounds__(64) void k_index(const uint8_t* file, const uint8_t
       const uint32_t w = r.byte(val_off);
       if (w > 32) { set_err(err, ERR_VALUES, p); return; }
       pg.enc_w = w;
+      if (di_page(pg)) {  // long index stream: walked by the k_di kernels
+        pages[p] = pg;
+        return;
+      }
       RunCur c;
       c.next = val_off + 1; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = val_off + 1;
       bool have = false;
@@ -1299,6 +1306,255 @@ __global__ void k_dl_tiles(const DlPage* dps, const uint32_t* tile_dp, int ntl, 
   tiles[T].val_skip = (uint32_t)((first - 1) % B);
   for (uint64_t b = bu; b <= lastb && b - bu < (uint64_t)NSUB; ++b)
     ckv[(size_t)T * NSUB + (b - bu)] = ck_at((uint64_t)(blkpos[dp.blk0 + b] - vp));
+}
+
+// ---------------------------------------------------------------------------
+// Long dictionary-index streams: hybrid runs of width w after the width
+// byte.  Same scheme once more: k_di_cand walks di_cand(w) candidate chains
+// per DI_SEG-byte segment counting values, k_di_link follows the true chain
+// up to the run covering the page's last non-null value, k_di_fill walks
+// each segment's runs from its entry and gives the tiles whose first value
+// lies in them their entry run (or walks a page whole, mode 1), and
+// k_di_ckpt derives each tile's value checkpoints from its entry, one per
+// lane, four tiles per wave.
+// ---------------------------------------------------------------------------
+constexpr uint32_t DI_LDS = DI_SEG + 64;
+constexpr uint32_t DI_WG = 256;
+
+struct DiStream {
+  const uint8_t* base;
+  uint64_t lim, off;  // value stream at base + off
+  uint32_t len;       // value-stream bytes
+  uint32_t w;         // index bit width
+  uint64_t total;     // indices (the page's non-null count)
+};
+__device__ __forceinline__ DiStream di_stream(const PageDev* pages, uint32_t p, const uint8_t* file,
+                                              const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim) {
+  DiStream st;
+  const bool sc = (pages[p].flags & 2) != 0;
+  st.base = sc ? scratch : file;
+  st.lim = sc ? scratch_lim : file_lim;
+  st.off = pages[p].val_off;
+  st.len = pages[p].val_len;
+  st.w = pages[p].enc_w;
+  st.total = pages[p].nonnull;
+  return st;
+}
+
+// One workgroup of DI_WG lanes per segment, each lane walking every
+// DI_WG-th candidate; the segment's run headers are staged in LDS.
+// Segment sg's candidates are cand[sg DI_CAND_MAX ..], di_cand(w) of them.
+__global__ __launch_bounds__(DI_WG) void k_di_cand(const DiPage* dps, const uint32_t* seg_page, const PageDev* pages,
+                                                   const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
+                                                   uint64_t scratch_lim, DiCand* cand, const uint32_t* err) {
+  __shared__ __align__(16) uint8_t s_seg[DI_LDS];
+  if (*(const volatile uint32_t*)err != 0) return;
+  const uint32_t sg = blockIdx.x;
+  const DiPage dp = dps[seg_page[sg]];
+  const DiStream st = di_stream(pages, dp.page, file, scratch, file_lim, scratch_lim);
+  const uint32_t j = sg - dp.seg0;
+  const uint64_t s0 = 1 + (uint64_t)j * DI_SEG;  // runs start after the width byte
+  DiCand* out = cand + (size_t)sg * DI_CAND_MAX;
+  const uint32_t ncand = di_cand(st.w);
+  if (s0 >= st.len) {
+    for (uint32_t c = threadIdx.x; c < ncand; c += DI_WG) out[c] = DiCand{DI_BAD, 0u};
+    return;
+  }
+  const uint32_t se = (uint32_t)min(s0 + DI_SEG, (uint64_t)st.len);       // run headers of this segment: [s0, se)
+  const uint32_t sh = (uint32_t)min(s0 + DI_SEG + 16, (uint64_t)st.len);  // staged: [s0, sh)
+  const uint64_t g0 = st.off + s0, a0 = g0 & ~15ull, ga = st.off + sh;
+  for (uint32_t k = threadIdx.x; a0 + 16ull * k < ga; k += DI_WG) {
+    const uint64_t a = a0 + 16ull * k;
+    wr_u4 v = {0u, 0u, 0u, 0u};
+    if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
+    *(lds_u4*)(&s_seg[16 * k]) = v;
+  }
+  __syncthreads();
+  const uint32_t d = (uint32_t)(g0 - a0) - (uint32_t)s0;  // LDS offset of stream byte x: d + x
+  const uint32_t vb = (st.w + 7) / 8;
+  for (uint32_t c = threadIdx.x; c < ncand; c += DI_WG) {
+    uint32_t q = (uint32_t)s0 + c, count = 0;
+    while (q < se) {
+      uint64_t h = 0;
+      uint32_t x = q;
+      bool whole = false;
+      for (uint32_t b7 = 0; b7 < 70; b7 += 7) {  // a header is 10 bytes at most
+        if (x >= st.len) break;
+        const uint32_t b = s_seg[d + x];
+        ++x;
+        if (b7 == 63 && (b & 0x7e)) break;
+        h |= (uint64_t)(b & 0x7f) << b7;
+        if (!(b & 0x80)) { whole = true; break; }
+      }
+      uint64_t n, nb;
+      if (!whole) { q = DI_BAD; break; }
+      if (h & 1) {
+        n = (h >> 1) * 8;
+        nb = (h >> 1) * st.w;
+        if ((h >> 1) > (1ull << 28) || nb > st.len - x) { q = DI_BAD; break; }
+      } else {
+        n = h >> 1;
+        nb = vb;
+        if (nb > st.len - x) { q = DI_BAD; break; }
+      }
+      count = lv_sat(count, n);
+      q = x + (uint32_t)nb;
+    }
+    out[c] = DiCand{q, count};
+  }
+}
+
+// One thread per page (see k_lv_link): ent[segment] = (entry offset, index
+// of the entry run's first value) along the true chain.
+__global__ void k_di_link(const DiPage* dps, int npg, const PageDev* pages, const DiCand* cand, DlEntry* ent,
+                          uint32_t* ok, uint32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npg) return;
+  const DiPage dp = dps[i];
+  for (uint32_t j = 0; j < dp.nseg; ++j) ent[dp.seg0 + j].q = LV_NONE;
+  ok[i] = 1;
+  if (*(volatile uint32_t*)err != 0) return;
+  const DiStream st = di_stream(pages, dp.page, nullptr, nullptr, 0, 0);
+  if (st.total == 0) return;
+  uint32_t q = 1, good = 1;
+  uint64_t K = 0;
+  for (;;) {
+    if (q >= st.len) { set_err(err, ERR_VALUES, dp.page); break; }  // the runs end before the last value
+    const uint32_t j = (q - 1) / DI_SEG, c = (q - 1) % DI_SEG;
+    if (j >= dp.nseg || c >= di_cand(st.w)) { good = 0; break; }
+    const DiCand cd = cand[(size_t)(dp.seg0 + j) * DI_CAND_MAX + c];
+    ent[dp.seg0 + j] = DlEntry{q, (uint32_t)K};
+    if (K + cd.count >= st.total) break;  // the run covering the last value starts in this segment
+    if (cd.exit == DI_BAD) { set_err(err, ERR_VALUES, dp.page); break; }
+    K += cd.count;
+    q = cd.exit;
+  }
+  if (!good) {
+    for (uint32_t j = 0; j < dp.nseg; ++j) ent[dp.seg0 + j].q = LV_NONE;
+    ok[i] = 0;
+  }
+}
+
+// mode 0: one wave per segment, from its entry; mode 1: one wave per page
+// that could not be linked.  Tiles holding values get the run that holds
+// their first value as entry.
+__global__ __launch_bounds__(64) void k_di_fill(const DiPage* dps, const uint32_t* seg_page, const DlEntry* ent,
+                                                const uint32_t* ok, const PageDev* pages, const uint8_t* file,
+                                                const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                                                TileDev* tiles, uint32_t* err, int mode) {
+  __shared__ wr_u4 s_win[WIN / 16];
+  if (*(volatile uint32_t*)err != 0) return;
+  uint32_t di, q, seg_end;
+  uint64_t K;
+  if (mode == 0) {
+    const DlEntry e = ent[blockIdx.x];
+    if (e.q == LV_NONE) return;
+    di = seg_page[blockIdx.x];
+    q = e.q;
+    K = e.k;
+    seg_end = 1 + (blockIdx.x - dps[di].seg0 + 1) * DI_SEG;
+  } else {
+    di = blockIdx.x;
+    if (ok[di] || pages[dps[di].page].nonnull == 0) return;
+    q = 1;
+    K = 0;
+    seg_end = 0xffffffffu;
+  }
+  const DiPage dp = dps[di];
+  const DiStream st = di_stream(pages, dp.page, file, scratch, file_lim, scratch_lim);
+  const uint32_t tb = pages[dp.page].tile_begin;
+  const uint32_t nt = (uint32_t)(((uint64_t)pages[dp.page].num_values + TILE_ROWS - 1) / TILE_ROWS);
+  // first tile whose first value is at or after K (k0 does not decrease)
+  uint32_t lo_t = 0, hi_t = nt;
+  while (lo_t < hi_t) {
+    const uint32_t mid = (lo_t + hi_t) / 2;
+    if (tiles[tb + mid].k0 < K) lo_t = mid + 1; else hi_t = mid;
+  }
+  uint32_t t = lo_t;
+  const bool lead = threadIdx.x == 0;
+  WR r;
+  r.init(st.base, st.lim, (lds_u4*)&s_win[0]);
+  const uint64_t vend = st.off + st.len;
+  RunCur c;
+  c.next = st.off + q; c.start = (int64_t)K; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = c.next;
+  for (;;) {
+    if (c.next - st.off >= seg_end) return;  // the next run belongs to a later segment
+    if (!run_next(r, vend, st.w, c)) { set_err(err, ERR_VALUES, dp.page); return; }
+    const uint64_t lo = (uint64_t)c.start, hi = lo + min(c.n, 1ull << 40);
+    for (; t < nt; ++t) {
+      const uint32_t k0 = tiles[tb + t].k0, nn = tiles[tb + t].nn;
+      if (k0 >= hi) break;
+      if (nn > 0 && lead) {
+        tiles[tb + t].val_pos = (uint32_t)(c.hp - st.off);
+        tiles[tb + t].val_skip = (uint32_t)(k0 - lo);
+      }
+    }
+    if (hi >= st.total) return;
+  }
+}
+
+// A dictionary-index run for one lane (run_next's rules for width w; the
+// RLE value is not read); byte(x) reads stream byte x (x < end).
+template <class Byte>
+__device__ __forceinline__ bool di_run_next(const Byte& byte, uint64_t end, uint32_t w, RunCur& c) {
+  uint64_t pos = c.next;
+  c.start += (int64_t)min(c.n, 1ull << 40);
+  c.hp = pos;
+  uint64_t h = 0;
+  bool whole = false;
+  for (int s = 0; s < 70; s += 7) {
+    if (pos >= end) return false;
+    const uint32_t b = byte(pos++);
+    if (s == 63 && (b & 0x7e)) return false;
+    h |= (uint64_t)(b & 0x7f) << s;
+    if (!(b & 0x80)) { whole = true; break; }
+  }
+  if (!whole) return false;
+  c.pay = pos;
+  c.val = 0;
+  if (h & 1) {
+    const uint64_t g = h >> 1;
+    if (g > (1ull << 28) || g * w > end - pos) return false;
+    c.bp = 1;
+    c.n = g * 8;
+    c.next = pos + g * w;
+  } else {
+    const uint32_t vb = (w + 7) / 8;
+    if (vb > end - pos) return false;
+    c.bp = 0;
+    c.n = h >> 1;
+    c.next = pos + vb;
+  }
+  return true;
+}
+
+// Four tiles per wave, lane 16 i + s computing checkpoint s of tile i: the
+// state of the run holding value k0 + 64 s, reached by walking the runs
+// from the tile's entry.
+__global__ __launch_bounds__(64) void k_di_ckpt(const DiPage* dps, const uint32_t* tile_dp, int ntl,
+                                                const PageDev* pages, const TileDev* tiles, const uint8_t* file,
+                                                const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                                                Ck* ckv, const uint32_t* err) {
+  static_assert(NSUB == 16, "16 lanes per tile");
+  if (*(const volatile uint32_t*)err != 0) return;
+  const uint32_t i = blockIdx.x * 4 + threadIdx.x / 16, sub = threadIdx.x % 16;
+  if ((int)i >= ntl) return;
+  const DiPage dp = dps[tile_dp[i]];
+  const DiStream st = di_stream(pages, dp.page, file, scratch, file_lim, scratch_lim);
+  const uint32_t T = pages[dp.page].tile_begin + (i - dp.tl0);
+  const TileDev td = tiles[T];
+  if ((uint64_t)sub * SUB_ROWS >= td.nn) return;
+  const uint64_t entry = st.off + td.val_pos, end = st.off + st.len;
+  const uint8_t* base = st.base;
+  auto byte = [&](uint64_t x) -> uint32_t { return base[x]; };
+  const int64_t target = (int64_t)td.k0 + (int64_t)sub * SUB_ROWS;
+  RunCur c;
+  c.next = entry; c.start = (int64_t)td.k0 - (int64_t)td.val_skip; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0;
+  c.hp = entry;
+  do {
+    if (!di_run_next(byte, end, st.w, c)) return;  // not reached for a linked stream
+  } while (c.start + (int64_t)min(c.n, 1ull << 40) <= target);
+  ckv[(size_t)T * NSUB + sub] = make_ck(c, target, st.w, entry, false);
 }
 
 }  // namespace pqk

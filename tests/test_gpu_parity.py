@@ -111,6 +111,23 @@ def _spec_cases():
             cases[f"long_delta_{blk}x{mini}{tag}"] = dg.FileSpec(
                 cols=dl_cols, num_rows=400_003, rg_rows=400_003, page_bytes=1 * dg.MiB, codec=codec,
                 page_version=ver, delta_block=blk, delta_mini=mini, name=f"long_delta_{blk}x{mini}{tag}")
+    # long dictionary-index streams, walked in segments side by side at
+    # open: index widths 1, 7, 10 (Zipf ranks: RLE runs among bit-packed
+    # ones), 14 (strings), 16 (bit-packed runs of 1009 bytes, the widest the
+    # candidates cover) and 20 (wider: those pages are walked whole); V1
+    # and V2 Snappy
+    di_cols = [
+        dg.Col(dg.INT32, dg.RLE_DICTIONARY, False, dg.DICTVALS, 0.0, hi=2),
+        dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.1, hi=100),
+        dg.Col(dg.INT32, dg.RLE_DICTIONARY, True, dg.ZIPF, 0.1, hi=1024, zipf_s=1.1),
+        dg.Col(dg.BYTE_ARRAY, dg.RLE_DICTIONARY, True, dg.STRINGS, 0.1, hi=10_000, str_min=8, str_max=44),
+        dg.Col(dg.INT32, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.05, hi=65536),
+        dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.DICTVALS, 0.05, hi=1_000_000),
+    ]
+    for ver, codec, tag in ((1, dg.UNCOMPRESSED, ""), (2, dg.SNAPPY, "_v2_snappy")):
+        cases[f"long_dict{tag}"] = dg.FileSpec(
+            cols=di_cols, num_rows=1_500_007, rg_rows=1_500_007, page_bytes=1 * dg.MiB, codec=codec,
+            page_version=ver, name=f"long_dict{tag}")
     return cases
 
 
@@ -295,6 +312,32 @@ def test_long_delta_stream_widths(how):
         assert used_mb < M
         b[wpos + used_mb] = 0xFF
         check_file(b, label="unused-width")
+
+
+def test_corrupt_long_index_stream_reported():
+    """3000 bytes of 0xFF in the middle of a long dictionary-index stream
+    (every run header there is an overlong ULEB128) are reported as corrupt
+    at open, as the oracle reports them."""
+    import oracle
+    import paper_2602_17335_amd as pqs
+    spec = dg.FileSpec(cols=[dg.Col(dg.INT64, dg.RLE_DICTIONARY, False, dg.DICTVALS, 0.0, hi=100)],
+                       num_rows=400_000, rg_rows=400_000, page_bytes=4 * dg.MiB)
+    b = dg.write(spec).copy()
+    raw = b.tobytes()
+    h, n = oracle.page_header(raw[4:4 + 256])
+    assert h.type == 2  # the dictionary page
+    at = 4 + n + h.compressed_size
+    h, n = oracle.page_header(raw[at:at + 256])
+    assert h.type == 0 and h.compressed_size == h.uncompressed_size and h.compressed_size > 4 * 32768
+    mid = at + n + h.compressed_size // 2
+    b[mid:mid + 3000] = 0xFF
+    with pytest.raises(oracle.OracleError):
+        oracle.File(b).read(0)
+    buf, n2 = pqs.to_device(b)
+    with pytest.raises(pqs.PqError) as e:
+        f = pqs.DeviceFile(buf, n2)
+        f.scan([0])
+    assert e.value.code == pqs.PQ_ECORRUPT
 
 
 def test_bad_magic_rejected_before_gpu_work():
