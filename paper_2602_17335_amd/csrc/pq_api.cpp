@@ -16,8 +16,12 @@
 #include "pq_internal.h"
 
 namespace pqk {
-__global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
-                       const uint32_t* page_base, PageDev* pages, uint32_t* err);
+__global__ void k_walk(const uint8_t* file, uint64_t file_lim, const ChunkDev* chunks, int nchunks, uint32_t* counts,
+                       const uint32_t* page_base, PageDev* pages, uint32_t* err, uint64_t* rec,
+                       const uint32_t* rec_base, const uint32_t* rec_cap, uint32_t* overflow);
+__global__ void k_walk_rec(const uint8_t* file, const ChunkDev* chunks, const uint64_t* rec, const uint32_t* rec_base,
+                           const uint32_t* page_base, const uint32_t* page_chunk, uint32_t npages, PageDev* pages,
+                           uint32_t* err);
 __global__ void k_index(const uint8_t* file, const uint8_t* scratch, PageDev* pages, int npages,
                         const ChunkDev* chunks, TileDev* tiles, uint32_t* strck, uint32_t* ckl, Ck* ckv,
                         uint32_t* err, uint64_t file_lim, uint64_t scratch_lim, const uint32_t* order,
@@ -28,10 +32,7 @@ __global__ void k_lv_link(const LvPage* lps, int npg, const PageDev* pages, cons
                           uint32_t* ok, uint32_t* err);
 __global__ void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const LvEntry* ent, const uint32_t* ok,
                            PageDev* pages, const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
-                           uint64_t scratch_lim, TileDev* tiles, uint32_t* err, int mode);
-__global__ void k_lv_ckpt(const LvPage* lps, const uint32_t* tile_lp, const PageDev* pages, const TileDev* tiles,
-                          const uint8_t* file, const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
-                          uint32_t* ckl, const uint32_t* err);
+                           uint64_t scratch_lim, TileDev* tiles, uint32_t* ckl, uint32_t* err, int mode);
 __global__ void k_dl_cand(const DlPage* dps, const uint32_t* seg_page, const PageDev* pages, const uint8_t* file,
                           const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim, DlCand* cand,
                           const uint32_t* err);
@@ -507,10 +508,13 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   HIP_OR(hipEventCreate(&e1));
   HIP_OR(hipEventRecord(e0, s));
   uint32_t *d_counts = nullptr, *d_base = nullptr;
+  uint8_t* d_rec = nullptr;  // header offsets recorded by the first walk, with their tables
   auto cleanup_tmp = [&]() {
     if (d_counts) (void)hipFree(d_counts);
     if (d_base) (void)hipFree(d_base);
+    if (d_rec) (void)hipFree(d_rec);
     d_counts = d_base = nullptr;
+    d_rec = nullptr;
   };
 #define OPEN_HIP(expr)                                                          \
   do {                                                                          \
@@ -529,15 +533,38 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
 
   OPEN_HIP(hipMalloc(&f->d_err, 4));
   OPEN_HIP(hipMemsetAsync(f->d_err, 0, 4, s));
+  // The first walk checks every header, counts the pages and records the
+  // header offsets of up to one page per KiB of each chunk; the page table
+  // is then parsed from the recorded offsets side by side, or, when a chunk
+  // has more pages than recorded, by a second walk.
+  std::vector<uint32_t> rec_base(nchunks + 1, 0), rec_cap(nchunks);
+  for (int q = 0; q < nchunks; ++q) {
+    rec_cap[q] = (uint32_t)std::min<uint64_t>((f->chunks[q].end - f->chunks[q].start) / 1024 + 8, 1u << 24);
+    rec_base[q + 1] = rec_base[q] + rec_cap[q];
+  }
+  const size_t o_rbase = align_up(8ull * rec_base[nchunks], 256), o_rcap = align_up(o_rbase + 4ull * nchunks, 256),
+               o_over = align_up(o_rcap + 4ull * nchunks, 256), o_pch = align_up(o_over + 4, 256);
+  uint32_t overflow = 1;
   if (nchunks > 0) {
     OPEN_HIP(hipMalloc(&f->d_chunks, sizeof(ChunkDev) * nchunks));
     OPEN_HIP(hipMalloc(&d_counts, sizeof(uint32_t) * nchunks));
     OPEN_HIP(hipMalloc(&d_base, sizeof(uint32_t) * nchunks));
     OPEN_HIP(hipMemcpyAsync(f->d_chunks, f->chunks.data(), sizeof(ChunkDev) * nchunks, hipMemcpyHostToDevice, s));
-    const int blocks = (nchunks + 63) / 64;
-    hipLaunchKernelGGL(k_walk, dim3(blocks), dim3(64), 0, s, file, f->d_chunks, nchunks, d_counts, nullptr, nullptr, f->d_err);
+    const bool record = hipMalloc(&d_rec, o_pch) == hipSuccess;  // (no room: the second walk)
+    uint64_t* d_recs = record ? reinterpret_cast<uint64_t*>(d_rec) : nullptr;
+    uint32_t* d_rbase = record ? reinterpret_cast<uint32_t*>(d_rec + o_rbase) : nullptr;
+    uint32_t* d_rcap = record ? reinterpret_cast<uint32_t*>(d_rec + o_rcap) : nullptr;
+    uint32_t* d_over = record ? reinterpret_cast<uint32_t*>(d_rec + o_over) : nullptr;
+    if (record) {
+      OPEN_HIP(hipMemcpyAsync(d_rbase, rec_base.data(), 4ull * nchunks, hipMemcpyHostToDevice, s));
+      OPEN_HIP(hipMemcpyAsync(d_rcap, rec_cap.data(), 4ull * nchunks, hipMemcpyHostToDevice, s));
+      OPEN_HIP(hipMemsetAsync(d_over, 0, 4, s));
+    }
+    hipLaunchKernelGGL(k_walk, dim3((uint32_t)nchunks), dim3(64), 0, s, file, (len + 15) & ~15ull, f->d_chunks, nchunks,
+                       d_counts, nullptr, nullptr, f->d_err, d_recs, d_rbase, d_rcap, d_over);
     OPEN_HIP(hipGetLastError());
     OPEN_ERR();
+    if (record) OPEN_HIP(hipMemcpy(&overflow, d_over, 4, hipMemcpyDeviceToHost));
   }
   std::vector<uint32_t> counts(nchunks);
   if (nchunks) OPEN_HIP(hipMemcpy(counts.data(), d_counts, sizeof(uint32_t) * nchunks, hipMemcpyDeviceToHost));
@@ -547,9 +574,30 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   if (npages > 0) {
     OPEN_HIP(hipMalloc(&f->d_pages, sizeof(PageDev) * npages));
     OPEN_HIP(hipMemcpyAsync(d_base, f->chunk_page0.data(), sizeof(uint32_t) * nchunks, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_walk, dim3((nchunks + 63) / 64), dim3(64), 0, s, file, f->d_chunks, nchunks, nullptr, d_base,
-                       f->d_pages, f->d_err);
-    OPEN_HIP(hipGetLastError());
+    uint32_t* d_pch = nullptr;
+    std::vector<uint32_t> page_chunk;
+    if (!overflow) {
+      page_chunk.resize(npages);
+      for (int q = 0; q < nchunks; ++q)
+        for (uint32_t p = f->chunk_page0[q]; p < f->chunk_page0[q + 1]; ++p) page_chunk[p] = (uint32_t)q;
+      if (hipMalloc(&d_pch, 4ull * npages) != hipSuccess) overflow = 1;
+    }
+    if (!overflow) {
+      hipError_t e2 = hipMemcpyAsync(d_pch, page_chunk.data(), 4ull * npages, hipMemcpyHostToDevice, s);
+      if (e2 == hipSuccess) {
+        hipLaunchKernelGGL(k_walk_rec, dim3((npages + 255) / 256), dim3(256), 0, s, file, f->d_chunks,
+                           reinterpret_cast<const uint64_t*>(d_rec), reinterpret_cast<const uint32_t*>(d_rec + o_rbase),
+                           d_base, d_pch, npages, f->d_pages, f->d_err);
+        e2 = hipGetLastError();
+      }
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);  // before d_pch and page_chunk go
+      (void)hipFree(d_pch);
+      OPEN_HIP(e2);
+    } else {
+      hipLaunchKernelGGL(k_walk, dim3((uint32_t)nchunks), dim3(64), 0, s, file, (len + 15) & ~15ull, f->d_chunks,
+                         nchunks, nullptr, d_base, f->d_pages, f->d_err, nullptr, nullptr, nullptr, nullptr);
+      OPEN_HIP(hipGetLastError());
+    }
     OPEN_ERR();
     f->pages.resize(npages);
     OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
@@ -775,37 +823,32 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     }
     if (!lv_list.empty()) {
       std::vector<LvPage> lps;
-      std::vector<uint32_t> seg_page, tile_lp, order2;
+      std::vector<uint32_t> seg_page, order2;
       for (uint32_t p : lv_list) {
         const PageDev& pg = f->pages[p];
         LvPage x;
         x.page = p;
         x.seg0 = (uint32_t)seg_page.size();
         x.nseg = (uint32_t)(((uint64_t)(pg.def_len > 0 ? pg.def_len : 0) + LV_SEG - 1) / LV_SEG);
-        x.tl0 = (uint32_t)tile_lp.size();
-        const uint32_t nt = (uint32_t)(((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS);
         for (uint32_t j = 0; j < x.nseg; ++j) seg_page.push_back((uint32_t)lps.size());
-        for (uint32_t j = 0; j < nt; ++j) tile_lp.push_back((uint32_t)lps.size());
         lps.push_back(x);
         order2.push_back(p);
       }
       std::stable_sort(order2.begin(), order2.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
-      const size_t npg = lps.size(), nseg = seg_page.size(), ntl = tile_lp.size();
-      const size_t o_seg = align_up(sizeof(LvPage) * npg, 256), o_tl = align_up(o_seg + 4 * nseg, 256),
-                   o_ord = align_up(o_tl + 4 * ntl, 256), o_cand = align_up(o_ord + 4 * npg, 256),
+      const size_t npg = lps.size(), nseg = seg_page.size();
+      const size_t o_seg = align_up(sizeof(LvPage) * npg, 256), o_ord = align_up(o_seg + 4 * nseg, 256),
+                   o_cand = align_up(o_ord + 4 * npg, 256),
                    o_ent = align_up(o_cand + sizeof(LvCand) * LV_CAND * nseg, 256),
                    o_ok = align_up(o_ent + sizeof(LvEntry) * nseg, 256), total = o_ok + 4 * npg;
       if (hipMalloc(&d_lv, total) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: level walk tables"); }
       LvPage* d_lps = reinterpret_cast<LvPage*>(d_lv);
       uint32_t* d_segp = reinterpret_cast<uint32_t*>(d_lv + o_seg);
-      uint32_t* d_tlp = reinterpret_cast<uint32_t*>(d_lv + o_tl);
       uint32_t* d_ord2 = reinterpret_cast<uint32_t*>(d_lv + o_ord);
       LvCand* d_cand = reinterpret_cast<LvCand*>(d_lv + o_cand);
       LvEntry* d_ent = reinterpret_cast<LvEntry*>(d_lv + o_ent);
       uint32_t* d_ok = reinterpret_cast<uint32_t*>(d_lv + o_ok);
       OPEN_HIP(hipMemcpyAsync(d_lps, lps.data(), sizeof(LvPage) * npg, hipMemcpyHostToDevice, s));
       if (nseg) OPEN_HIP(hipMemcpyAsync(d_segp, seg_page.data(), 4 * nseg, hipMemcpyHostToDevice, s));
-      if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_lp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
       OPEN_HIP(hipMemcpyAsync(d_ord2, order2.data(), 4 * npg, hipMemcpyHostToDevice, s));
       if (nseg)
         hipLaunchKernelGGL(k_lv_cand, dim3((uint32_t)nseg), dim3(LV_CAND), 0, s, d_lps, d_segp, f->d_pages, file,
@@ -814,12 +857,9 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
                          d_cand, d_ent, d_ok, f->d_err);
       if (nseg)
         hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)nseg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages,
-                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 0);
+                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_ckl, f->d_err, 0);
       hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)npg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages, file,
-                         d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 1);
-      if (ntl)
-        hipLaunchKernelGGL(k_lv_ckpt, dim3((uint32_t)ntl), dim3(64), 0, s, d_lps, d_tlp, f->d_pages, f->d_tiles, file,
-                           d_scratch, flim, (uint64_t)scratch, f->d_ckl, f->d_err);
+                         d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_ckl, f->d_err, 1);
       hipLaunchKernelGGL(k_index, dim3((uint32_t)npg), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npg,
                          f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, (uint64_t)scratch,
                          d_ord2, d_xscratch, xscratch, 2);

@@ -58,7 +58,8 @@ __device__ __forceinline__ uint64_t br_uleb(R& r, uint64_t& pos, uint64_t end, b
 __device__ __forceinline__ int64_t unzz(uint64_t v) { return (int64_t)(v >> 1) ^ -(int64_t)(v & 1); }
 
 // Skips one Thrift-compact value of `type` (iterative; nesting depth <= 8).
-__device__ inline bool th_skip(BR& r, uint64_t& pos, uint64_t end, int type) {
+template <class R>
+__device__ inline bool th_skip(R& r, uint64_t& pos, uint64_t end, int type) {
   struct Fr { int is_list; int etype; uint32_t left; };
   Fr st[8];
   int sp = 0;
@@ -115,8 +116,10 @@ struct PageHdr {
   int32_t has_sub;
 };
 
-// Parses one Thrift-compact PageHeader starting at pos; pos ends past it.
-__device__ inline bool parse_page_header(BR& r, uint64_t& pos, uint64_t end, PageHdr& h) {
+// Parses one Thrift-compact PageHeader starting at pos; pos ends past it
+// (through any reader with byte()).
+template <class R>
+__device__ inline bool parse_page_header(R& r, uint64_t& pos, uint64_t end, PageHdr& h) {
   h.type = -1; h.unc = -1; h.comp = -1; h.nv = -1; h.enc = -1; h.nnulls = 0; h.nrows = -1;
   h.def_len = 0; h.rep_len = 0; h.is_comp = 1; h.has_sub = 0;
   bool bad = false;

@@ -165,9 +165,9 @@ struct PageDev {
 // than LV_MIN level bytes are indexed in LV_SEG-byte segments side by side:
 // LV_CAND candidate chains per segment (one from each of its first LV_CAND
 // bytes), a per-page link through the candidates' exits, then the tile
-// entries per segment and the level checkpoints per tile.
+// entries and level checkpoints per segment.
 constexpr uint32_t LV_MIN = 8192;
-constexpr uint32_t LV_SEG = 16384;
+constexpr uint32_t LV_SEG = 2048;
 constexpr uint32_t LV_CAND = 128;
 constexpr uint32_t LV_NONE = 0xffffffffu;
 __host__ __device__ inline bool lv_page(const PageDev& pg, bool optional) {
@@ -178,7 +178,6 @@ __host__ __device__ inline bool lv_page(const PageDev& pg, bool optional) {
 }
 struct LvPage {
   uint32_t page, seg0, nseg;  // segments [seg0, seg0 + nseg) of the segment list
-  uint32_t tl0;               // first entry of the page in the tile list
 };
 // A candidate chain of one segment: stream offset where it leaves the
 // segment, rows and valid rows of the runs that start in it (saturating at

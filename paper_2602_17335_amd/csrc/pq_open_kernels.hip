@@ -4,7 +4,7 @@
 //            level and value streams of each data page, string checkpoints.
 //   k_schain_cand / k_schain_link / k_schain_fill / k_schain_seq
 //            string checkpoints of long dictionary pages, segments side by side
-//   k_lv_cand / k_lv_link / k_lv_tiles / k_lv_ckpt
+//   k_lv_cand / k_lv_link / k_lv_tiles
 //            tile entries, level checkpoints and non-null counts of pages
 //            with long definition-level streams, segments side by side
 //   k_dl_cand / k_dl_link / k_dl_fill / k_dl_tiles
@@ -19,82 +19,6 @@
 #include "pq_internal.h"
 
 namespace pqk {
-
-// One lane per column chunk.  Walks PageHeader, payload, PageHeader, ...
-// from the chunk start until the chunk's byte range is consumed.  With
-// `pages == nullptr` it only counts pages (first pass); otherwise it writes
-// the page table entries at page_base[chunk].
-__global__ void k_walk(const uint8_t* file, const ChunkDev* chunks, int nchunks, uint32_t* counts,
-                       const uint32_t* page_base, PageDev* pages, uint32_t* err) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nchunks) return;
-  ChunkDev c = chunks[q];
-  BR r;
-  r.init(file);
-  uint64_t pos = c.start;
-  uint32_t n = 0;
-  int64_t rows = 0;
-  bool seen_data = false, seen_dict = false;
-  while (pos < c.end) {
-    PageHdr h;
-    if (!parse_page_header(r, pos, c.end, h) || h.type < 0 || h.unc < 0 || h.comp < 0) { set_err(err, ERR_HEADER, q); return; }
-    uint64_t payload = pos;
-    if ((uint64_t)h.comp > c.end - payload) { set_err(err, ERR_CHUNK_BOUNDS, q); return; }
-    pos = payload + (uint64_t)h.comp;
-    if (h.type == PAGE_DICT) {
-      if (seen_data || seen_dict) { set_err(err, ERR_PAGE_ORDER, q); return; }
-      if (!h.has_sub || h.nv < 0) { set_err(err, ERR_HEADER, q); return; }
-      if (h.enc != E_PLAIN && h.enc != E_PLAIN_DICT) { set_err(err, ERR_UNSUPPORTED, q); return; }
-      if (c.codec == 0 && h.comp != h.unc) { set_err(err, ERR_HEADER, q); return; }
-      seen_dict = true;
-    } else if (h.type == PAGE_DATA || h.type == PAGE_DATA_V2) {
-      if (!h.has_sub || h.nv < 0) { set_err(err, ERR_HEADER, q); return; }
-      bool enc_ok = h.enc == E_PLAIN || h.enc == E_PLAIN_DICT || h.enc == E_RLE_DICT ||
-                    (h.enc == E_DELTA && (c.type == T_INT32 || c.type == T_INT64)) ||
-                    (h.enc == E_BSS && c.type != T_BYTE_ARRAY) ||
-                    ((h.enc == E_DLBA || h.enc == E_DBA) && c.type == T_BYTE_ARRAY);
-      // (DELTA_BYTE_ARRAY pages open, and are reported as unsupported only
-      // when a scan selects their column)
-      if (!enc_ok) { set_err(err, ERR_UNSUPPORTED, q); return; }
-      if (h.type == PAGE_DATA_V2) {
-        if (h.rep_len != 0) { set_err(err, ERR_UNSUPPORTED, q); return; }
-        if (h.def_len < 0 || h.nrows != h.nv || h.def_len > h.comp || h.def_len > h.unc || h.nnulls < 0 ||
-            (!c.optional && (h.def_len != 0 || h.nnulls != 0))) { set_err(err, ERR_V2, q); return; }
-        bool compressed = c.codec == 1 && h.is_comp;
-        if (!compressed && h.comp != h.unc) { set_err(err, ERR_V2, q); return; }
-      } else if (c.codec == 0 && h.comp != h.unc) { set_err(err, ERR_HEADER, q); return; }
-      rows += h.nv;
-      if (rows > c.rows) { set_err(err, ERR_ROWS, q); return; }
-      seen_data = true;
-    } else {
-      continue;  // index pages and unknown page types are skipped
-    }
-    if (pages) {
-      PageDev p;
-      p.payload = payload;
-      p.comp_size = (uint32_t)h.comp;
-      p.uncomp_size = (uint32_t)h.unc;
-      p.num_values = h.nv;
-      p.num_nulls = h.type == PAGE_DATA_V2 ? h.nnulls : -1;
-      p.chunk = (uint32_t)q;
-      p.kind = (uint8_t)h.type;
-      p.encoding = (uint8_t)h.enc;
-      p.v2_compressed = (uint8_t)(h.type == PAGE_DATA_V2 ? h.is_comp : 1);
-      p.flags = 0;
-      p.def_len = h.type == PAGE_DATA_V2 ? h.def_len : 0;
-      p.rep_len = h.type == PAGE_DATA_V2 ? h.rep_len : 0;
-      p.def_off = 0; p.val_off = 0; p.val_len = 0;
-      p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
-      p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u; p.dict_maxlen = 0;
-      p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.sblk_begin = 0; p.chars_at = 0;
-      p.x_src = 0; p.x_len = 0; p.x_sfx = 0; p.x_chars = 0; p.xlen = 0; p.x_total = 0; p.x_scratch = 0; p.x_off = 0;
-      pages[page_base[q] + n] = p;
-    }
-    ++n;
-  }
-  if (pos != c.end || rows != c.rows) { set_err(err, ERR_ROWS, q); return; }
-  if (counts) counts[q] = n;
-}
 
 // Hybrid-run cursor used by the index pass (one lane).
 struct RunCur {
@@ -173,6 +97,146 @@ struct WR {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3));
   }
 };
+
+// Wave reader with the window in registers: 256 bytes, four per lane; a
+// read at a wave-uniform offset is one v_readlane, so a walk whose every
+// position is wave-uniform waits on memory once per window, not per byte.
+// Every lane must take part in every read.  It reads a global buffer
+// readable up to lim (a multiple of 16); bytes at or past lim read as zero.
+struct GRegWin {
+  const uint8_t* base;
+  uint64_t lim, wl;  // window start (a multiple of 4)
+  uint32_t v;
+  __device__ __forceinline__ void init(const uint8_t* b, uint64_t l) {
+    base = b;
+    lim = l;
+    wl = 1ull << 63;  // far from every offset: the first read fills the window
+    v = 0;
+  }
+  __device__ __forceinline__ uint32_t byte(uint64_t off) {
+    if (off - wl >= 256) {
+      wl = off & ~3ull;
+      const uint64_t a = wl + 4ull * (threadIdx.x & 63);
+      v = a + 4 <= lim ? *reinterpret_cast<const uint32_t*>(base + a) : 0u;
+    }
+    const uint32_t o = (uint32_t)(off - wl);
+    return ((uint32_t)__builtin_amdgcn_readlane((int)v, (int)(o >> 2)) >> (8 * (o & 3))) & 0xffu;
+  }
+};
+
+// The page table entry of a page whose header h was parsed, payload first.
+__device__ __forceinline__ PageDev make_page(const PageHdr& h, uint64_t payload, uint32_t chunk) {
+  PageDev p;
+  p.payload = payload;
+  p.comp_size = (uint32_t)h.comp;
+  p.uncomp_size = (uint32_t)h.unc;
+  p.num_values = h.nv;
+  p.num_nulls = h.type == PAGE_DATA_V2 ? h.nnulls : -1;
+  p.chunk = chunk;
+  p.kind = (uint8_t)h.type;
+  p.encoding = (uint8_t)h.enc;
+  p.v2_compressed = (uint8_t)(h.type == PAGE_DATA_V2 ? h.is_comp : 1);
+  p.flags = 0;
+  p.def_len = h.type == PAGE_DATA_V2 ? h.def_len : 0;
+  p.rep_len = h.type == PAGE_DATA_V2 ? h.rep_len : 0;
+  p.def_off = 0; p.val_off = 0; p.val_len = 0;
+  p.scratch_len = 0; p.scratch_off = 0; p.row0 = 0;
+  p.tile_begin = 0; p.nonnull = 0; p.strck_begin = 0; p.dict_page = ~0u; p.dict_maxlen = 0;
+  p.enc_w = 0; p.enc_m = 0; p.delta_first = 0; p.blocks_at = 0; p.sblk_begin = 0; p.chars_at = 0;
+  p.x_src = 0; p.x_len = 0; p.x_sfx = 0; p.x_chars = 0; p.xlen = 0; p.x_total = 0; p.x_scratch = 0; p.x_off = 0;
+  return p;
+}
+
+// One wave per column chunk.  Walks PageHeader, payload, PageHeader, ...
+// from the chunk start until the chunk's byte range is consumed, checking
+// every header.  With `pages == nullptr` it counts pages (first pass) and,
+// when `rec` is given, records the header offsets of the first rec_cap[chunk]
+// pages at rec[rec_base[chunk] ..] (setting *overflow past that); otherwise
+// it writes the page table entries at page_base[chunk].  Each header is
+// read through a register window that the wave fills with one coalesced
+// load (the headers of a chunk lie a page apart, so a byte-serial reader
+// would wait on memory for every 16 bytes); every lane parses, lane 0
+// stores.
+__global__ __launch_bounds__(64) void k_walk(const uint8_t* file, uint64_t file_lim, const ChunkDev* chunks,
+                                             int nchunks, uint32_t* counts, const uint32_t* page_base,
+                                             PageDev* pages, uint32_t* err, uint64_t* rec, const uint32_t* rec_base,
+                                             const uint32_t* rec_cap, uint32_t* overflow) {
+  const int q = blockIdx.x;
+  if (q >= nchunks) return;
+  const bool lead = threadIdx.x == 0;
+  ChunkDev c = chunks[q];
+  GRegWin r;
+  r.init(file, file_lim);
+  uint64_t pos = c.start;
+  uint32_t n = 0;
+  int64_t rows = 0;
+  bool seen_data = false, seen_dict = false;
+  const uint32_t cap = rec ? rec_cap[q] : 0u;
+  while (pos < c.end) {
+    PageHdr h;
+    const uint64_t hpos = pos;
+    if (!parse_page_header(r, pos, c.end, h) || h.type < 0 || h.unc < 0 || h.comp < 0) { if (lead) set_err(err, ERR_HEADER, q); return; }
+    uint64_t payload = pos;
+    if ((uint64_t)h.comp > c.end - payload) { if (lead) set_err(err, ERR_CHUNK_BOUNDS, q); return; }
+    pos = payload + (uint64_t)h.comp;
+    if (h.type == PAGE_DICT) {
+      if (seen_data || seen_dict) { if (lead) set_err(err, ERR_PAGE_ORDER, q); return; }
+      if (!h.has_sub || h.nv < 0) { if (lead) set_err(err, ERR_HEADER, q); return; }
+      if (h.enc != E_PLAIN && h.enc != E_PLAIN_DICT) { if (lead) set_err(err, ERR_UNSUPPORTED, q); return; }
+      if (c.codec == 0 && h.comp != h.unc) { if (lead) set_err(err, ERR_HEADER, q); return; }
+      seen_dict = true;
+    } else if (h.type == PAGE_DATA || h.type == PAGE_DATA_V2) {
+      if (!h.has_sub || h.nv < 0) { if (lead) set_err(err, ERR_HEADER, q); return; }
+      bool enc_ok = h.enc == E_PLAIN || h.enc == E_PLAIN_DICT || h.enc == E_RLE_DICT ||
+                    (h.enc == E_DELTA && (c.type == T_INT32 || c.type == T_INT64)) ||
+                    (h.enc == E_BSS && c.type != T_BYTE_ARRAY) ||
+                    ((h.enc == E_DLBA || h.enc == E_DBA) && c.type == T_BYTE_ARRAY);
+      // (DELTA_BYTE_ARRAY pages open, and are reported as unsupported only
+      // when a scan selects their column)
+      if (!enc_ok) { if (lead) set_err(err, ERR_UNSUPPORTED, q); return; }
+      if (h.type == PAGE_DATA_V2) {
+        if (h.rep_len != 0) { if (lead) set_err(err, ERR_UNSUPPORTED, q); return; }
+        if (h.def_len < 0 || h.nrows != h.nv || h.def_len > h.comp || h.def_len > h.unc || h.nnulls < 0 ||
+            (!c.optional && (h.def_len != 0 || h.nnulls != 0))) { if (lead) set_err(err, ERR_V2, q); return; }
+        bool compressed = c.codec == 1 && h.is_comp;
+        if (!compressed && h.comp != h.unc) { if (lead) set_err(err, ERR_V2, q); return; }
+      } else if (c.codec == 0 && h.comp != h.unc) { if (lead) set_err(err, ERR_HEADER, q); return; }
+      rows += h.nv;
+      if (rows > c.rows) { if (lead) set_err(err, ERR_ROWS, q); return; }
+      seen_data = true;
+    } else {
+      continue;  // index pages and unknown page types are skipped
+    }
+    if (pages) {
+      const PageDev p = make_page(h, payload, (uint32_t)q);
+      if (lead) pages[page_base[q] + n] = p;
+    } else if (rec && lead) {
+      if (n < cap) rec[rec_base[q] + n] = hpos;
+      else *overflow = 1;
+    }
+    ++n;
+  }
+  if (pos != c.end || rows != c.rows) { if (lead) set_err(err, ERR_ROWS, q); return; }
+  if (counts && lead) counts[q] = n;
+}
+
+// One lane per page recorded by k_walk's first pass: parses its header again
+// (already checked there) into the page table.  page_chunk[i] is page i's
+// chunk; its header offset is rec[rec_base[chunk] + i - page_base[chunk]].
+__global__ void k_walk_rec(const uint8_t* file, const ChunkDev* chunks, const uint64_t* rec, const uint32_t* rec_base,
+                           const uint32_t* page_base, const uint32_t* page_chunk, uint32_t npages, PageDev* pages,
+                           uint32_t* err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npages) return;
+  const uint32_t q = page_chunk[i];
+  const uint64_t end = chunks[q].end;
+  uint64_t pos = rec[rec_base[q] + (i - page_base[q])];
+  BR r;
+  r.init(file);
+  PageHdr h;
+  if (!parse_page_header(r, pos, end, h)) { set_err(err, ERR_HEADER, q); return; }
+  pages[i] = make_page(h, pos, q);
+}
 
 // Reads the run header at cur.next; returns false when the stream ends or a
 // run leaves it.
@@ -805,17 +869,23 @@ __global__ __launch_bounds__(64) void k_schain_seq(const SChainPage* pgs, int np
 // chain that starts at byte c of the segment, summing the rows and valid rows
 // of the runs whose header lies in the segment, until it leaves it.  Runs are
 // short (a bit-packed run of 63 groups takes 65 bytes), so the true chain
-// enters each segment within its first LV_CAND bytes; k_lv_link follows it
-// from segment to segment through the candidates' exits, up to the run that
-// covers the page's last row.  k_lv_tiles walks each segment's true chain
-// once more from its entry, storing the entries of the tiles whose first row
-// lies in its runs and, in the segment of the last row, the page's non-null
-// count; a page whose chain leaves the candidates is walked whole by one wave
-// (mode 1).  k_lv_ckpt then derives each tile's level checkpoints from its
-// entry, one checkpoint per lane.
+// enters each segment within its first LV_CAND bytes.  A chain that does not
+// start at a run header soon reads an RLE value above 1 and stops, or meets
+// a true header and goes on as the true chain: chains that reach the same
+// header past the candidates' start bytes are walked from there once.
+// k_lv_link follows the true chain from segment to segment through the
+// candidates' exits, up to the run that covers the page's last row.
+// k_lv_tiles (mode 0) then indexes a segment with one wave: lane 0 finds the
+// first run header in each of its 64 sub-segments, each lane sums the valid
+// rows of its sub-segment's runs, and each lane walks them once more,
+// storing the entries of the tiles whose first row lies in them with the 64
+// level checkpoints of each such tile and, at the page's last row, the
+// non-null count.  A page whose chain leaves the candidates is walked whole
+// by one wave (mode 1).
 // ---------------------------------------------------------------------------
 constexpr uint32_t LV_XTRA = 1024;  // bytes staged past a segment, for the runs that leave it
 constexpr uint32_t LV_LDS = LV_SEG + LV_XTRA + 64;
+constexpr uint32_t LV_SUB = LV_SEG / 64;  // sub-segment bytes (one lane each)
 static_assert(LV_CAND <= LV_SEG && LV_CAND % 64 == 0, "candidates: whole waves inside a segment");
 
 struct LvStream {
@@ -841,12 +911,39 @@ __device__ __forceinline__ uint32_t lv_sat(uint32_t a, uint64_t b) {
   return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x;
 }
 
+// Stages stream bytes [s0, sh) of st in LDS (16-byte chunks from the one
+// holding byte s0; bytes at or past the readable limit read as zero), with
+// `nthr` threads; returns d such that stream byte x sits at LDS byte d + x
+// (32-bit wrap-around).
+__device__ __forceinline__ uint32_t lv_stage(const LvStream& st, uint32_t s0, uint32_t sh, uint8_t* lds, uint32_t nthr) {
+  const uint64_t g0 = st.off + s0, a0 = g0 & ~15ull, ga = st.off + sh;
+  for (uint32_t k = threadIdx.x; a0 + 16ull * k < ga; k += nthr) {
+    const uint64_t a = a0 + 16ull * k;
+    wr_u4 v = {0u, 0u, 0u, 0u};
+    if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
+    *(lds_u4*)(&lds[16 * k]) = v;
+  }
+  return (uint32_t)(g0 - a0) - s0;
+}
+
+// A run header of at most 4 bytes, decoded from the 4 bytes wv that start
+// with it: returns its length (0: longer, read it byte by byte) and sets h.
+__device__ __forceinline__ uint32_t uleb4(uint32_t wv, uint32_t& h) {
+  const uint32_t cont = ~wv & 0x80808080u;  // bytes that end the header
+  if (cont == 0) return 0;
+  const uint32_t hl = (__builtin_ctz(cont) >> 3) + 1;
+  const uint32_t hv = (wv & 0x7fu) | ((wv >> 1) & 0x3f80u) | ((wv >> 2) & 0x1fc000u) | ((wv >> 3) & 0xfe00000u);
+  h = hl == 4 ? hv : hv & ((1u << (7 * hl)) - 1u);
+  return hl;
+}
+
 // One workgroup of LV_CAND lanes per segment; the segment and LV_XTRA bytes
 // after it are staged in LDS.
 __global__ __launch_bounds__(LV_CAND) void k_lv_cand(const LvPage* lps, const uint32_t* seg_page, const PageDev* pages,
                                                      const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
                                                      uint64_t scratch_lim, LvCand* cand) {
   __shared__ __align__(16) uint8_t s_seg[LV_LDS];
+  __shared__ uint32_t s_p1[LV_CAND], s_exit[LV_CAND], s_state[LV_CAND], s_rows[LV_CAND], s_valid[LV_CAND];
   const uint32_t sg = blockIdx.x, c = threadIdx.x;
   const LvPage lp = lps[seg_page[sg]];
   const LvStream st = lv_stream(pages, lp.page, file, scratch, file_lim, scratch_lim);
@@ -856,58 +953,71 @@ __global__ __launch_bounds__(LV_CAND) void k_lv_cand(const LvPage* lps, const ui
     const uint32_t se = min(s0 + LV_SEG, st.len);           // run headers of this segment: [s0, se)
     const uint32_t sh = min(s0 + LV_SEG + LV_XTRA, st.len);  // staged stream bytes: [s0, sh)
     const bool to_end = sh == st.len;                        // the staged bytes reach the stream's end
-    const uint64_t g0 = st.off + s0, a0 = g0 & ~15ull, ga = st.off + sh;
-    for (uint32_t k = c; a0 + 16ull * k < ga; k += LV_CAND) {
-      const uint64_t a = a0 + 16ull * k;
-      wr_u4 v = {0u, 0u, 0u, 0u};
-      if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
-      *(lds_u4*)(&s_seg[16 * k]) = v;
+    const uint32_t d = lv_stage(st, s0, sh, &s_seg[0], LV_CAND);
+    __syncthreads();
+    const __attribute__((address_space(3))) uint32_t* w32 = (const __attribute__((address_space(3))) uint32_t*)&s_seg[0];
+    // walks the runs whose header lies before `lim` from q, adding their rows
+    // and valid rows; 0 when it got there, 1 at an invalid run, 2 at a run
+    // the staged bytes do not hold
+    auto walk = [&](uint32_t& q, uint32_t lim, uint32_t& rows, uint32_t& valid) -> uint32_t {
+      while (q < lim) {
+        uint64_t h = 0;
+        uint32_t x = q;
+        bool whole = false;
+        for (uint32_t b7 = 0; b7 < 70; b7 += 7) {
+          if (x >= sh) return to_end ? 1u : 2u;
+          const uint32_t b = s_seg[d + x];
+          ++x;
+          if (b7 == 63 && (b & 0x7e)) return 1;
+          h |= (uint64_t)(b & 0x7f) << b7;
+          if (!(b & 0x80)) { whole = true; break; }
+        }
+        if (!whole) return 1;
+        if (h & 1) {
+          const uint64_t g = h >> 1;  // payload bytes
+          if (g > (1ull << 28) || g > st.len - x) return 1;
+          if (x + g > sh) return 2;
+          uint32_t cnt = 0;
+          const uint32_t o = d + x;
+          for (uint32_t i = 0; i < (uint32_t)g; i += 4) {
+            uint32_t v = __builtin_amdgcn_alignbyte(w32[((o + i) >> 2) + 1], w32[(o + i) >> 2], (o + i) & 3);
+            if ((uint32_t)g - i < 4) v &= (1u << (8 * ((uint32_t)g - i))) - 1u;
+            cnt += __popc(v);
+          }
+          rows = lv_sat(rows, 8 * g);
+          valid = lv_sat(valid, cnt);
+          q = x + (uint32_t)g;
+        } else {
+          if (x >= st.len) return 1;
+          if (x >= sh) return 2;
+          const uint32_t v = s_seg[d + x];
+          if (v > 1) return 1;
+          rows = lv_sat(rows, h >> 1);
+          if (v) valid = lv_sat(valid, h >> 1);
+          q = x + 1;
+        }
+      }
+      return 0;
+    };
+    uint32_t q = s0 + c, rows = 0, valid = 0;
+    const uint32_t state = walk(q, min(se, s0 + LV_CAND), rows, valid);
+    const uint32_t p1 = (state == 0 && q < se) ? q : LV_NONE;  // first header past the start bytes
+    s_p1[c] = p1;
+    __syncthreads();
+    uint32_t lead = c;  // the first candidate that reached the same header
+    if (p1 != LV_NONE)
+      for (uint32_t k = 0; k < c; ++k)
+        if (s_p1[k] == p1) { lead = k; break; }
+    if (p1 != LV_NONE && lead == c) {
+      uint32_t q2 = q, r2 = 0, v2 = 0;
+      s_state[c] = walk(q2, se, r2, v2);
+      s_exit[c] = q2;
+      s_rows[c] = r2;
+      s_valid[c] = v2;
     }
     __syncthreads();
-    const uint32_t d = (uint32_t)(g0 - a0);  // LDS offset of stream byte s0
-    const __attribute__((address_space(3))) uint32_t* w32 = (const __attribute__((address_space(3))) uint32_t*)&s_seg[0];
-    uint32_t q = s0 + c, rows = 0, valid = 0, state = 0;
-    while (q < se) {
-      uint64_t h = 0;
-      uint32_t x = q;
-      bool whole = false;
-      for (uint32_t b7 = 0; b7 < 70; b7 += 7) {
-        if (x >= sh) { state = to_end ? 1u : 2u; break; }
-        const uint32_t b = s_seg[d + (x - s0)];
-        ++x;
-        if (b7 == 63 && (b & 0x7e)) { state = 1; break; }
-        h |= (uint64_t)(b & 0x7f) << b7;
-        if (!(b & 0x80)) { whole = true; break; }
-      }
-      if (!whole) {
-        if (state == 0) state = 1;
-        break;
-      }
-      if (h & 1) {
-        const uint64_t g = h >> 1;  // payload bytes
-        if (g > (1ull << 28) || g > st.len - x) { state = 1; break; }
-        if (x + g > sh) { state = 2; break; }
-        uint32_t cnt = 0;
-        const uint32_t o = d + (x - s0);
-        for (uint32_t i = 0; i < (uint32_t)g; i += 4) {
-          uint32_t v = __builtin_amdgcn_alignbyte(w32[((o + i) >> 2) + 1], w32[(o + i) >> 2], (o + i) & 3);
-          if ((uint32_t)g - i < 4) v &= (1u << (8 * ((uint32_t)g - i))) - 1u;
-          cnt += __popc(v);
-        }
-        rows = lv_sat(rows, 8 * g);
-        valid = lv_sat(valid, cnt);
-        q = x + (uint32_t)g;
-      } else {
-        if (x >= st.len) { state = 1; break; }
-        if (x >= sh) { state = 2; break; }
-        const uint32_t v = s_seg[d + (x - s0)];
-        if (v > 1) { state = 1; break; }
-        rows = lv_sat(rows, h >> 1);
-        if (v) valid = lv_sat(valid, h >> 1);
-        q = x + 1;
-      }
-    }
-    out = LvCand{q, state, rows, valid};
+    out = p1 != LV_NONE ? LvCand{s_exit[lead], s_state[lead], lv_sat(rows, s_rows[lead]), lv_sat(valid, s_valid[lead])}
+                        : LvCand{q, state, rows, valid};
   }
   cand[(size_t)sg * LV_CAND + c] = out;
 }
@@ -942,83 +1052,6 @@ __global__ void k_lv_link(const LvPage* lps, int npg, const PageDev* pages, cons
   if (!good)
     for (uint32_t j = 0; j < lp.nseg; ++j) ent[lp.seg0 + j].q = LV_NONE;
   ok[i] = good;
-}
-
-// mode 0: one wave per segment, from its entry; mode 1: one wave per page
-// that could not be linked, the whole chain.  The walk reads through an LDS
-// window (as k_index's) and stops at the first run whose header lies past the
-// segment, or at the run covering the page's last row.
-__global__ __launch_bounds__(64) void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const LvEntry* ent,
-                                                 const uint32_t* ok, PageDev* pages, const uint8_t* file,
-                                                 const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
-                                                 TileDev* tiles, uint32_t* err, int mode) {
-  __shared__ wr_u4 s_win[WIN / 16];
-  if (*(volatile uint32_t*)err != 0) return;
-  uint32_t li, q, hdr_end;
-  uint64_t before;
-  int64_t R;
-  if (mode == 0) {
-    const LvEntry e = ent[blockIdx.x];
-    if (e.q == LV_NONE) return;
-    li = seg_page[blockIdx.x];
-    q = e.q;
-    R = e.rows;
-    before = e.valid;
-    hdr_end = (blockIdx.x - lps[li].seg0 + 1) * LV_SEG;
-  } else {
-    li = blockIdx.x;
-    if (ok[li]) return;
-    q = 0;
-    R = 0;
-    before = 0;
-    hdr_end = 0xffffffffu;
-  }
-  const uint32_t p = lps[li].page;
-  const LvStream st = lv_stream(pages, p, file, scratch, file_lim, scratch_lim);
-  const uint32_t tile_begin = pages[p].tile_begin;
-  const bool lead = threadIdx.x == 0;
-  WR r;
-  r.init(st.base, st.lim, (lds_u4*)&s_win[0]);
-  const uint64_t end = st.off + st.len;
-  RunCur c;
-  c.next = st.off + q; c.start = R; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = c.next;
-  for (;;) {
-    if (c.next - st.off >= hdr_end) return;  // the next run belongs to a later segment
-    if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
-    const int64_t lo = c.start, n = (int64_t)min(c.n, 1ull << 40);
-    const int64_t hi = min(lo + n, st.nv);
-    // valid rows among the run's first k values; bit-packed runs count their
-    // payload bytes once, front to back (k does not decrease)
-    uint64_t acc_b = 0, acc_c = 0;
-    auto pop = [&](uint64_t k) -> uint64_t {
-      if (!c.bp) return (uint64_t)c.val * k;
-      const uint64_t kb = k >> 3;
-      if (kb > acc_b) {
-        acc_c += bp_popcount(r, c.pay + acc_b, (kb - acc_b) * 8);
-        acc_b = kb;
-      }
-      return acc_c + ((k & 7) ? (uint64_t)__popc(r.byte(c.pay + kb) & ((1u << (k & 7)) - 1u)) : 0u);
-    };
-    for (int64_t t = (lo + TILE_ROWS - 1) / TILE_ROWS; t * TILE_ROWS < hi; ++t) {
-      const uint64_t skip = (uint64_t)(t * TILE_ROWS - lo);
-      TileDev td;
-      td.page = p;
-      td.row0 = (uint32_t)(t * TILE_ROWS);
-      td.k0 = (uint32_t)(before + pop(skip));
-      td.nn = 0;
-      td.def_pos = (uint32_t)(c.hp - st.off);
-      td.def_skip = (uint32_t)skip;
-      td.val_pos = 0;
-      td.val_skip = 0;
-      if (lead) tiles[tile_begin + (uint32_t)t] = td;
-    }
-    if (lo + n >= st.nv) {
-      const uint32_t nonnull = (uint32_t)(before + pop((uint64_t)(st.nv - lo)));
-      if (lead) pages[p].nonnull = nonnull;
-      return;
-    }
-    before += pop((uint64_t)n);
-  }
 }
 
 // The next run of a 1-bit hybrid stream for one lane (run_next's rules);
@@ -1057,45 +1090,194 @@ __device__ __forceinline__ bool lv_run_next(const Byte& byte, uint64_t end, RunC
   return true;
 }
 
-// One wave per tile of the pages above: lane k computes level checkpoint k
-// (row row0 + 16k) by walking the runs from the tile's entry; the first KiB
-// from the entry is staged in LDS, later bytes are read from memory.
-__global__ __launch_bounds__(64) void k_lv_ckpt(const LvPage* lps, const uint32_t* tile_lp, const PageDev* pages,
-                                                const TileDev* tiles, const uint8_t* file, const uint8_t* scratch,
-                                                uint64_t file_lim, uint64_t scratch_lim, uint32_t* ckl,
-                                                const uint32_t* err) {
-  __shared__ __align__(16) uint8_t s_buf[1024];
-  if (*(const volatile uint32_t*)err != 0) return;
+// The whole level stream of one page by one wave (k_index's walk): tile
+// entries, level checkpoints every LROWS rows, the non-null count.
+__device__ void lv_page_walk(const LvStream& st, uint32_t p, uint32_t tile_begin, TileDev* tiles, uint32_t* ckl,
+                             PageDev* pages, uint32_t* err, lds_u4* win) {
+  WR r;
+  r.init(st.base, st.lim, win);
+  const bool lead = (threadIdx.x & 63) == 0;
+  const uint64_t def_off = st.off, end = st.off + st.len;
+  const int64_t nv = st.nv;
+  RunCur c;
+  c.next = def_off; c.start = 0; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = def_off;
+  uint64_t before = 0;  // valid rows in runs before the current one
+  bool have = false;
+  TileDev td;
+  for (int64_t target = 0; target < nv; target += LROWS) {
+    while (!have || c.start + (int64_t)c.n <= target) {
+      if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
+      if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
+      have = true;
+    }
+    const uint64_t skip = (uint64_t)(target - c.start);
+    const uint32_t t = (uint32_t)(target / TILE_ROWS), sub = (uint32_t)((target % TILE_ROWS) / LROWS);
+    if (sub == 0) {
+      td.page = p;
+      td.row0 = (uint32_t)target;
+      td.k0 = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, skip) : (uint64_t)c.val * skip));
+      td.nn = 0;
+      td.def_pos = (uint32_t)(c.hp - def_off);
+      td.def_skip = (uint32_t)skip;
+      td.val_pos = 0;
+      td.val_skip = 0;
+      if (lead) tiles[tile_begin + t] = td;
+    }
+    if (lead) ckl[(size_t)(tile_begin + t) * NLCK + sub] = make_lck(c, target, def_off + td.def_pos);
+  }
+  if (nv > 0 && lead)  // the last tile's checkpoints past the page's rows
+    for (int64_t target = ((nv + LROWS - 1) / LROWS) * LROWS; target % TILE_ROWS != 0; target += LROWS)
+      ckl[(size_t)(tile_begin + (uint32_t)(target / TILE_ROWS)) * NLCK + (target % TILE_ROWS) / LROWS] = LCK_NONE;
+  if (nv > 0) {
+    while (!have || c.start + (int64_t)c.n < nv) {
+      if (have) before += c.bp ? bp_popcount(r, c.pay, c.n) : (uint64_t)c.val * c.n;
+      if (!run_next(r, end, 1, c) || (!c.bp && c.val > 1)) { set_err(err, ERR_LEVELS, p); return; }
+      have = true;
+    }
+    const uint64_t part = (uint64_t)(nv - c.start);
+    const uint32_t nonnull = (uint32_t)(before + (c.bp ? bp_popcount(r, c.pay, part) : (uint64_t)c.val * part));
+    if (lead) pages[p].nonnull = nonnull;
+  }
+}
+
+// mode 0: one wave per linked segment; mode 1: one wave per page that could
+// not be linked (lv_page_walk).  In mode 0 the segment and LV_XTRA bytes
+// after it are staged in LDS; lanes read later bytes from memory.  Stream
+// positions are relative to the level stream's start.
+__global__ __launch_bounds__(64) void k_lv_tiles(const LvPage* lps, const uint32_t* seg_page, const LvEntry* ent,
+                                                 const uint32_t* ok, PageDev* pages, const uint8_t* file,
+                                                 const uint8_t* scratch, uint64_t file_lim, uint64_t scratch_lim,
+                                                 TileDev* tiles, uint32_t* ckl, uint32_t* err, int mode) {
+  __shared__ __align__(16) uint8_t s_seg[LV_LDS];
+  __shared__ uint32_t s_q[64], s_r[64], s_v[64];
+  if (*(volatile uint32_t*)err != 0) return;
+  if (mode == 1) {
+    if (ok[blockIdx.x]) return;
+    const uint32_t p = lps[blockIdx.x].page;
+    const LvStream st = lv_stream(pages, p, file, scratch, file_lim, scratch_lim);
+    lv_page_walk(st, p, pages[p].tile_begin, tiles, ckl, pages, err, (lds_u4*)&s_seg[0]);
+    return;
+  }
+  const LvEntry e = ent[blockIdx.x];
+  if (e.q == LV_NONE) return;
+  const LvPage lp = lps[seg_page[blockIdx.x]];
+  const uint32_t p = lp.page;
+  const LvStream st = lv_stream(pages, p, file, scratch, file_lim, scratch_lim);
+  const uint32_t tile_begin = pages[p].tile_begin;
+  const uint32_t s0 = (blockIdx.x - lp.seg0) * LV_SEG;
+  const uint32_t se = min(s0 + LV_SEG, st.len), sh = min(s0 + LV_SEG + LV_XTRA, st.len);
+  const uint32_t d = lv_stage(st, s0, sh, &s_seg[0], 64);
+  __syncthreads();
+  const uint8_t* gbase = st.base + st.off;
+  auto byte = [&](uint64_t x) -> uint32_t { return x < sh ? (uint32_t)s_seg[d + (uint32_t)x] : (uint32_t)gbase[x]; };
+  const __attribute__((address_space(3))) uint32_t* w32 = (const __attribute__((address_space(3))) uint32_t*)&s_seg[0];
+  // set bits among the k values of a bit-packed run from stream byte pay
+  auto popc = [&](uint64_t pay, uint64_t k) -> uint64_t {
+    uint64_t cnt = 0;
+    if (pay + (k + 7) / 8 <= sh) {
+      const uint32_t o = d + (uint32_t)pay;
+      for (uint32_t i = 0; 8ull * i < k; i += 4) {
+        uint32_t v = __builtin_amdgcn_alignbyte(w32[((o + i) >> 2) + 1], w32[(o + i) >> 2], (o + i) & 3);
+        const uint64_t left = k - 8ull * i;
+        if (left < 32) v &= (1u << left) - 1u;
+        cnt += __popc(v);
+      }
+    } else {
+      for (uint64_t i = 0; 8 * i < k; ++i) {
+        uint32_t v = byte(pay + i);
+        const uint64_t left = k - 8 * i;
+        if (left < 8) v &= (1u << left) - 1u;
+        cnt += __popc(v);
+      }
+    }
+    return cnt;
+  };
+  auto pop = [&](const RunCur& c, uint64_t k) -> uint64_t { return c.bp ? popc(c.pay, k) : (uint64_t)c.val * k; };
+  const int64_t nv = st.nv;
   const uint32_t lane = threadIdx.x;
-  const LvPage lp = lps[tile_lp[blockIdx.x]];
-  const LvStream st = lv_stream(pages, lp.page, file, scratch, file_lim, scratch_lim);
-  const uint32_t t = blockIdx.x - lp.tl0;
-  const uint32_t T = pages[lp.page].tile_begin + t;
-  const TileDev td = tiles[T];
-  const uint64_t entry = st.off + td.def_pos, end = st.off + st.len;
-  const uint64_t a0 = entry & ~15ull;
-  {
-    const uint64_t a = a0 + 16ull * lane;
-    wr_u4 v = {0u, 0u, 0u, 0u};
-    if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
-    *(lds_u4*)(&s_buf[16 * lane]) = v;
+  // lane 0: the first run header at or after each sub-segment's start, and
+  // the rows before it; LV_NONE after the run covering the last row
+  if (lane == 0) {
+    RunCur c;
+    c.next = e.q; c.start = (int64_t)e.rows; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = e.q;
+    s_q[0] = e.q;
+    s_r[0] = e.rows;
+    uint32_t k = 1;
+    bool done = false;
+    for (;;) {
+      const uint64_t h = done ? ~0ull : c.next;
+      const int64_t rows = c.start + (int64_t)min(c.n, 1ull << 40);
+      for (; k < 64 && h >= (uint64_t)s0 + (uint64_t)LV_SUB * k; ++k) {
+        s_q[k] = h < se ? (uint32_t)h : LV_NONE;
+        s_r[k] = (uint32_t)rows;
+      }
+      if (done || h >= se) break;
+      if (!lv_run_next(byte, st.len, c)) {
+        set_err(err, ERR_LEVELS, p);
+        done = true;
+        continue;
+      }
+      if (c.start + (int64_t)min(c.n, 1ull << 40) >= nv) done = true;
+    }
+    for (; k < 64; ++k) s_q[k] = LV_NONE;
   }
   __syncthreads();
-  const uint8_t* base = st.base;
-  auto byte = [&](uint64_t x) -> uint32_t { return x - a0 < 1024 ? (uint32_t)s_buf[x - a0] : (uint32_t)base[x]; };
-  const int64_t target = (int64_t)t * TILE_ROWS + (int64_t)LROWS * lane;
-  uint32_t lck = LCK_NONE;
-  if (target < st.nv && entry < end) {
+  const uint64_t q0 = s_q[lane];
+  const uint64_t qe = lane == 63 ? se : min((uint64_t)s0 + (uint64_t)LV_SUB * (lane + 1), (uint64_t)se);
+  // valid rows of this lane's runs (up to the last row)
+  uint64_t valid = 0;
+  if (q0 != LV_NONE) {
     RunCur c;
-    c.next = entry; c.start = (int64_t)td.row0 - (int64_t)td.def_skip; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0;
-    c.hp = entry;
-    bool good = true;
-    do {
-      if (!lv_run_next(byte, end, c)) { good = false; break; }
-    } while (c.start + (int64_t)min(c.n, 1ull << 40) <= target);
-    if (good) lck = make_lck(c, target, entry);
+    c.next = q0; c.start = (int64_t)s_r[lane]; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = q0;
+    while (c.next < qe && lv_run_next(byte, st.len, c)) {
+      const int64_t n = (int64_t)min(c.n, 1ull << 40);
+      if (c.start + n >= nv) { valid += pop(c, (uint64_t)(nv - c.start)); break; }
+      valid += pop(c, (uint64_t)n);
+    }
   }
-  ckl[(size_t)T * NLCK + lane] = lck;
+  s_v[lane] = (uint32_t)valid;
+  __syncthreads();
+  uint64_t before = e.valid;
+  for (uint32_t k = 0; k < lane; ++k) before += s_v[k];
+  if (q0 == LV_NONE) return;
+  // this lane's runs once more: tile entries with their checkpoints
+  RunCur c;
+  c.next = q0; c.start = (int64_t)s_r[lane]; c.n = 0; c.bp = 0; c.val = 0; c.pay = 0; c.hp = q0;
+  while (c.next < qe && lv_run_next(byte, st.len, c)) {
+    const int64_t lo = c.start, n = (int64_t)min(c.n, 1ull << 40), hi = min(lo + n, nv);
+    for (int64_t t = (lo + TILE_ROWS - 1) / TILE_ROWS; t * TILE_ROWS < hi; ++t) {
+      const uint64_t skip = (uint64_t)(t * TILE_ROWS - lo);
+      TileDev td;
+      td.page = p;
+      td.row0 = (uint32_t)(t * TILE_ROWS);
+      td.k0 = (uint32_t)(before + pop(c, skip));
+      td.nn = 0;
+      td.def_pos = (uint32_t)c.hp;
+      td.def_skip = (uint32_t)skip;
+      td.val_pos = 0;
+      td.val_skip = 0;
+      tiles[tile_begin + (uint32_t)t] = td;
+      // the tile's level checkpoints, walking on from this run
+      RunCur c2 = c;
+      bool good = true;
+      uint32_t* out = ckl + (size_t)(tile_begin + (uint32_t)t) * NLCK;
+      for (int k = 0; k < NLCK; ++k) {
+        const int64_t target = t * TILE_ROWS + (int64_t)k * LROWS;
+        uint32_t lck = LCK_NONE;
+        if (target < nv && good) {
+          while (c2.start + (int64_t)min(c2.n, 1ull << 40) <= target)
+            if (!lv_run_next(byte, st.len, c2)) { good = false; break; }
+          if (good) lck = make_lck(c2, target, c.hp);
+        }
+        out[k] = lck;
+      }
+    }
+    if (lo + n >= nv) {
+      pages[p].nonnull = (uint32_t)(before + pop(c, (uint64_t)(nv - lo)));
+      return;
+    }
+    before += pop(c, (uint64_t)n);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1344,10 +1526,18 @@ __device__ __forceinline__ DiStream di_stream(const PageDev* pages, uint32_t p, 
 // One workgroup of DI_WG lanes per segment, each lane walking every
 // DI_WG-th candidate; the segment's run headers are staged in LDS.
 // Segment sg's candidates are cand[sg DI_CAND_MAX ..], di_cand(w) of them.
+// Chains that reach the same run header past the candidates' start bytes go
+// on alike, so each such header is walked on from once (by the first
+// candidate that reached it, found through an LDS table over the DI_DEDUP
+// bytes that follow the start bytes).
+constexpr uint32_t DI_PER = DI_CAND_MAX / DI_WG;
+constexpr uint32_t DI_DEDUP = 2048;
+
 __global__ __launch_bounds__(DI_WG) void k_di_cand(const DiPage* dps, const uint32_t* seg_page, const PageDev* pages,
                                                    const uint8_t* file, const uint8_t* scratch, uint64_t file_lim,
                                                    uint64_t scratch_lim, DiCand* cand, const uint32_t* err) {
   __shared__ __align__(16) uint8_t s_seg[DI_LDS];
+  __shared__ uint32_t s_first[DI_DEDUP], s_exit[DI_CAND_MAX], s_cnt[DI_CAND_MAX];
   if (*(const volatile uint32_t*)err != 0) return;
   const uint32_t sg = blockIdx.x;
   const DiPage dp = dps[seg_page[sg]];
@@ -1369,38 +1559,89 @@ __global__ __launch_bounds__(DI_WG) void k_di_cand(const DiPage* dps, const uint
     if (a + 16 <= st.lim) v = *reinterpret_cast<const wr_u4*>(st.base + a);
     *(lds_u4*)(&s_seg[16 * k]) = v;
   }
+  for (uint32_t k = threadIdx.x; k < DI_DEDUP; k += DI_WG) s_first[k] = 0xffffffffu;
   __syncthreads();
   const uint32_t d = (uint32_t)(g0 - a0) - (uint32_t)s0;  // LDS offset of stream byte x: d + x
   const uint32_t vb = (st.w + 7) / 8;
-  for (uint32_t c = threadIdx.x; c < ncand; c += DI_WG) {
-    uint32_t q = (uint32_t)s0 + c, count = 0;
-    while (q < se) {
+  // walks the runs whose header lies before lim from q, counting values;
+  // false at an invalid run
+  const __attribute__((address_space(3))) uint32_t* w32 = (const __attribute__((address_space(3))) uint32_t*)&s_seg[0];
+  auto walk = [&](uint32_t& q, uint32_t lim, uint32_t& count) -> bool {
+    while (q < lim) {
       uint64_t h = 0;
-      uint32_t x = q;
-      bool whole = false;
-      for (uint32_t b7 = 0; b7 < 70; b7 += 7) {  // a header is 10 bytes at most
-        if (x >= st.len) break;
-        const uint32_t b = s_seg[d + x];
-        ++x;
-        if (b7 == 63 && (b & 0x7e)) break;
-        h |= (uint64_t)(b & 0x7f) << b7;
-        if (!(b & 0x80)) { whole = true; break; }
+      uint32_t x = q, hl = 0;
+      if (q + 8 <= sh) {  // the common short header, from one dword
+        const uint32_t o = d + q;
+        uint32_t h32 = 0;
+        hl = uleb4(__builtin_amdgcn_alignbyte(w32[(o >> 2) + 1], w32[o >> 2], o & 3), h32);
+        h = h32;
+        x = q + hl;
+      }
+      if (hl == 0) {
+        bool whole = false;
+        for (uint32_t b7 = 0; b7 < 70; b7 += 7) {  // a header is 10 bytes at most
+          if (x >= st.len) break;
+          const uint32_t b = s_seg[d + x];
+          ++x;
+          if (b7 == 63 && (b & 0x7e)) break;
+          h |= (uint64_t)(b & 0x7f) << b7;
+          if (!(b & 0x80)) { whole = true; break; }
+        }
+        if (!whole) return false;
       }
       uint64_t n, nb;
-      if (!whole) { q = DI_BAD; break; }
       if (h & 1) {
         n = (h >> 1) * 8;
         nb = (h >> 1) * st.w;
-        if ((h >> 1) > (1ull << 28) || nb > st.len - x) { q = DI_BAD; break; }
+        if ((h >> 1) > (1ull << 28) || nb > st.len - x) return false;
       } else {
         n = h >> 1;
         nb = vb;
-        if (nb > st.len - x) { q = DI_BAD; break; }
+        if (nb > st.len - x) return false;
       }
       count = lv_sat(count, n);
       q = x + (uint32_t)nb;
     }
-    out[c] = DiCand{q, count};
+    return true;
+  };
+  const uint32_t wend = (uint32_t)min(s0 + ncand, (uint64_t)se);  // end of the start bytes
+  uint32_t qa[DI_PER], ca[DI_PER];
+  bool oka[DI_PER];
+#pragma unroll
+  for (uint32_t u = 0; u < DI_PER; ++u) {
+    const uint32_t c = threadIdx.x + u * DI_WG;
+    qa[u] = (uint32_t)s0 + c;
+    ca[u] = 0;
+    oka[u] = false;
+    if (c < ncand) {
+      oka[u] = walk(qa[u], wend, ca[u]);
+      if (oka[u] && qa[u] < se && qa[u] - wend < DI_DEDUP) atomicMin(&s_first[qa[u] - wend], c);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t u = 0; u < DI_PER; ++u) {
+    const uint32_t c = threadIdx.x + u * DI_WG;
+    if (c < ncand && oka[u] && qa[u] < se) {
+      const uint32_t lead = qa[u] - wend < DI_DEDUP ? s_first[qa[u] - wend] : c;
+      if (lead == c) {
+        uint32_t q2 = qa[u], c2 = 0;
+        s_exit[c] = walk(q2, se, c2) ? q2 : DI_BAD;
+        s_cnt[c] = c2;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t u = 0; u < DI_PER; ++u) {
+    const uint32_t c = threadIdx.x + u * DI_WG;
+    if (c >= ncand) continue;
+    DiCand r = DiCand{oka[u] ? qa[u] : DI_BAD, ca[u]};
+    if (oka[u] && qa[u] < se) {
+      const uint32_t lead = qa[u] - wend < DI_DEDUP ? s_first[qa[u] - wend] : c;
+      r = DiCand{s_exit[lead], lv_sat(ca[u], s_cnt[lead])};
+    }
+    out[c] = r;
   }
 }
 
