@@ -62,7 +62,8 @@ __global__ void k_schain_fill(const SChainPage* pgs, const uint32_t* seg_page, c
 __global__ void k_schain_seq(const SChainPage* pgs, int npg, const uint32_t* ok, uint32_t* strck, PageDev* pages,
                              uint32_t* err);
 __global__ void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record, uint32_t* err);
-__global__ void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err);
+__global__ void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err, int dicts);
+__global__ void k_snap_index(const ColScan* cols, SegTable seg);
 __global__ void k_prep(const ColScan* cols, SegTable seg);
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, SegTable seg);
 __global__ void k_dict(const PageDev* pages, const uint32_t* strck, const DictSlot* slots, const DictWork* works,
@@ -715,10 +716,18 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     cs.fd.sblk = f->d_sblk;
     cs.fd.sblk_page = f->d_sblk_page;
     (void)hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s);
+    // block index from a walk over the element tags, then the indexed blocks
+    // side by side (dictionary pages included) and the other pages one wave
+    // each
     std::vector<Segment> segs{Segment{0, 0, npages, 0}};
     SegTable st2 = make_segs(segs);
-    const uint32_t waves = npages;
-    hipLaunchKernelGGL(k_snappy, dim3(waves), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
+    hipLaunchKernelGGL(k_snap_index, dim3(npages), dim3(64), 0, s, d_cs, st2);
+    if (sblk) {
+      std::vector<Segment> bsegs{Segment{0, 0, (uint32_t)sblk, 0}};
+      hipLaunchKernelGGL(k_snappy_blk, dim3((uint32_t)((sblk + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES))), dim3(256), 0, s,
+                         d_cs, make_segs(bsegs), d_scratch, f->d_err, 1);
+    }
+    hipLaunchKernelGGL(k_snappy, dim3(npages), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
   }
   // ---- DELTA_BYTE_ARRAY pages: facts, expansion layout, expansion ----
@@ -1497,7 +1506,7 @@ static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_c
   if (P.sblk_lanes) {
     ProfScope ps_(f, KP_SNAPPY_BLK, s);
     hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                       d_cols, make_segs(P.sblk_segs), ws, err);
+                       d_cols, make_segs(P.sblk_segs), ws, err, 0);
     HIP_OR(hipGetLastError());
   }
   if (P.dba_waves) {  // DELTA_BYTE_ARRAY pages (after their decompression) to the PLAIN layout
@@ -1612,34 +1621,39 @@ constexpr uint64_t INDEX_WS_CAP = 1ull << 30;
 // `need` selects, in row-group batches; fills val[t] for their tiles.
 static pq_status prefix_pass(pq_file f, int mode, const std::vector<bool>& need, std::vector<uint64_t>& val,
                              hipStream_t s) {
-  for (int c = 0; c < f->ncols; ++c) {
-    if (!need[(size_t)c]) continue;
-    for (int g0 = 0; g0 < f->nrg;) {
-      int n = f->nrg - g0;
-      Plan P;
-      for (;;) {
-        P = Plan();
-        pq_status st = make_plan(f, 1ull << c, g0, g0 + n, P, true);
-        if (st != PQ_OK) return st;
-        if (P.ws_total <= INDEX_WS_CAP || n == 1) break;
-        n = (n + 1) / 2;
-      }
-      const ColScan& cs = P.cols[0];
-      const uint32_t cnt = cs.tile_end - cs.tile_begin;
-      if (cnt) {
-        uint8_t* ws = nullptr;
-        if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
-        pq_status st = enqueue_index(f, P, ws, mode, s);
-        if (st == PQ_OK && hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt,
-                                          hipMemcpyDeviceToHost, s) != hipSuccess)
-          st = fail(PQ_EHIP, "open: prefix pass copy");
-        if (st == PQ_OK) st = read_err(f, s);
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(ws);
-        if (st != PQ_OK) return st;
-      }
-      g0 += n;
+  // every needed column at once (one decompression and one prepass launch
+  // per batch of row groups), the batches sized to INDEX_WS_CAP
+  uint64_t mask = 0;
+  for (int c = 0; c < f->ncols; ++c)
+    if (need[(size_t)c]) mask |= 1ull << c;
+  if (!mask) return PQ_OK;
+  for (int g0 = 0; g0 < f->nrg;) {
+    int n = f->nrg - g0;
+    Plan P;
+    for (;;) {
+      P = Plan();
+      pq_status st = make_plan(f, mask, g0, g0 + n, P, true);
+      if (st != PQ_OK) return st;
+      if (P.ws_total <= INDEX_WS_CAP || n == 1) break;
+      n = (n + 1) / 2;
     }
+    if (P.pre_units) {
+      uint8_t* ws = nullptr;
+      if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
+      pq_status st = enqueue_index(f, P, ws, mode, s);
+      for (const ColScan& cs : P.cols) {
+        const uint32_t cnt = cs.tile_end - cs.tile_begin;
+        if (st == PQ_OK && cs.ws_tile_aux && cnt &&
+            hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt, hipMemcpyDeviceToHost, s) !=
+                hipSuccess)
+          st = fail(PQ_EHIP, "open: prefix pass copy");
+      }
+      if (st == PQ_OK) st = read_err(f, s);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(ws);
+      if (st != PQ_OK) return st;
+    }
+    g0 += n;
   }
   return PQ_OK;
 }
@@ -2169,7 +2183,7 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
     if (P.sblk_lanes) {
       ProfScope ps_(prof, KP_SNAPPY_BLK, s);
       hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                         d_cols, seg_table(P.sblk_segs, ws, P.ws_sblk), ws, err);
+                         d_cols, seg_table(P.sblk_segs, ws, P.ws_sblk), ws, err, 0);
       HIP_OR(hipGetLastError());
     }
   } else {
@@ -2186,7 +2200,7 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
         ProfScope ps_(prof, KP_SNAPPY_BLK, s);
         std::vector<Segment> one{Segment{sp.cs, sp.b0, sp.b1, 0}};
         hipLaunchKernelGGL(k_snappy_blk, dim3((sp.b1 - sp.b0 + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                           d_cols, make_segs(one), ws, err);
+                           d_cols, make_segs(one), ws, err, 0);
         HIP_OR(hipGetLastError());
       }
     }

@@ -1140,7 +1140,9 @@ __device__ __forceinline__ void snap_flush(const lds_u8* ring, uint8_t* g0, uint
   }
 }
 
-__global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record,
+// mode 0 (scans): the data pages without a block index; mode 1 (open): the
+// pages without a block index, dictionary pages included.
+__global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int mode,
                                                uint32_t* err) {
   __shared__ __align__(16) uint8_t s_ring[SNAP_RING];
   __shared__ __align__(16) uint32_t s_in[SNAP_IN / 4 + 4];
@@ -1154,8 +1156,9 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
   const PageDev pg = cs.fd.pages[p];
   uint32_t* sblk = cs.fd.sblk;
   if (pg.scratch_len == 0) return;
-  // dictionaries are decompressed once, at open
-  if (!record && (pg.kind == PAGE_DICT || sblk[pg.sblk_begin] != SBLK_NONE)) return;  // or k_snappy_blk decodes it
+  // dictionaries are decompressed once, at open; pages with a block index
+  // by k_snappy_blk
+  if ((mode == 0 && pg.kind == PAGE_DICT) || sblk[pg.sblk_begin] != SBLK_NONE) return;
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
   const uint8_t* src = cs.fd.file + src_off;
@@ -1188,14 +1191,11 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
     }
     if (!bad && v != total) bad = true;
   }
-  bool blk_ok = true;  // every block boundary starts an element and no copy leaves its block
-  if (record && lane == 0) sblk[pg.sblk_begin] = ip - m;
   while (!bad && ip < iend) {
     const uint32_t o = in.at(ip);
     const uint64_t x = in.bytes8(o);
     const uint32_t t = (uint32_t)x & 0xffu;
     const uint32_t R = s0 + op;  // ring-space position of the element's first byte
-    if (record && op && (op & (SNAP_BLOCK - 1)) == 0 && lane == 0) sblk[pg.sblk_begin + op / SNAP_BLOCK] = ip - m;
     if ((t & 3) == 0) {  // literal
       uint32_t l = t >> 2, hl = 1;
       if (l >= 60) {
@@ -1278,7 +1278,6 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
           }
         }
       }
-      if (op / SNAP_BLOCK != (op + L - 1) / SNAP_BLOCK) blk_ok = false;
       ip += L;
       op += L;
     } else {  // copy
@@ -1313,7 +1312,6 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
         b = reinterpret_cast<volatile const uint8_t*>(g0)[sidx];
       }
       if (lane < len) ring[(R + lane) & SNAP_MASK] = (uint8_t)b;
-      if (op / SNAP_BLOCK != (op + len - 1) / SNAP_BLOCK || off > op % SNAP_BLOCK) blk_ok = false;
       op += len;
     }
     const uint32_t full = (s0 + op) >> 4;
@@ -1328,8 +1326,97 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
     wave_sync();
     snap_flush(ring, g0, fc, (s0 + op + 15) >> 4, s0, s0 + op);
   }
-  if (record && (bad || !blk_ok) && lane == 0) sblk[pg.sblk_begin] = SBLK_NONE;
   if (bad && lane == 0) set_err(err, ERR_SNAPPY, p);
+}
+
+// k_snap_index (open): the Snappy block index of every compressed page, from
+// a walk over its element tags alone, one wave per page with the stream
+// staged in LDS (literal bytes are skipped, not read).  Entry b of a page is
+// the stream offset of the element that starts output block b; the page's
+// first entry is SBLK_NONE when an element straddles a block boundary, a
+// copy reaches before the start of its block, or the stream is malformed:
+// such a page is decompressed sequentially by k_snappy, which reports what
+// is wrong.  (One lane per page, with a private LDS window each, was three
+// times slower.)
+__global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable seg) {
+  __shared__ __align__(16) uint32_t s_in[SNAP_IN / 4 + 4];
+  const uint32_t gw = blockIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const Segment sg = seg_lookup(seg, gw);
+  const uint32_t p = sg.t0 + (gw - sg.wg0);
+  if (p >= sg.t1) return;
+  const ColScan cs = cols[sg.cs];
+  const PageDev pg = cs.fd.pages[p];
+  uint32_t* sblk = cs.fd.sblk;
+  if (pg.scratch_len == 0) return;
+  uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
+  if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
+  const uint8_t* src = cs.fd.file + src_off;
+  const uint32_t total = pg.scratch_len;
+  const uint32_t m = (uint32_t)((uintptr_t)src & 3);
+  SnapIn in;
+  in.base = (glb_u32*)(src - m);
+  const uint32_t iend = m + (uint32_t)min(src_len64, (uint64_t)0x7fffffffu);
+  in.lim = iend;
+  in.buf = (lds_u32*)&s_in[0];
+  uint32_t ip = m;
+  in.fill(ip);
+  bool ok = src_len64 < 0x7fffffffull;
+  {  // stream length (varint)
+    uint64_t v = 0;
+    int sft = 0;
+    for (;;) {
+      if (!ok || ip >= iend || sft > 28) { ok = false; break; }
+      const uint32_t b = (uint32_t)in.bytes8(in.at(ip++)) & 0xffu;
+      v |= (uint64_t)(b & 0x7f) << sft;
+      if (!(b & 0x80)) break;
+      sft += 7;
+    }
+    if (ok && v != total) ok = false;
+  }
+  const uint32_t first = ip - m;
+  uint32_t op = 0;
+  while (ok && ip < iend) {
+    const uint64_t x = in.bytes8(in.at(ip));
+    const uint32_t t = (uint32_t)x & 0xffu;
+    if (op && (op & (SNAP_BLOCK - 1)) == 0 && lane == 0) sblk[pg.sblk_begin + op / SNAP_BLOCK] = ip - m;
+    uint32_t len, hl;
+    if ((t & 3) == 0) {  // literal
+      uint32_t l = t >> 2;
+      hl = 1;
+      if (l >= 60) {
+        const uint32_t nb = l - 59;
+        l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
+        hl += nb;
+      }
+      const uint64_t L64 = (uint64_t)l + 1;
+      if ((uint64_t)ip + hl + L64 > iend || L64 > total - op) { ok = false; break; }
+      len = (uint32_t)L64;
+      ip += hl + len;
+    } else {  // copy
+      uint32_t off;
+      if ((t & 3) == 1) {
+        hl = 2;
+        len = 4 + ((t >> 2) & 7);
+        off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
+      } else if ((t & 3) == 2) {
+        hl = 3;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8) & 0xffffu;
+      } else {
+        hl = 5;
+        len = (t >> 2) + 1;
+        off = (uint32_t)(x >> 8);
+      }
+      if (ip + hl > iend || off == 0 || off > op || len > total - op) { ok = false; break; }
+      if (off > op % SNAP_BLOCK) { ok = false; break; }  // reaches before its block
+      ip += hl;
+    }
+    if (op / SNAP_BLOCK != (op + len - 1) / SNAP_BLOCK) { ok = false; break; }  // straddles a boundary
+    op += len;
+  }
+  if (op != total) ok = false;
+  if (lane == 0) sblk[pg.sblk_begin] = ok ? first : SBLK_NONE;
 }
 
 // One lane copies n <= 64 bytes src -> dst (no overlap) with one round of
@@ -1435,7 +1522,7 @@ struct SnapLane {
   bool bad;
 };
 __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& seg, uint8_t* ws, uint32_t gid,
-                                          SnapLane& sl) {
+                                          SnapLane& sl, bool dicts) {
   const Segment sg = seg_lookup(seg, gid);
   const uint32_t b = sg.t0 + (gid - sg.wg0);
   if (b >= sg.t1) return false;
@@ -1443,7 +1530,7 @@ __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& s
   const uint32_t* sblk = cs.fd.sblk;
   const uint32_t p = cs.fd.sblk_page[b];
   const PageDev pg = cs.fd.pages[p];
-  if (pg.scratch_len == 0 || pg.kind == PAGE_DICT) return false;  // dictionaries: decompressed at open
+  if (pg.scratch_len == 0 || (pg.kind == PAGE_DICT && !dicts)) return false;  // dictionaries: decompressed at open
   const uint32_t first = pg.sblk_begin;
   if (sblk[first] == SBLK_NONE) return false;  // decoded sequentially by k_snappy
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
@@ -1462,13 +1549,15 @@ __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& s
   return true;
 }
 
-__global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err) {
+// dicts = 1 (open): dictionary pages too.
+__global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err,
+                                                   int dicts) {
   const uint32_t lw = threadIdx.x & 63;
   const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
   // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
   // copy long literals
   SnapLane sl = {nullptr, nullptr, 0u, 0u, 0u, 0u, 0u, 0u, false};
-  const bool live = lw < SNAP_LANES && snap_lane(cols, seg, ws, gid, sl);
+  const bool live = lw < SNAP_LANES && snap_lane(cols, seg, ws, gid, sl, dicts != 0);
   const uint8_t* src = sl.src;
   uint8_t* dst = sl.dst;
   uint32_t ip = sl.ip, op = sl.ob;
