@@ -442,6 +442,13 @@ static SegTable make_segs(const std::vector<Segment>& v, bool spread = false) {
 static pq_status build_tile_prefix(pq_file f, hipStream_t s);
 static pq_status build_dicts(pq_file f, const uint8_t* scratch, bool copy_all, hipStream_t s);
 
+// Decompressed bytes of the data pages indexed together at open.
+constexpr uint64_t OPEN_SCRATCH_CAP = 512ull << 20;
+// Bytes allocated before an open-time window: the index walks' stream
+// readers fill their LDS windows from up to 256 bytes before the position
+// they move to, which for a pass's first page lies before the window.
+constexpr uint64_t OPEN_GUARD = 4096;
+
 // The open of a file in device memory; with host_copy the buffer is a
 // temporary device copy of a host-resident file, so every dictionary is
 // copied into the handle's arena (none may point into the buffer).
@@ -618,7 +625,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     f->chunk_tile0[q] = (uint32_t)tiles;
     for (uint32_t p = f->chunk_page0[q]; p < f->chunk_page0[q + 1]; ++p) {
       PageDev& pg = f->pages[p];
-      pg.scratch_off = scratch;
+      pg.scratch_off = scratch;  // (dictionary pages: placed after the data pages below)
       f->scratch_prefix[p] = scratch;
       uint64_t slen = 0;
       if (cd.codec == 1) {
@@ -635,7 +642,8 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
         for (uint64_t j = 0; j < nb; ++j) sblk_page.push_back(p);
         sblk += nb;
       }
-      if (cd.codec == 1 && (pg.kind != PAGE_DATA_V2 || pg.v2_compressed)) scratch += align_up(slen + SCRATCH_PAD, 16);
+      if (cd.codec == 1 && (pg.kind != PAGE_DATA_V2 || pg.v2_compressed) && pg.kind != PAGE_DICT)
+        scratch += align_up(slen + SCRATCH_PAD, 16);
       if (pg.kind == PAGE_DICT) {
         dict = p;
         pg.row0 = row;
@@ -658,44 +666,77 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   }
   f->chunk_tile0[nchunks] = (uint32_t)tiles;
   f->scratch_prefix[npages] = scratch;
+  // the scratch layout: data pages in page order (a scan decompresses a
+  // column's data pages into one range), then the dictionary pages, which
+  // are decompressed at open only
+  uint64_t dict_scratch = 0;
+  for (uint32_t p = 0; p < npages; ++p) {
+    PageDev& pg = f->pages[p];
+    if (pg.kind != PAGE_DICT) continue;
+    pg.scratch_off = scratch + dict_scratch;
+    if (f->chunks[pg.chunk].codec == 1) dict_scratch += align_up((uint64_t)pg.scratch_len + SCRATCH_PAD, 16);
+  }
   f->xscratch_prefix.assign(npages + 1, 0);
   if (tiles > 0xffffffffull) { free_handle(f); return fail(PQ_EUNSUPPORTED, "too many tiles"); }
   f->total_tiles = tiles;
   f->total_strck = strck;
 
-  // ---- compressed pages decompressed once for the index pass ----
+  // ---- the index passes ----
+  // Compressed pages are decompressed for the index in passes, each into one
+  // window: first every dictionary page (their region follows the data
+  // pages' in the scratch layout), then the data pages in runs of
+  // consecutive pages whose decompressed bytes fit OPEN_SCRATCH_CAP (a larger
+  // page is a run of its own).  The kernels of a pass address the window
+  // through the file-wide scratch offsets, shifted by the pass's first one.
+  struct OpenPass { bool dict; uint32_t p0, p1; uint64_t s0, s1; };
+  std::vector<OpenPass> passes;
+  passes.push_back(OpenPass{true, 0, npages, scratch, scratch + dict_scratch});
+  for (uint32_t p = 0; p < npages;) {
+    uint32_t p1 = p + 1;
+    const uint64_t a = f->scratch_prefix[p];
+    while (p1 < npages && f->scratch_prefix[p1 + 1] - a <= OPEN_SCRATCH_CAP) ++p1;
+    passes.push_back(OpenPass{false, p, p1, a, f->scratch_prefix[p1]});
+    p = p1;
+  }
+  uint64_t window = 0;
+  for (const OpenPass& P : passes) window = std::max(window, P.s1 - P.s0);
+  uint8_t* d_scratch_mem = nullptr;  // the window, after OPEN_GUARD bytes
   uint8_t* d_scratch = nullptr;
   ColScan* d_cs = nullptr;
   uint32_t* d_order = nullptr;
   uint8_t* d_schain = nullptr;  // long string dictionaries: segment tables of the chain walk
-  uint8_t* d_lv = nullptr;      // long level streams: segment and tile tables of their walk
+  uint8_t* d_lv = nullptr;      // long level streams: segment tables of their walk
   uint8_t* d_dl = nullptr;      // long DELTA streams: segment, block and tile tables of their walk
   uint8_t* d_di = nullptr;      // long dictionary-index streams: segment and tile tables of their walk
-  uint8_t* d_xscratch = nullptr;  // DELTA_BYTE_ARRAY pages expanded to the PLAIN layout
+  uint8_t* d_xscratch_mem = nullptr;  // DELTA_BYTE_ARRAY pages of a pass expanded to the PLAIN layout,
+  uint8_t* d_xscratch = nullptr;      // after OPEN_GUARD bytes
   ColScan* d_xcols = nullptr;     // their column tables
-  uint64_t xscratch = 0;          // bytes of the expansion layout
-  auto cleanup_open = [&]() {
-    if (d_scratch) (void)hipFree(d_scratch);
-    if (d_cs) (void)hipFree(d_cs);
+  uint64_t xscratch = 0;          // bytes of the file-wide expansion layout so far
+  auto free_pass = [&]() {
     if (d_order) (void)hipFree(d_order);
     if (d_schain) (void)hipFree(d_schain);
     if (d_lv) (void)hipFree(d_lv);
     if (d_dl) (void)hipFree(d_dl);
     if (d_di) (void)hipFree(d_di);
-    if (d_xscratch) (void)hipFree(d_xscratch);
+    if (d_xscratch_mem) (void)hipFree(d_xscratch_mem);
     if (d_xcols) (void)hipFree(d_xcols);
-    d_scratch = nullptr;
-    d_cs = nullptr;
     d_order = nullptr;
     d_schain = nullptr;
     d_lv = nullptr;
     d_dl = nullptr;
     d_di = nullptr;
-    d_xscratch = nullptr;
+    d_xscratch_mem = d_xscratch = nullptr;
     d_xcols = nullptr;
   };
+  auto cleanup_open = [&]() {
+    free_pass();
+    if (d_scratch_mem) (void)hipFree(d_scratch_mem);
+    if (d_cs) (void)hipFree(d_cs);
+    d_scratch_mem = d_scratch = nullptr;
+    d_cs = nullptr;
+  };
   if (npages) OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
-  // Snappy block index, recorded by the decompression below
+  // Snappy block index, built by the decompression below
   f->total_sblk = sblk;
   if (sblk) {
     if (hipMalloc(&f->d_sblk, sizeof(uint32_t) * sblk) != hipSuccess ||
@@ -706,85 +747,11 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       cleanup_open(); free_handle(f); return fail(PQ_EHIP, "open: block index upload");
     }
   }
-  if (scratch > 0) {
-    if (hipMalloc(&d_scratch, scratch) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for decompression"); }
-    if (hipMalloc(&d_cs, sizeof(ColScan)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
-    ColScan cs;
-    memset(&cs, 0, sizeof(cs));
-    cs.fd.file = file;
-    cs.fd.pages = f->d_pages;
-    cs.fd.sblk = f->d_sblk;
-    cs.fd.sblk_page = f->d_sblk_page;
-    (void)hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s);
-    // block index from a walk over the element tags, then the indexed blocks
-    // side by side (dictionary pages included) and the other pages one wave
-    // each
-    std::vector<Segment> segs{Segment{0, 0, npages, 0}};
-    SegTable st2 = make_segs(segs);
-    hipLaunchKernelGGL(k_snap_index, dim3(npages), dim3(64), 0, s, d_cs, st2);
-    if (sblk) {
-      std::vector<Segment> bsegs{Segment{0, 0, (uint32_t)sblk, 0}};
-      hipLaunchKernelGGL(k_snappy_blk, dim3((uint32_t)((sblk + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES))), dim3(256), 0, s,
-                         d_cs, make_segs(bsegs), d_scratch, f->d_err, 1);
-    }
-    hipLaunchKernelGGL(k_snappy, dim3(npages), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
-    if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
+  if (window > 0) {
+    if (hipMalloc(&d_scratch_mem, OPEN_GUARD + window) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for decompression"); }
+    d_scratch = d_scratch_mem + OPEN_GUARD;
   }
-  // ---- DELTA_BYTE_ARRAY pages: facts, expansion layout, expansion ----
-  {
-    std::vector<ColScan> xc;
-    std::vector<Segment> xs;
-    uint32_t xw = 0;
-    for (int c = 0; c < f->ncols; ++c) {
-      if (f->cols[c].type != T_BYTE_ARRAY) continue;
-      const uint32_t p0 = f->chunk_page0[(size_t)c * f->nrg], p1 = f->chunk_page0[(size_t)(c + 1) * f->nrg];
-      bool any = false;
-      for (uint32_t pp = p0; pp < p1 && !any; ++pp) any = f->pages[pp].kind != PAGE_DICT && f->pages[pp].encoding == E_DBA;
-      if (!any) continue;
-      ColScan cs;
-      memset(&cs, 0, sizeof(cs));
-      cs.fd.file = file;
-      cs.fd.pages = f->d_pages;
-      cs.type = T_BYTE_ARRAY;
-      cs.optional = f->cols[c].optional;
-      cs.col = c;
-      cs.page_begin = p0;
-      cs.page_end = p1;
-      xs.push_back(Segment{(uint32_t)xc.size(), p0, p1, xw});
-      xw += p1 - p0;
-      xc.push_back(cs);
-    }
-    if (!xc.empty()) {
-      if (xs.size() > MAX_SEGS) { cleanup_open(); free_handle(f); return fail(PQ_EUNSUPPORTED, "too many DELTA_BYTE_ARRAY columns"); }
-      if (hipMalloc(&d_xcols, sizeof(ColScan) * xc.size()) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
-      OPEN_HIP(hipMemcpyAsync(d_xcols, xc.data(), sizeof(ColScan) * xc.size(), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, d_scratch,
-                         (uint8_t*)nullptr, f->d_pages, 0, f->d_err);
-      if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
-      {
-        pq_status stx = read_err(f, s);
-        if (stx != PQ_OK) { cleanup_open(); free_handle(f); return stx; }
-      }
-      OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
-      for (uint32_t pp = 0; pp < npages; ++pp) {
-        PageDev& pg = f->pages[pp];
-        f->xscratch_prefix[pp] = xscratch;
-        if (pg.kind == PAGE_DICT || pg.encoding != E_DBA || f->chunks[pg.chunk].type != T_BYTE_ARRAY ||
-            pg.x_total == DBA_UNSUPPORTED)
-          continue;
-        pg.x_off = xscratch;
-        xscratch += align_up((uint64_t)pg.xlen + SCRATCH_PAD, 16);
-      }
-      f->xscratch_prefix[npages] = xscratch;
-      OPEN_HIP(hipMemcpyAsync(f->d_pages, f->pages.data(), sizeof(PageDev) * npages, hipMemcpyHostToDevice, s));
-      if (xscratch) {
-        if (hipMalloc(&d_xscratch, xscratch) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for expansion"); }
-        hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, d_scratch,
-                           d_xscratch, f->d_pages, 1, f->d_err);
-        if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
-      }
-    }
-  }
+  if (hipMalloc(&d_cs, sizeof(ColScan)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
   if (tiles) {
     if (hipMalloc(&f->d_tiles, sizeof(TileDev) * tiles) != hipSuccess ||
         hipMalloc(&f->d_ckl, sizeof(uint32_t) * NLCK * tiles) != hipSuccess ||
@@ -795,39 +762,157 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   if (strck) {
     if (hipMalloc(&f->d_strck, sizeof(uint32_t) * strck) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: checkpoint allocation"); }
   }
-  if (npages) {
+  const uint64_t flim = (len + 15) & ~15ull;  // the file is readable up to len rounded up to 16
+  if (sblk) {
+    // the Snappy block index of every compressed page, from a walk over the
+    // element tags (it reads the compressed pages only, so one launch serves
+    // every pass)
+    ColScan cs;
+    memset(&cs, 0, sizeof(cs));
+    cs.fd.file = file;
+    cs.fd.pages = f->d_pages;
+    cs.fd.sblk = f->d_sblk;
+    cs.fd.sblk_page = f->d_sblk_page;
+    OPEN_HIP(hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s));
+    std::vector<Segment> segs{Segment{0, 0, npages, 0}};
+    hipLaunchKernelGGL(k_snap_index, dim3(npages), dim3(64), 0, s, d_cs, make_segs(segs));
+    if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snap_index launch failed"); }
+  }
+  for (const OpenPass& P : passes) {
+    // this pass's pages; scr + (file-wide scratch offset) addresses the window
+    std::vector<uint32_t> plist;
+    bool any_comp = false;
+    for (uint32_t p = P.p0; p < P.p1; ++p)
+      if ((f->pages[p].kind == PAGE_DICT) == P.dict) {
+        plist.push_back(p);
+        any_comp |= f->pages[p].scratch_len > 0;
+      }
+    const uint8_t* scr = d_scratch ? d_scratch - P.s0 : nullptr;
+    const uint64_t scr_lim = P.s1;
+    const uint8_t* xscr = nullptr;  // the pass's expansion region, addressed through the file-wide layout
+    uint64_t xscr_lim = 0;
+    if (any_comp) {
+      // the indexed blocks side by side, the other pages one wave each
+      ColScan cs;
+      memset(&cs, 0, sizeof(cs));
+      cs.fd.file = file;
+      cs.fd.pages = f->d_pages;
+      cs.fd.sblk = f->d_sblk;
+      cs.fd.sblk_page = f->d_sblk_page;
+      cs.scratch_base = P.s0;
+      cs.open_sel = P.dict ? 1 : 2;
+      OPEN_HIP(hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s));
+      std::vector<Segment> segs{Segment{0, P.p0, P.p1, 0}};
+      SegTable st2 = make_segs(segs);
+      const uint32_t b0 = f->pages[P.p0].sblk_begin, b1 = P.p1 < npages ? f->pages[P.p1].sblk_begin : (uint32_t)sblk;
+      if (b1 > b0) {
+        std::vector<Segment> bsegs{Segment{0, b0, b1, 0}};
+        hipLaunchKernelGGL(k_snappy_blk, dim3((b1 - b0 + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s, d_cs,
+                           make_segs(bsegs), d_scratch, f->d_err, 1);
+      }
+      hipLaunchKernelGGL(k_snappy, dim3(P.p1 - P.p0), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
+      if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
+    }
+    // ---- DELTA_BYTE_ARRAY pages: facts, expansion layout, expansion ----
+    if (!P.dict) {
+      std::vector<ColScan> xc;
+      std::vector<Segment> xs;
+      uint32_t xw = 0;
+      for (int c = 0; c < f->ncols; ++c) {
+        if (f->cols[c].type != T_BYTE_ARRAY) continue;
+        const uint32_t p0 = std::max(P.p0, f->chunk_page0[(size_t)c * f->nrg]),
+                       p1 = std::min(P.p1, f->chunk_page0[(size_t)(c + 1) * f->nrg]);
+        bool any = false;
+        for (uint32_t pp = p0; pp < p1 && !any; ++pp) any = f->pages[pp].kind != PAGE_DICT && f->pages[pp].encoding == E_DBA;
+        if (!any) continue;
+        ColScan cs;
+        memset(&cs, 0, sizeof(cs));
+        cs.fd.file = file;
+        cs.fd.pages = f->d_pages;
+        cs.type = T_BYTE_ARRAY;
+        cs.optional = f->cols[c].optional;
+        cs.col = c;
+        cs.page_begin = p0;
+        cs.page_end = p1;
+        xs.push_back(Segment{(uint32_t)xc.size(), p0, p1, xw});
+        xw += p1 - p0;
+        xc.push_back(cs);
+      }
+      const uint64_t xs0 = xscratch;
+      for (uint32_t pp = P.p0; pp < P.p1; ++pp) f->xscratch_prefix[pp] = xscratch;
+      if (!xc.empty()) {
+        if (xs.size() > MAX_SEGS) { cleanup_open(); free_handle(f); return fail(PQ_EUNSUPPORTED, "too many DELTA_BYTE_ARRAY columns"); }
+        if (hipMalloc(&d_xcols, sizeof(ColScan) * xc.size()) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: allocation failed"); }
+        OPEN_HIP(hipMemcpyAsync(d_xcols, xc.data(), sizeof(ColScan) * xc.size(), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, scr,
+                           (uint8_t*)nullptr, f->d_pages, 0, f->d_err);
+        if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
+        {
+          pq_status stx = read_err(f, s);
+          if (stx != PQ_OK) { cleanup_open(); free_handle(f); return stx; }
+        }
+        OPEN_HIP(hipMemcpy(f->pages.data() + P.p0, f->d_pages + P.p0, sizeof(PageDev) * (P.p1 - P.p0),
+                           hipMemcpyDeviceToHost));
+        for (uint32_t pp = P.p0; pp < P.p1; ++pp) {
+          PageDev& pg = f->pages[pp];
+          f->xscratch_prefix[pp] = xscratch;
+          if (pg.kind == PAGE_DICT || pg.encoding != E_DBA || f->chunks[pg.chunk].type != T_BYTE_ARRAY ||
+              pg.x_total == DBA_UNSUPPORTED)
+            continue;
+          pg.x_off = xscratch;
+          xscratch += align_up((uint64_t)pg.xlen + SCRATCH_PAD, 16);
+        }
+        OPEN_HIP(hipMemcpyAsync(f->d_pages + P.p0, f->pages.data() + P.p0, sizeof(PageDev) * (P.p1 - P.p0),
+                                hipMemcpyHostToDevice, s));
+        if (xscratch > xs0) {
+          if (hipMalloc(&d_xscratch_mem, OPEN_GUARD + (xscratch - xs0)) != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: no device memory for expansion"); }
+          d_xscratch = d_xscratch_mem + OPEN_GUARD;
+          hipLaunchKernelGGL(k_dba, dim3(xw), dim3(64), 0, s, d_xcols, make_segs(xs), (uint8_t*)nullptr, scr,
+                             d_xscratch - xs0, f->d_pages, 1, f->d_err);
+          if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_dba launch failed"); }
+          xscr = d_xscratch - xs0;
+          xscr_lim = xscratch;
+        }
+      }
+    }
+    if (plist.empty()) {
+      if (P.dict) {  // no dictionary pages: every chunk's slot says so
+        pq_status st5 = build_dicts(f, scr, host_copy, s);
+        if (st5 != PQ_OK) { cleanup_open(); free_handle(f); return st5; }
+      }
+      free_pass();
+      continue;
+    }
     // one wave per page, the longest walks first (string dictionaries by
     // bytes, then data pages by rows), so that they start at once instead of
-    // behind the waves of earlier pages; the file is readable up to len
-    // rounded up to 16
-    std::vector<uint32_t> order(npages);
-    std::vector<uint64_t> work(npages);
+    // behind the waves of earlier pages
+    const uint32_t npl = (uint32_t)plist.size();
+    std::vector<uint32_t> order(plist);
+    std::vector<uint64_t> work(npages, 0);
     std::vector<uint32_t> lv_list;  // pages whose levels the k_lv kernels walk
     bool any_delta = false;         // pages that may have their blocks walked by the k_dl kernels
     bool any_dict = false;          // pages that may have their indices walked by the k_di kernels
-    for (uint32_t p = 0; p < npages; ++p) {
+    for (uint32_t p : plist) {
       const PageDev& pg = f->pages[p];
       const bool sdict = pg.kind == PAGE_DICT && f->chunks[pg.chunk].type == T_BYTE_ARRAY && pg.uncomp_size <= SCHAIN_MIN;
       work[p] = sdict ? 16ull * pg.uncomp_size : (uint64_t)(pg.num_values > 0 ? pg.num_values : 0);
-      order[p] = p;
       if (pg.kind != PAGE_DICT && lv_page(pg, f->chunks[pg.chunk].optional != 0)) lv_list.push_back(p);
       if (pg.kind != PAGE_DICT && (pg.encoding == E_DELTA || pg.encoding == E_DLBA)) any_delta = true;
       if (pg.kind != PAGE_DICT && (pg.encoding == E_PLAIN_DICT || pg.encoding == E_RLE_DICT)) any_dict = true;
     }
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
-    if (hipMalloc(&d_order, sizeof(uint32_t) * npages) != hipSuccess ||
-        hipMemcpy(d_order, order.data(), sizeof(uint32_t) * npages, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMalloc(&d_order, sizeof(uint32_t) * npl) != hipSuccess ||
+        hipMemcpy(d_order, order.data(), sizeof(uint32_t) * npl, hipMemcpyHostToDevice) != hipSuccess) {
       cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: page order");
     }
-    hipLaunchKernelGGL(k_index, dim3(npages), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npages,
-                       f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, (len + 15) & ~15ull,
-                       (uint64_t)scratch, d_order, d_xscratch, xscratch, 1);
+    hipLaunchKernelGGL(k_index, dim3(npl), dim3(64), 0, s, file, scr, f->d_pages, (int)npl, f->d_chunks, f->d_tiles,
+                       f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, scr_lim, d_order, xscr, xscr_lim, 1);
     if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_index launch failed"); }
     // long level streams: their exact lengths (stored by the launch above),
     // then candidates, link, tile entries, checkpoints and the value streams
-    const uint64_t flim = (len + 15) & ~15ull;
     if (!lv_list.empty() || any_delta || any_dict) {
-      OPEN_HIP(hipMemcpyAsync(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost, s));
+      OPEN_HIP(hipMemcpyAsync(f->pages.data() + P.p0, f->d_pages + P.p0, sizeof(PageDev) * (P.p1 - P.p0),
+                              hipMemcpyDeviceToHost, s));
       OPEN_HIP(hipStreamSynchronize(s));
     }
     if (!lv_list.empty()) {
@@ -861,17 +946,17 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       OPEN_HIP(hipMemcpyAsync(d_ord2, order2.data(), 4 * npg, hipMemcpyHostToDevice, s));
       if (nseg)
         hipLaunchKernelGGL(k_lv_cand, dim3((uint32_t)nseg), dim3(LV_CAND), 0, s, d_lps, d_segp, f->d_pages, file,
-                           d_scratch, flim, (uint64_t)scratch, d_cand);
+                           scr, flim, scr_lim, d_cand);
       hipLaunchKernelGGL(k_lv_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_lps, (int)npg, f->d_pages,
                          d_cand, d_ent, d_ok, f->d_err);
       if (nseg)
         hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)nseg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages,
-                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_ckl, f->d_err, 0);
+                           file, scr, flim, scr_lim, f->d_tiles, f->d_ckl, f->d_err, 0);
       hipLaunchKernelGGL(k_lv_tiles, dim3((uint32_t)npg), dim3(64), 0, s, d_lps, d_segp, d_ent, d_ok, f->d_pages, file,
-                         d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_ckl, f->d_err, 1);
-      hipLaunchKernelGGL(k_index, dim3((uint32_t)npg), dim3(64), 0, s, file, d_scratch, f->d_pages, (int)npg,
-                         f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, (uint64_t)scratch,
-                         d_ord2, d_xscratch, xscratch, 2);
+                         scr, flim, scr_lim, f->d_tiles, f->d_ckl, f->d_err, 1);
+      hipLaunchKernelGGL(k_index, dim3((uint32_t)npg), dim3(64), 0, s, file, scr, f->d_pages, (int)npg,
+                         f->d_chunks, f->d_tiles, f->d_strck, f->d_ckl, f->d_ckv, f->d_err, flim, scr_lim,
+                         d_ord2, xscr, xscr_lim, 2);
       if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_lv launch failed"); }
     }
     // long DELTA block chains (headers parsed by the index pass above): block
@@ -880,7 +965,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       std::vector<DlPage> dps;
       std::vector<uint32_t> seg_page, tile_dp;
       uint64_t nblk = 0;
-      for (uint32_t p = 0; p < npages; ++p) {
+      for (uint32_t p : plist) {
         const PageDev& pg = f->pages[p];
         if (!dl_page(pg, f->chunks[pg.chunk].type)) continue;
         DlPage x;
@@ -917,14 +1002,14 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
         if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_dp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
         if (nseg)
           hipLaunchKernelGGL(k_dl_cand, dim3((uint32_t)nseg), dim3(DL_CAND), 0, s, d_dps, d_segp, f->d_pages, file,
-                             d_scratch, flim, (uint64_t)scratch, d_cand, f->d_err);
+                             scr, flim, scr_lim, d_cand, f->d_err);
         hipLaunchKernelGGL(k_dl_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_dps, (int)npg, f->d_pages,
                            d_cand, d_ent, d_ok, f->d_err);
         if (nseg)
           hipLaunchKernelGGL(k_dl_fill, dim3((uint32_t)nseg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
-                             file, d_scratch, flim, (uint64_t)scratch, d_blk, f->d_err, 0);
+                             file, scr, flim, scr_lim, d_blk, f->d_err, 0);
         hipLaunchKernelGGL(k_dl_fill, dim3((uint32_t)npg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
-                           file, d_scratch, flim, (uint64_t)scratch, d_blk, f->d_err, 1);
+                           file, scr, flim, scr_lim, d_blk, f->d_err, 1);
         if (ntl)
           hipLaunchKernelGGL(k_dl_tiles, dim3((uint32_t)((ntl + 255) / 256)), dim3(256), 0, s, d_dps, d_tlp, (int)ntl,
                              f->d_pages, f->d_tiles, f->d_ckv, d_blk, f->d_err);
@@ -936,7 +1021,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     if (any_dict) {
       std::vector<DiPage> dps;
       std::vector<uint32_t> seg_page, tile_dp;
-      for (uint32_t p = 0; p < npages; ++p) {
+      for (uint32_t p : plist) {
         const PageDev& pg = f->pages[p];
         if (!di_page(pg)) continue;
         DiPage x;
@@ -967,31 +1052,31 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
         if (ntl) OPEN_HIP(hipMemcpyAsync(d_tlp, tile_dp.data(), 4 * ntl, hipMemcpyHostToDevice, s));
         if (nseg)
           hipLaunchKernelGGL(k_di_cand, dim3((uint32_t)nseg), dim3(256), 0, s, d_dps, d_segp, f->d_pages, file,
-                             d_scratch, flim, (uint64_t)scratch, d_cand, f->d_err);
+                             scr, flim, scr_lim, d_cand, f->d_err);
         hipLaunchKernelGGL(k_di_link, dim3((uint32_t)((npg + 63) / 64)), dim3(64), 0, s, d_dps, (int)npg, f->d_pages,
                            d_cand, d_ent, d_ok, f->d_err);
         if (nseg)
           hipLaunchKernelGGL(k_di_fill, dim3((uint32_t)nseg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
-                             file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 0);
+                             file, scr, flim, scr_lim, f->d_tiles, f->d_err, 0);
         hipLaunchKernelGGL(k_di_fill, dim3((uint32_t)npg), dim3(64), 0, s, d_dps, d_segp, d_ent, d_ok, f->d_pages,
-                           file, d_scratch, flim, (uint64_t)scratch, f->d_tiles, f->d_err, 1);
+                           file, scr, flim, scr_lim, f->d_tiles, f->d_err, 1);
         if (ntl)
           hipLaunchKernelGGL(k_di_ckpt, dim3((uint32_t)((ntl + 3) / 4)), dim3(64), 0, s, d_dps, d_tlp, (int)ntl,
-                             f->d_pages, f->d_tiles, file, d_scratch, flim, (uint64_t)scratch, f->d_ckv, f->d_err);
+                             f->d_pages, f->d_tiles, file, scr, flim, scr_lim, f->d_ckv, f->d_err);
         if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_di launch failed"); }
       }
     }
     // long string dictionaries: their length chains, segments side by side
     std::vector<SChainPage> scp;
     std::vector<uint32_t> seg_page;
-    for (uint32_t p = 0; p < npages; ++p) {
+    for (uint32_t p : plist) {
       const PageDev& pg = f->pages[p];
       if (pg.kind != PAGE_DICT || f->chunks[pg.chunk].type != T_BYTE_ARRAY || pg.uncomp_size <= SCHAIN_MIN) continue;
       const bool in_scratch = pg.scratch_len > 0;
       SChainPage x;
-      x.base = in_scratch ? d_scratch : file;
+      x.base = in_scratch ? scr : file;
       x.off = in_scratch ? pg.scratch_off : pg.payload;
-      x.lim = in_scratch ? (uint64_t)scratch : (len + 15) & ~15ull;
+      x.lim = in_scratch ? scr_lim : flim;
       x.len = (uint32_t)pg.uncomp_size;
       x.n = pg.num_values > 0 ? (uint32_t)pg.num_values : 0u;
       x.page = p;
@@ -1025,7 +1110,23 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
                          f->d_err);
       if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_schain launch failed"); }
     }
+    if (P.dict) {
+      // resident dictionaries, while the window holds the decompressed pages
+      {
+        pq_status st3 = read_err(f, s);
+        if (st3 != PQ_OK) { cleanup_open(); free_handle(f); return st3; }
+      }
+      OPEN_HIP(hipMemcpy(f->pages.data(), f->d_pages, sizeof(PageDev) * npages, hipMemcpyDeviceToHost));
+      pq_status st5 = build_dicts(f, scr, host_copy, s);
+      if (st5 != PQ_OK) { cleanup_open(); free_handle(f); return st5; }
+    }
+    {
+      pq_status st6 = read_err(f, s);  // the pass is done: its tables may go
+      if (st6 != PQ_OK) { cleanup_open(); free_handle(f); return st6; }
+    }
+    free_pass();
   }
+  f->xscratch_prefix[npages] = xscratch;
   HIP_OR(hipEventRecord(e1, s));
   {
     pq_status st3 = read_err(f, s);
@@ -1044,13 +1145,9 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   f->fd.strck = f->d_strck;
   f->fd.sblk = f->d_sblk;
   f->fd.sblk_page = f->d_sblk_page;
-  // ---- resident dictionaries (decompressed pages are still in d_scratch) ----
-  {
-    pq_status st5 = build_dicts(f, d_scratch, host_copy, s);
-    if (st5 != PQ_OK) { cleanup_open(); free_handle(f); return st5; }
-  }
   f->fd.dicts = f->d_dicts;
   cleanup_open();
+
 #undef OPEN_HIP
 #undef OPEN_ERR
 
@@ -1615,14 +1712,35 @@ static pq_status enqueue(pq_file f, Plan& P, uint8_t* ws, hipStream_t s) {
 // Builds the tile prefix at open: for every column with string or DELTA
 // pages, the prefix pass over its row groups (in batches whose workspace
 // stays below INDEX_WS_CAP), then the prefix sum on the host.
-constexpr uint64_t INDEX_WS_CAP = 1ull << 30;
+constexpr uint64_t INDEX_WS_CAP = 512ull << 20;
 
 // One prefix pass (k_prepass in `mode`) over the tiles of every column that
 // `need` selects, in row-group batches; fills val[t] for their tiles.
+// One index plan over columns `mask` and row groups [g0, g0 + n): its
+// per-tile values into val.
+static pq_status prefix_plan(pq_file f, int mode, Plan& P, std::vector<uint64_t>& val, hipStream_t s) {
+  if (!P.pre_units) return PQ_OK;
+  uint8_t* ws = nullptr;
+  if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
+  pq_status st = enqueue_index(f, P, ws, mode, s);
+  for (const ColScan& cs : P.cols) {
+    const uint32_t cnt = cs.tile_end - cs.tile_begin;
+    if (st == PQ_OK && cs.ws_tile_aux && cnt &&
+        hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+      st = fail(PQ_EHIP, "open: prefix pass copy");
+  }
+  if (st == PQ_OK) st = read_err(f, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  return st;
+}
+
 static pq_status prefix_pass(pq_file f, int mode, const std::vector<bool>& need, std::vector<uint64_t>& val,
                              hipStream_t s) {
   // every needed column at once (one decompression and one prepass launch
-  // per batch of row groups), the batches sized to INDEX_WS_CAP
+  // per batch of row groups), the batches sized to INDEX_WS_CAP; a single
+  // row group over the cap is taken one column at a time
   uint64_t mask = 0;
   for (int c = 0; c < f->ncols; ++c)
     if (need[(size_t)c]) mask |= 1ull << c;
@@ -1637,21 +1755,17 @@ static pq_status prefix_pass(pq_file f, int mode, const std::vector<bool>& need,
       if (P.ws_total <= INDEX_WS_CAP || n == 1) break;
       n = (n + 1) / 2;
     }
-    if (P.pre_units) {
-      uint8_t* ws = nullptr;
-      if (hipMalloc(&ws, P.ws_total) != hipSuccess) return fail(PQ_ENOMEM, "open: no device memory for the prefix pass");
-      pq_status st = enqueue_index(f, P, ws, mode, s);
-      for (const ColScan& cs : P.cols) {
-        const uint32_t cnt = cs.tile_end - cs.tile_begin;
-        if (st == PQ_OK && cs.ws_tile_aux && cnt &&
-            hipMemcpyAsync(val.data() + cs.tile_begin, ws + cs.ws_tile_aux, 8ull * cnt, hipMemcpyDeviceToHost, s) !=
-                hipSuccess)
-          st = fail(PQ_EHIP, "open: prefix pass copy");
-      }
-      if (st == PQ_OK) st = read_err(f, s);
-      (void)hipStreamSynchronize(s);
-      (void)hipFree(ws);
+    if (P.ws_total <= INDEX_WS_CAP || __builtin_popcountll(mask) == 1) {
+      pq_status st = prefix_plan(f, mode, P, val, s);
       if (st != PQ_OK) return st;
+    } else {
+      for (int c = 0; c < f->ncols; ++c) {
+        if (!((mask >> c) & 1)) continue;
+        Plan Q;
+        pq_status st = make_plan(f, 1ull << c, g0, g0 + n, Q, true);
+        if (st == PQ_OK) st = prefix_plan(f, mode, Q, val, s);
+        if (st != PQ_OK) return st;
+      }
     }
     g0 += n;
   }

@@ -357,7 +357,13 @@ struct ColScan {
   int64_t* offsets;
   uint8_t* chars;
   uint64_t ws_edge;       // workspace offset of per-tile validity edge words (OPTIONAL columns)
+  int32_t open_sel;       // open-time decompression: 0 every page, 1 dictionary pages, 2 data pages
+  int32_t pad_;
 };
+// Whether the open-time decompression pass of ColScan cs takes page pg.
+__host__ __device__ inline bool open_sel_ok(const ColScan& cs, const PageDev& pg) {
+  return cs.open_sel == 0 || (cs.open_sel == 1) == (pg.kind == PAGE_DICT);
+}
 
 // A run of tiles handled by one launch: ColScan `cs`, tiles [t0, t1),
 // workgroups [wg0, wg0 + t1 - t0).

@@ -1158,7 +1158,8 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
   if (pg.scratch_len == 0) return;
   // dictionaries are decompressed once, at open; pages with a block index
   // by k_snappy_blk
-  if ((mode == 0 && pg.kind == PAGE_DICT) || sblk[pg.sblk_begin] != SBLK_NONE) return;
+  if ((mode == 0 && pg.kind == PAGE_DICT) || (mode == 1 && !open_sel_ok(cs, pg)) || sblk[pg.sblk_begin] != SBLK_NONE)
+    return;
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
   const uint8_t* src = cs.fd.file + src_off;
@@ -1348,7 +1349,7 @@ __global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable
   const ColScan cs = cols[sg.cs];
   const PageDev pg = cs.fd.pages[p];
   uint32_t* sblk = cs.fd.sblk;
-  if (pg.scratch_len == 0) return;
+  if (pg.scratch_len == 0 || !open_sel_ok(cs, pg)) return;
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
   if (pg.kind == PAGE_DATA_V2) { src_off += (uint64_t)pg.rep_len + (uint64_t)pg.def_len; src_len64 -= (uint64_t)pg.rep_len + (uint64_t)pg.def_len; }
   const uint8_t* src = cs.fd.file + src_off;
@@ -1531,6 +1532,7 @@ __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& s
   const uint32_t p = cs.fd.sblk_page[b];
   const PageDev pg = cs.fd.pages[p];
   if (pg.scratch_len == 0 || (pg.kind == PAGE_DICT && !dicts)) return false;  // dictionaries: decompressed at open
+  if (dicts && !open_sel_ok(cs, pg)) return false;
   const uint32_t first = pg.sblk_begin;
   if (sblk[first] == SBLK_NONE) return false;  // decoded sequentially by k_snappy
   uint64_t src_off = pg.payload, src_len64 = pg.comp_size;
