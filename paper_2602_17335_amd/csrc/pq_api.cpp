@@ -1404,7 +1404,10 @@ struct ColSetup {
   uint32_t b0 = 0, b1 = 0;  // its Snappy blocks
 };
 
-void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint64_t& off, bool index, ColSetup& k) {
+// pr0/pr1 (index plans only): the pages [pr0, pr1) of the chunks instead of
+// all of them.
+void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint64_t& off, bool index, ColSetup& k,
+               uint32_t pr0 = ~0u, uint32_t pr1 = ~0u) {
   ColScan& cs = k.cs;
   memset(&cs, 0, sizeof(cs));
   cs.fd = f->fd;
@@ -1419,6 +1422,19 @@ void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint6
   cs.page_end = f->chunk_page0[q1];
   cs.row_base = f->rg_row0[rg_b];
   cs.rows = rows;
+  if (pr0 != ~0u) {
+    cs.page_begin = pr0;
+    cs.page_end = pr1;
+    uint32_t tb = ~0u, te = 0;
+    for (uint32_t p = pr0; p < pr1; ++p) {
+      const PageDev& pg = f->pages[p];
+      if (pg.kind == PAGE_DICT) continue;
+      tb = std::min(tb, pg.tile_begin);
+      te = std::max(te, pg.tile_begin + (uint32_t)(((uint64_t)pg.num_values + TILE_ROWS - 1) / TILE_ROWS));
+    }
+    cs.tile_begin = tb == ~0u ? te : tb;
+    cs.tile_end = te;
+  }
   cs.scratch_base = f->scratch_prefix[cs.page_begin];
   k.sbytes = f->scratch_prefix[cs.page_end] - cs.scratch_base;
   cs.ws_scratch = off;
@@ -1458,7 +1474,8 @@ void col_setup(pq_file f, int c, int32_t rg_b, int32_t rg_e, int64_t rows, uint6
   }
 }
 
-pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P, bool index = false) {
+pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& P, bool index = false,
+                    uint32_t pr0 = ~0u, uint32_t pr1 = ~0u) {
   if (rg_b < 0 || rg_e > f->nrg || rg_b > rg_e) return fail(PQ_EINVAL, "bad row-group range [%d, %d)", rg_b, rg_e);
   if (f->ncols < 64 && (mask >> f->ncols)) return fail(PQ_EINVAL, "column mask selects missing columns");
   P.rows = f->rg_row0[rg_e] - f->rg_row0[rg_b];
@@ -1470,7 +1487,7 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
   for (int c = 0; c < f->ncols; ++c) {
     if (!((mask >> c) & 1)) continue;
     ColSetup k;
-    col_setup(f, c, rg_b, rg_e, P.rows, off, index, k);
+    col_setup(f, c, rg_b, rg_e, P.rows, off, index, k, pr0, pr1);
     const ColScan& cs = k.cs;
     const uint32_t nt = k.nt;
     const uint32_t idx = (uint32_t)P.cols.size();
@@ -1759,12 +1776,30 @@ static pq_status prefix_pass(pq_file f, int mode, const std::vector<bool>& need,
       pq_status st = prefix_plan(f, mode, P, val, s);
       if (st != PQ_OK) return st;
     } else {
+      // one column at a time, and a column over the cap in runs of pages
       for (int c = 0; c < f->ncols; ++c) {
         if (!((mask >> c) & 1)) continue;
         Plan Q;
         pq_status st = make_plan(f, 1ull << c, g0, g0 + n, Q, true);
-        if (st == PQ_OK) st = prefix_plan(f, mode, Q, val, s);
         if (st != PQ_OK) return st;
+        if (Q.ws_total <= INDEX_WS_CAP) {
+          st = prefix_plan(f, mode, Q, val, s);
+          if (st != PQ_OK) return st;
+          continue;
+        }
+        const uint32_t pe = f->chunk_page0[(size_t)c * f->nrg + g0 + n];
+        for (uint32_t p0 = f->chunk_page0[(size_t)c * f->nrg + g0]; p0 < pe;) {
+          uint32_t p1 = p0 + 1;
+          auto bytes = [&](uint32_t b) {
+            return (f->scratch_prefix[b] - f->scratch_prefix[p0]) + (f->xscratch_prefix[b] - f->xscratch_prefix[p0]);
+          };
+          while (p1 < pe && bytes(p1 + 1) <= INDEX_WS_CAP / 2) ++p1;
+          Plan R;
+          st = make_plan(f, 1ull << c, g0, g0 + n, R, true, p0, p1);
+          if (st == PQ_OK) st = prefix_plan(f, mode, R, val, s);
+          if (st != PQ_OK) return st;
+          p0 = p1;
+        }
       }
     }
     g0 += n;
