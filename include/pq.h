@@ -125,22 +125,25 @@ typedef struct {
  *            stream).
  *   out      receives the handle.
  * The footer is copied to the host and decoded there (file layout and
- * Thrift-compact metadata, Sec. 2's row-group/chunk/page hierarchy); a kernel
- * then walks every column chunk's page headers into a device page table, and
- * a second kernel builds the tile index (entry positions of every fixed-size
- * row tile in the level and value streams of each page) that lets a scan
- * start decoding at any tile.  Every dictionary page is then decoded once
- * into a resident dictionary kept by the handle (fixed-width arrays; string
+ * Thrift-compact metadata, Sec. 2's row-group/chunk/page hierarchy); kernels
+ * then walk every column chunk's page headers into a device page table and
+ * build the tile index (entry positions of every fixed-size row tile in the
+ * level and value streams of each page, with checkpoints inside the tile)
+ * that lets a scan start decoding at any tile.  The index is built in
+ * passes: the dictionary pages first, then runs of data pages whose
+ * decompressed bytes fit a 512 MiB window, each pass's compressed pages
+ * decompressed into that window.  Every dictionary page is decoded once into
+ * a resident dictionary kept by the handle (fixed-width arrays; string
  * positions, lengths and 64-byte slots), so scans never rebuild one.  Last,
- * the tile prefix: for every column with
- * DELTA_BINARY_PACKED or BYTE_ARRAY pages, a pass over its tiles (after
- * decompression and dictionary decode, in batches of row groups with at most
- * 1 GiB of temporary device memory) counts each tile's DELTA sum or string
- * bytes, and their exclusive prefix sum over the file's tiles is kept on the
- * device and the host (8 bytes per tile).  A scan takes DELTA carries and
- * string offsets from it, and pq_plan the chars sizes.  Returns PQ_ECORRUPT
- * for a malformed file (including corrupt DELTA, dictionary-index or string
- * data found by the prefix pass), PQ_EUNSUPPORTED for valid files outside the
+ * the tile prefix: for every column with DELTA_BINARY_PACKED or BYTE_ARRAY
+ * pages, a pass over its tiles (after decompression and dictionary decode,
+ * in batches of row groups, or of pages, with at most 512 MiB of temporary
+ * device memory) counts each tile's DELTA sum or string bytes, and their
+ * exclusive prefix sum over the file's tiles is kept on the device and the
+ * host (8 bytes per tile).  A scan takes DELTA carries and string offsets from
+ * it, and pq_plan the chars sizes.  Returns PQ_ECORRUPT for a malformed file
+ * (including corrupt level, DELTA, dictionary-index or string data found by
+ * the index or prefix passes), PQ_EUNSUPPORTED for valid files outside the
  * supported subset.
  */
 pq_status pq_open_device(const void* dev_buf, uint64_t len, pq_stream stream, pq_file* out);
