@@ -262,11 +262,10 @@ constexpr uint8_t E_UNDECODED = 0xff;
 // decompressed sequentially, the others one block per lane.
 constexpr uint32_t SNAP_BLOCK = 65536;
 // k_snappy_blk: blocks decoded per wave; the wave's other lanes only help
-// copy long literals.  A block is a long chain of dependent steps: with one
-// block per lane a file's blocks fill less than one wave per SIMD, which
-// then has nothing to issue while its wave waits; 8 blocks per wave give
-// about eight waves per SIMD (16 and 4 were slower).
-constexpr uint32_t SNAP_LANES = 8;
+// copy long literals.  A wave runs as many batches as its densest block
+// needs, so more blocks per wave leave more lanes idle, and fewer leave
+// more waves per SIMD: 16 measured best (8, 32 and 64 were slower).
+constexpr uint32_t SNAP_LANES = 16;
 constexpr uint32_t SBLK_NONE = 0xffffffffu;
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.

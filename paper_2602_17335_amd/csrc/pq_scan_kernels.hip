@@ -1507,12 +1507,23 @@ __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t
 
 // ---------------------------------------------------------------------------
 // k_snappy_blk: the pages of the Snappy block index, one lane per 64 KiB
-// output block (a lane decodes its block's elements in order; SNAP_LANES
-// blocks of one or several pages advance together in a wave, whose other
-// lanes join every copy of a literal longer than 64 bytes).  Copies read
-// their source from the block's own output in global memory after this
-// lane's earlier stores have completed.
+// output block (SNAP_LANES blocks of one or several pages advance together
+// in a wave, whose other lanes join every copy of a literal longer than 64
+// bytes).  A lane decodes its block in batches: up to SNAP_BATCH short
+// elements (at most SNAP_SHORT bytes each) are parsed from the lane's
+// SNAP_WIN-byte window of the stream in LDS, then all their sources are
+// loaded (one 16-byte load each: the literal's stream bytes or the copy's
+// earlier output), then all are stored, so that a batch costs one memory
+// round trip instead of one per element.  A copy whose source reaches into
+// the batch's own output ends the batch (it opens the next one); a longer
+// element, or a copy overlapping its own output, is decoded on its own after
+// the batch's stores.  Loads see the lane's earlier stores (program order),
+// so no wait is needed between batches.
 // ---------------------------------------------------------------------------
+constexpr int SNAP_BATCH = 8;
+constexpr uint32_t SNAP_SHORT = 13;  // a run of up to 13 bytes lies in the 16 bytes from its dword
+constexpr uint32_t SNAP_WIN = 64;
+constexpr uint32_t SNAP_WSTRIDE = 20;  // dwords per lane window (80 bytes: fewer bank conflicts)
 // One lane's block of k_snappy_blk: its page's compressed stream, output
 // region and element range.  False for a lane without a block (past the
 // segment, a page that is not compressed or is decoded by k_snappy).
@@ -1551,9 +1562,29 @@ __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& s
   return true;
 }
 
+// The 16 bytes from output dword k0 of a short element: bytes [sh, sh + n)
+// of v (sh <= 3, n <= SNAP_SHORT) placed at byte d = dop & 3, the d bytes
+// before them taken from tw (the earlier output of that dword); the bytes
+// after the run are whatever v holds there.
+__device__ __forceinline__ u32x4a place_short(const u32x4a v, uint32_t sh, uint32_t d, uint32_t tw) {
+  // output byte 4 k + i (k = 0..3) is v byte 4 k + i + (sh - d)
+  const int32_t e = (int32_t)sh - (int32_t)d;  // -3 .. 3
+  const uint32_t fs = (uint32_t)e & 3u;
+  const bool back = e < 0;
+  const uint32_t u[6] = {0u, v.x, v.y, v.z, v.w, 0u};  // u[i + 1] = v[i]
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    o[k] = __builtin_amdgcn_alignbyte(back ? u[k + 1] : u[k + 2], back ? u[k] : u[k + 1], fs);
+  const uint32_t m = (1u << (8 * d)) - 1u;  // the bytes before the run
+  o[0] = (o[0] & ~m) | (tw & m);
+  return u32x4a{o[0], o[1], o[2], o[3]};
+}
+
 // dicts = 1 (open): dictionary pages too.
 __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err,
                                                    int dicts) {
+  __shared__ __align__(16) uint32_t s_win[WG / 64][SNAP_LANES][SNAP_WSTRIDE];
   const uint32_t lw = threadIdx.x & 63;
   const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
   // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
@@ -1565,101 +1596,156 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
   uint32_t ip = sl.ip, op = sl.ob;
   const uint32_t iend = sl.iend, ob = sl.ob, oend = sl.oend, p = sl.page;
   bool bad = sl.bad;
-  // the 16 stream bytes from the dword holding byte ip: loaded one element
-  // ahead (the next element's position is known once its tag is decoded), so
-  // its latency overlaps the current element's loads and stores
+  lds_u32* win = (lds_u32*)&s_win[threadIdx.x / 64][lw < SNAP_LANES ? lw : 0][0];
   typedef const __attribute__((address_space(1))) u32x4a* gq4;
-  u32x4a qv = {0u, 0u, 0u, 0u};
-  if (live && !bad && ip < iend) qv = *(gq4)((uintptr_t)(src + ip) & ~(uintptr_t)3);
+  typedef __attribute__((address_space(1))) u32x4a* gs4;
+  // loads of unused batch slots and of lanes without a block read this
+  // (valid, never written) address
+  const uintptr_t dummy = (uintptr_t)cols;
+  // the window: the SNAP_WIN stream bytes from the dword holding byte ip,
+  // loaded during the previous batch (pieces that start past the stream's
+  // end read the dummy address instead)
+  const uintptr_t send = (uintptr_t)(src + iend);
+  uintptr_t wa = 0;
+  u32x4a wv[SNAP_WIN / 16];
+  auto wload = [&]() {
+    wa = (uintptr_t)(src + ip) & ~(uintptr_t)3;
+#pragma unroll
+    for (int c = 0; c < (int)(SNAP_WIN / 16); ++c) wv[c] = *(gq4)(wa + 16 * c < send ? wa + 16 * c : dummy);
+  };
+  wload();
+  uint32_t tw = 0;  // the output dword holding byte op (its bytes before op are final)
   bool run = live && !bad && op < oend;
   while (__ballot(run)) {
-    bool big = false;  // a literal longer than 64 bytes, copied by the whole wave below
-    uintptr_t bd = 0, bs = 0;
-    uint32_t bn = 0;
-    if (run) do {  // one element; a malformed one ends the lane's block
-      if (ip >= iend) { bad = true; break; }
-      const uint32_t sh = (uint32_t)((uintptr_t)(src + ip) & 3);
-      const uint64_t x = (uint64_t)__builtin_amdgcn_alignbyte(qv.y, qv.x, sh) |
-                         ((uint64_t)__builtin_amdgcn_alignbyte(qv.z, qv.y, sh) << 32);
-      const uint32_t t = (uint32_t)x & 0xffu;
-      uint32_t nip, len = 0, off = 0, hl;
-      uint64_t L = 0;
-      const bool lit = (t & 3) == 0;
-      if (lit) {
-        uint32_t l = t >> 2;
-        hl = 1;
-        if (l >= 60) {
-          const uint32_t nb = l - 59;
-          l = (uint32_t)(x >> 8) & (nb == 4 ? 0xffffffffu : ((1u << (8 * nb)) - 1));
-          hl += nb;
-        }
-        L = (uint64_t)l + 1;
-        if ((uint64_t)ip + hl + L > iend || L > oend - op) { bad = true; break; }
-        nip = ip + hl + (uint32_t)L;
-      } else {
-        if ((t & 3) == 1) {
-          hl = 2;
-          len = 4 + ((t >> 2) & 7);
-          off = ((t >> 5) << 8) | ((uint32_t)(x >> 8) & 0xffu);
-        } else if ((t & 3) == 2) {
-          hl = 3;
-          len = (t >> 2) + 1;
-          off = (uint32_t)(x >> 8) & 0xffffu;
-        } else {
-          hl = 5;
-          len = (t >> 2) + 1;
-          off = (uint32_t)(x >> 8);
-        }
-        if (ip + hl > iend || off == 0 || off > op - ob || len > oend - op) { bad = true; break; }
-        nip = ip + hl;
-      }
-      if (nip < iend) qv = *(gq4)((uintptr_t)(src + nip) & ~(uintptr_t)3);
-      // one copy routine for a literal of at most 64 bytes and for a copy that
-      // does not overlap its output (which reads this lane's earlier output);
-      // longer literals are copied by the whole wave below
-      big = lit && L > 64;
-      if (big) {
-        bd = (uintptr_t)(dst + op);
-        bs = (uintptr_t)(src + ip + hl);
-        bn = (uint32_t)L;
-      }
-      if ((lit && !big) || (!lit && off >= len))
-        lane_copy64(dst + op, lit ? src + ip + hl : dst + op - off, lit ? (uint32_t)L : len);
-      if (lit) {
-        op += (uint32_t)L;
-      } else {
-        if (off < len) {  // the copy overlaps its output: bytes repeat with period off
-          uint32_t r = 0;   // k0 mod off, carried from chunk to chunk
-          for (uint32_t k0 = 0; k0 < len; k0 += 8) {
-            uint32_t bb[8];
+    // the batch: element j is n bytes (nk[j] & 0xff; nk[j] & 0x100 marks a
+    // copy) to output offset dop[j] from offset so[j] of the stream (a
+    // literal) or of the output (a copy)
+    uint32_t dop[SNAP_BATCH], so[SNAP_BATCH], nk[SNAP_BATCH];
+    uint32_t nb = 0;
+    // the element decoded alone after the batch: kind 1 a literal of at most
+    // 64 bytes, 2 a longer literal (the whole wave copies it), 3 a copy
+    // that does not overlap its output, 4 one that does
+    uint32_t skind = 0, sop = 0, ssrc = 0, sn = 0, soff = 0;
+    if (run) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              bb[j] = dst[op - off + r];
-              r = r + 1 == off ? 0u : r + 1;
-            }
+      for (int c = 0; c < (int)(SNAP_WIN / 16); ++c)
+        *reinterpret_cast<__attribute__((address_space(3))) u32x4*>(win + 4 * c) =
+            u32x4{wv[c].x, wv[c].y, wv[c].z, wv[c].w};
+    }
+    {
+      const uint32_t bop0 = op;  // the output before bop0 is stored
+      bool act = run;
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-              if (k0 + j < len) dst[op + k0 + j] = (uint8_t)bb[j];
+      for (int j = 0; j < SNAP_BATCH; ++j) {
+        // every step is computed, and applied only where `take` holds
+        const uint32_t o = (uint32_t)((uintptr_t)(src + ip) - wa);
+        const bool room = o + 5 <= SNAP_WIN;
+        const uint32_t oc = room ? o : 0u;
+        const uint32_t w0 = win[oc >> 2], w1 = win[(oc >> 2) + 1];
+        const uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, oc & 3);  // bytes o .. o + 3
+        const uint32_t x4 = (w1 >> (8 * (oc & 3))) & 0xffu;            // byte o + 4
+        const uint32_t t = x & 0xffu, ty = t & 3u, l6 = t >> 2;
+        const uint32_t b1234 = (x >> 8) | (x4 << 24);  // bytes o + 1 .. o + 4
+        // a literal: length l6 + 1, or (l6 >= 60) the next l6 - 59 bytes + 1
+        const uint32_t nbb = l6 >= 60u ? l6 - 59u : 0u;
+        const uint32_t lsh = (32u - 8u * nbb) & 31u;
+        const uint32_t lext = (b1234 << lsh) >> lsh;
+        const uint32_t llen = (nbb ? lext : l6) + 1u;
+        // a copy with a 1-byte (ty 1), 2-byte (2) or 4-byte (3) offset
+        const uint32_t c1len = 4u + (l6 & 7u), cnlen = l6 + 1u;
+        const uint32_t c1off = ((t >> 5) << 8) | (b1234 & 0xffu);
+        const uint32_t cnoff = b1234 & (0xffffffffu >> (ty == 2u ? 16u : 0u));
+        const bool lit = ty == 0u, c1 = ty == 1u;
+        const uint32_t len = lit ? llen : (c1 ? c1len : cnlen);
+        const uint32_t off = c1 ? c1off : cnoff;
+        const uint32_t hl = lit ? 1u + nbb : ty + 1u + (ty >> 1 & ty & 1u);
+        const bool go = act & (op < oend) & room;
+        const bool ipend = ip >= iend;
+        const uint32_t rin = ipend ? 0u : iend - ip;  // stream bytes left
+        bool bd = ipend | (hl > rin) | (len > oend - op);
+        bd |= lit ? ((len == 0u) | (len > rin - hl)) : ((off == 0u) | (off > op - ob));
+        bd &= go;
+        const bool shortok = (len <= SNAP_SHORT) & (op + 16u <= oend) & (lit | (off >= len));
+        const bool conflict = !lit & shortok & (op - off + len > bop0);  // its source is this batch's output
+        const bool take = go & !bd & !conflict;
+        const bool bat = take & shortok;
+        const bool slw = take & !shortok;
+        dop[j] = op;
+        so[j] = lit ? ip + hl : op - off;
+        nk[j] = len | (lit ? 0u : 0x100u);
+        nb = bat ? (uint32_t)j + 1u : nb;
+        const uint32_t kind = lit ? 1u + (uint32_t)(len > 64u) : 3u + (uint32_t)(off < len);
+        skind = slw ? kind : skind;
+        sop = slw ? op : sop;
+        ssrc = slw ? ip + hl : ssrc;
+        sn = slw ? len : sn;
+        soff = slw ? off : soff;
+        bad |= bd;
+        ip = take ? ip + hl + (lit ? len : 0u) : ip;
+        op = take ? op + len : op;
+        act = bat;
+      }
+    }
+    // the batch's sources, then the next window, then the batch's stores
+    u32x4a v[SNAP_BATCH];
+#pragma unroll
+    for (int j = 0; j < SNAP_BATCH; ++j) {
+      const uintptr_t a = (nk[j] & 0x100u) ? (uintptr_t)dst + so[j] : (uintptr_t)src + so[j];
+      v[j] = *(gq4)(((uint32_t)j < nb ? a : dummy) & ~(uintptr_t)3);
+    }
+    run = run && !bad;
+    wload();
+#pragma unroll
+    for (int j = 0; j < SNAP_BATCH; ++j) {
+      if ((uint32_t)j < nb) {
+        const uintptr_t a = (nk[j] & 0x100u) ? (uintptr_t)dst + so[j] : (uintptr_t)src + so[j];
+        const uint32_t n = nk[j] & 0xffu, d = dop[j] & 3u;
+        const u32x4a w = place_short(v[j], (uint32_t)(a & 3), d, tw);
+        *(gs4)((uintptr_t)dst + (dop[j] & ~3u)) = w;
+        const uint32_t te = (d + n) >> 2;  // the dword holding the element's end
+        tw = te == 0u ? w.x : te == 1u ? w.y : te == 2u ? w.z : w.w;
+      }
+    }
+    // the element decoded alone
+    bool big = false;
+    if (run && skind) {
+      if (skind == 1) {
+        lane_copy64(dst + sop, src + ssrc, sn);
+      } else if (skind == 2) {
+        big = true;
+      } else if (skind == 3) {
+        lane_copy64(dst + sop, dst + sop - soff, sn);
+      } else {  // bytes repeat with period soff
+        uint32_t r = 0;  // k0 mod soff, carried from chunk to chunk
+        for (uint32_t k0 = 0; k0 < sn; k0 += 8) {
+          uint32_t bb[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            bb[j] = dst[sop - soff + r];
+            r = r + 1 == soff ? 0u : r + 1;
           }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (k0 + j < sn) dst[sop + k0 + j] = (uint8_t)bb[j];
         }
-        op += len;
       }
-      ip = nip;
-    } while (false);
-    // long literals of this step, one after the other, each copied by all 64
-    // lanes (a lane's later loads see them: the wave's stores are performed
-    // in order)
+    }
+    // long literals, one after the other, each copied by all 64 lanes (a
+    // lane's later loads see them: the wave's stores are performed in order)
     uint64_t m = __ballot(big);
     while (m) {
       const int l = __builtin_ctzll(m);
       m &= m - 1;
+      const uintptr_t bd = (uintptr_t)(dst + sop), bs = (uintptr_t)(src + ssrc);
       uint8_t* d = (uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bd >> 32), l) << 32) |
                               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bd, l));
       const uint8_t* s = (const uint8_t*)(((uintptr_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bs >> 32), l) << 32) |
                                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bs, l));
-      wave_copy(d, s, (uint32_t)__builtin_amdgcn_readlane((int)bn, l), lw, 64);
+      wave_copy(d, s, (uint32_t)__builtin_amdgcn_readlane((int)sn, l), lw, 64);
     }
-    run = run && !bad && op < oend;
+    // after an element decoded alone, the output dword holding op is read back
+    if (run && skind && (op & 3u)) tw = *(const __attribute__((address_space(1))) uint32_t*)((uintptr_t)dst + (op & ~3u));
+    run = run && op < oend;
   }
   if (!live) return;
   if (!bad && (op != oend || ip != iend)) bad = true;
