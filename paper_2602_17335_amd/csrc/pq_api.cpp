@@ -62,7 +62,9 @@ __global__ void k_schain_fill(const SChainPage* pgs, const uint32_t* seg_page, c
 __global__ void k_schain_seq(const SChainPage* pgs, int npg, const uint32_t* ok, uint32_t* strck, PageDev* pages,
                              uint32_t* err);
 __global__ void k_snappy(const ColScan* cols, SegTable seg, uint8_t* ws, int record, uint32_t* err);
-__global__ void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err, int dicts);
+__global__ void k_snappy_blk(const ColScan* cols, SegTable seg, const uint32_t* sord, uint32_t cap, uint8_t* ws,
+                             uint32_t* err, int dicts);
+__global__ void k_snap_order(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* sord, uint32_t cap, int mode);
 __global__ void k_snap_index(const ColScan* cols, SegTable seg);
 __global__ void k_prep(const ColScan* cols, SegTable seg);
 __global__ void k_edges(const uint8_t* ws, const ColScan* cols, SegTable seg);
@@ -739,7 +741,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   // Snappy block index, built by the decompression below
   f->total_sblk = sblk;
   if (sblk) {
-    if (hipMalloc(&f->d_sblk, sizeof(uint32_t) * sblk) != hipSuccess ||
+    if (hipMalloc(&f->d_sblk, 2 * sizeof(uint32_t) * sblk) != hipSuccess ||  // offsets, then element counts
         hipMalloc(&f->d_sblk_page, sizeof(uint32_t) * sblk) != hipSuccess) {
       cleanup_open(); free_handle(f); return fail(PQ_ENOMEM, "open: block index allocation");
     }
@@ -773,6 +775,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
     cs.fd.pages = f->d_pages;
     cs.fd.sblk = f->d_sblk;
     cs.fd.sblk_page = f->d_sblk_page;
+    cs.fd.sblk_ne = f->d_sblk + f->total_sblk;
     OPEN_HIP(hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s));
     std::vector<Segment> segs{Segment{0, 0, npages, 0}};
     hipLaunchKernelGGL(k_snap_index, dim3(npages), dim3(64), 0, s, d_cs, make_segs(segs));
@@ -799,6 +802,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       cs.fd.pages = f->d_pages;
       cs.fd.sblk = f->d_sblk;
       cs.fd.sblk_page = f->d_sblk_page;
+    cs.fd.sblk_ne = f->d_sblk + f->total_sblk;
       cs.scratch_base = P.s0;
       cs.open_sel = P.dict ? 1 : 2;
       OPEN_HIP(hipMemcpyAsync(d_cs, &cs, sizeof(cs), hipMemcpyHostToDevice, s));
@@ -808,7 +812,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
       if (b1 > b0) {
         std::vector<Segment> bsegs{Segment{0, b0, b1, 0}};
         hipLaunchKernelGGL(k_snappy_blk, dim3((b1 - b0 + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s, d_cs,
-                           make_segs(bsegs), d_scratch, f->d_err, 1);
+                           make_segs(bsegs), (const uint32_t*)nullptr, 0u, d_scratch, f->d_err, 1);
       }
       hipLaunchKernelGGL(k_snappy, dim3(P.p1 - P.p0), dim3(64), 0, s, d_cs, st2, d_scratch, 1, f->d_err);
       if (hipGetLastError() != hipSuccess) { cleanup_open(); free_handle(f); return fail(PQ_EHIP, "k_snappy launch failed"); }
@@ -1145,6 +1149,7 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   f->fd.strck = f->d_strck;
   f->fd.sblk = f->d_sblk;
   f->fd.sblk_page = f->d_sblk_page;
+  f->fd.sblk_ne = f->d_sblk ? f->d_sblk + f->total_sblk : nullptr;
   f->fd.dicts = f->d_dicts;
   cleanup_open();
 
@@ -1380,6 +1385,7 @@ struct Plan {
   std::vector<Segment> dba_segs;   // k_dba: pages of columns with DELTA_BYTE_ARRAY pages, one wave each
   uint32_t dba_waves = 0;
   uint32_t sblk_lanes = 0;
+  uint64_t ws_sord = 0;  // k_snap_order's density buckets (0: blocks taken in segment order)
   bool str_spread[2] = {false, false}, fixed_spread[8] = {};  // columns interleaved wave by wave
   uint32_t snappy_waves = 0, prep_threads = 0, pre_units = 0, fixed_units[8] = {}, delta_units = 0, str_units[2] = {0, 0},
            edge_threads = 0;
@@ -1557,6 +1563,10 @@ pq_status make_plan(pq_file f, uint64_t mask, int32_t rg_b, int32_t rg_e, Plan& 
     P.str_spread[k] = true;
     P.str_units[k] = (uint32_t)P.str_segs[k].size() * most;
   }
+  if (!index && P.sblk_lanes && f->total_sblk < (1ull << SNAP_ORD_BITS) && P.cols.size() <= 64) {
+    P.ws_sord = off;  // SNAP_BUCKETS counters, then SNAP_BUCKETS lists of sblk_lanes entries
+    off = align_up(off + 256 + sizeof(uint32_t) * SNAP_BUCKETS * (uint64_t)P.sblk_lanes, 256);
+  }
   if (f->host && !index && !P.cols.empty()) {
     uint64_t most = 0;
     for (int g = rg_b; g < rg_e; ++g) {
@@ -1606,8 +1616,10 @@ static pq_status upload_header(Plan& P, uint8_t* ws, hipStream_t s) {
 
 // Snappy decompression of the plan's compressed data pages (column table
 // d_cols).
+// sord_off, sord_cap: the workspace region of k_snap_order's buckets and
+// their capacity (a plan's ws_sord and sblk_lanes; 0: segment order).
 static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_cols, uint8_t* ws, uint32_t* err,
-                                    hipStream_t s) {
+                                    hipStream_t s, uint64_t sord_off, uint32_t sord_cap) {
   for (const auto* v : {&P.snappy_segs, &P.sblk_segs, &P.dba_segs, &P.prep_segs, &P.pre_segs, &P.fixed_segs[0], &P.fixed_segs[1], &P.fixed_segs[2],
                         &P.fixed_segs[3], &P.fixed_segs[4], &P.fixed_segs[6], &P.delta_segs, &P.str_segs[0], &P.str_segs[1],
                         &P.edge_segs})
@@ -1619,8 +1631,17 @@ static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_c
   }
   if (P.sblk_lanes) {
     ProfScope ps_(f, KP_SNAPPY_BLK, s);
+    uint32_t* sord = nullptr;
+    if (sord_off && sord_cap >= P.sblk_lanes) {  // the blocks in buckets of density, the densest first
+      sord = (uint32_t*)(ws + sord_off);
+      hipLaunchKernelGGL(k_snap_order, dim3(1), dim3(256), 0, s, d_cols, make_segs(P.sblk_segs), ws, sord,
+                         sord_cap, 0);
+      hipLaunchKernelGGL(k_snap_order, dim3((P.sblk_lanes + 255) / 256), dim3(256), 0, s, d_cols,
+                         make_segs(P.sblk_segs), ws, sord, sord_cap, 1);
+      HIP_OR(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                       d_cols, make_segs(P.sblk_segs), ws, err, 0);
+                       d_cols, make_segs(P.sblk_segs), (const uint32_t*)sord, sord_cap, ws, err, 0);
     HIP_OR(hipGetLastError());
   }
   if (P.dba_waves) {  // DELTA_BYTE_ARRAY pages (after their decompression) to the PLAIN layout
@@ -1636,7 +1657,7 @@ static pq_status enqueue_decompress(pq_file f, const Plan& P, const ColScan* d_c
 static pq_status enqueue_front(pq_file f, Plan& P, uint8_t* ws, uint32_t* err, hipStream_t s) {
   pq_status st = upload_header(P, ws, s);
   if (st != PQ_OK) return st;
-  return enqueue_decompress(f, P, reinterpret_cast<ColScan*>(ws + P.ws_cols), ws, err, s);
+  return enqueue_decompress(f, P, reinterpret_cast<ColScan*>(ws + P.ws_cols), ws, err, s, P.ws_sord, P.sblk_lanes);
 }
 
 // The open-time prefix pass of a plan made with index = true: per-tile DELTA
@@ -2020,7 +2041,8 @@ extern "C" pq_status pq_scan_streamed(pq_file f, uint64_t col_mask, int32_t rg_b
     Plan Pg;  // the launch lists of row group g alone (same column order)
     st = make_plan(f, col_mask, g, g + 1, Pg);
     const ColScan* d_cols = reinterpret_cast<const ColScan*>(ws + P.ws_rgcols + sizeof(ColScan) * P.cols.size() * (size_t)i);
-    if (st == PQ_OK) st = enqueue_decompress(f, Pg, d_cols, ws, err, s);
+    // (Pg's workspace offsets are not this workspace's: the buckets are P's)
+    if (st == PQ_OK) st = enqueue_decompress(f, Pg, d_cols, ws, err, s, P.ws_sord, P.sblk_lanes);
     if (st == PQ_OK) st = enqueue_decode(f, Pg, d_cols, ws, err, s);
     if (st == PQ_OK && hipEventRecord(freed[slot], s) != hipSuccess) st = fail(PQ_EHIP, "event record failed");
   }
@@ -2332,7 +2354,7 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
     if (P.sblk_lanes) {
       ProfScope ps_(prof, KP_SNAPPY_BLK, s);
       hipLaunchKernelGGL(k_snappy_blk, dim3((P.sblk_lanes + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                         d_cols, seg_table(P.sblk_segs, ws, P.ws_sblk), ws, err, 0);
+                         d_cols, seg_table(P.sblk_segs, ws, P.ws_sblk), (const uint32_t*)nullptr, 0u, ws, err, 0);
       HIP_OR(hipGetLastError());
     }
   } else {
@@ -2349,7 +2371,7 @@ pq_status enqueue_batch(const BatchPlan& P, const pq_tuning& T, uint8_t* ws, hip
         ProfScope ps_(prof, KP_SNAPPY_BLK, s);
         std::vector<Segment> one{Segment{sp.cs, sp.b0, sp.b1, 0}};
         hipLaunchKernelGGL(k_snappy_blk, dim3((sp.b1 - sp.b0 + 4 * SNAP_LANES - 1) / (4 * SNAP_LANES)), dim3(256), 0, s,
-                           d_cols, make_segs(one), ws, err, 0);
+                           d_cols, make_segs(one), (const uint32_t*)nullptr, 0u, ws, err, 0);
         HIP_OR(hipGetLastError());
       }
     }

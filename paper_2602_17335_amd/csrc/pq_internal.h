@@ -267,6 +267,12 @@ constexpr uint32_t SNAP_BLOCK = 65536;
 // more waves per SIMD: 16 measured best (8, 32 and 64 were slower).
 constexpr uint32_t SNAP_LANES = 16;
 constexpr uint32_t SBLK_NONE = 0xffffffffu;
+// k_snap_order: a scan's blocks in buckets of element count (bucket 0: 8192
+// or more, bucket k: [2^(13-k), 2^(14-k)), the last: fewer than 128), the
+// densest first, so that the blocks of a k_snappy_blk wave take similar
+// numbers of steps.  A bucket entry is (column-table index << 26) | block.
+constexpr uint32_t SNAP_BUCKETS = 8;
+constexpr uint32_t SNAP_ORD_BITS = 26;
 
 // One tile: rows [row0, row0 + min(TILE_ROWS, num_values - row0)) of page `page`.
 struct TileDev {
@@ -328,6 +334,7 @@ struct FileDev {
                                // DELTA_LENGTH_BYTE_ARRAY tiles (NULL when the file has none)
   uint32_t* sblk;              // Snappy block index (written by the open-time pass)
   const uint32_t* sblk_page;   // page of each Snappy block
+  uint32_t* sblk_ne;           // elements of each Snappy block (written with sblk)
   const DictSlot* dicts;       // resident dictionaries, one per chunk (col * nrg + rg)
 };
 

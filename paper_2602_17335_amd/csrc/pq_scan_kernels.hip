@@ -1376,11 +1376,17 @@ __global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable
     if (ok && v != total) ok = false;
   }
   const uint32_t first = ip - m;
-  uint32_t op = 0;
+  uint32_t op = 0, ne = 0;  // ne: elements of the current block
   while (ok && ip < iend) {
     const uint64_t x = in.bytes8(in.at(ip));
     const uint32_t t = (uint32_t)x & 0xffu;
-    if (op && (op & (SNAP_BLOCK - 1)) == 0 && lane == 0) sblk[pg.sblk_begin + op / SNAP_BLOCK] = ip - m;
+    if (op && (op & (SNAP_BLOCK - 1)) == 0) {
+      if (lane == 0) {
+        sblk[pg.sblk_begin + op / SNAP_BLOCK] = ip - m;
+        cs.fd.sblk_ne[pg.sblk_begin + op / SNAP_BLOCK - 1] = ne;
+      }
+      ne = 0;
+    }
     uint32_t len, hl;
     if ((t & 3) == 0) {  // literal
       uint32_t l = t >> 2;
@@ -1415,8 +1421,10 @@ __global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable
     }
     if (op / SNAP_BLOCK != (op + len - 1) / SNAP_BLOCK) { ok = false; break; }  // straddles a boundary
     op += len;
+    ++ne;
   }
   if (op != total) ok = false;
+  if (lane == 0 && ok && total) cs.fd.sblk_ne[pg.sblk_begin + (total - 1) / SNAP_BLOCK] = ne;
   if (lane == 0) sblk[pg.sblk_begin] = ok ? first : SBLK_NONE;
 }
 
@@ -1469,13 +1477,15 @@ __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, ui
 }
 
 // The wave's active lanes (rank r of nact) copy n bytes s -> d together (a
-// literal: no overlap), 16 destination bytes per lane and step.  Destination
-// dword k (counted from d's dword) holds source bytes [4 k - sh, 4 k - sh +
-// 4), sh = d & 3; every dword is stored whole except dword 0 when d is not
-// dword-aligned (its bytes before d are earlier output, written bytewise), so
-// up to 3 bytes after d + n are overwritten, which the owning lane's next
-// element writes again (a block ends on a 16-byte boundary, a page inside its
+// literal: no overlap), 16 destination bytes per lane and step, the loads of
+// WC_UNROLL steps issued before their stores.  Destination dword k (counted
+// from d's dword) holds source bytes [4 k - sh, 4 k - sh + 4), sh = d & 3;
+// every dword is stored whole except dword 0 when d is not dword-aligned
+// (its bytes before d are earlier output, written bytewise), so up to 3
+// bytes after d + n are overwritten, which the owning lane's next element
+// writes again (a block ends on a 16-byte boundary, a page inside its
 // scratch padding).  Reads at most 3 bytes before s and 7 after s + n.
+constexpr int WC_UNROLL = 2;
 __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t n, uint32_t r, uint32_t nact) {
   const uint32_t sh = (uint32_t)((uintptr_t)d & 3);
   __attribute__((address_space(1))) uint32_t* dw =
@@ -1485,21 +1495,29 @@ __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t
   const uint32_t e = (uint32_t)(a0 & 3);
   const __attribute__((address_space(1))) uint32_t* q =
       (const __attribute__((address_space(1))) uint32_t*)(a0 & ~(uintptr_t)3);
-  for (uint32_t k0 = 4 * r; k0 < nd; k0 += 4 * nact) {
-    uint32_t w[5];
+  const uint32_t step = 4 * nact;
+  for (uint32_t k0 = 4 * r; k0 < nd; k0 += WC_UNROLL * step) {
+    uint32_t w[WC_UNROLL][5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) w[c] = k0 + c <= nd ? q[k0 + c] : 0u;
+    for (int u = 0; u < WC_UNROLL; ++u) {
+      const uint32_t kk = k0 + u * step;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t k = k0 + j;
-      const uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], e);
-      if (k == 0 && sh) {
-        uint8_t* bp = (uint8_t*)dw;
+      for (int c = 0; c < 5; ++c) w[u][c] = kk + c <= nd ? q[kk + c] : 0u;
+    }
 #pragma unroll
-        for (int i = 1; i < 4; ++i)
-          if ((uint32_t)i >= sh && (uint32_t)i - sh < n) bp[i] = (uint8_t)(v >> (8 * i));
-      } else if (k < nd) {
-        dw[k] = v;
+    for (int u = 0; u < WC_UNROLL; ++u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t k = k0 + u * step + j;
+        const uint32_t v = __builtin_amdgcn_alignbyte(w[u][j + 1], w[u][j], e);
+        if (k == 0 && sh) {
+          uint8_t* bp = (uint8_t*)dw;
+#pragma unroll
+          for (int i = 1; i < 4; ++i)
+            if ((uint32_t)i >= sh && (uint32_t)i - sh < n) bp[i] = (uint8_t)(v >> (8 * i));
+        } else if (k < nd) {
+          dw[k] = v;
+        }
       }
     }
   }
@@ -1533,12 +1551,10 @@ struct SnapLane {
   uint32_t ip, iend, ob, oend, page, pad_;
   bool bad;
 };
-__device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& seg, uint8_t* ws, uint32_t gid,
-                                          SnapLane& sl, bool dicts) {
-  const Segment sg = seg_lookup(seg, gid);
-  const uint32_t b = sg.t0 + (gid - sg.wg0);
-  if (b >= sg.t1) return false;
-  const ColScan cs = cols[sg.cs];
+// Block b of column-table entry csi.
+__device__ __forceinline__ bool snap_lane_at(const ColScan* cols, uint32_t csi, uint32_t b, uint8_t* ws, SnapLane& sl,
+                                             bool dicts) {
+  const ColScan cs = cols[csi];
   const uint32_t* sblk = cs.fd.sblk;
   const uint32_t p = cs.fd.sblk_page[b];
   const PageDev pg = cs.fd.pages[p];
@@ -1561,6 +1577,49 @@ __device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& s
   sl.bad = src_len64 >= 0x7fffffffull || sl.ip > sl.iend || sl.iend > src_len;
   return true;
 }
+// Lane gid's block: from the density buckets sord (when given), else from
+// the segment table.
+__device__ __forceinline__ bool snap_lane(const ColScan* cols, const SegTable& seg, const uint32_t* sord,
+                                          uint32_t cap, uint8_t* ws, uint32_t gid, SnapLane& sl, bool dicts) {
+  if (sord) {
+    uint32_t base = 0, e = ~0u;
+#pragma unroll
+    for (uint32_t k = 0; k < SNAP_BUCKETS; ++k) {
+      const uint32_t c = sord[k];
+      if (gid >= base && gid - base < c) e = sord[64 + k * cap + (gid - base)];
+      base += c;
+    }
+    if (e == ~0u) return false;
+    return snap_lane_at(cols, e >> SNAP_ORD_BITS, e & ((1u << SNAP_ORD_BITS) - 1), ws, sl, dicts);
+  }
+  const Segment sg = seg_lookup(seg, gid);
+  const uint32_t b = sg.t0 + (gid - sg.wg0);
+  if (b >= sg.t1) return false;
+  return snap_lane_at(cols, sg.cs, b, ws, sl, dicts);
+}
+
+// k_snap_order (scans): mode 0 clears the bucket counters sord[0 ..
+// SNAP_BUCKETS); mode 1 puts every block of the segment table that
+// k_snappy_blk decodes into the bucket of its element count (bucket k's list
+// at sord + 64 + k cap; the order within a bucket is immaterial).
+__global__ __launch_bounds__(WG) void k_snap_order(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* sord,
+                                                   uint32_t cap, int mode) {
+  const uint32_t gid = blockIdx.x * WG + threadIdx.x;
+  if (mode == 0) {
+    if (gid < SNAP_BUCKETS) sord[gid] = 0;
+    return;
+  }
+  const Segment sg = seg_lookup(seg, gid);
+  const uint32_t b = sg.t0 + (gid - sg.wg0);
+  if (b >= sg.t1) return;
+  SnapLane sl;
+  if (!snap_lane_at(cols, sg.cs, b, ws, sl, false)) return;
+  const uint32_t ne = max(cols[sg.cs].fd.sblk_ne[b], 1u);
+  const uint32_t lg = 31u - (uint32_t)__builtin_clz(ne);
+  const uint32_t k = lg >= 13u ? 0u : lg <= 6u ? SNAP_BUCKETS - 1 : 13u - lg;
+  const uint32_t slot = atomicAdd(&sord[k], 1u);
+  sord[64 + k * cap + slot] = (sg.cs << SNAP_ORD_BITS) | b;
+}
 
 // The 16 bytes from output dword k0 of a short element: bytes [sh, sh + n)
 // of v (sh <= 3, n <= SNAP_SHORT) placed at byte d = dop & 3, the d bytes
@@ -1581,16 +1640,17 @@ __device__ __forceinline__ u32x4a place_short(const u32x4a v, uint32_t sh, uint3
   return u32x4a{o[0], o[1], o[2], o[3]};
 }
 
-// dicts = 1 (open): dictionary pages too.
-__global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, uint8_t* ws, uint32_t* err,
-                                                   int dicts) {
+// dicts = 1 (open): dictionary pages too.  sord: the density buckets of
+// k_snap_order (cap entries each), or null for the segment table's order.
+__global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, const uint32_t* sord,
+                                                   uint32_t cap, uint8_t* ws, uint32_t* err, int dicts) {
   __shared__ __align__(16) uint32_t s_win[WG / 64][SNAP_LANES][SNAP_WSTRIDE];
   const uint32_t lw = threadIdx.x & 63;
   const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
   // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
   // copy long literals
   SnapLane sl = {nullptr, nullptr, 0u, 0u, 0u, 0u, 0u, 0u, false};
-  const bool live = lw < SNAP_LANES && snap_lane(cols, seg, ws, gid, sl, dicts != 0);
+  const bool live = lw < SNAP_LANES && snap_lane(cols, seg, sord, cap, ws, gid, sl, dicts != 0);
   const uint8_t* src = sl.src;
   uint8_t* dst = sl.dst;
   uint32_t ip = sl.ip, op = sl.ob;
