@@ -1611,14 +1611,30 @@ __global__ __launch_bounds__(WG) void k_snap_order(const ColScan* cols, SegTable
   }
   const Segment sg = seg_lookup(seg, gid);
   const uint32_t b = sg.t0 + (gid - sg.wg0);
-  if (b >= sg.t1) return;
   SnapLane sl;
-  if (!snap_lane_at(cols, sg.cs, b, ws, sl, false)) return;
-  const uint32_t ne = max(cols[sg.cs].fd.sblk_ne[b], 1u);
-  const uint32_t lg = 31u - (uint32_t)__builtin_clz(ne);
-  const uint32_t k = lg >= 13u ? 0u : lg <= 6u ? SNAP_BUCKETS - 1 : 13u - lg;
-  const uint32_t slot = atomicAdd(&sord[k], 1u);
-  sord[64 + k * cap + slot] = (sg.cs << SNAP_ORD_BITS) | b;
+  const bool ok = b < sg.t1 && snap_lane_at(cols, sg.cs, b, ws, sl, false);
+  uint32_t k = SNAP_BUCKETS;
+  if (ok) {
+    const uint32_t ne = max(cols[sg.cs].fd.sblk_ne[b], 1u);
+    const uint32_t lg = 31u - (uint32_t)__builtin_clz(ne);
+    k = lg >= 13u ? 0u : lg <= 6u ? SNAP_BUCKETS - 1 : 13u - lg;
+  }
+  // one atomic per bucket and wave; a lane's slot is its rank among the
+  // wave's lanes of its bucket
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t below = (lane ? ~0ull >> (64 - lane) : 0ull);
+  uint32_t slot = 0;
+#pragma unroll
+  for (uint32_t kb = 0; kb < SNAP_BUCKETS; ++kb) {
+    const uint64_t m = __ballot(k == kb);
+    if (!m) continue;
+    const int lead = __builtin_ctzll(m);
+    uint32_t base = 0;
+    if ((int)lane == lead) base = atomicAdd(&sord[kb], (uint32_t)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, lead);
+    if (k == kb) slot = base + (uint32_t)__popcll(m & below);
+  }
+  if (ok) sord[64 + k * cap + slot] = (sg.cs << SNAP_ORD_BITS) | b;
 }
 
 // The 16 bytes from output dword k0 of a short element: bytes [sh, sh + n)
