@@ -1542,6 +1542,9 @@ constexpr int SNAP_BATCH = 8;
 constexpr uint32_t SNAP_SHORT = 13;  // a run of up to 13 bytes lies in the 16 bytes from its dword
 constexpr uint32_t SNAP_WIN = 64;
 constexpr uint32_t SNAP_WSTRIDE = 20;  // dwords per lane window (80 bytes: fewer bank conflicts)
+// dwords per lane of the batch's output in LDS (from the dword holding the
+// batch's first byte; 16 bytes per element written, at most SNAP_SHORT apart)
+constexpr uint32_t SNAP_BSTRIDE = ((SNAP_BATCH * SNAP_SHORT + 20 + 15) / 16) * 4 + 4;
 // One lane's block of k_snappy_blk: its page's compressed stream, output
 // region and element range.  False for a lane without a block (past the
 // segment, a page that is not compressed or is decoded by k_snappy).
@@ -1661,6 +1664,7 @@ __device__ __forceinline__ u32x4a place_short(const u32x4a v, uint32_t sh, uint3
 __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable seg, const uint32_t* sord,
                                                    uint32_t cap, uint8_t* ws, uint32_t* err, int dicts) {
   __shared__ __align__(16) uint32_t s_win[WG / 64][SNAP_LANES][SNAP_WSTRIDE];
+  __shared__ __align__(16) uint32_t s_bat[WG / 64][SNAP_LANES][SNAP_BSTRIDE];
   const uint32_t lw = threadIdx.x & 63;
   const uint32_t gid = (blockIdx.x * WG + threadIdx.x) / 64 * SNAP_LANES + lw;
   // lanes lw >= SNAP_LANES decode no block: they stay in the loop to help
@@ -1673,6 +1677,7 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
   const uint32_t iend = sl.iend, ob = sl.ob, oend = sl.oend, p = sl.page;
   bool bad = sl.bad;
   lds_u32* win = (lds_u32*)&s_win[threadIdx.x / 64][lw < SNAP_LANES ? lw : 0][0];
+  lds_u32* bat = (lds_u32*)&s_bat[threadIdx.x / 64][lw < SNAP_LANES ? lw : 0][0];
   typedef const __attribute__((address_space(1))) u32x4a* gq4;
   typedef __attribute__((address_space(1))) u32x4a* gs4;
   // loads of unused batch slots and of lanes without a block read this
@@ -1742,13 +1747,16 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
         bd |= lit ? ((len == 0u) | (len > rin - hl)) : ((off == 0u) | (off > op - ob));
         bd &= go;
         const bool shortok = (len <= SNAP_SHORT) & (op + 16u <= oend) & (lit | (off >= len));
-        const bool conflict = !lit & shortok & (op - off + len > bop0);  // its source is this batch's output
+        // a source reaching into this batch's output is read from the batch's
+        // copy in LDS, unless it starts before that copy's first dword
+        const bool insrc = !lit & (op - off + len > bop0);
+        const bool conflict = shortok & insrc & (op - off < (bop0 & ~3u));
         const bool take = go & !bd & !conflict;
         const bool bat = take & shortok;
         const bool slw = take & !shortok;
         dop[j] = op;
         so[j] = lit ? ip + hl : op - off;
-        nk[j] = len | (lit ? 0u : 0x100u);
+        nk[j] = len | (lit ? 0u : 0x100u) | (insrc ? 0x200u : 0u);
         nb = bat ? (uint32_t)j + 1u : nb;
         const uint32_t kind = lit ? 1u + (uint32_t)(len > 64u) : 3u + (uint32_t)(off < len);
         skind = slw ? kind : skind;
@@ -1767,17 +1775,35 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
 #pragma unroll
     for (int j = 0; j < SNAP_BATCH; ++j) {
       const uintptr_t a = (nk[j] & 0x100u) ? (uintptr_t)dst + so[j] : (uintptr_t)src + so[j];
-      v[j] = *(gq4)(((uint32_t)j < nb ? a : dummy) & ~(uintptr_t)3);
+      v[j] = *(gq4)(((uint32_t)j < nb && !(nk[j] & 0x200u) ? a : dummy) & ~(uintptr_t)3);
     }
     run = run && !bad;
     wload();
+    // stored in order; when a later element of the batch has its source in
+    // this batch's output, each element's 16 bytes also go to the batch's
+    // copy in LDS (bat, from the dword holding byte bop0), where it reads them
+    const uint32_t bb0 = dop[0] & ~3u;
+    bool usebat = false;  // some element of the batch reads it
+#pragma unroll
+    for (int j = 1; j < SNAP_BATCH; ++j) usebat |= (uint32_t)j < nb && (nk[j] & 0x200u);
 #pragma unroll
     for (int j = 0; j < SNAP_BATCH; ++j) {
       if ((uint32_t)j < nb) {
         const uintptr_t a = (nk[j] & 0x100u) ? (uintptr_t)dst + so[j] : (uintptr_t)src + so[j];
         const uint32_t n = nk[j] & 0xffu, d = dop[j] & 3u;
-        const u32x4a w = place_short(v[j], (uint32_t)(a & 3), d, tw);
+        u32x4a x = v[j];
+        uint32_t sh = (uint32_t)(a & 3);
+        if (nk[j] & 0x200u) {
+          const uint32_t r = so[j] - bb0, k = r >> 2;
+          x = u32x4a{bat[k], bat[k + 1], bat[k + 2], bat[k + 3]};
+          sh = r & 3u;
+        }
+        const u32x4a w = place_short(x, sh, d, tw);
         *(gs4)((uintptr_t)dst + (dop[j] & ~3u)) = w;
+        if (usebat) {
+          const uint32_t k = ((dop[j] & ~3u) - bb0) >> 2;
+          bat[k] = w.x; bat[k + 1] = w.y; bat[k + 2] = w.z; bat[k + 3] = w.w;
+        }
         const uint32_t te = (d + n) >> 2;  // the dword holding the element's end
         tw = te == 0u ? w.x : te == 1u ? w.y : te == 2u ? w.z : w.w;
       }
