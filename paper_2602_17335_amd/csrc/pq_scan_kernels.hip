@@ -3,8 +3,10 @@
 //
 //   k_snappy        Snappy page bodies -> workspace (one wave per page)
 //   k_dba           DELTA_BYTE_ARRAY pages -> PLAIN layout (one wave per page)
+//   k_snap_index    Snappy block index and element counts (at open, one wave per page)
+//   k_snap_order    a scan's Snappy blocks in buckets of element count
 //   k_snappy_blk    Snappy page bodies with a block index (one lane per 64 KiB block,
-//                   SNAP_LANES blocks per wave)
+//                   SNAP_LANES blocks per wave, elements in batches)
 //   k_prep          validity edge words cleared / REQUIRED validity set to ones
 //   k_dict          dictionary pages -> device dictionaries
 //   k_prepass       per-tile DELTA sums and string byte counts (at open)
@@ -1337,8 +1339,9 @@ __global__ __launch_bounds__(64) void k_snappy(const ColScan* cols, SegTable seg
 // first entry is SBLK_NONE when an element straddles a block boundary, a
 // copy reaches before the start of its block, or the stream is malformed:
 // such a page is decompressed sequentially by k_snappy, which reports what
-// is wrong.  (One lane per page, with a private LDS window each, was three
-// times slower.)
+// is wrong.  The walk also counts each block's elements (sblk_ne), by which
+// a scan orders its blocks.  (One lane per page, with a private LDS window
+// each, was three times slower.)
 __global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable seg) {
   __shared__ __align__(16) uint32_t s_in[SNAP_IN / 4 + 4];
   const uint32_t gw = blockIdx.x;
