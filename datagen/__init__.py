@@ -90,6 +90,7 @@ class FileSpec:
     rle_min: int = 8
     seed: int = 0x5EED0000
     snappy_literal_only: bool = False
+    snappy_varied_forms: bool = False  # every Snappy tag form in turn (decoder fixture)
     index_width: int = 0  # dictionary index bit width byte when wider than the minimum (legal; 0 = minimal)
     encoding_search: bool = False  # per chunk, the candidate encoding of smallest encoded size
     min_saving_pct: int = 0  # >0: chunks whose Snappy pages save no more than this stay uncompressed
@@ -110,7 +111,7 @@ class FileSpec:
         sp.rle_min = self.rle_min
         sp.ncols = len(self.cols)
         sp.nthreads = nthreads
-        sp.snappy_skip = 1 if self.snappy_literal_only else 0
+        sp.snappy_skip = 1 if self.snappy_literal_only else 2 if self.snappy_varied_forms else 0
         sp.index_width = self.index_width
         sp.encoding_search = 1 if self.encoding_search else 0
         sp.min_saving_pct = self.min_saving_pct
@@ -171,11 +172,13 @@ def write(spec: FileSpec, nthreads: Optional[int] = None) -> np.ndarray:
     return out
 
 
-def snappy_compress(data: bytes, literal_only: bool = False) -> bytes:
+def snappy_compress(data: bytes, literal_only: bool = False, varied_forms: bool = False) -> bytes:
+    """The fixture compressor: greedy matcher; one literal (literal_only); or
+    the greedy matcher's elements in every tag form in turn (varied_forms)."""
     L = lib()
     buf = ctypes.create_string_buffer(bytes(data), len(data))
     n = ctypes.c_size_t(0)
-    p = L.pqg_snappy(buf, len(data), 1 if literal_only else 0, ctypes.byref(n))
+    p = L.pqg_snappy(buf, len(data), 1 if literal_only else 2 if varied_forms else 0, ctypes.byref(n))
     try:
         return ctypes.string_at(p, n.value)
     finally:

@@ -65,7 +65,8 @@ typedef struct {
   int32_t rle_min;        /* repeat count at which the hybrid encoder switches to RLE */
   int32_t ncols;
   int32_t nthreads;
-  int32_t snappy_skip;    /* 0: greedy matcher; 1: literal-only Snappy streams */
+  int32_t snappy_skip;    /* 0: greedy matcher; 1: literal-only Snappy streams;
+                             2: greedy matcher, every tag form in turn */
   int32_t index_width;    /* dictionary index bit width when wider than the minimum (0: minimal) */
   int32_t encoding_search; /* 1: per chunk, the candidate encoding of smallest encoded size */
   int32_t min_saving_pct;  /* >0: a chunk stays uncompressed unless Snappy saves more than this many percent */
@@ -442,11 +443,52 @@ static void sn_copy(buf_t* b, size_t off, size_t len) {
   if (len > 64) { sn_copy1(b, off, 60); len -= 60; }
   sn_copy1(b, off, len);
 }
+/* mode 2: the same elements written in every legal form in turn (a fixture
+   for decoders): literal lengths in the tag or in 1-4 length bytes (more than
+   needed), copies with a 1-, 2- or 4-byte offset */
+static void sn_literal_v(buf_t* b, const uint8_t* s, size_t n, unsigned* ctr) {
+  while (n > 0) {
+    size_t take = n > 0xFFFFFFFFull ? 0xFFFFFFFFull : n;
+    size_t l = take - 1;
+    unsigned nb = l < 60 ? 0 : l < 256 ? 1 : l < 65536 ? 2 : l < (1u << 24) ? 3 : 4;
+    unsigned k = (*ctr)++ % 5;
+    if (k > nb) nb = k;
+    if (nb == 0) {
+      put_u8(b, (uint8_t)(l << 2));
+    } else {
+      put_u8(b, (uint8_t)((59 + nb) << 2));
+      for (unsigned i = 0; i < nb; ++i) put_u8(b, (uint8_t)(l >> (8 * i)));
+    }
+    put_bytes(b, s, take);
+    s += take; n -= take;
+  }
+}
+static void sn_copy_v(buf_t* b, size_t off, size_t len, unsigned* ctr) {
+  while (len > 0) {
+    size_t take = len > 64 ? 64 : len;
+    unsigned k = (*ctr)++ % 3;
+    if (k == 0 && off < 2048 && take >= 4 && take <= 11) {
+      put_u8(b, (uint8_t)(((off >> 8) << 5) | ((take - 4) << 2) | 1));
+      put_u8(b, (uint8_t)off);
+    } else if (k <= 1 && off < 65536) {
+      put_u8(b, (uint8_t)(((take - 1) << 2) | 2));
+      put_u8(b, (uint8_t)off); put_u8(b, (uint8_t)(off >> 8));
+    } else {
+      put_u8(b, (uint8_t)(((take - 1) << 2) | 3));
+      put_u32le(b, (uint32_t)off);
+    }
+    len -= take;
+  }
+}
+
 static inline uint32_t ld32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
 
-void pqg_snappy_compress(const uint8_t* src, size_t n, buf_t* b, int literal_only) {
+/* mode 0: greedy matcher; 1: one literal; 2: greedy matcher, the elements in
+   every tag form in turn */
+void pqg_snappy_compress(const uint8_t* src, size_t n, buf_t* b, int mode) {
   put_uleb(b, n);
-  if (literal_only) { if (n) sn_literal(b, src, n); return; }
+  if (mode == 1) { if (n) sn_literal(b, src, n); return; }
+  unsigned ctr_l = 0, ctr_c = 0;
   int32_t* table = (int32_t*)malloc(sizeof(int32_t) * (1 << 14));
   for (size_t f0 = 0; f0 < n; f0 += 65536) {
     size_t f1 = f0 + 65536 < n ? f0 + 65536 : n;
@@ -461,23 +503,31 @@ void pqg_snappy_compress(const uint8_t* src, size_t n, buf_t* b, int literal_onl
         size_t c = f0 + (size_t)cand;
         size_t len = 4;
         while (ip + len < f1 && src[c + len] == src[ip + len]) ++len;
-        if (ip > lit) sn_literal(b, src + lit, ip - lit);
-        sn_copy(b, ip - c, len);
+        if (mode == 2) {
+          if (ip > lit) sn_literal_v(b, src + lit, ip - lit, &ctr_l);
+          sn_copy_v(b, ip - c, len, &ctr_c);
+        } else {
+          if (ip > lit) sn_literal(b, src + lit, ip - lit);
+          sn_copy(b, ip - c, len);
+        }
         ip += len;
         lit = ip;
       } else {
         ++ip;
       }
     }
-    if (f1 > lit) sn_literal(b, src + lit, f1 - lit);
+    if (f1 > lit) {
+      if (mode == 2) sn_literal_v(b, src + lit, f1 - lit, &ctr_l);
+      else sn_literal(b, src + lit, f1 - lit);
+    }
   }
   free(table);
 }
 
 /* exported wrapper for tests: returns malloc'd buffer */
-uint8_t* pqg_snappy(const uint8_t* src, size_t n, int literal_only, size_t* out_len) {
+uint8_t* pqg_snappy(const uint8_t* src, size_t n, int mode, size_t* out_len) {
   buf_t b = {0};
-  pqg_snappy_compress(src, n, &b, literal_only);
+  pqg_snappy_compress(src, n, &b, mode);
   *out_len = b.n;
   return b.p;
 }

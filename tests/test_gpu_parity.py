@@ -35,6 +35,13 @@ def _spec_cases():
     lit = dg.snappy_wide_table(120_000, 120_000, 256 * dg.KiB)
     lit.snappy_literal_only = True
     cases["wide_snappy_literal_only"] = lit
+    # every Snappy tag form in turn (literal lengths in 0-4 extra bytes,
+    # copies with 1-, 2- and 4-byte offsets), V1 and V2 pages
+    for v in (1, 2):
+        vf = dg.snappy_wide_table(130_000, 130_000, 256 * dg.KiB)
+        vf.page_version = v
+        vf.snappy_varied_forms = True
+        cases[f"wide_snappy_varied_forms_v{v}"] = vf
     cases["edge"] = dg.FileSpec(cols=[
         dg.Col(dg.INT32, dg.PLAIN, True, dg.UNIFORM, 1.0),
         dg.Col(dg.INT64, dg.RLE_DICTIONARY, True, dg.CONST, 0.3, lo=-5),

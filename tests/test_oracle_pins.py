@@ -11,6 +11,7 @@ import pyarrow as pa
 import pyarrow.parquet as pq
 import pytest
 
+import datagen as dg
 import oracle
 from tests import golden_io
 
@@ -243,6 +244,47 @@ def test_snappy_vs_pyarrow(data):
     codec = pa.Codec("snappy")
     comp = codec.compress(data, asbytes=True)
     assert oracle.snappy_decompress(comp, len(data) + 16) == data
+
+
+def _tag_forms(stream):
+    """(length-byte counts of the literals, tag forms of the copies) in a raw
+    Snappy stream, by a walk over its element tags."""
+    i = 0
+    while stream[i] & 0x80:  # the uncompressed length
+        i += 1
+    i += 1
+    lit, cop = set(), set()
+    while i < len(stream):
+        t = stream[i]
+        if t & 3 == 0:
+            nb = max(0, (t >> 2) - 59)
+            n = (int.from_bytes(stream[i + 1:i + 1 + nb], "little") if nb else t >> 2) + 1
+            lit.add(nb)
+            i += 1 + nb + n
+        else:
+            cop.add(t & 3)
+            i += (2, 3, 5)[(t & 3) - 1]
+    return lit, cop
+
+
+@pytest.mark.parametrize("data", list(_snappy_inputs())[2:], ids=lambda d: f"len{len(d)}")
+def test_snappy_every_tag_form(data):
+    """The fixture writer's varied-forms streams (literal lengths in 0-4 extra
+    bytes, copies with 1-, 2- and 4-byte offsets) decode to the input with
+    pyarrow's codec and with the oracle."""
+    comp = dg.snappy_compress(data, varied_forms=True)
+    assert pa.Codec("snappy").decompress(comp, len(data), asbytes=True) == data
+    assert oracle.snappy_decompress(comp, len(data) + 16) == data
+
+
+def test_snappy_varied_forms_cover_every_tag_form():
+    """On an input with many short matches the varied-forms stream holds
+    every literal length form and every copy form."""
+    data = np.random.default_rng(3).integers(97, 101, 150_000, dtype=np.uint8).tobytes()
+    lit, cop = _tag_forms(dg.snappy_compress(data, varied_forms=True))
+    assert lit == {0, 1, 2, 3, 4} and cop == {1, 2, 3}
+    lit0, cop0 = _tag_forms(dg.snappy_compress(data))
+    assert 3 not in cop0  # the plain matcher never writes 4-byte offsets
 
 
 # ---------------------------------------------------------------------------
