@@ -1443,19 +1443,22 @@ __global__ __launch_bounds__(64) void k_snap_index(const ColScan* cols, SegTable
 // source may be this lane's own earlier output: a lane's loads see its
 // earlier stores (program order), so no wait is needed.
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
-__device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, uint32_t n) {
-  const uint32_t sh = (uint32_t)((uintptr_t)src & 3), d = (uint32_t)((uintptr_t)dst & 3);
+// lane_copy64 in two halves: the loads (into w), and the stores of the run
+// from w (sh: the source's byte offset in its dword).
+__device__ __forceinline__ void lane_load64(const uint8_t* src, uint32_t n, uint32_t (&w)[20]) {
+  const uint32_t sh = (uint32_t)((uintptr_t)src & 3);
   const __attribute__((address_space(1))) u32x4a* q =
       (const __attribute__((address_space(1))) u32x4a*)((uintptr_t)src & ~(uintptr_t)3);
   const uint32_t nq = (sh + n + 3) >> 2;  // source dwords, <= 17
-  uint32_t w[21];
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     u32x4a x = {0u, 0u, 0u, 0u};
     if ((uint32_t)(4 * c) < nq) x = q[c];
     w[4 * c] = x.x; w[4 * c + 1] = x.y; w[4 * c + 2] = x.z; w[4 * c + 3] = x.w;
   }
-  w[20] = 0u;
+}
+__device__ __forceinline__ void lane_store64(uint8_t* dst, uint32_t sh, uint32_t n, const uint32_t (&w)[20]) {
+  const uint32_t d = (uint32_t)((uintptr_t)dst & 3);
   // destination byte 4 j + i holds run byte 4 j + i - d = w byte 4 j + i + (sh - d)
   const int32_t e = (int32_t)sh - (int32_t)d;  // -3 .. 3
   const uint32_t fs = (uint32_t)e & 3u;
@@ -1466,7 +1469,7 @@ __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, ui
 #pragma unroll
   for (int j = 0; j < 17; ++j) {
     const uint32_t lo = back ? (j > 0 ? w[j - 1] : 0u) : w[j];
-    const uint32_t hi = back ? w[j] : w[j + 1];
+    const uint32_t hi = back ? w[j] : (j + 1 < 20 ? w[j + 1] : 0u);
     const uint32_t o = __builtin_amdgcn_alignbyte(hi, lo, fs);
     if (j == 0 && d) {
       uint8_t* bp = (uint8_t*)dw;
@@ -1477,6 +1480,11 @@ __device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, ui
       dw[j] = o;
     }
   }
+}
+__device__ __forceinline__ void lane_copy64(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  uint32_t w[20];
+  lane_load64(src, n, w);
+  lane_store64(dst, (uint32_t)((uintptr_t)src & 3), n, w);
 }
 
 // The wave's active lanes (rank r of nact) copy n bytes s -> d together (a
@@ -1781,6 +1789,10 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
       v[j] = *(gq4)(((uint32_t)j < nb && !(nk[j] & 0x200u) ? a : dummy) & ~(uintptr_t)3);
     }
     run = run && !bad;
+    // a literal of at most 64 bytes decoded alone after the batch: its stream
+    // bytes are loaded with the batch's sources (the stream is never written)
+    uint32_t sw[20];
+    if (run && skind == 1) lane_load64(src + ssrc, sn, sw);
     wload();
     // stored in order; when a later element of the batch has its source in
     // this batch's output, each element's 16 bytes also go to the batch's
@@ -1815,7 +1827,7 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
     bool big = false;
     if (run && skind) {
       if (skind == 1) {
-        lane_copy64(dst + sop, src + ssrc, sn);
+        lane_store64(dst + sop, (uint32_t)((uintptr_t)(src + ssrc) & 3), sn, sw);
       } else if (skind == 2) {
         big = true;
       } else if (skind == 3) {
