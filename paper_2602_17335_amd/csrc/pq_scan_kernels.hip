@@ -1543,11 +1543,15 @@ __device__ __forceinline__ void wave_copy(uint8_t* d, const uint8_t* s, uint32_t
 // SNAP_WIN-byte window of the stream in LDS, then all their sources are
 // loaded (one 16-byte load each: the literal's stream bytes or the copy's
 // earlier output), then all are stored, so that a batch costs one memory
-// round trip instead of one per element.  A copy whose source reaches into
-// the batch's own output ends the batch (it opens the next one); a longer
-// element, or a copy overlapping its own output, is decoded on its own after
-// the batch's stores.  Loads see the lane's earlier stores (program order),
-// so no wait is needed between batches.
+// round trip instead of one per element.  A copy whose source lies in the
+// batch's own output reads it from a per-lane LDS copy of that output (a
+// source starting before the copy's first dword ends the batch); a longer
+// element, or a copy overlapping its own output, ends the batch and is
+// decoded on its own after the batch's stores (a literal of at most 64
+// bytes with its stream bytes loaded beside the batch's sources).  Loads see
+// the lane's earlier stores (program order), so no wait is needed between
+// batches.  With sord, a scan's blocks come densest first (k_snap_order), so
+// that the blocks of a wave need similar numbers of batches.
 // ---------------------------------------------------------------------------
 constexpr int SNAP_BATCH = 8;
 constexpr uint32_t SNAP_SHORT = 13;  // a run of up to 13 bytes lies in the 16 bytes from its dword
@@ -1710,8 +1714,9 @@ __global__ __launch_bounds__(WG) void k_snappy_blk(const ColScan* cols, SegTable
   bool run = live && !bad && op < oend;
   while (__ballot(run)) {
     // the batch: element j is n bytes (nk[j] & 0xff; nk[j] & 0x100 marks a
-    // copy) to output offset dop[j] from offset so[j] of the stream (a
-    // literal) or of the output (a copy)
+    // copy, & 0x200 one whose source lies in this batch's output) to output
+    // offset dop[j] from offset so[j] of the stream (a literal) or of the
+    // output (a copy)
     uint32_t dop[SNAP_BATCH], so[SNAP_BATCH], nk[SNAP_BATCH];
     uint32_t nb = 0;
     // the element decoded alone after the batch: kind 1 a literal of at most
