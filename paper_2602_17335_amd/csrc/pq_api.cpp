@@ -1176,7 +1176,8 @@ static pq_status open_impl(const void* dev_buf, uint64_t len, pq_stream stream, 
   S.tiles = (int64_t)tiles;
   S.open_ms_device = ms + prefix_ms;
   f->device_bytes += 4 + sizeof(ChunkDev) * (uint64_t)nchunks + sizeof(PageDev) * (uint64_t)npages +
-                     (sizeof(TileDev) + 4ull * NLCK + sizeof(Ck) * NSUB) * tiles + 4ull * strck + 8ull * sblk +
+                     (sizeof(TileDev) + 4ull * NLCK + sizeof(Ck) * NSUB) * tiles + 4ull * strck +
+                     12ull * sblk +  // Snappy block index: offset, element count, page
                      8ull * (tiles + 1) + sizeof(DictSlot) * (uint64_t)nchunks;
   S.device_bytes = f->device_bytes;
   (void)t0;
