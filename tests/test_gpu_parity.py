@@ -156,6 +156,17 @@ def test_parity_subrange_and_projection():
     check_file(data, columns=[5, 6], rg_begin=3, rg_end=3, label="empty-range")
 
 
+def test_parity_snappy_subrange_and_projection():
+    """Snappy pages of several 64 KiB blocks under row-group sub-ranges and
+    projections (a scan's block-indexed blocks are taken in buckets of
+    element count: only the selected pages' blocks may enter them)."""
+    spec = dg.snappy_wide_table(300_000, 70_000, 256 * dg.KiB)
+    data = dg.write(spec)
+    check_file(data, columns=[0, 6, 9, 15], rg_begin=1, rg_end=4, label="snappy-sub")
+    check_file(data, columns=[13], rg_begin=2, rg_end=3, label="snappy-one")
+    check_file(data, columns=[3, 4, 5], rg_begin=0, rg_end=5, label="snappy-three")
+
+
 def _arrow_table(n, seed):
     rng = np.random.default_rng(seed)
     m = rng.random(n) < 0.1
